@@ -1,0 +1,168 @@
+"""Oracle pins: Jackson kernel, Gauss-Chebyshev quadrature and thermodynamics."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ed, hamiltonian, moments, thermo
+
+
+def _exact_problem_set(cl, eps=0.025, M=256):
+    secs = W.sectors(cl)
+    spec = ed.sector_spectra(secs)
+    mus, ab, probs = [], [], []
+    for s, (e, _, _) in zip(secs, spec):
+        lo, hi = e.min(), e.max()
+        if hi - lo < 1e-8:
+            lo, hi = lo - 0.5, hi + 0.5
+        a, b = hamiltonian.scale_from_bounds(lo, hi, eps)
+        mus.append(moments.exact_moments((e - b) / a, M))
+        ab.append((a, b))
+        probs.append(dict(cluster=0, n_sites=cl.n_sites, n_up=s.n_up))
+    return probs, np.array(mus), np.array(ab), spec
+
+
+def test_jackson_closed_values():
+    for M in (2, 10, 100, 1000):
+        g = thermo.jackson(M)
+        assert g[0] == pytest.approx(1.0, abs=1e-14)
+        if M > 1:
+            assert g[1] == pytest.approx(np.cos(np.pi / (M + 1)), abs=1e-14)
+        assert np.all(np.diff(g) < 0) and g[-1] > 0
+    # extending to n = M gives the inert top coefficient of the paper's sum
+    M = 50
+    n = M
+    q = np.pi / (M + 1)
+    top = ((M - n + 1) * np.cos(q * n) + np.sin(q * n) / np.tan(q)) / (M + 1)
+    assert abs(top) < 1e-15
+
+
+def test_jackson_keeps_delta_expansion_nonnegative():
+    M = 64
+    g = thermo.jackson(M)
+    x = np.linspace(-0.999, 0.999, 2001)
+    for x0 in (-0.9, -0.3, 0.0, 0.55, 0.97):
+        mu = np.cos(np.arange(M) * np.arccos(x0))
+        c = g * mu * np.where(np.arange(M) == 0, 1, 2)
+        rho = np.polynomial.chebyshev.chebval(x, c)
+        assert rho.min() > -1e-12
+        c1 = mu * np.where(np.arange(M) == 0, 1, 2)
+        assert np.polynomial.chebyshev.chebval(x, c1).min() < -1.0   # Gibbs without kernel
+
+
+def test_quadrature_exact_for_low_degree():
+    """Sec. II: the Gauss-Chebyshev rule is exact up to degree 2 Ntil - 1."""
+    Nt = 16
+    x = thermo.nodes(Nt)
+    for deg in range(2 * Nt):
+        c = np.zeros(deg + 1); c[-1] = 1
+        q = np.pi / Nt * np.polynomial.chebyshev.chebval(x, c).sum()
+        want = np.pi if deg == 0 else 0.0
+        assert q == pytest.approx(want, abs=1e-12)
+
+
+def test_exact_trace_kpm_matches_ed_ring12():
+    """g_n = 1, Ntil = M, exact traces: the KPM heat capacity of the N=12 ring
+    equals exact diagonalisation over T in [0.01, 10]."""
+    cl = W.ring(12)
+    probs, mus, ab, spec = _exact_problem_set(cl, 0.025, 256)
+    T = W.log_temperatures(200, 0.01, 10.0)
+    out = thermo.thermo(probs, mus, ab, T, "none", 256)
+    ref = ed.thermo_from_spectra(spec, T)
+    assert np.abs(out["C"][0] - ref["C"]).max() < 1e-8
+    assert np.abs(out["chi"][0] - ref["chi"]).max() < 1e-10
+    assert np.abs(out["E"][0] - ref["E"]).max() < 1e-9
+    assert np.abs(out["lnZ"][0] - ref["lnZ"]).max() < 1e-9
+    assert not out["z_nonpos"].any()
+
+
+def test_dimer_closed_form_thermodynamics():
+    J = 1.0
+    d = W.dimer(J)
+    probs, mus, ab, _ = _exact_problem_set(d, 0.0, 64)
+    T = np.array([0.2, 0.5, 1.0, 3.0, 10.0])
+    out = thermo.thermo(probs, mus, ab, T, "none", 64)
+    beta = 1 / T
+    Z = np.exp(0.75 * beta * J) + 3 * np.exp(-0.25 * beta * J)
+    E = (-0.75 * J * np.exp(0.75 * beta * J) + 0.75 * J * np.exp(-0.25 * beta * J)) / Z
+    E2 = (0.5625 * np.exp(0.75 * beta * J) + 3 * 0.0625 * np.exp(-0.25 * beta * J)) / Z
+    C = beta**2 * (E2 - E**2)
+    chi = beta * 2 * np.exp(-0.25 * beta * J) / Z
+    np.testing.assert_allclose(out["lnZ"][0], np.log(Z), atol=1e-10)
+    np.testing.assert_allclose(out["C"][0], C, atol=1e-10)
+    np.testing.assert_allclose(out["chi"][0], chi, atol=1e-10)
+
+
+def test_high_temperature_limits():
+    """Z -> 2^N, chi T -> N/4, C T^2 -> Tr H^2 / 2^N = (3/16) sum J^2."""
+    cl = W.random_regular_cluster(10, 3, 3, J_range=(0.5, 1.5))
+    probs, mus, ab, _ = _exact_problem_set(cl, 0.025, 128)
+    T = np.array([1e5])
+    out = thermo.thermo(probs, mus, ab, T, "none", 128)
+    assert out["lnZ"][0, 0] == pytest.approx(10 * np.log(2), abs=1e-4)
+    assert out["chi"][0, 0] * 1e5 == pytest.approx(10 / 4, rel=1e-4)
+    assert out["C"][0, 0] * 1e10 == pytest.approx(3 / 16 * np.sum(cl.J**2), rel=1e-4)
+
+
+def test_jackson_exact_traces_give_positive_C_and_chi():
+    cl = W.ring(10)
+    probs, mus, ab, _ = _exact_problem_set(cl, 0.025, 100)
+    T = W.log_temperatures(100, 1e-3, 10)
+    out = thermo.thermo(probs, mus, ab, T, "jackson", 100)
+    assert out["C"].min() >= -1e-9 and out["chi"].min() >= -1e-12
+
+
+def test_thermo_vjp_matches_finite_differences():
+    cl = W.ring(8)
+    probs, mus, ab, _ = _exact_problem_set(cl, 0.025, 40)
+    T = np.array([0.3, 1.0, 2.5])
+    rng = np.random.default_rng(0)
+    wC, wX = rng.normal(size=(1, 3)), rng.normal(size=(1, 3))
+    for kern in ("none", "jackson"):
+        lam = thermo.thermo_vjp(probs, mus, ab, T, wC, wX, kern, 48)
+        L = lambda m: (lambda o: np.sum(wC * o["C"]) + np.sum(wX * o["chi"]))(
+            thermo.thermo(probs, m, ab, T, kern, 48))
+        for p in (0, 2):
+            for n in (0, 1, 7, 39):
+                h = 1e-4 * max(1.0, abs(mus[p, n]))
+                mp, mm = mus.copy(), mus.copy()
+                mp[p, n] += h
+                mm[p, n] -= h
+                fd = (L(mp) - L(mm)) / (2 * h)
+                assert lam[p, n] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_ghost_dip_behaviour_ladder14():
+    """Qualitative statements of Sec. III.A (ladder, exact traces, Table I
+    parameters N_deg = Ntil = 100, eps = 0, g_n = 1), at N = 14: a negative
+    'ghost dip' of C in 1e-3 <= T <= 1e-2 while T >= 0.1 is exact; the Jackson
+    kernel turns the dip into a peak and spoils T >= 0.1; eps > 0 deepens the
+    dip; N_deg = 500 removes it."""
+    cl = W.ladder(14)
+    secs = W.sectors(cl)
+    spec = ed.sector_spectra(secs)
+    T = W.log_temperatures(300, 1e-3, 10)
+    ref = ed.thermo_from_spectra(spec, T)["C"]
+
+    def C(Nd, eps, kern):
+        mus, ab, probs = [], [], []
+        for s, (e, _, _) in zip(secs, spec):
+            lo, hi = e.min(), e.max()
+            if hi - lo < 1e-8:
+                lo, hi = lo - 0.5, hi + 0.5
+            a, b = hamiltonian.scale_from_bounds(lo, hi, eps)
+            mus.append(moments.exact_moments((e - b) / a, Nd))
+            ab.append((a, b))
+            probs.append(dict(cluster=0, n_sites=14, n_up=s.n_up))
+        return thermo.thermo(probs, np.array(mus), np.array(ab), T, kern, Nd)["C"][0]
+
+    w = (T >= 1e-3) & (T <= 1e-2)
+    hi = T >= 0.1
+    c0 = C(100, 0.0, "none")
+    assert c0[w].min() < -0.1
+    assert np.abs(c0 - ref)[hi].max() < 1e-9
+    cj = C(100, 0.0, "jackson")
+    assert (cj - ref)[w].min() > 0 and (cj - ref)[w].max() > 0.1
+    assert np.abs(cj - ref)[hi].max() > 1e-2
+    assert C(100, 0.025, "none")[w].min() < 10 * c0[w].min()
+    assert C(100, 0.1, "none")[w].min() < 10 * c0[w].min()
+    assert np.abs(C(500, 0.0, "none") - ref)[w].max() < 1e-5
