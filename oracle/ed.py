@@ -37,9 +37,14 @@ def thermo_from_spectra(spectra, T):
                 S2 += np.dot(bz, e * e)
                 SM1 += mm * bz.sum()
                 SM2 += mm * mm * bz.sum()
+        Em = S1 / S0
+        varE = 0.0
+        for e, m, w in spectra:
+            bz = np.exp(-beta * (e - E0))
+            varE += (1 if w == 1 else 2) * np.dot(bz, (e - Em) ** 2)
         res["lnZ"][t] = np.log(S0) - beta * E0
-        res["E"][t] = S1 / S0
-        res["C"][t] = beta**2 * (S2 / S0 - (S1 / S0) ** 2)
+        res["E"][t] = Em
+        res["C"][t] = beta**2 * varE / S0
         res["chi"][t] = beta * (SM2 / S0 - (SM1 / S0) ** 2)
     return res
 

@@ -45,10 +45,13 @@ def nodes(n_nodes: int) -> np.ndarray:
 
 
 def cos_matrix(n_nodes: int, M: int) -> np.ndarray:
-    """Cmat[k-1, n] = cos(n pi (k - 1/2)/Ntil)."""
-    k = np.arange(1, n_nodes + 1, dtype=np.float64)[:, None]
-    n = np.arange(M, dtype=np.float64)[None, :]
-    return np.cos(n * np.pi * (k - 0.5) / n_nodes)
+    """Cmat[k-1, n] = cos(n pi (k - 1/2)/Ntil), with the argument n (2k - 1)
+    reduced modulo 4 Ntil in integers before scaling by pi / (2 Ntil) (the same
+    angle; avoids rounding an argument that grows with n)."""
+    k = np.arange(1, n_nodes + 1, dtype=np.int64)[:, None]
+    n = np.arange(M, dtype=np.int64)[None, :]
+    m = (n * (2 * k - 1)) % (4 * n_nodes)
+    return np.cos(np.pi * m / (2 * n_nodes))
 
 
 def dos_weights(mu: np.ndarray, g: np.ndarray, n_nodes: int) -> np.ndarray:
@@ -92,24 +95,25 @@ def thermo(problems, mu: np.ndarray, ab: np.ndarray, T: np.ndarray,
         Eref = Ek[sel].min()
         for t, Tv in enumerate(T):
             beta = 1.0 / Tv
-            S0 = S1 = S2 = SM1 = SM2 = 0.0
+            ws, Es, ms = [], [], []
             for p in sel:
                 w = gam[p] * np.exp(-beta * (Ek[p] - Eref))
-                z = w.sum()
                 # both signs of S^z (the mirror sector of S^z > 0 is degenerate)
-                signs = [sz[p]] if W[p] == 1.0 else [sz[p], -sz[p]]
-                for m in signs:
-                    S0 += z
-                    S1 += np.dot(w, Ek[p])
-                    S2 += np.dot(w, Ek[p] ** 2)
-                    SM1 += m * z
-                    SM2 += m * m * z
+                for m in ([sz[p]] if W[p] == 1.0 else [sz[p], -sz[p]]):
+                    ws.append(w)
+                    Es.append(Ek[p])
+                    ms.append(np.full(Nt, m))
+            w, E, m = np.concatenate(ws), np.concatenate(Es), np.concatenate(ms)
+            S0 = w.sum()
+            Em = np.dot(w, E) / S0
+            varE = np.dot(w, (E - Em) ** 2) / S0          # <E^2> - <E>^2
+            m1 = np.dot(w, m) / S0
+            varM = np.dot(w, (m - m1) ** 2) / S0          # <S_z^2> - <S_z>^2
             out["z_nonpos"][c, t] = S0 <= 0.0
             out["lnZ"][c, t] = (np.log(S0 / Nt) if S0 > 0 else np.nan) - beta * Eref
-            Em = S1 / S0
             out["E"][c, t] = Em
-            out["C"][c, t] = beta**2 * (S2 / S0 - Em**2)
-            out["chi"][c, t] = beta * (SM2 / S0 - (SM1 / S0) ** 2)
+            out["C"][c, t] = beta**2 * varE
+            out["chi"][c, t] = beta * varM
     return out
 
 
