@@ -22,6 +22,8 @@ densities).
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 
@@ -55,12 +57,13 @@ def cos_matrix(n_nodes: int, M: int) -> np.ndarray:
 
 
 def dos_weights(mu: np.ndarray, g: np.ndarray, n_nodes: int) -> np.ndarray:
-    """gamma_k for k = 1..Ntil (direct sum; the DCT-III is a faster route to the
-    same numbers)."""
+    """gamma_k for k = 1..Ntil: the direct sum over n, exactly rounded (math.fsum;
+    the DCT-III is a faster route to the same numbers)."""
     M = mu.shape[-1]
     c = g * mu
     c = c * np.where(np.arange(M) == 0, 1.0, 2.0)
-    return cos_matrix(n_nodes, M) @ c
+    terms = cos_matrix(n_nodes, M) * c[None, :]
+    return np.array([math.fsum(row) for row in terms])
 
 
 def _sector_table(problems):
@@ -104,11 +107,11 @@ def thermo(problems, mu: np.ndarray, ab: np.ndarray, T: np.ndarray,
                     Es.append(Ek[p])
                     ms.append(np.full(Nt, m))
             w, E, m = np.concatenate(ws), np.concatenate(Es), np.concatenate(ms)
-            S0 = w.sum()
-            Em = np.dot(w, E) / S0
-            varE = np.dot(w, (E - Em) ** 2) / S0          # <E^2> - <E>^2
-            m1 = np.dot(w, m) / S0
-            varM = np.dot(w, (m - m1) ** 2) / S0          # <S_z^2> - <S_z>^2
+            S0 = math.fsum(w)                             # sums exactly rounded
+            Em = math.fsum(w * E) / S0
+            varE = math.fsum(w * (E - Em) ** 2) / S0      # <E^2> - <E>^2
+            m1 = math.fsum(w * m) / S0
+            varM = math.fsum(w * (m - m1) ** 2) / S0      # <S_z^2> - <S_z>^2
             out["z_nonpos"][c, t] = S0 <= 0.0
             out["lnZ"][c, t] = (np.log(S0 / Nt) if S0 > 0 else np.nan) - beta * Eref
             out["E"][c, t] = Em
