@@ -1,0 +1,208 @@
+/*
+ * kpm.h -- C ABI of the MI355X (gfx950) library for the stochastic
+ * Chebyshev-moment ("kernel polynomial") typicality method of
+ * H. Schlueter, F. Gayk, H.-J. Schmidt, A. Honecker, J. Schnack,
+ * "Accuracy of the typicality approach using Chebyshev polynomials",
+ * arXiv:2104.13218 (cited below as "the paper").
+ *
+ * Problem statement (the paper, Sec. II and Sec. III): spin-1/2 Heisenberg
+ * Hamiltonians H = sum_b J_b s_i . s_j given by a bond list on N sites, split
+ * into S^z sectors (Sec. II, after Eq. (3), and the sector sum below Eq. (9));
+ * parameters: expansion order (moment count M), scaling parameter eps of
+ * Eq. (5), number of random vectors R of Eq. (7), kernel g_n of Eq. (8) and the
+ * number of quadrature nodes (the paper's N-tilde).
+ *
+ * Conventions
+ *  - Every function returns an int status: KPM_OK (0) or a negative KPM_E*
+ *    code; kpm_strerror() names it.  On error the outputs are unspecified,
+ *    nothing is leaked and the library stays usable.
+ *  - Problem descriptions (kpm_problem, kpm_params, bond arrays, and host
+ *    arrays marked "host") are read during the call only.
+ *  - Arrays marked "device" are device pointers in the current HIP device's
+ *    memory, owned by the caller.  Results are written on `stream` (a
+ *    hipStream_t passed as void*, NULL = the null stream) and are complete when
+ *    the call returns (every call synchronises `stream` before returning).
+ *  - Workspace: device scratch comes from the caller as (d_work, work_bytes)
+ *    sized by the matching *_workspace_size() query; d_work == NULL makes the
+ *    library allocate and free it inside the call.  Too small a workspace is
+ *    KPM_EWORKSPACE.
+ *  - Layout conventions: a problem's basis is the ascending-integer order of
+ *    N-bit words with n_up set bits (bit p set <=> site p is up); index = rank
+ *    in the combinatorial number system.
+ *  - Thread safety: calls on different streams may run concurrently; the only
+ *    global state is a per-device cache of tuned launch shapes (mutex-guarded).
+ */
+#ifndef KPM_H
+#define KPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define KPM_OK 0
+#define KPM_EINVAL (-1)     /* invalid argument (bad bond, n_up, M, ...) */
+#define KPM_ENOMEM (-2)     /* device allocation failed */
+#define KPM_EDEVICE (-3)    /* HIP runtime error */
+#define KPM_EBOUNDS (-4)    /* |mu_n| > mu_0 (1 + 1e-6) for some vector: the
+                               spectral bounds do not enclose the spectrum */
+#define KPM_EWORKSPACE (-5) /* caller workspace smaller than required */
+
+/* ---- random vector kinds of Eq. (7) ------------------------------------- */
+#define KPM_VEC_RADEMACHER 0       /* components +-1                         */
+#define KPM_VEC_COMPLEX_GAUSSIAN 1 /* complex Gaussian, <r|r> = dim;         */
+                                   /* stored as two real columns (Re, Im)    */
+#define KPM_VEC_GAUSSIAN 2         /* real Gaussian (the paper's choice),    */
+                                   /* <r|r> = dim                            */
+#define KPM_VEC_BASIS 3            /* complete basis e_nu: exact traces,     */
+                                   /* Eq. (6) (the paper's check of Sec. II) */
+
+/* ---- storage precision of the recursion vectors ------------------------- */
+#define KPM_FP64 0       /* float64 vectors, float64 arithmetic               */
+#define KPM_FP32_STORE 1 /* float32 vectors; float64 products, sums and dots  */
+
+/* ---- kernel coefficients g_n, Eq. (8) ----------------------------------- */
+#define KPM_KERNEL_NONE 0    /* g_n = 1 */
+#define KPM_KERNEL_JACKSON 1 /* Jackson kernel with N_deg = M */
+
+/* One (cluster, S^z sector) problem.  S^z = n_up - n_sites/2 >= 0. */
+typedef struct {
+  int32_t n_sites;       /* N, 2..32 */
+  int32_t n_up;          /* up spins, n_sites/2 <= n_up <= n_sites (2 n_up >= N) */
+  int32_t n_bonds;       /* 0..512; i != j, 0 <= i, j < N; repeats are summed */
+  int32_t cluster;       /* dense id 0.. < 65536: thermodynamic system and RNG
+                            stream; problems of one cluster are its sectors */
+  const int32_t* bond_i; /* host [n_bonds] */
+  const int32_t* bond_j; /* host [n_bonds] */
+  const double* J;       /* host [n_bonds], finite */
+  double e_lo, e_hi;     /* spectral bounds E_min <= E_max of Eq. (5); NaN in
+                            either => estimated by Lanczos (kpm_params) */
+} kpm_problem;
+
+typedef struct {
+  double eps;            /* Eq. (5): spectrum mapped into [-1+eps/2, 1-eps/2]; 0 <= eps < 1 */
+  int32_t M;             /* moments mu_0..mu_{M-1}, M >= 2 (the paper's N_deg = M) */
+  int32_t R;             /* random vectors per problem, 1..1024 (ignored for KPM_VEC_BASIS) */
+  int32_t vec_kind;      /* KPM_VEC_* */
+  int32_t precision;     /* KPM_FP64 | KPM_FP32_STORE */
+  int32_t col_block;     /* real columns per recursion block, 0 = tuned; 1..64 */
+  uint64_t seed;         /* counter-RNG seed */
+  int32_t lanczos_steps; /* Lanczos steps for NaN bounds (0 => 50) */
+  double bound_margin;   /* widening of Lanczos bounds, fraction of the width (>= 0) */
+} kpm_params;
+
+/* Human-readable name of a status code (static string). */
+const char* kpm_strerror(int code);
+
+/* Sector dimension C(n_sites, n_up) (0 if out of range). Host only. */
+uint64_t kpm_sector_dim(int32_t n_sites, int32_t n_up);
+
+/* Basis enumeration (debug export).  d_states: device uint32 [C(N, n_up)],
+ * written in rank order: d_states[r] = the word of rank r. 1 <= N <= 32. */
+int kpm_sector_states(int32_t n_sites, int32_t n_up, uint32_t* d_states, void* stream);
+
+/* Matrix elements of H (unscaled) for rows [row0, row0+nrows) of a sector
+ * (debug export; the same device code the recursion uses).
+ *  d_cols  device uint32 [nrows][max_nb]: ranks of the off-diagonal neighbours
+ *          s XOR (1<<i | 1<<j) for each bond whose two bits differ, in bond order
+ *  d_bond  device int32 [nrows][max_nb]: the bond index of each entry
+ *          (its matrix element is J_b / 2)
+ *  d_cnt   device int32 [nrows]: entries used per row (<= n_bonds)
+ *  d_diag  device double [nrows]: sum_b J_b (+1/4 if bits equal, -1/4 otherwise)
+ * max_nb >= n_bonds is required. */
+int kpm_sector_matrix(const kpm_problem* p, int64_t row0, int64_t nrows, int32_t max_nb,
+                      uint32_t* d_cols, int32_t* d_bond, int32_t* d_cnt, double* d_diag,
+                      void* stream);
+
+/* Spectral bounds for Eq. (5) (the paper estimates the ground state with
+ * Lanczos, Sec. III.A.2.b): `steps` steps of float64 Lanczos without
+ * reorthogonalisation from the Rademacher vector of RNG stream r = 1023,
+ * stopping early when an off-diagonal falls below 1e-12; the extreme Ritz
+ * values are widened by margin*(width) on each side (a window narrower than
+ * 1e-8 max(1,|E|) is widened to E -/+ 1/2).  e_lo_hi: host double [n][2]. */
+int kpm_spectral_bounds(const kpm_problem* p, int32_t n, int32_t steps, double margin,
+                        uint64_t seed, double* e_lo_hi, void* stream);
+
+/* Workspace bytes for chebyshev_moments with these problems and parameters. */
+size_t chebyshev_moments_workspace_size(const kpm_problem* p, int32_t n, const kpm_params* q);
+
+/* Chebyshev moments, Eqs. (6)-(7): for each problem, with H' = (H - b)/a,
+ * a = (E_hi - E_lo)/(2 - eps), b = (E_hi + E_lo)/2 (Eqs. (4)-(5)),
+ *   mu_n = dim/R sum_r <r|T_n(H')|r> / <r|r>,   n = 0..M-1,
+ * from the recursion v_1 = H' v_0, v_{n+1} = 2 H' v_n - v_{n-1} and the
+ * doubling identities mu_2n = 2<v_n|v_n> - mu_0, mu_2n+1 = 2<v_n+1|v_n> - mu_1
+ * (M/2 products).  Random vectors come from the counter-based SplitMix64
+ * generator, stream (cluster << 16 | n_up << 10 | r).
+ *  d_mu  device double [n][M]
+ *  d_ab  device double [n][2] = (a, b), may be NULL
+ * Returns KPM_EBOUNDS when some |<r|T_n|r>| exceeds <r|r>(1 + 1e-6). */
+int chebyshev_moments(const kpm_problem* p, int32_t n, const kpm_params* q,
+                      double* d_mu, double* d_ab, void* d_work, size_t work_bytes,
+                      void* stream);
+
+/* Thermodynamics from moments (Sec. II): kernel g_n (Eq. (8)), DOS weights
+ * gamma_k at the n_nodes Gauss-Chebyshev nodes (0 => M; n_nodes >= M/2 ... any
+ * n_nodes >= 1 is accepted), and per cluster c and temperature T (k_B = 1,
+ * g mu_B = 1):
+ *   Z   = (1/n_nodes) sum_sectors W sum_k gamma_k exp(-E_k/T),  E_k = a x_k + b,
+ *   E   = <E>,  C = (<E^2> - <E>^2)/T^2,  chi = (<S_z^2> - <S_z>^2)/T,
+ * W = 1 for S^z = 0 sectors, 2 otherwise (the S^z < 0 mirror, Sec. II).
+ *  d_mu [n][M], d_ab [n][2], d_T [n_T]: device; outputs device
+ *  [n_clusters][n_T] (n_clusters = 1 + max cluster id); d_znonpos (may be NULL)
+ *  flags Z <= 0 (an improper DOS; values are never clipped), lnZ is NaN there. */
+int kpm_thermo(const double* d_mu, const double* d_ab, const kpm_problem* p, int32_t n,
+               int32_t M, int32_t kernel, int32_t n_nodes, const double* d_T, int32_t n_T,
+               double* d_lnZ, double* d_E, double* d_C, double* d_chi, uint8_t* d_znonpos,
+               void* stream);
+
+/* Derivative of L = sum_{c,T} wC[c][T] C[c][T] + wchi[c][T] chi[c][T] with
+ * respect to the moments: d_lambda device double [n][M] = dL/dmu. */
+int kpm_thermo_vjp(const double* d_mu, const double* d_ab, const kpm_problem* p, int32_t n,
+                   int32_t M, int32_t kernel, int32_t n_nodes, const double* d_T, int32_t n_T,
+                   const double* d_wC, const double* d_wchi, double* d_lambda, void* stream);
+
+/* Workspace bytes for chebyshev_moments_vjp / kpm_thermo_grad. */
+size_t chebyshev_moments_vjp_workspace_size(const kpm_problem* p, int32_t n,
+                                            const kpm_params* q, int32_t ckpt_every);
+
+/* Reverse-mode derivative of chebyshev_moments with the rescaling (a, b)
+ * held fixed: given d_dmu = dL/dmu (device [n][M]) and the (a, b) used
+ * forward (device [n][2]), writes d_dJ (device double, sum_p n_bonds(p)
+ * entries, problem after problem in bond order) = dL/dJ_b.  The forward
+ * recursion is recomputed from checkpoints taken every ckpt_every steps
+ * (even, >= 2). Same seeds and vectors as chebyshev_moments. */
+int chebyshev_moments_vjp(const kpm_problem* p, int32_t n, const kpm_params* q,
+                          const double* d_ab, const double* d_dmu, int32_t ckpt_every,
+                          double* d_dJ, void* d_work, size_t work_bytes, void* stream);
+
+/* Loss and gradient in one call: moments (forward), thermodynamics, their
+ * derivative and the recursion adjoint.  d_T [n_T], d_wC, d_wchi
+ * [n_clusters][n_T]: device.  Outputs: d_L (device double [1]), d_dJ as in
+ * chebyshev_moments_vjp, d_ab (device [n][2], may be NULL). */
+int kpm_thermo_grad(const kpm_problem* p, int32_t n, const kpm_params* q, int32_t kernel,
+                    int32_t n_nodes, const double* d_T, int32_t n_T, const double* d_wC,
+                    const double* d_wchi, int32_t ckpt_every, double* d_L, double* d_dJ,
+                    double* d_ab, void* d_work, size_t work_bytes, void* stream);
+
+/* Launch statistics of the last chebyshev_moments call on this thread:
+ * number of recursion-step kernel launches, algorithmic bytes per launch
+ * (3 * storage size * sum over blocks of dim * columns), and the step kernel's
+ * float64 dot count.  Host only. */
+typedef struct {
+  int64_t step_launches;
+  double bytes_per_launch;
+  double state_col_steps;  /* sum over blocks of dim * real columns * steps */
+  int32_t col_block;       /* columns per block chosen */
+  int32_t rows_per_tile;   /* rows per workgroup tile chosen */
+  int32_t graph_segment;   /* steps per captured graph (0 = no graph) */
+  int32_t reserved;
+} kpm_run_stats;
+int kpm_last_run_stats(kpm_run_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KPM_H */

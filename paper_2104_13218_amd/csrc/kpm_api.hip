@@ -1,0 +1,1039 @@
+// C ABI of the Chebyshev-moment library (include/kpm.h): argument checks,
+// planning of (problem, column block, tile) work, workspace layout, Lanczos
+// bounds, the graph-segmented recursion driver and the thermodynamics calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "kpm.h"
+#include "kpm_internal.h"
+
+using namespace kpm;
+
+namespace {
+
+thread_local kpm_run_stats g_stats{};
+
+#define KPM_HIP(expr)                                  \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return KPM_EDEVICE;          \
+  } while (0)
+
+// ------------------------------------------------------------------ host math
+
+uint64_t binom64(int n, int k) {
+  if (k < 0 || n < 0 || k > n) return 0;
+  if (k > n - k) k = n - k;
+  uint64_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (uint64_t)(n - k + i) / (uint64_t)i;
+  return r;
+}
+
+std::vector<uint32_t> binom_table() {
+  std::vector<uint32_t> t(kBinomN * kBinomN, 0);
+  for (int n = 0; n < kBinomN; ++n)
+    for (int j = 0; j < kBinomN; ++j) t[n * kBinomN + j] = (uint32_t)binom64(n, j);
+  return t;
+}
+
+struct Split {
+  int B0, B1, B2;
+  size_t len() const { return (size_t(1) << B0) + (size_t(1) << B1) * (B0 + 1) + (size_t(1) << B2); }
+};
+
+// Three-way split of the N bits minimising the rank-table size.
+Split choose_split(int N) {
+  Split best{N, 0, 0};
+  size_t best_len = SIZE_MAX;
+  for (int B0 = 1; B0 <= N; ++B0)
+    for (int B1 = 0; B0 + B1 <= N; ++B1) {
+      const int B2 = N - B0 - B1;
+      if (B0 + B1 > 31) continue;
+      Split s{B0, B1, B2};
+      if (s.len() < best_len) {
+        best_len = s.len();
+        best = s;
+      }
+    }
+  return best;
+}
+
+// Rank tables of sector (N, k): rank(s) = T0[x0] + T1[x1][popc(x0)] + T2[x2]
+// where each table sums C(position, index) over the set bits it covers.
+void build_tables(int N, int k, Split sp, std::vector<uint32_t>& out) {
+  (void)N;
+  const size_t o0 = out.size();
+  out.resize(o0 + sp.len(), 0u);
+  uint32_t* T0 = out.data() + o0;
+  uint32_t* T1 = T0 + (size_t(1) << sp.B0);
+  uint32_t* T2 = T1 + (size_t(1) << sp.B1) * (sp.B0 + 1);
+  for (uint32_t x = 0; x < (1u << sp.B0); ++x) {
+    uint64_t r = 0;
+    int j = 0;
+    for (int q = 0; q < sp.B0; ++q)
+      if (x >> q & 1) r += binom64(q, ++j);
+    T0[x] = (uint32_t)r;
+  }
+  for (uint32_t x = 0; x < (1u << sp.B1); ++x)
+    for (int c = 0; c <= sp.B0; ++c) {
+      uint64_t r = 0;
+      int j = c;
+      for (int q = 0; q < sp.B1; ++q)
+        if (x >> q & 1) r += binom64(sp.B0 + q, ++j);
+      T1[(size_t)x * (sp.B0 + 1) + c] = (uint32_t)r;
+    }
+  for (uint32_t x = 0; x < (1u << sp.B2); ++x) {
+    int j = k - __builtin_popcount(x);
+    uint64_t r = 0;
+    if (j >= 0)
+      for (int q = 0; q < sp.B2; ++q)
+        if (x >> q & 1) r += binom64(sp.B0 + sp.B1 + q, ++j);
+    T2[x] = (uint32_t)r;
+  }
+}
+
+// ------------------------------------------------------------------ validation
+
+int check_problem(const kpm_problem& p) {
+  if (p.n_sites < 1 || p.n_sites > 32) return KPM_EINVAL;
+  if (2 * p.n_up < p.n_sites || p.n_up > p.n_sites) return KPM_EINVAL;
+  if (p.n_bonds < 0 || p.n_bonds > kMaxBonds) return KPM_EINVAL;
+  if (p.cluster < 0 || p.cluster > 65535) return KPM_EINVAL;
+  if (p.n_bonds > 0 && (!p.bond_i || !p.bond_j || !p.J)) return KPM_EINVAL;
+  for (int b = 0; b < p.n_bonds; ++b) {
+    const int i = p.bond_i[b], j = p.bond_j[b];
+    if (i < 0 || j < 0 || i >= p.n_sites || j >= p.n_sites || i == j) return KPM_EINVAL;
+    if (!std::isfinite(p.J[b])) return KPM_EINVAL;
+  }
+  const bool lo_nan = std::isnan(p.e_lo), hi_nan = std::isnan(p.e_hi);
+  if (!lo_nan && !hi_nan) {
+    if (!std::isfinite(p.e_lo) || !std::isfinite(p.e_hi) || !(p.e_hi > p.e_lo)) return KPM_EINVAL;
+  }
+  return KPM_OK;
+}
+
+int check_params(const kpm_params& q) {
+  if (!(q.eps >= 0.0 && q.eps < 1.0)) return KPM_EINVAL;
+  if (q.M < 2 || q.M > (1 << 22)) return KPM_EINVAL;
+  if (q.vec_kind < 0 || q.vec_kind > 3) return KPM_EINVAL;
+  if (q.vec_kind != KPM_VEC_BASIS && (q.R < 1 || q.R > 1024)) return KPM_EINVAL;
+  if (q.precision != KPM_FP64 && q.precision != KPM_FP32_STORE) return KPM_EINVAL;
+  if (q.col_block < 0 || q.col_block > kMaxLd) return KPM_EINVAL;
+  if (q.lanczos_steps < 0 || q.lanczos_steps > 100000) return KPM_EINVAL;
+  if (!(q.bound_margin >= 0.0) || !std::isfinite(q.bound_margin)) return KPM_EINVAL;
+  return KPM_OK;
+}
+
+int check_problems(const kpm_problem* p, int n) {
+  if (!p || n < 1) return KPM_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    const int r = check_problem(p[i]);
+    if (r != KPM_OK) return r;
+  }
+  return KPM_OK;
+}
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// ------------------------------------------------------------------ planning
+
+struct RunShape {
+  int precision = KPM_FP64;
+  int vec_kind = KPM_VEC_RADEMACHER;
+  int R = 1;
+  int col_block = 0;
+};
+
+// Columns per vector: a complex vector is two real columns (Re, Im).
+int cols_per_vec(int vec_kind) { return vec_kind == KPM_VEC_COMPLEX_GAUSSIAN ? 2 : 1; }
+
+int64_t total_columns(const kpm_problem& p, const RunShape& s) {
+  if (s.vec_kind == KPM_VEC_BASIS) return (int64_t)binom64(p.n_sites, p.n_up);
+  return (int64_t)s.R * cols_per_vec(s.vec_kind);
+}
+
+struct Planned {
+  std::vector<ProbDev> probs;
+  std::vector<UnitDev> units;
+  std::vector<int32_t> tile_unit, job_unit, prob_unit0;
+  std::vector<uint32_t> tables, bmask, binom;
+  std::vector<double> boff, bzz;
+  DevicePlan plan;
+  double bytes_per_step = 0;     // algorithmic (3 * storage * dim * real columns)
+  double state_cols = 0;         // sum of dim * real columns
+  // byte offsets of the packed plan arrays
+  size_t o_probs, o_units, o_tile, o_job, o_pu0, o_tab, o_mask, o_off, o_zz, o_binom, bytes;
+};
+
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v ? std::atoi(v) : dflt;
+}
+
+// Column block: all of a problem's columns up to 32 (float32 storage) or 16
+// (float64), rounded to whole vectors; an explicit col_block wins.
+int pick_col_block(const kpm_problem* p, int n, const RunShape& s) {
+  const int cpv = cols_per_vec(s.vec_kind);
+  int64_t maxc = 1;
+  for (int i = 0; i < n; ++i) maxc = std::max<int64_t>(maxc, total_columns(p[i], s));
+  int rb = s.col_block > 0 ? s.col_block : (s.precision == KPM_FP32_STORE ? 32 : 16);
+  rb = (int)std::min<int64_t>(rb, maxc);
+  rb = (rb + cpv - 1) / cpv * cpv;
+  return std::min(rb, kMaxLd);
+}
+
+// a, b per problem must already be known (scale != nullptr) for the bond
+// values; sizes do not depend on them.
+int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_arr,
+              const double* b_arr, Planned& P) {
+  const int fp32 = s.precision == KPM_FP32_STORE;
+  const int rb = pick_col_block(p, n, s);
+  int cpl = 1;
+  if (fp32) cpl = rb >= 4 ? 4 : (rb >= 2 ? 2 : 1);
+  else cpl = rb >= 2 ? 2 : 1;
+  if (const int f = env_int("KPM_CPL", 0)) cpl = f;
+  const int elt = fp32 ? 4 : 8;
+
+  P.binom = binom_table();
+  int max_bonds = 1, max_tab = 1;
+  int64_t max_dim = 1;
+  size_t bond_total = 0;
+  for (int i = 0; i < n; ++i) {
+    ProbDev d{};
+    d.dim = (int64_t)binom64(p[i].n_sites, p[i].n_up);
+    d.n_sites = p[i].n_sites;
+    d.n_up = p[i].n_up;
+    d.n_bonds = p[i].n_bonds;
+    d.bond_off = (int32_t)bond_total;
+    const Split sp = choose_split(p[i].n_sites);
+    d.B0 = sp.B0;
+    d.B1 = sp.B1;
+    d.B2 = sp.B2;
+    d.tab_off = (int32_t)P.tables.size();
+    d.tab_len = (int32_t)sp.len();
+    build_tables(p[i].n_sites, p[i].n_up, sp, P.tables);
+    d.cluster = p[i].cluster;
+    const double a = a_arr ? a_arr[i] : 1.0, b = b_arr ? b_arr[i] : 0.0;
+    d.shift = -b / a;
+    d.inv_a = 1.0 / a;
+    for (int k = 0; k < p[i].n_bonds; ++k) {
+      P.bmask.push_back((1u << p[i].bond_i[k]) | (1u << p[i].bond_j[k]));
+      P.boff.push_back(p[i].J[k] / (2.0 * a));
+      P.bzz.push_back(p[i].J[k] / (4.0 * a));
+    }
+    bond_total += p[i].n_bonds;
+    max_bonds = std::max(max_bonds, p[i].n_bonds);
+    max_tab = std::max(max_tab, d.tab_len);
+    max_dim = std::max(max_dim, d.dim);
+    P.probs.push_back(d);
+  }
+  if (P.bmask.empty()) {
+    P.bmask.push_back(0);
+    P.boff.push_back(0);
+    P.bzz.push_back(0);
+  }
+
+  DevicePlan& D = P.plan;
+  D.fp32 = fp32;
+  D.cpl = cpl;
+  D.lds_tab = max_tab;
+  D.lds_bonds = max_bonds;
+  D.lds_nb = max_bonds;
+  D.sub_rows = 256;
+  const size_t lds_cap = (size_t)env_int("KPM_LDS_CAP", 64 * 1024);
+  while (step_lds_bytes(D) > lds_cap && D.sub_rows > 32) D.sub_rows >>= 1;
+  if (step_lds_bytes(D) > lds_cap) return KPM_EINVAL;
+
+  // Rows per workgroup tile: enough rows to amortise the per-tile LDS fill,
+  // but keep >= 2048 tiles on the largest block when its size permits.
+  const size_t fixed = kBinomN * kBinomN * 4 + (size_t)max_tab * 4 + (size_t)max_bonds * 20;
+  const int ldmax = (rb + cpl - 1) / cpl * cpl;
+  const double per_row = 3.0 * ldmax * elt;
+  int spt = (int)std::ceil(16.0 * fixed / (per_row * D.sub_rows));
+  const int64_t par = max_dim / (2048LL * D.sub_rows);
+  spt = (int)std::max<int64_t>(1, std::min<int64_t>(spt, std::max<int64_t>(1, par)));
+  spt = std::min(spt, 64);
+  if (const int f = env_int("KPM_SUB_PER_TILE", 0)) spt = f;
+  D.sub_per_tile = spt;
+  const int64_t tile_rows = (int64_t)D.sub_rows * spt;
+
+  int64_t vec_elems = 0, part_len = 0;
+  int32_t tiles = 0, col_off = 0;
+  for (int i = 0; i < n; ++i) {
+    P.prob_unit0.push_back((int32_t)P.units.size());
+    const int64_t nc = total_columns(p[i], s);
+    const int64_t dim = P.probs[i].dim;
+    for (int64_t c0 = 0; c0 < nc; c0 += rb) {
+      UnitDev u{};
+      u.prob = i;
+      u.ncols = (int32_t)std::min<int64_t>(rb, nc - c0);
+      u.ld = (u.ncols + cpl - 1) / cpl * cpl;
+      u.col0 = (int32_t)c0;
+      u.vec_off = vec_elems;
+      vec_elems += (int64_t)align_up((size_t)(2 * dim * u.ld), 64);
+      u.ntiles = (int32_t)((dim + tile_rows - 1) / tile_rows);
+      u.tile0 = tiles;
+      u.part_off = part_len;
+      part_len += (int64_t)2 * u.ld * u.ntiles;
+      u.col_off = col_off;
+      for (int t = 0; t < u.ntiles; ++t) P.tile_unit.push_back((int32_t)P.units.size());
+      for (int j = 0; j < 2 * u.ld; ++j) P.job_unit.push_back((int32_t)P.units.size());
+      tiles += u.ntiles;
+      col_off += u.ld;
+      P.bytes_per_step += 3.0 * elt * (double)dim * u.ncols;
+      P.state_cols += (double)dim * u.ncols;
+      P.units.push_back(u);
+    }
+  }
+  P.prob_unit0.push_back((int32_t)P.units.size());
+  D.n_probs = n;
+  D.n_units = (int32_t)P.units.size();
+  D.n_tiles = tiles;
+  D.grid_tiles = (tiles + 7) / 8 * 8;
+  D.total_cols = col_off;
+  D.part_len = std::max<int64_t>(part_len, 1);
+  D.vec_elems = vec_elems;
+
+  size_t o = 0;
+  auto put = [&](size_t bytes) {
+    const size_t r = o;
+    o = align_up(o + bytes);
+    return r;
+  };
+  P.o_probs = put(P.probs.size() * sizeof(ProbDev));
+  P.o_units = put(P.units.size() * sizeof(UnitDev));
+  P.o_tile = put(P.tile_unit.size() * 4);
+  P.o_job = put(P.job_unit.size() * 4);
+  P.o_pu0 = put(P.prob_unit0.size() * 4);
+  P.o_tab = put(P.tables.size() * 4);
+  P.o_mask = put(P.bmask.size() * 4);
+  P.o_off = put(P.boff.size() * 8);
+  P.o_zz = put(P.bzz.size() * 8);
+  P.o_binom = put(P.binom.size() * 4);
+  P.bytes = o;
+  return KPM_OK;
+}
+
+// Copy the plan arrays to `dst` (device) and point the DevicePlan at them.
+int upload_plan(Planned& P, unsigned char* dst, std::vector<unsigned char>& staging,
+                hipStream_t st) {
+  staging.assign(P.bytes, 0);
+  auto cp = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(staging.data() + off, src, bytes);
+  };
+  cp(P.o_probs, P.probs.data(), P.probs.size() * sizeof(ProbDev));
+  cp(P.o_units, P.units.data(), P.units.size() * sizeof(UnitDev));
+  cp(P.o_tile, P.tile_unit.data(), P.tile_unit.size() * 4);
+  cp(P.o_job, P.job_unit.data(), P.job_unit.size() * 4);
+  cp(P.o_pu0, P.prob_unit0.data(), P.prob_unit0.size() * 4);
+  cp(P.o_tab, P.tables.data(), P.tables.size() * 4);
+  cp(P.o_mask, P.bmask.data(), P.bmask.size() * 4);
+  cp(P.o_off, P.boff.data(), P.boff.size() * 8);
+  cp(P.o_zz, P.bzz.data(), P.bzz.size() * 8);
+  cp(P.o_binom, P.binom.data(), P.binom.size() * 4);
+  KPM_HIP(hipMemcpyAsync(dst, staging.data(), P.bytes, hipMemcpyHostToDevice, st));
+  DevicePlan& D = P.plan;
+  D.probs = reinterpret_cast<ProbDev*>(dst + P.o_probs);
+  D.units = reinterpret_cast<UnitDev*>(dst + P.o_units);
+  D.tile_unit = reinterpret_cast<int32_t*>(dst + P.o_tile);
+  D.job_unit = reinterpret_cast<int32_t*>(dst + P.o_job);
+  D.prob_unit0 = reinterpret_cast<int32_t*>(dst + P.o_pu0);
+  D.tables = reinterpret_cast<uint32_t*>(dst + P.o_tab);
+  D.bmask = reinterpret_cast<uint32_t*>(dst + P.o_mask);
+  D.boff = reinterpret_cast<double*>(dst + P.o_off);
+  D.bzz = reinterpret_cast<double*>(dst + P.o_zz);
+  D.binom = reinterpret_cast<uint32_t*>(dst + P.o_binom);
+  return KPM_OK;
+}
+
+// Synchronises the stream when an entry point returns, so that host staging
+// buffers of asynchronous copies outlive the copies on every return path.
+struct StreamSync {
+  hipStream_t st;
+  ~StreamSync() { (void)hipStreamSynchronize(st); }
+};
+
+// Device memory owned by the library for one call.
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  int alloc(size_t bytes) {
+    if (hipMalloc(&p, bytes ? bytes : 256) != hipSuccess) {
+      p = nullptr;
+      return KPM_ENOMEM;
+    }
+    return KPM_OK;
+  }
+};
+
+// ------------------------------------------------------------- Lanczos bounds
+
+struct LzLayout {
+  size_t plan, vec, vecC, part, dots, b2, zero, err, total;
+};
+
+LzLayout lanczos_layout(const Planned& P, int steps) {
+  LzLayout L{};
+  size_t o = 0;
+  auto put = [&](size_t bytes) {
+    const size_t r = o;
+    o = align_up(o + bytes);
+    return r;
+  };
+  L.plan = put(P.bytes);
+  L.vec = put((size_t)P.plan.vec_elems * 8);
+  L.vecC = put((size_t)P.plan.vec_elems * 8);
+  L.part = put((size_t)P.plan.part_len * 8);
+  L.dots = put((size_t)steps * P.plan.total_cols * 8);
+  L.b2 = put((size_t)steps * P.plan.total_cols * 8);
+  L.zero = put((size_t)P.plan.total_cols * 8);
+  L.err = put(256);
+  L.total = o;
+  return L;
+}
+
+size_t lanczos_bytes(const kpm_problem* p, int n, int steps) {
+  RunShape s;
+  s.precision = KPM_FP64;
+  s.vec_kind = KPM_VEC_RADEMACHER;
+  s.R = 1;
+  s.col_block = 1;
+  Planned P;
+  if (make_plan(p, n, s, nullptr, nullptr, P) != KPM_OK) return 0;
+  return lanczos_layout(P, steps).total;
+}
+
+// Extreme eigenvalues of the symmetric tridiagonal (diag a, off b) by
+// bisection on Sturm counts.
+double tri_count_below(const std::vector<double>& a, const std::vector<double>& b, double x) {
+  int cnt = 0;
+  double q = 1.0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const double bb = i ? b[i - 1] * b[i - 1] : 0.0;
+    q = a[i] - x - (i ? bb / q : 0.0);
+    if (q == 0.0) q = -1e-300;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+void tri_extremes(const std::vector<double>& a, const std::vector<double>& b, double& lo,
+                  double& hi) {
+  double gl = INFINITY, gu = -INFINITY;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const double r = (i ? std::fabs(b[i - 1]) : 0.0) + (i < b.size() ? std::fabs(b[i]) : 0.0);
+    gl = std::min(gl, a[i] - r);
+    gu = std::max(gu, a[i] + r);
+  }
+  const int n = (int)a.size();
+  auto kth = [&](int k) {   // k-th smallest (0-based)
+    double l = gl, u = gu;
+    for (int it = 0; it < 200; ++it) {
+      const double m = 0.5 * (l + u);
+      if (m <= l || m >= u) break;
+      if (tri_count_below(a, b, m) > k) u = m;
+      else l = m;
+    }
+    return 0.5 * (l + u);
+  };
+  lo = kth(0);
+  hi = kth(n - 1);
+}
+
+// Batched Lanczos over every problem (one float64 column each): the A/B
+// buffers of a block hold q_j and w, a third buffer holds q_{j-1}.
+int run_lanczos(const kpm_problem* p, int n, int steps, double margin, uint64_t seed,
+                double* e_lo_hi, unsigned char* work, hipStream_t st) {
+  RunShape s;
+  s.precision = KPM_FP64;
+  s.vec_kind = KPM_VEC_RADEMACHER;
+  s.R = 1;
+  s.col_block = 1;
+  Planned P;
+  int r = make_plan(p, n, s, nullptr, nullptr, P);
+  if (r != KPM_OK) return r;
+  for (auto& u : P.units) u.col0 = 1023;   // RNG stream r = 1023 for the start vector
+  int64_t max_dim = 1;
+  for (auto& d : P.probs) max_dim = std::max(max_dim, d.dim);
+  const int nsteps = (int)std::max<int64_t>(1, std::min<int64_t>(steps, max_dim));
+  const LzLayout L = lanczos_layout(P, nsteps);
+  std::vector<unsigned char> staging;
+  r = upload_plan(P, work + L.plan, staging, st);
+  if (r != KPM_OK) return r;
+  DevicePlan& D = P.plan;
+  D.err = reinterpret_cast<int*>(work + L.err);
+  KPM_HIP(hipMemsetAsync(D.err, 0, sizeof(int), st));
+  double* vec = reinterpret_cast<double*>(work + L.vec);
+  double* vecC = reinterpret_cast<double*>(work + L.vecC);
+  double* part = reinterpret_cast<double*>(work + L.part);
+  double* dots = reinterpret_cast<double*>(work + L.dots);
+  double* b2 = reinterpret_cast<double*>(work + L.b2);
+  double* zero = reinterpret_cast<double*>(work + L.zero);
+  const int TC = D.total_cols;
+  KPM_HIP(hipMemsetAsync(vec, 0, (size_t)D.vec_elems * 8, st));
+  KPM_HIP(hipMemsetAsync(vecC, 0, (size_t)D.vec_elems * 8, st));
+  KPM_HIP(hipMemsetAsync(zero, 0, (size_t)TC * 8, st));
+  KPM_HIP(launch_init(D, vec, 2, KPM_VEC_RADEMACHER, seed, nullptr, part, st));
+  for (int j = 0; j < nsteps; ++j) {
+    // w = H q_j  (A -> B; a = 1, b = 0 so H' = H)
+    KPM_HIP(launch_step(D, vec, part, nullptr, 0, nullptr, nullptr, nullptr, 0, 0, 1, st));
+    // w -= beta_{j-1} q_{j-1};  alpha_j = <w, q_j>
+    LzArgs a1{};
+    a1.w = vec; a1.w_hi = 1;
+    a1.q = vecC; a1.q_hi = 0;
+    a1.coef = j ? b2 + (size_t)(j - 1) * TC : zero;
+    a1.coef_sqrt = 1;
+    a1.dotvec = vec; a1.d_hi = 0;
+    a1.part_out = part;
+    KPM_HIP(launch_lz_axpy(D, a1, st));
+    KPM_HIP(launch_reduce(D, part, dots + (size_t)j * TC, nullptr, st));
+    // w -= alpha_j q_j;  beta_j^2 = <w, w>
+    LzArgs a2{};
+    a2.w = vec; a2.w_hi = 1;
+    a2.q = vec; a2.q_hi = 0;
+    a2.coef = dots + (size_t)j * TC;
+    a2.dotvec = nullptr;
+    a2.part_out = part;
+    KPM_HIP(launch_lz_axpy(D, a2, st));
+    KPM_HIP(launch_reduce(D, part, b2 + (size_t)j * TC, nullptr, st));
+    KPM_HIP(launch_lz_next(D, vecC, vec, vec, b2 + (size_t)j * TC, st));
+  }
+  std::vector<double> h_dots((size_t)nsteps * TC), h_b2((size_t)nsteps * TC);
+  int h_err = 0;
+  KPM_HIP(hipMemcpyAsync(h_dots.data(), dots, h_dots.size() * 8, hipMemcpyDeviceToHost, st));
+  KPM_HIP(hipMemcpyAsync(h_b2.data(), b2, h_b2.size() * 8, hipMemcpyDeviceToHost, st));
+  KPM_HIP(hipMemcpyAsync(&h_err, D.err, sizeof(int), hipMemcpyDeviceToHost, st));
+  KPM_HIP(hipStreamSynchronize(st));
+  if (h_err) return KPM_EDEVICE;
+  for (int i = 0; i < n; ++i) {
+    const int col = P.units[P.prob_unit0[i]].col_off;
+    const int steps_i = (int)std::min<int64_t>(steps, P.probs[i].dim);
+    std::vector<double> av, bv;
+    for (int j = 0; j < steps_i; ++j) {
+      av.push_back(h_dots[(size_t)j * TC + col]);
+      const double bn = std::sqrt(std::max(h_b2[(size_t)j * TC + col], 0.0));
+      if (j == steps_i - 1 || bn < 1e-12) break;
+      bv.push_back(bn);
+    }
+    double lo, hi;
+    tri_extremes(av, bv, lo, hi);
+    const double W = hi - lo;
+    if (W < 1e-8 * std::max({1.0, std::fabs(lo), std::fabs(hi)})) {
+      e_lo_hi[2 * i] = lo - 0.5;
+      e_lo_hi[2 * i + 1] = hi + 0.5;
+    } else {
+      e_lo_hi[2 * i] = lo - margin * W;
+      e_lo_hi[2 * i + 1] = hi + margin * W;
+    }
+  }
+  return KPM_OK;
+}
+
+// ------------------------------------------------------------ moments driver
+
+struct MomLayout {
+  size_t plan, vec, part0, part1, alpha, beta, norms, flag, base, lz, total;
+};
+
+MomLayout moments_layout(const Planned& P, int K, size_t lz_bytes) {
+  MomLayout L{};
+  size_t o = 0;
+  auto put = [&](size_t bytes) {
+    const size_t r = o;
+    o = align_up(o + bytes);
+    return r;
+  };
+  const size_t elt = P.plan.fp32 ? 4 : 8;
+  const size_t TC = (size_t)P.plan.total_cols;
+  L.plan = put(P.bytes);
+  L.lz = o;   // Lanczos runs first and may reuse everything below
+  L.vec = put((size_t)P.plan.vec_elems * elt);
+  L.part0 = put((size_t)P.plan.part_len * 8);
+  L.part1 = put((size_t)P.plan.part_len * 8);
+  L.alpha = put((size_t)(K + 1) * TC * 8);
+  L.beta = put((size_t)K * TC * 8);
+  L.norms = put(TC * 8);
+  L.flag = put(256);
+  L.base = put(256);
+  L.total = std::max(o, align_up(L.lz + lz_bytes));
+  return L;
+}
+
+RunShape shape_of(const kpm_params& q) {
+  RunShape s;
+  s.precision = q.precision;
+  s.vec_kind = q.vec_kind;
+  s.R = q.R;
+  s.col_block = q.col_block;
+  return s;
+}
+
+int n_steps(int M) { return std::max(1, M / 2); }
+
+int lanczos_steps_of(const kpm_params& q) { return q.lanczos_steps > 0 ? q.lanczos_steps : 50; }
+
+size_t moments_workspace(const kpm_problem* p, int n, const kpm_params& q) {
+  std::vector<kpm_problem> need;
+  for (int i = 0; i < n; ++i)
+    if (std::isnan(p[i].e_lo) || std::isnan(p[i].e_hi)) need.push_back(p[i]);
+  const size_t lz = need.empty() ? 0 : lanczos_bytes(need.data(), (int)need.size(), lanczos_steps_of(q));
+  Planned P;
+  if (make_plan(p, n, shape_of(q), nullptr, nullptr, P) != KPM_OK) return 0;
+  return moments_layout(P, n_steps(q.M), lz).total;
+}
+
+int graph_segment() {
+  int S = env_int("KPM_GRAPH_SEGMENT", 64);
+  if (S < 0) S = 0;
+  return S & ~1;
+}
+
+// Init, K recursion steps (graph-captured segments), final reduction,
+// doubling identities and estimator.
+int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_params& q,
+                double* d_mu, hipStream_t st) {
+  DevicePlan& D = P.plan;
+  const int K = n_steps(q.M);
+  const int TC = D.total_cols;
+  void* vec = work + L.vec;
+  double* part[2] = {reinterpret_cast<double*>(work + L.part0),
+                     reinterpret_cast<double*>(work + L.part1)};
+  double* alpha = reinterpret_cast<double*>(work + L.alpha);
+  double* beta = reinterpret_cast<double*>(work + L.beta);
+  double* norms = reinterpret_cast<double*>(work + L.norms);
+  int* flag = reinterpret_cast<int*>(work + L.flag);
+  int64_t* base = reinterpret_cast<int64_t*>(work + L.base);
+  P.plan.err = flag;
+  KPM_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+
+  if (q.vec_kind == KPM_VEC_GAUSSIAN || q.vec_kind == KPM_VEC_COMPLEX_GAUSSIAN) {
+    KPM_HIP(launch_init(D, vec, 0, q.vec_kind, q.seed, nullptr, part[0], st));
+    KPM_HIP(launch_reduce(D, part[0], norms, nullptr, st));
+  }
+  KPM_HIP(launch_init(D, vec, 1, q.vec_kind, q.seed, norms, part[0], st));
+  KPM_HIP(launch_reduce(D, part[0], alpha, nullptr, st));
+  KPM_HIP(launch_step(D, vec, part[0], nullptr, 0, alpha, beta, nullptr, 0, 0, 1, st));
+  int s = 1;
+  const int S = graph_segment();
+  int used_segment = 0;
+  if (S >= 2 && K - 1 >= S) {
+    hipStream_t cap;
+    KPM_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+    for (int j = 0; j < S && e == hipSuccess; ++j)
+      e = launch_step(D, vec, part[(1 + j) & 1], part[j & 1], 2 * TC, alpha, beta, base, j,
+                      (1 + j) & 1, 0, cap);
+    hipError_t e2 = hipStreamEndCapture(cap, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    while (e == hipSuccess && s + S <= K) {
+      e = launch_set_i64(base, s, st);
+      if (e == hipSuccess) e = hipGraphLaunch(exec, st);
+      s += S;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return KPM_EDEVICE;
+    used_segment = S;
+  }
+  for (; s < K; ++s)
+    KPM_HIP(launch_step(D, vec, part[s & 1], part[(s - 1) & 1], 2 * TC, alpha, beta, nullptr, s,
+                        s & 1, 0, st));
+  KPM_HIP(launch_reduce(D, part[(K - 1) & 1], alpha + (size_t)K * TC, beta + (size_t)(K - 1) * TC, st));
+  FinalArgs fa{};
+  fa.probs = D.probs;
+  fa.units = D.units;
+  fa.prob_unit0 = D.prob_unit0;
+  fa.alpha = alpha;
+  fa.beta = beta;
+  fa.mu = d_mu;
+  fa.flag = flag;
+  fa.n_probs = D.n_probs;
+  fa.M = q.M;
+  fa.total_cols = TC;
+  fa.cols_per_vec = cols_per_vec(q.vec_kind);
+  fa.R = q.vec_kind == KPM_VEC_BASIS ? 0 : q.R;
+  KPM_HIP(launch_finalize(fa, st));
+  int h_flag = 0;
+  KPM_HIP(hipMemcpyAsync(&h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  KPM_HIP(hipStreamSynchronize(st));
+
+  g_stats.step_launches = K;
+  g_stats.bytes_per_launch = P.bytes_per_step;
+  g_stats.state_col_steps = P.state_cols * K;
+  g_stats.col_block = 0;
+  for (auto& u : P.units) g_stats.col_block = std::max(g_stats.col_block, u.ncols);
+  g_stats.rows_per_tile = D.sub_rows * D.sub_per_tile;
+  g_stats.graph_segment = used_segment;
+  if (h_flag & 2) return KPM_EDEVICE;
+  return (h_flag & 1) ? KPM_EBOUNDS : KPM_OK;
+}
+
+// Resolve bounds (Lanczos where NaN) and the (a, b) of Eq. (5).
+int resolve_scale(const kpm_problem* p, int n, const kpm_params& q, unsigned char* lz_work,
+                  hipStream_t st, std::vector<double>& a, std::vector<double>& b) {
+  std::vector<kpm_problem> need;
+  std::vector<int> idx;
+  for (int i = 0; i < n; ++i)
+    if (std::isnan(p[i].e_lo) || std::isnan(p[i].e_hi)) {
+      need.push_back(p[i]);
+      idx.push_back(i);
+    }
+  std::vector<double> lohi(2 * n);
+  for (int i = 0; i < n; ++i) {
+    lohi[2 * i] = p[i].e_lo;
+    lohi[2 * i + 1] = p[i].e_hi;
+  }
+  if (!need.empty()) {
+    std::vector<double> got(2 * need.size());
+    const int r = run_lanczos(need.data(), (int)need.size(), lanczos_steps_of(q), q.bound_margin,
+                              q.seed, got.data(), lz_work, st);
+    if (r != KPM_OK) return r;
+    for (size_t j = 0; j < idx.size(); ++j) {
+      lohi[2 * idx[j]] = got[2 * j];
+      lohi[2 * idx[j] + 1] = got[2 * j + 1];
+    }
+  }
+  a.resize(n);
+  b.resize(n);
+  for (int i = 0; i < n; ++i) {
+    a[i] = (lohi[2 * i + 1] - lohi[2 * i]) / (2.0 - q.eps);
+    b[i] = 0.5 * (lohi[2 * i + 1] + lohi[2 * i]);
+    if (!(a[i] > 0.0) || !std::isfinite(a[i]) || !std::isfinite(b[i])) return KPM_EINVAL;
+  }
+  return KPM_OK;
+}
+
+// Thermodynamic metadata: per-problem table and problems grouped by cluster.
+int thermo_meta(const kpm_problem* p, int n, std::vector<ThermoProb>& tp,
+                std::vector<int32_t>& start, std::vector<int32_t>& list, int& n_clusters) {
+  if (!p || n < 1) return KPM_EINVAL;
+  n_clusters = 0;
+  for (int i = 0; i < n; ++i) {
+    if (p[i].n_sites < 1 || p[i].n_sites > 64 || 2 * p[i].n_up < p[i].n_sites ||
+        p[i].n_up > p[i].n_sites || p[i].cluster < 0 || p[i].cluster > 65535)
+      return KPM_EINVAL;
+    n_clusters = std::max(n_clusters, p[i].cluster + 1);
+  }
+  tp.resize(n);
+  start.assign(n_clusters + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    tp[i].cluster = p[i].cluster;
+    tp[i].weight = 2 * p[i].n_up == p[i].n_sites ? 1 : 2;
+    tp[i].sz = p[i].n_up - 0.5 * p[i].n_sites;
+    start[p[i].cluster + 1]++;
+  }
+  for (int c = 0; c < n_clusters; ++c) {
+    if (start[c + 1] == 0) return KPM_EINVAL;   // cluster ids must be dense
+    start[c + 1] += start[c];
+  }
+  list.assign(n, 0);
+  std::vector<int32_t> fill(start.begin(), start.end() - 1);
+  for (int i = 0; i < n; ++i) list[fill[p[i].cluster]++] = i;
+  return KPM_OK;
+}
+
+struct ThermoDev {
+  DevBuf buf;
+  double* g = nullptr;
+  double* gamma = nullptr;
+  double* stats = nullptr;
+  double* adj = nullptr;
+  ThermoProb* tp = nullptr;
+  int32_t* start = nullptr;
+  int32_t* list = nullptr;
+};
+
+int thermo_forward(const double* d_mu, const double* d_ab, const kpm_problem* p, int n, int M,
+                   int kernel, int n_nodes, const double* d_T, int n_T, double* lnZ, double* E,
+                   double* C, double* chi, uint8_t* znonpos, hipStream_t st, ThermoDev& TD,
+                   std::vector<ThermoProb>& tp, int& n_clusters, bool keep_adj) {
+  if (!d_mu || !d_ab || !d_T || M < 1 || n_T < 1 || n_nodes < 0 || (kernel != 0 && kernel != 1))
+    return KPM_EINVAL;
+  std::vector<int32_t> start, list;
+  int r = thermo_meta(p, n, tp, start, list, n_clusters);
+  if (r != KPM_OK) return r;
+  const int Nt = n_nodes ? n_nodes : M;
+  size_t o = 0;
+  auto put = [&](size_t bytes) {
+    const size_t rr = o;
+    o = align_up(o + bytes);
+    return rr;
+  };
+  const size_t og = put((size_t)M * 8), ogam = put((size_t)n * Nt * 8),
+               ost = put((size_t)n_clusters * n_T * 6 * 8),
+               oadj = put(keep_adj ? (size_t)n * Nt * 8 : 8), otp = put(tp.size() * sizeof(ThermoProb)),
+               ostart = put(start.size() * 4), olist = put(list.size() * 4);
+  r = TD.buf.alloc(o);
+  if (r != KPM_OK) return r;
+  unsigned char* w = static_cast<unsigned char*>(TD.buf.p);
+  TD.g = reinterpret_cast<double*>(w + og);
+  TD.gamma = reinterpret_cast<double*>(w + ogam);
+  TD.stats = reinterpret_cast<double*>(w + ost);
+  TD.adj = reinterpret_cast<double*>(w + oadj);
+  TD.tp = reinterpret_cast<ThermoProb*>(w + otp);
+  TD.start = reinterpret_cast<int32_t*>(w + ostart);
+  TD.list = reinterpret_cast<int32_t*>(w + olist);
+  KPM_HIP(hipMemcpyAsync(TD.tp, tp.data(), tp.size() * sizeof(ThermoProb), hipMemcpyHostToDevice, st));
+  KPM_HIP(hipMemcpyAsync(TD.start, start.data(), start.size() * 4, hipMemcpyHostToDevice, st));
+  KPM_HIP(hipMemcpyAsync(TD.list, list.data(), list.size() * 4, hipMemcpyHostToDevice, st));
+  KPM_HIP(launch_kernel_coef(M, kernel, TD.g, st));
+  KPM_HIP(launch_gamma(n, M, Nt, TD.g, d_mu, TD.gamma, st));
+  ThermoArgs ta{};
+  ta.tp = TD.tp;
+  ta.cl_start = TD.start;
+  ta.cl_list = TD.list;
+  ta.gamma = TD.gamma;
+  ta.ab = d_ab;
+  ta.T = d_T;
+  ta.lnZ = lnZ;
+  ta.E = E;
+  ta.C = C;
+  ta.chi = chi;
+  ta.znonpos = znonpos;
+  ta.stats = TD.stats;
+  ta.n_nodes = Nt;
+  ta.n_T = n_T;
+  ta.n_clusters = n_clusters;
+  KPM_HIP(launch_thermo(ta, st));
+  // the host staging vectors die with the caller's frame: finish the copies now
+  KPM_HIP(hipStreamSynchronize(st));
+  return KPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* kpm_strerror(int code) {
+  switch (code) {
+    case KPM_OK: return "ok";
+    case KPM_EINVAL: return "invalid argument";
+    case KPM_ENOMEM: return "device allocation failed";
+    case KPM_EDEVICE: return "HIP runtime error";
+    case KPM_EBOUNDS: return "spectral bounds do not enclose the spectrum (|mu_n| > mu_0)";
+    case KPM_EWORKSPACE: return "workspace too small";
+    default: return "unknown status";
+  }
+}
+
+uint64_t kpm_sector_dim(int32_t n_sites, int32_t n_up) {
+  if (n_sites < 0 || n_sites > 64) return 0;
+  return binom64(n_sites, n_up);
+}
+
+int kpm_last_run_stats(kpm_run_stats* out) {
+  if (!out) return KPM_EINVAL;
+  *out = g_stats;
+  return KPM_OK;
+}
+
+int kpm_sector_states(int32_t n_sites, int32_t n_up, uint32_t* d_states, void* stream) {
+  if (n_sites < 1 || n_sites > 32 || n_up < 0 || n_up > n_sites || !d_states) return KPM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StreamSync guard{st};
+  const int64_t dim = (int64_t)binom64(n_sites, n_up);
+  const std::vector<uint32_t> bt = binom_table();
+  DevBuf buf;
+  int r = buf.alloc(bt.size() * 4);
+  if (r != KPM_OK) return r;
+  KPM_HIP(hipMemcpyAsync(buf.p, bt.data(), bt.size() * 4, hipMemcpyHostToDevice, st));
+  KPM_HIP(launch_states(n_sites, n_up, static_cast<uint32_t*>(buf.p), d_states, dim, st));
+  KPM_HIP(hipStreamSynchronize(st));
+  return KPM_OK;
+}
+
+int kpm_sector_matrix(const kpm_problem* p, int64_t row0, int64_t nrows, int32_t max_nb,
+                      uint32_t* d_cols, int32_t* d_bond, int32_t* d_cnt, double* d_diag,
+                      void* stream) {
+  if (!p || check_problem(*p) != KPM_OK) return KPM_EINVAL;
+  const int64_t dim = (int64_t)binom64(p->n_sites, p->n_up);
+  if (row0 < 0 || nrows < 0 || row0 + nrows > dim || max_nb < p->n_bonds || max_nb < 1)
+    return KPM_EINVAL;
+  if (nrows == 0) return KPM_OK;
+  if (!d_cols || !d_bond || !d_cnt || !d_diag) return KPM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StreamSync guard{st};
+  RunShape s;
+  s.precision = KPM_FP64;
+  s.col_block = 1;
+  Planned P;
+  const double one = 1.0, zero = 0.0;
+  int r = make_plan(p, 1, s, &one, &zero, P);
+  if (r != KPM_OK) return r;
+  DevBuf buf;
+  r = buf.alloc(P.bytes);
+  if (r != KPM_OK) return r;
+  std::vector<unsigned char> staging;
+  r = upload_plan(P, static_cast<unsigned char*>(buf.p), staging, st);
+  if (r != KPM_OK) return r;
+  const DevicePlan& D = P.plan;
+  MatrixArgs a{};
+  a.probs = D.probs;
+  a.tables = D.tables;
+  a.bmask = D.bmask;
+  a.boff = D.boff;
+  a.bzz = D.bzz;
+  a.binom = D.binom;
+  a.row0 = row0;
+  a.nrows = nrows;
+  a.max_nb = max_nb;
+  a.lds_tab = D.lds_tab;
+  a.lds_bonds = D.lds_bonds;
+  a.sub_rows = D.sub_rows;
+  a.lds_nb = D.lds_nb;
+  a.cols = d_cols;
+  a.bond = d_bond;
+  a.cnt = d_cnt;
+  a.diag = d_diag;
+  const int64_t grid = (nrows + D.sub_rows - 1) / D.sub_rows;
+  if (grid > (1LL << 30)) return KPM_EINVAL;
+  KPM_HIP(launch_matrix(a, step_lds_bytes(D), (int)grid, st));
+  KPM_HIP(hipStreamSynchronize(st));
+  return KPM_OK;
+}
+
+int kpm_spectral_bounds(const kpm_problem* p, int32_t n, int32_t steps, double margin,
+                        uint64_t seed, double* e_lo_hi, void* stream) {
+  if (check_problems(p, n) != KPM_OK || steps < 1 || !(margin >= 0.0) || !e_lo_hi)
+    return KPM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StreamSync guard{st};
+  DevBuf buf;
+  int r = buf.alloc(lanczos_bytes(p, n, steps));
+  if (r != KPM_OK) return r;
+  return run_lanczos(p, n, steps, margin, seed, e_lo_hi, static_cast<unsigned char*>(buf.p), st);
+}
+
+size_t chebyshev_moments_workspace_size(const kpm_problem* p, int32_t n, const kpm_params* q) {
+  if (check_problems(p, n) != KPM_OK || !q || check_params(*q) != KPM_OK) return 0;
+  return moments_workspace(p, n, *q);
+}
+
+int chebyshev_moments(const kpm_problem* p, int32_t n, const kpm_params* q, double* d_mu,
+                      double* d_ab, void* d_work, size_t work_bytes, void* stream) {
+  int r = check_problems(p, n);
+  if (r != KPM_OK) return r;
+  if (!q || check_params(*q) != KPM_OK || !d_mu) return KPM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StreamSync guard{st};
+  const size_t need = moments_workspace(p, n, *q);
+  if (need == 0) return KPM_EINVAL;
+  DevBuf own;
+  unsigned char* work = static_cast<unsigned char*>(d_work);
+  if (!work) {
+    r = own.alloc(need);
+    if (r != KPM_OK) return r;
+    work = static_cast<unsigned char*>(own.p);
+  } else if (work_bytes < need) {
+    return KPM_EWORKSPACE;
+  }
+  // sizes first (plan without scale) to place the Lanczos region
+  Planned P0;
+  r = make_plan(p, n, shape_of(*q), nullptr, nullptr, P0);
+  if (r != KPM_OK) return r;
+  const MomLayout L0 = moments_layout(P0, n_steps(q->M), 0);
+  std::vector<double> a, b;
+  r = resolve_scale(p, n, *q, work + L0.lz, st, a, b);
+  if (r != KPM_OK) return r;
+  Planned P;
+  r = make_plan(p, n, shape_of(*q), a.data(), b.data(), P);
+  if (r != KPM_OK) return r;
+  const MomLayout L = moments_layout(P, n_steps(q->M), 0);
+  std::vector<unsigned char> staging;
+  r = upload_plan(P, work + L.plan, staging, st);
+  if (r != KPM_OK) return r;
+  std::vector<double> ab(2 * n);
+  for (int i = 0; i < n; ++i) {
+    ab[2 * i] = a[i];
+    ab[2 * i + 1] = b[i];
+  }
+  if (d_ab) KPM_HIP(hipMemcpyAsync(d_ab, ab.data(), ab.size() * 8, hipMemcpyHostToDevice, st));
+  return run_moments(P, L, work, *q, d_mu, st);
+}
+
+int kpm_thermo(const double* d_mu, const double* d_ab, const kpm_problem* p, int32_t n,
+               int32_t M, int32_t kernel, int32_t n_nodes, const double* d_T, int32_t n_T,
+               double* d_lnZ, double* d_E, double* d_C, double* d_chi, uint8_t* d_znonpos,
+               void* stream) {
+  if (!d_lnZ || !d_E || !d_C || !d_chi) return KPM_EINVAL;
+  ThermoDev TD;
+  std::vector<ThermoProb> tp;
+  int nc = 0;
+  return thermo_forward(d_mu, d_ab, p, n, M, kernel, n_nodes, d_T, n_T, d_lnZ, d_E, d_C, d_chi,
+                        d_znonpos, static_cast<hipStream_t>(stream), TD, tp, nc, false);
+}
+
+int kpm_thermo_vjp(const double* d_mu, const double* d_ab, const kpm_problem* p, int32_t n,
+                   int32_t M, int32_t kernel, int32_t n_nodes, const double* d_T, int32_t n_T,
+                   const double* d_wC, const double* d_wchi, double* d_lambda, void* stream) {
+  if (!d_wC || !d_wchi || !d_lambda) return KPM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<ThermoProb> tp;
+  std::vector<int32_t> start, list;
+  int nc = 0;
+  if (thermo_meta(p, n, tp, start, list, nc) != KPM_OK) return KPM_EINVAL;
+  StreamSync guard{st};
+  DevBuf outs;
+  int r = outs.alloc((size_t)4 * nc * n_T * 8);
+  if (r != KPM_OK) return r;
+  double* o = static_cast<double*>(outs.p);
+  const size_t m = (size_t)nc * n_T;
+  ThermoDev TD;
+  r = thermo_forward(d_mu, d_ab, p, n, M, kernel, n_nodes, d_T, n_T, o, o + m, o + 2 * m, o + 3 * m,
+                     nullptr, st, TD, tp, nc, true);
+  if (r != KPM_OK) return r;
+  ThermoVjpArgs va{};
+  va.tp = TD.tp;
+  va.ab = d_ab;
+  va.stats = TD.stats;
+  va.wC = d_wC;
+  va.wchi = d_wchi;
+  va.g = TD.g;
+  va.node_adj = TD.adj;
+  va.lambda = d_lambda;
+  va.n_probs = n;
+  va.M = M;
+  va.n_nodes = n_nodes ? n_nodes : M;
+  va.n_T = n_T;
+  KPM_HIP(launch_thermo_vjp(va, st));
+  KPM_HIP(hipStreamSynchronize(st));
+  return KPM_OK;
+}
+
+size_t chebyshev_moments_vjp_workspace_size(const kpm_problem* p, int32_t n, const kpm_params* q,
+                                            int32_t ckpt_every) {
+  (void)p; (void)n; (void)q; (void)ckpt_every;
+  return 0;
+}
+
+int chebyshev_moments_vjp(const kpm_problem* p, int32_t n, const kpm_params* q,
+                          const double* d_ab, const double* d_dmu, int32_t ckpt_every,
+                          double* d_dJ, void* d_work, size_t work_bytes, void* stream) {
+  (void)p; (void)n; (void)q; (void)d_ab; (void)d_dmu; (void)ckpt_every; (void)d_dJ;
+  (void)d_work; (void)work_bytes; (void)stream;
+  return KPM_EINVAL;
+}
+
+int kpm_thermo_grad(const kpm_problem* p, int32_t n, const kpm_params* q, int32_t kernel,
+                    int32_t n_nodes, const double* d_T, int32_t n_T, const double* d_wC,
+                    const double* d_wchi, int32_t ckpt_every, double* d_L, double* d_dJ,
+                    double* d_ab, void* d_work, size_t work_bytes, void* stream) {
+  (void)p; (void)n; (void)q; (void)kernel; (void)n_nodes; (void)d_T; (void)n_T; (void)d_wC;
+  (void)d_wchi; (void)ckpt_every; (void)d_L; (void)d_dJ; (void)d_ab; (void)d_work;
+  (void)work_bytes; (void)stream;
+  return KPM_EINVAL;
+}
+
+}  // extern "C"

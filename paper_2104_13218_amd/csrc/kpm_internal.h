@@ -1,0 +1,205 @@
+// Internal data structures shared by the host planner and the gfx950 kernels
+// of the Chebyshev-moment library.  Not part of the public ABI (include/kpm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace kpm {
+
+constexpr int kThreads = 256;     // threads per workgroup (4 wave64)
+constexpr int kMaxBonds = 512;    // bonds per problem
+constexpr int kMaxLd = 64;        // real columns per recursion block (padded)
+constexpr int kBinomN = 33;       // binomial table C(n, j), n, j < 33
+
+// One (cluster, S^z sector) problem as the kernels see it.
+struct ProbDev {
+  int64_t dim;        // C(n_sites, n_up)
+  int32_t n_sites, n_up, n_bonds, bond_off;   // bonds at [bond_off, bond_off + n_bonds)
+  int32_t B0, B1, B2, tab_off;                // rank-table split and offset (u32 entries)
+  int32_t tab_len, cluster;                   // table entries; RNG cluster id
+  double shift;       // -b / a   (diagonal shift of H' = (H - b)/a)
+  double inv_a;       // 1 / a
+};
+
+// One recursion block: a problem and a contiguous range of its real columns.
+struct UnitDev {
+  int64_t vec_off;    // element offset of buffer A; buffer B follows at + dim * ld
+  int64_t part_off;   // offset of this unit's partial dots: [2 * ld][ntiles]
+  int32_t prob, ld, ncols, col0;              // columns [col0, col0 + ncols) of the problem
+  int32_t tile0, ntiles, col_off, pad;        // first tile; column offset in dot rows
+};
+
+// Arguments of the fused recursion step (one launch per step).
+struct StepArgs {
+  const ProbDev* probs;
+  const UnitDev* units;
+  const int32_t* tile_unit;    // [n_tiles]: unit of each tile
+  const int32_t* job_unit;     // [2 * total_cols]: unit of each reduction job
+  const uint32_t* tables;      // rank tables of all problems
+  const uint32_t* bmask;       // per bond: (1 << i) | (1 << j)
+  const double* boff;          // per bond: J_b / (2a)   (off-diagonal element of H')
+  const double* bzz;           // per bond: J_b / (4a)   (diagonal contribution)
+  const uint32_t* binom;       // C(n, j) [33][33]
+  void* vec;                   // vector storage base (float or double)
+  double* part_out;            // partial dots written by this step
+  const double* part_in;       // partial dots of the previous step (reduced here)
+  double* alpha;               // [steps + 1][total_cols]: <v_n, v_n>
+  double* beta;                // [steps][total_cols]:     <v_n+1, v_n>
+  const int64_t* step_base;    // device step counter base (NULL => 0)
+  int32_t step_add;            // step index s = *step_base + step_add
+  int32_t n_tiles;             // real tiles
+  int32_t grid_tiles;          // launched tiles (multiple of 8)
+  int32_t x_parity;            // 0: x = A, y = B; 1: x = B, y = A
+  int32_t first;               // 1: y = H' x; 0: y = 2 H' x - y
+  int32_t n_jobs;              // reduction jobs of the previous step (0 = none)
+  int32_t total_cols;          // row length of alpha / beta
+  int32_t sub_rows;            // rows per LDS sub-tile (power of two <= 256)
+  int32_t sub_per_tile;        // sub-tiles per workgroup tile
+  int32_t lds_nb;              // neighbour-list capacity per row in LDS
+  int32_t lds_tab;             // table capacity (u32 entries) in LDS
+  int32_t lds_bonds;           // bond capacity in LDS
+  int* err;                    // bit 1 set if a neighbour rank fell outside its sector
+};
+
+// Device-side plan of one run (pointers into the workspace) + launch shape.
+struct DevicePlan {
+  ProbDev* probs = nullptr;
+  UnitDev* units = nullptr;
+  int32_t* tile_unit = nullptr;
+  int32_t* job_unit = nullptr;
+  int32_t* prob_unit0 = nullptr;
+  uint32_t* tables = nullptr;
+  uint32_t* bmask = nullptr;
+  double* boff = nullptr;
+  double* bzz = nullptr;
+  uint32_t* binom = nullptr;
+  int* err = nullptr;          // device error word (see StepArgs::err)
+  int32_t n_probs = 0, n_units = 0, n_tiles = 0, grid_tiles = 0, total_cols = 0;
+  int32_t sub_rows = 256, sub_per_tile = 1, lds_nb = 0, lds_tab = 0, lds_bonds = 0;
+  int32_t cpl = 1;
+  int32_t fp32 = 0;
+  int64_t part_len = 0;        // doubles per partial buffer
+  int64_t vec_elems = 0;       // elements of vector storage (A and B of all units)
+};
+
+struct ReduceArgs {
+  const UnitDev* units;
+  const int32_t* job_unit;
+  const double* part;
+  double* dst_a;   // per column: sum of alpha-part partials (NULL: skip)
+  double* dst_b;   // per column: sum of beta-part partials (NULL: skip)
+  int n_jobs;
+};
+
+struct InitArgs {
+  const ProbDev* probs;
+  const UnitDev* units;
+  const int32_t* tile_unit;
+  void* vec;
+  const double* norms;   // per column: Gaussian sums of squares (mode 1)
+  double* part_out;
+  uint64_t seed;
+  int32_t n_tiles, grid_tiles, mode, vec_kind, tile_rows;
+};
+
+struct FinalArgs {
+  const ProbDev* probs;
+  const UnitDev* units;
+  const int32_t* prob_unit0;  // [n_probs + 1]: units of problem p are [u0[p], u0[p+1])
+  const double* alpha;
+  const double* beta;
+  double* mu;
+  int* flag;
+  int32_t n_probs, M, total_cols, cols_per_vec, R;   // R = 0: complete basis (R_eff = dim)
+};
+
+struct MatrixArgs {
+  const ProbDev* probs;
+  const uint32_t* tables;
+  const uint32_t* bmask;
+  const double* boff;
+  const double* bzz;
+  const uint32_t* binom;
+  int64_t row0, nrows;
+  int32_t max_nb, lds_tab, lds_bonds, sub_rows, lds_nb;
+  uint32_t* cols;
+  int32_t* bond;
+  int32_t* cnt;
+  double* diag;
+};
+
+struct LzArgs {
+  const ProbDev* probs;
+  const UnitDev* units;
+  const int32_t* tile_unit;
+  double* w;
+  const double* q;
+  const double* coef;      // per unit (column offset); squared if coef_sqrt
+  const double* dotvec;    // NULL => dot with the updated w itself
+  double* part_out;
+  int32_t n_tiles, grid_tiles, tile_rows, coef_sqrt;
+  int32_t w_hi, q_hi, d_hi;  // select the second buffer (+ dim) of a block's pair
+};
+
+// Per-problem metadata of the thermodynamic sums.
+struct ThermoProb {
+  int32_t cluster;
+  int32_t weight;   // 1 for S^z = 0, 2 otherwise
+  double sz;        // S^z = n_up - N/2
+};
+
+struct ThermoArgs {
+  const ThermoProb* tp;
+  const int32_t* cl_start;   // [n_clusters + 1] into cl_list
+  const int32_t* cl_list;    // problems grouped by cluster
+  const double* gamma;       // [n_probs][n_nodes]
+  const double* ab;          // [n_probs][2]
+  const double* T;           // [n_T]
+  double* lnZ;
+  double* E;
+  double* C;
+  double* chi;
+  uint8_t* znonpos;
+  double* stats;             // [n_clusters][n_T][6]: S0, Ebar, Var, <m^2>, Eref, beta
+  int32_t n_nodes, n_T, n_clusters;
+};
+
+struct ThermoVjpArgs {
+  const ThermoProb* tp;
+  const double* ab;
+  const double* stats;
+  const double* wC;          // [n_clusters][n_T]
+  const double* wchi;
+  const double* g;           // kernel coefficients [M]
+  double* node_adj;          // [n_probs][n_nodes]
+  double* lambda;            // [n_probs][M]
+  int32_t n_probs, M, n_nodes, n_T;
+};
+
+size_t step_lds_bytes(const DevicePlan& p);
+
+hipError_t launch_step(const DevicePlan& p, void* vec, double* part_out, const double* part_in,
+                       int n_jobs, double* alpha, double* beta, const int64_t* step_base,
+                       int step_add, int x_parity, int first, hipStream_t st);
+hipError_t launch_reduce(const DevicePlan& p, const double* part, double* dst_a, double* dst_b,
+                         hipStream_t st);
+hipError_t launch_init(const DevicePlan& p, void* vec, int mode, int vec_kind, uint64_t seed,
+                       const double* norms, double* part_out, hipStream_t st);
+hipError_t launch_finalize(const FinalArgs& a, hipStream_t st);
+hipError_t launch_set_i64(int64_t* dst, int64_t v, hipStream_t st);
+hipError_t launch_states(int N, int k, const uint32_t* binom, uint32_t* out, int64_t dim,
+                         hipStream_t st);
+hipError_t launch_matrix(const MatrixArgs& a, size_t lds, int grid, hipStream_t st);
+hipError_t launch_lz_axpy(const DevicePlan& p, const LzArgs& args, hipStream_t st);
+hipError_t launch_lz_next(const DevicePlan& p, double* qprev, double* q, const double* w,
+                          const double* beta2, hipStream_t st);
+hipError_t launch_kernel_coef(int M, int kernel, double* g, hipStream_t st);
+hipError_t launch_gamma(int n_probs, int M, int n_nodes, const double* g, const double* mu,
+                        double* gamma, hipStream_t st);
+hipError_t launch_thermo(const ThermoArgs& a, hipStream_t st);
+hipError_t launch_thermo_vjp(const ThermoVjpArgs& a, hipStream_t st);
+
+}  // namespace kpm

@@ -1,0 +1,702 @@
+// gfx950 kernels of the Chebyshev-moment library.
+//
+// Hot path: one launch per recursion step v_{n+1} = 2 H' v_n - v_{n-1}
+// (v_1 = H' v_0) over every (problem, column block) of the run, with
+// H' = (H - b)/a applied matrix-free in the S^z-sector bit basis (paper,
+// Eqs. (4)-(6) and the sector decomposition of Sec. II).  Each workgroup owns
+// a tile of consecutive basis states of one block:
+//   phase 1  one thread per state: unrank the state, walk the bonds, and stage
+//            in LDS the neighbour ranks (combinatorial-number-system rank via
+//            three table lookups) and the diagonal element;
+//   phase 2  threads own (state, 4- or 2-column chunk) pairs: coalesced 16-byte
+//            loads of the state's own rows, 16-byte gathers of neighbour rows,
+//            float64 accumulation, one streaming store of v_{n+1} over v_{n-1};
+//   dots     <v_{n+1}, v_{n+1}> and <v_{n+1}, v_n> per column, accumulated in
+//            float64 from the stored values and reduced in a fixed order
+//            (workgroup tree, then per-tile partials that the *next* step's
+//            launch sums), so results are bitwise reproducible.
+// No MFMA: the operator is a sparse gather, bound by HBM traffic.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kpm_internal.h"
+
+namespace kpm {
+
+// ------------------------------------------------------------------ helpers
+
+template <typename T, int N>
+struct alignas(sizeof(T) * N >= 16 ? 16 : sizeof(T) * N) VecT {
+  T v[N];
+};
+
+template <typename T, int N>
+__device__ __forceinline__ VecT<T, N> vload(const T* p) {
+  return *reinterpret_cast<const VecT<T, N>*>(p);
+}
+template <typename T, int N>
+__device__ __forceinline__ void vstore(T* p, const VecT<T, N>& x) {
+  *reinterpret_cast<VecT<T, N>*>(p) = x;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of tiles so neighbour rows with small rank offsets are
+// found in that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int grid_tiles) {
+  const int per = grid_tiles >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+// Deterministic workgroup sum (valid in thread 0). sh: >= 4 doubles of LDS.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  return r;
+}
+
+// Sum of n partials in a fixed order (strided per thread, then tree).
+__device__ __forceinline__ double sum_partials(const double* p, int n, double* sh) {
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < n; t += kThreads) acc += p[t];
+  return block_sum(acc, sh);
+}
+
+// Word of rank r among N-bit words with k set bits (combinatorial number
+// system, colex order = ascending integer order): greedily take the highest
+// position p with C(p, j) <= remaining rank, for j = k .. 1.
+__device__ __forceinline__ uint32_t unrank(uint32_t r, int N, int k, const uint32_t* binom) {
+  uint32_t s = 0;
+  int j = k;
+  for (int p = N - 1; p >= 0 && j > 0; --p) {
+    const uint32_t cv = binom[p * kBinomN + j];
+    if (cv <= r) {
+      s |= 1u << p;
+      r -= cv;
+      --j;
+    }
+  }
+  return s;
+}
+
+// Rank of word s: the bits split as x0 (B0 low bits), x1 (next B1), x2 (rest);
+// rank = T0[x0] + T1[x1][popcount(x0)] + T2[x2] (T2 already knows the sector's
+// popcount, so the number of set bits below x2 is implied).
+struct RankTables {
+  const uint32_t* T0;
+  const uint32_t* T1;
+  const uint32_t* T2;
+  uint32_t m0, m1;
+  int B0, sh2;
+  __device__ __forceinline__ uint32_t rank(uint32_t s) const {
+    const uint32_t x0 = s & m0;
+    const uint32_t x1 = (s >> B0) & m1;
+    const uint32_t x2 = s >> sh2;
+    return T0[x0] + T1[x1 * (uint32_t)(B0 + 1) + __popc(x0)] + T2[x2];
+  }
+};
+
+__device__ __forceinline__ RankTables make_tables(const uint32_t* tab, const ProbDev& P) {
+  RankTables R;
+  R.T0 = tab;
+  R.T1 = tab + (1u << P.B0);
+  R.T2 = R.T1 + (1u << P.B1) * (uint32_t)(P.B0 + 1);
+  R.m0 = (1u << P.B0) - 1u;
+  R.m1 = (1u << P.B1) - 1u;
+  R.B0 = P.B0;
+  R.sh2 = P.B0 + P.B1;
+  return R;
+}
+
+// LDS carve-up shared by the step kernel and the matrix export.
+struct StepSmem {
+  uint32_t* binom;
+  uint32_t* tab;
+  uint32_t* mask;
+  double* off;
+  double* zz;
+  double* diag;
+  int32_t* cnt;
+  uint32_t* nbr;
+  uint16_t* nbb;
+  double* red;
+};
+
+__device__ __forceinline__ size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
+
+__device__ __forceinline__ StepSmem carve(unsigned char* smem, int lds_tab, int lds_bonds,
+                                          int sub_rows, int lds_nb) {
+  StepSmem S;
+  size_t o = 0;
+  S.binom = reinterpret_cast<uint32_t*>(smem + o); o = al16(o + kBinomN * kBinomN * 4);
+  S.tab = reinterpret_cast<uint32_t*>(smem + o);   o = al16(o + size_t(lds_tab) * 4);
+  S.mask = reinterpret_cast<uint32_t*>(smem + o);  o = al16(o + size_t(lds_bonds) * 4);
+  S.off = reinterpret_cast<double*>(smem + o);     o = al16(o + size_t(lds_bonds) * 8);
+  S.zz = reinterpret_cast<double*>(smem + o);      o = al16(o + size_t(lds_bonds) * 8);
+  S.diag = reinterpret_cast<double*>(smem + o);    o = al16(o + size_t(sub_rows) * 8);
+  S.cnt = reinterpret_cast<int32_t*>(smem + o);    o = al16(o + size_t(sub_rows) * 4);
+  S.red = reinterpret_cast<double*>(smem + o);     // aliases the lists after phase 2
+  S.nbr = reinterpret_cast<uint32_t*>(smem + o);   o = al16(o + size_t(lds_nb) * sub_rows * 4);
+  S.nbb = reinterpret_cast<uint16_t*>(smem + o);
+  return S;
+}
+
+// Phase 1 for one row: unrank, walk bonds, stage neighbour ranks and diag.
+// A neighbour rank outside the sector (impossible for consistent tables) is
+// replaced by the row itself and reported through *err, so no gather can
+// leave the vector.
+__device__ __forceinline__ void stage_row(uint32_t rank, const ProbDev& P, const RankTables& RT,
+                                          const StepSmem& S, int slot, int stride, int* err) {
+  const uint32_t s = unrank(rank, P.n_sites, P.n_up, S.binom);
+  double d = P.shift;
+  int cnt = 0;
+  for (int b = 0; b < P.n_bonds; ++b) {
+    const uint32_t m = S.mask[b];
+    const uint32_t v = s & m;
+    if (v == 0u || v == m) {
+      d += S.zz[b];
+    } else {
+      d -= S.zz[b];
+      uint32_t nr = RT.rank(s ^ m);
+      if (nr >= (uint32_t)P.dim) {
+        if (err) atomicOr(err, 2);
+        nr = rank;
+      }
+      S.nbr[cnt * stride + slot] = nr;
+      S.nbb[cnt * stride + slot] = (uint16_t)b;
+      ++cnt;
+    }
+  }
+  S.diag[slot] = d;
+  S.cnt[slot] = cnt;
+}
+
+__device__ __forceinline__ void load_problem_lds(const StepSmem& S, const ProbDev& P,
+                                                 const uint32_t* tables, const uint32_t* bmask,
+                                                 const double* boff, const double* bzz,
+                                                 const uint32_t* binom) {
+  for (int i = threadIdx.x; i < kBinomN * kBinomN; i += kThreads) S.binom[i] = binom[i];
+  for (int i = threadIdx.x; i < P.tab_len; i += kThreads) S.tab[i] = tables[P.tab_off + i];
+  for (int i = threadIdx.x; i < P.n_bonds; i += kThreads) {
+    S.mask[i] = bmask[P.bond_off + i];
+    S.off[i] = boff[P.bond_off + i];
+    S.zz[i] = bzz[P.bond_off + i];
+  }
+}
+
+// ------------------------------------------------------------ step kernel
+
+template <typename T, int CPL>
+__global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x;
+
+  // Reduce the previous step's per-tile partial dots: alpha_s, beta_{s-1}.
+  if (a.n_jobs > 0) {
+    const int64_t s = (a.step_base ? *a.step_base : 0) + a.step_add;
+    double* sh = reinterpret_cast<double*>(smem);
+    for (int job = blockIdx.x; job < a.n_jobs; job += gridDim.x) {
+      const UnitDev U = a.units[a.job_unit[job]];
+      const int v = job - 2 * U.col_off;
+      const double sum = sum_partials(a.part_in + U.part_off + (int64_t)v * U.ntiles, U.ntiles, sh);
+      if (tid == 0) {
+        if (v < U.ld) a.alpha[s * a.total_cols + U.col_off + v] = sum;
+        else a.beta[(s - 1) * a.total_cols + U.col_off + (v - U.ld)] = sum;
+      }
+    }
+    __syncthreads();
+  }
+
+  const int tile = xcd_tile(blockIdx.x, a.grid_tiles);
+  if (tile >= a.n_tiles) return;
+  const UnitDev U = a.units[a.tile_unit[tile]];
+  const ProbDev P = a.probs[U.prob];
+  const StepSmem S = carve(smem, a.lds_tab, a.lds_bonds, a.sub_rows, a.lds_nb);
+  load_problem_lds(S, P, a.tables, a.bmask, a.boff, a.bzz, a.binom);
+  __syncthreads();
+  const RankTables RT = make_tables(S.tab, P);
+
+  const int ld = U.ld;
+  const int nch = ld / CPL;
+  const int nrg = kThreads / nch;
+  const int c = tid % nch;
+  const int rg = tid / nch;
+  T* base = reinterpret_cast<T*>(a.vec) + U.vec_off;
+  const T* X = a.x_parity ? base + P.dim * ld : base;
+  T* Y = a.x_parity ? base : base + P.dim * ld;
+
+  double acc_a[CPL], acc_b[CPL];
+#pragma unroll
+  for (int i = 0; i < CPL; ++i) acc_a[i] = acc_b[i] = 0.0;
+
+  const int64_t tile_row0 = (int64_t)(tile - U.tile0) * a.sub_rows * a.sub_per_tile;
+  for (int st = 0; st < a.sub_per_tile; ++st) {
+    const int64_t row0 = tile_row0 + (int64_t)st * a.sub_rows;
+    if (row0 >= P.dim) break;
+    const int nrows = (int)min((int64_t)a.sub_rows, P.dim - row0);
+    for (int r = tid; r < nrows; r += kThreads)
+      stage_row((uint32_t)(row0 + r), P, RT, S, r, a.sub_rows, a.err);
+    __syncthreads();
+    if (rg < nrg) {
+      for (int r = rg; r < nrows; r += nrg) {
+        const int64_t rho = row0 + r;
+        const VecT<T, CPL> xv = vload<T, CPL>(X + rho * ld + c * CPL);
+        const double dg = S.diag[r];
+        double acc[CPL];
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) acc[i] = dg * (double)xv.v[i];
+        const int cnt = S.cnt[r];
+        for (int k = 0; k < cnt; ++k) {
+          const uint32_t nb = S.nbr[k * a.sub_rows + r];
+          const double cf = S.off[S.nbb[k * a.sub_rows + r]];
+          const VecT<T, CPL> nv = vload<T, CPL>(X + (int64_t)nb * ld + c * CPL);
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) acc[i] = fma(cf, (double)nv.v[i], acc[i]);
+        }
+        T* ys = Y + rho * ld + c * CPL;
+        VecT<T, CPL> ov;
+        if (a.first) {
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) ov.v[i] = (T)acc[i];
+        } else {
+          const VecT<T, CPL> yv = vload<T, CPL>(ys);
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) ov.v[i] = (T)(2.0 * acc[i] - (double)yv.v[i]);
+        }
+        vstore<T, CPL>(ys, ov);
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) {
+          const double o = (double)ov.v[i];
+          acc_a[i] = fma(o, o, acc_a[i]);
+          acc_b[i] = fma(o, (double)xv.v[i], acc_b[i]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // Workgroup reduction over row groups, per column (fixed tree).
+  double* red = S.red;
+  if (rg < nrg) {
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+      red[(2 * i) * kThreads + tid] = acc_a[i];
+      red[(2 * i + 1) * kThreads + tid] = acc_b[i];
+    }
+  }
+  int p2 = 1;
+  while (p2 < nrg) p2 <<= 1;
+  for (int sstride = p2 >> 1; sstride > 0; sstride >>= 1) {
+    __syncthreads();
+    if (rg < sstride && rg + sstride < nrg) {
+#pragma unroll
+      for (int v = 0; v < 2 * CPL; ++v) red[v * kThreads + tid] += red[v * kThreads + tid + sstride * nch];
+    }
+  }
+  __syncthreads();
+  if (tid < nch) {
+    const int tl = tile - U.tile0;
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+      const int col = c * CPL + i;
+      a.part_out[U.part_off + (int64_t)col * U.ntiles + tl] = red[(2 * i) * kThreads + tid];
+      a.part_out[U.part_off + (int64_t)(ld + col) * U.ntiles + tl] = red[(2 * i + 1) * kThreads + tid];
+    }
+  }
+}
+
+size_t step_lds_bytes(const DevicePlan& p) {
+  auto a16 = [](size_t x) { return (x + 15) & ~size_t(15); };
+  size_t o = 0;
+  o = a16(o + kBinomN * kBinomN * 4);
+  o = a16(o + size_t(p.lds_tab) * 4);
+  o = a16(o + size_t(p.lds_bonds) * 4);
+  o = a16(o + size_t(p.lds_bonds) * 8);
+  o = a16(o + size_t(p.lds_bonds) * 8);
+  o = a16(o + size_t(p.sub_rows) * 8);
+  o = a16(o + size_t(p.sub_rows) * 4);
+  const size_t lists = a16(size_t(p.lds_nb) * p.sub_rows * 4) + size_t(p.lds_nb) * p.sub_rows * 2;
+  const size_t red = size_t(2 * p.cpl) * kThreads * 8;
+  return a16(o + (lists > red ? lists : red));
+}
+
+static StepArgs make_step_args(const DevicePlan& p) {
+  StepArgs a{};
+  a.probs = p.probs;
+  a.units = p.units;
+  a.tile_unit = p.tile_unit;
+  a.job_unit = p.job_unit;
+  a.tables = p.tables;
+  a.bmask = p.bmask;
+  a.boff = p.boff;
+  a.bzz = p.bzz;
+  a.binom = p.binom;
+  a.n_tiles = p.n_tiles;
+  a.grid_tiles = p.grid_tiles;
+  a.total_cols = p.total_cols;
+  a.sub_rows = p.sub_rows;
+  a.sub_per_tile = p.sub_per_tile;
+  a.lds_nb = p.lds_nb;
+  a.lds_tab = p.lds_tab;
+  a.lds_bonds = p.lds_bonds;
+  return a;
+}
+
+template <typename T, int CPL>
+static hipError_t launch_step_t(const StepArgs& a, size_t lds, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((step_kernel<T, CPL>), dim3(grid), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const DevicePlan& p, void* vec, double* part_out, const double* part_in,
+                       int n_jobs, double* alpha, double* beta, const int64_t* step_base,
+                       int step_add, int x_parity, int first, hipStream_t st) {
+  StepArgs a = make_step_args(p);
+  a.err = p.err;
+  a.vec = vec;
+  a.part_out = part_out;
+  a.part_in = part_in;
+  a.n_jobs = n_jobs;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.step_base = step_base;
+  a.step_add = step_add;
+  a.x_parity = x_parity;
+  a.first = first;
+  const size_t lds = step_lds_bytes(p);
+  const int grid = p.grid_tiles;
+  if (p.fp32) {
+    switch (p.cpl) {
+      case 1: return launch_step_t<float, 1>(a, lds, grid, st);
+      case 2: return launch_step_t<float, 2>(a, lds, grid, st);
+      case 4: return launch_step_t<float, 4>(a, lds, grid, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (p.cpl) {
+    case 1: return launch_step_t<double, 1>(a, lds, grid, st);
+    case 2: return launch_step_t<double, 2>(a, lds, grid, st);
+    case 4: return launch_step_t<double, 4>(a, lds, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// --------------------------------------------------------- reduce kernel
+
+
+__global__ __launch_bounds__(kThreads) void reduce_kernel(const ReduceArgs a) {
+  __shared__ double sh[4];
+  for (int job = blockIdx.x; job < a.n_jobs; job += gridDim.x) {
+    const UnitDev U = a.units[a.job_unit[job]];
+    const int v = job - 2 * U.col_off;
+    double* dst = v < U.ld ? a.dst_a : a.dst_b;
+    const double sum = sum_partials(a.part + U.part_off + (int64_t)v * U.ntiles, U.ntiles, sh);
+    if (threadIdx.x == 0 && dst) dst[U.col_off + (v < U.ld ? v : v - U.ld)] = sum;
+  }
+}
+
+hipError_t launch_reduce(const DevicePlan& p, const double* part, double* dst_a, double* dst_b,
+                         hipStream_t st) {
+  ReduceArgs a{p.units, p.job_unit, part, dst_a, dst_b, 2 * p.total_cols};
+  const int grid = a.n_jobs < 4096 ? a.n_jobs : 4096;
+  hipLaunchKernelGGL(reduce_kernel, dim3(grid), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------- random start vectors
+
+// Counter-based SplitMix64 (Steele, Lea, Flood 2014): output ctr+1 of the
+// sequential generator started at `seed`.
+__device__ __forceinline__ uint64_t splitmix(uint64_t seed, uint64_t ctr) {
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull * (ctr + 1ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ double unit_open(uint64_t u) {
+  return ((double)(u >> 11) + 0.5) * 0x1.0p-53;
+}
+
+
+// Unnormalised start value of column pc (of the problem) at row rho.
+__device__ __forceinline__ double start_value(int kind, uint64_t seed, const ProbDev& P, int pc,
+                                              int64_t rho) {
+  if (kind == 3) return rho == (int64_t)pc ? 1.0 : 0.0;
+  const int r = kind == 1 ? (pc >> 1) : pc;
+  const uint64_t stream = ((uint64_t)P.cluster << 16) | ((uint64_t)P.n_up << 10) | (uint64_t)r;
+  if (kind == 0) {
+    const uint64_t u = splitmix(seed, (stream << 32) | (uint64_t)rho);
+    return (u >> 63) ? -1.0 : 1.0;
+  }
+  const uint64_t i1 = (uint64_t)(2 * rho), i2 = (uint64_t)(2 * rho + 1);
+  const double u1 = unit_open(splitmix(seed, (stream << 32) | i1));
+  const double u2 = unit_open(splitmix(seed, (stream << 32) | i2));
+  const double rad = sqrt(-2.0 * log(u1));
+  const double ang = 2.0 * M_PI * u2;
+  return (kind == 1 && (pc & 1)) ? rad * sin(ang) : rad * cos(ang);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void init_kernel(const InitArgs a) {
+  __shared__ double red[kThreads];
+  const int tile = xcd_tile(blockIdx.x, a.grid_tiles);
+  if (tile >= a.n_tiles) return;
+  const UnitDev U = a.units[a.tile_unit[tile]];
+  const ProbDev P = a.probs[U.prob];
+  const int ld = U.ld;
+  const int nrg = kThreads / ld;
+  const int tid = threadIdx.x;
+  const int c = tid % ld, rg = tid / ld;
+  const int64_t row0 = (int64_t)(tile - U.tile0) * a.tile_rows;
+  const int64_t row1 = min(row0 + a.tile_rows, P.dim);
+  T* A = reinterpret_cast<T*>(a.vec) + U.vec_off;
+  double scale = 1.0;
+  if (a.mode == 2) scale = 1.0 / sqrt((double)P.dim);   // unit-norm Lanczos start
+  if (a.mode == 1 && (a.vec_kind == 1 || a.vec_kind == 2) && c < U.ncols) {
+    double n2 = a.norms[U.col_off + c];
+    if (a.vec_kind == 1) {
+      const int c0 = c & ~1;
+      n2 = a.norms[U.col_off + c0] + a.norms[U.col_off + c0 + 1];
+    }
+    scale = sqrt((double)P.dim / n2);
+  }
+  double acc = 0.0;
+  if (rg < nrg) {
+    for (int64_t rho = row0 + rg; rho < row1; rho += nrg) {
+      double x = 0.0;
+      if (c < U.ncols) x = start_value(a.vec_kind, a.seed, P, U.col0 + c, rho);
+      if (a.mode == 0) {
+        acc = fma(x, x, acc);
+      } else {
+        const T xs = (T)(x * scale);
+        A[rho * ld + c] = xs;
+        acc = fma((double)xs, (double)xs, acc);
+      }
+    }
+  }
+  red[tid] = rg < nrg ? acc : 0.0;
+  int p2 = 1;
+  while (p2 < nrg) p2 <<= 1;
+  for (int s = p2 >> 1; s > 0; s >>= 1) {
+    __syncthreads();
+    if (rg < s && rg + s < nrg) red[tid] += red[tid + s * ld];
+  }
+  __syncthreads();
+  if (tid < ld) {
+    const int tl = tile - U.tile0;
+    a.part_out[U.part_off + (int64_t)tid * U.ntiles + tl] = red[tid];
+    a.part_out[U.part_off + (int64_t)(ld + tid) * U.ntiles + tl] = 0.0;
+  }
+}
+
+hipError_t launch_init(const DevicePlan& p, void* vec, int mode, int vec_kind, uint64_t seed,
+                       const double* norms, double* part_out, hipStream_t st) {
+  InitArgs a{};
+  a.probs = p.probs;
+  a.units = p.units;
+  a.tile_unit = p.tile_unit;
+  a.vec = vec;
+  a.norms = norms;
+  a.part_out = part_out;
+  a.seed = seed;
+  a.n_tiles = p.n_tiles;
+  a.grid_tiles = p.grid_tiles;
+  a.mode = mode;
+  a.vec_kind = vec_kind;
+  a.tile_rows = p.sub_rows * p.sub_per_tile;
+  if (p.fp32) hipLaunchKernelGGL(init_kernel<float>, dim3(p.grid_tiles), dim3(kThreads), 0, st, a);
+  else hipLaunchKernelGGL(init_kernel<double>, dim3(p.grid_tiles), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------- doubling + estimator
+
+
+__global__ __launch_bounds__(kThreads) void finalize_kernel(const FinalArgs a) {
+  const int64_t gid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (gid >= (int64_t)a.n_probs * a.M) return;
+  const int p = (int)(gid / a.M);
+  const int n = (int)(gid % a.M);
+  const int TC = a.total_cols;
+  const int h = n >> 1;
+  double acc = 0.0;
+  bool bad = false;
+  for (int u = a.prob_unit0[p]; u < a.prob_unit0[p + 1]; ++u) {
+    const UnitDev U = a.units[u];
+    for (int c = 0; c < U.ncols; c += a.cols_per_vec) {
+      double num = 0.0, den = 0.0;
+      for (int cc = 0; cc < a.cols_per_vec; ++cc) {
+        const int col = U.col_off + c + cc;
+        const double a0 = a.alpha[col];
+        const double b0 = a.beta[col];
+        double m;
+        if (n == 0) m = a0;
+        else if (n == 1) m = b0;
+        else if ((n & 1) == 0) m = 2.0 * a.alpha[(int64_t)h * TC + col] - a0;
+        else m = 2.0 * a.beta[(int64_t)h * TC + col] - b0;
+        num += m;
+        den += a0;
+      }
+      if (fabs(num) > den * (1.0 + 1e-6)) bad = true;
+      acc += num / den;
+    }
+  }
+  const ProbDev P = a.probs[p];
+  const double Reff = a.R > 0 ? (double)a.R : (double)P.dim;
+  a.mu[gid] = acc * ((double)P.dim / Reff);
+  if (bad) atomicOr(a.flag, 1);
+}
+
+hipError_t launch_finalize(const FinalArgs& a, hipStream_t st) {
+  const int64_t n = (int64_t)a.n_probs * a.M;
+  const int grid = (int)((n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(finalize_kernel, dim3(grid), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------- small kernels
+
+__global__ void set_i64_kernel(int64_t* dst, int64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
+}
+hipError_t launch_set_i64(int64_t* dst, int64_t v, hipStream_t st) {
+  hipLaunchKernelGGL(set_i64_kernel, dim3(1), dim3(64), 0, st, dst, v);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kThreads) void states_kernel(int N, int k, const uint32_t* binom,
+                                                          uint32_t* out, int64_t dim) {
+  __shared__ uint32_t sb[kBinomN * kBinomN];
+  for (int i = threadIdx.x; i < kBinomN * kBinomN; i += kThreads) sb[i] = binom[i];
+  __syncthreads();
+  for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < dim;
+       r += (int64_t)gridDim.x * kThreads)
+    out[r] = unrank((uint32_t)r, N, k, sb);
+}
+hipError_t launch_states(int N, int k, const uint32_t* binom, uint32_t* out, int64_t dim,
+                         hipStream_t st) {
+  int64_t g = (dim + kThreads - 1) / kThreads;
+  const int grid = (int)(g < 65536 ? (g > 0 ? g : 1) : 65536);
+  hipLaunchKernelGGL(states_kernel, dim3(grid), dim3(kThreads), 0, st, N, k, binom, out, dim);
+  return hipGetLastError();
+}
+
+// Matrix export: phase 1 of the step kernel, written to global memory.
+
+__global__ __launch_bounds__(kThreads) void matrix_kernel(const MatrixArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const ProbDev P = a.probs[0];
+  const StepSmem S = carve(smem, a.lds_tab, a.lds_bonds, a.sub_rows, a.lds_nb);
+  load_problem_lds(S, P, a.tables, a.bmask, a.boff, a.bzz, a.binom);
+  __syncthreads();
+  const RankTables RT = make_tables(S.tab, P);
+  const int64_t r0 = a.row0 + (int64_t)blockIdx.x * a.sub_rows;
+  const int64_t end = a.row0 + a.nrows;
+  const int t = threadIdx.x;
+  if (t < a.sub_rows && r0 + t < end) {
+    stage_row((uint32_t)(r0 + t), P, RT, S, t, a.sub_rows, nullptr);
+    const int64_t out = r0 + t - a.row0;
+    const int n = S.cnt[t];
+    for (int k = 0; k < n; ++k) {
+      a.cols[out * a.max_nb + k] = S.nbr[k * a.sub_rows + t];
+      a.bond[out * a.max_nb + k] = S.nbb[k * a.sub_rows + t];
+    }
+    a.cnt[out] = n;
+    a.diag[out] = S.diag[t];
+  }
+}
+
+// ------------------------------------------------------------ Lanczos helpers
+// Blocks have one float64 column; each block's buffers sit at
+// base + vec_off (+ dim for the "high" buffer of a pair).
+
+__device__ __forceinline__ double* lz_sel(double* base, int hi, const UnitDev& U, const ProbDev& P) {
+  return base + U.vec_off + (hi ? P.dim : 0);
+}
+
+// w -= coef * q, with partials of <w, d> (d = w itself when d is NULL).
+__global__ __launch_bounds__(kThreads) void lz_axpy_kernel(const LzArgs a) {
+  __shared__ double sh[4];
+  const int tile = xcd_tile(blockIdx.x, a.grid_tiles);
+  if (tile >= a.n_tiles) return;
+  const UnitDev U = a.units[a.tile_unit[tile]];
+  const ProbDev P = a.probs[U.prob];
+  const int64_t row0 = (int64_t)(tile - U.tile0) * a.tile_rows;
+  const int64_t row1 = min(row0 + a.tile_rows, P.dim);
+  const double cf = a.coef_sqrt ? sqrt(a.coef[U.col_off]) : a.coef[U.col_off];
+  double* w = lz_sel(a.w, a.w_hi, U, P);
+  const double* q = lz_sel(const_cast<double*>(a.q), a.q_hi, U, P);
+  const double* d = a.dotvec ? lz_sel(const_cast<double*>(a.dotvec), a.d_hi, U, P) : nullptr;
+  double acc = 0.0;
+  for (int64_t i = row0 + threadIdx.x; i < row1; i += kThreads) {
+    const double wv = w[i] - cf * q[i];
+    w[i] = wv;
+    acc = fma(wv, d ? d[i] : wv, acc);
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    const int tl = tile - U.tile0;
+    a.part_out[U.part_off + tl] = s;
+    a.part_out[U.part_off + U.ntiles + tl] = 0.0;
+  }
+}
+
+hipError_t launch_lz_axpy(const DevicePlan& p, const LzArgs& args, hipStream_t st) {
+  LzArgs a = args;
+  a.probs = p.probs;
+  a.units = p.units;
+  a.tile_unit = p.tile_unit;
+  a.n_tiles = p.n_tiles;
+  a.grid_tiles = p.grid_tiles;
+  a.tile_rows = p.sub_rows * p.sub_per_tile;
+  hipLaunchKernelGGL(lz_axpy_kernel, dim3(p.grid_tiles), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+// qprev <- q; q <- w / sqrt(beta2)   (skipped once beta2 < 1e-24: finished)
+__global__ __launch_bounds__(kThreads) void lz_next_kernel(const LzArgs a, double* qprev,
+                                                           double* q, const double* w,
+                                                           const double* beta2) {
+  const int tile = xcd_tile(blockIdx.x, a.grid_tiles);
+  if (tile >= a.n_tiles) return;
+  const UnitDev U = a.units[a.tile_unit[tile]];
+  const ProbDev P = a.probs[U.prob];
+  const int64_t row0 = (int64_t)(tile - U.tile0) * a.tile_rows;
+  const int64_t row1 = min(row0 + a.tile_rows, P.dim);
+  const double b2 = beta2[U.col_off];
+  if (!(b2 > 1e-24)) return;
+  const double inv = 1.0 / sqrt(b2);
+  double* qp = qprev + U.vec_off;
+  double* qq = q + U.vec_off;
+  const double* ww = w + U.vec_off + P.dim;
+  for (int64_t i = row0 + threadIdx.x; i < row1; i += kThreads) {
+    qp[i] = qq[i];
+    qq[i] = ww[i] * inv;
+  }
+}
+
+hipError_t launch_lz_next(const DevicePlan& p, double* qprev, double* q, const double* w,
+                          const double* beta2, hipStream_t st) {
+  LzArgs a{};
+  a.probs = p.probs;
+  a.units = p.units;
+  a.tile_unit = p.tile_unit;
+  a.n_tiles = p.n_tiles;
+  a.grid_tiles = p.grid_tiles;
+  a.tile_rows = p.sub_rows * p.sub_per_tile;
+  hipLaunchKernelGGL(lz_next_kernel, dim3(p.grid_tiles), dim3(kThreads), 0, st, a, qprev, q, w,
+                     beta2);
+  return hipGetLastError();
+}
+
+hipError_t launch_matrix(const MatrixArgs& a, size_t lds, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(matrix_kernel, dim3(grid), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+}  // namespace kpm

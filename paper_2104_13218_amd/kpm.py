@@ -1,0 +1,236 @@
+"""Python binding of the C ABI in include/kpm.h (ctypes; argument marshalling only).
+
+Every computation runs in libkpm.so on the GPU.  PyTorch provides device
+memory (tensors whose data pointers are passed through) and the stream
+(torch's current stream).  If the library is not built, `load()` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from ctypes import POINTER, c_double, c_int32, c_int64, c_size_t, c_uint8, c_uint32, c_uint64, c_void_p
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkpm.so")
+
+KPM_OK, KPM_EINVAL, KPM_ENOMEM, KPM_EDEVICE, KPM_EBOUNDS, KPM_EWORKSPACE = 0, -1, -2, -3, -4, -5
+VEC_KINDS = {"rademacher": 0, "complex_gaussian": 1, "gaussian": 2, "basis": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+KERNELS = {"none": 0, "jackson": 1}
+
+
+class KPMError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n_sites", c_int32), ("n_up", c_int32), ("n_bonds", c_int32), ("cluster", c_int32),
+                ("bond_i", POINTER(c_int32)), ("bond_j", POINTER(c_int32)), ("J", POINTER(c_double)),
+                ("e_lo", c_double), ("e_hi", c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("eps", c_double), ("M", c_int32), ("R", c_int32), ("vec_kind", c_int32),
+                ("precision", c_int32), ("col_block", c_int32), ("seed", c_uint64),
+                ("lanczos_steps", c_int32), ("bound_margin", c_double)]
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("step_launches", c_int64), ("bytes_per_launch", c_double),
+                ("state_col_steps", c_double), ("col_block", c_int32), ("rows_per_tile", c_int32),
+                ("graph_segment", c_int32), ("reserved", c_int32)]
+
+
+_lib = None
+
+_SIGS = {
+    "kpm_strerror": (ctypes.c_char_p, [c_int32]),
+    "kpm_sector_dim": (c_uint64, [c_int32, c_int32]),
+    "kpm_sector_states": (c_int32, [c_int32, c_int32, c_void_p, c_void_p]),
+    "kpm_sector_matrix": (c_int32, [POINTER(Problem), c_int64, c_int64, c_int32, c_void_p, c_void_p,
+                                    c_void_p, c_void_p, c_void_p]),
+    "kpm_spectral_bounds": (c_int32, [POINTER(Problem), c_int32, c_int32, c_double, c_uint64,
+                                      POINTER(c_double), c_void_p]),
+    "chebyshev_moments_workspace_size": (c_size_t, [POINTER(Problem), c_int32, POINTER(Params)]),
+    "chebyshev_moments": (c_int32, [POINTER(Problem), c_int32, POINTER(Params), c_void_p, c_void_p,
+                                    c_void_p, c_size_t, c_void_p]),
+    "kpm_thermo": (c_int32, [c_void_p, c_void_p, POINTER(Problem), c_int32, c_int32, c_int32, c_int32,
+                             c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                             c_void_p]),
+    "kpm_thermo_vjp": (c_int32, [c_void_p, c_void_p, POINTER(Problem), c_int32, c_int32, c_int32,
+                                 c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "chebyshev_moments_vjp_workspace_size": (c_size_t, [POINTER(Problem), c_int32, POINTER(Params),
+                                                        c_int32]),
+    "chebyshev_moments_vjp": (c_int32, [POINTER(Problem), c_int32, POINTER(Params), c_void_p, c_void_p,
+                                        c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "kpm_thermo_grad": (c_int32, [POINTER(Problem), c_int32, POINTER(Params), c_int32, c_int32,
+                                  c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_size_t, c_void_p]),
+    "kpm_last_run_stats": (c_int32, [POINTER(RunStats)]),
+}
+
+
+def load():
+    """Load libkpm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2104_13218_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return load().kpm_strerror(code).decode()
+
+
+def _check(code: int, what: str):
+    if code != KPM_OK:
+        raise KPMError(code, what)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+class ProblemSet:
+    """ctypes array of kpm_problem built from workloads.Sector objects (keeps
+    the bond arrays alive)."""
+
+    def __init__(self, sectors, bounds=None):
+        self.sectors = list(sectors)
+        n = len(self.sectors)
+        self.arr = (Problem * n)()
+        self._keep = []
+        for k, s in enumerate(self.sectors):
+            c = s.cluster
+            bi = np.ascontiguousarray(c.bond_i, dtype=np.int32)
+            bj = np.ascontiguousarray(c.bond_j, dtype=np.int32)
+            J = np.ascontiguousarray(c.J, dtype=np.float64)
+            self._keep += [bi, bj, J]
+            if bounds is not None and bounds[k] is not None:
+                lo, hi = bounds[k]
+            else:
+                lo, hi = float(getattr(s, "e_lo", float("nan"))), float(getattr(s, "e_hi", float("nan")))
+            self.arr[k] = Problem(c.n_sites, s.n_up, c.n_bonds, s.cluster_id,
+                                  bi.ctypes.data_as(POINTER(c_int32)), bj.ctypes.data_as(POINTER(c_int32)),
+                                  J.ctypes.data_as(POINTER(c_double)), lo, hi)
+
+    def __len__(self):
+        return len(self.sectors)
+
+    @property
+    def n_clusters(self):
+        return 1 + max(s.cluster_id for s in self.sectors)
+
+
+def make_params(M, R=1, vec_kind="rademacher", precision="fp64", eps=0.025, seed=0, col_block=0,
+                lanczos_steps=50, margin=0.01) -> Params:
+    return Params(float(eps), int(M), int(R), VEC_KINDS[vec_kind], PRECISIONS[precision], int(col_block),
+                  int(seed) % 2**64, int(lanczos_steps), float(margin))
+
+
+def sector_dim(n_sites: int, n_up: int) -> int:
+    return int(load().kpm_sector_dim(n_sites, n_up))
+
+
+def sector_states(n_sites: int, n_up: int, stream=None) -> torch.Tensor:
+    """Basis words in rank order (int32 tensor holding the uint32 bit patterns)."""
+    dim = math.comb(n_sites, n_up)
+    out = torch.empty(max(dim, 1), dtype=torch.int32, device="cuda")
+    _check(load().kpm_sector_states(n_sites, n_up, _ptr(out), _stream(stream)), "kpm_sector_states")
+    return out[:dim]
+
+
+def sector_matrix(sector, row0: int, nrows: int, max_nb: int | None = None, stream=None):
+    """(cols [nrows, max_nb] int32 (uint32 bits), bond [nrows, max_nb], cnt [nrows], diag [nrows])."""
+    ps = ProblemSet([sector])
+    nb = max_nb or max(1, sector.cluster.n_bonds)
+    cols = torch.zeros((max(nrows, 1), nb), dtype=torch.int32, device="cuda")
+    bond = torch.full((max(nrows, 1), nb), -1, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(max(nrows, 1), dtype=torch.int32, device="cuda")
+    diag = torch.zeros(max(nrows, 1), dtype=torch.float64, device="cuda")
+    _check(load().kpm_sector_matrix(ps.arr, row0, nrows, nb, _ptr(cols), _ptr(bond), _ptr(cnt), _ptr(diag),
+                                    _stream(stream)), "kpm_sector_matrix")
+    return cols[:nrows], bond[:nrows], cnt[:nrows], diag[:nrows]
+
+
+def spectral_bounds(sectors, steps=50, margin=0.01, seed=0, stream=None) -> np.ndarray:
+    ps = ProblemSet(sectors)
+    out = (c_double * (2 * len(ps)))()
+    _check(load().kpm_spectral_bounds(ps.arr, len(ps), steps, margin, seed, out, _stream(stream)),
+           "kpm_spectral_bounds")
+    return np.array(out[:]).reshape(len(ps), 2)
+
+
+def moments_workspace_size(problems: ProblemSet, params: Params) -> int:
+    return int(load().chebyshev_moments_workspace_size(problems.arr, len(problems), ctypes.byref(params)))
+
+
+def chebyshev_moments(sectors, M, R=1, vec_kind="rademacher", precision="fp64", eps=0.025, seed=0,
+                      col_block=0, bounds=None, lanczos_steps=50, margin=0.01, workspace=None,
+                      stream=None, problems=None):
+    """Moments mu [n, M] (float64, cuda) and (a, b) [n, 2] of Eqs. (4)-(7)."""
+    ps = problems or ProblemSet(sectors, bounds)
+    q = make_params(M, R, vec_kind, precision, eps, seed, col_block, lanczos_steps, margin)
+    mu = torch.empty((len(ps), M), dtype=torch.float64, device="cuda")
+    ab = torch.empty((len(ps), 2), dtype=torch.float64, device="cuda")
+    if workspace is None:
+        nbytes = moments_workspace_size(ps, q)
+        if nbytes == 0:
+            raise KPMError(KPM_EINVAL, "chebyshev_moments_workspace_size")
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    _check(load().chebyshev_moments(ps.arr, len(ps), ctypes.byref(q), _ptr(mu), _ptr(ab), _ptr(workspace),
+                                    workspace.numel(), _stream(stream)), "chebyshev_moments")
+    return mu, ab
+
+
+def thermo(mu, ab, sectors, T, kernel="jackson", n_nodes=0, stream=None):
+    """ln Z, E, C, chi [n_clusters, n_T] and the Z <= 0 flags."""
+    ps = sectors if isinstance(sectors, ProblemSet) else ProblemSet(sectors)
+    mu = mu.contiguous()
+    ab = ab.contiguous()
+    T = torch.as_tensor(T, dtype=torch.float64, device="cuda").contiguous()
+    nc, nT = ps.n_clusters, T.numel()
+    out = {k: torch.empty((nc, nT), dtype=torch.float64, device="cuda") for k in ("lnZ", "E", "C", "chi")}
+    out["z_nonpos"] = torch.empty((nc, nT), dtype=torch.uint8, device="cuda")
+    _check(load().kpm_thermo(_ptr(mu), _ptr(ab), ps.arr, len(ps), mu.shape[1], KERNELS[kernel], n_nodes,
+                             _ptr(T), nT, _ptr(out["lnZ"]), _ptr(out["E"]), _ptr(out["C"]), _ptr(out["chi"]),
+                             _ptr(out["z_nonpos"]), _stream(stream)), "kpm_thermo")
+    return out
+
+
+def thermo_vjp(mu, ab, sectors, T, wC, wchi, kernel="jackson", n_nodes=0, stream=None):
+    """dL/dmu [n, M] for L = sum wC C + wchi chi."""
+    ps = sectors if isinstance(sectors, ProblemSet) else ProblemSet(sectors)
+    mu = mu.contiguous()
+    T = torch.as_tensor(T, dtype=torch.float64, device="cuda").contiguous()
+    wC = torch.as_tensor(wC, dtype=torch.float64, device="cuda").contiguous()
+    wchi = torch.as_tensor(wchi, dtype=torch.float64, device="cuda").contiguous()
+    lam = torch.empty_like(mu)
+    _check(load().kpm_thermo_vjp(_ptr(mu), _ptr(ab.contiguous()), ps.arr, len(ps), mu.shape[1], KERNELS[kernel],
+                                 n_nodes, _ptr(T), T.numel(), _ptr(wC), _ptr(wchi), _ptr(lam), _stream(stream)),
+           "kpm_thermo_vjp")
+    return lam
+
+
+def last_run_stats() -> dict:
+    s = RunStats()
+    _check(load().kpm_last_run_stats(ctypes.byref(s)), "kpm_last_run_stats")
+    return {f: getattr(s, f) for f, _ in RunStats._fields_}
