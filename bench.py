@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Benchmark of the Chebyshev-moment hot path on one MI355X.
+
+Workload (one "step" = one pass of the whole path over one batch of input):
+spin-1/2 Heisenberg ring, N = 24, J = 1, S^z = 0 sector (2,704,156 states),
+10 complex Gaussian random vectors (20 real columns, one column block), M = 2000
+moments (1000 recursion launches), eps = 0.025, bounds from 50-step Lanczos with
+a 1% margin, float32 vector storage with float64 arithmetic and dots, then the
+Jackson-kernel thermodynamics at 200 log-spaced temperatures in [0.01, 10].
+
+`value` is state-column-steps per second of the whole pass (dim x real columns
+x recursion steps / wall time of the pass, inputs resident on the GPU).  The
+JSON line also carries:
+  roofline      the step kernel's algorithmic HBM bytes (3 x 4 B per state and
+                column) over its average launch time, measured with hipEvents on
+                the launch stream during the timed passes; `traffic` is the
+                rocprofv3-measured bytes per launch from the committed counter
+                summary, or null
+  fp64_plain    the same recursion in float64, one column per block (the
+                reference form), and fp64_batched (float64, all 20 columns)
+  accuracy      float32-storage error against float64 on the same seeds, all
+                13 S^z >= 0 sectors of the ring: C(T), chi(T), ln Z, E, moments
+  cpu_baseline  the CPU oracle on a bounded sample of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Chebyshev steps·dim/s + HBM GB/s at N=24 S^z=0; speedup vs FP64 at C(T) err"
+HBM_PEAK_GBS = 8000.0
+STEP_KERNEL = "step_kernel<float, 4>"
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "step_kernel_ring24_sz0_fp32_traffic.json")
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--M", type=int, default=2000)
+    ap.add_argument("--skip-extras", action="store_true",
+                    help="only the timed workload (for profiler runs)")
+    ap.add_argument("--cpu-steps", type=int, default=6,
+                    help="recursion steps of the CPU-oracle sample")
+    return ap.parse_args()
+
+
+def _traffic(bytes_per_launch):
+    """Measured HBM bytes per step launch from the committed rocprofv3 counter
+    summary, when it was taken on the current kernel source."""
+    try:
+        with open(PROFILE_TRAFFIC) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    from paper_2104_13218_amd import build as _b
+    import hashlib
+    src = open(os.path.join(_b.CSRC, "kpm_kernels.hip"), "rb").read()
+    if d.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    args = _parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the work would shard over independent sectors and column blocks; see the design notes).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2104_13218_amd import kpm
+
+    kpm.load()
+    torch.cuda.init()
+    dev = torch.cuda.get_device_name(0)
+
+    ring = W.ring(24)
+    sec = W.sectors(ring, only_sz0=True)
+    M = args.M
+    T = torch.tensor(W.log_temperatures(200, 0.01, 10.0), device="cuda")
+    ps = kpm.ProblemSet(sec)
+    q32 = kpm.make_params(M, 10, "complex_gaussian", "fp32", 0.025, 0, col_block=20)
+    ws = torch.empty(kpm.moments_workspace_size(ps, q32), dtype=torch.uint8, device="cuda")
+
+    def one_pass():
+        mu, ab = kpm.chebyshev_moments(None, M, 10, "complex_gaussian", "fp32", 0.025, 0, col_block=20,
+                                       workspace=ws, problems=ps)
+        kpm.thermo(mu, ab, ps, T, "jackson")
+        return kpm.last_run_stats()
+
+    for _ in range(args.warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(one_pass())
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    st = stats[-1]
+    value = st["state_col_steps"] / dt
+    avg_launch_s = sum(s["recursion_ms"] for s in stats) / len(stats) / 1e3 / st["step_launches"]
+    achieved = st["bytes_per_launch"] / avg_launch_s / 1e9
+    traffic = _traffic(st["bytes_per_launch"])
+    line = {
+        "metric": METRIC, "value": value, "unit": "state-column-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "heisenberg_ring_N24_Sz0", "dim": sec[0].dim, "vectors": "10 complex Gaussian",
+                   "real_columns": 20, "M": M, "recursion_launches": st["step_launches"], "eps": 0.025,
+                   "bounds": "lanczos50+1%", "storage": "f32", "col_block": st["col_block"],
+                   "rows_per_tile": st["rows_per_tile"], "graph_segment": st["graph_segment"],
+                   "device": dev},
+        "roofline": {"bound": "hbm", "kernel": STEP_KERNEL, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "algorithmic_bytes_per_launch": st["bytes_per_launch"],
+                     "avg_launch_us": avg_launch_s * 1e6,
+                     "traffic": traffic},
+    }
+
+    if not args.skip_extras:
+        line.update(extras(args, kpm, W, np, torch, sec, ps, T, M, value, ws))
+    print(json.dumps(line), flush=True)
+
+
+def _time_moments(kpm, torch, sec, M, R, kind, precision, col_block, reps=1):
+    kpm.chebyshev_moments(sec, M, R, kind, precision, 0.025, 0, col_block=col_block)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mu, ab = kpm.chebyshev_moments(sec, M, R, kind, precision, 0.025, 0, col_block=col_block)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    st = kpm.last_run_stats()
+    return mu, ab, dt, st
+
+
+def extras(args, kpm, W, np, torch, sec, ps, T, M, value, ws):
+    out = {}
+    # float64 comparators on the same workload.  The single-column form needs
+    # real vectors (a complex vector's Re and Im share one block): 20 real
+    # Gaussian vectors give the same dim x columns x steps.
+    _, _, dt, st = _time_moments(kpm, torch, sec, M, 20, "gaussian", "fp64", 1)
+    plain = st["state_col_steps"] / dt
+    _, _, dtb, stb = _time_moments(kpm, torch, sec, M, 10, "complex_gaussian", "fp64", 20)
+    batched = stb["state_col_steps"] / dtb
+    out["fp64_plain"] = {"value": plain, "ms": dt * 1e3, "col_block": 1,
+                         "avg_launch_us": st["recursion_ms"] * 1e3 / st["step_launches"]}
+    out["fp64_batched"] = {"value": batched, "ms": dtb * 1e3, "col_block": stb["col_block"],
+                           "avg_launch_us": stb["recursion_ms"] * 1e3 / stb["step_launches"]}
+    # recursion-only rate of the float32 form, for a like-for-like speedup
+    _, _, dtf, stf = _time_moments(kpm, torch, sec, M, 10, "complex_gaussian", "fp32", 20)
+    out["speedup_vs_fp64_plain"] = (stf["state_col_steps"] / dtf) / plain
+    out["speedup_vs_fp64_batched"] = (stf["state_col_steps"] / dtf) / batched
+
+    # accuracy of float32 storage against float64, all S^z >= 0 sectors
+    allsec = W.sectors(W.ring(24))
+    mu64, ab64 = kpm.chebyshev_moments(allsec, M, 10, "complex_gaussian", "fp64", 0.025, 0, col_block=20)
+    mu32, ab32 = kpm.chebyshev_moments(allsec, M, 10, "complex_gaussian", "fp32", 0.025, 0, col_block=20)
+    Th = T.cpu().numpy()
+    acc = {"moments_max_abs_err_over_mu0": float((mu32 - mu64).abs().max(dim=1).values.div(mu64[:, 0]).max())}
+    for kern in ("jackson", "none"):
+        t64 = kpm.thermo(mu64, ab64, allsec, T, kern)
+        t32 = kpm.thermo(mu32, ab32, allsec, T, kern)
+        C64 = t64["C"].cpu().numpy()[0]
+        bad = np.nonzero((C64 < 0) | t64["z_nonpos"].cpu().numpy()[0].astype(bool))[0]
+        i_phys = bad.max() + 1 if bad.size else 0
+        band = np.arange(Th.size) >= i_phys
+        rec = {"T_phys": float(Th[min(i_phys, Th.size - 1)])}
+        for qn in ("C", "chi"):
+            a = t64[qn].cpu().numpy()[0]
+            b = t32[qn].cpu().numpy()[0]
+            err = np.abs(a - b) / np.abs(a[band]).max()
+            rec[f"{qn}_max_err_T>=T_phys"] = float(err[band].max())
+            ok = np.nonzero(err <= 1e-6)[0]
+            lowest = None
+            for i in range(Th.size - 1, -1, -1):
+                if err[i] > 1e-6:
+                    break
+                lowest = float(Th[i])
+            rec[f"{qn}_lowest_T_with_err<=1e-6"] = lowest
+        for qn in ("lnZ", "E"):
+            a = t64[qn].cpu().numpy()[0][band]
+            b = t32[qn].cpu().numpy()[0][band]
+            rec[f"{qn}_max_rel_err_T>=T_phys"] = float(np.nanmax(np.abs(a - b) / np.abs(a)))
+        acc[kern] = rec
+    out["accuracy_fp32_vs_fp64_all_sectors"] = acc
+
+    # CPU oracle on a bounded sample of the same workload
+    out["cpu_baseline"] = cpu_baseline(args, W, np, sec)
+    return out
+
+
+def cpu_baseline(args, W, np, sec):
+    from threadpoolctl import threadpool_limits
+
+    from oracle import hamiltonian, moments, rng
+
+    s = sec[0]
+    H = hamiltonian.sector_hamiltonian(s.cluster, s.n_up)
+    lo, hi = -11.0, 7.0          # encloses the ring's spectrum (E_0 = -10.77, E_max = 6)
+    a, b = hamiltonian.scale_from_bounds(lo, hi, 0.025)
+    Ht = hamiltonian.rescaled(H, a, b)
+    V0, _, _ = rng.random_columns("complex_gaussian", 0, 0, s.n_up, 10, H.shape[0])
+    K = args.cpu_steps
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        moments.chebyshev_dots(Ht, V0, K, store=np.float32)
+        dt = time.perf_counter() - t0
+    rate = H.shape[0] * V0.shape[1] * K / dt
+    return {"value": rate, "unit": "state-column-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle float32-storage recursion, N=24 S^z=0 sector, 20 real columns, {K} steps "
+                      f"(matrix build excluded), {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -187,18 +187,19 @@ int kpm_thermo_grad(const kpm_problem* p, int32_t n, const kpm_params* q, int32_
                     const double* d_wchi, int32_t ckpt_every, double* d_L, double* d_dJ,
                     double* d_ab, void* d_work, size_t work_bytes, void* stream);
 
-/* Launch statistics of the last chebyshev_moments call on this thread:
- * number of recursion-step kernel launches, algorithmic bytes per launch
- * (3 * storage size * sum over blocks of dim * columns), and the step kernel's
- * float64 dot count.  Host only. */
+/* Launch statistics of the last chebyshev_moments call on this thread.
+ * Host only (reads what the call recorded). */
 typedef struct {
-  int64_t step_launches;
-  double bytes_per_launch;
+  int64_t step_launches;   /* recursion-step kernel launches (= M/2) */
+  double bytes_per_launch; /* algorithmic HBM bytes of one step: 3 * storage
+                              size * sum over blocks of dim * real columns */
   double state_col_steps;  /* sum over blocks of dim * real columns * steps */
-  int32_t col_block;       /* columns per block chosen */
-  int32_t rows_per_tile;   /* rows per workgroup tile chosen */
-  int32_t graph_segment;   /* steps per captured graph (0 = no graph) */
+  int32_t col_block;       /* real columns per block chosen */
+  int32_t rows_per_tile;   /* basis states per workgroup tile */
+  int32_t graph_segment;   /* steps per captured graph (0 = direct launches) */
   int32_t reserved;
+  double recursion_ms;     /* hipEvent time on the call's stream from the first
+                              to the last recursion-step launch, inclusive */
 } kpm_run_stats;
 int kpm_last_run_stats(kpm_run_stats* out);
 

@@ -246,9 +246,13 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   D.lds_bonds = max_bonds;
   D.lds_nb = max_bonds;
   D.sub_rows = 256;
-  const size_t lds_cap = (size_t)env_int("KPM_LDS_CAP", 64 * 1024);
-  while (step_lds_bytes(D) > lds_cap && D.sub_rows > 32) D.sub_rows >>= 1;
-  if (step_lds_bytes(D) > lds_cap) return KPM_EINVAL;
+  // Prefer <= 32 KB of LDS per workgroup (occupancy) while keeping >= 64 rows
+  // per sub-tile; never exceed 64 KB.
+  const size_t lds_soft = (size_t)env_int("KPM_LDS_CAP", 32 * 1024);
+  const size_t lds_hard = 64 * 1024;
+  while (step_lds_bytes(D) > lds_soft && D.sub_rows > 64) D.sub_rows >>= 1;
+  while (step_lds_bytes(D) > lds_hard && D.sub_rows > 32) D.sub_rows >>= 1;
+  if (step_lds_bytes(D) > lds_hard) return KPM_EINVAL;
 
   // Rows per workgroup tile: enough rows to amortise the per-tile LDS fill,
   // but keep >= 2048 tiles on the largest block when its size permits.
@@ -261,6 +265,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   spt = std::min(spt, 64);
   if (const int f = env_int("KPM_SUB_PER_TILE", 0)) spt = f;
   D.sub_per_tile = spt;
+  D.xcd_remap = env_int("KPM_XCD_REMAP", 1);
   const int64_t tile_rows = (int64_t)D.sub_rows * spt;
 
   int64_t vec_elems = 0, part_len = 0;
@@ -620,6 +625,20 @@ int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
   }
   KPM_HIP(launch_init(D, vec, 1, q.vec_kind, q.seed, norms, part[0], st));
   KPM_HIP(launch_reduce(D, part[0], alpha, nullptr, st));
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  KPM_HIP(hipEventCreate(&ev0));
+  if (hipEventCreate(&ev1) != hipSuccess) {
+    (void)hipEventDestroy(ev0);
+    return KPM_EDEVICE;
+  }
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } evg{ev0, ev1};
+  KPM_HIP(hipEventRecord(ev0, st));
   KPM_HIP(launch_step(D, vec, part[0], nullptr, 0, alpha, beta, nullptr, 0, 0, 1, st));
   int s = 1;
   const int S = graph_segment();
@@ -650,6 +669,7 @@ int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
   for (; s < K; ++s)
     KPM_HIP(launch_step(D, vec, part[s & 1], part[(s - 1) & 1], 2 * TC, alpha, beta, nullptr, s,
                         s & 1, 0, st));
+  KPM_HIP(hipEventRecord(ev1, st));
   KPM_HIP(launch_reduce(D, part[(K - 1) & 1], alpha + (size_t)K * TC, beta + (size_t)(K - 1) * TC, st));
   FinalArgs fa{};
   fa.probs = D.probs;
@@ -676,6 +696,8 @@ int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
   for (auto& u : P.units) g_stats.col_block = std::max(g_stats.col_block, u.ncols);
   g_stats.rows_per_tile = D.sub_rows * D.sub_per_tile;
   g_stats.graph_segment = used_segment;
+  float ms = 0.f;
+  g_stats.recursion_ms = hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess ? (double)ms : -1.0;
   if (h_flag & 2) return KPM_EDEVICE;
   return (h_flag & 1) ? KPM_EBOUNDS : KPM_OK;
 }

@@ -62,6 +62,7 @@ struct StepArgs {
   int32_t lds_tab;             // table capacity (u32 entries) in LDS
   int32_t lds_bonds;           // bond capacity in LDS
   int* err;                    // bit 1 set if a neighbour rank fell outside its sector
+  int32_t xcd_remap;           // 1: contiguous tile ranges per XCD
 };
 
 // Device-side plan of one run (pointers into the workspace) + launch shape.
@@ -81,6 +82,7 @@ struct DevicePlan {
   int32_t sub_rows = 256, sub_per_tile = 1, lds_nb = 0, lds_tab = 0, lds_bonds = 0;
   int32_t cpl = 1;
   int32_t fp32 = 0;
+  int32_t xcd_remap = 1;
   int64_t part_len = 0;        // doubles per partial buffer
   int64_t vec_elems = 0;       // elements of vector storage (A and B of all units)
 };

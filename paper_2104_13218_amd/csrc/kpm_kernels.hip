@@ -40,6 +40,57 @@ __device__ __forceinline__ void vstore(T* p, const VecT<T, N>& x) {
   *reinterpret_cast<VecT<T, N>*>(p) = x;
 }
 
+// Non-temporal (streaming) 16-byte accesses for data touched once per step:
+// v_{n-1} is read once and v_{n+1} written once, so they should not displace
+// the gathered rows of v_n from the caches.
+template <typename T, int N>
+struct NtVec;
+template <> struct NtVec<float, 4> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct NtVec<float, 2> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct NtVec<float, 1> { typedef float type; };
+template <> struct NtVec<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct NtVec<double, 1> { typedef double type; };
+
+template <typename T, int N>
+__device__ __forceinline__ VecT<T, N> vload_nt(const T* p) {
+  VecT<T, N> r;
+  if constexpr (N == 4 && sizeof(T) == 8) {
+    typedef typename NtVec<double, 2>::type V;
+    const V a = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+    const V b = __builtin_nontemporal_load(reinterpret_cast<const V*>(p) + 1);
+    r.v[0] = a[0]; r.v[1] = a[1]; r.v[2] = b[0]; r.v[3] = b[1];
+  } else if constexpr (N == 1) {
+    r.v[0] = __builtin_nontemporal_load(p);
+  } else {
+    typedef typename NtVec<T, N>::type V;
+    const V a = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.v[i] = a[i];
+  }
+  return r;
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void vstore_nt(T* p, const VecT<T, N>& x) {
+  if constexpr (N == 4 && sizeof(T) == 8) {
+    typedef typename NtVec<double, 2>::type V;
+    V a, b;
+    a[0] = x.v[0]; a[1] = x.v[1]; b[0] = x.v[2]; b[1] = x.v[3];
+    __builtin_nontemporal_store(a, reinterpret_cast<V*>(p));
+    __builtin_nontemporal_store(b, reinterpret_cast<V*>(p) + 1);
+  } else if constexpr (N == 1) {
+    __builtin_nontemporal_store(x.v[0], p);
+  } else {
+    typedef typename NtVec<T, N>::type V;
+    V a;
+#pragma unroll
+    for (int i = 0; i < N; ++i) a[i] = x.v[i];
+    __builtin_nontemporal_store(a, reinterpret_cast<V*>(p));
+  }
+}
+
+constexpr int kGatherBatch = 4;   // neighbour loads in flight per lane
+
 // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
 // contiguous range of tiles so neighbour rows with small rank offsets are
 // found in that XCD's L2.
@@ -213,7 +264,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
     __syncthreads();
   }
 
-  const int tile = xcd_tile(blockIdx.x, a.grid_tiles);
+  const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.grid_tiles) : (int)blockIdx.x;
   if (tile >= a.n_tiles) return;
   const UnitDev U = a.units[a.tile_unit[tile]];
   const ProbDev P = a.probs[U.prob];
@@ -252,24 +303,37 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
 #pragma unroll
         for (int i = 0; i < CPL; ++i) acc[i] = dg * (double)xv.v[i];
         const int cnt = S.cnt[r];
-        for (int k = 0; k < cnt; ++k) {
-          const uint32_t nb = S.nbr[k * a.sub_rows + r];
-          const double cf = S.off[S.nbb[k * a.sub_rows + r]];
-          const VecT<T, CPL> nv = vload<T, CPL>(X + (int64_t)nb * ld + c * CPL);
-#pragma unroll
-          for (int i = 0; i < CPL; ++i) acc[i] = fma(cf, (double)nv.v[i], acc[i]);
-        }
         T* ys = Y + rho * ld + c * CPL;
+        VecT<T, CPL> yv;
+        if (!a.first) yv = vload_nt<T, CPL>(ys);
+        // gathers issued kGatherBatch at a time (absent entries read the row
+        // itself with a zero coefficient), then accumulated in order
+        for (int k0 = 0; k0 < cnt; k0 += kGatherBatch) {
+          VecT<T, CPL> nv[kGatherBatch];
+          double cf[kGatherBatch];
+#pragma unroll
+          for (int j = 0; j < kGatherBatch; ++j) {
+            const int k = k0 + j;
+            const bool on = k < cnt;
+            const uint32_t nb = on ? S.nbr[k * a.sub_rows + r] : (uint32_t)rho;
+            cf[j] = on ? S.off[S.nbb[k * a.sub_rows + r]] : 0.0;
+            nv[j] = vload<T, CPL>(X + (int64_t)nb * ld + c * CPL);
+          }
+#pragma unroll
+          for (int j = 0; j < kGatherBatch; ++j) {
+#pragma unroll
+            for (int i = 0; i < CPL; ++i) acc[i] = fma(cf[j], (double)nv[j].v[i], acc[i]);
+          }
+        }
         VecT<T, CPL> ov;
         if (a.first) {
 #pragma unroll
           for (int i = 0; i < CPL; ++i) ov.v[i] = (T)acc[i];
         } else {
-          const VecT<T, CPL> yv = vload<T, CPL>(ys);
 #pragma unroll
           for (int i = 0; i < CPL; ++i) ov.v[i] = (T)(2.0 * acc[i] - (double)yv.v[i]);
         }
-        vstore<T, CPL>(ys, ov);
+        vstore_nt<T, CPL>(ys, ov);
 #pragma unroll
         for (int i = 0; i < CPL; ++i) {
           const double o = (double)ov.v[i];
@@ -345,6 +409,7 @@ static StepArgs make_step_args(const DevicePlan& p) {
   a.lds_nb = p.lds_nb;
   a.lds_tab = p.lds_tab;
   a.lds_bonds = p.lds_bonds;
+  a.xcd_remap = p.xcd_remap;
   return a;
 }
 
