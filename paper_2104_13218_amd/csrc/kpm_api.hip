@@ -148,7 +148,10 @@ struct RunShape {
   int vec_kind = KPM_VEC_RADEMACHER;
   int R = 1;
   int col_block = 0;
+  bool adjoint = false;   // block widths padded to the adjoint kernel's (1..16, power of 2)
 };
+
+constexpr int kAdjMaxLd = 16;
 
 // Columns per vector: a complex vector is two real columns (Re, Im).
 int cols_per_vec(int vec_kind) { return vec_kind == KPM_VEC_COMPLEX_GAUSSIAN ? 2 : 1; }
@@ -193,11 +196,18 @@ int pick_col_block(const kpm_problem* p, int n, const RunShape& s) {
 int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_arr,
               const double* b_arr, Planned& P) {
   const int fp32 = s.precision == KPM_FP32_STORE;
-  const int rb = pick_col_block(p, n, s);
+  int rb = pick_col_block(p, n, s);
+  int adj_ld = 0;
+  if (s.adjoint) {
+    rb = std::min(rb, kAdjMaxLd);
+    adj_ld = 1;
+    while (adj_ld < rb) adj_ld <<= 1;
+  }
   int cpl = 1;
   if (fp32) cpl = rb >= 4 ? 4 : (rb >= 2 ? 2 : 1);
   else cpl = rb >= 2 ? 2 : 1;
   if (const int f = env_int("KPM_CPL", 0)) cpl = f;
+  if (adj_ld) cpl = std::min(cpl, adj_ld);
   const int elt = fp32 ? 4 : 8;
 
   P.binom = binom_table();
@@ -252,7 +262,10 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   const size_t lds_hard = 64 * 1024;
   while (step_lds_bytes(D) > lds_soft && D.sub_rows > 64) D.sub_rows >>= 1;
   while (step_lds_bytes(D) > lds_hard && D.sub_rows > 32) D.sub_rows >>= 1;
+  if (s.adjoint)
+    while (adjoint_lds_bytes(D) > lds_hard && D.sub_rows > 32) D.sub_rows >>= 1;
   if (step_lds_bytes(D) > lds_hard) return KPM_EINVAL;
+  if (s.adjoint && (adjoint_lds_bytes(D) > lds_hard || max_bonds > D.sub_rows)) return KPM_EINVAL;
 
   // Rows per workgroup tile: enough rows to amortise the per-tile LDS fill,
   // but keep >= 2048 tiles on the largest block when its size permits.
@@ -268,7 +281,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   D.xcd_remap = env_int("KPM_XCD_REMAP", 1);
   const int64_t tile_rows = (int64_t)D.sub_rows * spt;
 
-  int64_t vec_elems = 0, part_len = 0;
+  int64_t vec_elems = 0, part_len = 0, bd_len = 0;
   int32_t tiles = 0, col_off = 0;
   for (int i = 0; i < n; ++i) {
     P.prob_unit0.push_back((int32_t)P.units.size());
@@ -278,14 +291,16 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
       UnitDev u{};
       u.prob = i;
       u.ncols = (int32_t)std::min<int64_t>(rb, nc - c0);
-      u.ld = (u.ncols + cpl - 1) / cpl * cpl;
+      u.ld = adj_ld ? adj_ld : (u.ncols + cpl - 1) / cpl * cpl;
       u.col0 = (int32_t)c0;
       u.vec_off = vec_elems;
-      vec_elems += (int64_t)align_up((size_t)(2 * dim * u.ld), 64);
+      vec_elems += (int64_t)align_up((size_t)(dim * u.ld), 64);
       u.ntiles = (int32_t)((dim + tile_rows - 1) / tile_rows);
       u.tile0 = tiles;
       u.part_off = part_len;
       part_len += (int64_t)2 * u.ld * u.ntiles;
+      u.bd_off = bd_len;
+      bd_len += (int64_t)u.ntiles * std::max(1, p[i].n_bonds);
       u.col_off = col_off;
       for (int t = 0; t < u.ntiles; ++t) P.tile_unit.push_back((int32_t)P.units.size());
       for (int j = 0; j < 2 * u.ld; ++j) P.job_unit.push_back((int32_t)P.units.size());
@@ -303,7 +318,9 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   D.grid_tiles = (tiles + 7) / 8 * 8;
   D.total_cols = col_off;
   D.part_len = std::max<int64_t>(part_len, 1);
-  D.vec_elems = vec_elems;
+  D.slot_stride = vec_elems;
+  D.vec_elems = 2 * vec_elems;
+  D.bd_len = std::max<int64_t>(bd_len, 1);
 
   size_t o = 0;
   auto put = [&](size_t bytes) {
@@ -737,6 +754,188 @@ int resolve_scale(const kpm_problem* p, int n, const kpm_params& q, unsigned cha
   return KPM_OK;
 }
 
+// ------------------------------------------------------------- adjoint driver
+
+struct VjpLayout {
+  size_t plan, seg, w, ckpt, part, norms, alpha0, abar, bbar, bd, flag, total;
+  int nck, C, K;
+};
+
+VjpLayout vjp_layout(const Planned& P, int M, int ckpt_every) {
+  VjpLayout L{};
+  const int K = n_steps(M);
+  const int C = std::max(2, ckpt_every & ~1);
+  L.K = K;
+  L.C = C;
+  L.nck = (K - 1) / C + 1;
+  const size_t elt = P.plan.fp32 ? 4 : 8;
+  const size_t slot = (size_t)P.plan.slot_stride * elt;
+  const size_t TC = (size_t)P.plan.total_cols;
+  size_t o = 0;
+  auto put = [&](size_t bytes) {
+    const size_t r = o;
+    o = align_up(o + bytes);
+    return r;
+  };
+  L.plan = put(P.bytes);
+  L.seg = put((size_t)(std::min(C, K) + 2) * slot);
+  L.w = put(2 * slot);
+  L.ckpt = put((size_t)L.nck * 2 * slot);
+  L.part = put((size_t)P.plan.part_len * 8);
+  L.norms = put(TC * 8);
+  L.alpha0 = put(TC * 8);
+  L.abar = put((size_t)(K + 1) * TC * 8);
+  L.bbar = put((size_t)(K + 1) * TC * 8);
+  L.bd = put((size_t)P.plan.bd_len * 8);
+  L.flag = put(256);
+  L.total = o;
+  return L;
+}
+
+RunShape adj_shape(const kpm_params& q) {
+  RunShape s = shape_of(q);
+  s.adjoint = true;
+  return s;
+}
+
+size_t vjp_workspace(const kpm_problem* p, int n, const kpm_params& q, int ckpt_every) {
+  Planned P;
+  if (make_plan(p, n, adj_shape(q), nullptr, nullptr, P) != KPM_OK) return 0;
+  return vjp_layout(P, q.M, ckpt_every).total;
+}
+
+// Forward recursion with checkpoints, then the reverse sweep segment by
+// segment (recomputing each segment's v_n from its checkpoint).
+int run_vjp(const kpm_problem* p, int n, const kpm_params& q, const double* h_ab,
+            const double* d_dmu, int ckpt_every, double* d_dJ, unsigned char* work,
+            hipStream_t st) {
+  std::vector<double> a(n), b(n);
+  for (int i = 0; i < n; ++i) {
+    a[i] = h_ab[2 * i];
+    b[i] = h_ab[2 * i + 1];
+    if (!(a[i] > 0.0) || !std::isfinite(a[i]) || !std::isfinite(b[i])) return KPM_EINVAL;
+  }
+  Planned P;
+  int r = make_plan(p, n, adj_shape(q), a.data(), b.data(), P);
+  if (r != KPM_OK) return r;
+  const VjpLayout L = vjp_layout(P, q.M, ckpt_every);
+  std::vector<unsigned char> staging;
+  r = upload_plan(P, work + L.plan, staging, st);
+  if (r != KPM_OK) return r;
+  DevicePlan& D = P.plan;
+  int* flag = reinterpret_cast<int*>(work + L.flag);
+  D.err = flag;
+  KPM_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+  const int K = L.K, C = L.C;
+  const size_t elt = D.fp32 ? 4 : 8;
+  const size_t slot_bytes = (size_t)D.slot_stride * elt;
+  unsigned char* seg = work + L.seg;
+  unsigned char* wbuf = work + L.w;
+  unsigned char* ckpt = work + L.ckpt;
+  double* part = reinterpret_cast<double*>(work + L.part);
+  double* norms = reinterpret_cast<double*>(work + L.norms);
+  double* alpha0 = reinterpret_cast<double*>(work + L.alpha0);
+  double* abar = reinterpret_cast<double*>(work + L.abar);
+  double* bbar = reinterpret_cast<double*>(work + L.bbar);
+  double* bd = reinterpret_cast<double*>(work + L.bd);
+  const int TC = D.total_cols;
+  int ld = 1;
+  for (auto& u : P.units) ld = std::max(ld, u.ld);
+
+  // forward: v_0 (and its norms), steps with a checkpoint of (v_j, v_{j+1}) at j = 0, C, 2C, ...
+  if (q.vec_kind == KPM_VEC_GAUSSIAN || q.vec_kind == KPM_VEC_COMPLEX_GAUSSIAN) {
+    KPM_HIP(launch_init(D, seg, 0, q.vec_kind, q.seed, nullptr, part, st));
+    KPM_HIP(launch_reduce(D, part, norms, nullptr, st));
+  }
+  KPM_HIP(launch_init(D, seg, 1, q.vec_kind, q.seed, norms, part, st));
+  KPM_HIP(launch_reduce(D, part, alpha0, nullptr, st));
+  KPM_HIP(launch_step_slots(D, seg, part, 0, 1, 1, 1, st));
+  for (int j = 0; j < K; ++j) {
+    if (j > 0) KPM_HIP(launch_step_slots(D, seg, part, j & 1, (j + 1) & 1, (j + 1) & 1, 0, st));
+    if (j % C == 0)
+      KPM_HIP(hipMemcpyAsync(ckpt + (size_t)(j / C) * 2 * slot_bytes, seg, 2 * slot_bytes,
+                             hipMemcpyDeviceToDevice, st));
+  }
+  // Each checkpoint m holds v_{mC} in slot (mC)&1 = 0 (C is even) and v_{mC+1} in slot 1.
+  DoublingVjpArgs dv{};
+  dv.probs = D.probs;
+  dv.units = D.units;
+  dv.job_unit = D.job_unit;
+  dv.lambda = d_dmu;
+  dv.alpha0 = alpha0;
+  dv.abar = abar;
+  dv.bbar = bbar;
+  dv.total_cols = TC;
+  dv.M = q.M;
+  dv.K = K;
+  dv.cols_per_vec = cols_per_vec(q.vec_kind);
+  dv.R = q.vec_kind == KPM_VEC_BASIS ? 0 : q.R;
+  KPM_HIP(hipMemsetAsync(bbar + (size_t)K * TC, 0, (size_t)TC * 8, st));
+  KPM_HIP(launch_doubling_vjp(dv, st));
+  KPM_HIP(hipMemsetAsync(wbuf, 0, 2 * slot_bytes, st));
+
+  bool first = true;
+  for (int m = L.nck - 1; m >= 0; --m) {
+    const int j0 = m * C;
+    const int j1 = std::min(j0 + C, K);
+    KPM_HIP(hipMemcpyAsync(seg, ckpt + (size_t)m * 2 * slot_bytes, 2 * slot_bytes,
+                           hipMemcpyDeviceToDevice, st));
+    const int top = std::min(j1 + 1, K);   // highest v index needed
+    for (int t = 1; j0 + t + 1 <= top; ++t)
+      KPM_HIP(launch_step_slots(D, seg, part, t, t - 1, t + 1, 0, st));
+    for (int nn = j1; nn >= j0 + 1; --nn) {
+      AdjArgs aa{};
+      aa.vseg = seg;
+      aa.wbuf = wbuf;
+      aa.vm1_slot = nn - 1 - j0;
+      aa.v0_slot = nn - j0;
+      aa.vp1_slot = nn + 1 <= K ? nn + 1 - j0 : -1;
+      aa.wx_slot = (nn + 1) & 1;
+      aa.wy_slot = nn & 1;
+      aa.abar_n = abar + (size_t)nn * TC;
+      aa.bbar_n = bbar + (size_t)nn * TC;
+      aa.bbar_nm1 = bbar + (size_t)(nn - 1) * TC;
+      aa.part_bd = bd;
+      aa.coef = 2.0;
+      aa.accumulate = first ? 0 : 1;
+      aa.dots_only = 0;
+      KPM_HIP(launch_adjoint(D, aa, ld, st));
+      first = false;
+    }
+  }
+  // <w_1, h_b v_0> with weight 1 (segment 0 is resident: slot 0 holds v_0)
+  AdjArgs fin{};
+  fin.vseg = seg;
+  fin.wbuf = wbuf;
+  fin.vm1_slot = -1;
+  fin.v0_slot = 0;
+  fin.vp1_slot = -1;
+  fin.wx_slot = 1;
+  fin.wy_slot = 0;
+  fin.abar_n = abar;
+  fin.bbar_n = bbar;
+  fin.bbar_nm1 = bbar;
+  fin.part_bd = bd;
+  fin.coef = 1.0;
+  fin.accumulate = 1;
+  fin.dots_only = 1;
+  KPM_HIP(launch_adjoint(D, fin, ld, st));
+  BondReduceArgs br{};
+  br.probs = D.probs;
+  br.units = D.units;
+  br.prob_unit0 = D.prob_unit0;
+  br.part_bd = bd;
+  br.dJ = d_dJ;
+  br.n_probs = n;
+  int total_bonds = 0;
+  for (int i = 0; i < n; ++i) total_bonds += p[i].n_bonds;
+  KPM_HIP(launch_bond_reduce(br, total_bonds, st));
+  int h_flag = 0;
+  KPM_HIP(hipMemcpyAsync(&h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  KPM_HIP(hipStreamSynchronize(st));
+  return h_flag ? KPM_EDEVICE : KPM_OK;
+}
+
 // Thermodynamic metadata: per-problem table and problems grouped by cluster.
 int thermo_meta(const kpm_problem* p, int n, std::vector<ThermoProb>& tp,
                 std::vector<int32_t>& start, std::vector<int32_t>& list, int& n_clusters) {
@@ -1036,26 +1235,88 @@ int kpm_thermo_vjp(const double* d_mu, const double* d_ab, const kpm_problem* p,
 
 size_t chebyshev_moments_vjp_workspace_size(const kpm_problem* p, int32_t n, const kpm_params* q,
                                             int32_t ckpt_every) {
-  (void)p; (void)n; (void)q; (void)ckpt_every;
-  return 0;
+  if (check_problems(p, n) != KPM_OK || !q || check_params(*q) != KPM_OK || ckpt_every < 2)
+    return 0;
+  return vjp_workspace(p, n, *q, ckpt_every);
 }
 
 int chebyshev_moments_vjp(const kpm_problem* p, int32_t n, const kpm_params* q,
                           const double* d_ab, const double* d_dmu, int32_t ckpt_every,
                           double* d_dJ, void* d_work, size_t work_bytes, void* stream) {
-  (void)p; (void)n; (void)q; (void)d_ab; (void)d_dmu; (void)ckpt_every; (void)d_dJ;
-  (void)d_work; (void)work_bytes; (void)stream;
-  return KPM_EINVAL;
+  int r = check_problems(p, n);
+  if (r != KPM_OK) return r;
+  if (!q || check_params(*q) != KPM_OK || !d_ab || !d_dmu || !d_dJ || ckpt_every < 2)
+    return KPM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StreamSync guard{st};
+  const size_t need = vjp_workspace(p, n, *q, ckpt_every);
+  if (need == 0) return KPM_EINVAL;
+  DevBuf own;
+  unsigned char* work = static_cast<unsigned char*>(d_work);
+  if (!work) {
+    r = own.alloc(need);
+    if (r != KPM_OK) return r;
+    work = static_cast<unsigned char*>(own.p);
+  } else if (work_bytes < need) {
+    return KPM_EWORKSPACE;
+  }
+  std::vector<double> h_ab(2 * n);
+  KPM_HIP(hipMemcpyAsync(h_ab.data(), d_ab, h_ab.size() * 8, hipMemcpyDeviceToHost, st));
+  KPM_HIP(hipStreamSynchronize(st));
+  return run_vjp(p, n, *q, h_ab.data(), d_dmu, ckpt_every, d_dJ, work, st);
 }
 
 int kpm_thermo_grad(const kpm_problem* p, int32_t n, const kpm_params* q, int32_t kernel,
                     int32_t n_nodes, const double* d_T, int32_t n_T, const double* d_wC,
                     const double* d_wchi, int32_t ckpt_every, double* d_L, double* d_dJ,
                     double* d_ab, void* d_work, size_t work_bytes, void* stream) {
-  (void)p; (void)n; (void)q; (void)kernel; (void)n_nodes; (void)d_T; (void)n_T; (void)d_wC;
-  (void)d_wchi; (void)ckpt_every; (void)d_L; (void)d_dJ; (void)d_ab; (void)d_work;
-  (void)work_bytes; (void)stream;
-  return KPM_EINVAL;
+  int r = check_problems(p, n);
+  if (r != KPM_OK) return r;
+  if (!q || check_params(*q) != KPM_OK || !d_T || n_T < 1 || !d_wC || !d_wchi || !d_L || !d_dJ ||
+      ckpt_every < 2 || (kernel != 0 && kernel != 1) || n_nodes < 0)
+    return KPM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StreamSync guard{st};
+  std::vector<ThermoProb> tp;
+  std::vector<int32_t> start, list;
+  int nc = 0;
+  if (thermo_meta(p, n, tp, start, list, nc) != KPM_OK) return KPM_EINVAL;
+  const size_t need_m = moments_workspace(p, n, *q);
+  const size_t need_v = vjp_workspace(p, n, *q, ckpt_every);
+  if (!need_m || !need_v) return KPM_EINVAL;
+  const size_t need = std::max(need_m, need_v);
+  DevBuf own;
+  unsigned char* work = static_cast<unsigned char*>(d_work);
+  if (!work) {
+    r = own.alloc(need);
+    if (r != KPM_OK) return r;
+    work = static_cast<unsigned char*>(own.p);
+  } else if (work_bytes < need) {
+    return KPM_EWORKSPACE;
+  }
+  const size_t m = (size_t)nc * n_T;
+  DevBuf tmp;
+  r = tmp.alloc(align_up((size_t)n * q->M * 8) * 2 + align_up((size_t)n * 16) + 4 * align_up(m * 8));
+  if (r != KPM_OK) return r;
+  unsigned char* t8 = static_cast<unsigned char*>(tmp.p);
+  double* mu = reinterpret_cast<double*>(t8);
+  double* lam = reinterpret_cast<double*>(t8 + align_up((size_t)n * q->M * 8));
+  double* ab = reinterpret_cast<double*>(t8 + 2 * align_up((size_t)n * q->M * 8));
+  double* outs = reinterpret_cast<double*>(t8 + 2 * align_up((size_t)n * q->M * 8) + align_up((size_t)n * 16));
+  const size_t ms = align_up(m * 8) / 8;
+  r = chebyshev_moments(p, n, q, mu, ab, work, need, stream);
+  if (r != KPM_OK) return r;
+  r = kpm_thermo_vjp(mu, ab, p, n, q->M, kernel, n_nodes, d_T, n_T, d_wC, d_wchi, lam, stream);
+  if (r != KPM_OK) return r;
+  r = kpm_thermo(mu, ab, p, n, q->M, kernel, n_nodes, d_T, n_T, outs, outs + ms, outs + 2 * ms,
+                 outs + 3 * ms, nullptr, stream);
+  if (r != KPM_OK) return r;
+  KPM_HIP(launch_loss(outs + 2 * ms, outs + 3 * ms, d_wC, d_wchi, (int)m, d_L, st));
+  if (d_ab) KPM_HIP(hipMemcpyAsync(d_ab, ab, (size_t)n * 16, hipMemcpyDeviceToDevice, st));
+  std::vector<double> h_ab(2 * n);
+  KPM_HIP(hipMemcpyAsync(h_ab.data(), ab, h_ab.size() * 8, hipMemcpyDeviceToHost, st));
+  KPM_HIP(hipStreamSynchronize(st));
+  return run_vjp(p, n, *q, h_ab.data(), lam, ckpt_every, d_dJ, work, st);
 }
 
 }  // extern "C"

@@ -1,0 +1,57 @@
+// Device helpers shared by the gfx950 kernels: basis unranking and ranking in
+// the combinatorial number system of an S^z sector.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kpm_internal.h"
+
+namespace kpm {
+
+// Word of rank r among N-bit words with k set bits (combinatorial number
+// system, colex order = ascending integer order): greedily take the highest
+// position p with C(p, j) <= remaining rank, for j = k .. 1.
+__device__ __forceinline__ uint32_t unrank(uint32_t r, int N, int k, const uint32_t* binom) {
+  uint32_t s = 0;
+  int j = k;
+  for (int p = N - 1; p >= 0 && j > 0; --p) {
+    const uint32_t cv = binom[p * kBinomN + j];
+    if (cv <= r) {
+      s |= 1u << p;
+      r -= cv;
+      --j;
+    }
+  }
+  return s;
+}
+
+// Rank of word s: the bits split as x0 (B0 low bits), x1 (next B1), x2 (rest);
+// rank = T0[x0] + T1[x1][popcount(x0)] + T2[x2] (T2 already knows the sector's
+// popcount, so the number of set bits below x2 is implied).
+struct RankTables {
+  const uint32_t* T0;
+  const uint32_t* T1;
+  const uint32_t* T2;
+  uint32_t m0, m1;
+  int B0, sh2;
+  __device__ __forceinline__ uint32_t rank(uint32_t s) const {
+    const uint32_t x0 = s & m0;
+    const uint32_t x1 = (s >> B0) & m1;
+    const uint32_t x2 = s >> sh2;
+    return T0[x0] + T1[x1 * (uint32_t)(B0 + 1) + __popc(x0)] + T2[x2];
+  }
+};
+
+__device__ __forceinline__ RankTables make_tables(const uint32_t* tab, const ProbDev& P) {
+  RankTables R;
+  R.T0 = tab;
+  R.T1 = tab + (1u << P.B0);
+  R.T2 = R.T1 + (1u << P.B1) * (uint32_t)(P.B0 + 1);
+  R.m0 = (1u << P.B0) - 1u;
+  R.m1 = (1u << P.B1) - 1u;
+  R.B0 = P.B0;
+  R.sh2 = P.B0 + P.B1;
+  return R;
+}
+
+}  // namespace kpm

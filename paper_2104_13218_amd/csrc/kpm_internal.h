@@ -25,9 +25,12 @@ struct ProbDev {
 };
 
 // One recursion block: a problem and a contiguous range of its real columns.
+// Vector storage is slot-major: slot k of this block is [dim][ld] at
+// base + k * slot_stride + vec_off (slot_stride is the same for all blocks).
 struct UnitDev {
-  int64_t vec_off;    // element offset of buffer A; buffer B follows at + dim * ld
+  int64_t vec_off;    // element offset of this block inside every slot
   int64_t part_off;   // offset of this unit's partial dots: [2 * ld][ntiles]
+  int64_t bd_off;     // offset of this unit's bond-dot partials: [ntiles][n_bonds]
   int32_t prob, ld, ncols, col0;              // columns [col0, col0 + ncols) of the problem
   int32_t tile0, ntiles, col_off, pad;        // first tile; column offset in dot rows
 };
@@ -44,6 +47,7 @@ struct StepArgs {
   const double* bzz;           // per bond: J_b / (4a)   (diagonal contribution)
   const uint32_t* binom;       // C(n, j) [33][33]
   void* vec;                   // vector storage base (float or double)
+  int64_t slot_stride;         // elements between consecutive slots
   double* part_out;            // partial dots written by this step
   const double* part_in;       // partial dots of the previous step (reduced here)
   double* alpha;               // [steps + 1][total_cols]: <v_n, v_n>
@@ -52,7 +56,9 @@ struct StepArgs {
   int32_t step_add;            // step index s = *step_base + step_add
   int32_t n_tiles;             // real tiles
   int32_t grid_tiles;          // launched tiles (multiple of 8)
-  int32_t x_parity;            // 0: x = A, y = B; 1: x = B, y = A
+  int32_t x_slot;              // slot of x = v_n (slot k of a block: + k * dim * ld)
+  int32_t yin_slot;            // slot of v_{n-1} (read)
+  int32_t yout_slot;           // slot receiving v_{n+1} (may equal yin_slot)
   int32_t first;               // 1: y = H' x; 0: y = 2 H' x - y
   int32_t n_jobs;              // reduction jobs of the previous step (0 = none)
   int32_t total_cols;          // row length of alpha / beta
@@ -84,7 +90,9 @@ struct DevicePlan {
   int32_t fp32 = 0;
   int32_t xcd_remap = 1;
   int64_t part_len = 0;        // doubles per partial buffer
-  int64_t vec_elems = 0;       // elements of vector storage (A and B of all units)
+  int64_t slot_stride = 0;     // elements of one slot (all blocks)
+  int64_t vec_elems = 0;       // elements of the two-slot storage of the recursion
+  int64_t bd_len = 0;          // doubles of bond-dot partials (adjoint)
 };
 
 struct ReduceArgs {
@@ -100,7 +108,7 @@ struct InitArgs {
   const ProbDev* probs;
   const UnitDev* units;
   const int32_t* tile_unit;
-  void* vec;
+  void* vec;                 // slot 0 is written
   const double* norms;   // per column: Gaussian sums of squares (mode 1)
   double* part_out;
   uint64_t seed;
@@ -142,8 +150,9 @@ struct LzArgs {
   const double* coef;      // per unit (column offset); squared if coef_sqrt
   const double* dotvec;    // NULL => dot with the updated w itself
   double* part_out;
+  int64_t slot_stride;
   int32_t n_tiles, grid_tiles, tile_rows, coef_sqrt;
-  int32_t w_hi, q_hi, d_hi;  // select the second buffer (+ dim) of a block's pair
+  int32_t w_hi, q_hi, d_hi;  // select slot 1 instead of slot 0
 };
 
 // Per-problem metadata of the thermodynamic sums.
@@ -181,11 +190,64 @@ struct ThermoVjpArgs {
   int32_t n_probs, M, n_nodes, n_T;
 };
 
+struct DoublingVjpArgs {
+  const ProbDev* probs;
+  const UnitDev* units;
+  const int32_t* job_unit;
+  const double* lambda;      // [n_probs][M] = dL/dmu
+  const double* alpha0;      // [total_cols] = <v_0, v_0> per column
+  double* abar;              // [K + 1][total_cols]
+  double* bbar;              // [K + 1][total_cols] (row K stays zero)
+  int32_t total_cols, M, K, cols_per_vec, R;   // R = 0: complete basis
+};
+
+struct AdjArgs {
+  const ProbDev* probs;
+  const UnitDev* units;
+  const int32_t* tile_unit;
+  const uint32_t* tables;
+  const uint32_t* bmask;
+  const double* boff;
+  const double* bzz;
+  const uint32_t* binom;
+  const void* vseg;          // slots of v (slot-major)
+  void* wbuf;                // two slots of w
+  int64_t slot_stride;
+  int32_t vm1_slot, v0_slot, vp1_slot;   // v_{n-1}, v_n, v_{n+1} (-1: absent)
+  int32_t wx_slot, wy_slot;              // w_{n+1} (gathered); w_{n+2} in, w_n out
+  const double* abar_n;      // [total_cols] row n
+  const double* bbar_n;      // row n
+  const double* bbar_nm1;    // row n-1
+  double* part_bd;           // per-tile bond dots, accumulated across launches
+  double coef;               // weight of this launch's bond dots
+  int32_t accumulate, dots_only;
+  int32_t n_tiles, grid_tiles, sub_rows, sub_per_tile, lds_tab, lds_bonds, xcd_remap;
+  int* err;
+};
+
+struct BondReduceArgs {
+  const ProbDev* probs;
+  const UnitDev* units;
+  const int32_t* prob_unit0;
+  const double* part_bd;
+  double* dJ;
+  int32_t n_probs;
+};
+
 size_t step_lds_bytes(const DevicePlan& p);
+size_t adjoint_lds_bytes(const DevicePlan& p);
+hipError_t launch_doubling_vjp(const DoublingVjpArgs& a, hipStream_t st);
+hipError_t launch_adjoint(const DevicePlan& p, AdjArgs a, int ld, hipStream_t st);
+hipError_t launch_bond_reduce(const BondReduceArgs& a, int total_bonds, hipStream_t st);
+hipError_t launch_loss(const double* C, const double* chi, const double* wC, const double* wchi,
+                       int n, double* L, hipStream_t st);
 
 hipError_t launch_step(const DevicePlan& p, void* vec, double* part_out, const double* part_in,
                        int n_jobs, double* alpha, double* beta, const int64_t* step_base,
                        int step_add, int x_parity, int first, hipStream_t st);
+// Same step with explicit buffer slots (x, v_{n-1} in, v_{n+1} out).
+hipError_t launch_step_slots(const DevicePlan& p, void* vec, double* part_out, int x_slot,
+                             int yin_slot, int yout_slot, int first, hipStream_t st);
 hipError_t launch_reduce(const DevicePlan& p, const double* part, double* dst_a, double* dst_b,
                          hipStream_t st);
 hipError_t launch_init(const DevicePlan& p, void* vec, int mode, int vec_kind, uint64_t seed,

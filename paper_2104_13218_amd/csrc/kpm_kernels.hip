@@ -20,6 +20,7 @@
 
 #include <cmath>
 
+#include "kpm_device.h"
 #include "kpm_internal.h"
 
 namespace kpm {
@@ -117,52 +118,6 @@ __device__ __forceinline__ double sum_partials(const double* p, int n, double* s
   double acc = 0.0;
   for (int t = threadIdx.x; t < n; t += kThreads) acc += p[t];
   return block_sum(acc, sh);
-}
-
-// Word of rank r among N-bit words with k set bits (combinatorial number
-// system, colex order = ascending integer order): greedily take the highest
-// position p with C(p, j) <= remaining rank, for j = k .. 1.
-__device__ __forceinline__ uint32_t unrank(uint32_t r, int N, int k, const uint32_t* binom) {
-  uint32_t s = 0;
-  int j = k;
-  for (int p = N - 1; p >= 0 && j > 0; --p) {
-    const uint32_t cv = binom[p * kBinomN + j];
-    if (cv <= r) {
-      s |= 1u << p;
-      r -= cv;
-      --j;
-    }
-  }
-  return s;
-}
-
-// Rank of word s: the bits split as x0 (B0 low bits), x1 (next B1), x2 (rest);
-// rank = T0[x0] + T1[x1][popcount(x0)] + T2[x2] (T2 already knows the sector's
-// popcount, so the number of set bits below x2 is implied).
-struct RankTables {
-  const uint32_t* T0;
-  const uint32_t* T1;
-  const uint32_t* T2;
-  uint32_t m0, m1;
-  int B0, sh2;
-  __device__ __forceinline__ uint32_t rank(uint32_t s) const {
-    const uint32_t x0 = s & m0;
-    const uint32_t x1 = (s >> B0) & m1;
-    const uint32_t x2 = s >> sh2;
-    return T0[x0] + T1[x1 * (uint32_t)(B0 + 1) + __popc(x0)] + T2[x2];
-  }
-};
-
-__device__ __forceinline__ RankTables make_tables(const uint32_t* tab, const ProbDev& P) {
-  RankTables R;
-  R.T0 = tab;
-  R.T1 = tab + (1u << P.B0);
-  R.T2 = R.T1 + (1u << P.B1) * (uint32_t)(P.B0 + 1);
-  R.m0 = (1u << P.B0) - 1u;
-  R.m1 = (1u << P.B1) - 1u;
-  R.B0 = P.B0;
-  R.sh2 = P.B0 + P.B1;
-  return R;
 }
 
 // LDS carve-up shared by the step kernel and the matrix export.
@@ -279,8 +234,9 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
   const int c = tid % nch;
   const int rg = tid / nch;
   T* base = reinterpret_cast<T*>(a.vec) + U.vec_off;
-  const T* X = a.x_parity ? base + P.dim * ld : base;
-  T* Y = a.x_parity ? base : base + P.dim * ld;
+  const T* X = base + a.x_slot * a.slot_stride;
+  const T* Yin = base + a.yin_slot * a.slot_stride;
+  T* Y = base + a.yout_slot * a.slot_stride;
 
   double acc_a[CPL], acc_b[CPL];
 #pragma unroll
@@ -305,7 +261,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
         const int cnt = S.cnt[r];
         T* ys = Y + rho * ld + c * CPL;
         VecT<T, CPL> yv;
-        if (!a.first) yv = vload_nt<T, CPL>(ys);
+        if (!a.first) yv = vload_nt<T, CPL>(Yin + rho * ld + c * CPL);
         // gathers issued kGatherBatch at a time (absent entries read the row
         // itself with a zero coefficient), then accumulated in order
         for (int k0 = 0; k0 < cnt; k0 += kGatherBatch) {
@@ -410,6 +366,7 @@ static StepArgs make_step_args(const DevicePlan& p) {
   a.lds_tab = p.lds_tab;
   a.lds_bonds = p.lds_bonds;
   a.xcd_remap = p.xcd_remap;
+  a.slot_stride = p.slot_stride;
   return a;
 }
 
@@ -418,6 +375,8 @@ static hipError_t launch_step_t(const StepArgs& a, size_t lds, int grid, hipStre
   hipLaunchKernelGGL((step_kernel<T, CPL>), dim3(grid), dim3(kThreads), lds, st, a);
   return hipGetLastError();
 }
+
+hipError_t launch_step_args(const DevicePlan& p, const StepArgs& a, hipStream_t st);
 
 hipError_t launch_step(const DevicePlan& p, void* vec, double* part_out, const double* part_in,
                        int n_jobs, double* alpha, double* beta, const int64_t* step_base,
@@ -432,8 +391,26 @@ hipError_t launch_step(const DevicePlan& p, void* vec, double* part_out, const d
   a.beta = beta;
   a.step_base = step_base;
   a.step_add = step_add;
-  a.x_parity = x_parity;
+  a.x_slot = x_parity;
+  a.yin_slot = a.yout_slot = 1 - x_parity;
   a.first = first;
+  return launch_step_args(p, a, st);
+}
+
+hipError_t launch_step_slots(const DevicePlan& p, void* vec, double* part_out, int x_slot,
+                             int yin_slot, int yout_slot, int first, hipStream_t st) {
+  StepArgs a = make_step_args(p);
+  a.err = p.err;
+  a.vec = vec;
+  a.part_out = part_out;
+  a.x_slot = x_slot;
+  a.yin_slot = yin_slot;
+  a.yout_slot = yout_slot;
+  a.first = first;
+  return launch_step_args(p, a, st);
+}
+
+hipError_t launch_step_args(const DevicePlan& p, const StepArgs& a, hipStream_t st) {
   const size_t lds = step_lds_bytes(p);
   const int grid = p.grid_tiles;
   if (p.fp32) {
@@ -681,8 +658,8 @@ __global__ __launch_bounds__(kThreads) void matrix_kernel(const MatrixArgs a) {
 // Blocks have one float64 column; each block's buffers sit at
 // base + vec_off (+ dim for the "high" buffer of a pair).
 
-__device__ __forceinline__ double* lz_sel(double* base, int hi, const UnitDev& U, const ProbDev& P) {
-  return base + U.vec_off + (hi ? P.dim : 0);
+__device__ __forceinline__ double* lz_sel(double* base, int hi, const UnitDev& U, int64_t stride) {
+  return base + U.vec_off + (hi ? stride : 0);
 }
 
 // w -= coef * q, with partials of <w, d> (d = w itself when d is NULL).
@@ -695,9 +672,9 @@ __global__ __launch_bounds__(kThreads) void lz_axpy_kernel(const LzArgs a) {
   const int64_t row0 = (int64_t)(tile - U.tile0) * a.tile_rows;
   const int64_t row1 = min(row0 + a.tile_rows, P.dim);
   const double cf = a.coef_sqrt ? sqrt(a.coef[U.col_off]) : a.coef[U.col_off];
-  double* w = lz_sel(a.w, a.w_hi, U, P);
-  const double* q = lz_sel(const_cast<double*>(a.q), a.q_hi, U, P);
-  const double* d = a.dotvec ? lz_sel(const_cast<double*>(a.dotvec), a.d_hi, U, P) : nullptr;
+  double* w = lz_sel(a.w, a.w_hi, U, a.slot_stride);
+  const double* q = lz_sel(const_cast<double*>(a.q), a.q_hi, U, a.slot_stride);
+  const double* d = a.dotvec ? lz_sel(const_cast<double*>(a.dotvec), a.d_hi, U, a.slot_stride) : nullptr;
   double acc = 0.0;
   for (int64_t i = row0 + threadIdx.x; i < row1; i += kThreads) {
     const double wv = w[i] - cf * q[i];
@@ -720,6 +697,7 @@ hipError_t launch_lz_axpy(const DevicePlan& p, const LzArgs& args, hipStream_t s
   a.n_tiles = p.n_tiles;
   a.grid_tiles = p.grid_tiles;
   a.tile_rows = p.sub_rows * p.sub_per_tile;
+  a.slot_stride = p.slot_stride;
   hipLaunchKernelGGL(lz_axpy_kernel, dim3(p.grid_tiles), dim3(kThreads), 0, st, a);
   return hipGetLastError();
 }
@@ -739,7 +717,7 @@ __global__ __launch_bounds__(kThreads) void lz_next_kernel(const LzArgs a, doubl
   const double inv = 1.0 / sqrt(b2);
   double* qp = qprev + U.vec_off;
   double* qq = q + U.vec_off;
-  const double* ww = w + U.vec_off + P.dim;
+  const double* ww = w + U.vec_off + a.slot_stride;
   for (int64_t i = row0 + threadIdx.x; i < row1; i += kThreads) {
     qp[i] = qq[i];
     qq[i] = ww[i] * inv;
@@ -755,6 +733,7 @@ hipError_t launch_lz_next(const DevicePlan& p, double* qprev, double* q, const d
   a.n_tiles = p.n_tiles;
   a.grid_tiles = p.grid_tiles;
   a.tile_rows = p.sub_rows * p.sub_per_tile;
+  a.slot_stride = p.slot_stride;
   hipLaunchKernelGGL(lz_next_kernel, dim3(p.grid_tiles), dim3(kThreads), 0, st, a, qprev, q, w,
                      beta2);
   return hipGetLastError();

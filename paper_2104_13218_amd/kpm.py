@@ -234,3 +234,94 @@ def last_run_stats() -> dict:
     s = RunStats()
     _check(load().kpm_last_run_stats(ctypes.byref(s)), "kpm_last_run_stats")
     return {f: getattr(s, f) for f, _ in RunStats._fields_}
+
+
+def moments_vjp(sectors, M, R, ab, dmu, vec_kind="rademacher", precision="fp64", eps=0.025, seed=0,
+                col_block=0, ckpt_every=64, problems=None, stream=None):
+    """dL/dJ (concatenated per problem, bond order) for dL/dmu = dmu, with the
+    rescaling ab held fixed (same seeds and vectors as chebyshev_moments)."""
+    ps = problems or ProblemSet(sectors)
+    q = make_params(M, R, vec_kind, precision, eps, seed, col_block)
+    lib = load()
+    nbytes = lib.chebyshev_moments_vjp_workspace_size(ps.arr, len(ps), ctypes.byref(q), ckpt_every)
+    if nbytes == 0:
+        raise KPMError(KPM_EINVAL, "chebyshev_moments_vjp_workspace_size")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    nb = sum(s.cluster.n_bonds for s in ps.sectors)
+    dJ = torch.empty(max(nb, 1), dtype=torch.float64, device="cuda")
+    ab = ab.contiguous()
+    dmu = dmu.to(device="cuda", dtype=torch.float64).contiguous()
+    _check(lib.chebyshev_moments_vjp(ps.arr, len(ps), ctypes.byref(q), _ptr(ab), _ptr(dmu), ckpt_every,
+                                     _ptr(dJ), _ptr(ws), nbytes, _stream(stream)), "chebyshev_moments_vjp")
+    return dJ[:nb]
+
+
+def thermo_grad(sectors, M, R, T, wC, wchi, vec_kind="rademacher", precision="fp64", eps=0.025, seed=0,
+                col_block=0, kernel="none", n_nodes=0, ckpt_every=64, bounds=None, problems=None,
+                stream=None):
+    """L = sum wC C + wchi chi and dL/dJ (per problem, bond order), bounds fixed."""
+    ps = problems or ProblemSet(sectors, bounds)
+    q = make_params(M, R, vec_kind, precision, eps, seed, col_block)
+    T = torch.as_tensor(T, dtype=torch.float64, device="cuda").contiguous()
+    wC = torch.as_tensor(wC, dtype=torch.float64, device="cuda").contiguous()
+    wchi = torch.as_tensor(wchi, dtype=torch.float64, device="cuda").contiguous()
+    nb = sum(s.cluster.n_bonds for s in ps.sectors)
+    L = torch.empty(1, dtype=torch.float64, device="cuda")
+    dJ = torch.empty(max(nb, 1), dtype=torch.float64, device="cuda")
+    ab = torch.empty((len(ps), 2), dtype=torch.float64, device="cuda")
+    _check(load().kpm_thermo_grad(ps.arr, len(ps), ctypes.byref(q), KERNELS[kernel], n_nodes, _ptr(T),
+                                  T.numel(), _ptr(wC), _ptr(wchi), ckpt_every, _ptr(L), _ptr(dJ), _ptr(ab),
+                                  None, 0, _stream(stream)), "kpm_thermo_grad")
+    return L[0], dJ[:nb], ab
+
+
+class KPMMoments(torch.autograd.Function):
+    """mu, ab = KPMMoments.apply(J, cluster, n_ups, M, R, vec_kind, precision, eps, seed, col_block,
+    bounds, ckpt_every): Chebyshev moments of the sectors n_ups of one cluster whose
+    couplings are J (float64 tensor [n_bonds]); backward gives dL/dJ through the
+    recursion adjoint with the rescaling held at the forward's values."""
+
+    @staticmethod
+    def forward(ctx, J, cluster, n_ups, M, R, vec_kind="rademacher", precision="fp64", eps=0.025, seed=0,
+                col_block=0, bounds=None, ckpt_every=64):
+        import workloads as W
+        cl = cluster.with_J(J.detach().to("cpu", torch.float64).numpy())
+        secs = [W.Sector(cl, k, 0) for k in n_ups]
+        ps = ProblemSet(secs, bounds)
+        mu, ab = chebyshev_moments(None, M, R, vec_kind, precision, eps, seed, col_block, problems=ps)
+        ctx.ps, ctx.ab = ps, ab
+        ctx.args = (M, R, vec_kind, precision, eps, seed, col_block, ckpt_every)
+        ctx.n_bonds, ctx.J_device = cl.n_bonds, J.device
+        ctx.mark_non_differentiable(ab)
+        return mu, ab
+
+    @staticmethod
+    def backward(ctx, dmu, dab):
+        M, R, vec_kind, precision, eps, seed, col_block, ckpt_every = ctx.args
+        dJ = moments_vjp(None, M, R, ctx.ab, dmu, vec_kind, precision, eps, seed, col_block, ckpt_every,
+                         problems=ctx.ps)
+        dJ = dJ.view(len(ctx.ps), ctx.n_bonds).sum(0).to(ctx.J_device)
+        return (dJ,) + (None,) * 11
+
+
+class KPMThermo(torch.autograd.Function):
+    """C, chi = KPMThermo.apply(mu, ab, problems, T, kernel, n_nodes) for one
+    or more clusters ([n_clusters, n_T]); backward gives dL/dmu."""
+
+    @staticmethod
+    def forward(ctx, mu, ab, problems, T, kernel="none", n_nodes=0):
+        out = thermo(mu, ab, problems, T, kernel, n_nodes)
+        ctx.save_for_backward(mu, ab)
+        ctx.problems, ctx.T, ctx.kernel, ctx.n_nodes = problems, T, kernel, n_nodes
+        return out["C"], out["chi"]
+
+    @staticmethod
+    def backward(ctx, dC, dchi):
+        mu, ab = ctx.saved_tensors
+        ps = ctx.problems if isinstance(ctx.problems, ProblemSet) else ProblemSet(ctx.problems)
+        shape = (ps.n_clusters, torch.as_tensor(ctx.T).numel())
+        zero = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        wC = zero if dC is None else dC.contiguous()
+        wchi = zero if dchi is None else dchi.contiguous()
+        lam = thermo_vjp(mu, ab, ps, ctx.T, wC, wchi, ctx.kernel, ctx.n_nodes)
+        return lam, None, None, None, None, None

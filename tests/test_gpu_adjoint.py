@@ -1,0 +1,161 @@
+"""GPU adjoint (dL/dJ_b with the rescaling fixed) against the oracle's reverse
+mode, against central finite differences, and, with exact traces, against the
+Hellmann-Feynman form of the moments' derivative."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import adjoint, hamiltonian, moments
+
+pytestmark = pytest.mark.gpu
+
+
+def _bounds(secs, pad=0.05):
+    out = []
+    for s in secs:
+        e = np.linalg.eigvalsh(hamiltonian.sector_hamiltonian(s.cluster, s.n_up).toarray())
+        lo, hi = e.min() - pad, e.max() + pad
+        out.append((lo, hi))
+    return out
+
+
+def _ab(bounds, eps):
+    return np.array([hamiltonian.scale_from_bounds(lo, hi, eps) for lo, hi in bounds])
+
+
+@pytest.mark.parametrize("kind,R,precision,col_block,ckpt", [
+    ("rademacher", 3, "fp64", 0, 4), ("complex_gaussian", 2, "fp64", 2, 2),
+    ("gaussian", 5, "fp64", 3, 64), ("rademacher", 6, "fp32", 4, 8)])
+def test_moments_vjp_matches_oracle(kpm, kind, R, precision, col_block, ckpt):
+    cl = W.j1j2_chain(10, 1.0, 0.5)
+    secs = W.sectors(cl)[:3]
+    bl = _bounds(secs)
+    M = 41
+    mu, ab = kpm.chebyshev_moments(secs, M, R, kind, precision, 0.025, 7, col_block, bounds=bl)
+    lam = np.random.default_rng(3).normal(size=(len(secs), M))
+    dJ = kpm.moments_vjp(secs, M, R, ab, torch.tensor(lam, device="cuda"), kind, precision, 0.025, 7,
+                         col_block, ckpt_every=ckpt).cpu().numpy().reshape(len(secs), -1)
+    abh = ab.cpu().numpy()
+    store = np.float32 if precision == "fp32" else np.float64
+    for p, s in enumerate(secs):
+        want = adjoint.sector_moments_vjp(s, abh[p, 0], abh[p, 1], M, R, kind, 7, lam[p], store=store)
+        tol = 1e-9 if precision == "fp64" else 1e-4
+        assert np.abs(dJ[p] - want).max() <= tol * np.abs(want).max(), p
+
+
+def test_checkpoint_interval_does_not_change_result(kpm):
+    secs = W.sectors(W.ring(12))[:2]
+    bl = _bounds(secs)
+    M = 90
+    mu, ab = kpm.chebyshev_moments(secs, M, 4, bounds=bl)
+    lam = torch.tensor(np.random.default_rng(1).normal(size=(2, M)), device="cuda")
+    ref = kpm.moments_vjp(secs, M, 4, ab, lam, ckpt_every=1000).cpu().numpy()
+    for c in (2, 6, 44):
+        got = kpm.moments_vjp(secs, M, 4, ab, lam, ckpt_every=c).cpu().numpy()
+        assert np.array_equal(got, ref), c
+
+
+def test_thermo_grad_matches_oracle_and_finite_differences(kpm):
+    cl = W.j1j2_chain(8, 1.0, 0.5)
+    secs = W.sectors(cl, only_sz0=True) + [W.Sector(cl, 5, 0)]
+    bl = _bounds(secs)
+    ab = _ab(bl, 0.025)
+    T = np.array([0.2, 0.6, 1.5])
+    wC = np.ones((1, 3))
+    wX = np.array([[0.3, -0.2, 0.5]])
+    L, dJ, abd = kpm.thermo_grad(secs, 40, 3, T, wC, wX, "rademacher", "fp64", 0.025, 0, kernel="none",
+                                 n_nodes=40, ckpt_every=4, bounds=bl)
+    g = dJ.cpu().numpy().reshape(len(secs), -1).sum(0)
+    want = adjoint.pipeline_grad(secs, ab, 40, 3, "rademacher", 0, T, wC, wX, "none", 40)
+    assert np.linalg.norm(g - want) <= 1e-9 * np.linalg.norm(want)
+    Lw = adjoint.pipeline_loss(secs, ab, 40, 3, "rademacher", 0, T, wC, wX, "none", 40)
+    assert abs(L.item() - Lw) <= 1e-10 * abs(Lw)
+    fd = adjoint.pipeline_grad_fd(secs, ab, 40, 3, "rademacher", 0, T, wC, wX, "none", 40)
+    assert np.linalg.norm(g - fd) <= 1e-5 * np.linalg.norm(g)
+
+
+def test_gradient_vs_gpu_finite_differences_jackson(kpm):
+    cl = W.random_regular_cluster(10, 3, 4, J_range=(0.5, 1.5))
+    secs = W.sectors(cl)
+    bl = _bounds(secs, 0.1)
+    T = W.log_temperatures(8, 0.1, 4.0)
+    wC = np.ones((1, 8))
+    wX = np.linspace(-1, 1, 8)[None, :]
+    L, dJ, _ = kpm.thermo_grad(secs, 64, 4, T, wC, wX, "complex_gaussian", "fp64", 0.05, 2, kernel="jackson",
+                               ckpt_every=8, bounds=bl)
+    g = dJ.cpu().numpy().reshape(len(secs), -1).sum(0)
+    h = 1e-5
+    for b in (0, 4, 11):
+        vals = []
+        for sgn in (1, -1):
+            J = cl.J.copy()
+            J[b] += sgn * h
+            s2 = [W.Sector(cl.with_J(J), s.n_up, 0) for s in secs]
+            Lh, _, _ = kpm.thermo_grad(s2, 64, 4, T, wC, wX, "complex_gaussian", "fp64", 0.05, 2,
+                                       kernel="jackson", ckpt_every=8, bounds=bl)
+            vals.append(Lh.item())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(g[b] - fd) <= 1e-5 * np.abs(g).max(), (b, g[b], fd)
+
+
+def test_complete_basis_adjoint_is_hellmann_feynman_n12(kpm):
+    cl = W.j1j2_chain(12, 1.0, 0.5)
+    s = W.Sector(cl, 7, 0)
+    bl = _bounds([s])
+    M = 100
+    mu, ab = kpm.chebyshev_moments([s], M, 0, "basis", "fp64", 0.025, bounds=bl)
+    a, b = ab.cpu().numpy()[0]
+    hf = adjoint.kpm_hellmann_feynman(s, a, b, M)            # [n_bonds, M]
+    lam = np.random.default_rng(5).normal(size=M) / np.arange(1, M + 1)
+    dJ = kpm.moments_vjp([s], M, 0, ab, torch.tensor(lam[None, :], device="cuda"), "basis", "fp64",
+                         ckpt_every=16).cpu().numpy()
+    want = hf @ lam
+    assert np.abs(dJ - want).max() <= 1e-9 * np.abs(want).max()
+
+
+def test_autograd_functions_compose(kpm):
+    cl = W.j1j2_chain(8, 1.0, 0.5)
+    n_ups = [4, 5, 6]
+    secs = [W.Sector(cl, k, 0) for k in n_ups]
+    bl = _bounds(secs)
+    T = torch.tensor([0.3, 1.0, 2.0], dtype=torch.float64)
+    J = torch.tensor(cl.J, dtype=torch.float64, requires_grad=True)
+    mu, ab = kpm.KPMMoments.apply(J, cl, n_ups, 40, 3, "rademacher", "fp64", 0.025, 0, 0, bl, 8)
+    C, chi = kpm.KPMThermo.apply(mu, ab, secs, T, "none", 0)
+    L = C.sum() + 0.5 * chi.sum()
+    L.backward()
+    _, dJ, _ = kpm.thermo_grad(secs, 40, 3, T, np.ones((1, 3)), 0.5 * np.ones((1, 3)), bounds=bl,
+                               ckpt_every=8)
+    want = dJ.cpu().numpy().reshape(3, -1).sum(0)
+    np.testing.assert_allclose(J.grad.numpy(), want, rtol=1e-10, atol=1e-12 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("t_lo,h", [(0.1, 1e-5), (0.05, 1e-4)])
+def test_j1j2_n20_full_size_vs_finite_differences(kpm, t_lo, h):
+    """J1-J2 chain N=20 (40 bonds), S^z=0 (dim 184,756), M=1000, R=16 Rademacher,
+    loss sum_T C(T) over 64 log-spaced T in [t_lo, 5], checkpoints every 64
+    steps; three bonds against central differences.  On T in [0.05, 5] the
+    difference quotient at h = 1e-5 is limited by roundoff (C at T = 0.05
+    amplifies the moments' rounding by ~1e5; measured spread 2e-4), so that band
+    is checked at the step minimising the quotient's error (h = 1e-4)."""
+    wl = W.j1j2_grad_workload()
+    secs = wl.problems
+    cl = secs[0].cluster
+    bl = [tuple(x) for x in kpm.spectral_bounds(secs)]
+    T = W.log_temperatures(64, t_lo, 5.0)
+    wC = np.ones((1, T.size))
+    wX = np.zeros((1, T.size))
+    L, dJ, _ = kpm.thermo_grad(secs, wl.M, wl.R, T, wC, wX, kernel="none", ckpt_every=64, bounds=bl)
+    g = dJ.cpu().numpy()
+    assert g.shape == (40,)
+    for b in (0, 7, 33):
+        vals = []
+        for sgn in (1, -1):
+            J = cl.J.copy()
+            J[b] += sgn * h
+            Lh, _, _ = kpm.thermo_grad([W.Sector(cl.with_J(J), secs[0].n_up, 0)], wl.M, wl.R, T, wC, wX,
+                                       kernel="none", ckpt_every=64, bounds=bl)
+            vals.append(Lh.item())
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(g[b] - fd) <= 1e-5 * abs(g[b]), (b, g[b], fd)
