@@ -51,6 +51,8 @@ def _parse():
                     help="only the timed workload (for profiler runs)")
     ap.add_argument("--cpu-steps", type=int, default=6,
                     help="recursion steps of the CPU-oracle sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device-to-device (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -88,6 +90,12 @@ def main():
     kpm.load()
     torch.cuda.init()
     dev = torch.cuda.get_device_name(0)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ring = W.ring(24)
     sec = W.sectors(ring, only_sz0=True)
