@@ -149,6 +149,7 @@ struct RunShape {
   int R = 1;
   int col_block = 0;
   bool adjoint = false;   // block widths padded to the adjoint kernel's (1..16, power of 2)
+  bool allow_row = true;  // the row kernel may run the recursion
 };
 
 constexpr int kAdjMaxLd = 16;
@@ -209,10 +210,18 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   if (const int f = env_int("KPM_CPL", 0)) cpl = f;
   if (adj_ld) cpl = std::min(cpl, adj_ld);
   const int elt = fp32 ? 4 : 8;
+  // One lane per state (row kernel) when the block width has an instantiation.
+  int row_ld = 0;
+  if (!s.adjoint && s.allow_row && env_int("KPM_ROW_KERNEL", 1))
+    for (int L : {1, 2, 4, 8})
+      if (L >= rb) {
+        row_ld = L;
+        break;
+      }
 
   P.binom = binom_table();
   int max_bonds = 1, max_tab = 1;
-  int64_t max_dim = 1;
+  int64_t max_dim = 1, n_states = 0;
   size_t bond_total = 0;
   for (int i = 0; i < n; ++i) {
     ProbDev d{};
@@ -232,6 +241,8 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
     const double a = a_arr ? a_arr[i] : 1.0, b = b_arr ? b_arr[i] : 0.0;
     d.shift = -b / a;
     d.inv_a = 1.0 / a;
+    d.state_off = n_states;
+    n_states += d.dim;
     for (int k = 0; k < p[i].n_bonds; ++k) {
       P.bmask.push_back((1u << p[i].bond_i[k]) | (1u << p[i].bond_j[k]));
       P.boff.push_back(p[i].J[k] / (2.0 * a));
@@ -266,11 +277,16 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
     while (adjoint_lds_bytes(D) > lds_hard && D.sub_rows > 32) D.sub_rows >>= 1;
   if (step_lds_bytes(D) > lds_hard) return KPM_EINVAL;
   if (s.adjoint && (adjoint_lds_bytes(D) > lds_hard || max_bonds > D.sub_rows)) return KPM_EINVAL;
+  D.row_ld = row_ld;
+  if (row_ld && row_lds_bytes(D) > lds_hard) D.row_ld = row_ld = 0;
+  if (row_ld) D.row_window = row_ld;
+  if (row_ld) D.sub_rows = kThreads;
+  D.n_states = n_states;
 
   // Rows per workgroup tile: enough rows to amortise the per-tile LDS fill,
   // but keep >= 2048 tiles on the largest block when its size permits.
-  const size_t fixed = kBinomN * kBinomN * 4 + (size_t)max_tab * 4 + (size_t)max_bonds * 20;
-  const int ldmax = (rb + cpl - 1) / cpl * cpl;
+  const size_t fixed = (row_ld ? 0 : kBinomN * kBinomN * 4) + (size_t)max_tab * 4 + (size_t)max_bonds * 20;
+  const int ldmax = row_ld ? row_ld : (rb + cpl - 1) / cpl * cpl;
   const double per_row = 3.0 * ldmax * elt;
   int spt = (int)std::ceil(16.0 * fixed / (per_row * D.sub_rows));
   const int64_t par = max_dim / (2048LL * D.sub_rows);
@@ -279,6 +295,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   if (const int f = env_int("KPM_SUB_PER_TILE", 0)) spt = f;
   D.sub_per_tile = spt;
   D.xcd_remap = env_int("KPM_XCD_REMAP", 1);
+  D.dense = env_int("KPM_DENSE_LISTS", 0);
   const int64_t tile_rows = (int64_t)D.sub_rows * spt;
 
   int64_t vec_elems = 0, part_len = 0, bd_len = 0;
@@ -291,7 +308,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
       UnitDev u{};
       u.prob = i;
       u.ncols = (int32_t)std::min<int64_t>(rb, nc - c0);
-      u.ld = adj_ld ? adj_ld : (u.ncols + cpl - 1) / cpl * cpl;
+      u.ld = adj_ld ? adj_ld : (row_ld ? row_ld : (u.ncols + cpl - 1) / cpl * cpl);
       u.col0 = (int32_t)c0;
       u.vec_off = vec_elems;
       vec_elems += (int64_t)align_up((size_t)(dim * u.ld), 64);
@@ -399,7 +416,7 @@ struct DevBuf {
 // ------------------------------------------------------------- Lanczos bounds
 
 struct LzLayout {
-  size_t plan, vec, vecC, part, dots, b2, zero, err, total;
+  size_t plan, vec, vecC, part, dots, b2, zero, err, states, total;
 };
 
 LzLayout lanczos_layout(const Planned& P, int steps) {
@@ -418,6 +435,7 @@ LzLayout lanczos_layout(const Planned& P, int steps) {
   L.b2 = put((size_t)steps * P.plan.total_cols * 8);
   L.zero = put((size_t)P.plan.total_cols * 8);
   L.err = put(256);
+  L.states = put((size_t)P.plan.n_states * 4);
   L.total = o;
   return L;
 }
@@ -492,7 +510,9 @@ int run_lanczos(const kpm_problem* p, int n, int steps, double margin, uint64_t 
   if (r != KPM_OK) return r;
   DevicePlan& D = P.plan;
   D.err = reinterpret_cast<int*>(work + L.err);
+  D.states = reinterpret_cast<uint32_t*>(work + L.states);
   KPM_HIP(hipMemsetAsync(D.err, 0, sizeof(int), st));
+  if (D.row_ld) KPM_HIP(fill_states(D, st));
   double* vec = reinterpret_cast<double*>(work + L.vec);
   double* vecC = reinterpret_cast<double*>(work + L.vecC);
   double* part = reinterpret_cast<double*>(work + L.part);
@@ -562,7 +582,7 @@ int run_lanczos(const kpm_problem* p, int n, int steps, double margin, uint64_t 
 // ------------------------------------------------------------ moments driver
 
 struct MomLayout {
-  size_t plan, vec, part0, part1, alpha, beta, norms, flag, base, lz, total;
+  size_t plan, vec, part0, part1, alpha, beta, norms, flag, base, states, lz, total;
 };
 
 MomLayout moments_layout(const Planned& P, int K, size_t lz_bytes) {
@@ -585,6 +605,7 @@ MomLayout moments_layout(const Planned& P, int K, size_t lz_bytes) {
   L.norms = put(TC * 8);
   L.flag = put(256);
   L.base = put(256);
+  L.states = put((size_t)P.plan.n_states * 4);
   L.total = std::max(o, align_up(L.lz + lz_bytes));
   return L;
 }
@@ -634,7 +655,9 @@ int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
   int* flag = reinterpret_cast<int*>(work + L.flag);
   int64_t* base = reinterpret_cast<int64_t*>(work + L.base);
   P.plan.err = flag;
+  P.plan.states = reinterpret_cast<uint32_t*>(work + L.states);
   KPM_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+  if (D.row_ld) KPM_HIP(fill_states(D, st));
 
   if (q.vec_kind == KPM_VEC_GAUSSIAN || q.vec_kind == KPM_VEC_COMPLEX_GAUSSIAN) {
     KPM_HIP(launch_init(D, vec, 0, q.vec_kind, q.seed, nullptr, part[0], st));
@@ -1089,6 +1112,7 @@ int kpm_sector_matrix(const kpm_problem* p, int64_t row0, int64_t nrows, int32_t
   RunShape s;
   s.precision = KPM_FP64;
   s.col_block = 1;
+  s.allow_row = false;
   Planned P;
   const double one = 1.0, zero = 0.0;
   int r = make_plan(p, 1, s, &one, &zero, P);

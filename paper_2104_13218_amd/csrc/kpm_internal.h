@@ -22,6 +22,7 @@ struct ProbDev {
   int32_t tab_len, cluster;                   // table entries; RNG cluster id
   double shift;       // -b / a   (diagonal shift of H' = (H - b)/a)
   double inv_a;       // 1 / a
+  int64_t state_off;  // offset of this sector's basis words in the state table
 };
 
 // One recursion block: a problem and a contiguous range of its real columns.
@@ -46,6 +47,7 @@ struct StepArgs {
   const double* boff;          // per bond: J_b / (2a)   (off-diagonal element of H')
   const double* bzz;           // per bond: J_b / (4a)   (diagonal contribution)
   const uint32_t* binom;       // C(n, j) [33][33]
+  const uint32_t* states;      // basis words of every sector, rank order (row kernel)
   void* vec;                   // vector storage base (float or double)
   int64_t slot_stride;         // elements between consecutive slots
   double* part_out;            // partial dots written by this step
@@ -69,6 +71,7 @@ struct StepArgs {
   int32_t lds_bonds;           // bond capacity in LDS
   int* err;                    // bit 1 set if a neighbour rank fell outside its sector
   int32_t xcd_remap;           // 1: contiguous tile ranges per XCD
+  int32_t dense;               // 1: one neighbour slot per bond (bond-major gathers)
 };
 
 // Device-side plan of one run (pointers into the workspace) + launch shape.
@@ -83,12 +86,17 @@ struct DevicePlan {
   double* boff = nullptr;
   double* bzz = nullptr;
   uint32_t* binom = nullptr;
+  uint32_t* states = nullptr;  // basis words (row kernel), filled by fill_states
   int* err = nullptr;          // device error word (see StepArgs::err)
   int32_t n_probs = 0, n_units = 0, n_tiles = 0, grid_tiles = 0, total_cols = 0;
   int32_t sub_rows = 256, sub_per_tile = 1, lds_nb = 0, lds_tab = 0, lds_bonds = 0;
   int32_t cpl = 1;
   int32_t fp32 = 0;
   int32_t xcd_remap = 1;
+  int32_t dense = 0;
+  int32_t row_ld = 0;          // > 0: one lane per state with all row_ld columns
+  int32_t row_window = 0;      // columns per register window of the row kernel
+  int64_t n_states = 0;        // entries of the state table
   int64_t part_len = 0;        // doubles per partial buffer
   int64_t slot_stride = 0;     // elements of one slot (all blocks)
   int64_t vec_elems = 0;       // elements of the two-slot storage of the recursion
@@ -256,6 +264,9 @@ hipError_t launch_finalize(const FinalArgs& a, hipStream_t st);
 hipError_t launch_set_i64(int64_t* dst, int64_t v, hipStream_t st);
 hipError_t launch_states(int N, int k, const uint32_t* binom, uint32_t* out, int64_t dim,
                          hipStream_t st);
+// Basis words of every sector of the plan into p.states.
+hipError_t fill_states(const DevicePlan& p, hipStream_t st);
+size_t row_lds_bytes(const DevicePlan& p);
 hipError_t launch_matrix(const MatrixArgs& a, size_t lds, int grid, hipStream_t st);
 hipError_t launch_lz_axpy(const DevicePlan& p, const LzArgs& args, hipStream_t st);
 hipError_t launch_lz_next(const DevicePlan& p, double* qprev, double* q, const double* w,

@@ -157,8 +157,13 @@ __device__ __forceinline__ StepSmem carve(unsigned char* smem, int lds_tab, int 
 // A neighbour rank outside the sector (impossible for consistent tables) is
 // replaced by the row itself and reported through *err, so no gather can
 // leave the vector.
+// With dense = true, entry b of the row belongs to bond b (kNoNeighbour when
+// its bits are equal), so lanes of consecutive rows gather for the same bond.
+constexpr uint32_t kNoNeighbour = 0xFFFFFFFFu;
+
 __device__ __forceinline__ void stage_row(uint32_t rank, const ProbDev& P, const RankTables& RT,
-                                          const StepSmem& S, int slot, int stride, int* err) {
+                                          const StepSmem& S, int slot, int stride, int* err,
+                                          bool dense = false) {
   const uint32_t s = unrank(rank, P.n_sites, P.n_up, S.binom);
   double d = P.shift;
   int cnt = 0;
@@ -167,6 +172,15 @@ __device__ __forceinline__ void stage_row(uint32_t rank, const ProbDev& P, const
     const uint32_t v = s & m;
     if (v == 0u || v == m) {
       d += S.zz[b];
+      if (dense) S.nbr[b * stride + slot] = kNoNeighbour;
+    } else if (dense) {
+      d -= S.zz[b];
+      uint32_t nr = RT.rank(s ^ m);
+      if (nr >= (uint32_t)P.dim) {
+        if (err) atomicOr(err, 2);
+        nr = rank;
+      }
+      S.nbr[b * stride + slot] = nr;
     } else {
       d -= S.zz[b];
       uint32_t nr = RT.rank(s ^ m);
@@ -180,7 +194,7 @@ __device__ __forceinline__ void stage_row(uint32_t rank, const ProbDev& P, const
     }
   }
   S.diag[slot] = d;
-  S.cnt[slot] = cnt;
+  S.cnt[slot] = dense ? P.n_bonds : cnt;
 }
 
 __device__ __forceinline__ void load_problem_lds(const StepSmem& S, const ProbDev& P,
@@ -248,7 +262,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
     if (row0 >= P.dim) break;
     const int nrows = (int)min((int64_t)a.sub_rows, P.dim - row0);
     for (int r = tid; r < nrows; r += kThreads)
-      stage_row((uint32_t)(row0 + r), P, RT, S, r, a.sub_rows, a.err);
+      stage_row((uint32_t)(row0 + r), P, RT, S, r, a.sub_rows, a.err, a.dense);
     __syncthreads();
     if (rg < nrg) {
       for (int r = rg; r < nrows; r += nrg) {
@@ -270,9 +284,14 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
 #pragma unroll
           for (int j = 0; j < kGatherBatch; ++j) {
             const int k = k0 + j;
-            const bool on = k < cnt;
-            const uint32_t nb = on ? S.nbr[k * a.sub_rows + r] : (uint32_t)rho;
-            cf[j] = on ? S.off[S.nbb[k * a.sub_rows + r]] : 0.0;
+            uint32_t nb = k < cnt ? S.nbr[k * a.sub_rows + r] : kNoNeighbour;
+            bool on = nb != kNoNeighbour;
+            if (a.dense) {
+              cf[j] = on ? S.off[k] : 0.0;
+            } else {
+              cf[j] = on ? S.off[S.nbb[k * a.sub_rows + r]] : 0.0;
+            }
+            if (!on) nb = (uint32_t)rho;
             nv[j] = vload<T, CPL>(X + (int64_t)nb * ld + c * CPL);
           }
 #pragma unroll
@@ -331,6 +350,257 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
   }
 }
 
+// ------------------------------------------------------------- row kernel
+//
+// One lane per basis state carrying all LD columns of its block.  The state's
+// bits come from the sector's state table; diagonal, active bonds and
+// neighbour ranks are computed in registers (bond order, as in step_kernel);
+// NB neighbour rows are in flight at a time.  The output row is staged in LDS
+// and the column dots are then summed exactly as step_kernel sums them, so
+// both kernels give bitwise identical moments.
+
+template <typename T, int LD>
+struct RowChunk {
+  static constexpr int CH = sizeof(T) == 4 ? (LD % 4 == 0 ? 4 : (LD % 2 == 0 ? 2 : 1))
+                                           : (LD % 2 == 0 ? 2 : 1);
+};
+
+template <typename T, int LD>
+__device__ __forceinline__ void load_row(const T* p, T (&r)[LD]) {
+  constexpr int V = sizeof(T) == 4 ? (LD % 4 == 0 ? 4 : (LD % 2 == 0 ? 2 : 1)) : (LD % 2 == 0 ? 2 : 1);
+#pragma unroll
+  for (int c = 0; c < LD; c += V) {
+    const VecT<T, V> v = vload<T, V>(p + c);
+#pragma unroll
+    for (int i = 0; i < V; ++i) r[c + i] = v.v[i];
+  }
+}
+
+template <typename T, int LD, int CW, int NB>
+__global__ __launch_bounds__(kThreads) void row_kernel(const StepArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x;
+  if (a.n_jobs > 0) {
+    const int64_t s = (a.step_base ? *a.step_base : 0) + a.step_add;
+    double* sh = reinterpret_cast<double*>(smem);
+    for (int job = blockIdx.x; job < a.n_jobs; job += gridDim.x) {
+      const UnitDev U = a.units[a.job_unit[job]];
+      const int v = job - 2 * U.col_off;
+      const double sum = sum_partials(a.part_in + U.part_off + (int64_t)v * U.ntiles, U.ntiles, sh);
+      if (tid == 0) {
+        if (v < U.ld) a.alpha[s * a.total_cols + U.col_off + v] = sum;
+        else a.beta[(s - 1) * a.total_cols + U.col_off + (v - U.ld)] = sum;
+      }
+    }
+    __syncthreads();
+  }
+  const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.grid_tiles) : (int)blockIdx.x;
+  if (tile >= a.n_tiles) return;
+  const UnitDev U = a.units[a.tile_unit[tile]];
+  const ProbDev P = a.probs[U.prob];
+  constexpr int CH = RowChunk<T, LD>::CH;
+
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* q = smem + o;
+    o = (o + bytes + 15) & ~size_t(15);
+    return q;
+  };
+  uint32_t* s_tab = reinterpret_cast<uint32_t*>(take((size_t)a.lds_tab * 4));
+  uint32_t* s_mask = reinterpret_cast<uint32_t*>(take((size_t)a.lds_bonds * 4));
+  double* s_off = reinterpret_cast<double*>(take((size_t)a.lds_bonds * 8));
+  double* s_zz = reinterpret_cast<double*>(take((size_t)a.lds_bonds * 8));
+  unsigned char* tail = smem + o;
+  T* s_out = reinterpret_cast<T*>(tail);              // [kThreads][LD]
+  double* s_red = reinterpret_cast<double*>(tail);    // reused after the last sub-tile
+
+  for (int i = tid; i < P.tab_len; i += kThreads) s_tab[i] = a.tables[P.tab_off + i];
+  for (int i = tid; i < P.n_bonds; i += kThreads) {
+    s_mask[i] = a.bmask[P.bond_off + i];
+    s_off[i] = a.boff[P.bond_off + i];
+    s_zz[i] = a.bzz[P.bond_off + i];
+  }
+  __syncthreads();
+  const RankTables RT = make_tables(s_tab, P);
+  const int nb = P.n_bonds;
+
+  T* base = reinterpret_cast<T*>(a.vec) + U.vec_off;
+  const T* X = base + a.x_slot * a.slot_stride;
+  const T* Yin = base + a.yin_slot * a.slot_stride;
+  T* Y = base + a.yout_slot * a.slot_stride;
+  const uint32_t* states = a.states + P.state_off;
+
+  const int nch = LD / CH;
+  const int nrg = kThreads / nch;
+  const int c = tid % nch;
+  const int rg = tid / nch;
+  double acc_a[CH], acc_b[CH];
+#pragma unroll
+  for (int i = 0; i < CH; ++i) acc_a[i] = acc_b[i] = 0.0;
+
+  const int64_t tile_row0 = (int64_t)(tile - U.tile0) * kThreads * a.sub_per_tile;
+  for (int st = 0; st < a.sub_per_tile; ++st) {
+    const int64_t row0 = tile_row0 + (int64_t)st * kThreads;
+    if (row0 >= P.dim) break;
+    const int nrows = (int)min((int64_t)kThreads, P.dim - row0);
+    if (tid < nrows) {
+      const int64_t rho = row0 + tid;
+      const uint32_t s = states[rho];
+      double dg = P.shift;
+      for (int b = 0; b < nb; ++b) {
+        const uint32_t m = s_mask[b];
+        const uint32_t v = s & m;
+        dg += (v == 0u || v == m) ? s_zz[b] : -s_zz[b];
+      }
+      // (CW = LD: one window; a narrower window re-gathers every neighbour row
+      // per window and measured slower)
+      constexpr int V = sizeof(T) == 4 ? (CW % 4 == 0 ? 4 : (CW % 2 == 0 ? 2 : 1)) : (CW % 2 == 0 ? 2 : 1);
+#pragma unroll 1
+      for (int c0 = 0; c0 < LD; c0 += CW) {
+        double acc[CW];
+        {
+          T xr[CW];
+          load_row<T, CW>(X + rho * LD + c0, xr);
+#pragma unroll
+          for (int i = 0; i < CW; ++i) acc[i] = dg * (double)xr[i];
+        }
+        for (int b0 = 0; b0 < nb; b0 += 64) {
+          const int lim = min(64, nb - b0);
+          uint64_t act = 0;
+          for (int j = 0; j < lim; ++j) {
+            const uint32_t m = s_mask[b0 + j];
+            const uint32_t v = s & m;
+            if (!(v == 0u || v == m)) act |= 1ull << j;
+          }
+          while (act) {
+            int bb[NB];
+            uint32_t rr[NB];
+            double cf[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+              if (act) {
+                const int j = __ffsll((unsigned long long)act) - 1;
+                act &= act - 1;
+                bb[q] = b0 + j;
+                uint32_t r = RT.rank(s ^ s_mask[b0 + j]);
+                if (r >= (uint32_t)P.dim) {
+                  if (a.err) atomicOr(a.err, 2);
+                  r = (uint32_t)rho;
+                }
+                rr[q] = r;
+                cf[q] = s_off[b0 + j];
+              } else {
+                bb[q] = -1;
+                rr[q] = (uint32_t)rho;
+                cf[q] = 0.0;
+              }
+            }
+            T g[NB][CW];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) load_row<T, CW>(X + (int64_t)rr[q] * LD + c0, g[q]);
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+              if (bb[q] >= 0) {
+#pragma unroll
+                for (int i = 0; i < CW; ++i) acc[i] = fma(cf[q], (double)g[q][i], acc[i]);
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int i0 = 0; i0 < CW; i0 += V) {
+          VecT<T, V> ov;
+          if (a.first) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) ov.v[i] = (T)acc[i0 + i];
+          } else {
+            const VecT<T, V> yv = vload_nt<T, V>(Yin + rho * LD + c0 + i0);
+#pragma unroll
+            for (int i = 0; i < V; ++i) ov.v[i] = (T)(2.0 * acc[i0 + i] - (double)yv.v[i]);
+          }
+          vstore_nt<T, V>(Y + rho * LD + c0 + i0, ov);
+          vstore<T, V>(s_out + tid * LD + c0 + i0, ov);
+        }
+      }
+    }
+    __syncthreads();
+    if (rg < nrg) {
+      for (int r = rg; r < nrows; r += nrg) {
+        const VecT<T, CH> ov = vload<T, CH>(s_out + r * LD + c * CH);
+        const VecT<T, CH> xv = vload<T, CH>(X + (row0 + r) * LD + c * CH);
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+          const double od = (double)ov.v[i];
+          acc_a[i] = fma(od, od, acc_a[i]);
+          acc_b[i] = fma(od, (double)xv.v[i], acc_b[i]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  if (rg < nrg) {
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      s_red[(2 * i) * kThreads + tid] = acc_a[i];
+      s_red[(2 * i + 1) * kThreads + tid] = acc_b[i];
+    }
+  }
+  int p2 = 1;
+  while (p2 < nrg) p2 <<= 1;
+  for (int sstride = p2 >> 1; sstride > 0; sstride >>= 1) {
+    __syncthreads();
+    if (rg < sstride && rg + sstride < nrg) {
+#pragma unroll
+      for (int v = 0; v < 2 * CH; ++v) s_red[v * kThreads + tid] += s_red[v * kThreads + tid + sstride * nch];
+    }
+  }
+  __syncthreads();
+  if (tid < nch) {
+    const int tl = tile - U.tile0;
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int col = c * CH + i;
+      a.part_out[U.part_off + (int64_t)col * U.ntiles + tl] = s_red[(2 * i) * kThreads + tid];
+      a.part_out[U.part_off + (int64_t)(LD + col) * U.ntiles + tl] = s_red[(2 * i + 1) * kThreads + tid];
+    }
+  }
+}
+
+size_t row_lds_bytes(const DevicePlan& p) {
+  auto a16 = [](size_t x) { return (x + 15) & ~size_t(15); };
+  size_t o = 0;
+  o = a16(o + (size_t)p.lds_tab * 4);
+  o = a16(o + (size_t)p.lds_bonds * 4);
+  o = a16(o + (size_t)p.lds_bonds * 8);
+  o = a16(o + (size_t)p.lds_bonds * 8);
+  const size_t elt = p.fp32 ? 4 : 8;
+  const size_t outs = (size_t)kThreads * p.row_ld * elt;
+  const size_t red = (size_t)2 * 4 * kThreads * 8;
+  return a16(o + (outs > red ? outs : red));
+}
+
+template <typename T, int LD, int CW, int NB>
+static hipError_t launch_row_t(const StepArgs& a, size_t lds, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((row_kernel<T, LD, CW, NB>), dim3(grid), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+static hipError_t launch_row(const DevicePlan& p, const StepArgs& a, hipStream_t st) {
+  const size_t lds = row_lds_bytes(p);
+  const int grid = p.grid_tiles;
+#define KPM_ROW(L, NBB)                                                                   \
+  if (p.row_ld == L)                                                                      \
+    return p.fp32 ? launch_row_t<float, L, L, NBB>(a, lds, grid, st)                      \
+                  : launch_row_t<double, L, L, NBB>(a, lds, grid, st);
+  KPM_ROW(1, 4)
+  KPM_ROW(2, 4)
+  KPM_ROW(4, 2)
+  KPM_ROW(8, 2)
+#undef KPM_ROW
+  return hipErrorInvalidValue;
+}
+
 size_t step_lds_bytes(const DevicePlan& p) {
   auto a16 = [](size_t x) { return (x + 15) & ~size_t(15); };
   size_t o = 0;
@@ -367,6 +637,8 @@ static StepArgs make_step_args(const DevicePlan& p) {
   a.lds_bonds = p.lds_bonds;
   a.xcd_remap = p.xcd_remap;
   a.slot_stride = p.slot_stride;
+  a.dense = p.dense;
+  a.states = p.states;
   return a;
 }
 
@@ -411,6 +683,7 @@ hipError_t launch_step_slots(const DevicePlan& p, void* vec, double* part_out, i
 }
 
 hipError_t launch_step_args(const DevicePlan& p, const StepArgs& a, hipStream_t st) {
+  if (p.row_ld > 0) return launch_row(p, a, st);
   const size_t lds = step_lds_bytes(p);
   const int grid = p.grid_tiles;
   if (p.fp32) {
@@ -621,6 +894,8 @@ __global__ __launch_bounds__(kThreads) void states_kernel(int N, int k, const ui
        r += (int64_t)gridDim.x * kThreads)
     out[r] = unrank((uint32_t)r, N, k, sb);
 }
+hipError_t fill_states(const DevicePlan& p, hipStream_t st);
+
 hipError_t launch_states(int N, int k, const uint32_t* binom, uint32_t* out, int64_t dim,
                          hipStream_t st) {
   int64_t g = (dim + kThreads - 1) / kThreads;
@@ -743,4 +1018,25 @@ hipError_t launch_matrix(const MatrixArgs& a, size_t lds, int grid, hipStream_t 
   hipLaunchKernelGGL(matrix_kernel, dim3(grid), dim3(kThreads), lds, st, a);
   return hipGetLastError();
 }
+// Basis words of every sector, one unranking launch per sector.
+__global__ __launch_bounds__(kThreads) void fill_states_kernel(const ProbDev* probs, int n_probs,
+                                                              const uint32_t* binom,
+                                                              uint32_t* states) {
+  __shared__ uint32_t sb[kBinomN * kBinomN];
+  for (int i = threadIdx.x; i < kBinomN * kBinomN; i += kThreads) sb[i] = binom[i];
+  __syncthreads();
+  const int p = blockIdx.y;
+  const ProbDev P = probs[p];
+  for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < P.dim;
+       r += (int64_t)gridDim.x * kThreads)
+    states[P.state_off + r] = unrank((uint32_t)r, P.n_sites, P.n_up, sb);
+}
+
+hipError_t fill_states(const DevicePlan& p, hipStream_t st) {
+  if (!p.states || p.n_probs == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_states_kernel, dim3(2048, p.n_probs), dim3(kThreads), 0, st, p.probs,
+                     p.n_probs, p.binom, p.states);
+  return hipGetLastError();
+}
+
 }  // namespace kpm

@@ -149,7 +149,7 @@ def test_j1j2_n20_full_size_vs_finite_differences(kpm, t_lo, h):
     L, dJ, _ = kpm.thermo_grad(secs, wl.M, wl.R, T, wC, wX, kernel="none", ckpt_every=64, bounds=bl)
     g = dJ.cpu().numpy()
     assert g.shape == (40,)
-    for b in (0, 7, 33):
+    for b in (0, 7, 26, 33):
         vals = []
         for sgn in (1, -1):
             J = cl.J.copy()
@@ -158,4 +158,6 @@ def test_j1j2_n20_full_size_vs_finite_differences(kpm, t_lo, h):
                                        kernel="none", ckpt_every=64, bounds=bl)
             vals.append(Lh.item())
         fd = (vals[0] - vals[1]) / (2 * h)
-        assert abs(g[b] - fd) <= 1e-5 * abs(g[b]), (b, g[b], fd)
+        # relative to the gradient's scale: bonds whose derivative is ~500x
+        # smaller than the rest carry the same absolute quotient noise
+        assert abs(g[b] - fd) <= 1e-5 * np.abs(g).max(), (b, g[b], fd)
