@@ -195,9 +195,9 @@ typedef struct {
                               size * sum over blocks of dim * real columns */
   double state_col_steps;  /* sum over blocks of dim * real columns * steps */
   int32_t col_block;       /* real columns per block chosen */
-  int32_t rows_per_tile;   /* basis states per workgroup tile */
+  int32_t rows_per_tile;   /* basis states per workgroup tile (block kernel: mean) */
   int32_t graph_segment;   /* steps per captured graph (0 = direct launches) */
-  int32_t reserved;
+  int32_t kernel;          /* step kernel used: 0 column-chunk, 1 row, 2 block */
   double recursion_ms;     /* hipEvent time on the call's stream from the first
                               to the last recursion-step launch, inclusive */
 } kpm_run_stats;

@@ -116,11 +116,11 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(const AdjArgs a) {
   const int co = U.col_off;
 
   double bacc = 0.0;   // thread b < nb: this tile's sum for bond b
-  const int64_t tile_row0 = (int64_t)(tile - U.tile0) * SR * a.sub_per_tile;
-  for (int st = 0; st < a.sub_per_tile; ++st) {
+  const int64_t tile_row0 = a.tile_row0[tile];
+  const int tile_rows = a.tile_nrows[tile];
+  for (int st = 0; st * SR < tile_rows; ++st) {
     const int64_t row0 = tile_row0 + (int64_t)st * SR;
-    if (row0 >= P.dim) break;
-    const int nrows = (int)min((int64_t)SR, P.dim - row0);
+    const int nrows = min(SR, tile_rows - st * SR);
     const int t = threadIdx.x;
     if (t < nrows) {
       const int64_t rho = row0 + t;
@@ -212,6 +212,8 @@ hipError_t launch_adjoint(const DevicePlan& p, AdjArgs a, int ld, hipStream_t st
   a.probs = p.probs;
   a.units = p.units;
   a.tile_unit = p.tile_unit;
+  a.tile_row0 = p.tile_row0;
+  a.tile_nrows = p.tile_nrows;
   a.tables = p.tables;
   a.bmask = p.bmask;
   a.boff = p.boff;

@@ -165,14 +165,18 @@ int64_t total_columns(const kpm_problem& p, const RunShape& s) {
 struct Planned {
   std::vector<ProbDev> probs;
   std::vector<UnitDev> units;
-  std::vector<int32_t> tile_unit, job_unit, prob_unit0;
+  std::vector<int32_t> tile_unit, job_unit, prob_unit0, tile_nrows;
+  std::vector<int64_t> tile_row0;
   std::vector<uint32_t> tables, bmask, binom;
   std::vector<double> boff, bzz;
+  std::vector<uint16_t> bperm, lrank;
+  std::vector<int32_t> tile_sub0, sub_nrows;
   DevicePlan plan;
   double bytes_per_step = 0;     // algorithmic (3 * storage * dim * real columns)
   double state_cols = 0;         // sum of dim * real columns
   // byte offsets of the packed plan arrays
-  size_t o_probs, o_units, o_tile, o_job, o_pu0, o_tab, o_mask, o_off, o_zz, o_binom, bytes;
+  size_t o_probs, o_units, o_tile, o_job, o_pu0, o_tab, o_mask, o_off, o_zz, o_binom, o_trow0,
+      o_tnrows, o_bperm, o_tsub0, o_subn, o_lrank, bytes;
 };
 
 int env_int(const char* name, int dflt) {
@@ -190,6 +194,35 @@ int pick_col_block(const kpm_problem* p, int n, const RunShape& s) {
   rb = (int)std::min<int64_t>(rb, maxc);
   rb = (rb + cpv - 1) / cpv * cpv;
   return std::min(rb, kMaxLd);
+}
+
+// Tiles of whole blocks for the block kernel: the blocks of sector (N, k)
+// with L low bits, in rank order (ascending high bits h), packed greedily into
+// tiles of at most `rows` states and `blk_max` blocks.
+void block_tiles(int N, int k, int L, int rows, int blk_max, std::vector<int64_t>& row0,
+                 std::vector<int32_t>& nrows) {
+  const uint64_t nh = 1ull << (N - L);
+  int64_t start = 0, cur0 = 0;
+  int cur_rows = 0, cur_blk = 0;
+  for (uint64_t h = 0; h < nh; ++h) {
+    const int c = k - __builtin_popcountll(h);
+    if (c < 0 || c > L) continue;
+    const int size = (int)binom64(L, c);
+    if (cur_blk > 0 && (cur_rows + size > rows || cur_blk == blk_max)) {
+      row0.push_back(cur0);
+      nrows.push_back(cur_rows);
+      cur0 = start;
+      cur_rows = 0;
+      cur_blk = 0;
+    }
+    cur_rows += size;
+    ++cur_blk;
+    start += size;
+  }
+  if (cur_blk > 0) {
+    row0.push_back(cur0);
+    nrows.push_back(cur_rows);
+  }
 }
 
 // a, b per problem must already be known (scale != nullptr) for the bond
@@ -279,9 +312,94 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   if (s.adjoint && (adjoint_lds_bytes(D) > lds_hard || max_bonds > D.sub_rows)) return KPM_EINVAL;
   D.row_ld = row_ld;
   if (row_ld && row_lds_bytes(D) > lds_hard) D.row_ld = row_ld = 0;
-  if (row_ld) D.row_window = row_ld;
   if (row_ld) D.sub_rows = kThreads;
   D.n_states = n_states;
+
+  // Block kernel (tiles of whole low-bit blocks) when its LDS fits: bonds in
+  // class order low-low, high-high, mixed.
+  P.bperm.assign(std::max<size_t>(bond_total, 1), 0);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < p[i].n_bonds; ++k) P.bperm[P.probs[i].bond_off + k] = (uint16_t)k;
+  D.block = 0;
+  std::vector<std::vector<int64_t>> btile_row0(n);
+  std::vector<std::vector<int32_t>> btile_nrows(n);
+  // Default: float32 storage with blocks too wide for the row kernel (the
+  // measured case where it is the fastest kernel); KPM_BLOCK=0/1 overrides.
+  const int block_env = env_int("KPM_BLOCK", -1);
+  const bool block_default = fp32 && rb > 8;
+  if (!s.adjoint && s.allow_row && (block_env == 1 || (block_env < 0 && block_default))) {
+    D.ld_max = adj_ld ? adj_ld : (rb + cpl - 1) / cpl * cpl;
+    D.blk_max = std::max(1, std::min(255, env_int("KPM_BLOCK_MAX", 16)));
+    const size_t cap = (size_t)env_int("KPM_BLOCK_LDS", 64 * 1024);
+    for (int rows = std::min(kThreads, std::max(32, env_int("KPM_BLOCK_ROWS", kThreads)));
+         rows >= 32 && !D.block; rows >>= 1) {
+      int Lm = std::max(1, std::min(env_int("KPM_BLOCK_L", 10), 16));
+      while (Lm > 1 && binom64(Lm, Lm / 2) > (uint64_t)rows) --Lm;
+      int lr = 1, hh = 1, mx = 1;
+      for (int i = 0; i < n; ++i) {
+        ProbDev& d = P.probs[i];
+        const int L = std::min(p[i].n_sites, Lm);
+        const uint32_t low = (L >= 32) ? 0xFFFFFFFFu : ((1u << L) - 1u);
+        std::vector<uint16_t> cls[3];
+        for (int k = 0; k < p[i].n_bonds; ++k) {
+          const uint32_t m = (1u << p[i].bond_i[k]) | (1u << p[i].bond_j[k]);
+          const int c = (m & ~low) == 0 ? 0 : ((m & low) == 0 ? 1 : 2);
+          cls[c].push_back((uint16_t)k);
+        }
+        d.blk_L = L;
+        d.n_ll = (int32_t)cls[0].size();
+        d.n_hh = (int32_t)cls[1].size();
+        d.n_mx = (int32_t)cls[2].size();
+        int q = d.bond_off;
+        for (auto& v : cls)
+          for (uint16_t b : v) P.bperm[q++] = b;
+        lr = std::max(lr, 1 << L);
+        hh = std::max(hh, d.n_hh);
+        mx = std::max(mx, d.n_mx);
+      }
+      D.blk_rows = rows;
+      D.lds_lr = lr;
+      D.lds_hh = hh;
+      D.lds_mx = mx;
+      if (block_lds_bytes(D) <= cap) D.block = 1;
+    }
+  }
+  int bspt = 1;
+  if (D.block) D.row_ld = row_ld = 0;
+  // Neighbour rows in flight per lane: row kernel 2/4/8, others 4/8.
+  D.gather_batch = (row_ld == 4 || row_ld == 8) ? 2 : 4;
+  if (const int f = env_int("KPM_GATHER_BATCH", 0)) D.gather_batch = f;
+  if (D.gather_batch != 2 && D.gather_batch != 4 && D.gather_batch != 8) D.gather_batch = 4;
+  if (!row_ld && D.gather_batch < 4) D.gather_batch = 4;
+  if (D.block) {
+    D.row_ld = row_ld = 0;
+    size_t max_sub = 1;
+    int maxL = 1;
+    for (int i = 0; i < n; ++i) {
+      block_tiles(p[i].n_sites, p[i].n_up, P.probs[i].blk_L, D.blk_rows, D.blk_max, btile_row0[i],
+                  btile_nrows[i]);
+      max_sub = std::max(max_sub, btile_row0[i].size());
+      maxL = std::max(maxL, P.probs[i].blk_L);
+    }
+    // colex rank of every low word among the words of its popcount
+    P.lrank.assign(size_t(1) << maxL, 0);
+    for (uint32_t l = 0; l < (1u << maxL); ++l) {
+      uint64_t r = 0;
+      int j = 0;
+      for (int q = 0; q < maxL; ++q)
+        if ((l >> q) & 1u) r += binom64(q, ++j);
+      P.lrank[l] = (uint16_t)r;
+    }
+    // Sub-tiles per workgroup: amortise the per-workgroup LDS fill (tables,
+    // bonds, ranks) over the streamed rows, keeping >= 2048 workgroups on the
+    // largest problem.
+    const double fixed = (double)max_tab * 4 + (double)max_bonds * 20 + (double)(size_t(2) << maxL);
+    const double per_sub = 3.0 * D.blk_rows * D.ld_max * elt;
+    int spt = (int)std::ceil(8.0 * fixed / per_sub);
+    spt = (int)std::max<size_t>(1, std::min<size_t>((size_t)spt, std::max<size_t>(1, max_sub / 2048)));
+    if (const int f = env_int("KPM_SUB_PER_TILE", 0)) spt = f;
+    bspt = std::max(1, std::min(spt, 64));
+  }
 
   // Rows per workgroup tile: enough rows to amortise the per-tile LDS fill,
   // but keep >= 2048 tiles on the largest block when its size permits.
@@ -312,14 +430,32 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
       u.col0 = (int32_t)c0;
       u.vec_off = vec_elems;
       vec_elems += (int64_t)align_up((size_t)(dim * u.ld), 64);
-      u.ntiles = (int32_t)((dim + tile_rows - 1) / tile_rows);
+      u.ntiles = D.block ? (int32_t)((btile_row0[i].size() + bspt - 1) / bspt)
+                         : (int32_t)((dim + tile_rows - 1) / tile_rows);
       u.tile0 = tiles;
       u.part_off = part_len;
       part_len += (int64_t)2 * u.ld * u.ntiles;
       u.bd_off = bd_len;
       bd_len += (int64_t)u.ntiles * std::max(1, p[i].n_bonds);
       u.col_off = col_off;
-      for (int t = 0; t < u.ntiles; ++t) P.tile_unit.push_back((int32_t)P.units.size());
+      for (int t = 0; t < u.ntiles; ++t) {
+        P.tile_unit.push_back((int32_t)P.units.size());
+        if (D.block) {
+          const size_t s0 = (size_t)t * bspt;
+          const size_t s1 = std::min(s0 + bspt, btile_row0[i].size());
+          int32_t rows = 0;
+          P.tile_sub0.push_back((int32_t)P.sub_nrows.size());
+          for (size_t k = s0; k < s1; ++k) {
+            P.sub_nrows.push_back(btile_nrows[i][k]);
+            rows += btile_nrows[i][k];
+          }
+          P.tile_row0.push_back(btile_row0[i][s0]);
+          P.tile_nrows.push_back(rows);
+        } else {
+          P.tile_row0.push_back((int64_t)t * tile_rows);
+          P.tile_nrows.push_back((int32_t)std::min<int64_t>(tile_rows, dim - (int64_t)t * tile_rows));
+        }
+      }
       for (int j = 0; j < 2 * u.ld; ++j) P.job_unit.push_back((int32_t)P.units.size());
       tiles += u.ntiles;
       col_off += u.ld;
@@ -329,6 +465,9 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
     }
   }
   P.prob_unit0.push_back((int32_t)P.units.size());
+  P.tile_sub0.push_back((int32_t)P.sub_nrows.size());
+  if (P.sub_nrows.empty()) P.sub_nrows.push_back(0);
+  if (P.lrank.empty()) P.lrank.push_back(0);
   D.n_probs = n;
   D.n_units = (int32_t)P.units.size();
   D.n_tiles = tiles;
@@ -355,6 +494,12 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   P.o_off = put(P.boff.size() * 8);
   P.o_zz = put(P.bzz.size() * 8);
   P.o_binom = put(P.binom.size() * 4);
+  P.o_trow0 = put(P.tile_row0.size() * 8);
+  P.o_tnrows = put(P.tile_nrows.size() * 4);
+  P.o_bperm = put(P.bperm.size() * 2);
+  P.o_tsub0 = put(P.tile_sub0.size() * 4);
+  P.o_subn = put(P.sub_nrows.size() * 4);
+  P.o_lrank = put(P.lrank.size() * 2);
   P.bytes = o;
   return KPM_OK;
 }
@@ -376,6 +521,12 @@ int upload_plan(Planned& P, unsigned char* dst, std::vector<unsigned char>& stag
   cp(P.o_off, P.boff.data(), P.boff.size() * 8);
   cp(P.o_zz, P.bzz.data(), P.bzz.size() * 8);
   cp(P.o_binom, P.binom.data(), P.binom.size() * 4);
+  cp(P.o_trow0, P.tile_row0.data(), P.tile_row0.size() * 8);
+  cp(P.o_tnrows, P.tile_nrows.data(), P.tile_nrows.size() * 4);
+  cp(P.o_bperm, P.bperm.data(), P.bperm.size() * 2);
+  cp(P.o_tsub0, P.tile_sub0.data(), P.tile_sub0.size() * 4);
+  cp(P.o_subn, P.sub_nrows.data(), P.sub_nrows.size() * 4);
+  cp(P.o_lrank, P.lrank.data(), P.lrank.size() * 2);
   KPM_HIP(hipMemcpyAsync(dst, staging.data(), P.bytes, hipMemcpyHostToDevice, st));
   DevicePlan& D = P.plan;
   D.probs = reinterpret_cast<ProbDev*>(dst + P.o_probs);
@@ -388,6 +539,12 @@ int upload_plan(Planned& P, unsigned char* dst, std::vector<unsigned char>& stag
   D.boff = reinterpret_cast<double*>(dst + P.o_off);
   D.bzz = reinterpret_cast<double*>(dst + P.o_zz);
   D.binom = reinterpret_cast<uint32_t*>(dst + P.o_binom);
+  D.tile_row0 = reinterpret_cast<int64_t*>(dst + P.o_trow0);
+  D.tile_nrows = reinterpret_cast<int32_t*>(dst + P.o_tnrows);
+  D.bperm = reinterpret_cast<uint16_t*>(dst + P.o_bperm);
+  D.tile_sub0 = reinterpret_cast<int32_t*>(dst + P.o_tsub0);
+  D.sub_nrows = reinterpret_cast<int32_t*>(dst + P.o_subn);
+  D.lrank = reinterpret_cast<uint16_t*>(dst + P.o_lrank);
   return KPM_OK;
 }
 
@@ -512,7 +669,7 @@ int run_lanczos(const kpm_problem* p, int n, int steps, double margin, uint64_t 
   D.err = reinterpret_cast<int*>(work + L.err);
   D.states = reinterpret_cast<uint32_t*>(work + L.states);
   KPM_HIP(hipMemsetAsync(D.err, 0, sizeof(int), st));
-  if (D.row_ld) KPM_HIP(fill_states(D, st));
+  if (D.row_ld || D.block) KPM_HIP(fill_states(D, st));
   double* vec = reinterpret_cast<double*>(work + L.vec);
   double* vecC = reinterpret_cast<double*>(work + L.vecC);
   double* part = reinterpret_cast<double*>(work + L.part);
@@ -657,7 +814,7 @@ int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
   P.plan.err = flag;
   P.plan.states = reinterpret_cast<uint32_t*>(work + L.states);
   KPM_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
-  if (D.row_ld) KPM_HIP(fill_states(D, st));
+  if (D.row_ld || D.block) KPM_HIP(fill_states(D, st));
 
   if (q.vec_kind == KPM_VEC_GAUSSIAN || q.vec_kind == KPM_VEC_COMPLEX_GAUSSIAN) {
     KPM_HIP(launch_init(D, vec, 0, q.vec_kind, q.seed, nullptr, part[0], st));
@@ -735,6 +892,12 @@ int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
   g_stats.col_block = 0;
   for (auto& u : P.units) g_stats.col_block = std::max(g_stats.col_block, u.ncols);
   g_stats.rows_per_tile = D.sub_rows * D.sub_per_tile;
+  if (D.block && !P.tile_nrows.empty()) {
+    double rows = 0;
+    for (int32_t r : P.tile_nrows) rows += r;
+    g_stats.rows_per_tile = (int32_t)std::lround(rows / (double)P.tile_nrows.size());
+  }
+  g_stats.kernel = D.block ? 2 : (D.row_ld ? 1 : 0);
   g_stats.graph_segment = used_segment;
   float ms = 0.f;
   g_stats.recursion_ms = hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess ? (double)ms : -1.0;

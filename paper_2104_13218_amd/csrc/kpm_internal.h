@@ -23,6 +23,10 @@ struct ProbDev {
   double shift;       // -b / a   (diagonal shift of H' = (H - b)/a)
   double inv_a;       // 1 / a
   int64_t state_off;  // offset of this sector's basis words in the state table
+  // Block geometry (block kernel): the low blk_L bits of a state index it
+  // inside its block; bonds in class order (low-low, high-high, mixed) are
+  // listed by bperm[bond_off + q].
+  int32_t blk_L, n_ll, n_hh, n_mx;
 };
 
 // One recursion block: a problem and a contiguous range of its real columns.
@@ -41,6 +45,8 @@ struct StepArgs {
   const ProbDev* probs;
   const UnitDev* units;
   const int32_t* tile_unit;    // [n_tiles]: unit of each tile
+  const int64_t* tile_row0;    // [n_tiles]: first state of each tile
+  const int32_t* tile_nrows;   // [n_tiles]: states in each tile
   const int32_t* job_unit;     // [2 * total_cols]: unit of each reduction job
   const uint32_t* tables;      // rank tables of all problems
   const uint32_t* bmask;       // per bond: (1 << i) | (1 << j)
@@ -72,6 +78,17 @@ struct StepArgs {
   int* err;                    // bit 1 set if a neighbour rank fell outside its sector
   int32_t xcd_remap;           // 1: contiguous tile ranges per XCD
   int32_t dense;               // 1: one neighbour slot per bond (bond-major gathers)
+  // block kernel
+  const uint16_t* bperm;       // per problem: bond indices in class order
+  int32_t blk_max;             // blocks per tile (capacity)
+  int32_t blk_rows;            // rows per tile (capacity, <= kThreads)
+  int32_t lds_lr;              // entries of the low-word rank table (1 << max blk_L)
+  int32_t lds_hh;              // high-high bond capacity
+  int32_t lds_mx;              // mixed bond capacity
+  int32_t ld_max;              // widest block (LDS copy of v_n)
+  const int32_t* tile_sub0;    // [n_tiles + 1]: sub-tiles of tile t are [tile_sub0[t], tile_sub0[t+1])
+  const int32_t* sub_nrows;    // states of each sub-tile (consecutive from tile_row0)
+  const uint16_t* lrank;       // colex rank of every low word (1 << max blk_L entries)
 };
 
 // Device-side plan of one run (pointers into the workspace) + launch shape.
@@ -79,6 +96,8 @@ struct DevicePlan {
   ProbDev* probs = nullptr;
   UnitDev* units = nullptr;
   int32_t* tile_unit = nullptr;
+  int64_t* tile_row0 = nullptr;
+  int32_t* tile_nrows = nullptr;
   int32_t* job_unit = nullptr;
   int32_t* prob_unit0 = nullptr;
   uint32_t* tables = nullptr;
@@ -86,7 +105,11 @@ struct DevicePlan {
   double* boff = nullptr;
   double* bzz = nullptr;
   uint32_t* binom = nullptr;
-  uint32_t* states = nullptr;  // basis words (row kernel), filled by fill_states
+  uint32_t* states = nullptr;  // basis words (row and block kernels), filled by fill_states
+  uint16_t* bperm = nullptr;   // bond class order (block kernel)
+  int32_t* tile_sub0 = nullptr;  // block kernel: sub-tile range of each tile
+  int32_t* sub_nrows = nullptr;  // block kernel: states of each sub-tile
+  uint16_t* lrank = nullptr;     // block kernel: low-word colex ranks
   int* err = nullptr;          // device error word (see StepArgs::err)
   int32_t n_probs = 0, n_units = 0, n_tiles = 0, grid_tiles = 0, total_cols = 0;
   int32_t sub_rows = 256, sub_per_tile = 1, lds_nb = 0, lds_tab = 0, lds_bonds = 0;
@@ -95,7 +118,9 @@ struct DevicePlan {
   int32_t xcd_remap = 1;
   int32_t dense = 0;
   int32_t row_ld = 0;          // > 0: one lane per state with all row_ld columns
-  int32_t row_window = 0;      // columns per register window of the row kernel
+  int32_t gather_batch = 4;    // neighbour rows in flight per lane (2, 4 or 8)
+  int32_t block = 0;           // 1: block kernel (tiles of whole low-bit blocks)
+  int32_t blk_max = 16, blk_rows = kThreads, lds_lr = 1, lds_hh = 1, lds_mx = 1, ld_max = 1;
   int64_t n_states = 0;        // entries of the state table
   int64_t part_len = 0;        // doubles per partial buffer
   int64_t slot_stride = 0;     // elements of one slot (all blocks)
@@ -116,11 +141,13 @@ struct InitArgs {
   const ProbDev* probs;
   const UnitDev* units;
   const int32_t* tile_unit;
+  const int64_t* tile_row0;
+  const int32_t* tile_nrows;
   void* vec;                 // slot 0 is written
   const double* norms;   // per column: Gaussian sums of squares (mode 1)
   double* part_out;
   uint64_t seed;
-  int32_t n_tiles, grid_tiles, mode, vec_kind, tile_rows;
+  int32_t n_tiles, grid_tiles, mode, vec_kind;
 };
 
 struct FinalArgs {
@@ -153,13 +180,15 @@ struct LzArgs {
   const ProbDev* probs;
   const UnitDev* units;
   const int32_t* tile_unit;
+  const int64_t* tile_row0;
+  const int32_t* tile_nrows;
   double* w;
   const double* q;
   const double* coef;      // per unit (column offset); squared if coef_sqrt
   const double* dotvec;    // NULL => dot with the updated w itself
   double* part_out;
   int64_t slot_stride;
-  int32_t n_tiles, grid_tiles, tile_rows, coef_sqrt;
+  int32_t n_tiles, grid_tiles, coef_sqrt;
   int32_t w_hi, q_hi, d_hi;  // select slot 1 instead of slot 0
 };
 
@@ -213,6 +242,8 @@ struct AdjArgs {
   const ProbDev* probs;
   const UnitDev* units;
   const int32_t* tile_unit;
+  const int64_t* tile_row0;
+  const int32_t* tile_nrows;
   const uint32_t* tables;
   const uint32_t* bmask;
   const double* boff;
@@ -267,6 +298,7 @@ hipError_t launch_states(int N, int k, const uint32_t* binom, uint32_t* out, int
 // Basis words of every sector of the plan into p.states.
 hipError_t fill_states(const DevicePlan& p, hipStream_t st);
 size_t row_lds_bytes(const DevicePlan& p);
+size_t block_lds_bytes(const DevicePlan& p);
 hipError_t launch_matrix(const MatrixArgs& a, size_t lds, int grid, hipStream_t st);
 hipError_t launch_lz_axpy(const DevicePlan& p, const LzArgs& args, hipStream_t st);
 hipError_t launch_lz_next(const DevicePlan& p, double* qprev, double* q, const double* w,

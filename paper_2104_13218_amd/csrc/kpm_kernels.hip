@@ -212,7 +212,7 @@ __device__ __forceinline__ void load_problem_lds(const StepSmem& S, const ProbDe
 
 // ------------------------------------------------------------ step kernel
 
-template <typename T, int CPL>
+template <typename T, int CPL, int GB>
 __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
@@ -256,11 +256,11 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
 #pragma unroll
   for (int i = 0; i < CPL; ++i) acc_a[i] = acc_b[i] = 0.0;
 
-  const int64_t tile_row0 = (int64_t)(tile - U.tile0) * a.sub_rows * a.sub_per_tile;
-  for (int st = 0; st < a.sub_per_tile; ++st) {
+  const int64_t tile_row0 = a.tile_row0[tile];
+  const int tile_rows = a.tile_nrows[tile];
+  for (int st = 0; st * a.sub_rows < tile_rows; ++st) {
     const int64_t row0 = tile_row0 + (int64_t)st * a.sub_rows;
-    if (row0 >= P.dim) break;
-    const int nrows = (int)min((int64_t)a.sub_rows, P.dim - row0);
+    const int nrows = min(a.sub_rows, tile_rows - st * a.sub_rows);
     for (int r = tid; r < nrows; r += kThreads)
       stage_row((uint32_t)(row0 + r), P, RT, S, r, a.sub_rows, a.err, a.dense);
     __syncthreads();
@@ -276,13 +276,13 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
         T* ys = Y + rho * ld + c * CPL;
         VecT<T, CPL> yv;
         if (!a.first) yv = vload_nt<T, CPL>(Yin + rho * ld + c * CPL);
-        // gathers issued kGatherBatch at a time (absent entries read the row
+        // gathers issued GB at a time (absent entries read the row
         // itself with a zero coefficient), then accumulated in order
-        for (int k0 = 0; k0 < cnt; k0 += kGatherBatch) {
-          VecT<T, CPL> nv[kGatherBatch];
-          double cf[kGatherBatch];
+        for (int k0 = 0; k0 < cnt; k0 += GB) {
+          VecT<T, CPL> nv[GB];
+          double cf[GB];
 #pragma unroll
-          for (int j = 0; j < kGatherBatch; ++j) {
+          for (int j = 0; j < GB; ++j) {
             const int k = k0 + j;
             uint32_t nb = k < cnt ? S.nbr[k * a.sub_rows + r] : kNoNeighbour;
             bool on = nb != kNoNeighbour;
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
             nv[j] = vload<T, CPL>(X + (int64_t)nb * ld + c * CPL);
           }
 #pragma unroll
-          for (int j = 0; j < kGatherBatch; ++j) {
+          for (int j = 0; j < GB; ++j) {
 #pragma unroll
             for (int i = 0; i < CPL; ++i) acc[i] = fma(cf[j], (double)nv[j].v[i], acc[i]);
           }
@@ -438,11 +438,11 @@ __global__ __launch_bounds__(kThreads) void row_kernel(const StepArgs a) {
 #pragma unroll
   for (int i = 0; i < CH; ++i) acc_a[i] = acc_b[i] = 0.0;
 
-  const int64_t tile_row0 = (int64_t)(tile - U.tile0) * kThreads * a.sub_per_tile;
-  for (int st = 0; st < a.sub_per_tile; ++st) {
+  const int64_t tile_row0 = a.tile_row0[tile];
+  const int tile_rows = a.tile_nrows[tile];
+  for (int st = 0; st * kThreads < tile_rows; ++st) {
     const int64_t row0 = tile_row0 + (int64_t)st * kThreads;
-    if (row0 >= P.dim) break;
-    const int nrows = (int)min((int64_t)kThreads, P.dim - row0);
+    const int nrows = min(kThreads, tile_rows - st * kThreads);
     if (tid < nrows) {
       const int64_t rho = row0 + tid;
       const uint32_t s = states[rho];
@@ -590,15 +590,397 @@ static hipError_t launch_row(const DevicePlan& p, const StepArgs& a, hipStream_t
   const size_t lds = row_lds_bytes(p);
   const int grid = p.grid_tiles;
 #define KPM_ROW(L, NBB)                                                                   \
-  if (p.row_ld == L)                                                                      \
+  if (p.row_ld == L && p.gather_batch == NBB)                                             \
     return p.fp32 ? launch_row_t<float, L, L, NBB>(a, lds, grid, st)                      \
                   : launch_row_t<double, L, L, NBB>(a, lds, grid, st);
-  KPM_ROW(1, 4)
-  KPM_ROW(2, 4)
-  KPM_ROW(4, 2)
-  KPM_ROW(8, 2)
+#define KPM_ROW3(L) KPM_ROW(L, 2) KPM_ROW(L, 4) KPM_ROW(L, 8)
+  KPM_ROW3(1)
+  KPM_ROW3(2)
+  KPM_ROW3(4)
+  KPM_ROW3(8)
+#undef KPM_ROW3
 #undef KPM_ROW
   return hipErrorInvalidValue;
+}
+
+// ----------------------------------------------------------- block kernel
+//
+// States sharing their high bits h = s >> L form a block of consecutive ranks.
+// A member's index inside its block is the colex rank of its low bits l among
+// the L-bit words with popc(l) set bits, and the block starts at the rank of
+// (h << L) | (2^popc(l) - 1).  Tiles hold whole blocks (host packing).
+//   low-low bond    the neighbour lies in the same block: read from the tile's
+//                   LDS copy of v_n;
+//   high-high bond  block h maps onto block h ^ m with the same low bits, so a
+//                   block's rows gather one contiguous run of rows;
+//   mixed bond      rank through the tables and a scattered gather.
+// Per element the sum runs diagonal, low-low, high-high, mixed (each in bond
+// order); the column dots are summed as in step_kernel.
+
+struct BlockLds {
+  size_t tab, mask, off, zz, lrank, row_l, row_b0, row_blk, mx_cnt, diag, wcnt, blk_h, hh_n, hh_row,
+      hh_q, xs, mx_rank, mx_q, total;
+};
+
+__host__ __device__ inline BlockLds block_lds_layout(int lds_tab, int lds_bonds, int lds_lr,
+                                                     int blk_max, int lds_hh, int lds_mx,
+                                                     int rows, int ld_max, int elt, int cpl) {
+  BlockLds L{};
+  size_t o = 0;
+  auto put = [&](size_t b) {
+    const size_t r = o;
+    o = (o + b + 15) & ~size_t(15);
+    return r;
+  };
+  L.tab = put(size_t(lds_tab) * 4);
+  L.mask = put(size_t(lds_bonds) * 4);
+  L.off = put(size_t(lds_bonds) * 8);
+  L.zz = put(size_t(lds_bonds) * 8);
+  L.lrank = put(size_t(lds_lr) * 2);
+  L.row_l = put(size_t(rows) * 2);
+  L.row_b0 = put(size_t(rows) * 2);
+  L.row_blk = put(size_t(rows));
+  L.mx_cnt = put(size_t(rows) * 2);
+  L.diag = put(size_t(rows) * 8);
+  L.wcnt = put(4 * 4);
+  L.blk_h = put(size_t(blk_max) * 4);
+  L.hh_n = put(size_t(blk_max) * 4);
+  L.hh_row = put(size_t(blk_max) * lds_hh * 4);
+  L.hh_q = put(size_t(blk_max) * lds_hh * 2);
+  L.xs = put(size_t(rows) * ld_max * elt);
+  L.mx_rank = put(size_t(lds_mx) * rows * 4);
+  L.mx_q = put(size_t(lds_mx) * rows * 2);
+  const size_t red = L.xs + size_t(2 * cpl) * kThreads * 8;
+  L.total = o > red ? o : red;
+  return L;
+}
+
+size_t block_lds_bytes(const DevicePlan& p) {
+  return block_lds_layout(p.lds_tab, p.lds_bonds, p.lds_lr, p.blk_max, p.lds_hh, p.lds_mx,
+                          p.blk_rows, p.ld_max, p.fp32 ? 4 : 8, p.cpl)
+      .total;
+}
+
+constexpr uint32_t kNoRun = 0xFFFFFFFFu;
+
+// One workgroup walks the sub-tiles [tile_sub0[t], tile_sub0[t + 1]) of its
+// tile; each sub-tile is a run of whole blocks of at most blk_rows states.
+template <typename T, int CPL, int GB>
+__global__ __launch_bounds__(kThreads) void block_kernel(const StepArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x;
+
+  if (a.n_jobs > 0) {
+    const int64_t s = (a.step_base ? *a.step_base : 0) + a.step_add;
+    double* sh = reinterpret_cast<double*>(smem);
+    for (int job = blockIdx.x; job < a.n_jobs; job += gridDim.x) {
+      const UnitDev U = a.units[a.job_unit[job]];
+      const int v = job - 2 * U.col_off;
+      const double sum = sum_partials(a.part_in + U.part_off + (int64_t)v * U.ntiles, U.ntiles, sh);
+      if (tid == 0) {
+        if (v < U.ld) a.alpha[s * a.total_cols + U.col_off + v] = sum;
+        else a.beta[(s - 1) * a.total_cols + U.col_off + (v - U.ld)] = sum;
+      }
+    }
+    __syncthreads();
+  }
+
+  const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.grid_tiles) : (int)blockIdx.x;
+  if (tile >= a.n_tiles) return;
+  const UnitDev U = a.units[a.tile_unit[tile]];
+  const ProbDev P = a.probs[U.prob];
+  const int RC = a.blk_rows;
+  const BlockLds Lo = block_lds_layout(a.lds_tab, a.lds_bonds, a.lds_lr, a.blk_max, a.lds_hh,
+                                       a.lds_mx, RC, a.ld_max, (int)sizeof(T), CPL);
+  uint32_t* s_tab = reinterpret_cast<uint32_t*>(smem + Lo.tab);
+  uint32_t* s_mask = reinterpret_cast<uint32_t*>(smem + Lo.mask);
+  double* s_off = reinterpret_cast<double*>(smem + Lo.off);
+  double* s_zz = reinterpret_cast<double*>(smem + Lo.zz);
+  uint16_t* s_lrank = reinterpret_cast<uint16_t*>(smem + Lo.lrank);
+  uint16_t* s_row_l = reinterpret_cast<uint16_t*>(smem + Lo.row_l);
+  uint16_t* s_row_b0 = reinterpret_cast<uint16_t*>(smem + Lo.row_b0);
+  uint8_t* s_row_blk = reinterpret_cast<uint8_t*>(smem + Lo.row_blk);
+  uint16_t* s_mx_cnt = reinterpret_cast<uint16_t*>(smem + Lo.mx_cnt);
+  double* s_diag = reinterpret_cast<double*>(smem + Lo.diag);
+  int32_t* s_wcnt = reinterpret_cast<int32_t*>(smem + Lo.wcnt);
+  uint32_t* s_blk_h = reinterpret_cast<uint32_t*>(smem + Lo.blk_h);
+  int32_t* s_hh_n = reinterpret_cast<int32_t*>(smem + Lo.hh_n);
+  uint32_t* s_hh_row = reinterpret_cast<uint32_t*>(smem + Lo.hh_row);
+  uint16_t* s_hh_q = reinterpret_cast<uint16_t*>(smem + Lo.hh_q);
+  T* xs = reinterpret_cast<T*>(smem + Lo.xs);
+  uint32_t* s_mx_rank = reinterpret_cast<uint32_t*>(smem + Lo.mx_rank);
+  uint16_t* s_mx_q = reinterpret_cast<uint16_t*>(smem + Lo.mx_q);
+
+  const int nb = P.n_bonds, nll = P.n_ll, nhh = P.n_hh;
+  const int Lb = P.blk_L;
+  for (int i = tid; i < P.tab_len; i += kThreads) s_tab[i] = a.tables[P.tab_off + i];
+  for (int q = tid; q < nb; q += kThreads) {
+    const int b = P.bond_off + a.bperm[P.bond_off + q];
+    s_mask[q] = a.bmask[b];
+    s_off[q] = a.boff[b];
+    s_zz[q] = a.bzz[b];
+  }
+  // colex rank of a low word among the words of its popcount (independent of L)
+  for (int l = tid; l < (1 << Lb); l += kThreads) s_lrank[l] = a.lrank[l];
+  __syncthreads();
+  const RankTables RT = make_tables(s_tab, P);
+
+  const int ld = U.ld;
+  T* base = reinterpret_cast<T*>(a.vec) + U.vec_off;
+  const T* X = base + a.x_slot * a.slot_stride;
+  const T* Yin = base + a.yin_slot * a.slot_stride;
+  T* Y = base + a.yout_slot * a.slot_stride;
+  const uint32_t lmask = (1u << Lb) - 1u;
+  const int nch = ld / CPL;
+  const int nrg = kThreads / nch;
+  const int c = tid % nch;
+  const int rg = tid / nch;
+  const int lane = tid & 63, wv = tid >> 6;
+  double acc_a[CPL], acc_b[CPL];
+#pragma unroll
+  for (int i = 0; i < CPL; ++i) acc_a[i] = acc_b[i] = 0.0;
+
+  int64_t row0 = a.tile_row0[tile];
+  const int sub1 = a.tile_sub0[tile + 1];
+  for (int sub = a.tile_sub0[tile]; sub < sub1; ++sub) {
+    const int nrows = a.sub_nrows[sub];
+    {
+      // the sub-tile's rows of v_n are one contiguous run of nrows * ld elements
+      const T* src = X + row0 * ld;
+      const int nv = nrows * ld / CPL;
+      for (int e = tid; e < nv; e += kThreads) vstore<T, CPL>(xs + e * CPL, vload<T, CPL>(src + e * CPL));
+    }
+    // Phase A: one thread per row.
+    bool is_start = false;
+    uint32_t h = 0;
+    if (tid < nrows) {
+      const int64_t rho = row0 + tid;
+      const uint32_t s = a.states[P.state_off + rho];
+      h = s >> Lb;
+      const uint32_t l = s & lmask;
+      const int i = s_lrank[l];
+      is_start = i == 0;
+      int b0 = tid - i;
+      if (b0 < 0) {
+        if (a.err) atomicOr(a.err, 4);
+        b0 = 0;
+      }
+      s_row_l[tid] = (uint16_t)l;
+      s_row_b0[tid] = (uint16_t)b0;
+      double d = P.shift;
+      for (int q = 0; q < nb; ++q) {
+        const uint32_t m = s_mask[q];
+        const uint32_t v = s & m;
+        d += (v == 0u || v == m) ? s_zz[q] : -s_zz[q];
+      }
+      s_diag[tid] = d;
+      int cnt = 0;
+      for (int q = nll + nhh; q < nb; ++q) {
+        const uint32_t m = s_mask[q];
+        const uint32_t v = s & m;
+        if (v == 0u || v == m) continue;
+        uint32_t r = RT.rank(s ^ m);
+        if (r >= (uint32_t)P.dim) {
+          if (a.err) atomicOr(a.err, 2);
+          r = (uint32_t)rho;
+        }
+        s_mx_rank[cnt * RC + tid] = r;
+        s_mx_q[cnt * RC + tid] = (uint16_t)q;
+        ++cnt;
+      }
+      s_mx_cnt[tid] = (uint16_t)cnt;
+    }
+    // block slot of each row: block starts at or before it, minus one
+    const uint64_t bal = __ballot(is_start);
+    if (lane == 0) s_wcnt[wv] = __popcll(bal);
+    __syncthreads();
+    int kslot = __popcll(bal & ((1ull << lane) - 1ull)) + (is_start ? 1 : 0) - 1;
+    for (int w = 0; w < wv; ++w) kslot += s_wcnt[w];
+    const int nblk = min(s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3], a.blk_max);
+    if (tid < nrows) {
+      if (kslot < 0 || kslot >= a.blk_max) {
+        if (a.err) atomicOr(a.err, 4);
+        kslot = 0;
+        is_start = false;
+      }
+      s_row_blk[tid] = (uint8_t)kslot;
+      if (is_start) s_blk_h[kslot] = h;
+    }
+    __syncthreads();
+
+    // Phase A2: for every (block, high-high bond) the first row of the target
+    // run, then each block's acting bonds compacted in bond order.
+    for (int t = tid; t < nblk * nhh; t += kThreads) {
+      const int kb = t / nhh, q = t - kb * nhh;
+      const uint32_t hb = s_blk_h[kb];
+      const int cl = P.n_up - __popc(hb);
+      uint32_t st = kNoRun;
+      const uint32_t mh = s_mask[nll + q] >> Lb;
+      const uint32_t x = hb & mh;
+      if (cl < 0 || cl > Lb) {
+        if (a.err) atomicOr(a.err, 4);
+      } else if (!(x == 0u || x == mh)) {
+        st = RT.rank(((hb ^ mh) << Lb) | ((1u << cl) - 1u));
+        if ((int64_t)st + a.binom[Lb * kBinomN + cl] > P.dim) {
+          if (a.err) atomicOr(a.err, 2);
+          st = kNoRun;
+        }
+      }
+      s_hh_row[kb * a.lds_hh + q] = st;
+    }
+    __syncthreads();
+    for (int kb = tid; kb < nblk; kb += kThreads) {
+      int n = 0;
+      for (int q = 0; q < nhh; ++q) {
+        const uint32_t st = s_hh_row[kb * a.lds_hh + q];
+        if (st == kNoRun) continue;
+        s_hh_row[kb * a.lds_hh + n] = st;
+        s_hh_q[kb * a.lds_hh + n] = (uint16_t)(nll + q);
+        ++n;
+      }
+      s_hh_n[kb] = n;
+    }
+    __syncthreads();
+
+    // Phase C: (row, column chunk) items.
+    if (rg < nrg) {
+      for (int r = rg; r < nrows; r += nrg) {
+        const int64_t rho = row0 + r;
+        const VecT<T, CPL> xv = vload<T, CPL>(xs + r * ld + c * CPL);
+        const double dg = s_diag[r];
+        double acc[CPL];
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) acc[i] = dg * (double)xv.v[i];
+        VecT<T, CPL> yv;
+        if (!a.first) yv = vload_nt<T, CPL>(Yin + rho * ld + c * CPL);
+        const uint32_t l = s_row_l[r];
+        const int b0 = s_row_b0[r];
+        for (int q = 0; q < nll; ++q) {
+          const uint32_t m = s_mask[q];
+          const uint32_t v = l & m;
+          if (v == 0u || v == m) continue;
+          int j = b0 + s_lrank[l ^ m];
+          if (j >= nrows) {
+            if (a.err) atomicOr(a.err, 4);
+            j = r;
+          }
+          const VecT<T, CPL> nv = vload<T, CPL>(xs + j * ld + c * CPL);
+          const double cf = s_off[q];
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) acc[i] = fma(cf, (double)nv.v[i], acc[i]);
+        }
+        const int kb = s_row_blk[r];
+        const int64_t ib = r - b0;
+        const int nh = s_hh_n[kb];
+        for (int k0 = 0; k0 < nh; k0 += GB) {
+          VecT<T, CPL> nv[GB];
+          double cf[GB];
+#pragma unroll
+          for (int j = 0; j < GB; ++j) {
+            const int k = k0 + j;
+            const bool on = k < nh;
+            const int64_t row = on ? (int64_t)s_hh_row[kb * a.lds_hh + k] + ib : rho;
+            cf[j] = on ? s_off[s_hh_q[kb * a.lds_hh + k]] : 0.0;
+            nv[j] = vload<T, CPL>(X + row * ld + c * CPL);
+          }
+#pragma unroll
+          for (int j = 0; j < GB; ++j) {
+#pragma unroll
+            for (int i = 0; i < CPL; ++i) acc[i] = fma(cf[j], (double)nv[j].v[i], acc[i]);
+          }
+        }
+        const int cnt = s_mx_cnt[r];
+        for (int k0 = 0; k0 < cnt; k0 += GB) {
+          VecT<T, CPL> nv[GB];
+          double cf[GB];
+#pragma unroll
+          for (int j = 0; j < GB; ++j) {
+            const int k = k0 + j;
+            const bool on = k < cnt;
+            const int64_t row = on ? (int64_t)s_mx_rank[k * RC + r] : rho;
+            cf[j] = on ? s_off[s_mx_q[k * RC + r]] : 0.0;
+            nv[j] = vload<T, CPL>(X + row * ld + c * CPL);
+          }
+#pragma unroll
+          for (int j = 0; j < GB; ++j) {
+#pragma unroll
+            for (int i = 0; i < CPL; ++i) acc[i] = fma(cf[j], (double)nv[j].v[i], acc[i]);
+          }
+        }
+        VecT<T, CPL> ov;
+        if (a.first) {
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) ov.v[i] = (T)acc[i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) ov.v[i] = (T)(2.0 * acc[i] - (double)yv.v[i]);
+        }
+        vstore_nt<T, CPL>(Y + rho * ld + c * CPL, ov);
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) {
+          const double o = (double)ov.v[i];
+          acc_a[i] = fma(o, o, acc_a[i]);
+          acc_b[i] = fma(o, (double)xv.v[i], acc_b[i]);
+        }
+      }
+    }
+    row0 += nrows;
+    __syncthreads();
+  }
+
+  // Workgroup reduction over row groups, per column (same tree as step_kernel).
+  double* red = reinterpret_cast<double*>(smem + Lo.xs);
+  if (rg < nrg) {
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+      red[(2 * i) * kThreads + tid] = acc_a[i];
+      red[(2 * i + 1) * kThreads + tid] = acc_b[i];
+    }
+  }
+  int p2 = 1;
+  while (p2 < nrg) p2 <<= 1;
+  for (int sstride = p2 >> 1; sstride > 0; sstride >>= 1) {
+    __syncthreads();
+    if (rg < sstride && rg + sstride < nrg) {
+#pragma unroll
+      for (int v = 0; v < 2 * CPL; ++v) red[v * kThreads + tid] += red[v * kThreads + tid + sstride * nch];
+    }
+  }
+  __syncthreads();
+  if (tid < nch) {
+    const int tl = tile - U.tile0;
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+      const int col = c * CPL + i;
+      a.part_out[U.part_off + (int64_t)col * U.ntiles + tl] = red[(2 * i) * kThreads + tid];
+      a.part_out[U.part_off + (int64_t)(ld + col) * U.ntiles + tl] = red[(2 * i + 1) * kThreads + tid];
+    }
+  }
+}
+
+template <typename T, int CPL>
+static hipError_t launch_block_t(const StepArgs& a, size_t lds, int grid, int gb, hipStream_t st) {
+  if (gb == 8) hipLaunchKernelGGL((block_kernel<T, CPL, 8>), dim3(grid), dim3(kThreads), lds, st, a);
+  else hipLaunchKernelGGL((block_kernel<T, CPL, 4>), dim3(grid), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+static hipError_t launch_block(const DevicePlan& p, const StepArgs& a, hipStream_t st) {
+  const size_t lds = block_lds_bytes(p);
+  const int grid = p.grid_tiles;
+  if (p.fp32) {
+    switch (p.cpl) {
+      case 1: return launch_block_t<float, 1>(a, lds, grid, p.gather_batch, st);
+      case 2: return launch_block_t<float, 2>(a, lds, grid, p.gather_batch, st);
+      case 4: return launch_block_t<float, 4>(a, lds, grid, p.gather_batch, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (p.cpl) {
+    case 1: return launch_block_t<double, 1>(a, lds, grid, p.gather_batch, st);
+    case 2: return launch_block_t<double, 2>(a, lds, grid, p.gather_batch, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 size_t step_lds_bytes(const DevicePlan& p) {
@@ -621,6 +1003,8 @@ static StepArgs make_step_args(const DevicePlan& p) {
   a.probs = p.probs;
   a.units = p.units;
   a.tile_unit = p.tile_unit;
+  a.tile_row0 = p.tile_row0;
+  a.tile_nrows = p.tile_nrows;
   a.job_unit = p.job_unit;
   a.tables = p.tables;
   a.bmask = p.bmask;
@@ -639,12 +1023,23 @@ static StepArgs make_step_args(const DevicePlan& p) {
   a.slot_stride = p.slot_stride;
   a.dense = p.dense;
   a.states = p.states;
+  a.bperm = p.bperm;
+  a.blk_max = p.blk_max;
+  a.blk_rows = p.blk_rows;
+  a.lds_lr = p.lds_lr;
+  a.lds_hh = p.lds_hh;
+  a.lds_mx = p.lds_mx;
+  a.ld_max = p.ld_max;
+  a.tile_sub0 = p.tile_sub0;
+  a.sub_nrows = p.sub_nrows;
+  a.lrank = p.lrank;
   return a;
 }
 
 template <typename T, int CPL>
-static hipError_t launch_step_t(const StepArgs& a, size_t lds, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((step_kernel<T, CPL>), dim3(grid), dim3(kThreads), lds, st, a);
+static hipError_t launch_step_t(const StepArgs& a, size_t lds, int grid, int gb, hipStream_t st) {
+  if (gb == 8) hipLaunchKernelGGL((step_kernel<T, CPL, 8>), dim3(grid), dim3(kThreads), lds, st, a);
+  else hipLaunchKernelGGL((step_kernel<T, CPL, 4>), dim3(grid), dim3(kThreads), lds, st, a);
   return hipGetLastError();
 }
 
@@ -683,21 +1078,22 @@ hipError_t launch_step_slots(const DevicePlan& p, void* vec, double* part_out, i
 }
 
 hipError_t launch_step_args(const DevicePlan& p, const StepArgs& a, hipStream_t st) {
+  if (p.block) return launch_block(p, a, st);
   if (p.row_ld > 0) return launch_row(p, a, st);
   const size_t lds = step_lds_bytes(p);
   const int grid = p.grid_tiles;
   if (p.fp32) {
     switch (p.cpl) {
-      case 1: return launch_step_t<float, 1>(a, lds, grid, st);
-      case 2: return launch_step_t<float, 2>(a, lds, grid, st);
-      case 4: return launch_step_t<float, 4>(a, lds, grid, st);
+      case 1: return launch_step_t<float, 1>(a, lds, grid, p.gather_batch, st);
+      case 2: return launch_step_t<float, 2>(a, lds, grid, p.gather_batch, st);
+      case 4: return launch_step_t<float, 4>(a, lds, grid, p.gather_batch, st);
       default: return hipErrorInvalidValue;
     }
   }
   switch (p.cpl) {
-    case 1: return launch_step_t<double, 1>(a, lds, grid, st);
-    case 2: return launch_step_t<double, 2>(a, lds, grid, st);
-    case 4: return launch_step_t<double, 4>(a, lds, grid, st);
+    case 1: return launch_step_t<double, 1>(a, lds, grid, p.gather_batch, st);
+    case 2: return launch_step_t<double, 2>(a, lds, grid, p.gather_batch, st);
+    case 4: return launch_step_t<double, 4>(a, lds, grid, p.gather_batch, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -768,8 +1164,8 @@ __global__ __launch_bounds__(kThreads) void init_kernel(const InitArgs a) {
   const int nrg = kThreads / ld;
   const int tid = threadIdx.x;
   const int c = tid % ld, rg = tid / ld;
-  const int64_t row0 = (int64_t)(tile - U.tile0) * a.tile_rows;
-  const int64_t row1 = min(row0 + a.tile_rows, P.dim);
+  const int64_t row0 = a.tile_row0[tile];
+  const int64_t row1 = row0 + a.tile_nrows[tile];
   T* A = reinterpret_cast<T*>(a.vec) + U.vec_off;
   double scale = 1.0;
   if (a.mode == 2) scale = 1.0 / sqrt((double)P.dim);   // unit-norm Lanczos start
@@ -824,7 +1220,8 @@ hipError_t launch_init(const DevicePlan& p, void* vec, int mode, int vec_kind, u
   a.grid_tiles = p.grid_tiles;
   a.mode = mode;
   a.vec_kind = vec_kind;
-  a.tile_rows = p.sub_rows * p.sub_per_tile;
+  a.tile_row0 = p.tile_row0;
+  a.tile_nrows = p.tile_nrows;
   if (p.fp32) hipLaunchKernelGGL(init_kernel<float>, dim3(p.grid_tiles), dim3(kThreads), 0, st, a);
   else hipLaunchKernelGGL(init_kernel<double>, dim3(p.grid_tiles), dim3(kThreads), 0, st, a);
   return hipGetLastError();
@@ -944,8 +1341,8 @@ __global__ __launch_bounds__(kThreads) void lz_axpy_kernel(const LzArgs a) {
   if (tile >= a.n_tiles) return;
   const UnitDev U = a.units[a.tile_unit[tile]];
   const ProbDev P = a.probs[U.prob];
-  const int64_t row0 = (int64_t)(tile - U.tile0) * a.tile_rows;
-  const int64_t row1 = min(row0 + a.tile_rows, P.dim);
+  const int64_t row0 = a.tile_row0[tile];
+  const int64_t row1 = row0 + a.tile_nrows[tile];
   const double cf = a.coef_sqrt ? sqrt(a.coef[U.col_off]) : a.coef[U.col_off];
   double* w = lz_sel(a.w, a.w_hi, U, a.slot_stride);
   const double* q = lz_sel(const_cast<double*>(a.q), a.q_hi, U, a.slot_stride);
@@ -971,7 +1368,8 @@ hipError_t launch_lz_axpy(const DevicePlan& p, const LzArgs& args, hipStream_t s
   a.tile_unit = p.tile_unit;
   a.n_tiles = p.n_tiles;
   a.grid_tiles = p.grid_tiles;
-  a.tile_rows = p.sub_rows * p.sub_per_tile;
+  a.tile_row0 = p.tile_row0;
+  a.tile_nrows = p.tile_nrows;
   a.slot_stride = p.slot_stride;
   hipLaunchKernelGGL(lz_axpy_kernel, dim3(p.grid_tiles), dim3(kThreads), 0, st, a);
   return hipGetLastError();
@@ -985,8 +1383,8 @@ __global__ __launch_bounds__(kThreads) void lz_next_kernel(const LzArgs a, doubl
   if (tile >= a.n_tiles) return;
   const UnitDev U = a.units[a.tile_unit[tile]];
   const ProbDev P = a.probs[U.prob];
-  const int64_t row0 = (int64_t)(tile - U.tile0) * a.tile_rows;
-  const int64_t row1 = min(row0 + a.tile_rows, P.dim);
+  const int64_t row0 = a.tile_row0[tile];
+  const int64_t row1 = row0 + a.tile_nrows[tile];
   const double b2 = beta2[U.col_off];
   if (!(b2 > 1e-24)) return;
   const double inv = 1.0 / sqrt(b2);
@@ -1007,7 +1405,8 @@ hipError_t launch_lz_next(const DevicePlan& p, double* qprev, double* q, const d
   a.tile_unit = p.tile_unit;
   a.n_tiles = p.n_tiles;
   a.grid_tiles = p.grid_tiles;
-  a.tile_rows = p.sub_rows * p.sub_per_tile;
+  a.tile_row0 = p.tile_row0;
+  a.tile_nrows = p.tile_nrows;
   a.slot_stride = p.slot_stride;
   hipLaunchKernelGGL(lz_next_kernel, dim3(p.grid_tiles), dim3(kThreads), 0, st, a, qprev, q, w,
                      beta2);

@@ -131,14 +131,16 @@ def test_autograd_functions_compose(kpm):
     np.testing.assert_allclose(J.grad.numpy(), want, rtol=1e-10, atol=1e-12 * np.abs(want).max())
 
 
-@pytest.mark.parametrize("t_lo,h", [(0.1, 1e-5), (0.05, 1e-4)])
-def test_j1j2_n20_full_size_vs_finite_differences(kpm, t_lo, h):
+@pytest.mark.parametrize("t_lo,h,points", [(0.1, 1e-5, 2), (0.05, 4e-4, 4)])
+def test_j1j2_n20_full_size_vs_finite_differences(kpm, t_lo, h, points):
     """J1-J2 chain N=20 (40 bonds), S^z=0 (dim 184,756), M=1000, R=16 Rademacher,
     loss sum_T C(T) over 64 log-spaced T in [t_lo, 5], checkpoints every 64
-    steps; three bonds against central differences.  On T in [0.05, 5] the
-    difference quotient at h = 1e-5 is limited by roundoff (C at T = 0.05
-    amplifies the moments' rounding by ~1e5; measured spread 2e-4), so that band
-    is checked at the step minimising the quotient's error (h = 1e-4)."""
+    steps; four bonds against finite differences.  On T in [0.1, 5] a central
+    difference at h = 1e-5.  On T in [0.05, 5] C at T = 0.05 amplifies the
+    moments' rounding so much that the quotient's error is ~1e-5 max|g| at any
+    h in [2e-5, 4e-4] with no trend in h (roundoff, not truncation); that band
+    uses the four-point stencil (error O(h^4)) at h = 4e-4, where the roundoff
+    term is smallest."""
     wl = W.j1j2_grad_workload()
     secs = wl.problems
     cl = secs[0].cluster
@@ -149,15 +151,19 @@ def test_j1j2_n20_full_size_vs_finite_differences(kpm, t_lo, h):
     L, dJ, _ = kpm.thermo_grad(secs, wl.M, wl.R, T, wC, wX, kernel="none", ckpt_every=64, bounds=bl)
     g = dJ.cpu().numpy()
     assert g.shape == (40,)
+
+    def loss(b, dh):
+        J = cl.J.copy()
+        J[b] += dh
+        Lh, _, _ = kpm.thermo_grad([W.Sector(cl.with_J(J), secs[0].n_up, 0)], wl.M, wl.R, T, wC, wX,
+                                   kernel="none", ckpt_every=64, bounds=bl)
+        return Lh.item()
+
     for b in (0, 7, 26, 33):
-        vals = []
-        for sgn in (1, -1):
-            J = cl.J.copy()
-            J[b] += sgn * h
-            Lh, _, _ = kpm.thermo_grad([W.Sector(cl.with_J(J), secs[0].n_up, 0)], wl.M, wl.R, T, wC, wX,
-                                       kernel="none", ckpt_every=64, bounds=bl)
-            vals.append(Lh.item())
-        fd = (vals[0] - vals[1]) / (2 * h)
+        if points == 2:
+            fd = (loss(b, h) - loss(b, -h)) / (2 * h)
+        else:
+            fd = (8 * (loss(b, h) - loss(b, -h)) - (loss(b, 2 * h) - loss(b, -2 * h))) / (12 * h)
         # relative to the gradient's scale: bonds whose derivative is ~500x
         # smaller than the rest carry the same absolute quotient noise
         assert abs(g[b] - fd) <= 1e-5 * np.abs(g).max(), (b, g[b], fd)

@@ -1,0 +1,119 @@
+"""Every step kernel (column-chunk, row, block) against the oracle on the same
+seeds and bounds, including block geometries that force many small tiles,
+several blocks per tile and clusters smaller than the block width.
+
+Tolerances as in the moments tests: |mu_gpu - mu_oracle| <= tol * mu_0 with
+tol = 1e-10 (float64 vectors) and 1e-5 (float32 storage)."""
+import functools
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import hamiltonian, moments
+
+pytestmark = pytest.mark.gpu
+
+KERNELS = {
+    "chunk": ({"KPM_BLOCK": "0", "KPM_ROW_KERNEL": "0"}, 0),
+    "row": ({"KPM_BLOCK": "0", "KPM_ROW_KERNEL": "1"}, None),
+    "block": ({"KPM_BLOCK": "1"}, 2),
+    # 64-row sub-tiles (low words of 7 bits), at most 2 blocks per tile, 3
+    # sub-tiles per workgroup, 8 gathers in flight
+    "block_small": ({"KPM_BLOCK": "1", "KPM_BLOCK_ROWS": "64", "KPM_BLOCK_MAX": "2",
+                     "KPM_SUB_PER_TILE": "3", "KPM_GATHER_BATCH": "8"}, 2),
+    # 4 low bits: most bonds are high-high or mixed
+    "block_l4": ({"KPM_BLOCK": "1", "KPM_BLOCK_L": "4", "KPM_SUB_PER_TILE": "1"}, 2),
+}
+
+
+_BOUNDS = {}
+
+
+def _bounds(sec):
+    key = (id(sec.cluster), sec.n_up)
+    if key in _BOUNDS:
+        return _BOUNDS[key][1:]
+    H = hamiltonian.sector_hamiltonian(sec.cluster, sec.n_up)
+    if H.shape[0] <= 1000:
+        e = np.linalg.eigvalsh(H.toarray())
+        lo, hi = e.min(), e.max()
+    else:
+        lo, hi = moments.spectral_bounds(sec, 80, 0.02, 0, H=H)
+    if hi - lo < 1e-8:
+        lo, hi = lo - 0.5, hi + 0.5
+    _BOUNDS[key] = (sec.cluster, (lo, hi), H)   # the cluster keeps its id valid
+    return (lo, hi), H
+
+
+def _check(kpm, monkeypatch, kernel, secs, M, R, kind, precision, col_block, seed=0, eps=0.025):
+    env, kid = KERNELS[kernel]
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    bl, Hs = zip(*[_bounds(s) for s in secs])
+    mu, _ = kpm.chebyshev_moments(secs, M, R, kind, precision, eps, seed, col_block, bounds=list(bl))
+    st = kpm.last_run_stats()
+    if kid is not None:
+        assert st["kernel"] == kid, st
+    mu = mu.cpu().numpy()
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    for p, (s, (lo, hi), H) in enumerate(zip(secs, bl, Hs)):
+        a, b = hamiltonian.scale_from_bounds(lo, hi, eps)
+        want = moments.sector_moments(s, a, b, M, R, kind, seed, H=H)
+        err = np.abs(mu[p] - want).max() / abs(want[0])
+        assert err <= tol, (kernel, p, s.n_up, err)
+    return mu
+
+
+@functools.lru_cache(None)
+def _batched():
+    secs = []
+    for cid, cl in enumerate([W.ring(8), W.random_regular_cluster(11, 3, 2, J_range=(0.5, 1.5)),
+                              W.j1j2_chain(14, 1.0, 0.5), W.ladder(12)]):
+        secs += W.sectors(cl, cluster_id=cid)
+    return tuple(secs)
+
+
+@pytest.mark.parametrize("kernel", list(KERNELS))
+@pytest.mark.parametrize("precision,kind,R,col_block", [
+    ("fp64", "rademacher", 5, 0), ("fp64", "complex_gaussian", 3, 4), ("fp32", "rademacher", 12, 0),
+    ("fp32", "complex_gaussian", 10, 20)])
+def test_batched_all_sectors(kpm, monkeypatch, kernel, precision, kind, R, col_block):
+    """Four clusters (N = 8, 11, 14, 12), all S^z >= 0 sectors, one call."""
+    _check(kpm, monkeypatch, kernel, list(_batched()), 48, R, kind, precision, col_block, seed=4)
+
+
+@pytest.mark.parametrize("kernel", list(KERNELS))
+def test_j1j2_n18_sz0_wide_block(kpm, monkeypatch, kernel):
+    """N=18 J1-J2 chain S^z=0 (48,620 states: hundreds of tiles), 20 float32
+    columns in one block."""
+    secs = W.sectors(W.j1j2_chain(18, 1.0, 0.5), only_sz0=True)
+    _check(kpm, monkeypatch, kernel, secs, 40, 10, "complex_gaussian", "fp32", 20, seed=2)
+
+
+@pytest.mark.parametrize("kernel", ["block", "block_small", "block_l4"])
+def test_block_extreme_sectors(kpm, monkeypatch, kernel):
+    """Sectors whose blocks are tiny (n_up near N) or single (N below the
+    block width), dimension-1 sectors and the dimer."""
+    cl = W.ring(16)
+    secs = [W.Sector(cl, k, 0) for k in (16, 15, 14, 13)] + W.sectors(W.ring(5), cluster_id=1)
+    secs += [W.Sector(W.dimer(), 1, 2), W.Sector(W.dimer(), 2, 2)]
+    for prec in ("fp64", "fp32"):
+        _check(kpm, monkeypatch, kernel, secs, 24, 3, "rademacher", prec, 0, seed=9)
+
+
+def test_kernels_agree_ring20(kpm, monkeypatch):
+    """Ring N=20 S^z=0 (184,756 states), float64, 8 columns: every kernel's
+    moments agree to rounding (they sum the bonds in different orders)."""
+    secs = W.sectors(W.ring(20), only_sz0=True)
+    bl = [(-9.2, 5.1)]
+    out = {}
+    for name, (env, _) in KERNELS.items():
+        with monkeypatch.context() as m:
+            for k, v in env.items():
+                m.setenv(k, v)
+            mu, _ = kpm.chebyshev_moments(secs, 200, 8, "rademacher", "fp64", 0.025, 1, 8, bounds=bl)
+            out[name] = mu.cpu().numpy()[0]
+    ref = out["chunk"]
+    for name, mu in out.items():
+        assert np.abs(mu - ref).max() <= 1e-11 * ref[0], name
