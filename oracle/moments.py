@@ -125,7 +125,12 @@ def spectral_bounds(sector, steps: int = 50, margin: float = 0.01, seed: int = 0
     side; a (near-)degenerate window is widened to E -/+ 1/2."""
     if H is None:
         H = hamiltonian.sector_hamiltonian(sector.cluster, sector.n_up)
-    v0 = rng.rademacher(seed, sector.cluster_id, sector.n_up, rng.LANCZOS_STREAM, H.shape[0])
+    # real Gaussian start (Box-Muller, stream r = 1023): a +-1 vector can be
+    # exactly orthogonal to an extreme eigenvector (e.g. the uniform one-magnon
+    # state of an N = 18, n_up = 17 sector when half the signs are +1), which
+    # leaves that eigenvalue out of the Krylov space; a Gaussian one is
+    # orthogonal with probability zero
+    v0, _ = rng.box_muller(seed, sector.cluster_id, sector.n_up, rng.LANCZOS_STREAM, H.shape[0])
     lo, hi = lanczos_extremes(H, v0, steps)
     W = hi - lo
     if W < 1e-8 * max(1.0, abs(lo), abs(hi)):

@@ -142,3 +142,21 @@ def test_fp32_storage_close_to_fp64():
     m32 = moments.sector_moments(s, a, b, 512, 4, "rademacher", 0, H=H, store=np.float32)
     d = np.abs(m32 - m64).max() / m64[0]
     assert 1e-12 < d < 1e-6
+
+
+def test_lanczos_bounds_enclose_symmetric_one_magnon_sectors():
+    """Regression: in the n_up = N-1 sectors of the 64-cluster workload the top
+    eigenvector is the uniform one-magnon state; a +-1 start vector with equal
+    numbers of signs is orthogonal to it.  The Gaussian start must still find
+    the exact extremes (steps >= dim: the Krylov space is the whole sector)."""
+    import workloads as W
+    from oracle import hamiltonian
+    cls = W.batched_clusters()
+    # cluster 24 (N = 18): its n_up = 17 start vector has nine +1 and nine -1
+    for cid in (24, 0, 1, 2):
+        cl = cls[cid]
+        for n_up in (cl.n_sites - 1, cl.n_sites - 2):
+            s = W.Sector(cl, n_up, cid)
+            e = np.linalg.eigvalsh(hamiltonian.sector_hamiltonian(cl, n_up).toarray())
+            lo, hi = moments.spectral_bounds(s, 50, 0.01, 0)
+            assert lo <= e.min() and hi >= e.max(), (cid, n_up, lo, hi, e.min(), e.max())
