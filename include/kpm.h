@@ -119,7 +119,8 @@ int kpm_sector_matrix(const kpm_problem* p, int64_t row0, int64_t nrows, int32_t
 
 /* Spectral bounds for Eq. (5) (the paper estimates the ground state with
  * Lanczos, Sec. III.A.2.b): `steps` steps of float64 Lanczos without
- * reorthogonalisation from the Rademacher vector of RNG stream r = 1023,
+ * reorthogonalisation from the unit-norm real Gaussian vector of RNG stream
+ * r = 1023 (a +-1 start can be exactly orthogonal to an extreme eigenvector),
  * stopping early when an off-diagonal falls below 1e-12; the extreme Ritz
  * values are widened by margin*(width) on each side (a window narrower than
  * 1e-8 max(1,|E|) is widened to E -/+ 1/2).  e_lo_hi: host double [n][2]. */
@@ -143,9 +144,26 @@ int chebyshev_moments(const kpm_problem* p, int32_t n, const kpm_params* q,
                       double* d_mu, double* d_ab, void* d_work, size_t work_bytes,
                       void* stream);
 
+/* Workspace bytes for chebyshev_vectors (0 if the arguments are invalid). */
+size_t chebyshev_vectors_workspace_size(const kpm_problem* p, const kpm_params* q,
+                                        int32_t n_vec);
+
+/* The Chebyshev vectors behind Eq. (6) for ONE problem: v_0 = the random
+ * vectors of chebyshev_moments (same seeds and normalisation), v_1 = H' v_0,
+ * v_{n+1} = 2 H' v_n - v_{n-1}; returns v_{n_vec} computed by the same plan
+ * and step kernels as chebyshev_moments (q->M is ignored).
+ *  d_out device [dim][R_cols] row-major, R_cols = R (x2 for complex vectors,
+ *        Re and Im adjacent; C(N, n_up) for the complete basis), float for
+ *        KPM_FP32_STORE, double for KPM_FP64
+ *  d_ab  device double [2] = (a, b), may be NULL
+ * Errors: KPM_EINVAL (arguments), KPM_EWORKSPACE (work_bytes too small),
+ * KPM_EDEVICE (HIP error or a neighbour rank outside the sector). */
+int chebyshev_vectors(const kpm_problem* p, const kpm_params* q, int32_t n_vec, void* d_out,
+                      double* d_ab, void* d_work, size_t work_bytes, void* stream);
+
 /* Thermodynamics from moments (Sec. II): kernel g_n (Eq. (8)), DOS weights
- * gamma_k at the n_nodes Gauss-Chebyshev nodes (0 => M; n_nodes >= M/2 ... any
- * n_nodes >= 1 is accepted), and per cluster c and temperature T (k_B = 1,
+ * gamma_k at the n_nodes Gauss-Chebyshev nodes (0 => M; any n_nodes >= 1 is
+ * accepted), and per cluster c and temperature T (k_B = 1,
  * g mu_B = 1):
  *   Z   = (1/n_nodes) sum_sectors W sum_k gamma_k exp(-E_k/T),  E_k = a x_k + b,
  *   E   = <E>,  C = (<E^2> - <E>^2)/T^2,  chi = (<S_z^2> - <S_z>^2)/T,

@@ -573,7 +573,7 @@ struct DevBuf {
 // ------------------------------------------------------------- Lanczos bounds
 
 struct LzLayout {
-  size_t plan, vec, vecC, part, dots, b2, zero, err, states, total;
+  size_t plan, vec, vecC, part, dots, b2, zero, norm, err, states, total;
 };
 
 LzLayout lanczos_layout(const Planned& P, int steps) {
@@ -591,6 +591,7 @@ LzLayout lanczos_layout(const Planned& P, int steps) {
   L.dots = put((size_t)steps * P.plan.total_cols * 8);
   L.b2 = put((size_t)steps * P.plan.total_cols * 8);
   L.zero = put((size_t)P.plan.total_cols * 8);
+  L.norm = put((size_t)P.plan.total_cols * 8);
   L.err = put(256);
   L.states = put((size_t)P.plan.n_states * 4);
   L.total = o;
@@ -680,7 +681,11 @@ int run_lanczos(const kpm_problem* p, int n, int steps, double margin, uint64_t 
   KPM_HIP(hipMemsetAsync(vec, 0, (size_t)D.vec_elems * 8, st));
   KPM_HIP(hipMemsetAsync(vecC, 0, (size_t)D.vec_elems * 8, st));
   KPM_HIP(hipMemsetAsync(zero, 0, (size_t)TC * 8, st));
-  KPM_HIP(launch_init(D, vec, 2, KPM_VEC_RADEMACHER, seed, nullptr, part, st));
+  // unit-norm real Gaussian start vector (RNG stream r = 1023)
+  double* norm = reinterpret_cast<double*>(work + L.norm);
+  KPM_HIP(launch_init(D, vec, 0, KPM_VEC_GAUSSIAN, seed, nullptr, part, st));
+  KPM_HIP(launch_reduce(D, part, norm, nullptr, st));
+  KPM_HIP(launch_init(D, vec, 2, KPM_VEC_GAUSSIAN, seed, norm, part, st));
   for (int j = 0; j < nsteps; ++j) {
     // w = H q_j  (A -> B; a = 1, b = 0 so H' = H)
     KPM_HIP(launch_step(D, vec, part, nullptr, 0, nullptr, nullptr, nullptr, 0, 0, 1, st));
@@ -903,6 +908,46 @@ int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
   g_stats.recursion_ms = hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess ? (double)ms : -1.0;
   if (h_flag & 2) return KPM_EDEVICE;
   return (h_flag & 1) ? KPM_EBOUNDS : KPM_OK;
+}
+
+// Init and n recursion steps of one problem (the steps chebyshev_moments
+// launches, without the dots' reduction), then v_n to d_out.
+int run_vectors(Planned& P, const MomLayout& L, unsigned char* work, const kpm_params& q, int nv,
+                void* d_out, hipStream_t st) {
+  DevicePlan& D = P.plan;
+  void* vec = work + L.vec;
+  double* part[2] = {reinterpret_cast<double*>(work + L.part0),
+                     reinterpret_cast<double*>(work + L.part1)};
+  double* norms = reinterpret_cast<double*>(work + L.norms);
+  int* flag = reinterpret_cast<int*>(work + L.flag);
+  P.plan.err = flag;
+  P.plan.states = reinterpret_cast<uint32_t*>(work + L.states);
+  KPM_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+  if (D.row_ld || D.block) KPM_HIP(fill_states(D, st));
+  if (q.vec_kind == KPM_VEC_GAUSSIAN || q.vec_kind == KPM_VEC_COMPLEX_GAUSSIAN) {
+    KPM_HIP(launch_init(D, vec, 0, q.vec_kind, q.seed, nullptr, part[0], st));
+    KPM_HIP(launch_reduce(D, part[0], norms, nullptr, st));
+  }
+  KPM_HIP(launch_init(D, vec, 1, q.vec_kind, q.seed, norms, part[0], st));
+  for (int s = 0; s < nv; ++s)
+    KPM_HIP(launch_step(D, vec, part[s & 1], nullptr, 0, nullptr, nullptr, nullptr, s, s & 1,
+                        s == 0 ? 1 : 0, st));
+  ExportArgs ea{};
+  ea.units = D.units;
+  ea.vec = vec;
+  ea.slot_stride = D.slot_stride;
+  ea.slot = nv & 1;
+  ea.unit0 = 0;
+  ea.rb = P.units[0].ncols;
+  ea.n_cols = 0;
+  for (auto& u : P.units) ea.n_cols += u.ncols;
+  ea.dim = P.probs[0].dim;
+  ea.out = d_out;
+  KPM_HIP(launch_export(ea, D.fp32, st));
+  int h_flag = 0;
+  KPM_HIP(hipMemcpyAsync(&h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  KPM_HIP(hipStreamSynchronize(st));
+  return (h_flag & 6) ? KPM_EDEVICE : KPM_OK;
 }
 
 // Resolve bounds (Lanczos where NaN) and the (a, b) of Eq. (5).
@@ -1369,6 +1414,58 @@ int chebyshev_moments(const kpm_problem* p, int32_t n, const kpm_params* q, doub
   }
   if (d_ab) KPM_HIP(hipMemcpyAsync(d_ab, ab.data(), ab.size() * 8, hipMemcpyHostToDevice, st));
   return run_moments(P, L, work, *q, d_mu, st);
+}
+
+static kpm_params vectors_params(const kpm_params& q, int32_t n_vec) {
+  kpm_params q2 = q;
+  q2.M = std::max(2, 2 * n_vec);
+  return q2;
+}
+
+size_t chebyshev_vectors_workspace_size(const kpm_problem* p, const kpm_params* q, int32_t n_vec) {
+  if (check_problems(p, 1) != KPM_OK || !q || n_vec < 0) return 0;
+  const kpm_params q2 = vectors_params(*q, n_vec);
+  if (check_params(q2) != KPM_OK) return 0;
+  return moments_workspace(p, 1, q2);
+}
+
+int chebyshev_vectors(const kpm_problem* p, const kpm_params* q, int32_t n_vec, void* d_out,
+                      double* d_ab, void* d_work, size_t work_bytes, void* stream) {
+  int r = check_problems(p, 1);
+  if (r != KPM_OK) return r;
+  if (!q || n_vec < 0 || !d_out) return KPM_EINVAL;
+  const kpm_params q2 = vectors_params(*q, n_vec);
+  if (check_params(q2) != KPM_OK) return KPM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StreamSync guard{st};
+  const size_t need = moments_workspace(p, 1, q2);
+  if (need == 0) return KPM_EINVAL;
+  DevBuf own;
+  unsigned char* work = static_cast<unsigned char*>(d_work);
+  if (!work) {
+    r = own.alloc(need);
+    if (r != KPM_OK) return r;
+    work = static_cast<unsigned char*>(own.p);
+  } else if (work_bytes < need) {
+    return KPM_EWORKSPACE;
+  }
+  Planned P0;
+  r = make_plan(p, 1, shape_of(q2), nullptr, nullptr, P0);
+  if (r != KPM_OK) return r;
+  const MomLayout L0 = moments_layout(P0, n_steps(q2.M), 0);
+  std::vector<double> a, b;
+  r = resolve_scale(p, 1, q2, work + L0.lz, st, a, b);
+  if (r != KPM_OK) return r;
+  Planned P;
+  r = make_plan(p, 1, shape_of(q2), a.data(), b.data(), P);
+  if (r != KPM_OK) return r;
+  const MomLayout L = moments_layout(P, n_steps(q2.M), 0);
+  std::vector<unsigned char> staging;
+  r = upload_plan(P, work + L.plan, staging, st);
+  if (r != KPM_OK) return r;
+  const double ab[2] = {a[0], b[0]};
+  if (d_ab) KPM_HIP(hipMemcpyAsync(d_ab, ab, sizeof(ab), hipMemcpyHostToDevice, st));
+  return run_vectors(P, L, work, q2, n_vec, d_out, st);
 }
 
 int kpm_thermo(const double* d_mu, const double* d_ab, const kpm_problem* p, int32_t n,

@@ -144,10 +144,10 @@ struct InitArgs {
   const int64_t* tile_row0;
   const int32_t* tile_nrows;
   void* vec;                 // slot 0 is written
-  const double* norms;   // per column: Gaussian sums of squares (mode 1)
+  const double* norms;   // per column: Gaussian sums of squares (modes 1, 2)
   double* part_out;
   uint64_t seed;
-  int32_t n_tiles, grid_tiles, mode, vec_kind;
+  int32_t n_tiles, grid_tiles, mode, vec_kind;   // mode 0 sums of squares, 1 write, 2 unit-norm
 };
 
 struct FinalArgs {
@@ -293,6 +293,16 @@ hipError_t launch_init(const DevicePlan& p, void* vec, int mode, int vec_kind, u
                        const double* norms, double* part_out, hipStream_t st);
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t st);
 hipError_t launch_set_i64(int64_t* dst, int64_t v, hipStream_t st);
+
+struct ExportArgs {
+  const UnitDev* units;
+  const void* vec;       // vector storage base
+  int64_t slot_stride;
+  int32_t slot, unit0, rb, n_cols;
+  int64_t dim;
+  void* out;             // [dim][n_cols], storage type
+};
+hipError_t launch_export(const ExportArgs& a, int fp32, hipStream_t st);
 hipError_t launch_states(int N, int k, const uint32_t* binom, uint32_t* out, int64_t dim,
                          hipStream_t st);
 // Basis words of every sector of the plan into p.states.

@@ -1168,7 +1168,7 @@ __global__ __launch_bounds__(kThreads) void init_kernel(const InitArgs a) {
   const int64_t row1 = row0 + a.tile_nrows[tile];
   T* A = reinterpret_cast<T*>(a.vec) + U.vec_off;
   double scale = 1.0;
-  if (a.mode == 2) scale = 1.0 / sqrt((double)P.dim);   // unit-norm Lanczos start
+  if (a.mode == 2 && c < U.ncols) scale = 1.0 / sqrt(a.norms[U.col_off + c]);   // unit-norm Lanczos start
   if (a.mode == 1 && (a.vec_kind == 1 || a.vec_kind == 2) && c < U.ncols) {
     double n2 = a.norms[U.col_off + c];
     if (a.vec_kind == 1) {
@@ -1269,6 +1269,32 @@ hipError_t launch_finalize(const FinalArgs& a, hipStream_t st) {
   const int64_t n = (int64_t)a.n_probs * a.M;
   const int grid = (int)((n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(finalize_kernel, dim3(grid), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------- vector export
+
+// out[row][col] (row-major, n_cols wide) from slot `slot` of the blocks
+// unit0, unit0 + 1, ... of one problem (block k holds columns [k*rb, ...)).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void export_kernel(const ExportArgs a) {
+  const T* base = reinterpret_cast<const T*>(a.vec) + (int64_t)a.slot * a.slot_stride;
+  T* out = reinterpret_cast<T*>(a.out);
+  const int64_t total = a.dim * a.n_cols;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * kThreads) {
+    const int64_t row = e / a.n_cols;
+    const int col = (int)(e - row * a.n_cols);
+    const UnitDev U = a.units[a.unit0 + col / a.rb];
+    out[e] = base[U.vec_off + row * U.ld + (col % a.rb)];
+  }
+}
+
+hipError_t launch_export(const ExportArgs& a, int fp32, hipStream_t st) {
+  const int64_t total = a.dim * a.n_cols;
+  const int grid = (int)std::min<int64_t>((total + kThreads - 1) / kThreads, 1 << 16);
+  if (fp32) hipLaunchKernelGGL(export_kernel<float>, dim3(grid), dim3(kThreads), 0, st, a);
+  else hipLaunchKernelGGL(export_kernel<double>, dim3(grid), dim3(kThreads), 0, st, a);
   return hipGetLastError();
 }
 

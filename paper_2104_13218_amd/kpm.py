@@ -60,6 +60,9 @@ _SIGS = {
     "chebyshev_moments_workspace_size": (c_size_t, [POINTER(Problem), c_int32, POINTER(Params)]),
     "chebyshev_moments": (c_int32, [POINTER(Problem), c_int32, POINTER(Params), c_void_p, c_void_p,
                                     c_void_p, c_size_t, c_void_p]),
+    "chebyshev_vectors_workspace_size": (c_size_t, [POINTER(Problem), POINTER(Params), c_int32]),
+    "chebyshev_vectors": (c_int32, [POINTER(Problem), POINTER(Params), c_int32, c_void_p, c_void_p,
+                                    c_void_p, c_size_t, c_void_p]),
     "kpm_thermo": (c_int32, [c_void_p, c_void_p, POINTER(Problem), c_int32, c_int32, c_int32, c_int32,
                              c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                              c_void_p]),
@@ -199,6 +202,26 @@ def chebyshev_moments(sectors, M, R=1, vec_kind="rademacher", precision="fp64", 
     _check(load().chebyshev_moments(ps.arr, len(ps), ctypes.byref(q), _ptr(mu), _ptr(ab), _ptr(workspace),
                                     workspace.numel(), _stream(stream)), "chebyshev_moments")
     return mu, ab
+
+
+def chebyshev_vectors(sector, n_vec, R=1, vec_kind="rademacher", precision="fp64", eps=0.025, seed=0,
+                      col_block=0, bounds=None, lanczos_steps=50, margin=0.01, stream=None):
+    """v_{n_vec} of one sector, [dim, real columns] (float32 for "fp32"
+    storage, else float64, cuda), and (a, b) [2]."""
+    ps = ProblemSet([sector], None if bounds is None else [bounds])
+    q = make_params(max(2, 2 * n_vec), R, vec_kind, precision, eps, seed, col_block, lanczos_steps, margin)
+    ncols = sector.dim if vec_kind == "basis" else R * (2 if vec_kind == "complex_gaussian" else 1)
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    out = torch.empty((sector.dim, ncols), dtype=dt, device="cuda")
+    ab = torch.empty(2, dtype=torch.float64, device="cuda")
+    lib = load()
+    nbytes = lib.chebyshev_vectors_workspace_size(ps.arr, ctypes.byref(q), n_vec)
+    if nbytes == 0:
+        raise KPMError(KPM_EINVAL, "chebyshev_vectors_workspace_size")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    _check(lib.chebyshev_vectors(ps.arr, ctypes.byref(q), n_vec, _ptr(out), _ptr(ab), _ptr(ws), ws.numel(),
+                                 _stream(stream)), "chebyshev_vectors")
+    return out, ab
 
 
 def thermo(mu, ab, sectors, T, kernel="jackson", n_nodes=0, stream=None):
