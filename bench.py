@@ -37,8 +37,9 @@ if ROOT not in sys.path:
 
 METRIC = "Chebyshev steps·dim/s + HBM GB/s at N=24 S^z=0; speedup vs FP64 at C(T) err"
 HBM_PEAK_GBS = 8000.0
-STEP_KERNEL = "step_kernel<float, 4>"
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "step_kernel_ring24_sz0_fp32_traffic.json")
+# step kernel families as reported by kpm_last_run_stats()["kernel"]
+KERNEL_FAMILY = {0: "step_kernel", 1: "row_kernel", 2: "block_kernel"}
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def _parse():
@@ -56,11 +57,13 @@ def _parse():
     return ap.parse_args()
 
 
-def _traffic(bytes_per_launch):
+def _traffic(family):
     """Measured HBM bytes per step launch from the committed rocprofv3 counter
-    summary, when it was taken on the current kernel source."""
+    summary of this kernel on this workload, when it was taken on the current
+    kernel source."""
+    path = os.path.join(PROFILES, f"{family}_ring24_sz0_fp32_traffic.json")
     try:
-        with open(PROFILE_TRAFFIC) as f:
+        with open(path) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
@@ -124,7 +127,8 @@ def main():
     value = st["state_col_steps"] / dt
     avg_launch_s = sum(s["recursion_ms"] for s in stats) / len(stats) / 1e3 / st["step_launches"]
     achieved = st["bytes_per_launch"] / avg_launch_s / 1e9
-    traffic = _traffic(st["bytes_per_launch"])
+    family = KERNEL_FAMILY.get(st["kernel"], "step_kernel")
+    traffic = _traffic(family)
     line = {
         "metric": METRIC, "value": value, "unit": "state-column-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
@@ -134,7 +138,7 @@ def main():
                    "bounds": "lanczos50+1%", "storage": "f32", "col_block": st["col_block"],
                    "rows_per_tile": st["rows_per_tile"], "graph_segment": st["graph_segment"],
                    "device": dev},
-        "roofline": {"bound": "hbm", "kernel": STEP_KERNEL, "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": family, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "algorithmic_bytes_per_launch": st["bytes_per_launch"],
                      "avg_launch_us": avg_launch_s * 1e6,
