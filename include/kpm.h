@@ -92,6 +92,13 @@ typedef struct {
   uint64_t seed;         /* counter-RNG seed */
   int32_t lanczos_steps; /* Lanczos steps for NaN bounds (0 => 50) */
   double bound_margin;   /* widening of Lanczos bounds, fraction of the width (>= 0) */
+  int32_t autotune;      /* 0: the planner's launch shape; 1: chebyshev_moments times a few
+                            recursion steps of each candidate shape (block width, step
+                            kernel, tile shape, gathers in flight) the first time a
+                            problem shape is seen on a device and reuses the fastest
+                            (process-wide cache, mutex-guarded).  Results then differ
+                            from the untuned plan by rounding only (other summation
+                            order); the workspace query covers every candidate. */
 } kpm_params;
 
 /* Human-readable name of a status code (static string). */
@@ -220,6 +227,9 @@ typedef struct {
                               to the last recursion-step launch, inclusive */
 } kpm_run_stats;
 int kpm_last_run_stats(kpm_run_stats* out);
+
+/* Forget every autotuned launch shape (the next autotuned call measures again). */
+int kpm_autotune_reset(void);
 
 #ifdef __cplusplus
 }

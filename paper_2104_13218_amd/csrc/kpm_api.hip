@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "kpm.h"
@@ -127,6 +129,7 @@ int check_params(const kpm_params& q) {
   if (q.col_block < 0 || q.col_block > kMaxLd) return KPM_EINVAL;
   if (q.lanczos_steps < 0 || q.lanczos_steps > 100000) return KPM_EINVAL;
   if (!(q.bound_margin >= 0.0) || !std::isfinite(q.bound_margin)) return KPM_EINVAL;
+  if (q.autotune != 0 && q.autotune != 1) return KPM_EINVAL;
   return KPM_OK;
 }
 
@@ -143,7 +146,18 @@ size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 // ------------------------------------------------------------------ planning
 
+// Launch shape chosen by the autotuner (0 / -1 = the planner's heuristic);
+// KPM_* environment variables, when set, override both.
+struct Tune {
+  int kernel = -1;        // -1 heuristic, 0 column-chunk, 1 row, 2 block
+  int col_block = 0;      // real columns per block
+  int block_L = 0;        // low bits of a block (block kernel)
+  int spt = 0;            // sub-tiles per workgroup (block kernel) / tiles' sub-tiles
+  int gather_batch = 0;   // neighbour rows in flight per lane
+};
+
 struct RunShape {
+  Tune tune;
   int precision = KPM_FP64;
   int vec_kind = KPM_VEC_RADEMACHER;
   int R = 1;
@@ -190,7 +204,8 @@ int pick_col_block(const kpm_problem* p, int n, const RunShape& s) {
   const int cpv = cols_per_vec(s.vec_kind);
   int64_t maxc = 1;
   for (int i = 0; i < n; ++i) maxc = std::max<int64_t>(maxc, total_columns(p[i], s));
-  int rb = s.col_block > 0 ? s.col_block : (s.precision == KPM_FP32_STORE ? 32 : 16);
+  int rb = s.col_block > 0 ? s.col_block
+                          : (s.tune.col_block > 0 ? s.tune.col_block : (s.precision == KPM_FP32_STORE ? 32 : 16));
   rb = (int)std::min<int64_t>(rb, maxc);
   rb = (rb + cpv - 1) / cpv * cpv;
   return std::min(rb, kMaxLd);
@@ -245,7 +260,8 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   const int elt = fp32 ? 4 : 8;
   // One lane per state (row kernel) when the block width has an instantiation.
   int row_ld = 0;
-  if (!s.adjoint && s.allow_row && env_int("KPM_ROW_KERNEL", 1))
+  const int kern = s.tune.kernel;
+  if (!s.adjoint && s.allow_row && env_int("KPM_ROW_KERNEL", kern < 0 || kern == 1 ? 1 : 0))
     for (int L : {1, 2, 4, 8})
       if (L >= rb) {
         row_ld = L;
@@ -325,7 +341,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   std::vector<std::vector<int32_t>> btile_nrows(n);
   // Default: float32 storage with blocks too wide for the row kernel (the
   // measured case where it is the fastest kernel); KPM_BLOCK=0/1 overrides.
-  const int block_env = env_int("KPM_BLOCK", -1);
+  const int block_env = env_int("KPM_BLOCK", kern < 0 ? -1 : (kern == 2 ? 1 : 0));
   const bool block_default = fp32 && rb > 8;
   if (!s.adjoint && s.allow_row && (block_env == 1 || (block_env < 0 && block_default))) {
     D.ld_max = adj_ld ? adj_ld : (rb + cpl - 1) / cpl * cpl;
@@ -333,7 +349,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
     const size_t cap = (size_t)env_int("KPM_BLOCK_LDS", 64 * 1024);
     for (int rows = std::min(kThreads, std::max(32, env_int("KPM_BLOCK_ROWS", kThreads)));
          rows >= 32 && !D.block; rows >>= 1) {
-      int Lm = std::max(1, std::min(env_int("KPM_BLOCK_L", 10), 16));
+      int Lm = std::max(1, std::min(env_int("KPM_BLOCK_L", s.tune.block_L > 0 ? s.tune.block_L : 9), 16));
       while (Lm > 1 && binom64(Lm, Lm / 2) > (uint64_t)rows) --Lm;
       int lr = 1, hh = 1, mx = 1;
       for (int i = 0; i < n; ++i) {
@@ -368,6 +384,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   if (D.block) D.row_ld = row_ld = 0;
   // Neighbour rows in flight per lane: row kernel 2/4/8, others 4/8.
   D.gather_batch = (row_ld == 4 || row_ld == 8) ? 2 : 4;
+  if (s.tune.gather_batch > 0) D.gather_batch = s.tune.gather_batch;
   if (const int f = env_int("KPM_GATHER_BATCH", 0)) D.gather_batch = f;
   if (D.gather_batch != 2 && D.gather_batch != 4 && D.gather_batch != 8) D.gather_batch = 4;
   if (!row_ld && D.gather_batch < 4) D.gather_batch = 4;
@@ -397,6 +414,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
     const double per_sub = 3.0 * D.blk_rows * D.ld_max * elt;
     int spt = (int)std::ceil(8.0 * fixed / per_sub);
     spt = (int)std::max<size_t>(1, std::min<size_t>((size_t)spt, std::max<size_t>(1, max_sub / 2048)));
+    if (s.tune.spt > 0) spt = s.tune.spt;
     if (const int f = env_int("KPM_SUB_PER_TILE", 0)) spt = f;
     bspt = std::max(1, std::min(spt, 64));
   }
@@ -410,6 +428,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   const int64_t par = max_dim / (2048LL * D.sub_rows);
   spt = (int)std::max<int64_t>(1, std::min<int64_t>(spt, std::max<int64_t>(1, par)));
   spt = std::min(spt, 64);
+  if (s.tune.spt > 0) spt = s.tune.spt;
   if (const int f = env_int("KPM_SUB_PER_TILE", 0)) spt = f;
   D.sub_per_tile = spt;
   D.xcd_remap = env_int("KPM_XCD_REMAP", 1);
@@ -772,8 +791,9 @@ MomLayout moments_layout(const Planned& P, int K, size_t lz_bytes) {
   return L;
 }
 
-RunShape shape_of(const kpm_params& q) {
+RunShape shape_of(const kpm_params& q, const Tune* t = nullptr) {
   RunShape s;
+  if (t) s.tune = *t;
   s.precision = q.precision;
   s.vec_kind = q.vec_kind;
   s.R = q.R;
@@ -785,6 +805,58 @@ int n_steps(int M) { return std::max(1, M / 2); }
 
 int lanczos_steps_of(const kpm_params& q) { return q.lanczos_steps > 0 ? q.lanczos_steps : 50; }
 
+// ------------------------------------------------------------ autotuning
+//
+// Per device and problem shape (sector sizes, bond counts, precision, vector
+// kind and count) the launch shape of the recursion -- block width, step
+// kernel, low-bit block width, sub-tiles per workgroup, gathers in flight --
+// is chosen by timing a few steps of every candidate the first time the shape
+// is seen, and cached for the process.
+
+std::vector<Tune> tune_candidates(const kpm_problem* p, int n, const kpm_params& q) {
+  const bool fp32 = q.precision == KPM_FP32_STORE;
+  const RunShape s0 = shape_of(q);
+  int64_t maxc = 1;
+  for (int i = 0; i < n; ++i) maxc = std::max<int64_t>(maxc, total_columns(p[i], s0));
+  const int cpv = cols_per_vec(q.vec_kind);
+  std::vector<int> widths;
+  if (q.col_block > 0) {
+    widths.push_back(q.col_block);
+  } else {
+    for (int w : {1, 2, 4, 8, 16, 32, kMaxLd}) {
+      int ww = (int)std::min<int64_t>(w, maxc);
+      ww = (ww + cpv - 1) / cpv * cpv;
+      if (fp32 && ww < 4 && maxc >= 4) continue;
+      if (std::find(widths.begin(), widths.end(), ww) == widths.end()) widths.push_back(ww);
+    }
+  }
+  std::vector<Tune> c;
+  c.push_back(Tune{});                       // the planner's heuristic
+  for (int w : widths) {
+    Tune t;
+    t.col_block = w;
+    if (w <= 8) {
+      t.kernel = 1;
+      c.push_back(t);
+      t.gather_batch = (w >= 4) ? 4 : 2;
+      c.push_back(t);
+      t.gather_batch = 0;
+    }
+    t.kernel = 0;
+    c.push_back(t);
+    if (w >= 4)
+      for (int L : {9, 10})
+        for (int spt : {0, 3}) {
+          Tune b = t;
+          b.kernel = 2;
+          b.block_L = L;
+          b.spt = spt;
+          c.push_back(b);
+        }
+  }
+  return c;
+}
+
 size_t moments_workspace(const kpm_problem* p, int n, const kpm_params& q) {
   std::vector<kpm_problem> need;
   for (int i = 0; i < n; ++i)
@@ -792,7 +864,97 @@ size_t moments_workspace(const kpm_problem* p, int n, const kpm_params& q) {
   const size_t lz = need.empty() ? 0 : lanczos_bytes(need.data(), (int)need.size(), lanczos_steps_of(q));
   Planned P;
   if (make_plan(p, n, shape_of(q), nullptr, nullptr, P) != KPM_OK) return 0;
-  return moments_layout(P, n_steps(q.M), lz).total;
+  size_t total = moments_layout(P, n_steps(q.M), lz).total;
+  if (q.autotune)
+    for (const Tune& t : tune_candidates(p, n, q)) {
+      Planned Pc;
+      if (make_plan(p, n, shape_of(q, &t), nullptr, nullptr, Pc) == KPM_OK)
+        total = std::max(total, moments_layout(Pc, n_steps(q.M), lz).total);
+    }
+  return total;
+}
+
+// Seconds per step of one candidate: plan, Rademacher start, two warm-up and
+// six timed steps (values are irrelevant to the timing).
+double time_candidate(const kpm_problem* p, int n, const kpm_params& q, const Tune& t,
+                      const double* a, const double* b, unsigned char* work, size_t bytes,
+                      hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  Planned P;
+  if (make_plan(p, n, shape_of(q, &t), a, b, P) != KPM_OK) return INFINITY;
+  const MomLayout L = moments_layout(P, 8, 0);
+  if (L.total > bytes) return INFINITY;
+  std::vector<unsigned char> staging;
+  if (upload_plan(P, work + L.plan, staging, st) != KPM_OK) return INFINITY;
+  DevicePlan& D = P.plan;
+  D.err = reinterpret_cast<int*>(work + L.flag);
+  D.states = reinterpret_cast<uint32_t*>(work + L.states);
+  void* vec = work + L.vec;
+  double* part[2] = {reinterpret_cast<double*>(work + L.part0),
+                     reinterpret_cast<double*>(work + L.part1)};
+  bool ok = hipMemsetAsync(D.err, 0, sizeof(int), st) == hipSuccess;
+  if (ok && (D.row_ld || D.block)) ok = fill_states(D, st) == hipSuccess;
+  if (ok) ok = launch_init(D, vec, 1, KPM_VEC_RADEMACHER, q.seed, nullptr, part[0], st) == hipSuccess;
+  const int warm = 3, meas = 6;
+  for (int k = 0; ok && k < warm + meas; ++k) {
+    if (k == warm) ok = hipEventRecord(e0, st) == hipSuccess;
+    if (ok)
+      ok = launch_step(D, vec, part[k & 1], nullptr, 0, nullptr, nullptr, nullptr, k, k & 1,
+                       k == 0 ? 1 : 0, st) == hipSuccess;
+  }
+  if (ok) ok = hipEventRecord(e1, st) == hipSuccess;
+  if (ok) ok = hipEventSynchronize(e1) == hipSuccess;
+  float ms = 0.f;
+  if (ok) ok = hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+  (void)hipStreamSynchronize(st);   // staging outlives its copy
+  return ok ? (double)ms / meas : INFINITY;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, Tune> g_tune_cache;
+
+std::string tune_key(int dev, const kpm_problem* p, int n, const kpm_params& q) {
+  std::string k = std::to_string(dev) + "|" + std::to_string(q.precision) + "," +
+                  std::to_string(q.vec_kind) + "," + std::to_string(q.R) + "," +
+                  std::to_string(q.col_block) + "|";
+  for (int i = 0; i < n; ++i)
+    k += std::to_string(p[i].n_sites) + "." + std::to_string(p[i].n_up) + "." +
+         std::to_string(p[i].n_bonds) + ";";
+  return k;
+}
+
+// The cached or freshly measured launch shape for these problems.  `work`
+// (bytes) is scratch for the trial runs.
+int get_tune(const kpm_problem* p, int n, const kpm_params& q, const double* a, const double* b,
+             unsigned char* work, size_t bytes, hipStream_t st, Tune& out) {
+  int dev = 0;
+  KPM_HIP(hipGetDevice(&dev));
+  const std::string key = tune_key(dev, p, n, q);
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune_cache.find(key);
+  if (it != g_tune_cache.end()) {
+    out = it->second;
+    return KPM_OK;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  KPM_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return KPM_EDEVICE;
+  }
+  double best = INFINITY;
+  Tune pick{};
+  for (const Tune& t : tune_candidates(p, n, q)) {
+    const double sec = time_candidate(p, n, q, t, a, b, work, bytes, st, e0, e1);
+    if (sec < best) {
+      best = sec;
+      pick = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g_tune_cache[key] = pick;
+  out = pick;
+  return KPM_OK;
 }
 
 int graph_segment() {
@@ -1285,6 +1447,12 @@ uint64_t kpm_sector_dim(int32_t n_sites, int32_t n_up) {
   return binom64(n_sites, n_up);
 }
 
+int kpm_autotune_reset(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune_cache.clear();
+  return KPM_OK;
+}
+
 int kpm_last_run_stats(kpm_run_stats* out) {
   if (!out) return KPM_EINVAL;
   *out = g_stats;
@@ -1400,10 +1568,16 @@ int chebyshev_moments(const kpm_problem* p, int32_t n, const kpm_params* q, doub
   std::vector<double> a, b;
   r = resolve_scale(p, n, *q, work + L0.lz, st, a, b);
   if (r != KPM_OK) return r;
+  Tune tn{};
+  if (q->autotune) {
+    r = get_tune(p, n, *q, a.data(), b.data(), work, need, st, tn);
+    if (r != KPM_OK) return r;
+  }
   Planned P;
-  r = make_plan(p, n, shape_of(*q), a.data(), b.data(), P);
+  r = make_plan(p, n, shape_of(*q, &tn), a.data(), b.data(), P);
   if (r != KPM_OK) return r;
   const MomLayout L = moments_layout(P, n_steps(q->M), 0);
+  if (L.total > need) return KPM_EWORKSPACE;
   std::vector<unsigned char> staging;
   r = upload_plan(P, work + L.plan, staging, st);
   if (r != KPM_OK) return r;

@@ -855,32 +855,63 @@ __global__ __launch_bounds__(kThreads) void block_kernel(const StepArgs a) {
         if (!a.first) yv = vload_nt<T, CPL>(Yin + rho * ld + c * CPL);
         const uint32_t l = s_row_l[r];
         const int b0 = s_row_b0[r];
-        for (int q = 0; q < nll; ++q) {
-          const uint32_t m = s_mask[q];
-          const uint32_t v = l & m;
-          if (v == 0u || v == m) continue;
-          int j = b0 + s_lrank[l ^ m];
-          if (j >= nrows) {
-            if (a.err) atomicOr(a.err, 4);
-            j = r;
-          }
-          const VecT<T, CPL> nv = vload<T, CPL>(xs + j * ld + c * CPL);
-          const double cf = s_off[q];
-#pragma unroll
-          for (int i = 0; i < CPL; ++i) acc[i] = fma(cf, (double)nv.v[i], acc[i]);
-        }
         const int kb = s_row_blk[r];
         const int64_t ib = r - b0;
         const int nh = s_hh_n[kb];
-        for (int k0 = 0; k0 < nh; k0 += GB) {
+        const uint32_t* hrow = s_hh_row + kb * a.lds_hh;
+        const uint16_t* hq = s_hh_q + kb * a.lds_hh;
+        // The first batch of high-high rows is in flight while the low-low
+        // neighbours are read from LDS (absent entries read the row itself
+        // with a zero coefficient; the summation order is unchanged).
+        VecT<T, CPL> hv[GB];
+        double hcf[GB];
+#pragma unroll
+        for (int j = 0; j < GB; ++j) {
+          const bool on = j < nh;
+          const int64_t row = on ? (int64_t)hrow[j] + ib : rho;
+          hcf[j] = on ? s_off[hq[j]] : 0.0;
+          hv[j] = vload<T, CPL>(X + row * ld + c * CPL);
+        }
+        for (int q0 = 0; q0 < nll; q0 += 4) {
+          int jj[4];
+          double cl[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int q = q0 + u;
+            const uint32_t m = q < nll ? s_mask[q] : 0u;
+            const uint32_t v = l & m;
+            const bool on = !(v == 0u || v == m);
+            int j = on ? b0 + s_lrank[l ^ m] : r;
+            if (j >= nrows) {
+              if (a.err) atomicOr(a.err, 4);
+              j = r;
+            }
+            jj[u] = j;
+            cl[u] = on ? s_off[q] : 0.0;
+          }
+          VecT<T, CPL> nl[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) nl[u] = vload<T, CPL>(xs + jj[u] * ld + c * CPL);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int i = 0; i < CPL; ++i) acc[i] = fma(cl[u], (double)nl[u].v[i], acc[i]);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < GB; ++j) {
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) acc[i] = fma(hcf[j], (double)hv[j].v[i], acc[i]);
+        }
+        for (int k0 = GB; k0 < nh; k0 += GB) {
           VecT<T, CPL> nv[GB];
           double cf[GB];
 #pragma unroll
           for (int j = 0; j < GB; ++j) {
             const int k = k0 + j;
             const bool on = k < nh;
-            const int64_t row = on ? (int64_t)s_hh_row[kb * a.lds_hh + k] + ib : rho;
-            cf[j] = on ? s_off[s_hh_q[kb * a.lds_hh + k]] : 0.0;
+            const int64_t row = on ? (int64_t)hrow[k] + ib : rho;
+            cf[j] = on ? s_off[hq[k]] : 0.0;
             nv[j] = vload<T, CPL>(X + row * ld + c * CPL);
           }
 #pragma unroll

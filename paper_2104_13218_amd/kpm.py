@@ -38,7 +38,7 @@ class Problem(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("eps", c_double), ("M", c_int32), ("R", c_int32), ("vec_kind", c_int32),
                 ("precision", c_int32), ("col_block", c_int32), ("seed", c_uint64),
-                ("lanczos_steps", c_int32), ("bound_margin", c_double)]
+                ("lanczos_steps", c_int32), ("bound_margin", c_double), ("autotune", c_int32)]
 
 
 class RunStats(ctypes.Structure):
@@ -76,6 +76,7 @@ _SIGS = {
                                   c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_size_t, c_void_p]),
     "kpm_last_run_stats": (c_int32, [POINTER(RunStats)]),
+    "kpm_autotune_reset": (c_int32, []),
 }
 
 
@@ -144,9 +145,9 @@ class ProblemSet:
 
 
 def make_params(M, R=1, vec_kind="rademacher", precision="fp64", eps=0.025, seed=0, col_block=0,
-                lanczos_steps=50, margin=0.01) -> Params:
+                lanczos_steps=50, margin=0.01, autotune=False) -> Params:
     return Params(float(eps), int(M), int(R), VEC_KINDS[vec_kind], PRECISIONS[precision], int(col_block),
-                  int(seed) % 2**64, int(lanczos_steps), float(margin))
+                  int(seed) % 2**64, int(lanczos_steps), float(margin), int(bool(autotune)))
 
 
 def sector_dim(n_sites: int, n_up: int) -> int:
@@ -188,10 +189,10 @@ def moments_workspace_size(problems: ProblemSet, params: Params) -> int:
 
 def chebyshev_moments(sectors, M, R=1, vec_kind="rademacher", precision="fp64", eps=0.025, seed=0,
                       col_block=0, bounds=None, lanczos_steps=50, margin=0.01, workspace=None,
-                      stream=None, problems=None):
+                      stream=None, problems=None, autotune=False):
     """Moments mu [n, M] (float64, cuda) and (a, b) [n, 2] of Eqs. (4)-(7)."""
     ps = problems or ProblemSet(sectors, bounds)
-    q = make_params(M, R, vec_kind, precision, eps, seed, col_block, lanczos_steps, margin)
+    q = make_params(M, R, vec_kind, precision, eps, seed, col_block, lanczos_steps, margin, autotune)
     mu = torch.empty((len(ps), M), dtype=torch.float64, device="cuda")
     ab = torch.empty((len(ps), 2), dtype=torch.float64, device="cuda")
     if workspace is None:
@@ -251,6 +252,10 @@ def thermo_vjp(mu, ab, sectors, T, wC, wchi, kernel="jackson", n_nodes=0, stream
                                  n_nodes, _ptr(T), T.numel(), _ptr(wC), _ptr(wchi), _ptr(lam), _stream(stream)),
            "kpm_thermo_vjp")
     return lam
+
+
+def autotune_reset():
+    _check(load().kpm_autotune_reset(), "kpm_autotune_reset")
 
 
 def last_run_stats() -> dict:
