@@ -13,7 +13,8 @@ Jackson-kernel thermodynamics at 200 log-spaced temperatures in [0.01, 10].
 x recursion steps / wall time of the pass, inputs resident on the GPU).  The
 JSON line also carries:
   roofline      the step kernel's algorithmic HBM bytes (3 x 4 B per state and
-                column) over its average launch time, measured with hipEvents on
+                column, + 4 B per state when the kernel streams the state
+                words) over its average launch time, measured with hipEvents on
                 the launch stream during the timed passes; `traffic` is the
                 rocprofv3-measured bytes per launch from the committed counter
                 summary, or null
@@ -51,7 +52,7 @@ def _parse():
     ap.add_argument("--M", type=int, default=2000)
     ap.add_argument("--skip-extras", action="store_true",
                     help="only the timed workload (for profiler runs)")
-    ap.add_argument("--cpu-steps", type=int, default=6,
+    ap.add_argument("--cpu-steps", type=int, default=30,
                     help="recursion steps of the CPU-oracle sample")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (reference for HBM byte counters)")

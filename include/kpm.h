@@ -217,7 +217,9 @@ int kpm_thermo_grad(const kpm_problem* p, int32_t n, const kpm_params* q, int32_
 typedef struct {
   int64_t step_launches;   /* recursion-step kernel launches (= M/2) */
   double bytes_per_launch; /* algorithmic HBM bytes of one step: 3 * storage
-                              size * sum over blocks of dim * real columns */
+                              size * sum over blocks of dim * real columns,
+                              + 4 * dim per block for the row and block
+                              kernels (they stream the 4-byte state words) */
   double state_col_steps;  /* sum over blocks of dim * real columns * steps */
   int32_t col_block;       /* real columns per block chosen */
   int32_t rows_per_tile;   /* basis states per workgroup tile (block kernel: mean) */

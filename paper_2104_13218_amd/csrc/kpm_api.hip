@@ -484,6 +484,9 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
     }
   }
   P.prob_unit0.push_back((int32_t)P.units.size());
+  // the row and block kernels also stream the 4-byte state word of every row
+  if (D.row_ld || D.block)
+    for (const auto& u : P.units) P.bytes_per_step += 4.0 * (double)P.probs[u.prob].dim;
   P.tile_sub0.push_back((int32_t)P.sub_nrows.size());
   if (P.sub_nrows.empty()) P.sub_nrows.push_back(0);
   if (P.lrank.empty()) P.lrank.push_back(0);
