@@ -120,6 +120,56 @@ def thermo(problems, mu: np.ndarray, ab: np.ndarray, T: np.ndarray,
     return out
 
 
+def thermo_field(problems, mu: np.ndarray, ab: np.ndarray, T: np.ndarray, h: np.ndarray,
+                 kernel: str = "jackson", n_nodes: int = 0):
+    """Thermodynamics with the Zeeman term of the ladder Hamiltonian (Sec. III.A,
+    Eq. (E-3-1-1)): H = H_0 + h S^z_total with h = g mu_B B, at the points
+    (T[t], h[t]).  S^z commutes with H_0, so a sector S^z = m keeps the DOS of
+    its zero-field moments and shifts every energy by h m; a sector S^z > 0
+    stands for itself (m = +S^z) and its mirror (m = -S^z).
+    Returns ln Z, E = <E>, C = beta^2 (<E^2> - <E>^2), chi = beta (<m^2> - <m>^2),
+    M = <m> = <S^z_total> per cluster and point, and the Z <= 0 flag; the
+    Boltzmann factors are shifted by the lowest node energy of the point."""
+    mu = np.atleast_2d(mu)
+    P, M = mu.shape
+    Nt = n_nodes or M
+    g = kernel_coefficients(M, kernel)
+    x = nodes(Nt)
+    cid, sz, W = _sector_table(problems)
+    nc = int(cid.max()) + 1
+    T = np.asarray(T, dtype=np.float64)
+    h = np.broadcast_to(np.asarray(h, dtype=np.float64), T.shape)
+    out = {k: np.zeros((nc, T.size)) for k in ("lnZ", "E", "C", "chi", "M")}
+    out["z_nonpos"] = np.zeros((nc, T.size), dtype=bool)
+    gam = np.stack([dos_weights(mu[p], g, Nt) for p in range(P)])
+    Ek = ab[:, 0:1] * x[None, :] + ab[:, 1:2]                      # [P, Nt]
+    for c in range(nc):
+        sel = np.nonzero(cid == c)[0]
+        for t, (Tv, hv) in enumerate(zip(T, h)):
+            beta = 1.0 / Tv
+            gs, Es, ms = [], [], []
+            for p in sel:
+                for m in ([sz[p]] if W[p] == 1.0 else [sz[p], -sz[p]]):
+                    gs.append(gam[p])
+                    Es.append(Ek[p] + hv * m)
+                    ms.append(np.full(Nt, m))
+            gw, E, m = np.concatenate(gs), np.concatenate(Es), np.concatenate(ms)
+            Eref = E.min()
+            w = gw * np.exp(-beta * (E - Eref))
+            S0 = math.fsum(w)
+            Em = math.fsum(w * E) / S0
+            varE = math.fsum(w * (E - Em) ** 2) / S0
+            m1 = math.fsum(w * m) / S0
+            varM = math.fsum(w * (m - m1) ** 2) / S0
+            out["z_nonpos"][c, t] = S0 <= 0.0
+            out["lnZ"][c, t] = (np.log(S0 / Nt) if S0 > 0 else np.nan) - beta * Eref
+            out["E"][c, t] = Em
+            out["C"][c, t] = beta**2 * varE
+            out["chi"][c, t] = beta * varM
+            out["M"][c, t] = m1
+    return out
+
+
 def thermo_vjp(problems, mu: np.ndarray, ab: np.ndarray, T: np.ndarray,
                wC: np.ndarray, wchi: np.ndarray, kernel: str = "jackson", n_nodes: int = 0):
     """lambda[p, n] = dL/dmu_n^p for L = sum_{c,T} wC[c,T] C[c,T] + wchi[c,T] chi[c,T].

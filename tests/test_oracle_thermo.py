@@ -166,3 +166,67 @@ def test_ghost_dip_behaviour_ladder14():
     assert C(100, 0.025, "none")[w].min() < 10 * c0[w].min()
     assert C(100, 0.1, "none")[w].min() < 10 * c0[w].min()
     assert np.abs(C(500, 0.0, "none") - ref)[w].max() < 1e-5
+
+
+def _dense_field_thermo(cl, T, h):
+    """Reference from the dense 2^N Hamiltonian with the Zeeman term
+    h S^z_total added (Kronecker construction, no sector logic)."""
+    H0 = hamiltonian.full_hamiltonian_kron(cl)
+    N = cl.n_sites
+    idx = np.arange(1 << N)
+    sz_tot = np.array([bin(i).count("1") for i in idx]) - 0.5 * N      # bit 1 = up
+    out = {k: np.zeros(len(T)) for k in ("lnZ", "E", "C", "chi", "M")}
+    for t, (Tv, hv) in enumerate(zip(T, h)):
+        e, U = np.linalg.eigh(H0 + hv * np.diag(sz_tot))
+        m_ii = (U * (sz_tot[:, None] * U)).sum(axis=0)       # <i|S^z|i>
+        m2_ii = (U * (sz_tot[:, None] ** 2 * U)).sum(axis=0)
+        beta = 1.0 / Tv
+        w = np.exp(-beta * (e - e.min()))
+        Z = w.sum()
+        Em = (w * e).sum() / Z
+        out["lnZ"][t] = np.log(Z) - beta * e.min()
+        out["E"][t] = Em
+        out["C"][t] = beta**2 * ((w * (e - Em) ** 2).sum() / Z)
+        Mm = (w * m_ii).sum() / Z
+        out["M"][t] = Mm
+        out["chi"][t] = beta * ((w * m2_ii).sum() / Z - Mm**2)
+    return out
+
+
+def test_field_thermo_zero_field_is_thermo():
+    cl = W.ring(10)
+    probs, mus, ab, _ = _exact_problem_set(cl, 0.025, 128)
+    T = W.log_temperatures(30, 0.05, 10.0)
+    a = thermo.thermo(probs, mus, ab, T, "jackson")
+    b = thermo.thermo_field(probs, mus, ab, T, np.zeros_like(T), "jackson")
+    for k in ("lnZ", "E", "C", "chi"):
+        np.testing.assert_allclose(b[k], a[k], rtol=1e-13, atol=1e-14)
+    assert np.all(np.abs(b["M"]) <= 1e-12)
+
+
+@pytest.mark.parametrize("cl", [W.ring(8), W.random_regular_cluster(9, 3, 2, J_range=(0.5, 1.5))])
+def test_field_thermo_exact_traces_match_dense_ed(cl):
+    """Exact traces, g_n = 1, Ntil = M = 400: KPM with the Zeeman term equals the
+    dense diagonalisation of H_0 + h S^z (odd N: every sector has a mirror)."""
+    probs, mus, ab, _ = _exact_problem_set(cl, 0.025, 400)
+    T = np.array([0.3, 0.3, 0.7, 1.5, 4.0, 0.5])
+    h = np.array([0.4, 2.5, 1.0, -1.3, 3.0, 0.0])
+    out = thermo.thermo_field(probs, mus, ab, T, h, "none", 400)
+    ref = _dense_field_thermo(cl, T, h)
+    for k, tol in (("lnZ", 1e-9), ("E", 1e-9), ("C", 1e-8), ("chi", 1e-9), ("M", 1e-9)):
+        assert np.abs(out[k][0] - ref[k]).max() < tol, k
+
+
+def test_field_thermo_saturation_and_susceptibility():
+    """Large field at low T polarises the ring (<S^z> -> -N/2 for h > 0 with
+    H = H_0 + h S^z); chi = -d<S^z>/dh."""
+    cl = W.ring(8)
+    probs, mus, ab, _ = _exact_problem_set(cl, 0.025, 400)
+    out = thermo.thermo_field(probs, mus, ab, [0.05, 0.05], [6.0, -6.0], "none", 400)
+    assert abs(out["M"][0, 0] + 4.0) < 1e-6 and abs(out["M"][0, 1] - 4.0) < 1e-6
+    T = np.full(3, 0.8)
+    for h0 in (0.0, 0.7, 2.2):
+        d = 1e-4
+        o = thermo.thermo_field(probs, mus, ab, T, np.array([h0 - d, h0, h0 + d]), "none", 400)
+        dM = (o["M"][0, 2] - o["M"][0, 0]) / (2 * d)
+        assert abs(o["chi"][0, 1] + dM) < 1e-6 * max(1.0, abs(dM)), h0
