@@ -12,7 +12,9 @@ Jackson-kernel thermodynamics at 200 log-spaced temperatures in [0.01, 10].
 `value` is state-column-steps per second of the whole pass (dim x real columns
 x recursion steps / wall time of the pass, inputs resident on the GPU).  The
 JSON line also carries:
-  roofline      the step kernel's algorithmic HBM bytes (3 x 4 B per state and
+  roofline      (also `measured_GBs` = counter bytes / launch time, and
+                `copy_GBs` = a 1 GiB device copy's rate, the achievable line)
+                the step kernel's algorithmic HBM bytes (3 x 4 B per state and
                 column, + 4 B per state when the kernel streams the state
                 words) over its average launch time, measured with hipEvents on
                 the launch stream during the timed passes; `traffic` is the
@@ -77,6 +79,25 @@ def _traffic(family):
     return d.get("hbm_bytes_per_launch")
 
 
+def _copy_rate(torch):
+    """Achievable line: read + write bytes of a 1 GiB device-to-device copy
+    over its hipEvent time (best of 5)."""
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * (1 << 30) / best / 1e9
+
+
 def main():
     args = _parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -134,6 +155,7 @@ def main():
     achieved = st["bytes_per_launch"] / avg_launch_s / 1e9
     family = KERNEL_FAMILY.get(st["kernel"], "step_kernel")
     traffic = _traffic(family)
+    copy_gbs = _copy_rate(torch)
     line = {
         "metric": METRIC, "value": value, "unit": "state-column-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
@@ -147,7 +169,9 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "algorithmic_bytes_per_launch": st["bytes_per_launch"],
                      "avg_launch_us": avg_launch_s * 1e6,
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     "measured_GBs": None if traffic is None else traffic / avg_launch_s / 1e9,
+                     "copy_GBs": copy_gbs},
     }
 
     if not args.skip_extras:

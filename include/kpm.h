@@ -183,6 +183,20 @@ int kpm_thermo(const double* d_mu, const double* d_ab, const kpm_problem* p, int
                double* d_lnZ, double* d_E, double* d_C, double* d_chi, uint8_t* d_znonpos,
                void* stream);
 
+/* Thermodynamics in a magnetic field: the Zeeman term g mu_B B sum_i s^z_i of
+ * the ladder Hamiltonian (Sec. III.A), H = H_0 + h S^z with h = g mu_B B in
+ * energy units, at n_pts points (d_T[t], d_h[t]).  S^z commutes with H_0, so
+ * every S^z > 0 sector enters twice, at m = +S^z and at its mirror m = -S^z,
+ * with the zero-field DOS of the moments and energies E + h m; S^z = 0 once.
+ * Outputs device [n_clusters][n_pts]: ln Z, E = <E> (Zeeman energy included),
+ * C = (<E^2> - <E>^2)/T^2, chi = (<S_z^2> - <S_z>^2)/T, d_mag = <S_z> (may be
+ * NULL; negative for h > 0), d_znonpos as in kpm_thermo.  Other arguments as
+ * in kpm_thermo; at h = 0 the results equal kpm_thermo's up to rounding. */
+int kpm_thermo_field(const double* d_mu, const double* d_ab, const kpm_problem* p, int32_t n,
+                     int32_t M, int32_t kernel, int32_t n_nodes, const double* d_T,
+                     const double* d_h, int32_t n_pts, double* d_lnZ, double* d_E, double* d_C,
+                     double* d_chi, double* d_mag, uint8_t* d_znonpos, void* stream);
+
 /* Derivative of L = sum_{c,T} wC[c][T] C[c][T] + wchi[c][T] chi[c][T] with
  * respect to the moments: d_lambda device double [n][M] = dL/dmu. */
 int kpm_thermo_vjp(const double* d_mu, const double* d_ab, const kpm_problem* p, int32_t n,

@@ -1375,7 +1375,8 @@ struct ThermoDev {
 int thermo_forward(const double* d_mu, const double* d_ab, const kpm_problem* p, int n, int M,
                    int kernel, int n_nodes, const double* d_T, int n_T, double* lnZ, double* E,
                    double* C, double* chi, uint8_t* znonpos, hipStream_t st, ThermoDev& TD,
-                   std::vector<ThermoProb>& tp, int& n_clusters, bool keep_adj) {
+                   std::vector<ThermoProb>& tp, int& n_clusters, bool keep_adj,
+                   const double* d_h = nullptr, double* d_mag = nullptr) {
   if (!d_mu || !d_ab || !d_T || M < 1 || n_T < 1 || n_nodes < 0 || (kernel != 0 && kernel != 1))
     return KPM_EINVAL;
   std::vector<int32_t> start, list;
@@ -1423,7 +1424,10 @@ int thermo_forward(const double* d_mu, const double* d_ab, const kpm_problem* p,
   ta.n_nodes = Nt;
   ta.n_T = n_T;
   ta.n_clusters = n_clusters;
-  KPM_HIP(launch_thermo(ta, st));
+  ta.h = d_h;
+  ta.mag = d_mag;
+  if (d_h) KPM_HIP(launch_thermo_field(ta, st));
+  else KPM_HIP(launch_thermo(ta, st));
   // the host staging vectors die with the caller's frame: finish the copies now
   KPM_HIP(hipStreamSynchronize(st));
   return KPM_OK;
@@ -1655,6 +1659,18 @@ int kpm_thermo(const double* d_mu, const double* d_ab, const kpm_problem* p, int
   int nc = 0;
   return thermo_forward(d_mu, d_ab, p, n, M, kernel, n_nodes, d_T, n_T, d_lnZ, d_E, d_C, d_chi,
                         d_znonpos, static_cast<hipStream_t>(stream), TD, tp, nc, false);
+}
+
+int kpm_thermo_field(const double* d_mu, const double* d_ab, const kpm_problem* p, int32_t n,
+                     int32_t M, int32_t kernel, int32_t n_nodes, const double* d_T,
+                     const double* d_h, int32_t n_pts, double* d_lnZ, double* d_E, double* d_C,
+                     double* d_chi, double* d_mag, uint8_t* d_znonpos, void* stream) {
+  if (!d_h || !d_lnZ || !d_E || !d_C || !d_chi) return KPM_EINVAL;
+  ThermoDev TD;
+  std::vector<ThermoProb> tp;
+  int nc = 0;
+  return thermo_forward(d_mu, d_ab, p, n, M, kernel, n_nodes, d_T, n_pts, d_lnZ, d_E, d_C, d_chi,
+                        d_znonpos, static_cast<hipStream_t>(stream), TD, tp, nc, false, d_h, d_mag);
 }
 
 int kpm_thermo_vjp(const double* d_mu, const double* d_ab, const kpm_problem* p, int32_t n,

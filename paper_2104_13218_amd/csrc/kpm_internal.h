@@ -213,6 +213,8 @@ struct ThermoArgs {
   uint8_t* znonpos;
   double* stats;             // [n_clusters][n_T][6]: S0, Ebar, Var, <m^2>, Eref, beta
   int32_t n_nodes, n_T, n_clusters;
+  const double* h;           // [n_T] Zeeman energies g mu_B B (field kernel only)
+  double* mag;               // [n_clusters][n_T] <S^z> (field kernel, may be NULL)
 };
 
 struct ThermoVjpArgs {
@@ -317,6 +319,7 @@ hipError_t launch_kernel_coef(int M, int kernel, double* g, hipStream_t st);
 hipError_t launch_gamma(int n_probs, int M, int n_nodes, const double* g, const double* mu,
                         double* gamma, hipStream_t st);
 hipError_t launch_thermo(const ThermoArgs& a, hipStream_t st);
+hipError_t launch_thermo_field(const ThermoArgs& a, hipStream_t st);
 hipError_t launch_thermo_vjp(const ThermoVjpArgs& a, hipStream_t st);
 
 }  // namespace kpm

@@ -173,6 +173,88 @@ hipError_t launch_thermo(const ThermoArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Thermodynamics with the Zeeman term h S^z (h = g mu_B B, per point): the
+// sector S^z = m keeps its zero-field DOS and every energy moves by h m; a
+// sector with S^z > 0 stands for m = +S^z and its mirror m = -S^z.  Sums as in
+// thermo_kernel, shifted by the lowest node energy of the point; the energy
+// and S^z variances are centred second passes.
+__global__ __launch_bounds__(kThreads) void thermo_field_kernel(const ThermoArgs a) {
+  __shared__ double sh[4];
+  const int t = blockIdx.x, c = blockIdx.y;
+  const int Nt = a.n_nodes;
+  const int p0 = a.cl_start[c], p1 = a.cl_start[c + 1];
+  const int64_t items = (int64_t)(p1 - p0) * Nt;
+  const double beta = 1.0 / a.T[t];
+  const double hf = a.h[t];
+
+  double emin = INFINITY;
+  for (int64_t i = threadIdx.x; i < items; i += kThreads) {
+    const int p = a.cl_list[p0 + i / Nt];
+    const int k = (int)(i % Nt) + 1;
+    const double E = a.ab[2 * p] * node_x(k, Nt) + a.ab[2 * p + 1];
+    const double sz = a.tp[p].sz;
+    emin = fmin(emin, E + hf * sz);
+    if (a.tp[p].weight > 1.0) emin = fmin(emin, E - hf * sz);
+  }
+  const double eref = wmin(emin, sh);
+
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int64_t i = threadIdx.x; i < items; i += kThreads) {
+    const int p = a.cl_list[p0 + i / Nt];
+    const int k = (int)(i % Nt) + 1;
+    const double E = a.ab[2 * p] * node_x(k, Nt) + a.ab[2 * p + 1];
+    const double gk = a.gamma[(int64_t)p * Nt + (k - 1)];
+    const double sz = a.tp[p].sz;
+    const int nm = a.tp[p].weight > 1.0 ? 2 : 1;
+    for (int j = 0; j < nm; ++j) {
+      const double m = j == 0 ? sz : -sz;
+      const double Et = E + hf * m;
+      const double w = gk * exp(-beta * (Et - eref));
+      s0 += w;
+      s1 = fma(w, Et, s1);
+      s2 = fma(w, m, s2);
+    }
+  }
+  const double S0 = wsum(s0, sh);
+  const double Ebar = wsum(s1, sh) / S0;
+  const double Mbar = wsum(s2, sh) / S0;
+
+  double ve = 0.0, vm = 0.0;
+  for (int64_t i = threadIdx.x; i < items; i += kThreads) {
+    const int p = a.cl_list[p0 + i / Nt];
+    const int k = (int)(i % Nt) + 1;
+    const double E = a.ab[2 * p] * node_x(k, Nt) + a.ab[2 * p + 1];
+    const double gk = a.gamma[(int64_t)p * Nt + (k - 1)];
+    const double sz = a.tp[p].sz;
+    const int nm = a.tp[p].weight > 1.0 ? 2 : 1;
+    for (int j = 0; j < nm; ++j) {
+      const double m = j == 0 ? sz : -sz;
+      const double Et = E + hf * m;
+      const double w = gk * exp(-beta * (Et - eref));
+      const double de = Et - Ebar, dm = m - Mbar;
+      ve = fma(w, de * de, ve);
+      vm = fma(w, dm * dm, vm);
+    }
+  }
+  const double VarE = wsum(ve, sh) / S0;
+  const double VarM = wsum(vm, sh) / S0;
+
+  if (threadIdx.x == 0) {
+    const int64_t o = (int64_t)c * a.n_T + t;
+    a.lnZ[o] = (S0 > 0.0 ? log(S0 / (double)Nt) : NAN) - beta * eref;
+    a.E[o] = Ebar;
+    a.C[o] = beta * beta * VarE;
+    a.chi[o] = beta * VarM;
+    if (a.mag) a.mag[o] = Mbar;
+    if (a.znonpos) a.znonpos[o] = S0 > 0.0 ? 0 : 1;
+  }
+}
+
+hipError_t launch_thermo_field(const ThermoArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(thermo_field_kernel, dim3(a.n_T, a.n_clusters), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
 // dL/dgamma at every node: for L = sum wC C + wchi chi,
 //   dC/dgamma_k  = beta^2 W e_k ((E_k - Ebar)^2 - Var) / S0,
 //   dchi/dgamma_k = beta W e_k (m^2 - <m^2>) / S0,   e_k = exp(-beta (E_k - E_ref)).

@@ -66,6 +66,9 @@ _SIGS = {
     "kpm_thermo": (c_int32, [c_void_p, c_void_p, POINTER(Problem), c_int32, c_int32, c_int32, c_int32,
                              c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                              c_void_p]),
+    "kpm_thermo_field": (c_int32, [c_void_p, c_void_p, POINTER(Problem), c_int32, c_int32, c_int32,
+                                   c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_void_p, c_void_p, c_void_p]),
     "kpm_thermo_vjp": (c_int32, [c_void_p, c_void_p, POINTER(Problem), c_int32, c_int32, c_int32,
                                  c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "chebyshev_moments_vjp_workspace_size": (c_size_t, [POINTER(Problem), c_int32, POINTER(Params),
@@ -237,6 +240,24 @@ def thermo(mu, ab, sectors, T, kernel="jackson", n_nodes=0, stream=None):
     _check(load().kpm_thermo(_ptr(mu), _ptr(ab), ps.arr, len(ps), mu.shape[1], KERNELS[kernel], n_nodes,
                              _ptr(T), nT, _ptr(out["lnZ"]), _ptr(out["E"]), _ptr(out["C"]), _ptr(out["chi"]),
                              _ptr(out["z_nonpos"]), _stream(stream)), "kpm_thermo")
+    return out
+
+
+def thermo_field(mu, ab, sectors, T, h, kernel="jackson", n_nodes=0, stream=None):
+    """ln Z, E, C, chi, M = <S^z> [n_clusters, n_pts] at the points (T, h) with
+    the Zeeman term h S^z (h = g mu_B B), and the Z <= 0 flags."""
+    ps = sectors if isinstance(sectors, ProblemSet) else ProblemSet(sectors)
+    mu = mu.contiguous()
+    ab = ab.contiguous()
+    T = torch.as_tensor(T, dtype=torch.float64, device="cuda").contiguous()
+    h = torch.as_tensor(h, dtype=torch.float64, device="cuda").expand_as(T).contiguous()
+    nc, nT = ps.n_clusters, T.numel()
+    out = {k: torch.empty((nc, nT), dtype=torch.float64, device="cuda") for k in ("lnZ", "E", "C", "chi", "M")}
+    out["z_nonpos"] = torch.empty((nc, nT), dtype=torch.uint8, device="cuda")
+    _check(load().kpm_thermo_field(_ptr(mu), _ptr(ab), ps.arr, len(ps), mu.shape[1], KERNELS[kernel], n_nodes,
+                                   _ptr(T), _ptr(h), nT, _ptr(out["lnZ"]), _ptr(out["E"]), _ptr(out["C"]),
+                                   _ptr(out["chi"]), _ptr(out["M"]), _ptr(out["z_nonpos"]), _stream(stream)),
+           "kpm_thermo_field")
     return out
 
 

@@ -116,3 +116,46 @@ def test_end_to_end_ring12_config(kpm):
     ex = ed.thermo_from_spectra(ed.sector_spectra(secs), T)
     hiT = T >= 0.5
     assert np.abs(out["C"].cpu().numpy()[0][hiT] - ex["C"][hiT]).max() < 0.05 * ex["C"].max()
+
+
+@pytest.mark.parametrize("kernel", ["none", "jackson"])
+def test_field_thermo_on_identical_moments(kpm, kernel):
+    """kpm_thermo_field vs the oracle's thermo_field on identical moments: two
+    clusters (even and odd N), 120 (T, h) points including h = 0 and h < 0."""
+    secs = W.sectors(W.ring(10)) + W.sectors(W.random_regular_cluster(9, 3, 2, J_range=(0.5, 1.5)),
+                                             cluster_id=1)
+    mus, ab = _exact_setup(secs, 0.025, 200)
+    T = np.tile(W.log_temperatures(40, 0.05, 8.0), 3)
+    h = np.repeat([0.0, 1.7, -0.6], 40)
+    out = kpm.thermo_field(torch.tensor(mus, device="cuda"), torch.tensor(ab, device="cuda"), secs, T, h, kernel)
+    ref = thermo.thermo_field(_probs(secs), mus, ab, T, h, kernel)
+    for q in ("lnZ", "E", "C", "chi"):
+        _cmp(out[q].cpu().numpy(), ref[q], q)
+    M = out["M"].cpu().numpy()
+    assert np.abs(M - ref["M"]).max() <= 1e-12 * 5.0      # |<S^z>| <= N/2
+    # zero field: the field kernel agrees with kpm_thermo to rounding
+    z = kpm.thermo(torch.tensor(mus, device="cuda"), torch.tensor(ab, device="cuda"), secs, T[:40], kernel)
+    for q in ("lnZ", "E", "C", "chi"):
+        _cmp(out[q].cpu().numpy()[:, :40], z[q].cpu().numpy(), q)
+    assert np.abs(M[:, :40]).max() <= 1e-12
+
+
+def test_field_thermo_end_to_end_ring12(kpm):
+    """GPU moments (float64, 20 Rademacher vectors) + GPU field thermodynamics
+    against the oracle's moments + thermo_field on the same seeds and bounds."""
+    secs = W.sectors(W.ring(12))
+    bl = []
+    for s in secs:
+        e = np.linalg.eigvalsh(hamiltonian.sector_hamiltonian(s.cluster, s.n_up).toarray())
+        bl.append((e.min() - 0.05, e.max() + 0.05))
+    M = 256
+    mu, ab = kpm.chebyshev_moments(secs, M, 20, "rademacher", "fp64", 0.025, 0, bounds=bl)
+    T = np.tile(W.log_temperatures(30, 0.2, 10.0), 2)
+    h = np.repeat([0.5, 2.0], 30)
+    out = kpm.thermo_field(mu, ab, secs, T, h, "jackson")
+    abh = ab.cpu().numpy()
+    want_mu = np.array([moments.sector_moments(s, a, b, M, 20, "rademacher", 0) for s, (a, b) in zip(secs, abh)])
+    ref = thermo.thermo_field(_probs(secs), want_mu, abh, T, h, "jackson")
+    for q in ("lnZ", "E", "C", "chi"):
+        _cmp(out[q].cpu().numpy(), ref[q], q, tol=1e-8)
+    assert np.abs(out["M"].cpu().numpy() - ref["M"]).max() <= 1e-8 * 6.0
