@@ -19,6 +19,7 @@ Modules
   hamiltonian  sector matrices of H = sum_b J_b s_i.s_j (CSR), Kronecker build
   rng          counter-based SplitMix64 random vectors
   rows         single rows of v_n = C_n(H') v_0 for sectors too large to hold
+  ftlm         finite-temperature Lanczos (the comparison method)
   moments      three-term recursion, doubling identities, estimator Eq. (7),
                exact traces by diagonalisation, Lanczos bounds
   thermo       Jackson kernel Eq. (8), Gauss-Chebyshev quadrature, Z, E, C, chi
@@ -27,4 +28,4 @@ Modules
                finite differences and Hellmann-Feynman references
   ed           thermodynamics from exact diagonalisation
 """
-from . import basis, hamiltonian, rng, rows, moments, thermo, adjoint, ed  # noqa: F401
+from . import basis, hamiltonian, rng, rows, moments, thermo, adjoint, ed, ftlm  # noqa: F401
