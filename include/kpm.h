@@ -197,6 +197,34 @@ int kpm_thermo_field(const double* d_mu, const double* d_ab, const kpm_problem* 
                      const double* d_h, int32_t n_pts, double* d_lnZ, double* d_E, double* d_C,
                      double* d_chi, double* d_mag, uint8_t* d_znonpos, void* stream);
 
+/* Workspace bytes for kpm_ftlm (0 if the arguments are invalid). */
+size_t kpm_ftlm_workspace_size(const kpm_problem* p, int32_t n, const kpm_params* q);
+
+/* Finite-temperature Lanczos method, the comparison method of the paper
+ * (Introduction, Sec. III.C): for every start vector r of every problem (the
+ * random vectors of chebyshev_moments: same kinds, seeds and streams, each
+ * real column on its own), q->M steps of float64 Lanczos on the unscaled H
+ * without reorthogonalisation (cut at the first off-diagonal below 1e-12 or
+ * at the sector dimension) give Ritz values eps_j and squared first
+ * eigenvector components; the estimator of Eq. (7) becomes
+ *   Tr_Gamma f(H) ~ dim/R sum_r sum_j w_{rj} f(eps_{rj}),
+ * with a complex vector's two real columns weighted by their share of |r|^2
+ * (R = dim and weight 1 for the complete basis).  Thermodynamics as in
+ * kpm_thermo_field at the points (d_T[t], d_h[t]) (d_h may be NULL: no field).
+ *  q: M = Krylov dimension (>= 2), precision must be KPM_FP64, col_block,
+ *     eps and the problems' bounds are not used
+ *  outputs device [n_clusters][n_pts]: d_lnZ, d_E, d_C, d_chi, d_mag (<S_z>,
+ *     may be NULL)
+ *  d_ritz, d_weight: device double [columns][min(M, largest dim)] (may be
+ *     NULL): Ritz values and estimator weights per real column (problem after
+ *     problem), zero past each column's length
+ * Errors: KPM_EINVAL, KPM_EWORKSPACE, KPM_EDEVICE (HIP error, or a tridiagonal
+ * that did not converge). */
+int kpm_ftlm(const kpm_problem* p, int32_t n, const kpm_params* q, const double* d_T,
+             const double* d_h, int32_t n_pts, double* d_lnZ, double* d_E, double* d_C,
+             double* d_chi, double* d_mag, double* d_ritz, double* d_weight, void* d_work,
+             size_t work_bytes, void* stream);
+
 /* Derivative of L = sum_{c,T} wC[c][T] C[c][T] + wchi[c][T] chi[c][T] with
  * respect to the moments: d_lambda device double [n][M] = dL/dmu. */
 int kpm_thermo_vjp(const double* d_mu, const double* d_ab, const kpm_problem* p, int32_t n,

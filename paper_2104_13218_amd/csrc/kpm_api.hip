@@ -164,6 +164,7 @@ struct RunShape {
   int col_block = 0;
   bool adjoint = false;   // block widths padded to the adjoint kernel's (1..16, power of 2)
   bool allow_row = true;  // the row kernel may run the recursion
+  bool split_vectors = false;  // complex vectors may be split across blocks (one column each)
 };
 
 constexpr int kAdjMaxLd = 16;
@@ -207,7 +208,7 @@ int pick_col_block(const kpm_problem* p, int n, const RunShape& s) {
   int rb = s.col_block > 0 ? s.col_block
                           : (s.tune.col_block > 0 ? s.tune.col_block : (s.precision == KPM_FP32_STORE ? 32 : 16));
   rb = (int)std::min<int64_t>(rb, maxc);
-  rb = (rb + cpv - 1) / cpv * cpv;
+  if (!s.split_vectors) rb = (rb + cpv - 1) / cpv * cpv;
   return std::min(rb, kMaxLd);
 }
 
@@ -1433,6 +1434,53 @@ int thermo_forward(const double* d_mu, const double* d_ab, const kpm_problem* p,
   return KPM_OK;
 }
 
+// ---------------------------------------------- finite-temperature Lanczos
+
+struct FtlmLayout {
+  size_t plan, vec, vecC, part, dots, b2, zero, norm, err, states, ritz, escr, weight, len, total;
+};
+
+RunShape ftlm_shape(const kpm_params& q) {
+  RunShape s = shape_of(q);
+  s.precision = KPM_FP64;
+  s.col_block = 1;
+  s.split_vectors = true;
+  return s;
+}
+
+int ftlm_steps(const Planned& P, int M) {
+  int64_t max_dim = 1;
+  for (auto& d : P.probs) max_dim = std::max(max_dim, d.dim);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(M, max_dim));
+}
+
+FtlmLayout ftlm_layout(const Planned& P, int steps) {
+  FtlmLayout L{};
+  size_t o = 0;
+  auto put = [&](size_t bytes) {
+    const size_t r = o;
+    o = align_up(o + bytes);
+    return r;
+  };
+  const size_t TC = (size_t)P.plan.total_cols;
+  L.plan = put(P.bytes);
+  L.vec = put((size_t)P.plan.vec_elems * 8);
+  L.vecC = put((size_t)P.plan.vec_elems * 8);
+  L.part = put((size_t)P.plan.part_len * 8);
+  L.dots = put((size_t)steps * TC * 8);
+  L.b2 = put((size_t)steps * TC * 8);
+  L.zero = put(TC * 8);
+  L.norm = put(TC * 8);
+  L.err = put(256);
+  L.states = put((size_t)P.plan.n_states * 4);
+  L.ritz = put(TC * steps * 8);
+  L.escr = put(TC * steps * 8);
+  L.weight = put(TC * steps * 8);
+  L.len = put(TC * 4);
+  L.total = o;
+  return L;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1794,6 +1842,137 @@ int kpm_thermo_grad(const kpm_problem* p, int32_t n, const kpm_params* q, int32_
   KPM_HIP(hipMemcpyAsync(h_ab.data(), ab, h_ab.size() * 8, hipMemcpyDeviceToHost, st));
   KPM_HIP(hipStreamSynchronize(st));
   return run_vjp(p, n, *q, h_ab.data(), lam, ckpt_every, d_dJ, work, st);
+}
+
+size_t kpm_ftlm_workspace_size(const kpm_problem* p, int32_t n, const kpm_params* q) {
+  if (check_problems(p, n) != KPM_OK || !q || check_params(*q) != KPM_OK) return 0;
+  if (q->precision != KPM_FP64) return 0;
+  Planned P;
+  if (make_plan(p, n, ftlm_shape(*q), nullptr, nullptr, P) != KPM_OK) return 0;
+  return ftlm_layout(P, ftlm_steps(P, q->M)).total;
+}
+
+int kpm_ftlm(const kpm_problem* p, int32_t n, const kpm_params* q, const double* d_T,
+             const double* d_h, int32_t n_pts, double* d_lnZ, double* d_E, double* d_C,
+             double* d_chi, double* d_mag, double* d_ritz, double* d_weight, void* d_work,
+             size_t work_bytes, void* stream) {
+  int r = check_problems(p, n);
+  if (r != KPM_OK) return r;
+  if (!q || check_params(*q) != KPM_OK || q->precision != KPM_FP64) return KPM_EINVAL;
+  if (!d_T || n_pts < 1 || !d_lnZ || !d_E || !d_C || !d_chi) return KPM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StreamSync guard{st};
+  Planned P;
+  r = make_plan(p, n, ftlm_shape(*q), nullptr, nullptr, P);   // H unscaled: a = 1, b = 0
+  if (r != KPM_OK) return r;
+  const int steps = ftlm_steps(P, q->M);
+  const FtlmLayout L = ftlm_layout(P, steps);
+  DevBuf own;
+  unsigned char* work = static_cast<unsigned char*>(d_work);
+  if (!work) {
+    r = own.alloc(L.total);
+    if (r != KPM_OK) return r;
+    work = static_cast<unsigned char*>(own.p);
+  } else if (work_bytes < L.total) {
+    return KPM_EWORKSPACE;
+  }
+  std::vector<unsigned char> staging;
+  r = upload_plan(P, work + L.plan, staging, st);
+  if (r != KPM_OK) return r;
+  DevicePlan& D = P.plan;
+  D.err = reinterpret_cast<int*>(work + L.err);
+  D.states = reinterpret_cast<uint32_t*>(work + L.states);
+  KPM_HIP(hipMemsetAsync(D.err, 0, sizeof(int), st));
+  if (D.row_ld || D.block) KPM_HIP(fill_states(D, st));
+  double* vec = reinterpret_cast<double*>(work + L.vec);
+  double* vecC = reinterpret_cast<double*>(work + L.vecC);
+  double* part = reinterpret_cast<double*>(work + L.part);
+  double* dots = reinterpret_cast<double*>(work + L.dots);
+  double* b2 = reinterpret_cast<double*>(work + L.b2);
+  double* zero = reinterpret_cast<double*>(work + L.zero);
+  double* norm = reinterpret_cast<double*>(work + L.norm);
+  const int TC = D.total_cols;
+  KPM_HIP(hipMemsetAsync(vec, 0, (size_t)D.vec_elems * 8, st));
+  KPM_HIP(hipMemsetAsync(vecC, 0, (size_t)D.vec_elems * 8, st));
+  KPM_HIP(hipMemsetAsync(zero, 0, (size_t)TC * 8, st));
+  // unit-norm start columns (the random vectors of Eq. (7)), |column|^2 kept
+  KPM_HIP(launch_init(D, vec, 0, q->vec_kind, q->seed, nullptr, part, st));
+  KPM_HIP(launch_reduce(D, part, norm, nullptr, st));
+  KPM_HIP(launch_init(D, vec, 2, q->vec_kind, q->seed, norm, part, st));
+  for (int j = 0; j < steps; ++j) {
+    KPM_HIP(launch_step(D, vec, part, nullptr, 0, nullptr, nullptr, nullptr, 0, 0, 1, st));
+    LzArgs a1{};
+    a1.w = vec; a1.w_hi = 1;
+    a1.q = vecC; a1.q_hi = 0;
+    a1.coef = j ? b2 + (size_t)(j - 1) * TC : zero;
+    a1.coef_sqrt = 1;
+    a1.dotvec = vec; a1.d_hi = 0;
+    a1.part_out = part;
+    KPM_HIP(launch_lz_axpy(D, a1, st));
+    KPM_HIP(launch_reduce(D, part, dots + (size_t)j * TC, nullptr, st));
+    LzArgs a2{};
+    a2.w = vec; a2.w_hi = 1;
+    a2.q = vec; a2.q_hi = 0;
+    a2.coef = dots + (size_t)j * TC;
+    a2.dotvec = nullptr;
+    a2.part_out = part;
+    KPM_HIP(launch_lz_axpy(D, a2, st));
+    KPM_HIP(launch_reduce(D, part, b2 + (size_t)j * TC, nullptr, st));
+    KPM_HIP(launch_lz_next(D, vecC, vec, vec, b2 + (size_t)j * TC, st));
+  }
+  // thermodynamic metadata (sector weights, S^z, clusters)
+  std::vector<ThermoProb> tp;
+  std::vector<int32_t> start, list;
+  int nc = 0;
+  r = thermo_meta(p, n, tp, start, list, nc);
+  if (r != KPM_OK) return r;
+  DevBuf meta;
+  const size_t otp = 0, ost = align_up(tp.size() * sizeof(ThermoProb)),
+               oli = ost + align_up(start.size() * 4);
+  r = meta.alloc(oli + list.size() * 4);
+  if (r != KPM_OK) return r;
+  unsigned char* mb = static_cast<unsigned char*>(meta.p);
+  KPM_HIP(hipMemcpyAsync(mb + otp, tp.data(), tp.size() * sizeof(ThermoProb), hipMemcpyHostToDevice, st));
+  KPM_HIP(hipMemcpyAsync(mb + ost, start.data(), start.size() * 4, hipMemcpyHostToDevice, st));
+  KPM_HIP(hipMemcpyAsync(mb + oli, list.data(), list.size() * 4, hipMemcpyHostToDevice, st));
+  FtlmArgs fa{};
+  fa.probs = D.probs;
+  fa.units = D.units;
+  fa.job_unit = D.job_unit;
+  fa.prob_unit0 = D.prob_unit0;
+  fa.dots = dots;
+  fa.b2 = b2;
+  fa.norms = norm;
+  fa.ritz = reinterpret_cast<double*>(work + L.ritz);
+  fa.escr = reinterpret_cast<double*>(work + L.escr);
+  fa.weight = reinterpret_cast<double*>(work + L.weight);
+  fa.len = reinterpret_cast<int32_t*>(work + L.len);
+  fa.err = D.err;
+  fa.total_cols = TC;
+  fa.steps = steps;
+  fa.vec_kind = q->vec_kind;
+  fa.R = q->vec_kind == KPM_VEC_BASIS ? 0 : q->R;
+  fa.tp = reinterpret_cast<ThermoProb*>(mb + otp);
+  fa.cl_start = reinterpret_cast<int32_t*>(mb + ost);
+  fa.cl_list = reinterpret_cast<int32_t*>(mb + oli);
+  fa.T = d_T;
+  fa.h = d_h;
+  fa.lnZ = d_lnZ;
+  fa.E = d_E;
+  fa.C = d_C;
+  fa.chi = d_chi;
+  fa.mag = d_mag;
+  fa.n_pts = n_pts;
+  fa.n_clusters = nc;
+  KPM_HIP(launch_ftlm_ritz(fa, st));
+  KPM_HIP(launch_ftlm_thermo(fa, st));
+  if (d_ritz) KPM_HIP(hipMemcpyAsync(d_ritz, fa.ritz, (size_t)TC * steps * 8, hipMemcpyDeviceToDevice, st));
+  if (d_weight)
+    KPM_HIP(hipMemcpyAsync(d_weight, fa.weight, (size_t)TC * steps * 8, hipMemcpyDeviceToDevice, st));
+  int h_err = 0;
+  KPM_HIP(hipMemcpyAsync(&h_err, D.err, sizeof(int), hipMemcpyDeviceToHost, st));
+  KPM_HIP(hipStreamSynchronize(st));
+  return h_err ? KPM_EDEVICE : KPM_OK;
 }
 
 }  // extern "C"

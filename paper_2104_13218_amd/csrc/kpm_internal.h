@@ -217,6 +217,36 @@ struct ThermoArgs {
   double* mag;               // [n_clusters][n_T] <S^z> (field kernel, may be NULL)
 };
 
+// Finite-temperature Lanczos: Ritz values/weights per column and the sums.
+struct FtlmArgs {
+  const ProbDev* probs;
+  const UnitDev* units;
+  const int32_t* job_unit;
+  const int32_t* prob_unit0;
+  const double* dots;        // [steps][total_cols] alpha_j
+  const double* b2;          // [steps][total_cols] beta_j^2
+  const double* norms;       // [total_cols] |start column|^2
+  double* ritz;              // [total_cols][steps]
+  double* escr;              // [total_cols][steps] scratch
+  double* weight;            // [total_cols][steps]
+  int32_t* len;              // [total_cols] Ritz values per column
+  int* err;                  // bit 3: QL did not converge
+  int32_t total_cols, steps, vec_kind, R;
+  const ThermoProb* tp;
+  const int32_t* cl_start;
+  const int32_t* cl_list;
+  const double* T;           // [n_pts]
+  const double* h;           // [n_pts] Zeeman energies or NULL
+  double* lnZ;
+  double* E;
+  double* C;
+  double* chi;
+  double* mag;               // may be NULL
+  int32_t n_pts, n_clusters;
+};
+hipError_t launch_ftlm_ritz(const FtlmArgs& a, hipStream_t st);
+hipError_t launch_ftlm_thermo(const FtlmArgs& a, hipStream_t st);
+
 struct ThermoVjpArgs {
   const ThermoProb* tp;
   const double* ab;

@@ -1,0 +1,71 @@
+// Symmetric tridiagonal eigenproblem for the Lanczos quadrature of the
+// finite-temperature Lanczos method: eigenvalues of T (diagonal d[0..n),
+// off-diagonal e[i] between rows i and i+1, i < n-1) and the first component
+// of every normalised eigenvector, by the implicit QL method with the shift
+// from the trailing 2x2 block.  Only row 0 of the accumulated plane rotations
+// is kept (it starts as the unit vector e_0), so the cost is O(n^2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+namespace kpm {
+
+// d[n], e[n] (e[n-1] is scratch), z[n] out: d -> eigenvalues (unordered),
+// z -> first eigenvector components.  Returns false if an eigenvalue needed
+// more than 60 sweeps.
+__host__ __device__ inline bool tridiag_ql_first_row(double* d, double* e, double* z, int n) {
+  for (int i = 0; i < n; ++i) z[i] = i == 0 ? 1.0 : 0.0;
+  if (n <= 0) return true;
+  e[n - 1] = 0.0;
+  for (int l = 0; l < n; ++l) {
+    int iter = 0;
+    int m;
+    do {
+      // smallest m >= l whose off-diagonal is negligible next to its diagonal pair
+      for (m = l; m < n - 1; ++m) {
+        const double dd = fabs(d[m]) + fabs(d[m + 1]);
+        if (fabs(e[m]) + dd == dd) break;
+      }
+      if (m != l) {
+        if (++iter > 60) return false;
+        double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+        double r = hypot(g, 1.0);
+        g = d[m] - d[l] + e[l] / (g + copysign(r, g));
+        double s = 1.0, c = 1.0, p = 0.0;
+        int i;
+        bool deflated = false;
+        for (i = m - 1; i >= l; --i) {
+          double f = s * e[i];
+          const double b = c * e[i];
+          r = hypot(f, g);
+          e[i + 1] = r;
+          if (r == 0.0) {
+            d[i + 1] -= p;
+            e[m] = 0.0;
+            deflated = true;
+            break;
+          }
+          s = f / r;
+          c = g / r;
+          g = d[i + 1] - p;
+          r = (d[i] - g) * s + 2.0 * c * b;
+          p = s * r;
+          d[i + 1] = g + p;
+          g = c * r - b;
+          f = z[i + 1];
+          z[i + 1] = s * z[i] + c * f;
+          z[i] = c * z[i] - s * f;
+        }
+        if (deflated) continue;
+        d[l] -= p;
+        e[l] = g;
+        e[m] = 0.0;
+      }
+    } while (m != l);
+  }
+  return true;
+}
+
+}  // namespace kpm

@@ -69,6 +69,10 @@ _SIGS = {
     "kpm_thermo_field": (c_int32, [c_void_p, c_void_p, POINTER(Problem), c_int32, c_int32, c_int32,
                                    c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_void_p, c_void_p, c_void_p]),
+    "kpm_ftlm_workspace_size": (c_size_t, [POINTER(Problem), c_int32, POINTER(Params)]),
+    "kpm_ftlm": (c_int32, [POINTER(Problem), c_int32, POINTER(Params), c_void_p, c_void_p, c_int32,
+                           c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                           c_void_p, c_size_t, c_void_p]),
     "kpm_thermo_vjp": (c_int32, [c_void_p, c_void_p, POINTER(Problem), c_int32, c_int32, c_int32,
                                  c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "chebyshev_moments_vjp_workspace_size": (c_size_t, [POINTER(Problem), c_int32, POINTER(Params),
@@ -258,6 +262,38 @@ def thermo_field(mu, ab, sectors, T, h, kernel="jackson", n_nodes=0, stream=None
                                    _ptr(T), _ptr(h), nT, _ptr(out["lnZ"]), _ptr(out["E"]), _ptr(out["C"]),
                                    _ptr(out["chi"]), _ptr(out["M"]), _ptr(out["z_nonpos"]), _stream(stream)),
            "kpm_thermo_field")
+    return out
+
+
+def ftlm(sectors, krylov_dim, R=1, vec_kind="rademacher", T=(1.0,), h=None, seed=0, ritz=False,
+         stream=None):
+    """Finite-temperature Lanczos thermodynamics: ln Z, E, C, chi, M = <S^z>
+    [n_clusters, n_pts] at the points (T, h); with ritz=True also the Ritz
+    values and estimator weights [real columns, steps]."""
+    ps = sectors if isinstance(sectors, ProblemSet) else ProblemSet(sectors)
+    q = make_params(krylov_dim, R, vec_kind, "fp64", 0.0, seed)
+    T = torch.as_tensor(T, dtype=torch.float64, device="cuda").contiguous()
+    hh = None if h is None else torch.as_tensor(h, dtype=torch.float64, device="cuda").expand_as(T).contiguous()
+    nc, nT = ps.n_clusters, T.numel()
+    out = {k: torch.empty((nc, nT), dtype=torch.float64, device="cuda") for k in ("lnZ", "E", "C", "chi", "M")}
+    lib = load()
+    nbytes = lib.kpm_ftlm_workspace_size(ps.arr, len(ps), ctypes.byref(q))
+    if nbytes == 0:
+        raise KPMError(KPM_EINVAL, "kpm_ftlm_workspace_size")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    rz = wt = None
+    if ritz:
+        dims = [s.dim for s in ps.sectors]
+        cols = sum(s.dim if vec_kind == "basis" else R * (2 if vec_kind == "complex_gaussian" else 1)
+                   for s in ps.sectors)
+        steps = max(1, min(krylov_dim, max(dims)))
+        rz = torch.empty((cols, steps), dtype=torch.float64, device="cuda")
+        wt = torch.empty_like(rz)
+    _check(lib.kpm_ftlm(ps.arr, len(ps), ctypes.byref(q), _ptr(T), _ptr(hh), nT, _ptr(out["lnZ"]), _ptr(out["E"]),
+                        _ptr(out["C"]), _ptr(out["chi"]), _ptr(out["M"]), _ptr(rz), _ptr(wt), _ptr(ws),
+                        ws.numel(), _stream(stream)), "kpm_ftlm")
+    if ritz:
+        out["ritz"], out["weight"] = rz, wt
     return out
 
 

@@ -1,0 +1,93 @@
+"""GPU vs oracle: the finite-temperature Lanczos method (the paper's comparison
+method, Introduction and Sec. III.C) run on the library's recursion kernels.
+
+* Ritz values and estimator weights per real column within 1e-10 (relative
+  to the spectral width, resp. to dim/R) for Krylov spaces short enough that
+  the Lanczos vectors of both sides are still orthogonal to working precision;
+* thermodynamics (ln Z, E, C, chi, <S^z>, with and without the Zeeman term)
+  within 1e-9 of the oracle on the same seeds;
+* complete basis = exact diagonalisation."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import ed, ftlm, hamiltonian
+
+pytestmark = pytest.mark.gpu
+
+
+def _probs(secs):
+    return [dict(cluster=s.cluster_id, n_sites=s.cluster.n_sites, n_up=s.n_up) for s in secs]
+
+
+def _oracle_lists(secs, M_L, R, kind, seed):
+    return [ftlm.sector_ritz(s, M_L, R, kind, seed) for s in secs]
+
+
+@pytest.mark.parametrize("kind,R", [("rademacher", 3), ("complex_gaussian", 2), ("gaussian", 2)])
+def test_ritz_values_and_weights(kpm, kind, R):
+    secs = W.sectors(W.ring(10))
+    M_L = 10
+    out = kpm.ftlm(secs, M_L, R, kind, T=[1.0], seed=7, ritz=True)
+    rz, wt = out["ritz"].cpu().numpy(), out["weight"].cpu().numpy()
+    lists = _oracle_lists(secs, M_L, R, kind, 7)
+    c = 0
+    for s, lst in zip(secs, lists):
+        for e_ref, w_ref in lst:
+            n = e_ref.size
+            order = np.argsort(rz[c, :n])
+            e, w = rz[c, :n][order], wt[c, :n][order]
+            width = max(1.0, np.abs(e_ref).max())
+            assert np.abs(e - e_ref).max() <= 1e-10 * width, (s.n_up, c)
+            assert np.abs(w - w_ref).max() <= 1e-10 * s.dim / R, (s.n_up, c)
+            assert np.all(rz[c, n:] == 0.0) and np.all(wt[c, n:] == 0.0)
+            c += 1
+    assert c == rz.shape[0]
+
+
+@pytest.mark.parametrize("kind,R,field", [("rademacher", 4, False), ("complex_gaussian", 2, True)])
+def test_thermodynamics_vs_oracle(kpm, kind, R, field):
+    """Two clusters (ladder and ring) with every S^z >= 0 sector; 30 Lanczos steps."""
+    secs = W.sectors(W.ladder(10), cluster_id=0) + W.sectors(W.ring(9), cluster_id=1)
+    M_L = 30
+    T = W.log_temperatures(40, 0.05, 10.0)
+    h = np.linspace(0.0, 1.5, T.size) if field else 0.0
+    out = kpm.ftlm(secs, M_L, R, kind, T=T, h=h if field else None, seed=3)
+    ref = ftlm.ftlm_thermo(_probs(secs), _oracle_lists(secs, M_L, R, kind, 3), T, h)
+    for q in ("lnZ", "E", "C", "chi", "M"):
+        g, w = out[q].cpu().numpy(), ref[q]
+        scale = max(1.0, np.abs(w).max())
+        assert np.abs(g - w).max() <= 1e-9 * scale, (q, np.abs(g - w).max())
+
+
+def test_complete_basis_equals_ed(kpm):
+    cl = W.ring(8)
+    secs = W.sectors(cl)
+    T = W.log_temperatures(25, 0.1, 10.0)
+    out = kpm.ftlm(secs, 70, 0, "basis", T=T)
+    ref = ed.thermo_from_spectra(ed.sector_spectra(secs), T)
+    for q in ("lnZ", "E", "C", "chi"):
+        g = out[q].cpu().numpy()[0]
+        assert np.abs(g - ref[q]).max() <= 1e-8 * max(1.0, np.abs(ref[q]).max()), q
+    assert np.abs(out["M"].cpu().numpy()).max() <= 1e-12
+
+
+def test_dimension_one_and_short_sectors(kpm):
+    """Sectors with dim < M_L (down to dim 1) stop at their dimension."""
+    secs = W.sectors(W.ring(6))
+    out = kpm.ftlm(secs, 50, 2, "rademacher", T=[0.3, 3.0], seed=1, ritz=True)
+    ref = ftlm.ftlm_thermo(_probs(secs), _oracle_lists(secs, 50, 2, "rademacher", 1), [0.3, 3.0])
+    for q in ("lnZ", "E", "C", "chi"):
+        assert np.abs(out[q].cpu().numpy() - ref[q]).max() <= 1e-9 * max(1.0, np.abs(ref[q]).max()), q
+    rz = out["ritz"].cpu().numpy()
+    assert rz.shape[1] == 20          # largest sector of the N=6 ring
+
+
+def test_rejects_float32_storage(kpm):
+    secs = W.sectors(W.ring(6))
+    ps = kpm.ProblemSet(secs)
+    q = kpm.make_params(10, 2, "rademacher", "fp32", 0.0, 0)
+    assert kpm.load().kpm_ftlm_workspace_size(ps.arr, len(ps), ctypes.byref(q)) == 0
