@@ -42,7 +42,7 @@ if ROOT not in sys.path:
 METRIC = "Chebyshev steps·dim/s + HBM GB/s at N=24 S^z=0; speedup vs FP64 at C(T) err"
 HBM_PEAK_GBS = 8000.0
 # step kernel families as reported by kpm_last_run_stats()["kernel"]
-KERNEL_FAMILY = {0: "step_kernel", 1: "row_kernel", 2: "block_kernel"}
+KERNEL_FAMILY = {0: "step_kernel", 1: "row_kernel", 2: "block_kernel", 3: "tab_kernel"}
 PROFILES = os.path.join(ROOT, "profiles")
 
 

@@ -261,12 +261,16 @@ typedef struct {
   double bytes_per_launch; /* algorithmic HBM bytes of one step: 3 * storage
                               size * sum over blocks of dim * real columns,
                               + 4 * dim per block for the row and block
-                              kernels (they stream the 4-byte state words) */
+                              kernels (they stream the 4-byte state words);
+                              the block-table kernel reads per-block tables
+                              instead: per block of low-bit states
+                              12 + 6 * (high-high bonds) + 4 * (mixed bonds) */
   double state_col_steps;  /* sum over blocks of dim * real columns * steps */
   int32_t col_block;       /* real columns per block chosen */
-  int32_t rows_per_tile;   /* basis states per workgroup tile (block kernel: mean) */
+  int32_t rows_per_tile;   /* basis states per workgroup tile (block kernels: mean) */
   int32_t graph_segment;   /* steps per captured graph (0 = direct launches) */
-  int32_t kernel;          /* step kernel used: 0 column-chunk, 1 row, 2 block */
+  int32_t kernel;          /* step kernel used: 0 column-chunk, 1 row, 2 block,
+                              3 block-table */
   double recursion_ms;     /* hipEvent time on the call's stream from the first
                               to the last recursion-step launch, inclusive */
 } kpm_run_stats;

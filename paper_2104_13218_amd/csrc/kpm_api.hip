@@ -149,11 +149,12 @@ size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 // Launch shape chosen by the autotuner (0 / -1 = the planner's heuristic);
 // KPM_* environment variables, when set, override both.
 struct Tune {
-  int kernel = -1;        // -1 heuristic, 0 column-chunk, 1 row, 2 block
+  int kernel = -1;        // -1 heuristic, 0 column-chunk, 1 row, 2 block, 3 block-table
   int col_block = 0;      // real columns per block
   int block_L = 0;        // low bits of a block (block kernel)
   int spt = 0;            // sub-tiles per workgroup (block kernel) / tiles' sub-tiles
   int gather_batch = 0;   // neighbour rows in flight per lane
+  int lds_x = -1;         // block-table kernel: 1 rows of v_n staged in LDS, 0 not, -1 heuristic
 };
 
 struct RunShape {
@@ -186,12 +187,16 @@ struct Planned {
   std::vector<double> boff, bzz;
   std::vector<uint16_t> bperm, lrank;
   std::vector<int32_t> tile_sub0, sub_nrows;
+  // block-table kernel: blocks of every problem, sub-tile -> blocks, low-word tables
+  std::vector<uint32_t> blk_h, blk_start;
+  std::vector<int32_t> sub_blk0, sub_nblk, koff;
+  std::vector<uint16_t> lunr;
   DevicePlan plan;
   double bytes_per_step = 0;     // algorithmic (3 * storage * dim * real columns)
   double state_cols = 0;         // sum of dim * real columns
   // byte offsets of the packed plan arrays
   size_t o_probs, o_units, o_tile, o_job, o_pu0, o_tab, o_mask, o_off, o_zz, o_binom, o_trow0,
-      o_tnrows, o_bperm, o_tsub0, o_subn, o_lrank, bytes;
+      o_tnrows, o_bperm, o_tsub0, o_subn, o_lrank, o_bh, o_bst, o_sb0, o_snb, o_lunr, o_koff, bytes;
 };
 
 int env_int(const char* name, int dflt) {
@@ -215,30 +220,47 @@ int pick_col_block(const kpm_problem* p, int n, const RunShape& s) {
 // Tiles of whole blocks for the block kernel: the blocks of sector (N, k)
 // with L low bits, in rank order (ascending high bits h), packed greedily into
 // tiles of at most `rows` states and `blk_max` blocks.
+// With `blocks` the blocks themselves are listed too (high word, first rank)
+// and each sub-tile's first block index and block count.
+struct BlockList {
+  std::vector<uint32_t> h, start;
+  std::vector<int32_t> sub_b0, sub_nb;
+};
+
 void block_tiles(int N, int k, int L, int rows, int blk_max, std::vector<int64_t>& row0,
-                 std::vector<int32_t>& nrows) {
+                 std::vector<int32_t>& nrows, BlockList* blocks = nullptr) {
   const uint64_t nh = 1ull << (N - L);
   int64_t start = 0, cur0 = 0;
-  int cur_rows = 0, cur_blk = 0;
+  int cur_rows = 0, cur_blk = 0, cur_b0 = 0, nblk = 0;
+  auto close = [&]() {
+    row0.push_back(cur0);
+    nrows.push_back(cur_rows);
+    if (blocks) {
+      blocks->sub_b0.push_back(cur_b0);
+      blocks->sub_nb.push_back(cur_blk);
+    }
+  };
   for (uint64_t h = 0; h < nh; ++h) {
     const int c = k - __builtin_popcountll(h);
     if (c < 0 || c > L) continue;
     const int size = (int)binom64(L, c);
     if (cur_blk > 0 && (cur_rows + size > rows || cur_blk == blk_max)) {
-      row0.push_back(cur0);
-      nrows.push_back(cur_rows);
+      close();
       cur0 = start;
       cur_rows = 0;
       cur_blk = 0;
+      cur_b0 = nblk;
+    }
+    if (blocks) {
+      blocks->h.push_back((uint32_t)h);
+      blocks->start.push_back((uint32_t)start);
     }
     cur_rows += size;
     ++cur_blk;
+    ++nblk;
     start += size;
   }
-  if (cur_blk > 0) {
-    row0.push_back(cur0);
-    nrows.push_back(cur_rows);
-  }
+  if (cur_blk > 0) close();
 }
 
 // a, b per problem must already be known (scale != nullptr) for the bond
@@ -340,14 +362,21 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   D.block = 0;
   std::vector<std::vector<int64_t>> btile_row0(n);
   std::vector<std::vector<int32_t>> btile_nrows(n);
+  std::vector<BlockList> blists(n);
   // Default: float32 storage with blocks too wide for the row kernel (the
   // measured case where it is the fastest kernel); KPM_BLOCK=0/1 overrides.
-  const int block_env = env_int("KPM_BLOCK", kern < 0 ? -1 : (kern == 2 ? 1 : 0));
-  const bool block_default = fp32 && rb > 8;
-  if (!s.adjoint && s.allow_row && (block_env == 1 || (block_env < 0 && block_default))) {
+  // Default: the block-table kernel for blocks too wide for the row kernel
+  // (the measured case where it is the fastest kernel); KPM_BLOCK=0/1/2 and
+  // the autotuner override.
+  const int block_env = env_int("KPM_BLOCK", kern < 0 ? -1 : (kern == 2 ? 1 : (kern == 3 ? 2 : 0)));
+  const bool block_default = rb > 8;
+  const bool tab = block_env == 2 || (block_env < 0 && block_default);
+  if (!s.adjoint && s.allow_row && (block_env == 1 || tab || (block_env < 0 && block_default))) {
     D.ld_max = adj_ld ? adj_ld : (rb + cpl - 1) / cpl * cpl;
     D.blk_max = std::max(1, std::min(255, env_int("KPM_BLOCK_MAX", 16)));
     const size_t cap = (size_t)env_int("KPM_BLOCK_LDS", 64 * 1024);
+    // rows of v_n staged in LDS: measured faster for float32 storage only
+    D.tab_xl = tab ? env_int("KPM_TAB_XL", s.tune.lds_x >= 0 ? s.tune.lds_x : fp32) != 0 : 0;
     for (int rows = std::min(kThreads, std::max(32, env_int("KPM_BLOCK_ROWS", kThreads)));
          rows >= 32 && !D.block; rows >>= 1) {
       int Lm = std::max(1, std::min(env_int("KPM_BLOCK_L", s.tune.block_L > 0 ? s.tune.block_L : 9), 16));
@@ -378,7 +407,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
       D.lds_lr = lr;
       D.lds_hh = hh;
       D.lds_mx = mx;
-      if (block_lds_bytes(D) <= cap) D.block = 1;
+      if ((tab ? tab_lds_bytes(D) : block_lds_bytes(D)) <= cap) D.block = tab ? 2 : 1;
     }
   }
   int bspt = 1;
@@ -394,8 +423,19 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
     size_t max_sub = 1;
     int maxL = 1;
     for (int i = 0; i < n; ++i) {
+      BlockList* bl = nullptr;
+      if (D.block >= 2) {
+        bl = &blists[i];
+        P.probs[i].blk_off = (int32_t)P.blk_h.size();
+      }
       block_tiles(p[i].n_sites, p[i].n_up, P.probs[i].blk_L, D.blk_rows, D.blk_max, btile_row0[i],
-                  btile_nrows[i]);
+                  btile_nrows[i], bl);
+      if (bl) {
+        if (P.blk_h.size() + bl->h.size() > (size_t)INT32_MAX) return KPM_EINVAL;
+        P.probs[i].n_blk = (int32_t)bl->h.size();
+        P.blk_h.insert(P.blk_h.end(), bl->h.begin(), bl->h.end());
+        P.blk_start.insert(P.blk_start.end(), bl->start.begin(), bl->start.end());
+      }
       max_sub = std::max(max_sub, btile_row0[i].size());
       maxL = std::max(maxL, P.probs[i].blk_L);
     }
@@ -407,6 +447,19 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
       for (int q = 0; q < maxL; ++q)
         if ((l >> q) & 1u) r += binom64(q, ++j);
       P.lrank[l] = (uint16_t)r;
+    }
+    if (D.block >= 2) {
+      // low words by popcount class, each class in colex order (its first
+      // C(L, k) entries are the L-bit words for any L <= maxL)
+      P.koff.assign(kKoffLen, 0);
+      for (int k = 0; k + 1 < kKoffLen; ++k)
+        P.koff[k + 1] = P.koff[k] + (k <= maxL ? (int32_t)binom64(maxL, k) : 0);
+      P.lunr.assign(size_t(1) << maxL, 0);
+      for (uint32_t l = 0; l < (1u << maxL); ++l)
+        P.lunr[P.koff[__builtin_popcount(l)] + P.lrank[l]] = (uint16_t)l;
+      D.meta_hh = D.lds_hh;
+      D.meta_mx = D.lds_mx;
+      D.n_blk = (int32_t)P.blk_h.size();
     }
     // Sub-tiles per workgroup: amortise the per-workgroup LDS fill (tables,
     // bonds, ranks) over the streamed rows, keeping >= 2048 workgroups on the
@@ -468,6 +521,10 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
           for (size_t k = s0; k < s1; ++k) {
             P.sub_nrows.push_back(btile_nrows[i][k]);
             rows += btile_nrows[i][k];
+            if (D.block >= 2) {
+              P.sub_blk0.push_back(P.probs[i].blk_off + blists[i].sub_b0[k]);
+              P.sub_nblk.push_back(blists[i].sub_nb[k]);
+            }
           }
           P.tile_row0.push_back(btile_row0[i][s0]);
           P.tile_nrows.push_back(rows);
@@ -485,9 +542,17 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
     }
   }
   P.prob_unit0.push_back((int32_t)P.units.size());
-  // the row and block kernels also stream the 4-byte state word of every row
-  if (D.row_ld || D.block)
+  // the row and block kernels also stream the 4-byte state word of every row;
+  // the block-table kernel reads its per-block tables instead
+  if (D.block >= 2) {
+    for (const auto& u : P.units) {
+      const ProbDev& d = P.probs[u.prob];
+      P.bytes_per_step += (double)d.n_blk * (12.0 + 6.0 * d.n_hh + 4.0 * d.n_mx);
+    }
+    D.n_states = (int64_t)((tab_meta_bytes(D) + 3) / 4);
+  } else if (D.row_ld || D.block) {
     for (const auto& u : P.units) P.bytes_per_step += 4.0 * (double)P.probs[u.prob].dim;
+  }
   P.tile_sub0.push_back((int32_t)P.sub_nrows.size());
   if (P.sub_nrows.empty()) P.sub_nrows.push_back(0);
   if (P.lrank.empty()) P.lrank.push_back(0);
@@ -523,6 +588,12 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   P.o_tsub0 = put(P.tile_sub0.size() * 4);
   P.o_subn = put(P.sub_nrows.size() * 4);
   P.o_lrank = put(P.lrank.size() * 2);
+  P.o_bh = put(P.blk_h.size() * 4);
+  P.o_bst = put(P.blk_start.size() * 4);
+  P.o_sb0 = put(P.sub_blk0.size() * 4);
+  P.o_snb = put(P.sub_nblk.size() * 4);
+  P.o_lunr = put(P.lunr.size() * 2);
+  P.o_koff = put(P.koff.size() * 4);
   P.bytes = o;
   return KPM_OK;
 }
@@ -550,6 +621,12 @@ int upload_plan(Planned& P, unsigned char* dst, std::vector<unsigned char>& stag
   cp(P.o_tsub0, P.tile_sub0.data(), P.tile_sub0.size() * 4);
   cp(P.o_subn, P.sub_nrows.data(), P.sub_nrows.size() * 4);
   cp(P.o_lrank, P.lrank.data(), P.lrank.size() * 2);
+  cp(P.o_bh, P.blk_h.data(), P.blk_h.size() * 4);
+  cp(P.o_bst, P.blk_start.data(), P.blk_start.size() * 4);
+  cp(P.o_sb0, P.sub_blk0.data(), P.sub_blk0.size() * 4);
+  cp(P.o_snb, P.sub_nblk.data(), P.sub_nblk.size() * 4);
+  cp(P.o_lunr, P.lunr.data(), P.lunr.size() * 2);
+  cp(P.o_koff, P.koff.data(), P.koff.size() * 4);
   KPM_HIP(hipMemcpyAsync(dst, staging.data(), P.bytes, hipMemcpyHostToDevice, st));
   DevicePlan& D = P.plan;
   D.probs = reinterpret_cast<ProbDev*>(dst + P.o_probs);
@@ -568,6 +645,12 @@ int upload_plan(Planned& P, unsigned char* dst, std::vector<unsigned char>& stag
   D.tile_sub0 = reinterpret_cast<int32_t*>(dst + P.o_tsub0);
   D.sub_nrows = reinterpret_cast<int32_t*>(dst + P.o_subn);
   D.lrank = reinterpret_cast<uint16_t*>(dst + P.o_lrank);
+  D.blk_h = reinterpret_cast<uint32_t*>(dst + P.o_bh);
+  D.blk_start = reinterpret_cast<uint32_t*>(dst + P.o_bst);
+  D.sub_blk0 = reinterpret_cast<int32_t*>(dst + P.o_sb0);
+  D.sub_nblk = reinterpret_cast<int32_t*>(dst + P.o_snb);
+  D.lunr = reinterpret_cast<uint16_t*>(dst + P.o_lunr);
+  D.koff = reinterpret_cast<int32_t*>(dst + P.o_koff);
   return KPM_OK;
 }
 
@@ -857,6 +940,15 @@ std::vector<Tune> tune_candidates(const kpm_problem* p, int n, const kpm_params&
           b.spt = spt;
           c.push_back(b);
         }
+    for (int xl : {0, 1})
+      for (int spt : {2, 4}) {
+        Tune b = t;
+        b.kernel = 3;
+        b.block_L = 9;
+        b.spt = spt;
+        b.lds_x = xl;
+        c.push_back(b);
+      }
   }
   return c;
 }
@@ -1068,7 +1160,7 @@ int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
     for (int32_t r : P.tile_nrows) rows += r;
     g_stats.rows_per_tile = (int32_t)std::lround(rows / (double)P.tile_nrows.size());
   }
-  g_stats.kernel = D.block ? 2 : (D.row_ld ? 1 : 0);
+  g_stats.kernel = D.block == 2 ? 3 : (D.block ? 2 : (D.row_ld ? 1 : 0));
   g_stats.graph_segment = used_segment;
   float ms = 0.f;
   g_stats.recursion_ms = hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess ? (double)ms : -1.0;

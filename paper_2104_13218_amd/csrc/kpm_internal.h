@@ -13,6 +13,7 @@ constexpr int kThreads = 256;     // threads per workgroup (4 wave64)
 constexpr int kMaxBonds = 512;    // bonds per problem
 constexpr int kMaxLd = 64;        // real columns per recursion block (padded)
 constexpr int kBinomN = 33;       // binomial table C(n, j), n, j < 33
+constexpr int kKoffLen = 34;      // popcount-class offsets of the low-word table (0..32, end)
 
 // One (cluster, S^z sector) problem as the kernels see it.
 struct ProbDev {
@@ -27,6 +28,9 @@ struct ProbDev {
   // inside its block; bonds in class order (low-low, high-high, mixed) are
   // listed by bperm[bond_off + q].
   int32_t blk_L, n_ll, n_hh, n_mx;
+  // Block-table kernel: this problem's blocks are [blk_off, blk_off + n_blk)
+  // of the plan's block list (ascending h, i.e. rank order).
+  int32_t blk_off, n_blk;
 };
 
 // One recursion block: a problem and a contiguous range of its real columns.
@@ -89,6 +93,18 @@ struct StepArgs {
   const int32_t* tile_sub0;    // [n_tiles + 1]: sub-tiles of tile t are [tile_sub0[t], tile_sub0[t+1])
   const int32_t* sub_nrows;    // states of each sub-tile (consecutive from tile_row0)
   const uint16_t* lrank;       // colex rank of every low word (1 << max blk_L entries)
+  // block-table kernel
+  const uint32_t* blk_h;       // [n_blk] high word h of each block
+  const uint32_t* blk_start;   // [n_blk] rank of the block's first state in its sector
+  const int32_t* sub_blk0;     // per sub-tile: first block (global block index)
+  const int32_t* sub_nblk;     // per sub-tile: blocks
+  const uint16_t* lunr;        // low words by (popcount, colex rank): lunr[koff[k] + i]
+  const int32_t* koff;         // [kKoffLen] start of popcount class k in lunr
+  const uint32_t* meta_hcnt;   // [n_blk] acting high-high bonds of the block
+  const uint32_t* meta_hstart; // [n_blk][meta_hh] first rank of each target block (acting first)
+  const uint16_t* meta_hq;     // [n_blk][meta_hh] its bond index inside the high-high class
+  const uint32_t* meta_mstart; // [n_blk][meta_mx] per mixed bond: target block's first rank
+  int32_t meta_hh, meta_mx;    // row lengths of the per-block tables (>= 1)
 };
 
 // Device-side plan of one run (pointers into the workspace) + launch shape.
@@ -110,6 +126,12 @@ struct DevicePlan {
   int32_t* tile_sub0 = nullptr;  // block kernel: sub-tile range of each tile
   int32_t* sub_nrows = nullptr;  // block kernel: states of each sub-tile
   uint16_t* lrank = nullptr;     // block kernel: low-word colex ranks
+  uint32_t* blk_h = nullptr;     // block-table kernel: blocks (see StepArgs)
+  uint32_t* blk_start = nullptr;
+  int32_t* sub_blk0 = nullptr;
+  int32_t* sub_nblk = nullptr;
+  uint16_t* lunr = nullptr;
+  int32_t* koff = nullptr;
   int* err = nullptr;          // device error word (see StepArgs::err)
   int32_t n_probs = 0, n_units = 0, n_tiles = 0, grid_tiles = 0, total_cols = 0;
   int32_t sub_rows = 256, sub_per_tile = 1, lds_nb = 0, lds_tab = 0, lds_bonds = 0;
@@ -119,7 +141,11 @@ struct DevicePlan {
   int32_t dense = 0;
   int32_t row_ld = 0;          // > 0: one lane per state with all row_ld columns
   int32_t gather_batch = 4;    // neighbour rows in flight per lane (2, 4 or 8)
-  int32_t block = 0;           // 1: block kernel (tiles of whole low-bit blocks)
+  int32_t block = 0;           // 1: block kernel (tiles of whole low-bit blocks),
+                               // 2: block-table kernel (same tiles, per-block tables),
+  int32_t n_blk = 0;           // block-table kernel: blocks of all problems
+  int32_t meta_hh = 1, meta_mx = 1;   // per-block table widths (StepArgs)
+  int32_t tab_xl = 0;          // block-table kernel: sub-tile rows of v_n staged in LDS
   int32_t blk_max = 16, blk_rows = kThreads, lds_lr = 1, lds_hh = 1, lds_mx = 1, ld_max = 1;
   int64_t n_states = 0;        // entries of the state table
   int64_t part_len = 0;        // doubles per partial buffer
@@ -341,6 +367,10 @@ hipError_t launch_states(int N, int k, const uint32_t* binom, uint32_t* out, int
 hipError_t fill_states(const DevicePlan& p, hipStream_t st);
 size_t row_lds_bytes(const DevicePlan& p);
 size_t block_lds_bytes(const DevicePlan& p);
+size_t tab_lds_bytes(const DevicePlan& p);
+// Bytes of the per-block tables of the block-table kernel (kept in the state
+// table region; built by fill_states).
+size_t tab_meta_bytes(const DevicePlan& p);
 hipError_t launch_matrix(const MatrixArgs& a, size_t lds, int grid, hipStream_t st);
 hipError_t launch_lz_axpy(const DevicePlan& p, const LzArgs& args, hipStream_t st);
 hipError_t launch_lz_next(const DevicePlan& p, double* qprev, double* q, const double* w,

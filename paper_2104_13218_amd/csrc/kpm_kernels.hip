@@ -1014,6 +1014,486 @@ static hipError_t launch_block(const DevicePlan& p, const StepArgs& a, hipStream
   }
 }
 
+// ----------------------------------------------------- block-table kernel
+//
+// Same tiles of whole low-bit blocks as the block kernel, but everything a
+// block needs besides its own rows is looked up in per-block tables written
+// once per call (tab_meta_kernel): the first rank of the target block of every
+// acting high-high bond (compacted, in bond order) and of every mixed bond.
+// Member i of block h (popcount class k of its low word) has the low word
+// lunr[koff[k] + i]; its neighbours are
+//   low-low    block start + lrank(l ^ m)          (same block)
+//   high-high  target start + i                    (same low word)
+//   mixed      target start + lrank(l ^ m_low)     (target class k +- 1).
+// No state words are streamed and no ranks are computed per step; the own
+// block's rows are read through L1 by the low-low bonds.  Per element the sum
+// runs diagonal, low-low, high-high, mixed (each in bond order).
+
+struct TabLds {
+  size_t mask, off, zz, lrank, lunr, koff, bstart, bh, boff, bcnt, bhs, bhq, bms, rblk, rl, ri,
+      rdiag, xs, total;
+};
+
+// xs_bytes: the sub-tile's rows of v_n in LDS (0 = read through L1).
+__host__ __device__ inline TabLds tab_lds_layout(int lds_bonds, int lds_lr, int blk_max,
+                                                 int lds_hh, int lds_mx, int rows, int cpl,
+                                                 size_t xs_bytes) {
+  TabLds L{};
+  size_t o = 0;
+  auto put = [&](size_t b) {
+    const size_t r = o;
+    o = (o + b + 15) & ~size_t(15);
+    return r;
+  };
+  L.mask = put(size_t(lds_bonds) * 4);
+  L.off = put(size_t(lds_bonds) * 8);
+  L.zz = put(size_t(lds_bonds) * 8);
+  L.lrank = put(size_t(lds_lr) * 2);
+  L.lunr = put(size_t(lds_lr) * 2);
+  L.koff = put(size_t(kKoffLen) * 4);
+  L.bstart = put(size_t(blk_max) * 4);
+  L.bh = put(size_t(blk_max) * 4);
+  L.boff = put(size_t(blk_max) * 4);
+  L.bcnt = put(size_t(blk_max) * 4);
+  L.bhs = put(size_t(blk_max) * lds_hh * 4);
+  L.bhq = put(size_t(blk_max) * lds_hh * 2);
+  L.bms = put(size_t(blk_max) * lds_mx * 4);
+  L.rblk = put(size_t(rows));
+  L.rl = put(size_t(rows) * 2);
+  L.ri = put(size_t(rows) * 2);
+  L.rdiag = put(size_t(rows) * 8);
+  L.xs = put(xs_bytes);
+  const size_t red = size_t(2 * cpl) * kThreads * 8;   // final reduction overlays all of it
+  L.total = o > red ? o : red;
+  return L;
+}
+
+size_t tab_lds_bytes(const DevicePlan& p) {
+  const size_t xs = p.tab_xl ? size_t(p.blk_rows) * p.ld_max * (p.fp32 ? 4 : 8) : 0;
+  return tab_lds_layout(p.lds_bonds, p.lds_lr, p.blk_max, p.lds_hh, p.lds_mx, p.blk_rows, p.cpl, xs)
+      .total;
+}
+
+struct TabMeta {
+  size_t hcnt, hstart, mstart, hq, total;
+};
+
+__host__ __device__ inline TabMeta tab_meta_layout(int64_t n_blk, int hh, int mx) {
+  TabMeta m{};
+  size_t o = 0;
+  auto put = [&](size_t b) {
+    const size_t r = o;
+    o = (o + b + 255) & ~size_t(255);
+    return r;
+  };
+  m.hcnt = put(size_t(n_blk) * 4);
+  m.hstart = put(size_t(n_blk) * hh * 4);
+  m.mstart = put(size_t(n_blk) * mx * 4);
+  m.hq = put(size_t(n_blk) * hh * 2);
+  m.total = o;
+  return m;
+}
+
+size_t tab_meta_bytes(const DevicePlan& p) { return tab_meta_layout(p.n_blk, p.meta_hh, p.meta_mx).total; }
+
+// Rank of the first state of block hp with k low bits set: the k lowest bits
+// contribute C(j - 1, j) = 0, so only the high bits count.
+__device__ __forceinline__ uint32_t block_first_rank(uint32_t hp, int L, int k, const uint32_t* binom) {
+  uint32_t r = 0;
+  int j = k;
+  for (uint32_t x = hp; x; x &= x - 1u) {
+    const int pos = L + __ffs(x) - 1;
+    ++j;
+    r += binom[pos * kBinomN + j];
+  }
+  return r;
+}
+
+// Per-block tables of the block-table kernel, one thread per block.
+__global__ __launch_bounds__(kThreads) void tab_meta_kernel(const ProbDev* probs,
+                                                            const uint32_t* bmask,
+                                                            const uint16_t* bperm,
+                                                            const uint32_t* binom,
+                                                            const uint32_t* blk_h, int meta_hh,
+                                                            int meta_mx, uint32_t* hcnt,
+                                                            uint32_t* hstart, uint32_t* mstart,
+                                                            uint16_t* hq, int* err) {
+  __shared__ uint32_t sb[kBinomN * kBinomN];
+  for (int i = threadIdx.x; i < kBinomN * kBinomN; i += kThreads) sb[i] = binom[i];
+  __syncthreads();
+  const ProbDev P = probs[blockIdx.y];
+  const int L = P.blk_L;
+  const int q_hh = P.bond_off + P.n_ll, q_mx = q_hh + P.n_hh;
+  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < P.n_blk;
+       t += (int64_t)gridDim.x * kThreads) {
+    const int64_t g = P.blk_off + t;
+    const uint32_t h = blk_h[g];
+    const int k = P.n_up - __popc(h);
+    int n = 0;
+    for (int q = 0; q < P.n_hh; ++q) {
+      const uint32_t mh = bmask[P.bond_off + bperm[q_hh + q]] >> L;
+      const uint32_t x = h & mh;
+      if (x == 0u || x == mh) continue;
+      const uint32_t st = block_first_rank(h ^ mh, L, k, sb);
+      if (k < 0 || k > L || (int64_t)st + sb[L * kBinomN + k] > P.dim) {
+        if (err) atomicOr(err, 2);
+        continue;
+      }
+      hstart[g * meta_hh + n] = st;
+      hq[g * meta_hh + n] = (uint16_t)q;
+      ++n;
+    }
+    hcnt[g] = (uint32_t)n;
+    for (int q = 0; q < P.n_mx; ++q) {
+      const uint32_t mh = bmask[P.bond_off + bperm[q_mx + q]] >> L;   // one high bit
+      const int kk = (h & mh) ? k + 1 : k - 1;
+      uint32_t st = kNoRun;
+      if (kk >= 0 && kk <= L) {
+        st = block_first_rank(h ^ mh, L, kk, sb);
+        if ((int64_t)st + sb[L * kBinomN + kk] > P.dim) {
+          if (err) atomicOr(err, 2);
+          st = kNoRun;
+        }
+      }
+      mstart[g * meta_mx + q] = st;
+    }
+  }
+}
+
+hipError_t build_tab_meta(const DevicePlan& p, hipStream_t st) {
+  const TabMeta m = tab_meta_layout(p.n_blk, p.meta_hh, p.meta_mx);
+  unsigned char* base = reinterpret_cast<unsigned char*>(p.states);
+  hipLaunchKernelGGL(tab_meta_kernel, dim3(256, p.n_probs), dim3(kThreads), 0, st, p.probs,
+                     p.bmask, p.bperm, p.binom, p.blk_h, p.meta_hh, p.meta_mx,
+                     reinterpret_cast<uint32_t*>(base + m.hcnt),
+                     reinterpret_cast<uint32_t*>(base + m.hstart),
+                     reinterpret_cast<uint32_t*>(base + m.mstart),
+                     reinterpret_cast<uint16_t*>(base + m.hq), p.err);
+  return hipGetLastError();
+}
+
+// XL: the sub-tile's rows of v_n are copied to LDS first and the own row and
+// the low-low neighbours are read from there.
+template <typename T, int CPL, int GB, bool XL>
+__global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x;
+
+  if (a.n_jobs > 0) {
+    const int64_t s = (a.step_base ? *a.step_base : 0) + a.step_add;
+    double* sh = reinterpret_cast<double*>(smem);
+    for (int job = blockIdx.x; job < a.n_jobs; job += gridDim.x) {
+      const UnitDev U = a.units[a.job_unit[job]];
+      const int v = job - 2 * U.col_off;
+      const double sum = sum_partials(a.part_in + U.part_off + (int64_t)v * U.ntiles, U.ntiles, sh);
+      if (tid == 0) {
+        if (v < U.ld) a.alpha[s * a.total_cols + U.col_off + v] = sum;
+        else a.beta[(s - 1) * a.total_cols + U.col_off + (v - U.ld)] = sum;
+      }
+    }
+    __syncthreads();
+  }
+
+  const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.grid_tiles) : (int)blockIdx.x;
+  if (tile >= a.n_tiles) return;
+  const UnitDev U = a.units[a.tile_unit[tile]];
+  const ProbDev P = a.probs[U.prob];
+  const TabLds Lo = tab_lds_layout(a.lds_bonds, a.lds_lr, a.blk_max, a.lds_hh, a.lds_mx,
+                                   a.blk_rows, CPL,
+                                   XL ? size_t(a.blk_rows) * a.ld_max * sizeof(T) : 0);
+  uint32_t* s_mask = reinterpret_cast<uint32_t*>(smem + Lo.mask);
+  double* s_off = reinterpret_cast<double*>(smem + Lo.off);
+  double* s_zz = reinterpret_cast<double*>(smem + Lo.zz);
+  uint16_t* s_lrank = reinterpret_cast<uint16_t*>(smem + Lo.lrank);
+  uint16_t* s_lunr = reinterpret_cast<uint16_t*>(smem + Lo.lunr);
+  int32_t* s_koff = reinterpret_cast<int32_t*>(smem + Lo.koff);
+  uint32_t* s_bstart = reinterpret_cast<uint32_t*>(smem + Lo.bstart);
+  uint32_t* s_bh = reinterpret_cast<uint32_t*>(smem + Lo.bh);
+  int32_t* s_boff = reinterpret_cast<int32_t*>(smem + Lo.boff);
+  int32_t* s_bcnt = reinterpret_cast<int32_t*>(smem + Lo.bcnt);
+  uint32_t* s_bhs = reinterpret_cast<uint32_t*>(smem + Lo.bhs);
+  uint16_t* s_bhq = reinterpret_cast<uint16_t*>(smem + Lo.bhq);
+  uint32_t* s_bms = reinterpret_cast<uint32_t*>(smem + Lo.bms);
+  uint8_t* s_rblk = reinterpret_cast<uint8_t*>(smem + Lo.rblk);
+  uint16_t* s_rl = reinterpret_cast<uint16_t*>(smem + Lo.rl);
+  uint16_t* s_ri = reinterpret_cast<uint16_t*>(smem + Lo.ri);
+  double* s_rdiag = reinterpret_cast<double*>(smem + Lo.rdiag);
+  T* xs = reinterpret_cast<T*>(smem + Lo.xs);
+
+  const int nb = P.n_bonds, nll = P.n_ll, nhh = P.n_hh, nmx = P.n_mx;
+  const int Lb = P.blk_L;
+  for (int q = tid; q < nb; q += kThreads) {
+    const int b = P.bond_off + a.bperm[P.bond_off + q];
+    s_mask[q] = a.bmask[b];
+    s_off[q] = a.boff[b];
+    s_zz[q] = a.bzz[b];
+  }
+  for (int l = tid; l < a.lds_lr; l += kThreads) {
+    s_lrank[l] = a.lrank[l];
+    s_lunr[l] = a.lunr[l];
+  }
+  for (int k = tid; k < kKoffLen; k += kThreads) s_koff[k] = a.koff[k];
+
+  const int ld = U.ld;
+  T* base = reinterpret_cast<T*>(a.vec) + U.vec_off;
+  const T* X = base + a.x_slot * a.slot_stride;
+  const T* Yin = base + a.yin_slot * a.slot_stride;
+  T* Y = base + a.yout_slot * a.slot_stride;
+  const uint32_t lmask = (1u << Lb) - 1u;
+  const int nch = ld / CPL;
+  const int nrg = kThreads / nch;
+  const int c = tid % nch;
+  const int rg = tid / nch;
+  double acc_a[CPL], acc_b[CPL];
+#pragma unroll
+  for (int i = 0; i < CPL; ++i) acc_a[i] = acc_b[i] = 0.0;
+
+  int64_t row0 = a.tile_row0[tile];
+  const int sub1 = a.tile_sub0[tile + 1];
+  for (int sub = a.tile_sub0[tile]; sub < sub1; ++sub) {
+    const int nrows = a.sub_nrows[sub];
+    const int g0 = a.sub_blk0[sub];
+    const int nblk = min(a.sub_nblk[sub], a.blk_max);
+    for (int t = tid; t < nblk; t += kThreads) {
+      const uint32_t st = a.blk_start[g0 + t];
+      s_bstart[t] = st;
+      s_bh[t] = a.blk_h[g0 + t];
+      s_boff[t] = (int)((int64_t)st - row0);
+      s_bcnt[t] = (int)min(a.meta_hcnt[g0 + t], (uint32_t)nhh);
+    }
+    for (int t = tid; t < nblk * nhh; t += kThreads) {
+      const int kb = t / nhh, j = t - kb * nhh;
+      const int64_t src = (int64_t)(g0 + kb) * a.meta_hh + j;
+      s_bhs[kb * a.lds_hh + j] = a.meta_hstart[src];
+      s_bhq[kb * a.lds_hh + j] = a.meta_hq[src];
+    }
+    for (int t = tid; t < nblk * nmx; t += kThreads) {
+      const int kb = t / nmx, j = t - kb * nmx;
+      s_bms[kb * a.lds_mx + j] = a.meta_mstart[(int64_t)(g0 + kb) * a.meta_mx + j];
+    }
+    if (XL) {
+      // the sub-tile's rows of v_n are one contiguous run of nrows * ld elements
+      const T* src = X + row0 * ld;
+      const int nv = nrows * ld / CPL;
+      for (int e = tid; e < nv; e += kThreads) vstore<T, CPL>(xs + e * CPL, vload<T, CPL>(src + e * CPL));
+    }
+    __syncthreads();
+    // Phase A: one thread per row (its block, low word and diagonal element).
+    if (tid < nrows) {
+      int kb = 0;
+      while (kb + 1 < nblk && s_boff[kb + 1] <= tid) ++kb;
+      int i = tid - s_boff[kb];
+      const uint32_t h = s_bh[kb];
+      const int k = P.n_up - __popc(h);
+      uint32_t l = 0;
+      if (k < 0 || k > Lb || i < 0 || i >= s_koff[k + 1] - s_koff[k]) {
+        if (a.err) atomicOr(a.err, 4);
+        i = 0;
+      } else {
+        l = s_lunr[s_koff[k] + i];
+      }
+      const uint32_t sw = (h << Lb) | l;
+      double d = P.shift;
+#pragma unroll 2
+      for (int q = 0; q < nb; ++q) {
+        const uint32_t m = s_mask[q];
+        const uint32_t v = sw & m;
+        d += (v == 0u || v == m) ? s_zz[q] : -s_zz[q];
+      }
+      s_rblk[tid] = (uint8_t)kb;
+      s_rl[tid] = (uint16_t)l;
+      s_ri[tid] = (uint16_t)i;
+      s_rdiag[tid] = d;
+    }
+    __syncthreads();
+
+    // Phase C: (row, column chunk) items.
+    if (rg < nrg) {
+      for (int r = rg; r < nrows; r += nrg) {
+        const int64_t rho = row0 + r;
+        const VecT<T, CPL> xv = XL ? vload<T, CPL>(xs + r * ld + c * CPL)
+                                   : vload<T, CPL>(X + rho * ld + c * CPL);
+        VecT<T, CPL> yv;
+        if (!a.first) yv = vload_nt<T, CPL>(Yin + rho * ld + c * CPL);
+        const double dg = s_rdiag[r];
+        double acc[CPL];
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) acc[i] = dg * (double)xv.v[i];
+        const uint32_t l = s_rl[r];
+        const int kb = s_rblk[r];
+        const int64_t ib = s_ri[r];
+        const int64_t bst = s_bstart[kb];
+        const uint32_t h = s_bh[kb];
+        const int nh = s_bcnt[kb];
+        const uint32_t* hs = s_bhs + kb * a.lds_hh;
+        const uint16_t* hq = s_bhq + kb * a.lds_hh;
+        const uint32_t* ms = s_bms + kb * a.lds_mx;
+        // first batch of high-high rows in flight during the low-low part
+        // (absent entries read the row itself with a zero coefficient)
+        VecT<T, CPL> hv[GB];
+        double hcf[GB];
+#pragma unroll
+        for (int j = 0; j < GB; ++j) {
+          const bool on = j < nh;
+          const int64_t row = on ? (int64_t)hs[j] + ib : rho;
+          hcf[j] = on ? s_off[nll + hq[j]] : 0.0;
+          hv[j] = vload<T, CPL>(X + row * ld + c * CPL);
+        }
+        for (int q0 = 0; q0 < nll; q0 += 4) {
+          int64_t jj[4];
+          double cl[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int q = q0 + u;
+            const uint32_t m = q < nll ? s_mask[q] : 0u;
+            const uint32_t v = l & m;
+            const bool on = !(v == 0u || v == m);
+            if (XL) jj[u] = on ? s_boff[kb] + s_lrank[l ^ m] : r;
+            else jj[u] = on ? bst + s_lrank[l ^ m] : rho;
+            cl[u] = on ? s_off[q] : 0.0;
+          }
+          VecT<T, CPL> nl[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            nl[u] = XL ? vload<T, CPL>(xs + jj[u] * ld + c * CPL) : vload<T, CPL>(X + jj[u] * ld + c * CPL);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int i = 0; i < CPL; ++i) acc[i] = fma(cl[u], (double)nl[u].v[i], acc[i]);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < GB; ++j) {
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) acc[i] = fma(hcf[j], (double)hv[j].v[i], acc[i]);
+        }
+        for (int k0 = GB; k0 < nh; k0 += GB) {
+          VecT<T, CPL> nv[GB];
+          double cf[GB];
+#pragma unroll
+          for (int j = 0; j < GB; ++j) {
+            const int k = k0 + j;
+            const bool on = k < nh;
+            const int64_t row = on ? (int64_t)hs[k] + ib : rho;
+            cf[j] = on ? s_off[nll + hq[k]] : 0.0;
+            nv[j] = vload<T, CPL>(X + row * ld + c * CPL);
+          }
+#pragma unroll
+          for (int j = 0; j < GB; ++j) {
+#pragma unroll
+            for (int i = 0; i < CPL; ++i) acc[i] = fma(cf[j], (double)nv[j].v[i], acc[i]);
+          }
+        }
+        for (int k0 = 0; k0 < nmx; k0 += GB) {
+          VecT<T, CPL> nv[GB];
+          double cf[GB];
+#pragma unroll
+          for (int j = 0; j < GB; ++j) {
+            const int q = k0 + j;
+            bool on = false;
+            int64_t row = rho;
+            if (q < nmx) {
+              const uint32_t m = s_mask[nll + nhh + q];
+              const uint32_t ml = m & lmask, mh = m >> Lb;
+              on = ((l & ml) != 0u) != ((h & mh) != 0u);
+              const uint32_t st = ms[q];
+              if (on && st == kNoRun) {
+                if (a.err) atomicOr(a.err, 2);
+                on = false;
+              }
+              if (on) row = (int64_t)st + s_lrank[l ^ ml];
+            }
+            cf[j] = on ? s_off[nll + nhh + q] : 0.0;
+            nv[j] = vload<T, CPL>(X + row * ld + c * CPL);
+          }
+#pragma unroll
+          for (int j = 0; j < GB; ++j) {
+#pragma unroll
+            for (int i = 0; i < CPL; ++i) acc[i] = fma(cf[j], (double)nv[j].v[i], acc[i]);
+          }
+        }
+        VecT<T, CPL> ov;
+        if (a.first) {
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) ov.v[i] = (T)acc[i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) ov.v[i] = (T)(2.0 * acc[i] - (double)yv.v[i]);
+        }
+        vstore_nt<T, CPL>(Y + rho * ld + c * CPL, ov);
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) {
+          const double o = (double)ov.v[i];
+          acc_a[i] = fma(o, o, acc_a[i]);
+          acc_b[i] = fma(o, (double)xv.v[i], acc_b[i]);
+        }
+      }
+    }
+    row0 += nrows;
+    __syncthreads();
+  }
+
+  // Workgroup reduction over row groups, per column (same tree as step_kernel).
+  double* red = reinterpret_cast<double*>(smem);
+  if (rg < nrg) {
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+      red[(2 * i) * kThreads + tid] = acc_a[i];
+      red[(2 * i + 1) * kThreads + tid] = acc_b[i];
+    }
+  }
+  int p2 = 1;
+  while (p2 < nrg) p2 <<= 1;
+  for (int sstride = p2 >> 1; sstride > 0; sstride >>= 1) {
+    __syncthreads();
+    if (rg < sstride && rg + sstride < nrg) {
+#pragma unroll
+      for (int v = 0; v < 2 * CPL; ++v) red[v * kThreads + tid] += red[v * kThreads + tid + sstride * nch];
+    }
+  }
+  __syncthreads();
+  if (tid < nch) {
+    const int tl = tile - U.tile0;
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+      const int col = c * CPL + i;
+      a.part_out[U.part_off + (int64_t)col * U.ntiles + tl] = red[(2 * i) * kThreads + tid];
+      a.part_out[U.part_off + (int64_t)(ld + col) * U.ntiles + tl] = red[(2 * i + 1) * kThreads + tid];
+    }
+  }
+}
+
+template <typename T, int CPL>
+static hipError_t launch_tab_t(const StepArgs& a, size_t lds, int grid, int gb, bool xl,
+                               hipStream_t st) {
+  if (xl) {
+    if (gb == 8) hipLaunchKernelGGL((tab_kernel<T, CPL, 8, true>), dim3(grid), dim3(kThreads), lds, st, a);
+    else hipLaunchKernelGGL((tab_kernel<T, CPL, 4, true>), dim3(grid), dim3(kThreads), lds, st, a);
+  } else {
+    if (gb == 8) hipLaunchKernelGGL((tab_kernel<T, CPL, 8, false>), dim3(grid), dim3(kThreads), lds, st, a);
+    else hipLaunchKernelGGL((tab_kernel<T, CPL, 4, false>), dim3(grid), dim3(kThreads), lds, st, a);
+  }
+  return hipGetLastError();
+}
+
+static hipError_t launch_tab(const DevicePlan& p, const StepArgs& a, hipStream_t st) {
+  const size_t lds = tab_lds_bytes(p);
+  const int grid = p.grid_tiles;
+  if (p.fp32) {
+    switch (p.cpl) {
+      case 1: return launch_tab_t<float, 1>(a, lds, grid, p.gather_batch, p.tab_xl, st);
+      case 2: return launch_tab_t<float, 2>(a, lds, grid, p.gather_batch, p.tab_xl, st);
+      case 4: return launch_tab_t<float, 4>(a, lds, grid, p.gather_batch, p.tab_xl, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (p.cpl) {
+    case 1: return launch_tab_t<double, 1>(a, lds, grid, p.gather_batch, p.tab_xl, st);
+    case 2: return launch_tab_t<double, 2>(a, lds, grid, p.gather_batch, p.tab_xl, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 size_t step_lds_bytes(const DevicePlan& p) {
   auto a16 = [](size_t x) { return (x + 15) & ~size_t(15); };
   size_t o = 0;
@@ -1064,6 +1544,22 @@ static StepArgs make_step_args(const DevicePlan& p) {
   a.tile_sub0 = p.tile_sub0;
   a.sub_nrows = p.sub_nrows;
   a.lrank = p.lrank;
+  if (p.block >= 2) {
+    const TabMeta m = tab_meta_layout(p.n_blk, p.meta_hh, p.meta_mx);
+    const unsigned char* mb = reinterpret_cast<const unsigned char*>(p.states);
+    a.blk_h = p.blk_h;
+    a.blk_start = p.blk_start;
+    a.sub_blk0 = p.sub_blk0;
+    a.sub_nblk = p.sub_nblk;
+    a.lunr = p.lunr;
+    a.koff = p.koff;
+    a.meta_hcnt = reinterpret_cast<const uint32_t*>(mb + m.hcnt);
+    a.meta_hstart = reinterpret_cast<const uint32_t*>(mb + m.hstart);
+    a.meta_mstart = reinterpret_cast<const uint32_t*>(mb + m.mstart);
+    a.meta_hq = reinterpret_cast<const uint16_t*>(mb + m.hq);
+    a.meta_hh = p.meta_hh;
+    a.meta_mx = p.meta_mx;
+  }
   return a;
 }
 
@@ -1109,6 +1605,7 @@ hipError_t launch_step_slots(const DevicePlan& p, void* vec, double* part_out, i
 }
 
 hipError_t launch_step_args(const DevicePlan& p, const StepArgs& a, hipStream_t st) {
+  if (p.block == 2) return launch_tab(p, a, st);
   if (p.block) return launch_block(p, a, st);
   if (p.row_ld > 0) return launch_row(p, a, st);
   const size_t lds = step_lds_bytes(p);
@@ -1490,6 +1987,7 @@ __global__ __launch_bounds__(kThreads) void fill_states_kernel(const ProbDev* pr
 
 hipError_t fill_states(const DevicePlan& p, hipStream_t st) {
   if (!p.states || p.n_probs == 0) return hipSuccess;
+  if (p.block >= 2) return build_tab_meta(p, st);
   hipLaunchKernelGGL(fill_states_kernel, dim3(2048, p.n_probs), dim3(kThreads), 0, st, p.probs,
                      p.n_probs, p.binom, p.states);
   return hipGetLastError();

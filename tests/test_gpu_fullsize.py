@@ -40,13 +40,13 @@ def _props(mu, dims, tol0=1e-9):
         assert np.all(np.abs(mu[p]) <= mu[p, 0] * (1 + 1e-6)), p
 
 
-def test_ring24_sz0_bench_block_first_moments(kpm, ring24_sz0):
+def test_ring24_sz0_bench_kernel_first_moments(kpm, ring24_sz0):
     s, H = ring24_sz0
     lo, hi = -11.0, 7.0                       # E_0 = -10.77, E_max = 6
     M = 10
     mu, ab = kpm.chebyshev_moments([s], M, 10, "complex_gaussian", "fp32", 0.025, 0, 20, bounds=[(lo, hi)])
     st = kpm.last_run_stats()
-    assert st["col_block"] == 20 and st["kernel"] == 2, st
+    assert st["col_block"] == 20 and st["kernel"] in (2, 3), st   # block or block-table kernel
     a, b = hamiltonian.scale_from_bounds(lo, hi, 0.025)
     want = moments.sector_moments(s, a, b, M, 10, "complex_gaussian", 0, store=np.float32, H=H)
     got = mu.cpu().numpy()[0]

@@ -1,4 +1,4 @@
-"""Every step kernel (column-chunk, row, block) against the oracle on the same
+"""Every step kernel (column-chunk, row, block, block-table) against the oracle on the same
 seeds and bounds, including block geometries that force many small tiles,
 several blocks per tile and clusters smaller than the block width.
 
@@ -24,6 +24,11 @@ KERNELS = {
                      "KPM_SUB_PER_TILE": "3", "KPM_GATHER_BATCH": "8"}, 2),
     # 4 low bits: most bonds are high-high or mixed
     "block_l4": ({"KPM_BLOCK": "1", "KPM_BLOCK_L": "4", "KPM_SUB_PER_TILE": "1"}, 2),
+    # block-table kernel, default geometry, small tiles and 4 low bits
+    "tab": ({"KPM_BLOCK": "2"}, 3),
+    "tab_small": ({"KPM_BLOCK": "2", "KPM_BLOCK_ROWS": "64", "KPM_BLOCK_MAX": "2",
+                   "KPM_SUB_PER_TILE": "3", "KPM_GATHER_BATCH": "8"}, 3),
+    "tab_l4": ({"KPM_BLOCK": "2", "KPM_BLOCK_L": "4", "KPM_SUB_PER_TILE": "1"}, 3),
 }
 
 
@@ -91,7 +96,7 @@ def test_j1j2_n18_sz0_wide_block(kpm, monkeypatch, kernel):
     _check(kpm, monkeypatch, kernel, secs, 40, 10, "complex_gaussian", "fp32", 20, seed=2)
 
 
-@pytest.mark.parametrize("kernel", ["block", "block_small", "block_l4"])
+@pytest.mark.parametrize("kernel", ["block", "block_small", "block_l4", "tab", "tab_small", "tab_l4"])
 def test_block_extreme_sectors(kpm, monkeypatch, kernel):
     """Sectors whose blocks are tiny (n_up near N) or single (N below the
     block width), dimension-1 sectors and the dimer."""
