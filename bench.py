@@ -25,6 +25,15 @@ JSON line also carries:
   accuracy      float32-storage error against float64 on the same seeds, all
                 13 S^z >= 0 sectors of the ring: C(T), chi(T), ln Z, E, moments
   cpu_baseline  the CPU oracle on a bounded sample of the same workload
+
+`--workload` measures one of the other workloads instead (one JSON line of
+the same form, no CPU leg): batched_rr3 (64 random 3-regular clusters,
+N = 16..22, all sectors, 32 Rademacher vectors, float32, M = 1024),
+j1j2_grad (the adjoint: dL/dJ of L = sum_T C(T) for the J1-J2 chain N = 20,
+S^z = 0, 16 vectors, float64, M = 1000, checkpoints every 64 steps), rr4_30
+(random 4-regular graph, N = 30, S^z = 0 = 155,117,520 states, 4 Rademacher
+vectors, M = 500, float32 and float64) and ftlm_ring24 (finite-temperature
+Lanczos on the headline sector, 20 real columns, 200 Lanczos steps).
 """
 from __future__ import annotations
 
@@ -56,6 +65,8 @@ def _parse():
                     help="only the timed workload (for profiler runs)")
     ap.add_argument("--cpu-steps", type=int, default=30,
                     help="recursion steps of the CPU-oracle sample")
+    ap.add_argument("--workload", default="ring24_sz0",
+                    choices=["ring24_sz0", "batched_rr3", "j1j2_grad", "rr4_30", "ftlm_ring24"])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (reference for HBM byte counters)")
     return ap.parse_args()
@@ -123,6 +134,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.workload != "ring24_sz0":
+        print(json.dumps(other_workload(args, kpm, W, np, torch, dev)), flush=True)
+        return
+
     ring = W.ring(24)
     sec = W.sectors(ring, only_sz0=True)
     M = args.M
@@ -177,6 +192,101 @@ def main():
     if not args.skip_extras:
         line.update(extras(args, kpm, W, np, torch, sec, ps, T, M, value, ws))
     print(json.dumps(line), flush=True)
+
+
+def _line(args, workload, value, unit, dt, config, roofline=None, extra=None):
+    line = {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": dict({"workload": workload}, **config)}
+    if roofline is not None:
+        line["roofline"] = roofline
+    if extra:
+        line.update(extra)
+    return line
+
+
+def _roofline(st):
+    t = st["recursion_ms"] / 1e3 / st["step_launches"]
+    ach = st["bytes_per_launch"] / t / 1e9
+    return {"bound": "hbm", "kernel": KERNEL_FAMILY.get(st["kernel"], "step_kernel"), "achieved": ach,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_launch": st["bytes_per_launch"], "avg_launch_us": t * 1e6,
+            "traffic": None}
+
+
+def _timed(args, torch, fn):
+    """fn() warmup + timed; returns (seconds per call, last result)."""
+    out = None
+    for _ in range(max(1, args.warmup)):
+        out = fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / args.steps, out
+
+
+def other_workload(args, kpm, W, np, torch, dev):
+    name = args.workload
+    if name in ("batched_rr3", "rr4_30"):
+        wl = W.batched_workload() if name == "batched_rr3" else W.rr4_30_workload("fp32")
+        ab = kpm.spectral_bounds(wl.problems)              # fixed bounds: Lanczos outside the timing
+        ps = kpm.ProblemSet(wl.problems, [tuple(x) for x in ab])
+        T = torch.tensor(wl.temperatures, device="cuda")
+
+        def run(prec):
+            mu, abd = kpm.chebyshev_moments(None, wl.M, wl.R, wl.vec_kind, prec, wl.eps, wl.seed,
+                                            problems=ps, autotune=True)
+            kpm.thermo(mu, abd, ps, T, wl.kernel)
+            return kpm.last_run_stats()
+
+        dt, st = _timed(args, torch, lambda: run("fp32"))
+        dims = [s.dim for s in wl.problems]
+        cfg = {"problems": len(dims), "states": int(sum(dims)), "max_dim": int(max(dims)), "M": wl.M,
+               "vectors": f"{wl.R} {wl.vec_kind}", "storage": "f32", "col_block": st["col_block"],
+               "bounds": "lanczos50+1% (outside the timing)", "device": dev}
+        extra = None
+        if name == "rr4_30":
+            dt64, st64 = _timed(args, torch, lambda: run("fp64"))
+            extra = {"fp64": {"value": st64["state_col_steps"] / dt64, "ms": dt64 * 1e3,
+                              "roofline": _roofline(st64)},
+                     "speedup_vs_fp64": (st["state_col_steps"] / dt) / (st64["state_col_steps"] / dt64)}
+        return _line(args, name, st["state_col_steps"] / dt, "state-column-steps/s", dt, cfg,
+                     _roofline(st), extra)
+    if name == "j1j2_grad":
+        wl = W.j1j2_grad_workload()
+        ab = kpm.spectral_bounds(wl.problems)
+        bl = [tuple(x) for x in ab]
+        T = wl.temperatures
+        wC = np.ones((1, T.size))
+        wX = np.zeros((1, T.size))
+
+        def run():
+            return kpm.thermo_grad(wl.problems, wl.M, wl.R, T, wC, wX, wl.vec_kind, "fp64", wl.eps, wl.seed,
+                                   kernel=wl.kernel, ckpt_every=64, bounds=bl)
+
+        dt, _ = _timed(args, torch, run)
+        dtf, _ = _timed(args, torch, lambda: kpm.chebyshev_moments(wl.problems, wl.M, wl.R, wl.vec_kind, "fp64",
+                                                                    wl.eps, wl.seed, bounds=bl))
+        dim = wl.problems[0].dim
+        work = dim * wl.R * (wl.M // 2)
+        cfg = {"dim": dim, "bonds": wl.problems[0].cluster.n_bonds, "M": wl.M, "vectors": f"{wl.R} rademacher",
+               "storage": "f64", "checkpoint_every": 64, "loss": "sum_T C(T), 64 T in [0.05, 5]",
+               "device": dev}
+        return _line(args, name, work / dt, "forward-equivalent state-column-steps/s", dt, cfg, None,
+                     {"forward_ms": dtf * 1e3, "gradient_over_forward_time": dt / dtf})
+    if name == "ftlm_ring24":
+        sec = W.sectors(W.ring(24), only_sz0=True)
+        T = W.log_temperatures(200, 0.01, 10.0)
+        ML = 200
+        dt, _ = _timed(args, torch, lambda: kpm.ftlm(sec, ML, 10, "complex_gaussian", T=T))
+        work = sec[0].dim * 20 * ML
+        cfg = {"dim": sec[0].dim, "vectors": "10 complex Gaussian (20 real columns)", "lanczos_steps": ML,
+               "storage": "f64", "device": dev}
+        return _line(args, name, work / dt, "state-column-steps/s", dt, cfg)
+    raise ValueError(name)
 
 
 def _time_moments(kpm, torch, sec, M, R, kind, precision, col_block, reps=1):

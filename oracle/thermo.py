@@ -170,6 +170,62 @@ def thermo_field(problems, mu: np.ndarray, ab: np.ndarray, T: np.ndarray, h: np.
     return out
 
 
+def thermo_hybrid(problems, mu: np.ndarray, ab: np.ndarray, spectra, T: np.ndarray, h=0.0,
+                  kernel: str = "jackson", n_nodes: int = 0):
+    """Thermodynamics with the small sectors treated exactly (Sec. II: sectors
+    whose dimension is small are diagonalised completely instead of being
+    estimated stochastically).  spectra[p] is None for a sector taken from its
+    moments (nodes x_k, weights gamma_k as in thermo_field) or the array of its
+    eigenvalues; an eigenvalue carries weight Ntil, the scale on which the
+    gamma_k of a dimension-D sector sum to Ntil * D (discrete orthogonality),
+    so both kinds add into one Z.  Zeeman term, mirror sectors, shift and
+    flags as in thermo_field."""
+    mu = np.atleast_2d(mu)
+    P, M = mu.shape
+    Nt = n_nodes or M
+    g = kernel_coefficients(M, kernel)
+    x = nodes(Nt)
+    cid, sz, W = _sector_table(problems)
+    nc = int(cid.max()) + 1
+    T = np.asarray(T, dtype=np.float64)
+    h = np.broadcast_to(np.asarray(h, dtype=np.float64), T.shape)
+    out = {k: np.zeros((nc, T.size)) for k in ("lnZ", "E", "C", "chi", "M")}
+    out["z_nonpos"] = np.zeros((nc, T.size), dtype=bool)
+    pts = []
+    for p in range(P):
+        if spectra[p] is None:
+            pts.append((dos_weights(mu[p], g, Nt), ab[p, 0] * x + ab[p, 1]))
+        else:
+            e = np.asarray(spectra[p], dtype=np.float64)
+            pts.append((np.full(e.size, float(Nt)), e))
+    for c in range(nc):
+        sel = np.nonzero(cid == c)[0]
+        for t, (Tv, hv) in enumerate(zip(T, h)):
+            beta = 1.0 / Tv
+            gs, Es, ms = [], [], []
+            for p in sel:
+                wp, Ep = pts[p]
+                for m in ([sz[p]] if W[p] == 1.0 else [sz[p], -sz[p]]):
+                    gs.append(wp)
+                    Es.append(Ep + hv * m)
+                    ms.append(np.full(Ep.size, m))
+            gw, E, m = np.concatenate(gs), np.concatenate(Es), np.concatenate(ms)
+            Eref = E.min()
+            w = gw * np.exp(-beta * (E - Eref))
+            S0 = math.fsum(w)
+            Em = math.fsum(w * E) / S0
+            varE = math.fsum(w * (E - Em) ** 2) / S0
+            m1 = math.fsum(w * m) / S0
+            varM = math.fsum(w * (m - m1) ** 2) / S0
+            out["z_nonpos"][c, t] = S0 <= 0.0
+            out["lnZ"][c, t] = (np.log(S0 / Nt) if S0 > 0 else np.nan) - beta * Eref
+            out["E"][c, t] = Em
+            out["C"][c, t] = beta**2 * varE
+            out["chi"][c, t] = beta * varM
+            out["M"][c, t] = m1
+    return out
+
+
 def thermo_vjp(problems, mu: np.ndarray, ab: np.ndarray, T: np.ndarray,
                wC: np.ndarray, wchi: np.ndarray, kernel: str = "jackson", n_nodes: int = 0):
     """lambda[p, n] = dL/dmu_n^p for L = sum_{c,T} wC[c,T] C[c,T] + wchi[c,T] chi[c,T].

@@ -230,3 +230,43 @@ def test_field_thermo_saturation_and_susceptibility():
         o = thermo.thermo_field(probs, mus, ab, T, np.array([h0 - d, h0, h0 + d]), "none", 400)
         dM = (o["M"][0, 2] - o["M"][0, 0]) / (2 * d)
         assert abs(o["chi"][0, 1] + dM) < 1e-6 * max(1.0, abs(dM)), h0
+
+
+@pytest.mark.parametrize("cl", [W.ring(8), W.random_regular_cluster(9, 3, 2, J_range=(0.5, 1.5))])
+def test_hybrid_all_exact_is_dense_ed(cl):
+    """Every sector diagonalised: the hybrid sums are the exact thermodynamics
+    of H_0 + h S^z from the dense diagonalisation of the whole space."""
+    probs, mus, ab, spec = _exact_problem_set(cl, 0.025, 64)
+    T = np.array([0.05, 0.3, 0.7, 1.5, 4.0, 0.5])
+    h = np.array([0.0, 2.5, 1.0, -1.3, 3.0, 0.2])
+    out = thermo.thermo_hybrid(probs, mus, ab, [e for e, _, _ in spec], T, h, "jackson")
+    ref = _dense_field_thermo(cl, T, h)
+    for k in ("lnZ", "E", "C", "chi", "M"):
+        assert np.abs(out[k][0] - ref[k]).max() < 1e-10 * max(1.0, np.abs(ref[k]).max()), k
+
+
+def test_hybrid_no_exact_sector_is_field_thermo():
+    cl = W.ladder(10)
+    probs, mus, ab, _ = _exact_problem_set(cl, 0.025, 96)
+    T = W.log_temperatures(20, 0.05, 10.0)
+    h = np.linspace(0.0, 1.0, T.size)
+    a = thermo.thermo_field(probs, mus, ab, T, h, "jackson", 150)
+    b = thermo.thermo_hybrid(probs, mus, ab, [None] * len(probs), T, h, "jackson", 150)
+    for k in ("lnZ", "E", "C", "chi", "M"):
+        np.testing.assert_allclose(b[k], a[k], rtol=1e-13, atol=1e-14)
+
+
+def test_hybrid_mixed_exact_traces_match_dense_ed():
+    """Large sectors from exact-trace moments (g_n = 1, Ntil = M = 400), the
+    three smallest diagonalised: equal to dense ED within the quadrature error."""
+    cl = W.ring(10)
+    probs, mus, ab, spec = _exact_problem_set(cl, 0.025, 400)
+    dims = [e.size for e, _, _ in spec]
+    small = set(np.argsort(dims)[:3])
+    spectra = [spec[p][0] if p in small else None for p in range(len(probs))]
+    T = np.array([0.3, 0.7, 1.5, 4.0, 0.5])
+    h = np.array([0.4, 1.0, -1.3, 3.0, 0.0])
+    out = thermo.thermo_hybrid(probs, mus, ab, spectra, T, h, "none", 400)
+    ref = _dense_field_thermo(cl, T, h)
+    for k, tol in (("lnZ", 1e-9), ("E", 1e-9), ("C", 1e-8), ("chi", 1e-9), ("M", 1e-9)):
+        assert np.abs(out[k][0] - ref[k]).max() < tol, k
