@@ -211,8 +211,10 @@ size_t kpm_ftlm_workspace_size(const kpm_problem* p, int32_t n, const kpm_params
  * with a complex vector's two real columns weighted by their share of |r|^2
  * (R = dim and weight 1 for the complete basis).  Thermodynamics as in
  * kpm_thermo_field at the points (d_T[t], d_h[t]) (d_h may be NULL: no field).
- *  q: M = Krylov dimension (>= 2), precision must be KPM_FP64, col_block,
- *     eps and the problems' bounds are not used
+ *  q: M = Krylov dimension (>= 2), precision must be KPM_FP64; col_block
+ *     batches columns into recursion blocks as for chebyshev_moments (each
+ *     column keeps its own Lanczos coefficients); eps and the problems'
+ *     bounds are not used
  *  outputs device [n_clusters][n_pts]: d_lnZ, d_E, d_C, d_chi, d_mag (<S_z>,
  *     may be NULL)
  *  d_ritz, d_weight: device double [columns][min(M, largest dim)] (may be
@@ -224,6 +226,40 @@ int kpm_ftlm(const kpm_problem* p, int32_t n, const kpm_params* q, const double*
              const double* d_h, int32_t n_pts, double* d_lnZ, double* d_E, double* d_C,
              double* d_chi, double* d_mag, double* d_ritz, double* d_weight, void* d_work,
              size_t work_bytes, void* stream);
+
+/* Workspace bytes for kpm_sector_eigenvalues (0 if the arguments are invalid). */
+size_t kpm_sector_eigenvalues_workspace_size(const kpm_problem* p, int32_t n, int32_t max_dim);
+
+/* Exact spectra of the small sectors (Sec. II: a sector of small dimension is
+ * diagonalised completely instead of being estimated stochastically).  For
+ * every problem i with D = C(n_sites, n_up) <= max_dim, row i of d_evals gets
+ * the D eigenvalues of H (unscaled; the problem's bounds are not used) on the
+ * sector, ascending, followed by NaN; rows of larger sectors are all NaN.
+ * Float64 throughout: the dense sector matrix, Householder reduction to
+ * tridiagonal form, implicit QL; one workgroup per sector.
+ *  max_dim   1..1024
+ *  d_evals   device double [n][max_dim]
+ *  d_work    device workspace of kpm_sector_eigenvalues_workspace_size bytes
+ *            (8 D^2 per diagonalised sector + small tables), or NULL: allocated
+ *            and freed inside the call
+ * Errors: KPM_EINVAL, KPM_EWORKSPACE, KPM_EDEVICE (HIP error, or QL did not
+ * converge). */
+int kpm_sector_eigenvalues(const kpm_problem* p, int32_t n, int32_t max_dim, double* d_evals,
+                           void* d_work, size_t work_bytes, void* stream);
+
+/* Thermodynamics with exact small sectors: problem i with h_exact[i] != 0
+ * (host uint8 [n]) contributes the C(n_sites, n_up) eigenvalues in row i of
+ * d_evals (device double [n][evals_ld], as written by kpm_sector_eigenvalues),
+ * each with the weight Ntil on which a dimension-D sector's DOS weights gamma_k
+ * sum to Ntil * D; the other problems contribute their moments d_mu as in
+ * kpm_thermo_field.  d_h may be NULL (no field).  Outputs as kpm_thermo_field.
+ * Errors: KPM_EINVAL (also when an exact sector does not fit evals_ld),
+ * KPM_ENOMEM, KPM_EDEVICE. */
+int kpm_thermo_hybrid(const double* d_mu, const double* d_ab, const kpm_problem* p, int32_t n,
+                      int32_t M, int32_t kernel, int32_t n_nodes, const double* d_evals,
+                      int32_t evals_ld, const uint8_t* h_exact, const double* d_T, const double* d_h,
+                      int32_t n_pts, double* d_lnZ, double* d_E, double* d_C, double* d_chi,
+                      double* d_mag, uint8_t* d_znonpos, void* stream);
 
 /* Derivative of L = sum_{c,T} wC[c][T] C[c][T] + wchi[c][T] chi[c][T] with
  * respect to the moments: d_lambda device double [n][M] = dL/dmu. */

@@ -1532,11 +1532,13 @@ struct FtlmLayout {
   size_t plan, vec, vecC, part, dots, b2, zero, norm, err, states, ritz, escr, weight, len, total;
 };
 
+// Every real column runs its own Lanczos recursion; columns are batched in
+// blocks like the Chebyshev recursion (q->col_block, 0 = the planner's width;
+// width 1 splits a complex vector's Re and Im into separate blocks).
 RunShape ftlm_shape(const kpm_params& q) {
   RunShape s = shape_of(q);
   s.precision = KPM_FP64;
-  s.col_block = 1;
-  s.split_vectors = true;
+  s.split_vectors = q.col_block == 1;
   return s;
 }
 
@@ -1571,6 +1573,58 @@ FtlmLayout ftlm_layout(const Planned& P, int steps) {
   L.len = put(TC * 4);
   L.total = o;
   return L;
+}
+
+// ------------------------------------------------ exact spectra (small sectors)
+
+constexpr int kEdMaxDim = 1024;
+
+struct EdPlan {
+  std::vector<EigProb> probs;
+  std::vector<uint32_t> bmask;
+  std::vector<double> J;
+  size_t o_probs = 0, o_mask = 0, o_J = 0, o_binom = 0, o_err = 0, o_mat = 0, total = 0;
+  int max_bonds = 1;
+};
+
+int ed_plan(const kpm_problem* p, int n, int max_dim, EdPlan& E) {
+  int r = check_problems(p, n);
+  if (r != KPM_OK) return r;
+  if (max_dim < 1 || max_dim > kEdMaxDim) return KPM_EINVAL;
+  int64_t mat = 0;
+  for (int i = 0; i < n; ++i) {
+    const uint64_t dim = binom64(p[i].n_sites, p[i].n_up);
+    if (dim > (uint64_t)max_dim) continue;
+    EigProb e{};
+    e.n_sites = p[i].n_sites;
+    e.n_up = p[i].n_up;
+    e.dim = (int32_t)dim;
+    e.n_bonds = p[i].n_bonds;
+    e.bond_off = (int32_t)E.bmask.size();
+    e.out_row = i;
+    e.mat_off = mat;
+    mat += (int64_t)dim * (int64_t)dim;
+    for (int k = 0; k < p[i].n_bonds; ++k) {
+      E.bmask.push_back((1u << p[i].bond_i[k]) | (1u << p[i].bond_j[k]));
+      E.J.push_back(p[i].J[k]);
+    }
+    E.max_bonds = std::max(E.max_bonds, p[i].n_bonds);
+    E.probs.push_back(e);
+  }
+  size_t o = 0;
+  auto put = [&](size_t bytes) {
+    const size_t rr = o;
+    o = align_up(o + bytes);
+    return rr;
+  };
+  E.o_probs = put(std::max<size_t>(E.probs.size(), 1) * sizeof(EigProb));
+  E.o_mask = put(std::max<size_t>(E.bmask.size(), 1) * 4);
+  E.o_J = put(std::max<size_t>(E.J.size(), 1) * 8);
+  E.o_binom = put((size_t)kBinomN * kBinomN * 4);
+  E.o_err = put(256);
+  E.o_mat = put((size_t)std::max<int64_t>(mat, 1) * 8);
+  E.total = o;
+  return KPM_OK;
 }
 
 }  // namespace
@@ -2058,13 +2112,147 @@ int kpm_ftlm(const kpm_problem* p, int32_t n, const kpm_params* q, const double*
   fa.n_clusters = nc;
   KPM_HIP(launch_ftlm_ritz(fa, st));
   KPM_HIP(launch_ftlm_thermo(fa, st));
-  if (d_ritz) KPM_HIP(hipMemcpyAsync(d_ritz, fa.ritz, (size_t)TC * steps * 8, hipMemcpyDeviceToDevice, st));
-  if (d_weight)
-    KPM_HIP(hipMemcpyAsync(d_weight, fa.weight, (size_t)TC * steps * 8, hipMemcpyDeviceToDevice, st));
+  // real columns only (blocks may be padded), problem after problem
+  if (d_ritz || d_weight) {
+    size_t row = 0;
+    for (const auto& u : P.units) {
+      const size_t bytes = (size_t)u.ncols * steps * 8, src = (size_t)u.col_off * steps;
+      if (d_ritz)
+        KPM_HIP(hipMemcpyAsync(d_ritz + row * steps, fa.ritz + src, bytes, hipMemcpyDeviceToDevice, st));
+      if (d_weight)
+        KPM_HIP(hipMemcpyAsync(d_weight + row * steps, fa.weight + src, bytes, hipMemcpyDeviceToDevice, st));
+      row += (size_t)u.ncols;
+    }
+  }
   int h_err = 0;
   KPM_HIP(hipMemcpyAsync(&h_err, D.err, sizeof(int), hipMemcpyDeviceToHost, st));
   KPM_HIP(hipStreamSynchronize(st));
   return h_err ? KPM_EDEVICE : KPM_OK;
+}
+
+size_t kpm_sector_eigenvalues_workspace_size(const kpm_problem* p, int32_t n, int32_t max_dim) {
+  EdPlan E;
+  if (ed_plan(p, n, max_dim, E) != KPM_OK) return 0;
+  return E.total;
+}
+
+int kpm_sector_eigenvalues(const kpm_problem* p, int32_t n, int32_t max_dim, double* d_evals,
+                           void* d_work, size_t work_bytes, void* stream) {
+  EdPlan E;
+  int r = ed_plan(p, n, max_dim, E);
+  if (r != KPM_OK) return r;
+  if (!d_evals) return KPM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StreamSync guard{st};
+  DevBuf own;
+  unsigned char* work = static_cast<unsigned char*>(d_work);
+  if (!work) {
+    r = own.alloc(E.total);
+    if (r != KPM_OK) return r;
+    work = static_cast<unsigned char*>(own.p);
+  } else if (work_bytes < E.total) {
+    return KPM_EWORKSPACE;
+  }
+  // NaN (all bits set) past each spectrum and in the rows of larger sectors
+  KPM_HIP(hipMemsetAsync(d_evals, 0xFF, (size_t)n * max_dim * 8, st));
+  const std::vector<uint32_t> bt = binom_table();
+  std::vector<unsigned char> staging(E.o_mat, 0);
+  std::memcpy(staging.data() + E.o_probs, E.probs.data(), E.probs.size() * sizeof(EigProb));
+  std::memcpy(staging.data() + E.o_mask, E.bmask.data(), E.bmask.size() * 4);
+  std::memcpy(staging.data() + E.o_J, E.J.data(), E.J.size() * 8);
+  std::memcpy(staging.data() + E.o_binom, bt.data(), bt.size() * 4);
+  KPM_HIP(hipMemcpyAsync(work, staging.data(), E.o_mat, hipMemcpyHostToDevice, st));
+  EigArgs a{};
+  a.probs = reinterpret_cast<const EigProb*>(work + E.o_probs);
+  a.bmask = reinterpret_cast<const uint32_t*>(work + E.o_mask);
+  a.J = reinterpret_cast<const double*>(work + E.o_J);
+  a.binom = reinterpret_cast<const uint32_t*>(work + E.o_binom);
+  a.err = reinterpret_cast<int*>(work + E.o_err);
+  a.mat = reinterpret_cast<double*>(work + E.o_mat);
+  a.evals = d_evals;
+  a.ld = max_dim;
+  a.max_dim = 1;
+  for (const auto& e : E.probs) a.max_dim = std::max(a.max_dim, e.dim);
+  // LDS: binomial table and bond masks, bond J values, five work vectors
+  a.o_bonds = (int32_t)align_up((size_t)(kBinomN * kBinomN + E.max_bonds) * 4, 16);
+  a.o_vec = (int32_t)align_up((size_t)a.o_bonds + (size_t)E.max_bonds * 8, 16);
+  const size_t lds = (size_t)a.o_vec + (size_t)5 * a.max_dim * 8;
+  if (lds > 64 * 1024) return KPM_EINVAL;
+  KPM_HIP(hipMemsetAsync(a.err, 0, sizeof(int), st));
+  KPM_HIP(launch_sector_eig(a, (int)E.probs.size(), lds, st));
+  int h_err = 0;
+  KPM_HIP(hipMemcpyAsync(&h_err, a.err, sizeof(int), hipMemcpyDeviceToHost, st));
+  KPM_HIP(hipStreamSynchronize(st));
+  return h_err ? KPM_EDEVICE : KPM_OK;
+}
+
+int kpm_thermo_hybrid(const double* d_mu, const double* d_ab, const kpm_problem* p, int32_t n,
+                      int32_t M, int32_t kernel, int32_t n_nodes, const double* d_evals,
+                      int32_t evals_ld, const uint8_t* h_exact, const double* d_T, const double* d_h,
+                      int32_t n_pts, double* d_lnZ, double* d_E, double* d_C, double* d_chi,
+                      double* d_mag, uint8_t* d_znonpos, void* stream) {
+  if (!d_mu || !d_ab || !d_T || !h_exact || !d_lnZ || !d_E || !d_C || !d_chi || M < 1 ||
+      n_pts < 1 || n_nodes < 0 || (kernel != 0 && kernel != 1))
+    return KPM_EINVAL;
+  std::vector<ThermoProb> tp;
+  std::vector<int32_t> start, list;
+  int nc = 0;
+  int r = thermo_meta(p, n, tp, start, list, nc);
+  if (r != KPM_OK) return r;
+  std::vector<int32_t> cnt(n, 0);
+  for (int i = 0; i < n; ++i) {
+    if (!h_exact[i]) continue;
+    const uint64_t dim = binom64(p[i].n_sites, p[i].n_up);
+    if (!d_evals || dim > (uint64_t)std::max(evals_ld, 0)) return KPM_EINVAL;
+    cnt[i] = (int32_t)dim;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StreamSync guard{st};
+  const int Nt = n_nodes ? n_nodes : M;
+  size_t o = 0;
+  auto put = [&](size_t bytes) {
+    const size_t rr = o;
+    o = align_up(o + bytes);
+    return rr;
+  };
+  const size_t og = put((size_t)M * 8), ogam = put((size_t)n * Nt * 8),
+               otp = put(tp.size() * sizeof(ThermoProb)), ostart = put(start.size() * 4),
+               olist = put(list.size() * 4), ocnt = put(cnt.size() * 4);
+  DevBuf buf;
+  r = buf.alloc(o);
+  if (r != KPM_OK) return r;
+  unsigned char* w = static_cast<unsigned char*>(buf.p);
+  KPM_HIP(hipMemcpyAsync(w + otp, tp.data(), tp.size() * sizeof(ThermoProb), hipMemcpyHostToDevice, st));
+  KPM_HIP(hipMemcpyAsync(w + ostart, start.data(), start.size() * 4, hipMemcpyHostToDevice, st));
+  KPM_HIP(hipMemcpyAsync(w + olist, list.data(), list.size() * 4, hipMemcpyHostToDevice, st));
+  KPM_HIP(hipMemcpyAsync(w + ocnt, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice, st));
+  double* g = reinterpret_cast<double*>(w + og);
+  double* gamma = reinterpret_cast<double*>(w + ogam);
+  KPM_HIP(launch_kernel_coef(M, kernel, g, st));
+  KPM_HIP(launch_gamma(n, M, Nt, g, d_mu, gamma, st));
+  ThermoArgs ta{};
+  ta.tp = reinterpret_cast<const ThermoProb*>(w + otp);
+  ta.cl_start = reinterpret_cast<const int32_t*>(w + ostart);
+  ta.cl_list = reinterpret_cast<const int32_t*>(w + olist);
+  ta.gamma = gamma;
+  ta.ab = d_ab;
+  ta.T = d_T;
+  ta.lnZ = d_lnZ;
+  ta.E = d_E;
+  ta.C = d_C;
+  ta.chi = d_chi;
+  ta.znonpos = d_znonpos;
+  ta.n_nodes = Nt;
+  ta.n_T = n_pts;
+  ta.n_clusters = nc;
+  ta.h = d_h;
+  ta.mag = d_mag;
+  ta.ed_count = reinterpret_cast<const int32_t*>(w + ocnt);
+  ta.evals = d_evals;
+  ta.evals_ld = evals_ld;
+  KPM_HIP(launch_thermo_hybrid(ta, st));
+  KPM_HIP(hipStreamSynchronize(st));
+  return KPM_OK;
 }
 
 }  // extern "C"

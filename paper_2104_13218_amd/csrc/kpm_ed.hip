@@ -1,0 +1,254 @@
+// Exact spectra of small S^z sectors (Sec. II: a sector of small dimension is
+// diagonalised completely instead of being estimated stochastically) and the
+// thermodynamics that mix such spectra with the moments of the other sectors.
+//
+// One workgroup per sector: the dense float64 matrix of H on the sector basis
+// (rank order) is built in the workspace, reduced to a symmetric tridiagonal
+// matrix by Householder reflections applied from both sides, and its
+// eigenvalues are taken by implicit QL (kpm_tridiag.h), then sorted.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kpm_device.h"
+#include "kpm_internal.h"
+#include "kpm_tridiag.h"
+
+namespace kpm {
+
+namespace {
+
+// Sum over the workgroup, returned to every thread (fixed order).
+__device__ __forceinline__ double ed_sum(double v, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  const double r = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  __syncthreads();
+  return r;
+}
+
+// Colex (= ascending-integer) rank of word s among the words of its popcount.
+__device__ __forceinline__ uint32_t cns_rank(uint32_t s, const uint32_t* binom) {
+  uint32_t r = 0;
+  int j = 0;
+  for (uint32_t x = s; x; x &= x - 1u) {
+    ++j;
+    r += binom[(__ffs(x) - 1) * kBinomN + j];
+  }
+  return r;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kThreads) void sector_eig_kernel(const EigArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x;
+  const EigProb P = a.probs[blockIdx.x];
+  const int D = P.dim;
+  uint32_t* sb = reinterpret_cast<uint32_t*>(smem);                       // [33 * 33]
+  uint32_t* s_mask = sb + kBinomN * kBinomN;                               // [lds_bonds]
+  double* s_J = reinterpret_cast<double*>(smem + a.o_bonds);              // [lds_bonds]
+  double* v = reinterpret_cast<double*>(smem + a.o_vec);                  // [max_dim] x 5
+  double* w = v + a.max_dim;
+  double* d = w + a.max_dim;
+  double* e = d + a.max_dim;
+  double* z = e + a.max_dim;
+  __shared__ double sh[4];
+  for (int i = tid; i < kBinomN * kBinomN; i += kThreads) sb[i] = a.binom[i];
+  for (int q = tid; q < P.n_bonds; q += kThreads) {
+    s_mask[q] = a.bmask[P.bond_off + q];
+    s_J[q] = a.J[P.bond_off + q];
+  }
+  double* A = a.mat + P.mat_off;
+  for (int64_t i = tid; i < (int64_t)D * D; i += kThreads) A[i] = 0.0;
+  __syncthreads();
+
+  // H on the sector basis: s_i s_j = 1/4 for equal spins, -1/4 otherwise;
+  // unequal spins are exchanged with amplitude J/2.  Each row is one thread's.
+  for (int r = tid; r < D; r += kThreads) {
+    const uint32_t s = unrank((uint32_t)r, P.n_sites, P.n_up, sb);
+    double diag = 0.0;
+    for (int q = 0; q < P.n_bonds; ++q) {
+      const uint32_t m = s_mask[q];
+      const uint32_t x = s & m;
+      if (x == 0u || x == m) {
+        diag += 0.25 * s_J[q];
+      } else {
+        diag -= 0.25 * s_J[q];
+        const uint32_t c = cns_rank(s ^ m, sb);
+        if (c < (uint32_t)D) A[(int64_t)r * D + c] += 0.5 * s_J[q];
+        else if (a.err) atomicOr(a.err, 2);
+      }
+    }
+    A[(int64_t)r * D + r] += diag;
+  }
+  __syncthreads();
+
+  // Householder: column k below the diagonal becomes alpha e_1.
+  for (int k = 0; k + 2 < D; ++k) {
+    const int n2 = D - k - 1;
+    const double* rowk = A + (int64_t)k * D + (k + 1);
+    double part = 0.0;
+    for (int i = tid; i < n2; i += kThreads) {
+      const double x = rowk[i];
+      v[i] = x;
+      part = fma(x, x, part);
+    }
+    const double sigma = ed_sum(part, sh);
+    const double x0 = v[0];
+    const double tail = sigma - x0 * x0;
+    if (tid == 0) d[k] = A[(int64_t)k * D + k];
+    if (!(tail > 1e-300)) {          // already tridiagonal in this column
+      if (tid == 0) e[k] = x0;
+      __syncthreads();
+      continue;
+    }
+    const double alpha = -copysign(sqrt(sigma), x0);
+    if (tid == 0) e[k] = alpha;
+    const double v0 = x0 - alpha;
+    const double inv = 1.0 / sqrt(tail + v0 * v0);
+    __syncthreads();
+    for (int i = tid; i < n2; i += kThreads) v[i] = (i == 0 ? v0 : v[i]) * inv;
+    __syncthreads();
+    // p = 2 A' v (A' symmetric: thread i walks column i, rows coalesced)
+    const double* Ap = A + (int64_t)(k + 1) * D + (k + 1);
+    for (int i = tid; i < n2; i += kThreads) {
+      double acc = 0.0;
+      for (int j = 0; j < n2; ++j) acc = fma(Ap[(int64_t)j * D + i], v[j], acc);
+      w[i] = 2.0 * acc;
+    }
+    __syncthreads();
+    part = 0.0;
+    for (int i = tid; i < n2; i += kThreads) part = fma(v[i], w[i], part);
+    const double K = ed_sum(part, sh);
+    for (int i = tid; i < n2; i += kThreads) w[i] = fma(-K, v[i], w[i]);
+    __syncthreads();
+    // A' <- A' - v w^T - w v^T
+    double* Am = A + (int64_t)(k + 1) * D + (k + 1);
+    for (int j = 0; j < n2; ++j) {
+      const double vj = v[j], wj = w[j];
+      for (int i = tid; i < n2; i += kThreads) {
+        double& x = Am[(int64_t)j * D + i];
+        x = fma(-vj, w[i], fma(-wj, v[i], x));
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (D >= 2) {
+      d[D - 2] = A[(int64_t)(D - 2) * D + (D - 2)];
+      d[D - 1] = A[(int64_t)(D - 1) * D + (D - 1)];
+      e[D - 2] = A[(int64_t)(D - 1) * D + (D - 2)];
+    } else {
+      d[0] = A[0];
+    }
+    if (!tridiag_ql_first_row(d, e, z, D) && a.err) atomicOr(a.err, 8);
+  }
+  __syncthreads();
+  // ascending order: each value goes to its rank (ties by index)
+  double* out = a.evals + (int64_t)P.out_row * a.ld;
+  for (int i = tid; i < D; i += kThreads) {
+    const double x = d[i];
+    int rk = 0;
+    for (int j = 0; j < D; ++j) rk += (d[j] < x || (d[j] == x && j < i)) ? 1 : 0;
+    out[rk] = x;
+  }
+}
+
+hipError_t launch_sector_eig(const EigArgs& a, int n_sectors, size_t lds, hipStream_t st) {
+  if (n_sectors == 0) return hipSuccess;
+  hipLaunchKernelGGL(sector_eig_kernel, dim3(n_sectors), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+// Thermodynamics at the points (T, h) of every cluster: a sector with an
+// exact spectrum (ed_count > 0) contributes its eigenvalues with weight Nt
+// each (the scale on which a dimension-D sector's gamma_k sum to Nt * D),
+// the others their nodes and gamma_k as in thermo_field_kernel.  Mirror
+// sectors, the shift by the lowest energy of the point and the centred
+// second passes as there.
+__global__ __launch_bounds__(kThreads) void thermo_hybrid_kernel(const ThermoArgs a) {
+  __shared__ double sh[4];
+  const int t = blockIdx.x, c = blockIdx.y;
+  const int Nt = a.n_nodes;
+  const int p0 = a.cl_start[c], p1 = a.cl_start[c + 1];
+  const double beta = 1.0 / a.T[t];
+  const double hf = a.h ? a.h[t] : 0.0;
+
+  double emin = INFINITY, s0 = 0.0, s1 = 0.0, s2 = 0.0, ve = 0.0, vm = 0.0;
+  double eref = 0.0, S0 = 0.0, Ebar = 0.0, Mbar = 0.0;
+  for (int pass = 0; pass < 3; ++pass) {
+    for (int qq = p0; qq < p1; ++qq) {
+      const int p = a.cl_list[qq];
+      const ThermoProb tp = a.tp[p];
+      const int ned = a.ed_count[p];
+      const int items = ned > 0 ? ned : Nt;
+      const int nm = tp.weight > 1.0 ? 2 : 1;
+      for (int i = threadIdx.x; i < items; i += kThreads) {
+        double E, g;
+        if (ned > 0) {
+          E = a.evals[(int64_t)p * a.evals_ld + i];
+          g = (double)Nt;
+        } else {
+          const double x = cos(M_PI * ((double)i + 0.5) / (double)Nt);
+          E = a.ab[2 * p] * x + a.ab[2 * p + 1];
+          g = a.gamma[(int64_t)p * Nt + i];
+        }
+        for (int j = 0; j < nm; ++j) {
+          const double m = j == 0 ? tp.sz : -tp.sz;
+          const double Et = E + hf * m;
+          if (pass == 0) {
+            emin = fmin(emin, Et);
+          } else {
+            const double wgt = g * exp(-beta * (Et - eref));
+            if (pass == 1) {
+              s0 += wgt;
+              s1 = fma(wgt, Et, s1);
+              s2 = fma(wgt, m, s2);
+            } else {
+              const double de = Et - Ebar, dm = m - Mbar;
+              ve = fma(wgt, de * de, ve);
+              vm = fma(wgt, dm * dm, vm);
+            }
+          }
+        }
+      }
+    }
+    if (pass == 0) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) emin = fmin(emin, __shfl_down(emin, off, 64));
+      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      __syncthreads();
+      if (lane == 0) sh[wv] = emin;
+      __syncthreads();
+      eref = fmin(fmin(sh[0], sh[1]), fmin(sh[2], sh[3]));
+      __syncthreads();
+    } else if (pass == 1) {
+      S0 = ed_sum(s0, sh);
+      Ebar = ed_sum(s1, sh) / S0;
+      Mbar = ed_sum(s2, sh) / S0;
+    }
+  }
+  const double VarE = ed_sum(ve, sh) / S0;
+  const double VarM = ed_sum(vm, sh) / S0;
+  if (threadIdx.x == 0) {
+    const int64_t o = (int64_t)c * a.n_T + t;
+    a.lnZ[o] = (S0 > 0.0 ? log(S0 / (double)Nt) : NAN) - beta * eref;
+    a.E[o] = Ebar;
+    a.C[o] = beta * beta * VarE;
+    a.chi[o] = beta * VarM;
+    if (a.mag) a.mag[o] = Mbar;
+    if (a.znonpos) a.znonpos[o] = S0 > 0.0 ? 0 : 1;
+  }
+}
+
+hipError_t launch_thermo_hybrid(const ThermoArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(thermo_hybrid_kernel, dim3(a.n_T, a.n_clusters), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace kpm

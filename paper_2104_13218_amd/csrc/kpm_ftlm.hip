@@ -52,6 +52,12 @@ __global__ __launch_bounds__(kThreads) void ftlm_ritz_kernel(const FtlmArgs a) {
   double* d = a.ritz + (int64_t)c * S;
   double* e = a.escr + (int64_t)c * S;
   double* z = a.weight + (int64_t)c * S;
+  const int lc = c - U.col_off;          // column inside the block; padding past ncols
+  if (lc >= U.ncols) {
+    for (int j = 0; j < S; ++j) d[j] = z[j] = 0.0;
+    a.len[c] = 0;
+    return;
+  }
   const int L = (int)min((int64_t)S, P.dim);
   int n = 0;
   for (int j = 0; j < L; ++j) {
@@ -65,7 +71,7 @@ __global__ __launch_bounds__(kThreads) void ftlm_ritz_kernel(const FtlmArgs a) {
   if (a.vec_kind == 3) {
     cw = 1.0;
   } else if (a.vec_kind == 1) {
-    const int partner = (U.col0 & 1) ? c - 1 : c + 1;
+    const int partner = ((U.col0 + lc) & 1) ? c - 1 : c + 1;   // Re / Im of one vector
     cw = (double)P.dim / a.R * a.norms[c] / (a.norms[c] + a.norms[partner]);
   } else {
     cw = (double)P.dim / a.R;
@@ -101,8 +107,10 @@ __global__ __launch_bounds__(kThreads) void ftlm_thermo_kernel(const FtlmArgs a)
     for (int qq = q0; qq < q1; ++qq) {
       const int p = a.cl_list[qq];
       const ThermoProb tp = a.tp[p];
+      // the problem's columns: its blocks are consecutive (padding has no Ritz values)
       const int c0 = a.units[a.prob_unit0[p]].col_off;
-      const int c1 = c0 + (a.prob_unit0[p + 1] - a.prob_unit0[p]);
+      const UnitDev Ul = a.units[a.prob_unit0[p + 1] - 1];
+      const int c1 = Ul.col_off + Ul.ld;
       const int64_t items = (int64_t)(c1 - c0) * S;
       const int nm = tp.weight > 1 ? 2 : 1;
       for (int64_t i = threadIdx.x; i < items; i += kThreads) {

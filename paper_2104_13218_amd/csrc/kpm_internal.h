@@ -210,7 +210,7 @@ struct LzArgs {
   const int32_t* tile_nrows;
   double* w;
   const double* q;
-  const double* coef;      // per unit (column offset); squared if coef_sqrt
+  const double* coef;      // per column (col_off + c); squared if coef_sqrt
   const double* dotvec;    // NULL => dot with the updated w itself
   double* part_out;
   int64_t slot_stride;
@@ -241,7 +241,33 @@ struct ThermoArgs {
   int32_t n_nodes, n_T, n_clusters;
   const double* h;           // [n_T] Zeeman energies g mu_B B (field kernel only)
   double* mag;               // [n_clusters][n_T] <S^z> (field kernel, may be NULL)
+  // hybrid kernel: problem p with ed_count[p] > 0 contributes the eigenvalues
+  // evals[p * evals_ld + i], i < ed_count[p], instead of its nodes
+  const int32_t* ed_count;
+  const double* evals;
+  int32_t evals_ld;
 };
+
+// Exact spectrum of one small sector (dense diagonalisation).
+struct EigProb {
+  int32_t n_sites, n_up, dim, n_bonds;
+  int32_t bond_off, out_row;   // bonds in the packed arrays; row of the output
+  int64_t mat_off;             // doubles from the matrix workspace base
+};
+
+struct EigArgs {
+  const EigProb* probs;        // one per workgroup
+  const uint32_t* bmask;       // per bond: (1 << i) | (1 << j)
+  const double* J;             // per bond: J_b (unscaled H)
+  const uint32_t* binom;       // C(n, j) [33][33]
+  double* mat;                 // dense sector matrices
+  double* evals;               // [rows][ld] ascending eigenvalues
+  int* err;                    // bit 1: rank out of range, bit 3: QL did not converge
+  int32_t ld, max_dim;
+  int32_t o_bonds, o_vec;      // LDS byte offsets (bond J values, the five work vectors)
+};
+hipError_t launch_sector_eig(const EigArgs& a, int n_sectors, size_t lds, hipStream_t st);
+hipError_t launch_thermo_hybrid(const ThermoArgs& a, hipStream_t st);
 
 // Finite-temperature Lanczos: Ritz values/weights per column and the sums.
 struct FtlmArgs {

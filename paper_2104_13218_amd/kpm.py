@@ -73,6 +73,12 @@ _SIGS = {
     "kpm_ftlm": (c_int32, [POINTER(Problem), c_int32, POINTER(Params), c_void_p, c_void_p, c_int32,
                            c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                            c_void_p, c_size_t, c_void_p]),
+    "kpm_sector_eigenvalues_workspace_size": (c_size_t, [POINTER(Problem), c_int32, c_int32]),
+    "kpm_sector_eigenvalues": (c_int32, [POINTER(Problem), c_int32, c_int32, c_void_p, c_void_p, c_size_t,
+                                         c_void_p]),
+    "kpm_thermo_hybrid": (c_int32, [c_void_p, c_void_p, POINTER(Problem), c_int32, c_int32, c_int32, c_int32,
+                                    c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
+                                    c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "kpm_thermo_vjp": (c_int32, [c_void_p, c_void_p, POINTER(Problem), c_int32, c_int32, c_int32,
                                  c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "chebyshev_moments_vjp_workspace_size": (c_size_t, [POINTER(Problem), c_int32, POINTER(Params),
@@ -266,12 +272,12 @@ def thermo_field(mu, ab, sectors, T, h, kernel="jackson", n_nodes=0, stream=None
 
 
 def ftlm(sectors, krylov_dim, R=1, vec_kind="rademacher", T=(1.0,), h=None, seed=0, ritz=False,
-         stream=None):
+         col_block=0, stream=None):
     """Finite-temperature Lanczos thermodynamics: ln Z, E, C, chi, M = <S^z>
     [n_clusters, n_pts] at the points (T, h); with ritz=True also the Ritz
     values and estimator weights [real columns, steps]."""
     ps = sectors if isinstance(sectors, ProblemSet) else ProblemSet(sectors)
-    q = make_params(krylov_dim, R, vec_kind, "fp64", 0.0, seed)
+    q = make_params(krylov_dim, R, vec_kind, "fp64", 0.0, seed, col_block)
     T = torch.as_tensor(T, dtype=torch.float64, device="cuda").contiguous()
     hh = None if h is None else torch.as_tensor(h, dtype=torch.float64, device="cuda").expand_as(T).contiguous()
     nc, nT = ps.n_clusters, T.numel()
@@ -294,6 +300,42 @@ def ftlm(sectors, krylov_dim, R=1, vec_kind="rademacher", T=(1.0,), h=None, seed
                         ws.numel(), _stream(stream)), "kpm_ftlm")
     if ritz:
         out["ritz"], out["weight"] = rz, wt
+    return out
+
+
+def sector_eigenvalues(sectors, max_dim=512, stream=None):
+    """Exact spectra [n, max_dim] (ascending, NaN-padded; NaN rows for sectors
+    larger than max_dim)."""
+    ps = sectors if isinstance(sectors, ProblemSet) else ProblemSet(sectors)
+    lib = load()
+    nbytes = lib.kpm_sector_eigenvalues_workspace_size(ps.arr, len(ps), max_dim)
+    if nbytes == 0:
+        raise KPMError(KPM_EINVAL, "kpm_sector_eigenvalues_workspace_size")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    ev = torch.empty((len(ps), max_dim), dtype=torch.float64, device="cuda")
+    _check(lib.kpm_sector_eigenvalues(ps.arr, len(ps), max_dim, _ptr(ev), _ptr(ws), ws.numel(),
+                                      _stream(stream)), "kpm_sector_eigenvalues")
+    return ev
+
+
+def thermo_hybrid(mu, ab, sectors, evals, exact, T, h=None, kernel="jackson", n_nodes=0, stream=None):
+    """Thermodynamics [n_clusters, n_pts] with the sectors flagged in `exact`
+    taken from their spectra (rows of evals) and the rest from their moments."""
+    ps = sectors if isinstance(sectors, ProblemSet) else ProblemSet(sectors)
+    T = torch.as_tensor(T, dtype=torch.float64, device="cuda").contiguous()
+    hh = None if h is None else torch.as_tensor(h, dtype=torch.float64, device="cuda").expand_as(T).contiguous()
+    ex = np.ascontiguousarray(np.asarray(exact, dtype=np.uint8))
+    if ex.size != len(ps):
+        raise KPMError(KPM_EINVAL, "thermo_hybrid: one exact flag per problem")
+    evals = evals.contiguous()
+    nc, nT = ps.n_clusters, T.numel()
+    out = {k: torch.empty((nc, nT), dtype=torch.float64, device="cuda") for k in ("lnZ", "E", "C", "chi", "M")}
+    out["z_nonpos"] = torch.empty((nc, nT), dtype=torch.uint8, device="cuda")
+    _check(load().kpm_thermo_hybrid(_ptr(mu.contiguous()), _ptr(ab.contiguous()), ps.arr, len(ps), mu.shape[1],
+                                    KERNELS[kernel], n_nodes, _ptr(evals), evals.shape[1],
+                                    ex.ctypes.data_as(c_void_p), _ptr(T), _ptr(hh), nT, _ptr(out["lnZ"]),
+                                    _ptr(out["E"]), _ptr(out["C"]), _ptr(out["chi"]), _ptr(out["M"]),
+                                    _ptr(out["z_nonpos"]), _stream(stream)), "kpm_thermo_hybrid")
     return out
 
 

@@ -96,3 +96,17 @@ def test_workspace_size_query_is_host_only(kpmlib):
     n = kpmlib.load().chebyshev_moments_workspace_size(ps.arr, len(ps), ctypes.byref(q))
     # at least the two float64 recursion buffers of every (sector, column block)
     assert n >= 2 * 8 * 20 * 2**12 // 2
+
+
+def test_exact_spectra_arguments_on_host(kpmlib):
+    """kpm_sector_eigenvalues: workspace query and argument checks need no device."""
+    import workloads as W
+    lib = kpmlib.load()
+    ps = kpmlib.ProblemSet(W.sectors(W.ring(12)))               # dims 924, 792, 495, 220, 66, 12, 1
+    assert lib.kpm_sector_eigenvalues_workspace_size(ps.arr, len(ps), 0) == 0
+    assert lib.kpm_sector_eigenvalues_workspace_size(ps.arr, len(ps), 1025) == 0
+    small = lib.kpm_sector_eigenvalues_workspace_size(ps.arr, len(ps), 100)
+    big = lib.kpm_sector_eigenvalues_workspace_size(ps.arr, len(ps), 1000)
+    assert small >= 8 * (66**2 + 12**2 + 1) and big >= 8 * sum(d * d for d in (924, 792, 495, 220, 66, 12, 1))
+    assert lib.kpm_sector_eigenvalues(ps.arr, len(ps), 2000, None, None, 0, None) == kpmlib.KPM_EINVAL
+    assert lib.kpm_sector_eigenvalues(ps.arr, len(ps), 100, None, None, 0, None) == kpmlib.KPM_EINVAL

@@ -27,11 +27,13 @@ def _oracle_lists(secs, M_L, R, kind, seed):
     return [ftlm.sector_ritz(s, M_L, R, kind, seed) for s in secs]
 
 
+@pytest.mark.parametrize("col_block", [1, 0, 3])
 @pytest.mark.parametrize("kind,R", [("rademacher", 3), ("complex_gaussian", 2), ("gaussian", 2)])
-def test_ritz_values_and_weights(kpm, kind, R):
+def test_ritz_values_and_weights(kpm, kind, R, col_block):
+    """One column per block, the planner's blocks, and padded blocks."""
     secs = W.sectors(W.ring(10))
     M_L = 10
-    out = kpm.ftlm(secs, M_L, R, kind, T=[1.0], seed=7, ritz=True)
+    out = kpm.ftlm(secs, M_L, R, kind, T=[1.0], seed=7, ritz=True, col_block=col_block)
     rz, wt = out["ritz"].cpu().numpy(), out["weight"].cpu().numpy()
     lists = _oracle_lists(secs, M_L, R, kind, 7)
     c = 0
@@ -63,11 +65,12 @@ def test_thermodynamics_vs_oracle(kpm, kind, R, field):
         assert np.abs(g - w).max() <= 1e-9 * scale, (q, np.abs(g - w).max())
 
 
-def test_complete_basis_equals_ed(kpm):
+@pytest.mark.parametrize("col_block", [1, 0])
+def test_complete_basis_equals_ed(kpm, col_block):
     cl = W.ring(8)
     secs = W.sectors(cl)
     T = W.log_temperatures(25, 0.1, 10.0)
-    out = kpm.ftlm(secs, 70, 0, "basis", T=T)
+    out = kpm.ftlm(secs, 70, 0, "basis", T=T, col_block=col_block)
     ref = ed.thermo_from_spectra(ed.sector_spectra(secs), T)
     for q in ("lnZ", "E", "C", "chi"):
         g = out[q].cpu().numpy()[0]
