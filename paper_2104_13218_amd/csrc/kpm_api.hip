@@ -381,7 +381,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
          rows >= 32 && !D.block; rows >>= 1) {
       int Lm = std::max(1, std::min(env_int("KPM_BLOCK_L", s.tune.block_L > 0 ? s.tune.block_L : 9), 16));
       while (Lm > 1 && binom64(Lm, Lm / 2) > (uint64_t)rows) --Lm;
-      int lr = 1, hh = 1, mx = 1;
+      int lr = 1, hh = 1, mx = 1, ll = 1;
       for (int i = 0; i < n; ++i) {
         ProbDev& d = P.probs[i];
         const int L = std::min(p[i].n_sites, Lm);
@@ -402,12 +402,16 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
         lr = std::max(lr, 1 << L);
         hh = std::max(hh, d.n_hh);
         mx = std::max(mx, d.n_mx);
+        ll = std::max(ll, d.n_ll);
       }
       D.blk_rows = rows;
       D.lds_lr = lr;
       D.lds_hh = hh;
       D.lds_mx = mx;
-      if ((tab ? tab_lds_bytes(D) : block_lds_bytes(D)) <= cap) D.block = tab ? 2 : 1;
+      D.lds_ll = ll;
+      // the block-table kernel packs (row, low-low bond) into 16 bits
+      if ((tab ? tab_lds_bytes(D) : block_lds_bytes(D)) <= cap && (!tab || ll <= 255))
+        D.block = tab ? 2 : 1;
     }
   }
   int bspt = 1;

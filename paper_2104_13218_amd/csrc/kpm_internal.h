@@ -105,6 +105,7 @@ struct StepArgs {
   const uint16_t* meta_hq;     // [n_blk][meta_hh] its bond index inside the high-high class
   const uint32_t* meta_mstart; // [n_blk][meta_mx] per mixed bond: target block's first rank
   int32_t meta_hh, meta_mx;    // row lengths of the per-block tables (>= 1)
+  int32_t lds_ll;              // low-low bond capacity per row (block-table kernel)
 };
 
 // Device-side plan of one run (pointers into the workspace) + launch shape.
@@ -146,6 +147,7 @@ struct DevicePlan {
   int32_t n_blk = 0;           // block-table kernel: blocks of all problems
   int32_t meta_hh = 1, meta_mx = 1;   // per-block table widths (StepArgs)
   int32_t tab_xl = 0;          // block-table kernel: sub-tile rows of v_n staged in LDS
+  int32_t lds_ll = 1;          // block-table kernel: low-low bond capacity per row (<= 255)
   int32_t blk_max = 16, blk_rows = kThreads, lds_lr = 1, lds_hh = 1, lds_mx = 1, ld_max = 1;
   int64_t n_states = 0;        // entries of the state table
   int64_t part_len = 0;        // doubles per partial buffer

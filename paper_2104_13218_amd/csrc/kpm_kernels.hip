@@ -1031,13 +1031,13 @@ static hipError_t launch_block(const DevicePlan& p, const StepArgs& a, hipStream
 
 struct TabLds {
   size_t mask, off, zz, lrank, lunr, koff, bstart, bh, boff, bcnt, bhs, bhq, bms, rblk, rl, ri,
-      rdiag, xs, total;
+      rdiag, rlln, rll, xs, total;
 };
 
 // xs_bytes: the sub-tile's rows of v_n in LDS (0 = read through L1).
 __host__ __device__ inline TabLds tab_lds_layout(int lds_bonds, int lds_lr, int blk_max,
-                                                 int lds_hh, int lds_mx, int rows, int cpl,
-                                                 size_t xs_bytes) {
+                                                 int lds_hh, int lds_mx, int lds_ll, int rows,
+                                                 int cpl, size_t xs_bytes) {
   TabLds L{};
   size_t o = 0;
   auto put = [&](size_t b) {
@@ -1062,6 +1062,8 @@ __host__ __device__ inline TabLds tab_lds_layout(int lds_bonds, int lds_lr, int 
   L.rl = put(size_t(rows) * 2);
   L.ri = put(size_t(rows) * 2);
   L.rdiag = put(size_t(rows) * 8);
+  L.rlln = put(size_t(rows));
+  L.rll = put(size_t(rows) * lds_ll * 2);
   L.xs = put(xs_bytes);
   const size_t red = size_t(2 * cpl) * kThreads * 8;   // final reduction overlays all of it
   L.total = o > red ? o : red;
@@ -1070,7 +1072,8 @@ __host__ __device__ inline TabLds tab_lds_layout(int lds_bonds, int lds_lr, int 
 
 size_t tab_lds_bytes(const DevicePlan& p) {
   const size_t xs = p.tab_xl ? size_t(p.blk_rows) * p.ld_max * (p.fp32 ? 4 : 8) : 0;
-  return tab_lds_layout(p.lds_bonds, p.lds_lr, p.blk_max, p.lds_hh, p.lds_mx, p.blk_rows, p.cpl, xs)
+  return tab_lds_layout(p.lds_bonds, p.lds_lr, p.blk_max, p.lds_hh, p.lds_mx, p.lds_ll, p.blk_rows,
+                        p.cpl, xs)
       .total;
 }
 
@@ -1198,7 +1201,7 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
   if (tile >= a.n_tiles) return;
   const UnitDev U = a.units[a.tile_unit[tile]];
   const ProbDev P = a.probs[U.prob];
-  const TabLds Lo = tab_lds_layout(a.lds_bonds, a.lds_lr, a.blk_max, a.lds_hh, a.lds_mx,
+  const TabLds Lo = tab_lds_layout(a.lds_bonds, a.lds_lr, a.blk_max, a.lds_hh, a.lds_mx, a.lds_ll,
                                    a.blk_rows, CPL,
                                    XL ? size_t(a.blk_rows) * a.ld_max * sizeof(T) : 0);
   uint32_t* s_mask = reinterpret_cast<uint32_t*>(smem + Lo.mask);
@@ -1218,6 +1221,8 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
   uint16_t* s_rl = reinterpret_cast<uint16_t*>(smem + Lo.rl);
   uint16_t* s_ri = reinterpret_cast<uint16_t*>(smem + Lo.ri);
   double* s_rdiag = reinterpret_cast<double*>(smem + Lo.rdiag);
+  uint8_t* s_rlln = reinterpret_cast<uint8_t*>(smem + Lo.rlln);
+  uint16_t* s_rll = reinterpret_cast<uint16_t*>(smem + Lo.rll);
   T* xs = reinterpret_cast<T*>(smem + Lo.xs);
 
   const int nb = P.n_bonds, nll = P.n_ll, nhh = P.n_hh, nmx = P.n_mx;
@@ -1300,6 +1305,22 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
         const uint32_t v = sw & m;
         d += (v == 0u || v == m) ? s_zz[q] : -s_zz[q];
       }
+      // acting low-low bonds: the neighbour is row boff + lrank(l ^ m) of this
+      // sub-tile; (row, bond) packed in 16 bits
+      int nl = 0;
+      for (int q = 0; q < nll; ++q) {
+        const uint32_t m = s_mask[q];
+        const uint32_t v = l & m;
+        if (v == 0u || v == m) continue;
+        const int jr = s_boff[kb] + s_lrank[l ^ m];
+        if (jr < 0 || jr >= nrows) {
+          if (a.err) atomicOr(a.err, 4);
+          continue;
+        }
+        s_rll[tid * a.lds_ll + nl] = (uint16_t)(jr | (q << 8));
+        ++nl;
+      }
+      s_rlln[tid] = (uint8_t)nl;
       s_rblk[tid] = (uint8_t)kb;
       s_rl[tid] = (uint16_t)l;
       s_ri[tid] = (uint16_t)i;
@@ -1307,67 +1328,52 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
     }
     __syncthreads();
 
-    // Phase C: (row, column chunk) items.
+    // Phase C: (row, column chunk) items.  Diagonal, low-low (own sub-tile),
+    // high-high and mixed rows, GB loads in flight per batch; v_{n-1} is read
+    // and the own row read again only at the end, so that few registers stay
+    // live across the gathers.
     if (rg < nrg) {
       for (int r = rg; r < nrows; r += nrg) {
         const int64_t rho = row0 + r;
-        const VecT<T, CPL> xv = XL ? vload<T, CPL>(xs + r * ld + c * CPL)
-                                   : vload<T, CPL>(X + rho * ld + c * CPL);
-        VecT<T, CPL> yv;
-        if (!a.first) yv = vload_nt<T, CPL>(Yin + rho * ld + c * CPL);
-        const double dg = s_rdiag[r];
         double acc[CPL];
+        {
+          const VecT<T, CPL> xv = XL ? vload<T, CPL>(xs + r * ld + c * CPL)
+                                     : vload<T, CPL>(X + rho * ld + c * CPL);
+          const double dg = s_rdiag[r];
 #pragma unroll
-        for (int i = 0; i < CPL; ++i) acc[i] = dg * (double)xv.v[i];
-        const uint32_t l = s_rl[r];
+          for (int i = 0; i < CPL; ++i) acc[i] = dg * (double)xv.v[i];
+        }
+        {
+          // acting low-low neighbours, four at a time (a lane past its count adds nothing)
+          const int nl = s_rlln[r];
+          const uint16_t* ll = s_rll + r * a.lds_ll;
+          for (int k0 = 0; k0 < nl; k0 += 4) {
+            VecT<T, CPL> nv[4];
+            double cl[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const bool on = k0 + u < nl;
+              const uint32_t e = on ? ll[k0 + u] : 0u;
+              cl[u] = on ? s_off[e >> 8] : 0.0;
+              const int jr = on ? (int)(e & 0xFFu) : r;
+              nv[u] = XL ? vload<T, CPL>(xs + jr * ld + c * CPL)
+                         : vload<T, CPL>(X + (row0 + jr) * ld + c * CPL);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+#pragma unroll
+              for (int i = 0; i < CPL; ++i) acc[i] = fma(cl[u], (double)nv[u].v[i], acc[i]);
+            }
+          }
+        }
         const int kb = s_rblk[r];
         const int64_t ib = s_ri[r];
-        const int64_t bst = s_bstart[kb];
-        const uint32_t h = s_bh[kb];
         const int nh = s_bcnt[kb];
         const uint32_t* hs = s_bhs + kb * a.lds_hh;
         const uint16_t* hq = s_bhq + kb * a.lds_hh;
-        const uint32_t* ms = s_bms + kb * a.lds_mx;
-        // first batch of high-high rows in flight during the low-low part
-        // (absent entries read the row itself with a zero coefficient)
-        VecT<T, CPL> hv[GB];
-        double hcf[GB];
-#pragma unroll
-        for (int j = 0; j < GB; ++j) {
-          const bool on = j < nh;
-          const int64_t row = on ? (int64_t)hs[j] + ib : rho;
-          hcf[j] = on ? s_off[nll + hq[j]] : 0.0;
-          hv[j] = vload<T, CPL>(X + row * ld + c * CPL);
-        }
-        for (int q0 = 0; q0 < nll; q0 += 4) {
-          int64_t jj[4];
-          double cl[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int q = q0 + u;
-            const uint32_t m = q < nll ? s_mask[q] : 0u;
-            const uint32_t v = l & m;
-            const bool on = !(v == 0u || v == m);
-            if (XL) jj[u] = on ? s_boff[kb] + s_lrank[l ^ m] : r;
-            else jj[u] = on ? bst + s_lrank[l ^ m] : rho;
-            cl[u] = on ? s_off[q] : 0.0;
-          }
-          VecT<T, CPL> nl[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            nl[u] = XL ? vload<T, CPL>(xs + jj[u] * ld + c * CPL) : vload<T, CPL>(X + jj[u] * ld + c * CPL);
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-#pragma unroll
-            for (int i = 0; i < CPL; ++i) acc[i] = fma(cl[u], (double)nl[u].v[i], acc[i]);
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < GB; ++j) {
-#pragma unroll
-          for (int i = 0; i < CPL; ++i) acc[i] = fma(hcf[j], (double)hv[j].v[i], acc[i]);
-        }
-        for (int k0 = GB; k0 < nh; k0 += GB) {
+        // high-high rows: target block start + index in block (absent entries
+        // read the row itself with a zero coefficient)
+        for (int k0 = 0; k0 < nh; k0 += GB) {
           VecT<T, CPL> nv[GB];
           double cf[GB];
 #pragma unroll
@@ -1384,32 +1390,37 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
             for (int i = 0; i < CPL; ++i) acc[i] = fma(cf[j], (double)nv[j].v[i], acc[i]);
           }
         }
-        for (int k0 = 0; k0 < nmx; k0 += GB) {
-          VecT<T, CPL> nv[GB];
-          double cf[GB];
+        if (nmx > 0) {
+          const uint32_t l = s_rl[r];
+          const uint32_t h = s_bh[kb];
+          const uint32_t* ms = s_bms + kb * a.lds_mx;
+          for (int k0 = 0; k0 < nmx; k0 += GB) {
+            VecT<T, CPL> nv[GB];
+            double cf[GB];
 #pragma unroll
-          for (int j = 0; j < GB; ++j) {
-            const int q = k0 + j;
-            bool on = false;
-            int64_t row = rho;
-            if (q < nmx) {
-              const uint32_t m = s_mask[nll + nhh + q];
-              const uint32_t ml = m & lmask, mh = m >> Lb;
-              on = ((l & ml) != 0u) != ((h & mh) != 0u);
-              const uint32_t st = ms[q];
-              if (on && st == kNoRun) {
-                if (a.err) atomicOr(a.err, 2);
-                on = false;
+            for (int j = 0; j < GB; ++j) {
+              const int q = k0 + j;
+              bool on = false;
+              int64_t row = rho;
+              if (q < nmx) {
+                const uint32_t m = s_mask[nll + nhh + q];
+                const uint32_t ml = m & lmask, mh = m >> Lb;
+                on = ((l & ml) != 0u) != ((h & mh) != 0u);
+                const uint32_t st = ms[q];
+                if (on && st == kNoRun) {
+                  if (a.err) atomicOr(a.err, 2);
+                  on = false;
+                }
+                if (on) row = (int64_t)st + s_lrank[l ^ ml];
               }
-              if (on) row = (int64_t)st + s_lrank[l ^ ml];
+              cf[j] = on ? s_off[nll + nhh + q] : 0.0;
+              nv[j] = vload<T, CPL>(X + row * ld + c * CPL);
             }
-            cf[j] = on ? s_off[nll + nhh + q] : 0.0;
-            nv[j] = vload<T, CPL>(X + row * ld + c * CPL);
-          }
 #pragma unroll
-          for (int j = 0; j < GB; ++j) {
+            for (int j = 0; j < GB; ++j) {
 #pragma unroll
-            for (int i = 0; i < CPL; ++i) acc[i] = fma(cf[j], (double)nv[j].v[i], acc[i]);
+              for (int i = 0; i < CPL; ++i) acc[i] = fma(cf[j], (double)nv[j].v[i], acc[i]);
+            }
           }
         }
         VecT<T, CPL> ov;
@@ -1417,10 +1428,13 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
 #pragma unroll
           for (int i = 0; i < CPL; ++i) ov.v[i] = (T)acc[i];
         } else {
+          const VecT<T, CPL> yv = vload_nt<T, CPL>(Yin + rho * ld + c * CPL);
 #pragma unroll
           for (int i = 0; i < CPL; ++i) ov.v[i] = (T)(2.0 * acc[i] - (double)yv.v[i]);
         }
         vstore_nt<T, CPL>(Y + rho * ld + c * CPL, ov);
+        const VecT<T, CPL> xv = XL ? vload<T, CPL>(xs + r * ld + c * CPL)
+                                   : vload<T, CPL>(X + rho * ld + c * CPL);
 #pragma unroll
         for (int i = 0; i < CPL; ++i) {
           const double o = (double)ov.v[i];
@@ -1559,6 +1573,7 @@ static StepArgs make_step_args(const DevicePlan& p) {
     a.meta_hq = reinterpret_cast<const uint16_t*>(mb + m.hq);
     a.meta_hh = p.meta_hh;
     a.meta_mx = p.meta_mx;
+    a.lds_ll = p.lds_ll;
   }
   return a;
 }
