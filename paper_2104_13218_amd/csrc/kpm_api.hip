@@ -370,7 +370,12 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   // the autotuner override.
   const int block_env = env_int("KPM_BLOCK", kern < 0 ? -1 : (kern == 2 ? 1 : (kern == 3 ? 2 : 0)));
   const bool block_default = rb > 8;
-  const bool tab = block_env == 2 || (block_env < 0 && block_default);
+  // the block-table kernel addresses a block's slot with 32-bit element offsets
+  int64_t max_elems = 0;
+  for (int i = 0; i < n; ++i)
+    max_elems = std::max<int64_t>(max_elems, (int64_t)binom64(p[i].n_sites, p[i].n_up) *
+                                                 ((rb + cpl - 1) / cpl * cpl));
+  const bool tab = (block_env == 2 || (block_env < 0 && block_default)) && max_elems < (int64_t(1) << 32);
   if (!s.adjoint && s.allow_row && (block_env == 1 || tab || (block_env < 0 && block_default))) {
     D.ld_max = adj_ld ? adj_ld : (rb + cpl - 1) / cpl * cpl;
     D.blk_max = std::max(1, std::min(255, env_int("KPM_BLOCK_MAX", 16)));

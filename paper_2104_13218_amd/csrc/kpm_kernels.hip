@@ -1055,15 +1055,17 @@ __host__ __device__ inline TabLds tab_lds_layout(int lds_bonds, int lds_lr, int 
   L.bh = put(size_t(blk_max) * 4);
   L.boff = put(size_t(blk_max) * 4);
   L.bcnt = put(size_t(blk_max) * 4);
-  L.bhs = put(size_t(blk_max) * lds_hh * 4);
-  L.bhq = put(size_t(blk_max) * lds_hh * 2);
+  // + 8 entries: a batch of gathers may read up to GB - 1 entries past a
+  // block's list (those lanes are masked)
+  L.bhs = put((size_t(blk_max) * lds_hh + 8) * 4);
+  L.bhq = put((size_t(blk_max) * lds_hh + 8) * 2);
   L.bms = put(size_t(blk_max) * lds_mx * 4);
   L.rblk = put(size_t(rows));
   L.rl = put(size_t(rows) * 2);
   L.ri = put(size_t(rows) * 2);
   L.rdiag = put(size_t(rows) * 8);
   L.rlln = put(size_t(rows));
-  L.rll = put(size_t(rows) * lds_ll * 2);
+  L.rll = put((size_t(rows) * lds_ll + 4) * 2);
   L.xs = put(xs_bytes);
   const size_t red = size_t(2 * cpl) * kThreads * 8;   // final reduction overlays all of it
   L.total = o > red ? o : red;
@@ -1331,20 +1333,24 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
     // Phase C: (row, column chunk) items.  Diagonal, low-low (own sub-tile),
     // high-high and mixed rows, GB loads in flight per batch; v_{n-1} is read
     // and the own row read again only at the end, so that few registers stay
-    // live across the gathers.
+    // live across the gathers.  Element offsets inside the block's slot fit
+    // 32 bits (the planner guarantees dim * ld < 2^32); a slot past a row's
+    // count reads the row itself with a zero coefficient, so every lane of a
+    // batch issues its loads without branching.
     if (rg < nrg) {
+      const uint32_t ldu = (uint32_t)ld, cc = (uint32_t)(c * CPL);
       for (int r = rg; r < nrows; r += nrg) {
-        const int64_t rho = row0 + r;
+        const uint32_t rho = (uint32_t)(row0 + r);
         double acc[CPL];
         {
           const VecT<T, CPL> xv = XL ? vload<T, CPL>(xs + r * ld + c * CPL)
-                                     : vload<T, CPL>(X + rho * ld + c * CPL);
+                                     : vload<T, CPL>(X + (rho * ldu + cc));
           const double dg = s_rdiag[r];
 #pragma unroll
           for (int i = 0; i < CPL; ++i) acc[i] = dg * (double)xv.v[i];
         }
         {
-          // acting low-low neighbours, four at a time (a lane past its count adds nothing)
+          // acting low-low neighbours, four at a time
           const int nl = s_rlln[r];
           const uint16_t* ll = s_rll + r * a.lds_ll;
           for (int k0 = 0; k0 < nl; k0 += 4) {
@@ -1353,11 +1359,12 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               const bool on = k0 + u < nl;
-              const uint32_t e = on ? ll[k0 + u] : 0u;
-              cl[u] = on ? s_off[e >> 8] : 0.0;
-              const int jr = on ? (int)(e & 0xFFu) : r;
-              nv[u] = XL ? vload<T, CPL>(xs + jr * ld + c * CPL)
-                         : vload<T, CPL>(X + (row0 + jr) * ld + c * CPL);
+              const uint32_t e = ll[k0 + u];
+              cl[u] = s_off[on ? (e >> 8) : 0u];
+              cl[u] = on ? cl[u] : 0.0;
+              const uint32_t jr = on ? (e & 0xFFu) : (uint32_t)r;
+              nv[u] = XL ? vload<T, CPL>(xs + jr * ldu + cc)
+                         : vload<T, CPL>(X + (((uint32_t)row0 + jr) * ldu + cc));
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -1367,12 +1374,11 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
           }
         }
         const int kb = s_rblk[r];
-        const int64_t ib = s_ri[r];
+        const uint32_t ib = s_ri[r];
         const int nh = s_bcnt[kb];
         const uint32_t* hs = s_bhs + kb * a.lds_hh;
         const uint16_t* hq = s_bhq + kb * a.lds_hh;
-        // high-high rows: target block start + index in block (absent entries
-        // read the row itself with a zero coefficient)
+        // high-high rows: target block start + index in block
         for (int k0 = 0; k0 < nh; k0 += GB) {
           VecT<T, CPL> nv[GB];
           double cf[GB];
@@ -1380,9 +1386,12 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
           for (int j = 0; j < GB; ++j) {
             const int k = k0 + j;
             const bool on = k < nh;
-            const int64_t row = on ? (int64_t)hs[k] + ib : rho;
-            cf[j] = on ? s_off[nll + hq[k]] : 0.0;
-            nv[j] = vload<T, CPL>(X + row * ld + c * CPL);
+            const uint32_t hsv = hs[k];
+            const uint32_t hqv = hq[k];
+            const uint32_t row = on ? hsv + ib : rho;
+            cf[j] = s_off[nll + (on ? hqv : 0u)];
+            cf[j] = on ? cf[j] : 0.0;
+            nv[j] = vload<T, CPL>(X + (row * ldu + cc));
           }
 #pragma unroll
           for (int j = 0; j < GB; ++j) {
@@ -1401,7 +1410,7 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
             for (int j = 0; j < GB; ++j) {
               const int q = k0 + j;
               bool on = false;
-              int64_t row = rho;
+              uint32_t row = rho;
               if (q < nmx) {
                 const uint32_t m = s_mask[nll + nhh + q];
                 const uint32_t ml = m & lmask, mh = m >> Lb;
@@ -1411,10 +1420,10 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
                   if (a.err) atomicOr(a.err, 2);
                   on = false;
                 }
-                if (on) row = (int64_t)st + s_lrank[l ^ ml];
+                if (on) row = st + s_lrank[l ^ ml];
               }
               cf[j] = on ? s_off[nll + nhh + q] : 0.0;
-              nv[j] = vload<T, CPL>(X + row * ld + c * CPL);
+              nv[j] = vload<T, CPL>(X + (row * ldu + cc));
             }
 #pragma unroll
             for (int j = 0; j < GB; ++j) {
@@ -1428,13 +1437,13 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
 #pragma unroll
           for (int i = 0; i < CPL; ++i) ov.v[i] = (T)acc[i];
         } else {
-          const VecT<T, CPL> yv = vload_nt<T, CPL>(Yin + rho * ld + c * CPL);
+          const VecT<T, CPL> yv = vload_nt<T, CPL>(Yin + (rho * ldu + cc));
 #pragma unroll
           for (int i = 0; i < CPL; ++i) ov.v[i] = (T)(2.0 * acc[i] - (double)yv.v[i]);
         }
-        vstore_nt<T, CPL>(Y + rho * ld + c * CPL, ov);
+        vstore_nt<T, CPL>(Y + (rho * ldu + cc), ov);
         const VecT<T, CPL> xv = XL ? vload<T, CPL>(xs + r * ld + c * CPL)
-                                   : vload<T, CPL>(X + rho * ld + c * CPL);
+                                   : vload<T, CPL>(X + (rho * ldu + cc));
 #pragma unroll
         for (int i = 0; i < CPL; ++i) {
           const double o = (double)ov.v[i];
