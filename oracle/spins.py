@@ -1,0 +1,152 @@
+"""Spin-s Heisenberg sectors (oracle), the basis of the paper's spin-5/2 Fe10
+molecule (Sec. III.B).  Test infrastructure only.
+
+A site carries d = s + m in {0, .., 2s} (m = S^z of the site).  The sector
+with total sum d_i = n (S^z = n - N s) holds all digit strings with that sum,
+ordered by the value sum_i d_i B^i, B = 2s + 1, ascending; for s = 1/2 this is
+the spin-1/2 basis of `basis` (d_i = bit i, value = the word itself).
+
+  H = sum_b J_b (S^z_i S^z_j + (S^+_i S^-_j + S^-_i S^+_j)/2),
+  S^+ |m> = sqrt(s(s+1) - m(m+1)) |m+1>.
+
+Two ways to the index of a state are kept apart: brute-force enumeration with
+binary search (used by the Hamiltonian), and the counting formula
+(`rank_formula`): rank = sum over sites i, from the most significant down, of
+the number of states that agree above i and carry a smaller digit at i,
+cnt(i, r - v) summed over v < d_i, where cnt(i, r) counts digit strings of
+length i with sum r and r is the sum still left for sites 0..i.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def counts(N: int, two_s: int) -> np.ndarray:
+    """cnt[i, r]: digit strings of length i (digits 0..2s) with sum r."""
+    B = two_s + 1
+    cnt = np.zeros((N + 1, two_s * N + 1), dtype=np.int64)
+    cnt[0, 0] = 1
+    for i in range(1, N + 1):
+        for r in range(two_s * i + 1):
+            cnt[i, r] = sum(cnt[i - 1, r - v] for v in range(B) if r - v >= 0)
+    return cnt
+
+
+def sector_dim(N: int, two_s: int, n: int) -> int:
+    if not (0 <= n <= two_s * N):
+        return 0
+    return int(counts(N, two_s)[N, n])
+
+
+def sector_digits(N: int, two_s: int, n: int) -> np.ndarray:
+    """All digit strings [dim, N] (column i = site i) with sum n, ascending value
+    (brute force over B^N strings; small N only)."""
+    B = two_s + 1
+    if B ** N > 20_000_000:
+        raise ValueError("too many strings for brute force")
+    vals = np.arange(B ** N, dtype=np.int64)
+    digs = np.stack([(vals // B ** i) % B for i in range(N)], axis=1)
+    keep = digs.sum(axis=1) == n
+    return digs[keep]
+
+
+def values(digits: np.ndarray, two_s: int) -> np.ndarray:
+    B = two_s + 1
+    w = B ** np.arange(digits.shape[1], dtype=np.int64)
+    return digits.astype(np.int64) @ w
+
+
+def rank_formula(d, two_s: int) -> int:
+    """Index of digit string d in its sector by the counting formula."""
+    N = len(d)
+    cnt = counts(N, two_s)
+    r = int(sum(d))
+    rank = 0
+    for i in range(N - 1, -1, -1):
+        for v in range(int(d[i])):
+            if r - v >= 0:
+                rank += int(cnt[i, r - v])
+        r -= int(d[i])
+    return rank
+
+
+def _ladder(s: float, m: np.ndarray) -> np.ndarray:
+    """<m+1| S^+ |m> = sqrt(s(s+1) - m(m+1)) (0 at m = s)."""
+    return np.sqrt(np.maximum(s * (s + 1) - m * (m + 1), 0.0))
+
+
+def sector_hamiltonian(cluster, two_s: int, n: int) -> sp.csr_matrix:
+    """H on the sector (n = S^z + N s), CSR in the ascending value order;
+    neighbour indices by binary search in the enumerated basis."""
+    N = cluster.n_sites
+    s = two_s / 2.0
+    digs = sector_digits(N, two_s, n)
+    vals = values(digs, two_s)
+    B = two_s + 1
+    dim = vals.size
+    m = digs - s
+    diag = np.zeros(dim)
+    rows, cols, data = [], [], []
+    for i, j, Jb in zip(cluster.bond_i, cluster.bond_j, cluster.J):
+        i, j = int(i), int(j)
+        diag += Jb * m[:, i] * m[:, j]
+        # S^+_i S^-_j and S^-_i S^+_j
+        for a, b in ((i, j), (j, i)):
+            ok = (digs[:, a] < two_s) & (digs[:, b] > 0)
+            r = np.nonzero(ok)[0]
+            if not r.size:
+                continue
+            amp = 0.5 * Jb * _ladder(s, m[r, a]) * _ladder(s, -m[r, b])
+            t = vals[r] + B ** a - B ** b
+            c = np.searchsorted(vals, t)
+            assert np.all(vals[c] == t)
+            rows.append(r); cols.append(c); data.append(amp)
+    rows.append(np.arange(dim)); cols.append(np.arange(dim)); data.append(diag)
+    H = sp.coo_matrix((np.concatenate(data), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(dim, dim)).tocsr()
+    H.sum_duplicates()
+    return H
+
+
+def spin_matrices(two_s: int):
+    """S^x, S^y, S^z in the basis d = 0..2s (m = d - s)."""
+    s = two_s / 2.0
+    B = two_s + 1
+    m = np.arange(B) - s
+    Sp = np.zeros((B, B))
+    for d in range(B - 1):
+        Sp[d + 1, d] = math.sqrt(s * (s + 1) - m[d] * (m[d] + 1))
+    Sm = Sp.T
+    return (Sp + Sm) / 2, (Sp - Sm) / 2j, np.diag(m)
+
+
+def full_hamiltonian_kron(cluster, two_s: int) -> np.ndarray:
+    """Dense B^N x B^N H from Kronecker products (site i = digit i of the
+    value, so the leftmost factor is site N-1)."""
+    N = cluster.n_sites
+    B = two_s + 1
+    ops = spin_matrices(two_s)
+
+    def site(op, p):
+        out = np.ones((1, 1))
+        for q in range(N - 1, -1, -1):
+            out = np.kron(out, op if q == p else np.eye(B))
+        return out
+
+    H = np.zeros((B ** N, B ** N), dtype=complex)
+    for i, j, Jb in zip(cluster.bond_i, cluster.bond_j, cluster.J):
+        for op in ops:
+            H += Jb * (site(op, int(i)) @ site(op, int(j)))
+    assert np.abs(H.imag).max() < 1e-12
+    return H.real
+
+
+def sectors(cluster, two_s: int, cluster_id: int = 0):
+    """(n, dim) of every sector with S^z >= 0 (2n >= 2s N)."""
+    N = cluster.n_sites
+    lo = (two_s * N + 1) // 2
+    return [(n, sector_dim(N, two_s, n)) for n in range(lo, two_s * N + 1)]
