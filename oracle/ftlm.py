@@ -73,12 +73,13 @@ def sector_ritz(sector, M_L: int, R: int, kind: str, seed: int, H=None):
 
 def ftlm_thermo(problems, ritz_lists, T, h=0.0):
     """ln Z, E, C, chi, M = <S^z> per cluster and point (T[t], h[t]).
-    problems: dicts with cluster, n_sites, n_up; ritz_lists[p]: the
+    problems: dicts with cluster, n_sites, n_up (two_s for spin-s sites);
+    ritz_lists[p]: the
     (values, weights) pairs of sector p's columns."""
     T = np.asarray(T, dtype=np.float64)
     h = np.broadcast_to(np.asarray(h, dtype=np.float64), T.shape)
     cid = np.array([q["cluster"] for q in problems])
-    sz = np.array([q["n_up"] - 0.5 * q["n_sites"] for q in problems])
+    sz = np.array([q["n_up"] - 0.5 * q.get("two_s", 1) * q["n_sites"] for q in problems])
     nc = int(cid.max()) + 1
     out = {k: np.zeros((nc, T.size)) for k in ("lnZ", "E", "C", "chi", "M")}
     for c in range(nc):

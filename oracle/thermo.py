@@ -67,10 +67,14 @@ def dos_weights(mu: np.ndarray, g: np.ndarray, n_nodes: int) -> np.ndarray:
 
 
 def _sector_table(problems):
-    """cluster id, S^z and weight per problem; dense cluster ids."""
+    """cluster id, S^z and weight per problem; dense cluster ids.  For spin-s
+    sites (key two_s = 2s, default 1) n_up is the sum of the site digits
+    s + m_i, so S^z = n_up - s N; a sector with S^z != 0 stands for its
+    degenerate mirror too (weight 2)."""
     cid = np.array([p["cluster"] for p in problems])
-    sz = np.array([p["n_up"] - 0.5 * p["n_sites"] for p in problems])
-    W = np.array([1.0 if 2 * p["n_up"] == p["n_sites"] else 2.0 for p in problems])
+    tsn = np.array([p.get("two_s", 1) * p["n_sites"] for p in problems])
+    sz = np.array([p["n_up"] - 0.5 * t for p, t in zip(problems, tsn)])
+    W = np.array([1.0 if 2 * p["n_up"] == t else 2.0 for p, t in zip(problems, tsn)])
     return cid, sz, W
 
 
@@ -79,7 +83,8 @@ def thermo(problems, mu: np.ndarray, ab: np.ndarray, T: np.ndarray,
     """ln Z, E = <E>, C = beta^2 (<E^2> - <E>^2), chi = beta (<S_z^2> - <S_z>^2)
     per cluster and temperature (k_B = g mu_B = 1), and the Z <= 0 flag.
 
-    problems: list of dicts with keys cluster, n_sites, n_up; mu [P, M];
+    problems: list of dicts with keys cluster, n_sites, n_up (and two_s for
+    spin-s sites); mu [P, M];
     ab [P, 2] = (a, b) of each problem's rescaling."""
     mu = np.atleast_2d(mu)
     P, M = mu.shape

@@ -91,3 +91,75 @@ def test_su2_multiplets_fe10_like_ring():
                 assert abs(prev[k] - x) < 1e-9
                 prev = np.delete(prev, k)
         prev = e
+
+
+@pytest.mark.parametrize("two_s,cl", [(2, W.ring(4)), (3, W.Cluster(3, np.array([0, 1, 0]), np.array([1, 2, 2]),
+                                                                      np.array([1.0, 0.6, -0.8])))])
+def test_sector_thermodynamics_with_mirrors_match_full_space(two_s, cl):
+    """The S^z >= 0 sectors with weight 2 for S^z != 0 (two_s given to the
+    thermodynamics) reproduce ln Z, E, C, chi and <S^z> in a field h of the
+    whole B^N space, with H - h S^z_total from Kronecker products."""
+    from oracle import thermo
+    N = cl.n_sites
+    secs = spins.sectors(cl, two_s)
+    probs = [dict(cluster=0, n_sites=N, n_up=n, two_s=two_s) for n, _ in secs]
+    spectra = [np.linalg.eigvalsh(spins.sector_hamiltonian(cl, two_s, n).toarray()) for n, _ in secs]
+    M = 8
+    mus = np.zeros((len(secs), M))
+    ab = np.tile([1.0, 0.0], (len(secs), 1))
+    T = np.array([0.2, 0.7, 1.5, 4.0])
+    h = np.array([0.0, 0.5, -1.1, 2.0])
+    out = thermo.thermo_hybrid(probs, mus, ab, spectra, T, h, "none", M)
+    H = spins.full_hamiltonian_kron(cl, two_s)
+    Sz = spins.spin_matrices(two_s)[2]
+    B = two_s + 1
+    Szt = sum(np.kron(np.kron(np.eye(B ** (N - 1 - p)), Sz), np.eye(B ** p)) for p in range(N)).real
+    for t, (Tv, hv) in enumerate(zip(T, h)):
+        e, U = np.linalg.eigh(H + hv * Szt)    # Zeeman term with the sign convention E + h m
+        # <S^z> and <(S^z)^2> per eigenvector (degenerate eigenvectors may mix
+        # S^z sectors, so the square is taken as an operator)
+        mz = np.einsum("ij,ik,kj->j", U, Szt, U)
+        mz2 = np.einsum("ij,ik,kj->j", U, Szt @ Szt, U)
+        w = np.exp(-(e - e.min()) / Tv)
+        Z = w.sum()
+        E = (w * e).sum() / Z
+        Mz = (w * mz).sum() / Z
+        ref = dict(lnZ=np.log(Z) - e.min() / Tv, E=E, C=((w * (e - E) ** 2).sum() / Z) / Tv ** 2,
+                   chi=((w * mz2).sum() / Z - Mz ** 2) / Tv, M=Mz)
+        for k, v in ref.items():
+            assert abs(out[k][0, t] - v) < 1e-9 * max(1.0, abs(v)), (k, t, out[k][0, t], v)
+
+
+@pytest.mark.parametrize("N,two_s,n", [(4, 2, 4), (5, 3, 8), (3, 5, 7), (6, 1, 3), (4, 7, 14), (3, 2, 6)])
+def test_rank_table_and_unrank_invert_enumeration(N, two_s, n):
+    digs = spins.sector_digits(N, two_s, n)
+    np.testing.assert_array_equal(spins.rank_many(digs, two_s, n), np.arange(len(digs)))
+    for r in range(len(digs)):
+        np.testing.assert_array_equal(spins.unrank_formula(r, N, two_s, n), digs[r])
+    with pytest.raises(ValueError):
+        spins.unrank_formula(len(digs), N, two_s, n)
+
+
+@pytest.mark.parametrize("two_s,cl,n,kind", [
+    (2, W.ring(5), 5, "rademacher"),
+    (3, W.Cluster(4, np.array([0, 1, 2, 0]), np.array([1, 2, 3, 2]), np.array([1.0, -0.7, 0.4, 1.2])), 7,
+     "gaussian"),
+    (5, W.ring(3), 9, "complex_gaussian")])
+def test_recursion_rows_match_dense_chebyshev(two_s, cl, n, kind):
+    """Rows of T_m(H') v_0 from the cones equal the dense recursion on the
+    enumerated sector (m = 0..4, every row)."""
+    from oracle import hamiltonian, rng
+    H = spins.sector_hamiltonian(cl, two_s, n).toarray()
+    dim = H.shape[0]
+    e = np.linalg.eigvalsh(H)
+    a, b = hamiltonian.scale_from_bounds(e.min() - 0.1, e.max() + 0.1, 0.025)
+    Ht = (H - b * np.eye(dim)) / a
+    V0, _, R_eff = rng.random_columns(kind, 3, 2, n, 2, dim)
+    prev, cur = None, V0
+    for m in range(5):
+        if m == 1:
+            prev, cur = cur, Ht @ cur
+        elif m > 1:
+            prev, cur = cur, 2 * Ht @ cur - prev
+        got = spins.recursion_rows(cl, two_s, n, a, b, kind, 3, 2, np.arange(dim), m, cluster_id=2)
+        np.testing.assert_allclose(got, cur, rtol=0, atol=1e-12 * max(1.0, np.abs(cur).max()))
