@@ -68,10 +68,12 @@ extern "C" {
 #define KPM_KERNEL_NONE 0    /* g_n = 1 */
 #define KPM_KERNEL_JACKSON 1 /* Jackson kernel with N_deg = M */
 
-/* One (cluster, S^z sector) problem.  S^z = n_up - n_sites/2 >= 0. */
+/* One (cluster, S^z sector) problem.  S^z = n_up - n_sites/2 >= 0 (spin 1/2). */
 typedef struct {
-  int32_t n_sites;       /* N, 2..32 */
-  int32_t n_up;          /* up spins, n_sites/2 <= n_up <= n_sites (2 n_up >= N) */
+  int32_t n_sites;       /* N, 2..32 (spin s > 1/2: 2..16 with 2s N <= 63) */
+  int32_t n_up;          /* up spins, n_sites/2 <= n_up <= n_sites (2 n_up >= N); for
+                            spin s (two_s >= 2): sum over sites of s + m_i = S^z + N s,
+                            with 2 n_up >= 2s N (S^z >= 0) and n_up <= 2s N */
   int32_t n_bonds;       /* 0..512; i != j, 0 <= i, j < N; repeats are summed */
   int32_t cluster;       /* dense id 0.. < 65536: thermodynamic system and RNG
                             stream; problems of one cluster are its sectors */
@@ -80,6 +82,18 @@ typedef struct {
   const double* J;       /* host [n_bonds], finite */
   double e_lo, e_hi;     /* spectral bounds E_min <= E_max of Eq. (5); NaN in
                             either => estimated by Lanczos (kpm_params) */
+  int32_t two_s;         /* 2s of every site: 0 or 1 = spin 1/2; 2..7 = spin 1 .. 7/2
+                            (the spin-5/2 Fe10 wheel of Sec. III.B).  H = sum_b J_b
+                            S_i . S_j; the sector basis is the digit strings d_i = s + m_i
+                            with the given sum in ascending value sum_i d_i (2s+1)^i.
+                            Spin s > 1/2 is accepted by chebyshev_moments,
+                            chebyshev_vectors, kpm_spectral_bounds, kpm_ftlm and the
+                            thermodynamics entry points (kpm_thermo, kpm_thermo_field,
+                            kpm_thermo_hybrid); the gradient entry points,
+                            kpm_sector_eigenvalues and kpm_sector_matrix reject it with
+                            KPM_EINVAL.  A call holding any spin-s problem runs every
+                            problem of the call with the spin-s step kernel */
+  int32_t reserved;      /* must be 0 */
 } kpm_problem;
 
 typedef struct {
@@ -306,7 +320,7 @@ typedef struct {
   int32_t rows_per_tile;   /* basis states per workgroup tile (block kernels: mean) */
   int32_t graph_segment;   /* steps per captured graph (0 = direct launches) */
   int32_t kernel;          /* step kernel used: 0 column-chunk, 1 row, 2 block,
-                              3 block-table */
+                              3 block-table, 4 spin-s */
   double recursion_ms;     /* hipEvent time on the call's stream from the first
                               to the last recursion-step launch, inclusive */
 } kpm_run_stats;

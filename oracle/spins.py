@@ -46,14 +46,36 @@ def sector_dim(N: int, two_s: int, n: int) -> int:
 
 def sector_digits(N: int, two_s: int, n: int) -> np.ndarray:
     """All digit strings [dim, N] (column i = site i) with sum n, ascending value
-    (brute force over B^N strings; small N only)."""
+    (brute force over B^N strings when that is small, else a depth-first walk
+    from the most significant site with the sum still reachable by the rest)."""
     B = two_s + 1
-    if B ** N > 20_000_000:
-        raise ValueError("too many strings for brute force")
-    vals = np.arange(B ** N, dtype=np.int64)
-    digs = np.stack([(vals // B ** i) % B for i in range(N)], axis=1)
-    keep = digs.sum(axis=1) == n
-    return digs[keep]
+    if B ** N <= 20_000_000:
+        vals = np.arange(B ** N, dtype=np.int64)
+        digs = np.stack([(vals // B ** i) % B for i in range(N)], axis=1)
+        keep = digs.sum(axis=1) == n
+        return digs[keep]
+    return _walk_digits(N, two_s, n)
+
+
+def _walk_digits(N: int, two_s: int, n: int, limit: int = 2_000_000) -> np.ndarray:
+    out = []
+    d = [0] * N
+
+    def rec(i, left):
+        if i < 0:
+            if left == 0:
+                out.append(list(d))
+                if len(out) > limit:
+                    raise ValueError("sector too large to enumerate")
+            return
+        for x in range(0, min(two_s, left) + 1):
+            if left - x <= two_s * i:
+                d[i] = x
+                rec(i - 1, left - x)
+        d[i] = 0
+
+    rec(N - 1, n)
+    return np.array(out, dtype=np.int64).reshape(-1, N)
 
 
 def values(digits: np.ndarray, two_s: int) -> np.ndarray:

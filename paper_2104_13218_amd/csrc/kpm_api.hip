@@ -37,6 +37,51 @@ uint64_t binom64(int n, int k) {
   return r;
 }
 
+// Spin-s sectors: 2s of a problem (1 for spin 1/2) and the counts
+// cnt[i][r] of digit strings of length i (digits 0..2s) with sum r.
+int two_s_of(const kpm_problem& p) { return p.two_s <= 1 ? 1 : p.two_s; }
+
+std::vector<uint64_t> spin_counts(int N, int ts) {
+  const int R1 = ts * N + 1;
+  std::vector<uint64_t> cnt((size_t)(N + 1) * R1, 0);
+  cnt[0] = 1;
+  for (int i = 1; i <= N; ++i)
+    for (int r = 0; r < R1; ++r) {
+      uint64_t v = 0;
+      for (int d = 0; d <= ts && d <= r; ++d) v += cnt[(size_t)(i - 1) * R1 + (r - d)];
+      cnt[(size_t)i * R1 + r] = v;
+    }
+  return cnt;
+}
+
+// Sector dimension of a problem (C(N, n_up) for spin 1/2).
+uint64_t prob_dim(const kpm_problem& p) {
+  const int ts = two_s_of(p);
+  if (ts == 1) return binom64(p.n_sites, p.n_up);
+  if (p.n_up < 0 || p.n_up > ts * p.n_sites) return 0;
+  return spin_counts(p.n_sites, ts)[(size_t)p.n_sites * (ts * p.n_sites + 1) + p.n_up];
+}
+
+// Rank table of a spin-s sector: P[i][r][d] = sum_{v < d} cnt[i][r - v].
+void build_spin_table(int N, int ts, std::vector<uint32_t>& out) {
+  const int R1 = ts * N + 1, B = ts + 1;
+  const std::vector<uint64_t> cnt = spin_counts(N, ts);
+  for (int i = 0; i < N; ++i)
+    for (int r = 0; r < R1; ++r) {
+      uint64_t acc = 0;
+      for (int d = 0; d < B; ++d) {
+        out.push_back((uint32_t)acc);
+        if (r - d >= 0) acc += cnt[(size_t)i * R1 + (r - d)];
+      }
+    }
+}
+
+bool any_spin(const kpm_problem* p, int n) {
+  for (int i = 0; p && i < n; ++i)
+    if (two_s_of(p[i]) > 1) return true;
+  return false;
+}
+
 std::vector<uint32_t> binom_table() {
   std::vector<uint32_t> t(kBinomN * kBinomN, 0);
   for (int n = 0; n < kBinomN; ++n)
@@ -103,8 +148,17 @@ void build_tables(int N, int k, Split sp, std::vector<uint32_t>& out) {
 // ------------------------------------------------------------------ validation
 
 int check_problem(const kpm_problem& p) {
-  if (p.n_sites < 1 || p.n_sites > 32) return KPM_EINVAL;
-  if (2 * p.n_up < p.n_sites || p.n_up > p.n_sites) return KPM_EINVAL;
+  if (p.two_s < 0 || p.two_s > 7 || p.reserved != 0) return KPM_EINVAL;
+  const int ts = two_s_of(p);
+  if (ts == 1) {
+    if (p.n_sites < 1 || p.n_sites > 32) return KPM_EINVAL;
+    if (2 * p.n_up < p.n_sites || p.n_up > p.n_sites) return KPM_EINVAL;
+  } else {
+    // digits in 4 bits of a 64-bit word; the digit sum is the RNG stream's 6-bit sector field
+    if (p.n_sites < 1 || p.n_sites > 16 || ts * p.n_sites > 63) return KPM_EINVAL;
+    if (2 * p.n_up < ts * p.n_sites || p.n_up > ts * p.n_sites) return KPM_EINVAL;
+    if (prob_dim(p) >= (uint64_t(1) << 32)) return KPM_EINVAL;
+  }
   if (p.n_bonds < 0 || p.n_bonds > kMaxBonds) return KPM_EINVAL;
   if (p.cluster < 0 || p.cluster > 65535) return KPM_EINVAL;
   if (p.n_bonds > 0 && (!p.bond_i || !p.bond_j || !p.J)) return KPM_EINVAL;
@@ -174,7 +228,7 @@ constexpr int kAdjMaxLd = 16;
 int cols_per_vec(int vec_kind) { return vec_kind == KPM_VEC_COMPLEX_GAUSSIAN ? 2 : 1; }
 
 int64_t total_columns(const kpm_problem& p, const RunShape& s) {
-  if (s.vec_kind == KPM_VEC_BASIS) return (int64_t)binom64(p.n_sites, p.n_up);
+  if (s.vec_kind == KPM_VEC_BASIS) return (int64_t)prob_dim(p);
   return (int64_t)s.R * cols_per_vec(s.vec_kind);
 }
 
@@ -292,23 +346,31 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
       }
 
   P.binom = binom_table();
+  // any spin s > 1/2: the spin kernel runs every problem of the plan
+  const bool spin = any_spin(p, n);
   int max_bonds = 1, max_tab = 1;
   int64_t max_dim = 1, n_states = 0;
   size_t bond_total = 0;
   for (int i = 0; i < n; ++i) {
     ProbDev d{};
-    d.dim = (int64_t)binom64(p[i].n_sites, p[i].n_up);
+    d.dim = (int64_t)prob_dim(p[i]);
     d.n_sites = p[i].n_sites;
     d.n_up = p[i].n_up;
     d.n_bonds = p[i].n_bonds;
     d.bond_off = (int32_t)bond_total;
-    const Split sp = choose_split(p[i].n_sites);
-    d.B0 = sp.B0;
-    d.B1 = sp.B1;
-    d.B2 = sp.B2;
+    d.two_s = two_s_of(p[i]);
     d.tab_off = (int32_t)P.tables.size();
-    d.tab_len = (int32_t)sp.len();
-    build_tables(p[i].n_sites, p[i].n_up, sp, P.tables);
+    if (spin) {
+      build_spin_table(p[i].n_sites, d.two_s, P.tables);
+      d.tab_len = (int32_t)(P.tables.size() - d.tab_off);
+    } else {
+      const Split sp = choose_split(p[i].n_sites);
+      d.B0 = sp.B0;
+      d.B1 = sp.B1;
+      d.B2 = sp.B2;
+      d.tab_len = (int32_t)sp.len();
+      build_tables(p[i].n_sites, p[i].n_up, sp, P.tables);
+    }
     d.cluster = p[i].cluster;
     const double a = a_arr ? a_arr[i] : 1.0, b = b_arr ? b_arr[i] : 0.0;
     d.shift = -b / a;
@@ -316,7 +378,8 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
     d.state_off = n_states;
     n_states += d.dim;
     for (int k = 0; k < p[i].n_bonds; ++k) {
-      P.bmask.push_back((1u << p[i].bond_i[k]) | (1u << p[i].bond_j[k]));
+      if (spin) P.bmask.push_back((uint32_t)p[i].bond_i[k] | ((uint32_t)p[i].bond_j[k] << 8));
+      else P.bmask.push_back((1u << p[i].bond_i[k]) | (1u << p[i].bond_j[k]));
       P.boff.push_back(p[i].J[k] / (2.0 * a));
       P.bzz.push_back(p[i].J[k] / (4.0 * a));
     }
@@ -343,16 +406,25 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   // per sub-tile; never exceed 64 KB.
   const size_t lds_soft = (size_t)env_int("KPM_LDS_CAP", 32 * 1024);
   const size_t lds_hard = 64 * 1024;
-  while (step_lds_bytes(D) > lds_soft && D.sub_rows > 64) D.sub_rows >>= 1;
-  while (step_lds_bytes(D) > lds_hard && D.sub_rows > 32) D.sub_rows >>= 1;
+  if (spin) {
+    // spin kernel: every problem, no row/block kernels; two neighbours per bond
+    if (s.adjoint) return KPM_EINVAL;
+    D.spin = 1;
+    D.lds_nb = 2 * max_bonds;
+    while (spin_lds_bytes(D) > lds_soft && D.sub_rows > 32) D.sub_rows >>= 1;
+    if (spin_lds_bytes(D) > lds_hard) return KPM_EINVAL;
+    row_ld = 0;
+  }
+  while (!spin && step_lds_bytes(D) > lds_soft && D.sub_rows > 64) D.sub_rows >>= 1;
+  while (!spin && step_lds_bytes(D) > lds_hard && D.sub_rows > 32) D.sub_rows >>= 1;
   if (s.adjoint)
     while (adjoint_lds_bytes(D) > lds_hard && D.sub_rows > 32) D.sub_rows >>= 1;
-  if (step_lds_bytes(D) > lds_hard) return KPM_EINVAL;
+  if (!spin && step_lds_bytes(D) > lds_hard) return KPM_EINVAL;
   if (s.adjoint && (adjoint_lds_bytes(D) > lds_hard || max_bonds > D.sub_rows)) return KPM_EINVAL;
   D.row_ld = row_ld;
   if (row_ld && row_lds_bytes(D) > lds_hard) D.row_ld = row_ld = 0;
   if (row_ld) D.sub_rows = kThreads;
-  D.n_states = n_states;
+  D.n_states = spin ? 0 : n_states;   // the spin kernel unranks every row itself
 
   // Block kernel (tiles of whole low-bit blocks) when its LDS fits: bonds in
   // class order low-low, high-high, mixed.
@@ -363,8 +435,6 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   std::vector<std::vector<int64_t>> btile_row0(n);
   std::vector<std::vector<int32_t>> btile_nrows(n);
   std::vector<BlockList> blists(n);
-  // Default: float32 storage with blocks too wide for the row kernel (the
-  // measured case where it is the fastest kernel); KPM_BLOCK=0/1 overrides.
   // Default: the block-table kernel for blocks too wide for the row kernel
   // (the measured case where it is the fastest kernel); KPM_BLOCK=0/1/2 and
   // the autotuner override.
@@ -373,10 +443,10 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   // the block-table kernel addresses a block's slot with 32-bit element offsets
   int64_t max_elems = 0;
   for (int i = 0; i < n; ++i)
-    max_elems = std::max<int64_t>(max_elems, (int64_t)binom64(p[i].n_sites, p[i].n_up) *
+    max_elems = std::max<int64_t>(max_elems, (int64_t)prob_dim(p[i]) *
                                                  ((rb + cpl - 1) / cpl * cpl));
   const bool tab = (block_env == 2 || (block_env < 0 && block_default)) && max_elems < (int64_t(1) << 32);
-  if (!s.adjoint && s.allow_row && (block_env == 1 || tab || (block_env < 0 && block_default))) {
+  if (!spin && !s.adjoint && s.allow_row && (block_env == 1 || tab || (block_env < 0 && block_default))) {
     D.ld_max = adj_ld ? adj_ld : (rb + cpl - 1) / cpl * cpl;
     D.blk_max = std::max(1, std::min(255, env_int("KPM_BLOCK_MAX", 16)));
     const size_t cap = (size_t)env_int("KPM_BLOCK_LDS", 64 * 1024);
@@ -1169,7 +1239,7 @@ int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
     for (int32_t r : P.tile_nrows) rows += r;
     g_stats.rows_per_tile = (int32_t)std::lround(rows / (double)P.tile_nrows.size());
   }
-  g_stats.kernel = D.block == 2 ? 3 : (D.block ? 2 : (D.row_ld ? 1 : 0));
+  g_stats.kernel = D.spin ? 4 : (D.block == 2 ? 3 : (D.block ? 2 : (D.row_ld ? 1 : 0)));
   g_stats.graph_segment = used_segment;
   float ms = 0.f;
   g_stats.recursion_ms = hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess ? (double)ms : -1.0;
@@ -1440,8 +1510,10 @@ int thermo_meta(const kpm_problem* p, int n, std::vector<ThermoProb>& tp,
   if (!p || n < 1) return KPM_EINVAL;
   n_clusters = 0;
   for (int i = 0; i < n; ++i) {
-    if (p[i].n_sites < 1 || p[i].n_sites > 64 || 2 * p[i].n_up < p[i].n_sites ||
-        p[i].n_up > p[i].n_sites || p[i].cluster < 0 || p[i].cluster > 65535)
+    const int ts = two_s_of(p[i]);
+    if (p[i].two_s < 0 || p[i].two_s > 7 || p[i].n_sites < 1 || p[i].n_sites > 64 ||
+        2 * p[i].n_up < ts * p[i].n_sites || p[i].n_up > ts * p[i].n_sites || p[i].cluster < 0 ||
+        p[i].cluster > 65535)
       return KPM_EINVAL;
     n_clusters = std::max(n_clusters, p[i].cluster + 1);
   }
@@ -1449,8 +1521,9 @@ int thermo_meta(const kpm_problem* p, int n, std::vector<ThermoProb>& tp,
   start.assign(n_clusters + 1, 0);
   for (int i = 0; i < n; ++i) {
     tp[i].cluster = p[i].cluster;
-    tp[i].weight = 2 * p[i].n_up == p[i].n_sites ? 1 : 2;
-    tp[i].sz = p[i].n_up - 0.5 * p[i].n_sites;
+    const int ts = two_s_of(p[i]);
+    tp[i].weight = 2 * p[i].n_up == ts * p[i].n_sites ? 1 : 2;
+    tp[i].sz = p[i].n_up - 0.5 * ts * p[i].n_sites;
     start[p[i].cluster + 1]++;
   }
   for (int c = 0; c < n_clusters; ++c) {
@@ -1600,6 +1673,7 @@ int ed_plan(const kpm_problem* p, int n, int max_dim, EdPlan& E) {
   int r = check_problems(p, n);
   if (r != KPM_OK) return r;
   if (max_dim < 1 || max_dim > kEdMaxDim) return KPM_EINVAL;
+  if (any_spin(p, n)) return KPM_EINVAL;
   int64_t mat = 0;
   for (int i = 0; i < n; ++i) {
     const uint64_t dim = binom64(p[i].n_sites, p[i].n_up);
@@ -1687,7 +1761,7 @@ int kpm_sector_states(int32_t n_sites, int32_t n_up, uint32_t* d_states, void* s
 int kpm_sector_matrix(const kpm_problem* p, int64_t row0, int64_t nrows, int32_t max_nb,
                       uint32_t* d_cols, int32_t* d_bond, int32_t* d_cnt, double* d_diag,
                       void* stream) {
-  if (!p || check_problem(*p) != KPM_OK) return KPM_EINVAL;
+  if (!p || check_problem(*p) != KPM_OK || two_s_of(*p) > 1) return KPM_EINVAL;
   const int64_t dim = (int64_t)binom64(p->n_sites, p->n_up);
   if (row0 < 0 || nrows < 0 || row0 + nrows > dim || max_nb < p->n_bonds || max_nb < 1)
     return KPM_EINVAL;
@@ -2211,7 +2285,7 @@ int kpm_thermo_hybrid(const double* d_mu, const double* d_ab, const kpm_problem*
   std::vector<int32_t> cnt(n, 0);
   for (int i = 0; i < n; ++i) {
     if (!h_exact[i]) continue;
-    const uint64_t dim = binom64(p[i].n_sites, p[i].n_up);
+    const uint64_t dim = prob_dim(p[i]);
     if (!d_evals || dim > (uint64_t)std::max(evals_ld, 0)) return KPM_EINVAL;
     cnt[i] = (int32_t)dim;
   }

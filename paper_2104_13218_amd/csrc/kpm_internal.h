@@ -31,6 +31,10 @@ struct ProbDev {
   // Block-table kernel: this problem's blocks are [blk_off, blk_off + n_blk)
   // of the plan's block list (ascending h, i.e. rank order).
   int32_t blk_off, n_blk;
+  // Spin-s sites (spin kernel): 2s; the rank table at tab_off is
+  // P[i][r][d] = number of digit strings of sites 0..i with sum r and digit
+  // < d at site i, [n_sites][2s n_sites + 1][2s + 1]; bond masks hold i | j << 8.
+  int32_t two_s, pad_s;
 };
 
 // One recursion block: a problem and a contiguous range of its real columns.
@@ -147,6 +151,7 @@ struct DevicePlan {
   int32_t n_blk = 0;           // block-table kernel: blocks of all problems
   int32_t meta_hh = 1, meta_mx = 1;   // per-block table widths (StepArgs)
   int32_t tab_xl = 0;          // block-table kernel: sub-tile rows of v_n staged in LDS
+  int32_t spin = 0;            // 1: spin-s plan (spin kernel for every step)
   int32_t lds_ll = 1;          // block-table kernel: low-low bond capacity per row (<= 255)
   int32_t blk_max = 16, blk_rows = kThreads, lds_lr = 1, lds_hh = 1, lds_mx = 1, ld_max = 1;
   int64_t n_states = 0;        // entries of the state table
@@ -395,6 +400,7 @@ hipError_t launch_states(int N, int k, const uint32_t* binom, uint32_t* out, int
 hipError_t fill_states(const DevicePlan& p, hipStream_t st);
 size_t row_lds_bytes(const DevicePlan& p);
 size_t block_lds_bytes(const DevicePlan& p);
+size_t spin_lds_bytes(const DevicePlan& p);
 size_t tab_lds_bytes(const DevicePlan& p);
 // Bytes of the per-block tables of the block-table kernel (kept in the state
 // table region; built by fill_states).

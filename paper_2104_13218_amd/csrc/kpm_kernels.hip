@@ -350,6 +350,281 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
   }
 }
 
+// ------------------------------------------------------------ spin kernel
+//
+// Spin-s sites (the spin-5/2 Fe10 wheel of the paper, Sec. III.B): a state is
+// the digit string d_i = s + m_i, its rank the count of sector states of
+// smaller value sum_i d_i (2s+1)^i, read off the table P[i][r][d] site by
+// site from the most significant one.  Per sub-tile one thread per row
+// unranks its state, sums the diagonal sum_b J_b m_i m_j / a - b/a, and lists
+// its neighbours S^+_i S^-_j and S^-_i S^+_j (rank and amplitude
+// J_b/(2a) sqrt(s(s+1) - m(m+1)) sqrt(s(s+1) - m'(m'-1))) in bond order; the
+// (row, column chunk) items then gather as in step_kernel.
+
+struct SpinSmem {
+  uint32_t* tab;
+  uint32_t* sites;   // per bond: i | j << 8
+  double* off;       // per bond: J_b / (2a)
+  double* zz;        // per bond: J_b / (4a)
+  double* up;        // [2s + 1]: sqrt(s(s+1) - m(m+1)), m = d - s
+  double* diag;
+  int32_t* cnt;
+  uint32_t* nbr;
+  double* nbc;
+  double* red;
+};
+
+__host__ __device__ inline size_t spin_lds_layout(int lds_tab, int lds_bonds, int sub_rows,
+                                                  int lds_nb, int cpl, size_t* offs) {
+  size_t o = 0;
+  auto put = [&](size_t b) {
+    const size_t r = o;
+    o = (o + b + 15) & ~size_t(15);
+    return r;
+  };
+  offs[0] = put(size_t(lds_tab) * 4);
+  offs[1] = put(size_t(lds_bonds) * 4);
+  offs[2] = put(size_t(lds_bonds) * 8);
+  offs[3] = put(size_t(lds_bonds) * 8);
+  offs[4] = put(16 * 8);
+  offs[5] = put(size_t(sub_rows) * 8);
+  offs[6] = put(size_t(sub_rows) * 4);
+  offs[7] = o;   // reduction buffer aliases the lists after the last sub-tile
+  offs[8] = put(size_t(lds_nb) * sub_rows * 4);
+  offs[9] = put(size_t(lds_nb) * sub_rows * 8);
+  const size_t red_end = offs[7] + size_t(2 * cpl) * kThreads * 8;
+  return o > red_end ? o : red_end;
+}
+
+size_t spin_lds_bytes(const DevicePlan& p) {
+  size_t offs[10];
+  return spin_lds_layout(p.lds_tab, p.lds_bonds, p.sub_rows, p.lds_nb, p.cpl, offs);
+}
+
+// Rank of the digit string dg (4 bits per site) with digit sum n.
+__device__ __forceinline__ uint32_t spin_rank(uint64_t dg, int N, int n, int R1, int B,
+                                              const uint32_t* tab) {
+  uint32_t rank = 0;
+  int r = n;
+  for (int i = N - 1; i >= 0; --i) {
+    const int d = (int)((dg >> (4 * i)) & 15u);
+    rank += tab[(i * R1 + r) * B + d];
+    r -= d;
+  }
+  return rank;
+}
+
+template <typename T, int CPL, int GB>
+__global__ __launch_bounds__(kThreads) void spin_kernel(const StepArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x;
+
+  if (a.n_jobs > 0) {
+    const int64_t s = (a.step_base ? *a.step_base : 0) + a.step_add;
+    double* sh = reinterpret_cast<double*>(smem);
+    for (int job = blockIdx.x; job < a.n_jobs; job += gridDim.x) {
+      const UnitDev U = a.units[a.job_unit[job]];
+      const int v = job - 2 * U.col_off;
+      const double sum = sum_partials(a.part_in + U.part_off + (int64_t)v * U.ntiles, U.ntiles, sh);
+      if (tid == 0) {
+        if (v < U.ld) a.alpha[s * a.total_cols + U.col_off + v] = sum;
+        else a.beta[(s - 1) * a.total_cols + U.col_off + (v - U.ld)] = sum;
+      }
+    }
+    __syncthreads();
+  }
+
+  const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.grid_tiles) : (int)blockIdx.x;
+  if (tile >= a.n_tiles) return;
+  const UnitDev U = a.units[a.tile_unit[tile]];
+  const ProbDev P = a.probs[U.prob];
+  size_t offs[10];
+  spin_lds_layout(a.lds_tab, a.lds_bonds, a.sub_rows, a.lds_nb, CPL, offs);
+  SpinSmem S;
+  S.tab = reinterpret_cast<uint32_t*>(smem + offs[0]);
+  S.sites = reinterpret_cast<uint32_t*>(smem + offs[1]);
+  S.off = reinterpret_cast<double*>(smem + offs[2]);
+  S.zz = reinterpret_cast<double*>(smem + offs[3]);
+  S.up = reinterpret_cast<double*>(smem + offs[4]);
+  S.diag = reinterpret_cast<double*>(smem + offs[5]);
+  S.cnt = reinterpret_cast<int32_t*>(smem + offs[6]);
+  S.red = reinterpret_cast<double*>(smem + offs[7]);
+  S.nbr = reinterpret_cast<uint32_t*>(smem + offs[8]);
+  S.nbc = reinterpret_cast<double*>(smem + offs[9]);
+  const int N = P.n_sites, two_s = P.two_s, B = two_s + 1, R1 = two_s * N + 1;
+  const double sv = 0.5 * two_s;
+  for (int i = tid; i < P.tab_len; i += kThreads) S.tab[i] = a.tables[P.tab_off + i];
+  for (int i = tid; i < P.n_bonds; i += kThreads) {
+    S.sites[i] = a.bmask[P.bond_off + i];
+    S.off[i] = a.boff[P.bond_off + i];
+    S.zz[i] = a.bzz[P.bond_off + i];
+  }
+  if (tid < B) {
+    const double m = tid - sv;
+    S.up[tid] = sqrt(fmax(sv * (sv + 1.0) - m * (m + 1.0), 0.0));
+  }
+  __syncthreads();
+
+  const int ld = U.ld;
+  const int nch = ld / CPL;
+  const int nrg = kThreads / nch;
+  const int c = tid % nch;
+  const int rg = tid / nch;
+  T* base = reinterpret_cast<T*>(a.vec) + U.vec_off;
+  const T* X = base + a.x_slot * a.slot_stride;
+  const T* Yin = base + a.yin_slot * a.slot_stride;
+  T* Y = base + a.yout_slot * a.slot_stride;
+  double acc_a[CPL], acc_b[CPL];
+#pragma unroll
+  for (int i = 0; i < CPL; ++i) acc_a[i] = acc_b[i] = 0.0;
+
+  const int64_t tile_row0 = a.tile_row0[tile];
+  const int tile_rows = a.tile_nrows[tile];
+  for (int st = 0; st * a.sub_rows < tile_rows; ++st) {
+    const int64_t row0 = tile_row0 + (int64_t)st * a.sub_rows;
+    const int nrows = min(a.sub_rows, tile_rows - st * a.sub_rows);
+    for (int rr = tid; rr < nrows; rr += kThreads) {
+      const uint32_t rank = (uint32_t)(row0 + rr);
+      // unrank: largest digit whose table entry does not exceed what is left
+      uint64_t dg = 0;
+      uint32_t rem = rank;
+      int r = P.n_up;
+      for (int i = N - 1; i >= 0; --i) {
+        int d = min(two_s, r);
+        while (d > 0 && S.tab[(i * R1 + r) * B + d] > rem) --d;
+        rem -= S.tab[(i * R1 + r) * B + d];
+        dg |= (uint64_t)d << (4 * i);
+        r -= d;
+      }
+      if (rem != 0u || r != 0) {
+        if (a.err) atomicOr(a.err, 4);
+      }
+      double diag = P.shift;
+      int cnt = 0;
+      for (int b = 0; b < P.n_bonds; ++b) {
+        const int i = (int)(S.sites[b] & 0xFFu), j = (int)(S.sites[b] >> 8);
+        const int di = (int)((dg >> (4 * i)) & 15u), dj = (int)((dg >> (4 * j)) & 15u);
+        diag = fma(4.0 * S.zz[b], (di - sv) * (dj - sv), diag);
+        // S^+_i S^-_j, then S^-_i S^+_j
+        for (int w = 0; w < 2; ++w) {
+          const int a1 = w == 0 ? i : j, a2 = w == 0 ? j : i;
+          const int d1 = w == 0 ? di : dj, d2 = w == 0 ? dj : di;
+          if (d1 >= two_s || d2 <= 0) continue;
+          const uint64_t t = dg + ((uint64_t)1 << (4 * a1)) - ((uint64_t)1 << (4 * a2));
+          uint32_t nr = spin_rank(t, N, P.n_up, R1, B, S.tab);
+          if (nr >= (uint32_t)P.dim || cnt >= a.lds_nb) {
+            if (a.err) atomicOr(a.err, 2);
+            continue;
+          }
+          S.nbr[cnt * a.sub_rows + rr] = nr;
+          S.nbc[cnt * a.sub_rows + rr] = S.off[b] * S.up[d1] * S.up[d2 - 1];
+          ++cnt;
+        }
+      }
+      S.diag[rr] = diag;
+      S.cnt[rr] = cnt;
+    }
+    __syncthreads();
+    if (rg < nrg) {
+      for (int rr = rg; rr < nrows; rr += nrg) {
+        const int64_t rho = row0 + rr;
+        const VecT<T, CPL> xv = vload<T, CPL>(X + rho * ld + c * CPL);
+        const double dgn = S.diag[rr];
+        double acc[CPL];
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) acc[i] = dgn * (double)xv.v[i];
+        const int cnt = S.cnt[rr];
+        for (int k0 = 0; k0 < cnt; k0 += GB) {
+          VecT<T, CPL> nv[GB];
+          double cf[GB];
+#pragma unroll
+          for (int j = 0; j < GB; ++j) {
+            const int k = k0 + j;
+            const bool on = k < cnt;
+            const uint32_t nb = on ? S.nbr[k * a.sub_rows + rr] : (uint32_t)rho;
+            cf[j] = on ? S.nbc[k * a.sub_rows + rr] : 0.0;
+            nv[j] = vload<T, CPL>(X + (int64_t)nb * ld + c * CPL);
+          }
+#pragma unroll
+          for (int j = 0; j < GB; ++j) {
+#pragma unroll
+            for (int i = 0; i < CPL; ++i) acc[i] = fma(cf[j], (double)nv[j].v[i], acc[i]);
+          }
+        }
+        VecT<T, CPL> ov;
+        if (a.first) {
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) ov.v[i] = (T)acc[i];
+        } else {
+          const VecT<T, CPL> yv = vload_nt<T, CPL>(Yin + rho * ld + c * CPL);
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) ov.v[i] = (T)(2.0 * acc[i] - (double)yv.v[i]);
+        }
+        vstore_nt<T, CPL>(Y + rho * ld + c * CPL, ov);
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) {
+          const double o = (double)ov.v[i];
+          acc_a[i] = fma(o, o, acc_a[i]);
+          acc_b[i] = fma(o, (double)xv.v[i], acc_b[i]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  double* red = S.red;
+  if (rg < nrg) {
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+      red[(2 * i) * kThreads + tid] = acc_a[i];
+      red[(2 * i + 1) * kThreads + tid] = acc_b[i];
+    }
+  }
+  int p2 = 1;
+  while (p2 < nrg) p2 <<= 1;
+  for (int sstride = p2 >> 1; sstride > 0; sstride >>= 1) {
+    __syncthreads();
+    if (rg < sstride && rg + sstride < nrg) {
+#pragma unroll
+      for (int v = 0; v < 2 * CPL; ++v) red[v * kThreads + tid] += red[v * kThreads + tid + sstride * nch];
+    }
+  }
+  __syncthreads();
+  if (tid < nch) {
+    const int tl = tile - U.tile0;
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+      const int col = c * CPL + i;
+      a.part_out[U.part_off + (int64_t)col * U.ntiles + tl] = red[(2 * i) * kThreads + tid];
+      a.part_out[U.part_off + (int64_t)(ld + col) * U.ntiles + tl] = red[(2 * i + 1) * kThreads + tid];
+    }
+  }
+}
+
+template <typename T, int CPL>
+static hipError_t launch_spin_t(const StepArgs& a, size_t lds, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((spin_kernel<T, CPL, 4>), dim3(grid), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+static hipError_t launch_spin(const DevicePlan& p, const StepArgs& a, hipStream_t st) {
+  const size_t lds = spin_lds_bytes(p);
+  const int grid = p.grid_tiles;
+  if (p.fp32) {
+    switch (p.cpl) {
+      case 1: return launch_spin_t<float, 1>(a, lds, grid, st);
+      case 2: return launch_spin_t<float, 2>(a, lds, grid, st);
+      case 4: return launch_spin_t<float, 4>(a, lds, grid, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (p.cpl) {
+    case 1: return launch_spin_t<double, 1>(a, lds, grid, st);
+    case 2: return launch_spin_t<double, 2>(a, lds, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // ------------------------------------------------------------- row kernel
 //
 // One lane per basis state carrying all LD columns of its block.  The state's
@@ -1629,6 +1904,7 @@ hipError_t launch_step_slots(const DevicePlan& p, void* vec, double* part_out, i
 }
 
 hipError_t launch_step_args(const DevicePlan& p, const StepArgs& a, hipStream_t st) {
+  if (p.spin) return launch_spin(p, a, st);
   if (p.block == 2) return launch_tab(p, a, st);
   if (p.block) return launch_block(p, a, st);
   if (p.row_ld > 0) return launch_row(p, a, st);

@@ -32,7 +32,7 @@ class KPMError(RuntimeError):
 class Problem(ctypes.Structure):
     _fields_ = [("n_sites", c_int32), ("n_up", c_int32), ("n_bonds", c_int32), ("cluster", c_int32),
                 ("bond_i", POINTER(c_int32)), ("bond_j", POINTER(c_int32)), ("J", POINTER(c_double)),
-                ("e_lo", c_double), ("e_hi", c_double)]
+                ("e_lo", c_double), ("e_hi", c_double), ("two_s", c_int32), ("reserved", c_int32)]
 
 
 class Params(ctypes.Structure):
@@ -147,7 +147,7 @@ class ProblemSet:
                 lo, hi = float(getattr(s, "e_lo", float("nan"))), float(getattr(s, "e_hi", float("nan")))
             self.arr[k] = Problem(c.n_sites, s.n_up, c.n_bonds, s.cluster_id,
                                   bi.ctypes.data_as(POINTER(c_int32)), bj.ctypes.data_as(POINTER(c_int32)),
-                                  J.ctypes.data_as(POINTER(c_double)), lo, hi)
+                                  J.ctypes.data_as(POINTER(c_double)), lo, hi, int(getattr(s, "two_s", 1)), 0)
 
     def __len__(self):
         return len(self.sectors)

@@ -163,3 +163,8 @@ def test_recursion_rows_match_dense_chebyshev(two_s, cl, n, kind):
             prev, cur = cur, 2 * Ht @ cur - prev
         got = spins.recursion_rows(cl, two_s, n, a, b, kind, 3, 2, np.arange(dim), m, cluster_id=2)
         np.testing.assert_allclose(got, cur, rtol=0, atol=1e-12 * max(1.0, np.abs(cur).max()))
+
+
+@pytest.mark.parametrize("N,two_s,n", [(5, 2, 4), (4, 5, 11), (6, 3, 9), (3, 7, 20)])
+def test_depth_first_enumeration_equals_brute_force(N, two_s, n):
+    np.testing.assert_array_equal(spins._walk_digits(N, two_s, n), spins.sector_digits(N, two_s, n))

@@ -65,6 +65,61 @@ class Sector:
         return 1 if 2 * self.n_up == self.cluster.n_sites else 2
 
 
+@dataclass
+class SpinSector:
+    """One (cluster, S^z) problem of spin-s sites (two_s = 2s): the site digits
+    d = s + m sum to n, S^z = n - N s.  `n_up` is that sum (the name of the
+    field in the C problem record)."""
+
+    cluster: Cluster
+    two_s: int
+    n: int
+    cluster_id: int = 0
+    e_lo: float = float("nan")
+    e_hi: float = float("nan")
+
+    @property
+    def n_up(self) -> int:
+        return self.n
+
+    @property
+    def dim(self) -> int:
+        """Number of digit strings (digits 0..2s) of length N with sum n."""
+        ways = [1]
+        for _ in range(self.cluster.n_sites):
+            nxt = [0] * (len(ways) + self.two_s)
+            for r, w in enumerate(ways):
+                for d in range(self.two_s + 1):
+                    nxt[r + d] += w
+            ways = nxt
+        return ways[self.n] if 0 <= self.n < len(ways) else 0
+
+    @property
+    def sz(self) -> float:
+        return self.n - 0.5 * self.two_s * self.cluster.n_sites
+
+    @property
+    def weight(self) -> int:
+        return 1 if 2 * self.n == self.two_s * self.cluster.n_sites else 2
+
+
+def spin_sectors(cluster: Cluster, two_s: int, cluster_id: int = 0, only_sz0: bool = False):
+    """The S^z >= 0 sectors of a spin-s cluster (S^z = 0 or 1/2 first)."""
+    N = cluster.n_sites
+    lo = (two_s * N + 1) // 2
+    hi = lo if only_sz0 else two_s * N
+    return [SpinSector(cluster, two_s, n, cluster_id) for n in range(lo, hi + 1)]
+
+
+def fe10(J: float = 1.0) -> Cluster:
+    """The ferric wheel Fe10 of Sec. III.B as a model: ten spin-5/2 sites on a
+    ring with one antiferromagnetic nearest-neighbour coupling J (in units of
+    the exchange; use with two_s = 5)."""
+    c = ring(10, J)
+    c.name = "fe10"
+    return c
+
+
 def ring(n: int, J: float = 1.0) -> Cluster:
     """Periodic nearest-neighbour chain (Sec. III.B)."""
     i = np.arange(n)
