@@ -51,7 +51,7 @@ if ROOT not in sys.path:
 METRIC = "Chebyshev steps·dim/s + HBM GB/s at N=24 S^z=0; speedup vs FP64 at C(T) err"
 HBM_PEAK_GBS = 8000.0
 # step kernel families as reported by kpm_last_run_stats()["kernel"]
-KERNEL_FAMILY = {0: "step_kernel", 1: "row_kernel", 2: "block_kernel", 3: "tab_kernel"}
+KERNEL_FAMILY = {0: "step_kernel", 1: "row_kernel", 2: "block_kernel", 3: "tab_kernel", 4: "spin_kernel"}
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -66,7 +66,7 @@ def _parse():
     ap.add_argument("--cpu-steps", type=int, default=30,
                     help="recursion steps of the CPU-oracle sample")
     ap.add_argument("--workload", default="ring24_sz0",
-                    choices=["ring24_sz0", "batched_rr3", "j1j2_grad", "rr4_30", "ftlm_ring24"])
+                    choices=["ring24_sz0", "batched_rr3", "j1j2_grad", "rr4_30", "ftlm_ring24", "fe10"])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (reference for HBM byte counters)")
     return ap.parse_args()
@@ -253,6 +253,27 @@ def other_workload(args, kpm, W, np, torch, dev):
             extra = {"fp64": {"value": st64["state_col_steps"] / dt64, "ms": dt64 * 1e3,
                               "roofline": _roofline(st64)},
                      "speedup_vs_fp64": (st["state_col_steps"] / dt) / (st64["state_col_steps"] / dt64)}
+        return _line(args, name, st["state_col_steps"] / dt, "state-column-steps/s", dt, cfg,
+                     _roofline(st), extra)
+    if name == "fe10":
+        wl = W.fe10_workload("fp32")
+        ab = kpm.spectral_bounds(wl.problems)              # fixed bounds: Lanczos outside the timing
+        ps = kpm.ProblemSet(wl.problems, [tuple(x) for x in ab])
+        T = torch.tensor(wl.temperatures, device="cuda")
+
+        def run(prec):
+            mu, abd = kpm.chebyshev_moments(None, wl.M, wl.R, wl.vec_kind, prec, wl.eps, wl.seed,
+                                            problems=ps)
+            kpm.thermo(mu, abd, ps, T, wl.kernel)
+            return kpm.last_run_stats()
+
+        dt, st = _timed(args, torch, lambda: run("fp32"))
+        dt64, st64 = _timed(args, torch, lambda: run("fp64"))
+        dims = [s.dim for s in wl.problems]
+        cfg = {"sites": 10, "spin": "5/2", "problems": len(dims), "states": int(sum(dims)),
+               "max_dim": int(max(dims)), "M": wl.M, "vectors": f"{wl.R} {wl.vec_kind}", "storage": "f32",
+               "col_block": st["col_block"], "bounds": "lanczos50+1% (outside the timing)", "device": dev}
+        extra = {"fp64": {"value": st64["state_col_steps"] / dt64, "ms": dt64 * 1e3, "roofline": _roofline(st64)}}
         return _line(args, name, st["state_col_steps"] / dt, "state-column-steps/s", dt, cfg,
                      _roofline(st), extra)
     if name == "j1j2_grad":

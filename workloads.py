@@ -278,3 +278,12 @@ def rr4_30_workload(precision: str = "fp32", M: int = 500) -> Workload:
     c = random_regular_cluster(30, 4, 0)
     return Workload("rr4_30_sz0", sectors(c, only_sz0=True), M=M, R=4,
                     vec_kind="rademacher", eps=0.025, precision=precision, seed=0)
+
+
+def fe10_workload(precision: str = "fp32", M: int = 200, R: int = 100) -> Workload:
+    """The ferric wheel Fe10 of Sec. III.B: ten spin-5/2 sites on a J = 1 ring,
+    all 26 S^z >= 0 sectors (32,430,816 states; S^z = 0: 4,395,456), R = 100
+    random vectors and N_deg = 200 as in the paper's best estimate, no kernel."""
+    return Workload("fe10_all", spin_sectors(fe10(), 5), M=M, R=R, vec_kind="rademacher",
+                    eps=0.025, precision=precision, seed=0, kernel="none",
+                    temperatures=log_temperatures(200, 0.05, 50.0))
