@@ -87,10 +87,10 @@ typedef struct {
                             S_i . S_j; the sector basis is the digit strings d_i = s + m_i
                             with the given sum in ascending value sum_i d_i (2s+1)^i.
                             Spin s > 1/2 is accepted by chebyshev_moments,
-                            chebyshev_vectors, kpm_spectral_bounds, kpm_ftlm and the
-                            thermodynamics entry points (kpm_thermo, kpm_thermo_field,
-                            kpm_thermo_hybrid); the gradient entry points,
-                            kpm_sector_eigenvalues and kpm_sector_matrix reject it with
+                            chebyshev_vectors, kpm_spectral_bounds, kpm_ftlm,
+                            kpm_sector_eigenvalues and the thermodynamics entry points
+                            (kpm_thermo, kpm_thermo_field, kpm_thermo_hybrid); the
+                            gradient entry points and kpm_sector_matrix reject it with
                             KPM_EINVAL.  A call holding any spin-s problem runs every
                             problem of the call with the spin-s step kernel */
   int32_t reserved;      /* must be 0 */
@@ -314,7 +314,9 @@ typedef struct {
                               kernels (they stream the 4-byte state words);
                               the block-table kernel reads per-block tables
                               instead: per block of low-bit states
-                              12 + 6 * (high-high bonds) + 4 * (mixed bonds) */
+                              12 + 6 * (high-high bonds) + 4 * (mixed bonds);
+                              the spin-s kernel reads 8 + 8 * n_bonds per row
+                              (digit string, neighbour-rank slots) */
   double state_col_steps;  /* sum over blocks of dim * real columns * steps */
   int32_t col_block;       /* real columns per block chosen */
   int32_t rows_per_tile;   /* basis states per workgroup tile (block kernels: mean) */

@@ -264,8 +264,10 @@ int pick_col_block(const kpm_problem* p, int n, const RunShape& s) {
   const int cpv = cols_per_vec(s.vec_kind);
   int64_t maxc = 1;
   for (int i = 0; i < n; ++i) maxc = std::max<int64_t>(maxc, total_columns(p[i], s));
-  int rb = s.col_block > 0 ? s.col_block
-                          : (s.tune.col_block > 0 ? s.tune.col_block : (s.precision == KPM_FP32_STORE ? 32 : 16));
+  // spin-s plans: the widest block (the per-row lists are read once per block
+  // and step; measured fastest for the Fe10 wheel)
+  const int dflt = any_spin(p, n) ? kMaxLd : (s.precision == KPM_FP32_STORE ? 32 : 16);
+  int rb = s.col_block > 0 ? s.col_block : (s.tune.col_block > 0 ? s.tune.col_block : dflt);
   rb = (int)std::min<int64_t>(rb, maxc);
   if (!s.split_vectors) rb = (rb + cpv - 1) / cpv * cpv;
   return std::min(rb, kMaxLd);
@@ -424,7 +426,8 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   D.row_ld = row_ld;
   if (row_ld && row_lds_bytes(D) > lds_hard) D.row_ld = row_ld = 0;
   if (row_ld) D.sub_rows = kThreads;
-  D.n_states = spin ? 0 : n_states;   // the spin kernel unranks every row itself
+  D.n_states = spin ? n_states * (2 + D.lds_nb) : n_states;   // spin: digits + neighbour ranks
+  D.spin_rows = spin ? n_states : 0;
 
   // Block kernel (tiles of whole low-bit blocks) when its LDS fits: bonds in
   // class order low-low, high-high, mixed.
@@ -631,6 +634,12 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
     D.n_states = (int64_t)((tab_meta_bytes(D) + 3) / 4);
   } else if (D.row_ld || D.block) {
     for (const auto& u : P.units) P.bytes_per_step += 4.0 * (double)P.probs[u.prob].dim;
+  } else if (D.spin) {
+    // the spin kernel reads each row's digit string and its neighbour-rank slots
+    for (const auto& u : P.units) {
+      const ProbDev& d = P.probs[u.prob];
+      P.bytes_per_step += (8.0 + 8.0 * d.n_bonds) * (double)d.dim;
+    }
   }
   P.tile_sub0.push_back((int32_t)P.sub_nrows.size());
   if (P.sub_nrows.empty()) P.sub_nrows.push_back(0);
@@ -855,7 +864,7 @@ int run_lanczos(const kpm_problem* p, int n, int steps, double margin, uint64_t 
   D.err = reinterpret_cast<int*>(work + L.err);
   D.states = reinterpret_cast<uint32_t*>(work + L.states);
   KPM_HIP(hipMemsetAsync(D.err, 0, sizeof(int), st));
-  if (D.row_ld || D.block) KPM_HIP(fill_states(D, st));
+  if (D.row_ld || D.block || D.spin) KPM_HIP(fill_states(D, st));
   double* vec = reinterpret_cast<double*>(work + L.vec);
   double* vecC = reinterpret_cast<double*>(work + L.vecC);
   double* part = reinterpret_cast<double*>(work + L.part);
@@ -1067,7 +1076,7 @@ double time_candidate(const kpm_problem* p, int n, const kpm_params& q, const Tu
   double* part[2] = {reinterpret_cast<double*>(work + L.part0),
                      reinterpret_cast<double*>(work + L.part1)};
   bool ok = hipMemsetAsync(D.err, 0, sizeof(int), st) == hipSuccess;
-  if (ok && (D.row_ld || D.block)) ok = fill_states(D, st) == hipSuccess;
+  if (ok && (D.row_ld || D.block || D.spin)) ok = fill_states(D, st) == hipSuccess;
   if (ok) ok = launch_init(D, vec, 1, KPM_VEC_RADEMACHER, q.seed, nullptr, part[0], st) == hipSuccess;
   const int warm = 3, meas = 6;
   for (int k = 0; ok && k < warm + meas; ++k) {
@@ -1156,7 +1165,7 @@ int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
   P.plan.err = flag;
   P.plan.states = reinterpret_cast<uint32_t*>(work + L.states);
   KPM_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
-  if (D.row_ld || D.block) KPM_HIP(fill_states(D, st));
+  if (D.row_ld || D.block || D.spin) KPM_HIP(fill_states(D, st));
 
   if (q.vec_kind == KPM_VEC_GAUSSIAN || q.vec_kind == KPM_VEC_COMPLEX_GAUSSIAN) {
     KPM_HIP(launch_init(D, vec, 0, q.vec_kind, q.seed, nullptr, part[0], st));
@@ -1260,7 +1269,7 @@ int run_vectors(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
   P.plan.err = flag;
   P.plan.states = reinterpret_cast<uint32_t*>(work + L.states);
   KPM_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
-  if (D.row_ld || D.block) KPM_HIP(fill_states(D, st));
+  if (D.row_ld || D.block || D.spin) KPM_HIP(fill_states(D, st));
   if (q.vec_kind == KPM_VEC_GAUSSIAN || q.vec_kind == KPM_VEC_COMPLEX_GAUSSIAN) {
     KPM_HIP(launch_init(D, vec, 0, q.vec_kind, q.seed, nullptr, part[0], st));
     KPM_HIP(launch_reduce(D, part[0], norms, nullptr, st));
@@ -1665,7 +1674,8 @@ struct EdPlan {
   std::vector<EigProb> probs;
   std::vector<uint32_t> bmask;
   std::vector<double> J;
-  size_t o_probs = 0, o_mask = 0, o_J = 0, o_binom = 0, o_err = 0, o_mat = 0, total = 0;
+  std::vector<uint32_t> tables;
+  size_t o_probs = 0, o_mask = 0, o_J = 0, o_binom = 0, o_tab = 0, o_err = 0, o_mat = 0, total = 0;
   int max_bonds = 1;
 };
 
@@ -1673,10 +1683,9 @@ int ed_plan(const kpm_problem* p, int n, int max_dim, EdPlan& E) {
   int r = check_problems(p, n);
   if (r != KPM_OK) return r;
   if (max_dim < 1 || max_dim > kEdMaxDim) return KPM_EINVAL;
-  if (any_spin(p, n)) return KPM_EINVAL;
   int64_t mat = 0;
   for (int i = 0; i < n; ++i) {
-    const uint64_t dim = binom64(p[i].n_sites, p[i].n_up);
+    const uint64_t dim = prob_dim(p[i]);
     if (dim > (uint64_t)max_dim) continue;
     EigProb e{};
     e.n_sites = p[i].n_sites;
@@ -1686,9 +1695,13 @@ int ed_plan(const kpm_problem* p, int n, int max_dim, EdPlan& E) {
     e.bond_off = (int32_t)E.bmask.size();
     e.out_row = i;
     e.mat_off = mat;
+    e.two_s = two_s_of(p[i]);
+    e.tab_off = (int32_t)E.tables.size();
+    if (e.two_s > 1) build_spin_table(p[i].n_sites, e.two_s, E.tables);
     mat += (int64_t)dim * (int64_t)dim;
     for (int k = 0; k < p[i].n_bonds; ++k) {
-      E.bmask.push_back((1u << p[i].bond_i[k]) | (1u << p[i].bond_j[k]));
+      if (e.two_s > 1) E.bmask.push_back((uint32_t)p[i].bond_i[k] | ((uint32_t)p[i].bond_j[k] << 8));
+      else E.bmask.push_back((1u << p[i].bond_i[k]) | (1u << p[i].bond_j[k]));
       E.J.push_back(p[i].J[k]);
     }
     E.max_bonds = std::max(E.max_bonds, p[i].n_bonds);
@@ -1704,6 +1717,7 @@ int ed_plan(const kpm_problem* p, int n, int max_dim, EdPlan& E) {
   E.o_mask = put(std::max<size_t>(E.bmask.size(), 1) * 4);
   E.o_J = put(std::max<size_t>(E.J.size(), 1) * 8);
   E.o_binom = put((size_t)kBinomN * kBinomN * 4);
+  E.o_tab = put(std::max<size_t>(E.tables.size(), 1) * 4);
   E.o_err = put(256);
   E.o_mat = put((size_t)std::max<int64_t>(mat, 1) * 8);
   E.total = o;
@@ -2112,7 +2126,7 @@ int kpm_ftlm(const kpm_problem* p, int32_t n, const kpm_params* q, const double*
   D.err = reinterpret_cast<int*>(work + L.err);
   D.states = reinterpret_cast<uint32_t*>(work + L.states);
   KPM_HIP(hipMemsetAsync(D.err, 0, sizeof(int), st));
-  if (D.row_ld || D.block) KPM_HIP(fill_states(D, st));
+  if (D.row_ld || D.block || D.spin) KPM_HIP(fill_states(D, st));
   double* vec = reinterpret_cast<double*>(work + L.vec);
   double* vecC = reinterpret_cast<double*>(work + L.vecC);
   double* part = reinterpret_cast<double*>(work + L.part);
@@ -2244,12 +2258,14 @@ int kpm_sector_eigenvalues(const kpm_problem* p, int32_t n, int32_t max_dim, dou
   std::memcpy(staging.data() + E.o_mask, E.bmask.data(), E.bmask.size() * 4);
   std::memcpy(staging.data() + E.o_J, E.J.data(), E.J.size() * 8);
   std::memcpy(staging.data() + E.o_binom, bt.data(), bt.size() * 4);
+  if (!E.tables.empty()) std::memcpy(staging.data() + E.o_tab, E.tables.data(), E.tables.size() * 4);
   KPM_HIP(hipMemcpyAsync(work, staging.data(), E.o_mat, hipMemcpyHostToDevice, st));
   EigArgs a{};
   a.probs = reinterpret_cast<const EigProb*>(work + E.o_probs);
   a.bmask = reinterpret_cast<const uint32_t*>(work + E.o_mask);
   a.J = reinterpret_cast<const double*>(work + E.o_J);
   a.binom = reinterpret_cast<const uint32_t*>(work + E.o_binom);
+  a.tables = reinterpret_cast<const uint32_t*>(work + E.o_tab);
   a.err = reinterpret_cast<int*>(work + E.o_err);
   a.mat = reinterpret_cast<double*>(work + E.o_mat);
   a.evals = d_evals;

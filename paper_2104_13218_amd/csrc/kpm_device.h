@@ -54,4 +54,20 @@ __device__ __forceinline__ RankTables make_tables(const uint32_t* tab, const Pro
   return R;
 }
 
+// Spin-s sites: rank of the digit string dg (4 bits per site, digit sum n)
+// in its sector, from the table P[i][r][d] (strings of sites 0..i with sum r
+// and digit < d at site i): the entries of each site's digit, from the most
+// significant site down, with r the sum still left.
+__device__ __forceinline__ uint32_t spin_rank(uint64_t dg, int N, int n, int R1, int B,
+                                              const uint32_t* tab) {
+  uint32_t rank = 0;
+  int r = n;
+  for (int i = N - 1; i >= 0; --i) {
+    const int d = (int)((dg >> (4 * i)) & 15u);
+    rank += tab[(i * R1 + r) * B + d];
+    r -= d;
+  }
+  return rank;
+}
+
 }  // namespace kpm

@@ -42,6 +42,47 @@ __device__ __forceinline__ uint32_t cns_rank(uint32_t s, const uint32_t* binom) 
   return r;
 }
 
+// Rows of H on a spin-s sector (digits d_i = s + m_i with sum n_up): diagonal
+// sum_b J_b m_i m_j, S^+_i S^-_j and S^-_i S^+_j with amplitude
+// J_b/2 sqrt(s(s+1) - m(m+1)) sqrt(s(s+1) - m'(m'-1)).  One row per thread.
+__device__ void spin_rows(const EigProb& P, const EigArgs& a, const uint32_t* s_sites, const double* s_J,
+                          double* A) {
+  const int N = P.n_sites, two_s = P.two_s, B = two_s + 1, R1 = two_s * N + 1, D = P.dim;
+  const double sv = 0.5 * two_s;
+  const uint32_t* tab = a.tables + P.tab_off;
+  for (int r = threadIdx.x; r < D; r += kThreads) {
+    uint64_t dg = 0;
+    uint32_t rem = (uint32_t)r;
+    int left = P.n_up;
+    for (int i = N - 1; i >= 0; --i) {
+      int d = min(two_s, left);
+      while (d > 0 && tab[(i * R1 + left) * B + d] > rem) --d;
+      rem -= tab[(i * R1 + left) * B + d];
+      dg |= (uint64_t)d << (4 * i);
+      left -= d;
+    }
+    double diag = 0.0;
+    for (int q = 0; q < P.n_bonds; ++q) {
+      const int i = (int)(s_sites[q] & 0xFFu), j = (int)(s_sites[q] >> 8);
+      const int di = (int)((dg >> (4 * i)) & 15u), dj = (int)((dg >> (4 * j)) & 15u);
+      diag += s_J[q] * (di - sv) * (dj - sv);
+      for (int w = 0; w < 2; ++w) {
+        const int a1 = w == 0 ? i : j, a2 = w == 0 ? j : i;
+        const int d1 = w == 0 ? di : dj, d2 = w == 0 ? dj : di;
+        if (d1 >= two_s || d2 <= 0) continue;
+        const double m1 = d1 - sv, m2 = d2 - sv;
+        const double amp = 0.5 * s_J[q] * sqrt(sv * (sv + 1.0) - m1 * (m1 + 1.0)) *
+                           sqrt(sv * (sv + 1.0) - m2 * (m2 - 1.0));
+        const uint32_t c =
+            spin_rank(dg + ((uint64_t)1 << (4 * a1)) - ((uint64_t)1 << (4 * a2)), N, P.n_up, R1, B, tab);
+        if (c < (uint32_t)D) A[(int64_t)r * D + c] += amp;
+        else if (a.err) atomicOr(a.err, 2);
+      }
+    }
+    A[(int64_t)r * D + r] += diag;
+  }
+}
+
 }  // namespace
 
 __global__ __launch_bounds__(kThreads) void sector_eig_kernel(const EigArgs a) {
@@ -67,6 +108,9 @@ __global__ __launch_bounds__(kThreads) void sector_eig_kernel(const EigArgs a) {
   for (int64_t i = tid; i < (int64_t)D * D; i += kThreads) A[i] = 0.0;
   __syncthreads();
 
+  if (P.two_s > 1) {
+    spin_rows(P, a, s_mask, s_J, A);
+  } else {
   // H on the sector basis: s_i s_j = 1/4 for equal spins, -1/4 otherwise;
   // unequal spins are exchanged with amplitude J/2.  Each row is one thread's.
   for (int r = tid; r < D; r += kThreads) {
@@ -85,6 +129,7 @@ __global__ __launch_bounds__(kThreads) void sector_eig_kernel(const EigArgs a) {
       }
     }
     A[(int64_t)r * D + r] += diag;
+  }
   }
   __syncthreads();
 

@@ -61,7 +61,9 @@ struct StepArgs {
   const double* boff;          // per bond: J_b / (2a)   (off-diagonal element of H')
   const double* bzz;           // per bond: J_b / (4a)   (diagonal contribution)
   const uint32_t* binom;       // C(n, j) [33][33]
-  const uint32_t* states;      // basis words of every sector, rank order (row kernel)
+  const uint32_t* states;      // basis words of every sector, rank order (row kernel);
+                               // spin kernel: digit strings (u64) then neighbour ranks
+  int64_t spin_rows;           // spin kernel: rows of all problems (u64 digit strings)
   void* vec;                   // vector storage base (float or double)
   int64_t slot_stride;         // elements between consecutive slots
   double* part_out;            // partial dots written by this step
@@ -152,6 +154,10 @@ struct DevicePlan {
   int32_t meta_hh = 1, meta_mx = 1;   // per-block table widths (StepArgs)
   int32_t tab_xl = 0;          // block-table kernel: sub-tile rows of v_n staged in LDS
   int32_t spin = 0;            // 1: spin-s plan (spin kernel for every step)
+  int64_t spin_rows = 0;       // spin plan: rows of all problems; the state table holds
+                               // the u64 digit string of every row, then per problem
+                               // [lds_nb][dim] u32 neighbour ranks (slot 2b + w: bond b,
+                               // w = 0 S^+_i S^-_j, w = 1 S^-_i S^+_j; written when acting)
   int32_t lds_ll = 1;          // block-table kernel: low-low bond capacity per row (<= 255)
   int32_t blk_max = 16, blk_rows = kThreads, lds_lr = 1, lds_hh = 1, lds_mx = 1, ld_max = 1;
   int64_t n_states = 0;        // entries of the state table
@@ -260,13 +266,15 @@ struct EigProb {
   int32_t n_sites, n_up, dim, n_bonds;
   int32_t bond_off, out_row;   // bonds in the packed arrays; row of the output
   int64_t mat_off;             // doubles from the matrix workspace base
+  int32_t two_s, tab_off;      // spin s > 1/2: 2s and its rank table (EigArgs::tables)
 };
 
 struct EigArgs {
   const EigProb* probs;        // one per workgroup
-  const uint32_t* bmask;       // per bond: (1 << i) | (1 << j)
+  const uint32_t* bmask;       // per bond: (1 << i) | (1 << j); spin s > 1/2: i | j << 8
   const double* J;             // per bond: J_b (unscaled H)
   const uint32_t* binom;       // C(n, j) [33][33]
+  const uint32_t* tables;      // spin-s rank tables P[i][r][d] (as ProbDev)
   double* mat;                 // dense sector matrices
   double* evals;               // [rows][ld] ascending eigenvalues
   int* err;                    // bit 1: rank out of range, bit 3: QL did not converge

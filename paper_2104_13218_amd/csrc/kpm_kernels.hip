@@ -355,14 +355,15 @@ __global__ __launch_bounds__(kThreads) void step_kernel(const StepArgs a) {
 // Spin-s sites (the spin-5/2 Fe10 wheel of the paper, Sec. III.B): a state is
 // the digit string d_i = s + m_i, its rank the count of sector states of
 // smaller value sum_i d_i (2s+1)^i, read off the table P[i][r][d] site by
-// site from the most significant one.  Per sub-tile one thread per row
-// unranks its state, sums the diagonal sum_b J_b m_i m_j / a - b/a, and lists
-// its neighbours S^+_i S^-_j and S^-_i S^+_j (rank and amplitude
-// J_b/(2a) sqrt(s(s+1) - m(m+1)) sqrt(s(s+1) - m'(m'-1))) in bond order; the
-// (row, column chunk) items then gather as in step_kernel.
+// site from the most significant one.  Once per call spin_lists_kernel
+// unranks every row and stores its digit string and the ranks of its
+// neighbours S^+_i S^-_j and S^-_i S^+_j (slot 2b + w) in the state table.
+// Per step and sub-tile one thread per row reads them, sums the diagonal
+// sum_b J_b m_i m_j / a - b/a and lists the acting neighbours with their
+// amplitudes J_b/(2a) sqrt(s(s+1) - m(m+1)) sqrt(s(s+1) - m'(m'-1)) in LDS;
+// the (row, column chunk) items then gather as in step_kernel.
 
 struct SpinSmem {
-  uint32_t* tab;
   uint32_t* sites;   // per bond: i | j << 8
   double* off;       // per bond: J_b / (2a)
   double* zz;        // per bond: J_b / (4a)
@@ -374,15 +375,15 @@ struct SpinSmem {
   double* red;
 };
 
-__host__ __device__ inline size_t spin_lds_layout(int lds_tab, int lds_bonds, int sub_rows,
-                                                  int lds_nb, int cpl, size_t* offs) {
+__host__ __device__ inline size_t spin_lds_layout(int lds_bonds, int sub_rows, int lds_nb, int cpl,
+                                                  size_t* offs) {
   size_t o = 0;
   auto put = [&](size_t b) {
     const size_t r = o;
     o = (o + b + 15) & ~size_t(15);
     return r;
   };
-  offs[0] = put(size_t(lds_tab) * 4);
+  offs[0] = 0;
   offs[1] = put(size_t(lds_bonds) * 4);
   offs[2] = put(size_t(lds_bonds) * 8);
   offs[3] = put(size_t(lds_bonds) * 8);
@@ -398,20 +399,7 @@ __host__ __device__ inline size_t spin_lds_layout(int lds_tab, int lds_bonds, in
 
 size_t spin_lds_bytes(const DevicePlan& p) {
   size_t offs[10];
-  return spin_lds_layout(p.lds_tab, p.lds_bonds, p.sub_rows, p.lds_nb, p.cpl, offs);
-}
-
-// Rank of the digit string dg (4 bits per site) with digit sum n.
-__device__ __forceinline__ uint32_t spin_rank(uint64_t dg, int N, int n, int R1, int B,
-                                              const uint32_t* tab) {
-  uint32_t rank = 0;
-  int r = n;
-  for (int i = N - 1; i >= 0; --i) {
-    const int d = (int)((dg >> (4 * i)) & 15u);
-    rank += tab[(i * R1 + r) * B + d];
-    r -= d;
-  }
-  return rank;
+  return spin_lds_layout(p.lds_bonds, p.sub_rows, p.lds_nb, p.cpl, offs);
 }
 
 template <typename T, int CPL, int GB>
@@ -439,9 +427,8 @@ __global__ __launch_bounds__(kThreads) void spin_kernel(const StepArgs a) {
   const UnitDev U = a.units[a.tile_unit[tile]];
   const ProbDev P = a.probs[U.prob];
   size_t offs[10];
-  spin_lds_layout(a.lds_tab, a.lds_bonds, a.sub_rows, a.lds_nb, CPL, offs);
+  spin_lds_layout(a.lds_bonds, a.sub_rows, a.lds_nb, CPL, offs);
   SpinSmem S;
-  S.tab = reinterpret_cast<uint32_t*>(smem + offs[0]);
   S.sites = reinterpret_cast<uint32_t*>(smem + offs[1]);
   S.off = reinterpret_cast<double*>(smem + offs[2]);
   S.zz = reinterpret_cast<double*>(smem + offs[3]);
@@ -451,9 +438,10 @@ __global__ __launch_bounds__(kThreads) void spin_kernel(const StepArgs a) {
   S.red = reinterpret_cast<double*>(smem + offs[7]);
   S.nbr = reinterpret_cast<uint32_t*>(smem + offs[8]);
   S.nbc = reinterpret_cast<double*>(smem + offs[9]);
-  const int N = P.n_sites, two_s = P.two_s, B = two_s + 1, R1 = two_s * N + 1;
+  const int two_s = P.two_s, B = two_s + 1;
   const double sv = 0.5 * two_s;
-  for (int i = tid; i < P.tab_len; i += kThreads) S.tab[i] = a.tables[P.tab_off + i];
+  const uint64_t* sdig = reinterpret_cast<const uint64_t*>(a.states) + P.state_off;
+  const uint32_t* snbr = a.states + 2 * a.spin_rows + P.state_off * a.lds_nb;
   for (int i = tid; i < P.n_bonds; i += kThreads) {
     S.sites[i] = a.bmask[P.bond_off + i];
     S.off[i] = a.boff[P.bond_off + i];
@@ -484,21 +472,8 @@ __global__ __launch_bounds__(kThreads) void spin_kernel(const StepArgs a) {
     const int64_t row0 = tile_row0 + (int64_t)st * a.sub_rows;
     const int nrows = min(a.sub_rows, tile_rows - st * a.sub_rows);
     for (int rr = tid; rr < nrows; rr += kThreads) {
-      const uint32_t rank = (uint32_t)(row0 + rr);
-      // unrank: largest digit whose table entry does not exceed what is left
-      uint64_t dg = 0;
-      uint32_t rem = rank;
-      int r = P.n_up;
-      for (int i = N - 1; i >= 0; --i) {
-        int d = min(two_s, r);
-        while (d > 0 && S.tab[(i * R1 + r) * B + d] > rem) --d;
-        rem -= S.tab[(i * R1 + r) * B + d];
-        dg |= (uint64_t)d << (4 * i);
-        r -= d;
-      }
-      if (rem != 0u || r != 0) {
-        if (a.err) atomicOr(a.err, 4);
-      }
+      const int64_t rho = row0 + rr;
+      const uint64_t dg = sdig[rho];
       double diag = P.shift;
       int cnt = 0;
       for (int b = 0; b < P.n_bonds; ++b) {
@@ -507,11 +482,9 @@ __global__ __launch_bounds__(kThreads) void spin_kernel(const StepArgs a) {
         diag = fma(4.0 * S.zz[b], (di - sv) * (dj - sv), diag);
         // S^+_i S^-_j, then S^-_i S^+_j
         for (int w = 0; w < 2; ++w) {
-          const int a1 = w == 0 ? i : j, a2 = w == 0 ? j : i;
           const int d1 = w == 0 ? di : dj, d2 = w == 0 ? dj : di;
           if (d1 >= two_s || d2 <= 0) continue;
-          const uint64_t t = dg + ((uint64_t)1 << (4 * a1)) - ((uint64_t)1 << (4 * a2));
-          uint32_t nr = spin_rank(t, N, P.n_up, R1, B, S.tab);
+          const uint32_t nr = snbr[(int64_t)(2 * b + w) * P.dim + rho];
           if (nr >= (uint32_t)P.dim || cnt >= a.lds_nb) {
             if (a.err) atomicOr(a.err, 2);
             continue;
@@ -599,6 +572,59 @@ __global__ __launch_bounds__(kThreads) void spin_kernel(const StepArgs a) {
       a.part_out[U.part_off + (int64_t)(ld + col) * U.ntiles + tl] = red[(2 * i + 1) * kThreads + tid];
     }
   }
+}
+
+// Digit strings and neighbour ranks of every row of every spin-s problem
+// (grid: x strides over rows, y = problem); the rank table in LDS.
+__global__ __launch_bounds__(kThreads) void spin_lists_kernel(const ProbDev* probs,
+                                                              const uint32_t* tables,
+                                                              const uint32_t* bmask, uint32_t* states,
+                                                              int64_t spin_rows, int nb, int* err) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t* tab = reinterpret_cast<uint32_t*>(smem);
+  const ProbDev P = probs[blockIdx.y];
+  for (int i = threadIdx.x; i < P.tab_len; i += kThreads) tab[i] = tables[P.tab_off + i];
+  __syncthreads();
+  const int N = P.n_sites, two_s = P.two_s, B = two_s + 1, R1 = two_s * N + 1;
+  uint64_t* dig = reinterpret_cast<uint64_t*>(states) + P.state_off;
+  uint32_t* nbr = states + 2 * spin_rows + P.state_off * nb;
+  for (int64_t rho = (int64_t)blockIdx.x * kThreads + threadIdx.x; rho < P.dim;
+       rho += (int64_t)gridDim.x * kThreads) {
+    // unrank: at each site, the largest digit whose table entry does not
+    // exceed what is left of the rank
+    uint64_t dg = 0;
+    uint32_t rem = (uint32_t)rho;
+    int r = P.n_up;
+    for (int i = N - 1; i >= 0; --i) {
+      int d = min(two_s, r);
+      while (d > 0 && tab[(i * R1 + r) * B + d] > rem) --d;
+      rem -= tab[(i * R1 + r) * B + d];
+      dg |= (uint64_t)d << (4 * i);
+      r -= d;
+    }
+    if ((rem != 0u || r != 0) && err) atomicOr(err, 4);
+    dig[rho] = dg;
+    for (int b = 0; b < P.n_bonds; ++b) {
+      const uint32_t sij = bmask[P.bond_off + b];
+      const int i = (int)(sij & 0xFFu), j = (int)(sij >> 8);
+      const int di = (int)((dg >> (4 * i)) & 15u), dj = (int)((dg >> (4 * j)) & 15u);
+      for (int w = 0; w < 2; ++w) {
+        const int a1 = w == 0 ? i : j, a2 = w == 0 ? j : i;
+        const int d1 = w == 0 ? di : dj, d2 = w == 0 ? dj : di;
+        uint32_t nr = (uint32_t)rho;
+        if (d1 < two_s && d2 > 0)
+          nr = spin_rank(dg + ((uint64_t)1 << (4 * a1)) - ((uint64_t)1 << (4 * a2)), N, P.n_up, R1, B, tab);
+        nbr[(int64_t)(2 * b + w) * P.dim + rho] = nr;
+      }
+    }
+  }
+}
+
+static hipError_t build_spin_lists(const DevicePlan& p, hipStream_t st) {
+  const size_t lds = (size_t)p.lds_tab * 4;
+  hipLaunchKernelGGL(spin_lists_kernel, dim3(1024, p.n_probs), dim3(kThreads), lds, st, p.probs, p.tables,
+                     p.bmask, p.states, p.spin_rows, p.lds_nb, p.err);
+  return hipGetLastError();
 }
 
 template <typename T, int CPL>
@@ -1832,6 +1858,7 @@ static StepArgs make_step_args(const DevicePlan& p) {
   a.slot_stride = p.slot_stride;
   a.dense = p.dense;
   a.states = p.states;
+  a.spin_rows = p.spin_rows;
   a.bperm = p.bperm;
   a.blk_max = p.blk_max;
   a.blk_rows = p.blk_rows;
@@ -2308,6 +2335,7 @@ __global__ __launch_bounds__(kThreads) void fill_states_kernel(const ProbDev* pr
 
 hipError_t fill_states(const DevicePlan& p, hipStream_t st) {
   if (!p.states || p.n_probs == 0) return hipSuccess;
+  if (p.spin) return build_spin_lists(p, st);
   if (p.block >= 2) return build_tab_meta(p, st);
   hipLaunchKernelGGL(fill_states_kernel, dim3(2048, p.n_probs), dim3(kThreads), 0, st, p.probs,
                      p.n_probs, p.binom, p.states);

@@ -12,7 +12,9 @@ Sec. III.B and other spin s > 1/2 clusters) through the spin-s step kernel.
 * the full Fe10 wheel (N = 10, s = 5/2, S^z = 0: 4,395,456 states; all 26
   S^z >= 0 sectors: 32,430,816 states): sampled rows of v_1..v_3 against the
   oracle's cone recursion, mu_0 = dim and |mu_n| <= mu_0 everywhere;
-* the entry points without spin-s support refuse it."""
+* exact spectra of small spin-s sectors (the five smallest Fe10 sectors
+  among them) and the hybrid sums that mix them with moments;
+* the gradient entry points refuse spin s."""
 import numpy as np
 import pytest
 import torch
@@ -191,6 +193,52 @@ def test_fe10_all_sectors_properties(kpm):
 def test_unsupported_entry_points_refuse_spin_s(kpm):
     secs = W.spin_sectors(W.ring(4), 2)
     with pytest.raises(kpm.KPMError):
-        kpm.sector_eigenvalues(secs, 64)
-    with pytest.raises(kpm.KPMError):
         kpm.thermo_grad(secs, 16, 2, W.log_temperatures(4, 0.5, 2.0), np.ones(4), np.zeros(4))
+
+
+@pytest.mark.parametrize("name", ["s1_ring6", "s5/2_ring4", "s1_random7", "s7/2_triangle"])
+def test_exact_spectra_of_spin_sectors(kpm, name):
+    two_s, cl = CLUSTERS[name]
+    secs = W.spin_sectors(cl, two_s)
+    ev = kpm.sector_eigenvalues(secs, 512).cpu().numpy()
+    for p, s in enumerate(secs):
+        if s.dim > 512:
+            assert np.all(np.isnan(ev[p])), p
+            continue
+        e = np.linalg.eigvalsh(_H(s).toarray())
+        assert np.abs(ev[p, :s.dim] - e).max() <= 1e-10 * max(1.0, np.abs(e).max()), p
+        assert np.all(np.isnan(ev[p, s.dim:])), p
+
+
+def test_fe10_small_sectors_exact(kpm):
+    """The Fe10 sectors of dimension <= 1024 (S^z = 25..21: 1, 10, 55, 220, 715
+    states) against the oracle's dense diagonalisation; the others NaN."""
+    secs = W.spin_sectors(W.fe10(), 5)
+    ev = kpm.sector_eigenvalues(secs, 1024).cpu().numpy()
+    small = [p for p, s in enumerate(secs) if s.dim <= 1024]
+    assert [secs[p].dim for p in small] == [715, 220, 55, 10, 1]
+    for p in small:
+        e = np.linalg.eigvalsh(_H(secs[p]).toarray())
+        assert np.abs(ev[p, :secs[p].dim] - e).max() <= 1e-10 * max(1.0, np.abs(e).max()), p
+    assert ev[-1, 0] == pytest.approx(62.5, abs=1e-10)     # the ferromagnetic state: N s^2 J
+    assert all(np.all(np.isnan(ev[p])) for p in range(len(secs)) if p not in small)
+
+
+def test_hybrid_thermodynamics_spin_sectors(kpm):
+    """Spin-3/2 ring N=6: sectors with D <= 100 exact on the GPU, the others
+    by GPU moments; against the oracle's hybrid sums on the same seeds."""
+    secs = W.spin_sectors(W.ring(6), 3)
+    M, R = 96, 5
+    got, want, ab, _, _ = _moments(kpm, secs, M, R, "rademacher", "fp64", seed=6)
+    exact = np.array([s.dim <= 100 for s in secs], dtype=np.uint8)
+    assert 0 < exact.sum() < len(secs)
+    ev = kpm.sector_eigenvalues(secs, 128)
+    T = W.log_temperatures(30, 0.1, 20.0)
+    h = np.linspace(0.0, 2.0, T.size)
+    out = kpm.thermo_hybrid(torch.tensor(got, device="cuda"), torch.tensor(ab, device="cuda"), secs, ev, exact,
+                            T, h)
+    spectra = [np.linalg.eigvalsh(_H(s).toarray()) if exact[p] else None for p, s in enumerate(secs)]
+    ref = thermo.thermo_hybrid(_probs(secs), want, ab, spectra, T, h, "jackson")
+    for q in ("lnZ", "E", "C", "chi", "M"):
+        g, w = out[q].cpu().numpy(), ref[q]
+        assert np.abs(g - w).max() <= 1e-9 * max(1.0, np.abs(w).max()), (q, np.abs(g - w).max())
