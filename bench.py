@@ -82,12 +82,24 @@ def _traffic(family):
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    from paper_2104_13218_amd import build as _b
-    import hashlib
-    src = open(os.path.join(_b.CSRC, "kpm_kernels.hip"), "rb").read()
-    if d.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+    if d.get("kernel_text_sha256") != kernel_text_sha256(family):
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def kernel_text_sha256(family):
+    """sha256 of the kernel function's source text (its template line to the
+    closing brace in column 0) in kpm_kernels.hip: a counter record stays
+    valid while that text is unchanged."""
+    import hashlib
+    import re
+    from paper_2104_13218_amd import build as _b
+    src = open(os.path.join(_b.CSRC, "kpm_kernels.hip")).read()
+    m = re.search(r"template <[^\n]*>\n__global__[^\n]*void %s\(" % re.escape(family), src)
+    if m is None:
+        return None
+    end = src.index("\n}\n", m.start())
+    return hashlib.sha256(src[m.start():end + 3].encode()).hexdigest()
 
 
 def _copy_rate(torch):
