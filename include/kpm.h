@@ -325,6 +325,11 @@ typedef struct {
                               3 block-table, 4 spin-s */
   double recursion_ms;     /* hipEvent time on the call's stream from the first
                               to the last recursion-step launch, inclusive */
+  int32_t relabelled;      /* problems whose sites the block kernels relabel (fewer
+                              bonds between the low and the high bits; results are
+                              unchanged: start vectors and exported rows keep the
+                              original basis order) */
+  int32_t reserved;
 } kpm_run_stats;
 int kpm_last_run_stats(kpm_run_stats* out);
 

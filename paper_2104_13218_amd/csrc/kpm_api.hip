@@ -273,6 +273,101 @@ int pick_col_block(const kpm_problem* p, int n, const RunShape& s) {
   return std::min(rb, kMaxLd);
 }
 
+// Site relabelling for the block kernels: a set S of L sites to become the low
+// bits, chosen to cut few bonds (a bond with one end in S is a "mixed" bond,
+// gathered row by row through the rank tables; bonds inside S stay in the
+// block, bonds outside it move whole blocks).  Local search (best single swap
+// between S and its complement until none lowers the cut) from the first L
+// sites of a breadth-first walk from every site; the identity is kept unless
+// a set with a strictly smaller cut is found.  perm[i] is the new label of
+// site i: S in ascending order gets 0..L-1, the other sites follow in
+// breadth-first order from S (sites bonded to S get the lowest high bits).
+bool choose_relabel(const kpm_problem& p, int L, std::vector<uint8_t>& perm) {
+  const int N = p.n_sites;
+  if (L <= 0 || L >= N || env_int("KPM_RELABEL", 1) == 0) return false;
+  std::vector<std::vector<int>> adj(N);
+  for (int k = 0; k < p.n_bonds; ++k) {
+    adj[p.bond_i[k]].push_back(p.bond_j[k]);
+    adj[p.bond_j[k]].push_back(p.bond_i[k]);
+  }
+  for (auto& a : adj) std::sort(a.begin(), a.end());
+  auto cut_of = [&](const std::vector<char>& in) {
+    int c = 0;
+    for (int k = 0; k < p.n_bonds; ++k) c += in[p.bond_i[k]] != in[p.bond_j[k]];
+    return c;
+  };
+  std::vector<char> best(N, 0);
+  for (int i = 0; i < L; ++i) best[i] = 1;
+  const int cut0 = cut_of(best);
+  int best_cut = cut0;
+  for (int seed = 0; seed < N; ++seed) {
+    std::vector<char> in(N, 0);
+    std::vector<int> order{seed};
+    std::vector<char> seen(N, 0);
+    seen[seed] = 1;
+    for (size_t h = 0; h < order.size() && (int)order.size() < N; ++h)
+      for (int v : adj[order[h]])
+        if (!seen[v]) {
+          seen[v] = 1;
+          order.push_back(v);
+        }
+    for (int v = 0; v < N && (int)order.size() < N; ++v)
+      if (!seen[v]) order.push_back(v);
+    for (int t = 0; t < L; ++t) in[order[t]] = 1;
+    int cut = cut_of(in);
+    for (;;) {
+      // gain of moving v across: bonds to the other side minus bonds to its own
+      std::vector<int> g(N, 0);
+      for (int v = 0; v < N; ++v)
+        for (int u : adj[v]) g[v] += in[u] != in[v] ? 1 : -1;
+      int bg = 0, ba = -1, bb = -1;
+      for (int a = 0; a < N; ++a) {
+        if (!in[a]) continue;
+        for (int b = 0; b < N; ++b) {
+          if (in[b]) continue;
+          int shared = 0;
+          for (int u : adj[a]) shared += u == b;
+          const int gain = g[a] + g[b] - 2 * shared;
+          if (gain > bg) {
+            bg = gain;
+            ba = a;
+            bb = b;
+          }
+        }
+      }
+      if (ba < 0) break;
+      in[ba] = 0;
+      in[bb] = 1;
+      cut -= bg;
+    }
+    if (cut < best_cut) {
+      best_cut = cut;
+      best = in;
+    }
+  }
+  if (best_cut >= cut0) return false;
+  perm.assign(32, 0);
+  int next = 0;
+  std::vector<char> placed(N, 0);
+  std::vector<int> queue;
+  for (int v = 0; v < N; ++v)
+    if (best[v]) {
+      perm[v] = (uint8_t)next++;
+      placed[v] = 1;
+      queue.push_back(v);
+    }
+  for (size_t h = 0; h < queue.size(); ++h)
+    for (int u : adj[queue[h]])
+      if (!placed[u]) {
+        placed[u] = 1;
+        perm[u] = (uint8_t)next++;
+        queue.push_back(u);
+      }
+  for (int v = 0; v < N; ++v)
+    if (!placed[v]) perm[v] = (uint8_t)next++;
+  return true;
+}
+
 // Tiles of whole blocks for the block kernel: the blocks of sector (N, k)
 // with L low bits, in rank order (ascending high bits h), packed greedily into
 // tiles of at most `rows` states and `blk_max` blocks.
@@ -438,6 +533,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   std::vector<std::vector<int64_t>> btile_row0(n);
   std::vector<std::vector<int32_t>> btile_nrows(n);
   std::vector<BlockList> blists(n);
+  std::vector<std::vector<uint8_t>> relabels(n);
   // Default: the block-table kernel for blocks too wide for the row kernel
   // (the measured case where it is the fastest kernel); KPM_BLOCK=0/1/2 and
   // the autotuner override.
@@ -464,9 +560,21 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
         ProbDev& d = P.probs[i];
         const int L = std::min(p[i].n_sites, Lm);
         const uint32_t low = (L >= 32) ? 0xFFFFFFFFu : ((1u << L) - 1u);
+        std::vector<uint8_t>& pm = relabels[i];
+        pm.clear();
+        // the sectors of one cluster share its bond arrays: one search per cluster
+        const size_t nbb = (size_t)p[i].n_bonds * sizeof(int32_t);
+        const int j = i > 0 && p[i - 1].n_bonds == p[i].n_bonds && p[i - 1].n_sites == p[i].n_sites &&
+                              (nbb == 0 || (std::memcmp(p[i - 1].bond_i, p[i].bond_i, nbb) == 0 &&
+                                            std::memcmp(p[i - 1].bond_j, p[i].bond_j, nbb) == 0))
+                          ? i - 1
+                          : -1;
+        if (j >= 0) pm = relabels[j];
+        else choose_relabel(p[i], L, pm);
+        auto lab = [&](int site) { return pm.empty() ? site : (int)pm[site]; };
         std::vector<uint16_t> cls[3];
         for (int k = 0; k < p[i].n_bonds; ++k) {
-          const uint32_t m = (1u << p[i].bond_i[k]) | (1u << p[i].bond_j[k]);
+          const uint32_t m = (1u << lab(p[i].bond_i[k])) | (1u << lab(p[i].bond_j[k]));
           const int c = (m & ~low) == 0 ? 0 : ((m & low) == 0 ? 1 : 2);
           cls[c].push_back((uint16_t)k);
         }
@@ -494,6 +602,15 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   }
   int bspt = 1;
   if (D.block) D.row_ld = row_ld = 0;
+  // relabelled sites: the kernels see the bonds (and so every word) in the new labels
+  for (int i = 0; D.block && i < n; ++i) {
+    if (relabels[i].empty()) continue;
+    ProbDev& d = P.probs[i];
+    d.relabel = 1;
+    for (int t = 0; t < 32; ++t) d.perm[t] = relabels[i][t];
+    for (int k = 0; k < p[i].n_bonds; ++k)
+      P.bmask[d.bond_off + k] = (1u << relabels[i][p[i].bond_i[k]]) | (1u << relabels[i][p[i].bond_j[k]]);
+  }
   // Neighbour rows in flight per lane: row kernel 2/4/8, others 4/8.
   D.gather_batch = (row_ld == 4 || row_ld == 8) ? 2 : 4;
   if (s.tune.gather_batch > 0) D.gather_batch = s.tune.gather_batch;
@@ -1250,6 +1367,8 @@ int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
   }
   g_stats.kernel = D.spin ? 4 : (D.block == 2 ? 3 : (D.block ? 2 : (D.row_ld ? 1 : 0)));
   g_stats.graph_segment = used_segment;
+  g_stats.relabelled = 0;
+  for (const auto& d : P.probs) g_stats.relabelled += d.relabel;
   float ms = 0.f;
   g_stats.recursion_ms = hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess ? (double)ms : -1.0;
   if (h_flag & 2) return KPM_EDEVICE;
@@ -1289,6 +1408,8 @@ int run_vectors(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
   for (auto& u : P.units) ea.n_cols += u.ncols;
   ea.dim = P.probs[0].dim;
   ea.out = d_out;
+  ea.prob = D.probs;
+  ea.binom = D.binom;
   KPM_HIP(launch_export(ea, D.fp32, st));
   int h_flag = 0;
   KPM_HIP(hipMemcpyAsync(&h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -54,6 +54,28 @@ __device__ __forceinline__ RankTables make_tables(const uint32_t* tab, const Pro
   return R;
 }
 
+// Colex (= ascending-integer) rank of word s among the words of its popcount.
+__device__ __forceinline__ uint32_t word_rank(uint32_t s, const uint32_t* binom) {
+  uint32_t r = 0;
+  int j = 0;
+  for (uint32_t x = s; x; x &= x - 1u) {
+    ++j;
+    r += binom[(__ffs(x) - 1) * kBinomN + j];
+  }
+  return r;
+}
+
+// Relabelled sites: the word with bit i moved to bit perm[i] (to_kernel) or
+// back (from the kernels' labels to the problem's).
+__device__ __forceinline__ uint32_t relabel_word(uint32_t w, const uint8_t* perm, int N, bool to_kernel) {
+  uint32_t o = 0;
+  for (int i = 0; i < N; ++i) {
+    if (to_kernel) o |= ((w >> i) & 1u) << perm[i];
+    else o |= ((w >> perm[i]) & 1u) << i;
+  }
+  return o;
+}
+
 // Spin-s sites: rank of the digit string dg (4 bits per site, digit sum n)
 // in its sector, from the table P[i][r][d] (strings of sites 0..i with sum r
 // and digit < d at site i): the entries of each site's digit, from the most

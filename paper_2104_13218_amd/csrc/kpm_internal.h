@@ -34,7 +34,14 @@ struct ProbDev {
   // Spin-s sites (spin kernel): 2s; the rank table at tab_off is
   // P[i][r][d] = number of digit strings of sites 0..i with sum r and digit
   // < d at site i, [n_sites][2s n_sites + 1][2s + 1]; bond masks hold i | j << 8.
-  int32_t two_s, pad_s;
+  int32_t two_s;
+  // Block kernels: the sites are relabelled (site i of the problem is bit
+  // perm[i] of the words the kernels see) so that few bonds join the low
+  // bits to the high bits.  Rows are then in the rank order of the
+  // relabelled words; the start vectors and exported rows use the rank of
+  // the original word.
+  int32_t relabel;
+  uint8_t perm[32];
 };
 
 // One recursion block: a problem and a contiguous range of its real columns.
@@ -186,6 +193,7 @@ struct InitArgs {
   const double* norms;   // per column: Gaussian sums of squares (modes 1, 2)
   double* part_out;
   uint64_t seed;
+  const uint32_t* binom;     // C(n, j) [33][33] (rank of the original word of a relabelled row)
   int32_t n_tiles, grid_tiles, mode, vec_kind;   // mode 0 sums of squares, 1 write, 2 unit-norm
 };
 
@@ -400,6 +408,8 @@ struct ExportArgs {
   int32_t slot, unit0, rb, n_cols;
   int64_t dim;
   void* out;             // [dim][n_cols], storage type
+  const ProbDev* prob;   // the problem (rows of relabelled sites are mapped back)
+  const uint32_t* binom; // C(n, j) [33][33]
 };
 hipError_t launch_export(const ExportArgs& a, int fp32, hipStream_t st);
 hipError_t launch_states(int N, int k, const uint32_t* binom, uint32_t* out, int64_t dim,

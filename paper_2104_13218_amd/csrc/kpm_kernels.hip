@@ -2036,7 +2036,13 @@ __global__ __launch_bounds__(kThreads) void init_kernel(const InitArgs a) {
   if (rg < nrg) {
     for (int64_t rho = row0 + rg; rho < row1; rho += nrg) {
       double x = 0.0;
-      if (c < U.ncols) x = start_value(a.vec_kind, a.seed, P, U.col0 + c, rho);
+      // a relabelled row draws the value of its word's original rank
+      const int64_t idx = P.relabel ? (int64_t)word_rank(relabel_word(unrank((uint32_t)rho, P.n_sites, P.n_up,
+                                                                                a.binom),
+                                                                         P.perm, P.n_sites, false),
+                                                             a.binom)
+                                    : rho;
+      if (c < U.ncols) x = start_value(a.vec_kind, a.seed, P, U.col0 + c, idx);
       if (a.mode == 0) {
         acc = fma(x, x, acc);
       } else {
@@ -2077,6 +2083,7 @@ hipError_t launch_init(const DevicePlan& p, void* vec, int mode, int vec_kind, u
   a.vec_kind = vec_kind;
   a.tile_row0 = p.tile_row0;
   a.tile_nrows = p.tile_nrows;
+  a.binom = p.binom;
   if (p.fp32) hipLaunchKernelGGL(init_kernel<float>, dim3(p.grid_tiles), dim3(kThreads), 0, st, a);
   else hipLaunchKernelGGL(init_kernel<double>, dim3(p.grid_tiles), dim3(kThreads), 0, st, a);
   return hipGetLastError();
@@ -2141,7 +2148,13 @@ __global__ __launch_bounds__(kThreads) void export_kernel(const ExportArgs a) {
     const int64_t row = e / a.n_cols;
     const int col = (int)(e - row * a.n_cols);
     const UnitDev U = a.units[a.unit0 + col / a.rb];
-    out[e] = base[U.vec_off + row * U.ld + (col % a.rb)];
+    int64_t src = row;
+    if (a.prob && a.prob->relabel) {
+      const ProbDev& P = *a.prob;
+      src = word_rank(relabel_word(unrank((uint32_t)row, P.n_sites, P.n_up, a.binom), P.perm, P.n_sites, true),
+                      a.binom);
+    }
+    out[e] = base[U.vec_off + src * U.ld + (col % a.rb)];
   }
 }
 

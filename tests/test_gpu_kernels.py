@@ -122,3 +122,68 @@ def test_kernels_agree_ring20(kpm, monkeypatch):
     ref = out["chunk"]
     for name, mu in out.items():
         assert np.abs(mu - ref).max() <= 1e-11 * ref[0], name
+
+
+# ------------------------------------------------- relabelled sites (block kernels)
+
+def _rr(n, seed):
+    return W.random_regular_cluster(n, 3, seed, J_range=(0.5, 1.5))
+
+
+@pytest.mark.parametrize("kernel", ["block", "tab", "tab_small"])
+@pytest.mark.parametrize("kind,R", [("rademacher", 4), ("gaussian", 3), ("complex_gaussian", 2), ("basis", 1)])
+def test_relabelled_random_graphs(kpm, monkeypatch, kernel, kind, R):
+    """Random 3-regular clusters (N = 13, 15) whose labels cut many bonds at
+    the low/high boundary: the block kernels relabel their sites, and the
+    moments still match the oracle (start vectors drawn by original rank)."""
+    secs = W.sectors(_rr(13, 21), cluster_id=0) + W.sectors(_rr(15, 22), cluster_id=1)
+    if kind == "basis":
+        secs = [s for s in secs if s.dim <= 500]
+    _check(kpm, monkeypatch, kernel, secs, 32, R, kind, "fp64", 0, seed=3)
+    assert kpm.last_run_stats()["relabelled"] == len(secs)
+
+
+def test_relabelling_keeps_the_ring(kpm, monkeypatch):
+    monkeypatch.setenv("KPM_BLOCK", "2")
+    kpm.chebyshev_moments(W.sectors(W.ring(16), only_sz0=True), 8, 2, "rademacher", "fp64", bounds=[(-8, 5)])
+    assert kpm.last_run_stats()["relabelled"] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_relabelled_vectors_in_original_order(kpm, monkeypatch, precision):
+    """v_3 of a relabelled N=18 sector, exported in the original rank order,
+    against the oracle's dense recursion."""
+    from oracle import rows
+    monkeypatch.setenv("KPM_BLOCK", "2")
+    s = W.sectors(_rr(18, 23), only_sz0=True)[0]
+    (lo, hi), H = _bounds(s)
+    kpm.chebyshev_moments([s], 8, 4, "gaussian", precision, 0.025, 5, 4, bounds=[(lo, hi)])
+    assert kpm.last_run_stats()["relabelled"] == 1          # the same plan as the vectors'
+    V, _ = kpm.chebyshev_vectors(s, 3, 4, "gaussian", precision, 0.025, 5, 4, bounds=(lo, hi))
+    a, b = hamiltonian.scale_from_bounds(lo, hi, 0.025)
+    sample = np.concatenate([np.random.default_rng(0).choice(s.dim, 40, replace=False), [0, s.dim - 1]])
+    got = V.double().cpu().numpy()[sample]
+    want = rows.recursion_rows(s.cluster, s.n_up, a, b, "gaussian", 5, 4, sample, 3,
+                               store=np.float32 if precision == "fp32" else np.float64)
+    tol = 1e-6 if precision == "fp32" else 1e-12
+    assert np.abs(got - want).max() <= tol * np.abs(want).max()
+
+
+def test_relabelled_lanczos_and_ftlm(kpm, monkeypatch):
+    """Lanczos bounds and FTLM Ritz values through the relabelled block-table
+    kernel (their start vectors come from the same original-rank draw)."""
+    from oracle import ftlm
+    monkeypatch.setenv("KPM_BLOCK", "2")
+    secs = W.sectors(_rr(14, 24))
+    got = kpm.spectral_bounds(secs, 30, 0.01, 2)
+    for p, s in enumerate(secs):
+        want = moments.spectral_bounds(s, 30, 0.01, 2)
+        assert np.abs(got[p] - np.array(want)).max() <= 1e-9 * max(1.0, np.abs(want).max()), p
+    out = kpm.ftlm(secs, 8, 2, "rademacher", T=[1.0], seed=7, ritz=True, col_block=2)
+    rz = out["ritz"].cpu().numpy()
+    c = 0
+    for s in secs:
+        for e_ref, _ in ftlm.sector_ritz(s, 8, 2, "rademacher", 7):
+            e = np.sort(rz[c, :e_ref.size])
+            assert np.abs(e - e_ref).max() <= 1e-9 * max(1.0, np.abs(e_ref).max()), (s.n_up, c)
+            c += 1
