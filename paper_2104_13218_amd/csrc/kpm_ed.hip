@@ -31,17 +31,6 @@ __device__ __forceinline__ double ed_sum(double v, double* sh) {
   return r;
 }
 
-// Colex (= ascending-integer) rank of word s among the words of its popcount.
-__device__ __forceinline__ uint32_t cns_rank(uint32_t s, const uint32_t* binom) {
-  uint32_t r = 0;
-  int j = 0;
-  for (uint32_t x = s; x; x &= x - 1u) {
-    ++j;
-    r += binom[(__ffs(x) - 1) * kBinomN + j];
-  }
-  return r;
-}
-
 // Rows of H on a spin-s sector (digits d_i = s + m_i with sum n_up): diagonal
 // sum_b J_b m_i m_j, S^+_i S^-_j and S^-_i S^+_j with amplitude
 // J_b/2 sqrt(s(s+1) - m(m+1)) sqrt(s(s+1) - m'(m'-1)).  One row per thread.
@@ -123,7 +112,7 @@ __global__ __launch_bounds__(kThreads) void sector_eig_kernel(const EigArgs a) {
         diag += 0.25 * s_J[q];
       } else {
         diag -= 0.25 * s_J[q];
-        const uint32_t c = cns_rank(s ^ m, sb);
+        const uint32_t c = word_rank(s ^ m, sb);
         if (c < (uint32_t)D) A[(int64_t)r * D + c] += 0.5 * s_J[q];
         else if (a.err) atomicOr(a.err, 2);
       }
