@@ -51,6 +51,7 @@ if ROOT not in sys.path:
 METRIC = "Chebyshev steps·dim/s + HBM GB/s at N=24 S^z=0; speedup vs FP64 at C(T) err"
 HBM_PEAK_GBS = 8000.0
 # step kernel families as reported by kpm_last_run_stats()["kernel"]
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X, dense float64 vector arithmetic
 KERNEL_FAMILY = {0: "step_kernel", 1: "row_kernel", 2: "block_kernel", 3: "tab_kernel", 4: "spin_kernel"}
 PROFILES = os.path.join(ROOT, "profiles")
 
@@ -66,7 +67,8 @@ def _parse():
     ap.add_argument("--cpu-steps", type=int, default=30,
                     help="recursion steps of the CPU-oracle sample")
     ap.add_argument("--workload", default="ring24_sz0",
-                    choices=["ring24_sz0", "batched_rr3", "j1j2_grad", "rr4_30", "ftlm_ring24", "fe10"])
+                    choices=["ring24_sz0", "batched_rr3", "j1j2_grad", "rr4_30", "ftlm_ring24", "fe10",
+                             "ed_batched"])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (reference for HBM byte counters)")
     return ap.parse_args()
@@ -288,6 +290,24 @@ def other_workload(args, kpm, W, np, torch, dev):
         extra = {"fp64": {"value": st64["state_col_steps"] / dt64, "ms": dt64 * 1e3, "roofline": _roofline(st64)}}
         return _line(args, name, st["state_col_steps"] / dt, "state-column-steps/s", dt, cfg,
                      _roofline(st), extra)
+    if name == "ed_batched":
+        # exact spectra of the small sectors of the 64 random clusters (the
+        # hybrid form: sectors of dimension <= 1024 diagonalised completely)
+        secs = []
+        for cid, cl in enumerate(W.batched_clusters(64)):
+            secs += W.sectors(cl, cluster_id=cid)
+        small = [s for s in secs if s.dim <= 1024]
+        ps = kpm.ProblemSet(small)
+        dt, _ = _timed(args, torch, lambda: kpm.sector_eigenvalues(ps, 1024))
+        # Householder tridiagonalisation: 2 n^2 (A v) + 4 n^2 (rank-2 update) per column
+        flops = float(sum(2.0 * s.dim ** 3 for s in small))
+        ach = flops / dt / 1e12
+        cfg = {"sectors": len(small), "max_dim": int(max(s.dim for s in small)),
+               "states": int(sum(s.dim for s in small)), "storage": "f64", "device": dev}
+        roof = {"bound": "alu", "kernel": "sector_eig_kernel", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS,
+                "algorithmic_flops_per_launch": flops, "traffic": None}
+        return _line(args, name, len(small) / dt, "sectors/s", dt, cfg, roof)
     if name == "j1j2_grad":
         wl = W.j1j2_grad_workload()
         ab = kpm.spectral_bounds(wl.problems)

@@ -1796,7 +1796,8 @@ struct EdPlan {
   std::vector<uint32_t> bmask;
   std::vector<double> J;
   std::vector<uint32_t> tables;
-  size_t o_probs = 0, o_mask = 0, o_J = 0, o_binom = 0, o_tab = 0, o_err = 0, o_mat = 0, total = 0;
+  size_t o_probs = 0, o_mask = 0, o_J = 0, o_binom = 0, o_tab = 0, o_err = 0, o_mat = 0, o_vecs = 0, total = 0;
+  int64_t vec_len = 0;   // doubles of each work vector set (sum of the dims)
   int max_bonds = 1;
 };
 
@@ -1815,11 +1816,9 @@ int ed_plan(const kpm_problem* p, int n, int max_dim, EdPlan& E) {
     e.n_bonds = p[i].n_bonds;
     e.bond_off = (int32_t)E.bmask.size();
     e.out_row = i;
-    e.mat_off = mat;
     e.two_s = two_s_of(p[i]);
     e.tab_off = (int32_t)E.tables.size();
     if (e.two_s > 1) build_spin_table(p[i].n_sites, e.two_s, E.tables);
-    mat += (int64_t)dim * (int64_t)dim;
     for (int k = 0; k < p[i].n_bonds; ++k) {
       if (e.two_s > 1) E.bmask.push_back((uint32_t)p[i].bond_i[k] | ((uint32_t)p[i].bond_j[k] << 8));
       else E.bmask.push_back((1u << p[i].bond_i[k]) | (1u << p[i].bond_j[k]));
@@ -1827,6 +1826,15 @@ int ed_plan(const kpm_problem* p, int n, int max_dim, EdPlan& E) {
     }
     E.max_bonds = std::max(E.max_bonds, p[i].n_bonds);
     E.probs.push_back(e);
+  }
+  // descending dimension: the sectors still reducing at any step are a prefix
+  std::stable_sort(E.probs.begin(), E.probs.end(),
+                   [](const EigProb& x, const EigProb& y) { return x.dim > y.dim; });
+  for (auto& e : E.probs) {
+    e.mat_off = mat;
+    e.vec_off = E.vec_len;
+    mat += (int64_t)e.dim * (int64_t)e.dim;
+    E.vec_len += std::max(e.dim, 4);   // >= 4: the bisection parameters reuse hv
   }
   size_t o = 0;
   auto put = [&](size_t bytes) {
@@ -1841,6 +1849,7 @@ int ed_plan(const kpm_problem* p, int n, int max_dim, EdPlan& E) {
   E.o_tab = put(std::max<size_t>(E.tables.size(), 1) * 4);
   E.o_err = put(256);
   E.o_mat = put((size_t)std::max<int64_t>(mat, 1) * 8);
+  E.o_vecs = put((size_t)std::max<int64_t>(E.vec_len, 1) * 4 * 8);
   E.total = o;
   return KPM_OK;
 }
@@ -2389,17 +2398,26 @@ int kpm_sector_eigenvalues(const kpm_problem* p, int32_t n, int32_t max_dim, dou
   a.tables = reinterpret_cast<const uint32_t*>(work + E.o_tab);
   a.err = reinterpret_cast<int*>(work + E.o_err);
   a.mat = reinterpret_cast<double*>(work + E.o_mat);
+  double* vecs = reinterpret_cast<double*>(work + E.o_vecs);
+  a.hv = vecs;
+  a.hp = vecs + E.vec_len;
+  a.hd = vecs + 2 * E.vec_len;
+  a.he = vecs + 3 * E.vec_len;
   a.evals = d_evals;
   a.ld = max_dim;
   a.max_dim = 1;
-  for (const auto& e : E.probs) a.max_dim = std::max(a.max_dim, e.dim);
-  // LDS: binomial table and bond masks, bond J values, five work vectors
+  std::vector<int> dims;
+  for (const auto& e : E.probs) {
+    a.max_dim = std::max(a.max_dim, e.dim);
+    dims.push_back(e.dim);
+  }
+  // LDS: binomial table, bond masks and J values (build); the tridiagonal matrix (finish)
   a.o_bonds = (int32_t)align_up((size_t)(kBinomN * kBinomN + E.max_bonds) * 4, 16);
-  a.o_vec = (int32_t)align_up((size_t)a.o_bonds + (size_t)E.max_bonds * 8, 16);
-  const size_t lds = (size_t)a.o_vec + (size_t)5 * a.max_dim * 8;
-  if (lds > 64 * 1024) return KPM_EINVAL;
+  const size_t lds_build = (size_t)a.o_bonds + (size_t)E.max_bonds * 8;
+  const size_t lds_finish = (size_t)2 * a.max_dim * 8;   // d, e^2 (bisection)
+  if (lds_build > 64 * 1024 || lds_finish > 64 * 1024) return KPM_EINVAL;
   KPM_HIP(hipMemsetAsync(a.err, 0, sizeof(int), st));
-  KPM_HIP(launch_sector_eig(a, (int)E.probs.size(), lds, st));
+  KPM_HIP(launch_sector_eig(a, dims.data(), (int)E.probs.size(), lds_build, lds_finish, st));
   int h_err = 0;
   KPM_HIP(hipMemcpyAsync(&h_err, a.err, sizeof(int), hipMemcpyDeviceToHost, st));
   KPM_HIP(hipStreamSynchronize(st));

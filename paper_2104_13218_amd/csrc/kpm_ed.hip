@@ -2,17 +2,19 @@
 // diagonalised completely instead of being estimated stochastically) and the
 // thermodynamics that mix such spectra with the moments of the other sectors.
 //
-// One workgroup per sector: the dense float64 matrix of H on the sector basis
-// (rank order) is built in the workspace, reduced to a symmetric tridiagonal
-// matrix by Householder reflections applied from both sides, and its
-// eigenvalues are taken by implicit QL (kpm_tridiag.h), then sorted.
+// The dense float64 matrix of H on each sector basis (rank order) is built in
+// the workspace and reduced to a symmetric tridiagonal matrix by Householder
+// reflections applied from both sides, one column per step for all sectors at
+// once (three launches per step, the trailing block split over row tiles so
+// that large sectors spread over the chip); the eigenvalues of the
+// tridiagonal matrix then come from bisection on Sturm counts, one
+// workgroup per sector and one eigenvalue per thread.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 
 #include "kpm_device.h"
 #include "kpm_internal.h"
-#include "kpm_tridiag.h"
 
 namespace kpm {
 
@@ -74,7 +76,8 @@ __device__ void spin_rows(const EigProb& P, const EigArgs& a, const uint32_t* s_
 
 }  // namespace
 
-__global__ __launch_bounds__(kThreads) void sector_eig_kernel(const EigArgs a) {
+// Dense H of every sector (one workgroup per sector, one row per thread).
+__global__ __launch_bounds__(kThreads) void ed_build_kernel(const EigArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const EigProb P = a.probs[blockIdx.x];
@@ -82,12 +85,6 @@ __global__ __launch_bounds__(kThreads) void sector_eig_kernel(const EigArgs a) {
   uint32_t* sb = reinterpret_cast<uint32_t*>(smem);                       // [33 * 33]
   uint32_t* s_mask = sb + kBinomN * kBinomN;                               // [lds_bonds]
   double* s_J = reinterpret_cast<double*>(smem + a.o_bonds);              // [lds_bonds]
-  double* v = reinterpret_cast<double*>(smem + a.o_vec);                  // [max_dim] x 5
-  double* w = v + a.max_dim;
-  double* d = w + a.max_dim;
-  double* e = d + a.max_dim;
-  double* z = e + a.max_dim;
-  __shared__ double sh[4];
   for (int i = tid; i < kBinomN * kBinomN; i += kThreads) sb[i] = a.binom[i];
   for (int q = tid; q < P.n_bonds; q += kThreads) {
     s_mask[q] = a.bmask[P.bond_off + q];
@@ -96,12 +93,12 @@ __global__ __launch_bounds__(kThreads) void sector_eig_kernel(const EigArgs a) {
   double* A = a.mat + P.mat_off;
   for (int64_t i = tid; i < (int64_t)D * D; i += kThreads) A[i] = 0.0;
   __syncthreads();
-
   if (P.two_s > 1) {
     spin_rows(P, a, s_mask, s_J, A);
-  } else {
-  // H on the sector basis: s_i s_j = 1/4 for equal spins, -1/4 otherwise;
-  // unequal spins are exchanged with amplitude J/2.  Each row is one thread's.
+    return;
+  }
+  // s_i s_j = 1/4 for equal spins, -1/4 otherwise; unequal spins are
+  // exchanged with amplitude J/2.
   for (int r = tid; r < D; r += kThreads) {
     const uint32_t s = unrank((uint32_t)r, P.n_sites, P.n_up, sb);
     double diag = 0.0;
@@ -119,59 +116,111 @@ __global__ __launch_bounds__(kThreads) void sector_eig_kernel(const EigArgs a) {
     }
     A[(int64_t)r * D + r] += diag;
   }
-  }
-  __syncthreads();
+}
 
-  // Householder: column k below the diagonal becomes alpha e_1.
-  for (int k = 0; k + 2 < D; ++k) {
-    const int n2 = D - k - 1;
-    const double* rowk = A + (int64_t)k * D + (k + 1);
-    double part = 0.0;
-    for (int i = tid; i < n2; i += kThreads) {
-      const double x = rowk[i];
-      v[i] = x;
-      part = fma(x, x, part);
-    }
-    const double sigma = ed_sum(part, sh);
-    const double x0 = v[0];
-    const double tail = sigma - x0 * x0;
-    if (tid == 0) d[k] = A[(int64_t)k * D + k];
-    if (!(tail > 1e-300)) {          // already tridiagonal in this column
-      if (tid == 0) e[k] = x0;
-      __syncthreads();
-      continue;
-    }
-    const double alpha = -copysign(sqrt(sigma), x0);
-    if (tid == 0) e[k] = alpha;
-    const double v0 = x0 - alpha;
-    const double inv = 1.0 / sqrt(tail + v0 * v0);
-    __syncthreads();
-    for (int i = tid; i < n2; i += kThreads) v[i] = (i == 0 ? v0 : v[i]) * inv;
-    __syncthreads();
-    // p = 2 A' v (A' symmetric: thread i walks column i, rows coalesced)
-    const double* Ap = A + (int64_t)(k + 1) * D + (k + 1);
-    for (int i = tid; i < n2; i += kThreads) {
-      double acc = 0.0;
-      for (int j = 0; j < n2; ++j) acc = fma(Ap[(int64_t)j * D + i], v[j], acc);
-      w[i] = 2.0 * acc;
-    }
-    __syncthreads();
-    part = 0.0;
-    for (int i = tid; i < n2; i += kThreads) part = fma(v[i], w[i], part);
-    const double K = ed_sum(part, sh);
-    for (int i = tid; i < n2; i += kThreads) w[i] = fma(-K, v[i], w[i]);
-    __syncthreads();
-    // A' <- A' - v w^T - w v^T
-    double* Am = A + (int64_t)(k + 1) * D + (k + 1);
-    for (int j = 0; j < n2; ++j) {
-      const double vj = v[j], wj = w[j];
-      for (int i = tid; i < n2; i += kThreads) {
-        double& x = Am[(int64_t)j * D + i];
-        x = fma(-vj, w[i], fma(-wj, v[i], x));
-      }
-    }
-    __syncthreads();
+// Householder step k, part 1 (one workgroup per active sector): the part of
+// row k right of the diagonal, x, becomes alpha e_1 under I - 2 v v^T with
+// v = (x - alpha e_1) / |x - alpha e_1|, alpha = -sign(x_0) |x|; d[k], e[k]
+// are recorded.  A row that is already zero there keeps v = 0.
+__global__ __launch_bounds__(kThreads) void ed_hh_vec_kernel(const EigArgs a, int k) {
+  __shared__ double sh[4];
+  const EigProb P = a.probs[blockIdx.x];
+  const int D = P.dim, n2 = D - k - 1;
+  if (k + 2 >= D) return;
+  const double* x = a.mat + P.mat_off + (int64_t)k * D + (k + 1);
+  double* v = a.hv + P.vec_off;
+  double part = 0.0;
+  for (int i = threadIdx.x; i < n2; i += kThreads) part = fma(x[i], x[i], part);
+  const double sigma = ed_sum(part, sh);
+  const double x0 = x[0];
+  const double tail = sigma - x0 * x0;
+  if (threadIdx.x == 0) a.hd[P.vec_off + k] = a.mat[P.mat_off + (int64_t)k * D + k];
+  if (!(tail > 1e-300)) {
+    if (threadIdx.x == 0) a.he[P.vec_off + k] = x0;
+    for (int i = threadIdx.x; i < n2; i += kThreads) v[i] = 0.0;
+    return;
   }
+  const double alpha = -copysign(sqrt(sigma), x0);
+  if (threadIdx.x == 0) a.he[P.vec_off + k] = alpha;
+  const double v0 = x0 - alpha;
+  const double inv = 1.0 / sqrt(tail + v0 * v0);
+  for (int i = threadIdx.x; i < n2; i += kThreads) v[i] = (i == 0 ? v0 : x[i]) * inv;
+}
+
+// Part 2 (grid: active sectors x tiles of kEdRows rows): p = 2 A' v over the
+// trailing block A' (rows and columns k+1..D-1); each wave takes rows of the
+// tile, its lanes stride over the row.
+__global__ __launch_bounds__(kThreads) void ed_hh_matvec_kernel(const EigArgs a, int k) {
+  const EigProb P = a.probs[blockIdx.x];
+  const int D = P.dim, n2 = D - k - 1;
+  if (k + 2 >= D) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double* v = a.hv + P.vec_off;
+  double* pv = a.hp + P.vec_off;
+  for (int rr = wv; rr < kEdRows; rr += kThreads / 64) {
+    const int i = blockIdx.y * kEdRows + rr;
+    if (i >= n2) break;
+    const double* row = a.mat + P.mat_off + (int64_t)(k + 1 + i) * D + (k + 1);
+    double acc = 0.0;
+    for (int j = lane; j < n2; j += 64) acc = fma(row[j], v[j], acc);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (lane == 0) pv[i] = 2.0 * acc;
+  }
+}
+
+// Part 3 (same grid): K = v.p, w = p - K v, A' -= v w^T + w v^T on the tile's
+// rows (every workgroup sums K in the same order).
+__global__ __launch_bounds__(kThreads) void ed_hh_update_kernel(const EigArgs a, int k) {
+  __shared__ double sh[4];
+  const EigProb P = a.probs[blockIdx.x];
+  const int D = P.dim, n2 = D - k - 1;
+  if (k + 2 >= D) return;
+  const double* v = a.hv + P.vec_off;
+  const double* pv = a.hp + P.vec_off;
+  double part = 0.0;
+  for (int i = threadIdx.x; i < n2; i += kThreads) part = fma(v[i], pv[i], part);
+  const double K = ed_sum(part, sh);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int rr = wv; rr < kEdRows; rr += kThreads / 64) {
+    const int i = blockIdx.y * kEdRows + rr;
+    if (i >= n2) break;
+    const double vi = v[i], wi = fma(-K, vi, pv[i]);
+    double* row = a.mat + P.mat_off + (int64_t)(k + 1 + i) * D + (k + 1);
+    for (int j = lane; j < n2; j += 64) {
+      const double wj = fma(-K, v[j], pv[j]);
+      row[j] = fma(-vi, wj, fma(-wi, v[j], row[j]));
+    }
+  }
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix (d, e):
+// the negative pivots of the LDL^T factorisation of T - x (Sturm sequence),
+// a pivot of magnitude below pivmin taken as -pivmin.
+__device__ __forceinline__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    q = (d[i] - x) - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+// Last part, 1 (one workgroup per sector): the final 2 x 2 block, the
+// squared off-diagonal, the Gershgorin interval and the pivot floor.
+__global__ __launch_bounds__(kThreads) void ed_tri_kernel(const EigArgs a) {
+  __shared__ double sh_lo[kThreads], sh_hi[kThreads], sh_e2[kThreads];
+  const int tid = threadIdx.x;
+  const EigProb P = a.probs[blockIdx.x];
+  const int D = P.dim;
+  double* d = a.hd + P.vec_off;
+  double* e = a.he + P.vec_off;
+  double* e2 = a.hp + P.vec_off;
+  const double* A = a.mat + P.mat_off;
   if (tid == 0) {
     if (D >= 2) {
       d[D - 2] = A[(int64_t)(D - 2) * D + (D - 2)];
@@ -180,22 +229,87 @@ __global__ __launch_bounds__(kThreads) void sector_eig_kernel(const EigArgs a) {
     } else {
       d[0] = A[0];
     }
-    if (!tridiag_ql_first_row(d, e, z, D) && a.err) atomicOr(a.err, 8);
+    e[D - 1] = 0.0;
   }
   __syncthreads();
-  // ascending order: each value goes to its rank (ties by index)
-  double* out = a.evals + (int64_t)P.out_row * a.ld;
+  double lo = INFINITY, hi = -INFINITY, m2 = 0.0;
   for (int i = tid; i < D; i += kThreads) {
-    const double x = d[i];
-    int rk = 0;
-    for (int j = 0; j < D; ++j) rk += (d[j] < x || (d[j] == x && j < i)) ? 1 : 0;
-    out[rk] = x;
+    const double r = fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0);
+    lo = fmin(lo, d[i] - r);
+    hi = fmax(hi, d[i] + r);
+    e2[i] = e[i] * e[i];
+    m2 = fmax(m2, e2[i]);
+  }
+  sh_lo[tid] = lo;
+  sh_hi[tid] = hi;
+  sh_e2[tid] = m2;
+  __syncthreads();
+  for (int st = kThreads / 2; st > 0; st >>= 1) {
+    if (tid < st) {
+      sh_lo[tid] = fmin(sh_lo[tid], sh_lo[tid + st]);
+      sh_hi[tid] = fmax(sh_hi[tid], sh_hi[tid + st]);
+      sh_e2[tid] = fmax(sh_e2[tid], sh_e2[tid + st]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double span = fmax(fabs(sh_lo[0]), fabs(sh_hi[0]));
+    double* g = a.hv + P.vec_off;   // the Householder vectors are no longer needed
+    g[0] = sh_lo[0] - 1e-14 * span - 1e-300;
+    g[1] = sh_hi[0] + 1e-14 * span + 1e-300;
+    g[2] = 1e-290 * fmax(1.0, sh_e2[0]);
+    g[3] = span;
   }
 }
 
-hipError_t launch_sector_eig(const EigArgs& a, int n_sectors, size_t lds, hipStream_t st) {
+// Last part, 2 (grid: sectors x tiles of 64 eigenvalue indices, one per
+// thread): eigenvalue idx by bisection on the Sturm count from the Gershgorin
+// interval, down to adjacent floating-point numbers or 1e-16 of the spectral
+// radius; written in ascending order.
+__global__ __launch_bounds__(64) void ed_bisect_kernel(const EigArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const EigProb P = a.probs[blockIdx.x];
+  const int D = P.dim;
+  if ((int)blockIdx.y * 64 >= D) return;
+  double* d = reinterpret_cast<double*>(smem);
+  double* e2 = d + a.max_dim;
+  for (int i = threadIdx.x; i < D; i += 64) {
+    d[i] = a.hd[P.vec_off + i];
+    e2[i] = a.hp[P.vec_off + i];
+  }
+  const double* g = a.hv + P.vec_off;
+  const double g_lo = g[0], g_hi = g[1], pivmin = g[2], span = g[3];
+  __syncthreads();
+  const int idx = blockIdx.y * 64 + threadIdx.x;
+  if (idx >= D) return;
+  double x0 = g_lo, x1 = g_hi;
+  for (int it = 0; it < 256; ++it) {
+    const double mid = 0.5 * (x0 + x1);
+    // adjacent numbers, or a width at the rounding level of the matrix
+    if (!(mid > x0 && mid < x1) || x1 - x0 <= 1e-16 * span) break;
+    if (sturm_count(d, e2, D, mid, pivmin) > idx) x1 = mid;
+    else x0 = mid;
+  }
+  a.evals[(int64_t)P.out_row * a.ld + idx] = 0.5 * (x0 + x1);
+}
+
+// The sectors are sorted by descending dimension, so the sectors still active
+// at step k (D > k + 2) are a prefix.
+hipError_t launch_sector_eig(const EigArgs& a, const int* dims, int n_sectors, size_t lds_build,
+                             size_t lds_finish, hipStream_t st) {
   if (n_sectors == 0) return hipSuccess;
-  hipLaunchKernelGGL(sector_eig_kernel, dim3(n_sectors), dim3(kThreads), lds, st, a);
+  hipLaunchKernelGGL(ed_build_kernel, dim3(n_sectors), dim3(kThreads), lds_build, st, a);
+  int active = n_sectors;
+  for (int k = 0; k + 2 < dims[0]; ++k) {
+    while (active > 0 && dims[active - 1] <= k + 2) --active;
+    const int n2 = dims[0] - k - 1;
+    const dim3 grid(active, (n2 + kEdRows - 1) / kEdRows);
+    hipLaunchKernelGGL(ed_hh_vec_kernel, dim3(active), dim3(kThreads), 0, st, a, k);
+    hipLaunchKernelGGL(ed_hh_matvec_kernel, grid, dim3(kThreads), 0, st, a, k);
+    hipLaunchKernelGGL(ed_hh_update_kernel, grid, dim3(kThreads), 0, st, a, k);
+  }
+  hipLaunchKernelGGL(ed_tri_kernel, dim3(n_sectors), dim3(kThreads), 0, st, a);
+  hipLaunchKernelGGL(ed_bisect_kernel, dim3(n_sectors, (dims[0] + 63) / 64), dim3(64), lds_finish, st, a);
   return hipGetLastError();
 }
 

@@ -275,7 +275,10 @@ struct EigProb {
   int32_t bond_off, out_row;   // bonds in the packed arrays; row of the output
   int64_t mat_off;             // doubles from the matrix workspace base
   int32_t two_s, tab_off;      // spin s > 1/2: 2s and its rank table (EigArgs::tables)
+  int64_t vec_off;             // doubles from the work-vector bases (hv, hp, hd, he)
 };
+
+constexpr int kEdRows = 4;     // rows of the trailing block per workgroup (Householder steps)
 
 struct EigArgs {
   const EigProb* probs;        // one per workgroup
@@ -284,12 +287,19 @@ struct EigArgs {
   const uint32_t* binom;       // C(n, j) [33][33]
   const uint32_t* tables;      // spin-s rank tables P[i][r][d] (as ProbDev)
   double* mat;                 // dense sector matrices
+  double* hv;                  // per sector [max(dim, 4)]: Householder vector of the current
+                               // step, then the bisection interval, pivot floor and radius
+  double* hp;                  // per sector [dim]: 2 A' v
+  double* hd;                  // per sector [dim]: diagonal of the tridiagonal matrix
+  double* he;                  // per sector [dim]: its off-diagonal
   double* evals;               // [rows][ld] ascending eigenvalues
-  int* err;                    // bit 1: rank out of range, bit 3: QL did not converge
+  int* err;                    // bit 1: rank out of range
   int32_t ld, max_dim;
-  int32_t o_bonds, o_vec;      // LDS byte offsets (bond J values, the five work vectors)
+  int32_t o_bonds;             // LDS byte offset of the bond J values (build kernel)
 };
-hipError_t launch_sector_eig(const EigArgs& a, int n_sectors, size_t lds, hipStream_t st);
+// probs sorted by descending dim; dims[i] = probs[i].dim on the host.
+hipError_t launch_sector_eig(const EigArgs& a, const int* dims, int n_sectors, size_t lds_build,
+                             size_t lds_finish, hipStream_t st);
 hipError_t launch_thermo_hybrid(const ThermoArgs& a, hipStream_t st);
 
 // Finite-temperature Lanczos: Ritz values/weights per column and the sums.
