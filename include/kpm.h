@@ -246,18 +246,20 @@ size_t kpm_sector_eigenvalues_workspace_size(const kpm_problem* p, int32_t n, in
 
 /* Exact spectra of the small sectors (Sec. II: a sector of small dimension is
  * diagonalised completely instead of being estimated stochastically).  For
- * every problem i with D = C(n_sites, n_up) <= max_dim, row i of d_evals gets
- * the D eigenvalues of H (unscaled; the problem's bounds are not used) on the
- * sector, ascending, followed by NaN; rows of larger sectors are all NaN.
- * Float64 throughout: the dense sector matrix, Householder reduction to
- * tridiagonal form, implicit QL; one workgroup per sector.
+ * every problem i whose sector dimension D (C(n_sites, n_up) for spin 1/2) is
+ * <= max_dim, row i of d_evals gets the D eigenvalues of H (unscaled; the
+ * problem's bounds are not used) on the sector, ascending, followed by NaN;
+ * rows of larger sectors are all NaN.  Float64 throughout: the dense sector
+ * matrix, Householder reduction to tridiagonal form (one column per step for
+ * all sectors at once, spread over row tiles), every eigenvalue by bisection
+ * on Sturm counts to the rounding level of the matrix.
  *  max_dim   1..1024
  *  d_evals   device double [n][max_dim]
  *  d_work    device workspace of kpm_sector_eigenvalues_workspace_size bytes
- *            (8 D^2 per diagonalised sector + small tables), or NULL: allocated
- *            and freed inside the call
- * Errors: KPM_EINVAL, KPM_EWORKSPACE, KPM_EDEVICE (HIP error, or QL did not
- * converge). */
+ *            (8 D^2 + 32 max(D, 4) per diagonalised sector + small tables), or
+ *            NULL: allocated and freed inside the call
+ * Errors: KPM_EINVAL, KPM_EWORKSPACE, KPM_EDEVICE (HIP error, or a neighbour
+ * rank outside its sector). */
 int kpm_sector_eigenvalues(const kpm_problem* p, int32_t n, int32_t max_dim, double* d_evals,
                            void* d_work, size_t work_bytes, void* stream);
 
