@@ -1741,7 +1741,7 @@ int thermo_forward(const double* d_mu, const double* d_ab, const kpm_problem* p,
 // ---------------------------------------------- finite-temperature Lanczos
 
 struct FtlmLayout {
-  size_t plan, vec, vecC, part, dots, b2, zero, norm, err, states, ritz, escr, weight, len, total;
+  size_t plan, vec, part, dots, b2, zero, norm, err, states, ritz, escr, weight, len, total;
 };
 
 // Every real column runs its own Lanczos recursion; columns are batched in
@@ -1771,7 +1771,6 @@ FtlmLayout ftlm_layout(const Planned& P, int steps) {
   const size_t TC = (size_t)P.plan.total_cols;
   L.plan = put(P.bytes);
   L.vec = put((size_t)P.plan.vec_elems * 8);
-  L.vecC = put((size_t)P.plan.vec_elems * 8);
   L.part = put((size_t)P.plan.part_len * 8);
   L.dots = put((size_t)steps * TC * 8);
   L.b2 = put((size_t)steps * TC * 8);
@@ -2221,7 +2220,8 @@ size_t kpm_ftlm_workspace_size(const kpm_problem* p, int32_t n, const kpm_params
   if (check_problems(p, n) != KPM_OK || !q || check_params(*q) != KPM_OK) return 0;
   if (q->precision != KPM_FP64) return 0;
   Planned P;
-  if (make_plan(p, n, ftlm_shape(*q), nullptr, nullptr, P) != KPM_OK) return 0;
+  const std::vector<double> two(n, 2.0), zero(n, 0.0);
+  if (make_plan(p, n, ftlm_shape(*q), two.data(), zero.data(), P) != KPM_OK) return 0;
   return ftlm_layout(P, ftlm_steps(P, q->M)).total;
 }
 
@@ -2236,7 +2236,9 @@ int kpm_ftlm(const kpm_problem* p, int32_t n, const kpm_params* q, const double*
   hipStream_t st = static_cast<hipStream_t>(stream);
   StreamSync guard{st};
   Planned P;
-  r = make_plan(p, n, ftlm_shape(*q), nullptr, nullptr, P);   // H unscaled: a = 1, b = 0
+  // H' = H / 2 (a = 2, b = 0), so that the recursion step's 2 H' x - y is H q_j - beta_j q_{j-1}
+  const std::vector<double> two(n, 2.0), zero_b(n, 0.0);
+  r = make_plan(p, n, ftlm_shape(*q), two.data(), zero_b.data(), P);
   if (r != KPM_OK) return r;
   const int steps = ftlm_steps(P, q->M);
   const FtlmLayout L = ftlm_layout(P, steps);
@@ -2258,7 +2260,6 @@ int kpm_ftlm(const kpm_problem* p, int32_t n, const kpm_params* q, const double*
   KPM_HIP(hipMemsetAsync(D.err, 0, sizeof(int), st));
   if (D.row_ld || D.block || D.spin) KPM_HIP(fill_states(D, st));
   double* vec = reinterpret_cast<double*>(work + L.vec);
-  double* vecC = reinterpret_cast<double*>(work + L.vecC);
   double* part = reinterpret_cast<double*>(work + L.part);
   double* dots = reinterpret_cast<double*>(work + L.dots);
   double* b2 = reinterpret_cast<double*>(work + L.b2);
@@ -2266,32 +2267,30 @@ int kpm_ftlm(const kpm_problem* p, int32_t n, const kpm_params* q, const double*
   double* norm = reinterpret_cast<double*>(work + L.norm);
   const int TC = D.total_cols;
   KPM_HIP(hipMemsetAsync(vec, 0, (size_t)D.vec_elems * 8, st));
-  KPM_HIP(hipMemsetAsync(vecC, 0, (size_t)D.vec_elems * 8, st));
   KPM_HIP(hipMemsetAsync(zero, 0, (size_t)TC * 8, st));
   // unit-norm start columns (the random vectors of Eq. (7)), |column|^2 kept
   KPM_HIP(launch_init(D, vec, 0, q->vec_kind, q->seed, nullptr, part, st));
   KPM_HIP(launch_reduce(D, part, norm, nullptr, st));
   KPM_HIP(launch_init(D, vec, 2, q->vec_kind, q->seed, norm, part, st));
+  // Lanczos (per column): slot x holds q_j, slot y holds beta_j q_{j-1} (0 at
+  // j = 0).  One recursion step gives w_j = 2 H' q_j - y = H q_j - beta_j q_{j-1}
+  // and alpha_j = <w_j, q_j>; then w_j -= alpha_j q_j with |w_j|^2 = beta_{j+1}^2;
+  // the turn leaves q_{j+1} in slot y and beta_{j+1} q_j in slot x, whose roles
+  // then swap.
+  int px = 0;
   for (int j = 0; j < steps; ++j) {
-    KPM_HIP(launch_step(D, vec, part, nullptr, 0, nullptr, nullptr, nullptr, 0, 0, 1, st));
-    LzArgs a1{};
-    a1.w = vec; a1.w_hi = 1;
-    a1.q = vecC; a1.q_hi = 0;
-    a1.coef = j ? b2 + (size_t)(j - 1) * TC : zero;
-    a1.coef_sqrt = 1;
-    a1.dotvec = vec; a1.d_hi = 0;
-    a1.part_out = part;
-    KPM_HIP(launch_lz_axpy(D, a1, st));
-    KPM_HIP(launch_reduce(D, part, dots + (size_t)j * TC, nullptr, st));
+    KPM_HIP(launch_step(D, vec, part, nullptr, 0, nullptr, nullptr, nullptr, 0, px, 0, st));
+    KPM_HIP(launch_reduce(D, part, nullptr, dots + (size_t)j * TC, st));
     LzArgs a2{};
-    a2.w = vec; a2.w_hi = 1;
-    a2.q = vec; a2.q_hi = 0;
+    a2.w = vec; a2.w_hi = 1 - px;
+    a2.q = vec; a2.q_hi = px;
     a2.coef = dots + (size_t)j * TC;
     a2.dotvec = nullptr;
     a2.part_out = part;
     KPM_HIP(launch_lz_axpy(D, a2, st));
     KPM_HIP(launch_reduce(D, part, b2 + (size_t)j * TC, nullptr, st));
-    KPM_HIP(launch_lz_next(D, vecC, vec, vec, b2 + (size_t)j * TC, st));
+    KPM_HIP(launch_lz_turn(D, vec, 1 - px, b2 + (size_t)j * TC, st));
+    px = 1 - px;
   }
   // thermodynamic metadata (sector weights, S^z, clusters)
   std::vector<ThermoProb> tp;

@@ -2312,6 +2312,53 @@ __global__ __launch_bounds__(kThreads) void lz_next_kernel(const LzArgs a, doubl
   }
 }
 
+// After w_j = H q_j - beta_j q_{j-1} and w_j -= alpha_j q_j: per column with
+// beta_{j+1}^2 = |w_j|^2 > 1e-24, y <- w_j / beta_{j+1} (= q_{j+1}) and
+// x <- beta_{j+1} q_j (the term the next step subtracts); a column whose Krylov
+// space is exhausted keeps q_j (y <- x) and drops the term (x <- 0).  The
+// caller then swaps the two slots' roles.
+__global__ __launch_bounds__(kThreads) void lz_turn_kernel(const LzArgs a, const double* beta2) {
+  const int tile = xcd_tile(blockIdx.x, a.grid_tiles);
+  if (tile >= a.n_tiles) return;
+  const UnitDev U = a.units[a.tile_unit[tile]];
+  const int64_t row0 = a.tile_row0[tile];
+  const int64_t row1 = row0 + a.tile_nrows[tile];
+  const int ld = U.ld;
+  const int nrg = kThreads / ld;
+  const int c = threadIdx.x % ld, rg = threadIdx.x / ld;
+  if (rg >= nrg) return;
+  double* y = lz_sel(a.w, a.w_hi, U, a.slot_stride);
+  double* x = lz_sel(const_cast<double*>(a.q), a.q_hi, U, a.slot_stride);
+  const double b2 = beta2[U.col_off + c];
+  const bool live = b2 > 1e-24;
+  const double b = live ? sqrt(b2) : 0.0;
+  const double inv = live ? 1.0 / b : 0.0;
+  for (int64_t r = row0 + rg; r < row1; r += nrg) {
+    const int64_t i = r * ld + c;
+    const double xv = x[i];
+    y[i] = live ? y[i] * inv : xv;
+    x[i] = b * xv;
+  }
+}
+
+hipError_t launch_lz_turn(const DevicePlan& p, double* vec, int y_hi, const double* beta2, hipStream_t st) {
+  LzArgs a{};
+  a.probs = p.probs;
+  a.units = p.units;
+  a.tile_unit = p.tile_unit;
+  a.n_tiles = p.n_tiles;
+  a.grid_tiles = p.grid_tiles;
+  a.tile_row0 = p.tile_row0;
+  a.tile_nrows = p.tile_nrows;
+  a.slot_stride = p.slot_stride;
+  a.w = vec;
+  a.w_hi = y_hi;
+  a.q = vec;
+  a.q_hi = 1 - y_hi;
+  hipLaunchKernelGGL(lz_turn_kernel, dim3(p.grid_tiles), dim3(kThreads), 0, st, a, beta2);
+  return hipGetLastError();
+}
+
 hipError_t launch_lz_next(const DevicePlan& p, double* qprev, double* q, const double* w,
                           const double* beta2, hipStream_t st) {
   LzArgs a{};
