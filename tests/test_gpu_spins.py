@@ -172,6 +172,28 @@ def test_fe10_sz0_sampled_rows(kpm, precision, kind, R, col_block, n):
     assert np.abs(got - want).max() <= tol * np.abs(want).max()
 
 
+def test_fe10_bench_configuration(kpm):
+    """The benchmark's launch configuration (100 float32 columns, default
+    blocks of 64 + 36): sampled rows of v_2 of the S^z = 0 sector against the
+    oracle, and mu_0 = dim, |mu_n| <= mu_0 on all 26 sectors."""
+    s = W.spin_sectors(W.fe10(), 5, only_sz0=True)[0]
+    V, _ = kpm.chebyshev_vectors(s, 2, 100, "rademacher", "fp32", 0.025, 0, 0, bounds=FE10_BOUNDS)
+    sample = np.concatenate([np.random.default_rng(7).choice(s.dim, size=10, replace=False), [0, s.dim - 1]])
+    got = V[torch.as_tensor(sample, device="cuda")].double().cpu().numpy()
+    del V
+    a, b = hamiltonian.scale_from_bounds(*FE10_BOUNDS, 0.025)
+    want = spins.recursion_rows(s.cluster, 5, s.n, a, b, "rademacher", 0, 100, sample, 2, store=np.float32)
+    assert np.abs(got - want).max() <= 1e-6 * np.abs(want).max()
+    secs = W.spin_sectors(W.fe10(), 5)
+    mu, _ = kpm.chebyshev_moments(secs, 32, 100, "rademacher", "fp32", 0.025, 0, bounds=[FE10_BOUNDS] * len(secs))
+    st = kpm.last_run_stats()
+    assert st["kernel"] == 4 and st["col_block"] == 64, st
+    mu = mu.cpu().numpy()
+    for p, sec in enumerate(secs):
+        assert abs(mu[p, 0] - sec.dim) <= 1e-9 * sec.dim, p
+        assert np.all(np.abs(mu[p]) <= mu[p, 0] * (1 + 1e-6)), p
+
+
 def test_fe10_all_sectors_properties(kpm):
     secs = W.spin_sectors(W.fe10(), 5)
     assert len(secs) == 26 and sum(s.dim for s in secs) == 32430816
