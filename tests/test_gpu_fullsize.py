@@ -13,6 +13,9 @@ configuration the benchmark times (default kernel choice, graph segments).
   vectors, float32 and float64, M = 500: sampled rows of v_3 against the
   oracle's row-by-row recursion, mu_0 = dim, |mu_n| <= mu_0, and the two
   precisions' moments side by side.
+* The largest words, N = 32 S^z = 0 (601,080,390 states) on a random
+  3-regular graph, with the row kernel and the relabelled block-table kernel:
+  sampled rows of v_2, mu_0 = dim and |mu_n| <= mu_0.
 
 |mu_n| <= mu_0 holds for every estimate because ||T_n(H')|| <= 1 on the
 rescaled spectrum and mu_0 = dim exactly for normalised vectors (Eq. (7))."""
@@ -132,3 +135,30 @@ def test_rr4_30_full_size(kpm):
         _props(mus[precision], [s.dim])
         torch.cuda.empty_cache()
     assert np.abs(mus["fp32"] - mus["fp64"]).max() <= 1e-4 * s.dim
+
+
+@pytest.mark.parametrize("block", [None, "2"])
+def test_n32_maximum_sites(kpm, monkeypatch, block):
+    """The largest basis words (N = 32 sites, S^z = 0: 601,080,390 states) on a
+    seeded random 3-regular graph, with the default kernel (row kernel for two
+    columns) and with the block-table kernel, whose plan relabels the sites:
+    sampled rows of v_2 against the oracle's row-by-row recursion (rows in the
+    original order), mu_0 = dim and |mu_n| <= mu_0."""
+    if block:
+        monkeypatch.setenv("KPM_BLOCK", block)
+    cl = W.random_regular_cluster(32, 3, 7)
+    s = W.sectors(cl, only_sz0=True)[0]
+    assert s.dim == 601080390
+    lo, hi = -37.0, 13.0            # -3/4 <= s_i.s_j <= 1/4 per bond, 48 bonds
+    V, _ = kpm.chebyshev_vectors(s, 2, 2, "rademacher", "fp32", 0.025, 3, 2, bounds=(lo, hi))
+    sample = np.concatenate([np.random.default_rng(32).choice(s.dim, size=16, replace=False), [0, s.dim - 1]])
+    got = V[torch.as_tensor(sample, device="cuda")].double().cpu().numpy()
+    del V
+    torch.cuda.empty_cache()
+    a, b = hamiltonian.scale_from_bounds(lo, hi, 0.025)
+    want = rows.recursion_rows(cl, s.n_up, a, b, "rademacher", 3, 2, sample, 2, store=np.float32)
+    assert np.abs(got - want).max() <= 1e-6 * np.abs(want).max()
+    mu, _ = kpm.chebyshev_moments([s], 8, 2, "rademacher", "fp32", 0.025, 3, 2, bounds=[(lo, hi)])
+    st = kpm.last_run_stats()
+    assert (st["kernel"], st["relabelled"]) == ((3, 1) if block else (1, 0)), st
+    _props(mu.cpu().numpy(), [s.dim], tol0=1e-6)
