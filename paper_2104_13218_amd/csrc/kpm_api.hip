@@ -220,6 +220,7 @@ struct RunShape {
   bool adjoint = false;   // block widths padded to the adjoint kernel's (1..16, power of 2)
   bool allow_row = true;  // the row kernel may run the recursion
   bool split_vectors = false;  // complex vectors may be split across blocks (one column each)
+  bool allow_relabel = true;   // block kernels may relabel sites (rows then in relabelled order)
 };
 
 constexpr int kAdjMaxLd = 16;
@@ -570,7 +571,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
                           ? i - 1
                           : -1;
         if (j >= 0) pm = relabels[j];
-        else choose_relabel(p[i], L, pm);
+        else if (s.allow_relabel) choose_relabel(p[i], L, pm);
         auto lab = [&](int site) { return pm.empty() ? site : (int)pm[site]; };
         std::vector<uint16_t> cls[3];
         for (int k = 0; k < p[i].n_bonds; ++k) {
@@ -1455,11 +1456,32 @@ int resolve_scale(const kpm_problem* p, int n, const kpm_params& q, unsigned cha
 // ------------------------------------------------------------- adjoint driver
 
 struct VjpLayout {
-  size_t plan, seg, w, ckpt, part, norms, alpha0, abar, bbar, bd, flag, total;
+  size_t plan, seg, w, ckpt, part, norms, alpha0, abar, bbar, bd, flag, planf, statesf, partf, total;
   int nck, C, K;
 };
 
-VjpLayout vjp_layout(const Planned& P, int M, int ckpt_every) {
+// Plan of the forward and recompute steps of the adjoint: the fastest forward
+// kernel (block-table or row kernel) on the same vector layout as the adjoint
+// plan P (same blocks, widths and offsets; sites not relabelled).  Returns
+// false when the layouts differ: the adjoint plan's own kernel then runs them.
+bool forward_plan_for(const kpm_problem* p, int n, const kpm_params& q, const Planned& P,
+                      const double* a, const double* b, Planned& F) {
+  if (env_int("KPM_ADJ_FWD", 1) == 0 || P.units.empty()) return false;
+  RunShape s = shape_of(q);
+  s.allow_relabel = false;
+  s.col_block = P.units[0].ncols;
+  if (make_plan(p, n, s, a, b, F) != KPM_OK) return false;
+  if (F.units.size() != P.units.size() || F.plan.slot_stride != P.plan.slot_stride || F.plan.fp32 != P.plan.fp32)
+    return false;
+  for (size_t i = 0; i < P.units.size(); ++i) {
+    const UnitDev &u = P.units[i], &f = F.units[i];
+    if (u.ld != f.ld || u.vec_off != f.vec_off || u.prob != f.prob || u.ncols != f.ncols || u.col0 != f.col0)
+      return false;
+  }
+  return F.plan.block || F.plan.row_ld;
+}
+
+VjpLayout vjp_layout(const Planned& P, const Planned* F, int M, int ckpt_every) {
   VjpLayout L{};
   const int K = n_steps(M);
   const int C = std::max(2, ckpt_every & ~1);
@@ -1486,6 +1508,11 @@ VjpLayout vjp_layout(const Planned& P, int M, int ckpt_every) {
   L.bbar = put((size_t)(K + 1) * TC * 8);
   L.bd = put((size_t)P.plan.bd_len * 8);
   L.flag = put(256);
+  if (F) {
+    L.planf = put(F->bytes);
+    L.statesf = put((size_t)F->plan.n_states * 4);
+    L.partf = put((size_t)F->plan.part_len * 8);
+  }
   L.total = o;
   return L;
 }
@@ -1497,9 +1524,10 @@ RunShape adj_shape(const kpm_params& q) {
 }
 
 size_t vjp_workspace(const kpm_problem* p, int n, const kpm_params& q, int ckpt_every) {
-  Planned P;
+  Planned P, F;
   if (make_plan(p, n, adj_shape(q), nullptr, nullptr, P) != KPM_OK) return 0;
-  return vjp_layout(P, q.M, ckpt_every).total;
+  const bool fwd = forward_plan_for(p, n, q, P, nullptr, nullptr, F);
+  return vjp_layout(P, fwd ? &F : nullptr, q.M, ckpt_every).total;
 }
 
 // Forward recursion with checkpoints, then the reverse sweep segment by
@@ -1513,17 +1541,30 @@ int run_vjp(const kpm_problem* p, int n, const kpm_params& q, const double* h_ab
     b[i] = h_ab[2 * i + 1];
     if (!(a[i] > 0.0) || !std::isfinite(a[i]) || !std::isfinite(b[i])) return KPM_EINVAL;
   }
-  Planned P;
+  Planned P, F;
   int r = make_plan(p, n, adj_shape(q), a.data(), b.data(), P);
   if (r != KPM_OK) return r;
-  const VjpLayout L = vjp_layout(P, q.M, ckpt_every);
-  std::vector<unsigned char> staging;
+  const bool fwd = forward_plan_for(p, n, q, P, a.data(), b.data(), F);
+  const VjpLayout L = vjp_layout(P, fwd ? &F : nullptr, q.M, ckpt_every);
+  std::vector<unsigned char> staging, staging_f;
   r = upload_plan(P, work + L.plan, staging, st);
   if (r != KPM_OK) return r;
   DevicePlan& D = P.plan;
   int* flag = reinterpret_cast<int*>(work + L.flag);
   D.err = flag;
   KPM_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+  // forward and recompute steps: F's kernel on the same vectors (partial dots discarded)
+  DevicePlan* Dfw = &D;
+  double* part_fw = reinterpret_cast<double*>(work + L.part);
+  if (fwd) {
+    r = upload_plan(F, work + L.planf, staging_f, st);
+    if (r != KPM_OK) return r;
+    F.plan.err = flag;
+    F.plan.states = reinterpret_cast<uint32_t*>(work + L.statesf);
+    if (F.plan.row_ld || F.plan.block) KPM_HIP(fill_states(F.plan, st));
+    Dfw = &F.plan;
+    part_fw = reinterpret_cast<double*>(work + L.partf);
+  }
   const int K = L.K, C = L.C;
   const size_t elt = D.fp32 ? 4 : 8;
   const size_t slot_bytes = (size_t)D.slot_stride * elt;
@@ -1547,9 +1588,9 @@ int run_vjp(const kpm_problem* p, int n, const kpm_params& q, const double* h_ab
   }
   KPM_HIP(launch_init(D, seg, 1, q.vec_kind, q.seed, norms, part, st));
   KPM_HIP(launch_reduce(D, part, alpha0, nullptr, st));
-  KPM_HIP(launch_step_slots(D, seg, part, 0, 1, 1, 1, st));
+  KPM_HIP(launch_step_slots(*Dfw, seg, part_fw, 0, 1, 1, 1, st));
   for (int j = 0; j < K; ++j) {
-    if (j > 0) KPM_HIP(launch_step_slots(D, seg, part, j & 1, (j + 1) & 1, (j + 1) & 1, 0, st));
+    if (j > 0) KPM_HIP(launch_step_slots(*Dfw, seg, part_fw, j & 1, (j + 1) & 1, (j + 1) & 1, 0, st));
     if (j % C == 0)
       KPM_HIP(hipMemcpyAsync(ckpt + (size_t)(j / C) * 2 * slot_bytes, seg, 2 * slot_bytes,
                              hipMemcpyDeviceToDevice, st));
@@ -1580,7 +1621,7 @@ int run_vjp(const kpm_problem* p, int n, const kpm_params& q, const double* h_ab
                            hipMemcpyDeviceToDevice, st));
     const int top = std::min(j1 + 1, K);   // highest v index needed
     for (int t = 1; j0 + t + 1 <= top; ++t)
-      KPM_HIP(launch_step_slots(D, seg, part, t, t - 1, t + 1, 0, st));
+      KPM_HIP(launch_step_slots(*Dfw, seg, part_fw, t, t - 1, t + 1, 0, st));
     for (int nn = j1; nn >= j0 + 1; --nn) {
       AdjArgs aa{};
       aa.vseg = seg;
