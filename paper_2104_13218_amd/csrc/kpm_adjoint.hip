@@ -68,10 +68,13 @@ hipError_t launch_doubling_vjp(const DoublingVjpArgs& a, hipStream_t st) {
 }
 
 // One reverse step (or, with dots_only, the final <w_1, h_b v_0> pass).
-// One thread per basis state with all LD columns of its block; the workgroup
-// has sub_rows threads.
+// Q = LD / CPT consecutive threads share a basis state, each with CPT of its
+// block's LD columns (row dots are summed across the Q lanes); a sub-tile has
+// sub_rows states and the workgroup sub_rows * Q threads.
 template <typename T, int LD>
 __global__ __launch_bounds__(kThreads) void adjoint_kernel(const AdjArgs a) {
+  constexpr int CPT = LD < 4 ? LD : 4;
+  constexpr int Q = LD / CPT;
   extern __shared__ __align__(16) unsigned char smem[];
   const int nthr = blockDim.x;
   int tile = blockIdx.x;
@@ -118,32 +121,38 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(const AdjArgs a) {
   double bacc = 0.0;   // thread b < nb: this tile's sum for bond b
   const int64_t tile_row0 = a.tile_row0[tile];
   const int tile_rows = a.tile_nrows[tile];
+  const int t = threadIdx.x;
+  const int rr = t / Q, cq = t - rr * Q;   // state of the sub-tile, column group
+  const int c0 = cq * CPT;
   for (int st = 0; st * SR < tile_rows; ++st) {
     const int64_t row0 = tile_row0 + (int64_t)st * SR;
     const int nrows = min(SR, tile_rows - st * SR);
-    const int t = threadIdx.x;
-    if (t < nrows) {
-      const int64_t rho = row0 + t;
+    if (rr < nrows) {
+      const int64_t rho = row0 + rr;
       const uint32_t s = unrank((uint32_t)rho, P.n_sites, P.n_up, s_binom);
-      double w[LD], v[LD], acc[LD];
+      double w[CPT], v[CPT], acc[CPT];
 #pragma unroll
-      for (int c = 0; c < LD; ++c) {
-        w[c] = (double)Wx[rho * LD + c];
-        v[c] = (double)Vn[rho * LD + c];
+      for (int c = 0; c < CPT; ++c) {
+        w[c] = (double)Wx[rho * LD + c0 + c];
+        v[c] = (double)Vn[rho * LD + c0 + c];
       }
+      // <w, v> of the state over all LD columns (the Q lanes of a state are
+      // consecutive and take the same branches)
       double self = 0.0;
 #pragma unroll
-      for (int c = 0; c < LD; ++c) self = fma(w[c], v[c], self);
+      for (int c = 0; c < CPT; ++c) self = fma(w[c], v[c], self);
+#pragma unroll
+      for (int off = 1; off < Q; off <<= 1) self += __shfl_xor(self, off, 64);
       double dg = P.shift;
       for (int b = 0; b < nb; ++b) {
         const uint32_t m = s_mask[b];
         const uint32_t x = s & m;
         const bool differ = !(x == 0u || x == m);
         dg += differ ? -s_zz[b] : s_zz[b];
-        s_contrib[t * nb + b] = differ ? -0.25 * self : 0.25 * self;
+        if (cq == 0) s_contrib[rr * nb + b] = differ ? -0.25 * self : 0.25 * self;
       }
 #pragma unroll
-      for (int c = 0; c < LD; ++c) acc[c] = dg * w[c];
+      for (int c = 0; c < CPT; ++c) acc[c] = dg * w[c];
       for (int b = 0; b < nb; ++b) {
         const uint32_t m = s_mask[b];
         const uint32_t x = s & m;
@@ -153,25 +162,28 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(const AdjArgs a) {
           if (a.err) atomicOr(a.err, 2);
           r = (uint32_t)rho;
         }
-        const T* g = Wx + (int64_t)r * LD;
+        const T* g = Wx + (int64_t)r * LD + c0;
         const double cf = s_off[b];
         double pk = 0.0;
 #pragma unroll
-        for (int c = 0; c < LD; ++c) {
+        for (int c = 0; c < CPT; ++c) {
           const double gv = (double)g[c];
           acc[c] = fma(cf, gv, acc[c]);
           pk = fma(gv, v[c], pk);
         }
-        s_contrib[t * nb + b] += 0.5 * pk;
+#pragma unroll
+        for (int off = 1; off < Q; off <<= 1) pk += __shfl_xor(pk, off, 64);
+        if (cq == 0) s_contrib[rr * nb + b] += 0.5 * pk;
       }
       if (!a.dots_only) {
 #pragma unroll
-        for (int c = 0; c < LD; ++c) {
-          double g = 2.0 * a.abar_n[co + c] * v[c];
-          if (Vp1) g = fma(a.bbar_n[co + c], (double)Vp1[rho * LD + c], g);
-          if (Vm1) g = fma(a.bbar_nm1[co + c], (double)Vm1[rho * LD + c], g);
-          const double wn = g + 2.0 * acc[c] - (double)Wy[rho * LD + c];
-          Wy[rho * LD + c] = (T)wn;
+        for (int c = 0; c < CPT; ++c) {
+          const int col = c0 + c;
+          double g = 2.0 * a.abar_n[co + col] * v[c];
+          if (Vp1) g = fma(a.bbar_n[co + col], (double)Vp1[rho * LD + col], g);
+          if (Vm1) g = fma(a.bbar_nm1[co + col], (double)Vm1[rho * LD + col], g);
+          const double wn = g + 2.0 * acc[c] - (double)Wy[rho * LD + col];
+          Wy[rho * LD + col] = (T)wn;
         }
       }
     }
@@ -228,11 +240,12 @@ hipError_t launch_adjoint(const DevicePlan& p, AdjArgs a, int ld, hipStream_t st
   a.xcd_remap = p.xcd_remap;
   a.slot_stride = p.slot_stride;
   a.err = p.err;
-  // every bond needs a thread for the per-tile reduction
-  if (p.lds_bonds > p.sub_rows) return hipErrorInvalidValue;
+  // Q threads per state (adjoint_kernel); every bond needs a thread for the
+  // per-tile reduction
+  const int thr = p.sub_rows * adjoint_lanes(ld);
+  if (p.lds_bonds > thr || thr > kThreads) return hipErrorInvalidValue;
   const size_t lds = adjoint_lds_bytes(p);
   const int grid = p.grid_tiles;
-  const int thr = p.sub_rows;
 #define KPM_ADJ_CASE(L)                                                         \
   case L:                                                                       \
     return p.fp32 ? launch_adj_t<float, L>(a, lds, grid, thr, st)               \

@@ -515,10 +515,14 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   }
   while (!spin && step_lds_bytes(D) > lds_soft && D.sub_rows > 64) D.sub_rows >>= 1;
   while (!spin && step_lds_bytes(D) > lds_hard && D.sub_rows > 32) D.sub_rows >>= 1;
-  if (s.adjoint)
+  if (s.adjoint) {
+    // adjoint_kernel runs adjoint_lanes(ld) threads per state, <= kThreads per workgroup
+    while (D.sub_rows * adjoint_lanes(adj_ld) > kThreads) D.sub_rows >>= 1;
     while (adjoint_lds_bytes(D) > lds_hard && D.sub_rows > 32) D.sub_rows >>= 1;
+  }
   if (!spin && step_lds_bytes(D) > lds_hard) return KPM_EINVAL;
-  if (s.adjoint && (adjoint_lds_bytes(D) > lds_hard || max_bonds > D.sub_rows)) return KPM_EINVAL;
+  if (s.adjoint && (adjoint_lds_bytes(D) > lds_hard || max_bonds > D.sub_rows * adjoint_lanes(adj_ld)))
+    return KPM_EINVAL;
   D.row_ld = row_ld;
   if (row_ld && row_lds_bytes(D) > lds_hard) D.row_ld = row_ld = 0;
   if (row_ld) D.sub_rows = kThreads;

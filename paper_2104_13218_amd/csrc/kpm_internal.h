@@ -355,6 +355,10 @@ struct DoublingVjpArgs {
   int32_t total_cols, M, K, cols_per_vec, R;   // R = 0: complete basis
 };
 
+// Threads per basis state in adjoint_kernel for a block of ld columns (each
+// takes min(ld, 4) of them).
+__host__ __device__ inline int adjoint_lanes(int ld) { return ld / (ld < 4 ? ld : 4); }
+
 struct AdjArgs {
   const ProbDev* probs;
   const UnitDev* units;
