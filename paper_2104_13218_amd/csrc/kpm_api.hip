@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -1460,7 +1461,8 @@ int resolve_scale(const kpm_problem* p, int n, const kpm_params& q, unsigned cha
 // ------------------------------------------------------------- adjoint driver
 
 struct VjpLayout {
-  size_t plan, seg, w, ckpt, part, norms, alpha0, abar, bbar, bd, flag, planf, statesf, partf, total;
+  size_t plan, seg, w, ckpt, part, norms, alpha0, abar, bbar, bd, flag, planf, statesf, partf, partf2,
+      falpha, fbeta, total;
   int nck, C, K;
 };
 
@@ -1512,11 +1514,16 @@ VjpLayout vjp_layout(const Planned& P, const Planned* F, int M, int ckpt_every) 
   L.bbar = put((size_t)(K + 1) * TC * 8);
   L.bd = put((size_t)P.plan.bd_len * 8);
   L.flag = put(256);
+  // the forward steps' dots (when the forward pass also gives the moments)
+  const Planned& Q = F ? *F : P;
   if (F) {
     L.planf = put(F->bytes);
     L.statesf = put((size_t)F->plan.n_states * 4);
     L.partf = put((size_t)F->plan.part_len * 8);
   }
+  L.partf2 = put((size_t)Q.plan.part_len * 8);
+  L.falpha = put((size_t)(K + 1) * Q.plan.total_cols * 8);
+  L.fbeta = put((size_t)K * Q.plan.total_cols * 8);
   L.total = o;
   return L;
 }
@@ -1536,9 +1543,13 @@ size_t vjp_workspace(const kpm_problem* p, int n, const kpm_params& q, int ckpt_
 
 // Forward recursion with checkpoints, then the reverse sweep segment by
 // segment (recomputing each segment's v_n from its checkpoint).
+// With d_mu, the forward pass also reduces its dots into the moments
+// (doubling identities and estimator of Eq. (7)) and `between` runs after it,
+// before d_dmu is read: the loss gradient may then be formed from those
+// moments.  Returns KPM_EBOUNDS when |mu_n| > mu_0 there.
 int run_vjp(const kpm_problem* p, int n, const kpm_params& q, const double* h_ab,
             const double* d_dmu, int ckpt_every, double* d_dJ, unsigned char* work,
-            hipStream_t st) {
+            hipStream_t st, double* d_mu = nullptr, const std::function<int()>& between = {}) {
   std::vector<double> a(n), b(n);
   for (int i = 0; i < n; ++i) {
     a[i] = h_ab[2 * i];
@@ -1592,12 +1603,54 @@ int run_vjp(const kpm_problem* p, int n, const kpm_params& q, const double* h_ab
   }
   KPM_HIP(launch_init(D, seg, 1, q.vec_kind, q.seed, norms, part, st));
   KPM_HIP(launch_reduce(D, part, alpha0, nullptr, st));
-  KPM_HIP(launch_step_slots(*Dfw, seg, part_fw, 0, 1, 1, 1, st));
-  for (int j = 0; j < K; ++j) {
-    if (j > 0) KPM_HIP(launch_step_slots(*Dfw, seg, part_fw, j & 1, (j + 1) & 1, (j + 1) & 1, 0, st));
-    if (j % C == 0)
-      KPM_HIP(hipMemcpyAsync(ckpt + (size_t)(j / C) * 2 * slot_bytes, seg, 2 * slot_bytes,
-                             hipMemcpyDeviceToDevice, st));
+  if (!d_mu) {
+    KPM_HIP(launch_step_slots(*Dfw, seg, part_fw, 0, 1, 1, 1, st));
+    for (int j = 0; j < K; ++j) {
+      if (j > 0) KPM_HIP(launch_step_slots(*Dfw, seg, part_fw, j & 1, (j + 1) & 1, (j + 1) & 1, 0, st));
+      if (j % C == 0)
+        KPM_HIP(hipMemcpyAsync(ckpt + (size_t)(j / C) * 2 * slot_bytes, seg, 2 * slot_bytes,
+                               hipMemcpyDeviceToDevice, st));
+    }
+  } else {
+    // the same steps with their dots reduced one launch later (as for the
+    // moments alone), then the moments
+    const int TF = Dfw->total_cols;
+    double* pf[2] = {part_fw, reinterpret_cast<double*>(work + L.partf2)};
+    double* fal = reinterpret_cast<double*>(work + L.falpha);
+    double* fbe = reinterpret_cast<double*>(work + L.fbeta);
+    KPM_HIP(hipMemcpyAsync(fal, alpha0, (size_t)TF * 8, hipMemcpyDeviceToDevice, st));   // <v_0, v_0>
+    KPM_HIP(launch_step(*Dfw, seg, pf[0], nullptr, 0, fal, fbe, nullptr, 0, 0, 1, st));
+    for (int j = 0; j < K; ++j) {
+      if (j > 0)
+        KPM_HIP(launch_step(*Dfw, seg, pf[j & 1], pf[(j - 1) & 1], 2 * TF, fal, fbe, nullptr, j, j & 1, 0, st));
+      if (j % C == 0)
+        KPM_HIP(hipMemcpyAsync(ckpt + (size_t)(j / C) * 2 * slot_bytes, seg, 2 * slot_bytes,
+                               hipMemcpyDeviceToDevice, st));
+    }
+    KPM_HIP(launch_reduce(*Dfw, pf[(K - 1) & 1], fal + (size_t)K * TF, fbe + (size_t)(K - 1) * TF, st));
+    FinalArgs fa{};
+    fa.probs = Dfw->probs;
+    fa.units = Dfw->units;
+    fa.prob_unit0 = Dfw->prob_unit0;
+    fa.alpha = fal;
+    fa.beta = fbe;
+    fa.mu = d_mu;
+    fa.flag = flag;
+    fa.n_probs = Dfw->n_probs;
+    fa.M = q.M;
+    fa.total_cols = TF;
+    fa.cols_per_vec = cols_per_vec(q.vec_kind);
+    fa.R = q.vec_kind == KPM_VEC_BASIS ? 0 : q.R;
+    KPM_HIP(launch_finalize(fa, st));
+    int h_flag = 0;
+    KPM_HIP(hipMemcpyAsync(&h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    KPM_HIP(hipStreamSynchronize(st));
+    if (h_flag & 2) return KPM_EDEVICE;
+    if (h_flag & 1) return KPM_EBOUNDS;
+    if (between) {
+      const int rb = between();
+      if (rb != KPM_OK) return rb;
+    }
   }
   // Each checkpoint m holds v_{mC} in slot (mC)&1 = 0 (C is even) and v_{mC+1} in slot 1.
   DoublingVjpArgs dv{};
@@ -2246,19 +2299,33 @@ int kpm_thermo_grad(const kpm_problem* p, int32_t n, const kpm_params* q, int32_
   double* ab = reinterpret_cast<double*>(t8 + 2 * align_up((size_t)n * q->M * 8));
   double* outs = reinterpret_cast<double*>(t8 + 2 * align_up((size_t)n * q->M * 8) + align_up((size_t)n * 16));
   const size_t ms = align_up(m * 8) / 8;
-  r = chebyshev_moments(p, n, q, mu, ab, work, need, stream);
+  // bounds and (a, b) as chebyshev_moments resolves them
+  Planned P0;
+  r = make_plan(p, n, shape_of(*q), nullptr, nullptr, P0);
   if (r != KPM_OK) return r;
-  r = kpm_thermo_vjp(mu, ab, p, n, q->M, kernel, n_nodes, d_T, n_T, d_wC, d_wchi, lam, stream);
+  const MomLayout L0 = moments_layout(P0, n_steps(q->M), 0);
+  std::vector<double> a, b;
+  r = resolve_scale(p, n, *q, work + L0.lz, st, a, b);
   if (r != KPM_OK) return r;
-  r = kpm_thermo(mu, ab, p, n, q->M, kernel, n_nodes, d_T, n_T, outs, outs + ms, outs + 2 * ms,
-                 outs + 3 * ms, nullptr, stream);
-  if (r != KPM_OK) return r;
-  KPM_HIP(launch_loss(outs + 2 * ms, outs + 3 * ms, d_wC, d_wchi, (int)m, d_L, st));
-  if (d_ab) KPM_HIP(hipMemcpyAsync(d_ab, ab, (size_t)n * 16, hipMemcpyDeviceToDevice, st));
   std::vector<double> h_ab(2 * n);
-  KPM_HIP(hipMemcpyAsync(h_ab.data(), ab, h_ab.size() * 8, hipMemcpyDeviceToHost, st));
-  KPM_HIP(hipStreamSynchronize(st));
-  return run_vjp(p, n, *q, h_ab.data(), lam, ckpt_every, d_dJ, work, st);
+  for (int i = 0; i < n; ++i) {
+    h_ab[2 * i] = a[i];
+    h_ab[2 * i + 1] = b[i];
+  }
+  KPM_HIP(hipMemcpyAsync(ab, h_ab.data(), h_ab.size() * 8, hipMemcpyHostToDevice, st));
+  if (d_ab) KPM_HIP(hipMemcpyAsync(d_ab, ab, (size_t)n * 16, hipMemcpyDeviceToDevice, st));
+  // the adjoint's checkpointed forward pass gives the moments; between it and
+  // the reverse sweep: dL/dmu, and L from the thermodynamics
+  auto between = [&]() -> int {
+    int rr = kpm_thermo_vjp(mu, ab, p, n, q->M, kernel, n_nodes, d_T, n_T, d_wC, d_wchi, lam, stream);
+    if (rr != KPM_OK) return rr;
+    rr = kpm_thermo(mu, ab, p, n, q->M, kernel, n_nodes, d_T, n_T, outs, outs + ms, outs + 2 * ms,
+                    outs + 3 * ms, nullptr, stream);
+    if (rr != KPM_OK) return rr;
+    KPM_HIP(launch_loss(outs + 2 * ms, outs + 3 * ms, d_wC, d_wchi, (int)m, d_L, st));
+    return KPM_OK;
+  };
+  return run_vjp(p, n, *q, h_ab.data(), lam, ckpt_every, d_dJ, work, st, mu, between);
 }
 
 size_t kpm_ftlm_workspace_size(const kpm_problem* p, int32_t n, const kpm_params* q) {
