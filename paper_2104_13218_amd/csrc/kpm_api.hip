@@ -1839,7 +1839,7 @@ int thermo_forward(const double* d_mu, const double* d_ab, const kpm_problem* p,
 // ---------------------------------------------- finite-temperature Lanczos
 
 struct FtlmLayout {
-  size_t plan, vec, part, dots, b2, zero, norm, err, states, ritz, escr, weight, len, total;
+  size_t plan, vec, part, dots, b2, norm, err, states, ritz, escr, weight, len, total;
 };
 
 // Every real column runs its own Lanczos recursion; columns are batched in
@@ -1872,7 +1872,6 @@ FtlmLayout ftlm_layout(const Planned& P, int steps) {
   L.part = put((size_t)P.plan.part_len * 8);
   L.dots = put((size_t)steps * TC * 8);
   L.b2 = put((size_t)steps * TC * 8);
-  L.zero = put(TC * 8);
   L.norm = put(TC * 8);
   L.err = put(256);
   L.states = put((size_t)P.plan.n_states * 4);
@@ -2375,11 +2374,9 @@ int kpm_ftlm(const kpm_problem* p, int32_t n, const kpm_params* q, const double*
   double* part = reinterpret_cast<double*>(work + L.part);
   double* dots = reinterpret_cast<double*>(work + L.dots);
   double* b2 = reinterpret_cast<double*>(work + L.b2);
-  double* zero = reinterpret_cast<double*>(work + L.zero);
   double* norm = reinterpret_cast<double*>(work + L.norm);
   const int TC = D.total_cols;
   KPM_HIP(hipMemsetAsync(vec, 0, (size_t)D.vec_elems * 8, st));
-  KPM_HIP(hipMemsetAsync(zero, 0, (size_t)TC * 8, st));
   // unit-norm start columns (the random vectors of Eq. (7)), |column|^2 kept
   KPM_HIP(launch_init(D, vec, 0, q->vec_kind, q->seed, nullptr, part, st));
   KPM_HIP(launch_reduce(D, part, norm, nullptr, st));
