@@ -110,3 +110,26 @@ def test_exact_spectra_arguments_on_host(kpmlib):
     assert small >= 8 * (66**2 + 12**2 + 1) and big >= 8 * sum(d * d for d in (924, 792, 495, 220, 66, 12, 1))
     assert lib.kpm_sector_eigenvalues(ps.arr, len(ps), 2000, None, None, 0, None) == kpmlib.KPM_EINVAL
     assert lib.kpm_sector_eigenvalues(ps.arr, len(ps), 100, None, None, 0, None) == kpmlib.KPM_EINVAL
+
+
+def test_empty_and_spin_arguments_on_host(kpmlib):
+    """No problems, and spin-s problems outside the supported range, are
+    refused before any device work; valid spin-s problems size a workspace."""
+    import workloads as W
+    lib = kpmlib.load()
+    E = kpmlib.KPM_EINVAL
+    q = kpmlib.make_params(M=16, R=2)
+    ps = kpmlib.ProblemSet(W.sectors(W.ring(6)))
+    assert lib.chebyshev_moments_workspace_size(ps.arr, 0, ctypes.byref(q)) == 0
+    assert lib.chebyshev_moments(ps.arr, 0, ctypes.byref(q), None, None, None, 0, None) == E
+    spin = kpmlib.ProblemSet(W.spin_sectors(W.ring(4), 5))
+    assert lib.chebyshev_moments_workspace_size(spin.arr, len(spin), ctypes.byref(q)) > 0
+    for field, value in (("two_s", 8), ("two_s", -1), ("reserved", 1)):
+        bad = kpmlib.ProblemSet(W.spin_sectors(W.ring(4), 5))
+        setattr(bad.arr[0], field, value)
+        assert lib.chebyshev_moments_workspace_size(bad.arr, len(bad), ctypes.byref(q)) == 0, field
+        assert lib.chebyshev_moments(bad.arr, len(bad), ctypes.byref(q), None, None, None, 0, None) == E
+    big = kpmlib.ProblemSet([W.SpinSector(W.ring(17), 2, 17)])          # spin 1, N = 17 > 16
+    assert lib.chebyshev_moments_workspace_size(big.arr, 1, ctypes.byref(q)) == 0
+    low = kpmlib.ProblemSet([W.SpinSector(W.ring(4), 5, 9)])            # S^z = 9 - 10 < 0
+    assert lib.chebyshev_moments_workspace_size(low.arr, 1, ctypes.byref(q)) == 0
