@@ -297,8 +297,29 @@ int chebyshev_moments_vjp(const kpm_problem* p, int32_t n, const kpm_params* q,
                           const double* d_ab, const double* d_dmu, int32_t ckpt_every,
                           double* d_dJ, void* d_work, size_t work_bytes, void* stream);
 
-/* Loss and gradient in one call: moments (forward), thermodynamics, their
- * derivative and the recursion adjoint.  d_T [n_T], d_wC, d_wchi
+/* The gradient in two calls, for callers that form dL/dmu themselves between
+ * them (an autograd graph): chebyshev_moments_ckpt runs the recursion once,
+ * writes the moments d_mu (device [n][M]) and the (a, b) it used d_ab (device
+ * [n][2]; bounds as chebyshev_moments resolves them), and keeps the
+ * recursion's checkpoints (every ckpt_every steps, even >= 2) in d_work;
+ * chebyshev_moments_vjp_resume then runs only the reverse sweep of
+ * chebyshev_moments_vjp from them.  d_work (caller-owned, both calls,
+ * chebyshev_moments_ckpt_workspace_size bytes; NULL is refused) must hold
+ * what the forward call left: the same p, n, q and ckpt_every, and no other
+ * call on that memory in between.  Moments equal chebyshev_moments' to
+ * rounding (the recursion may run on another kernel).
+ * Errors: KPM_EINVAL, KPM_EWORKSPACE, KPM_EBOUNDS (forward), KPM_EDEVICE. */
+size_t chebyshev_moments_ckpt_workspace_size(const kpm_problem* p, int32_t n, const kpm_params* q,
+                                             int32_t ckpt_every);
+int chebyshev_moments_ckpt(const kpm_problem* p, int32_t n, const kpm_params* q, int32_t ckpt_every,
+                           double* d_mu, double* d_ab, void* d_work, size_t work_bytes, void* stream);
+int chebyshev_moments_vjp_resume(const kpm_problem* p, int32_t n, const kpm_params* q,
+                                 const double* d_ab, const double* d_dmu, int32_t ckpt_every,
+                                 double* d_dJ, void* d_work, size_t work_bytes, void* stream);
+
+/* Loss and gradient in one call: moments, thermodynamics, their derivative
+ * and the recursion adjoint, with the recursion run forward once (its
+ * checkpointed pass gives the moments).  d_T [n_T], d_wC, d_wchi
  * [n_clusters][n_T]: device.  Outputs: d_L (device double [1]), d_dJ as in
  * chebyshev_moments_vjp, d_ab (device [n][2], may be NULL). */
 int kpm_thermo_grad(const kpm_problem* p, int32_t n, const kpm_params* q, int32_t kernel,

@@ -1546,10 +1546,15 @@ size_t vjp_workspace(const kpm_problem* p, int n, const kpm_params& q, int ckpt_
 // With d_mu, the forward pass also reduces its dots into the moments
 // (doubling identities and estimator of Eq. (7)) and `between` runs after it,
 // before d_dmu is read: the loss gradient may then be formed from those
-// moments.  Returns KPM_EBOUNDS when |mu_n| > mu_0 there.
+// moments.  Returns KPM_EBOUNDS when |mu_n| > mu_0 there.  `phases` selects
+// the forward pass (kVjpForward: v_0, the steps and their checkpoints), the
+// reverse sweep (kVjpReverse, which reads what a forward pass with the same
+// arguments left in `work`), or both.
+constexpr int kVjpForward = 1, kVjpReverse = 2;
 int run_vjp(const kpm_problem* p, int n, const kpm_params& q, const double* h_ab,
             const double* d_dmu, int ckpt_every, double* d_dJ, unsigned char* work,
-            hipStream_t st, double* d_mu = nullptr, const std::function<int()>& between = {}) {
+            hipStream_t st, double* d_mu = nullptr, const std::function<int()>& between = {},
+            int phases = kVjpForward | kVjpReverse) {
   std::vector<double> a(n), b(n);
   for (int i = 0; i < n; ++i) {
     a[i] = h_ab[2 * i];
@@ -1597,6 +1602,7 @@ int run_vjp(const kpm_problem* p, int n, const kpm_params& q, const double* h_ab
   for (auto& u : P.units) ld = std::max(ld, u.ld);
 
   // forward: v_0 (and its norms), steps with a checkpoint of (v_j, v_{j+1}) at j = 0, C, 2C, ...
+  if (phases & kVjpForward) {
   if (q.vec_kind == KPM_VEC_GAUSSIAN || q.vec_kind == KPM_VEC_COMPLEX_GAUSSIAN) {
     KPM_HIP(launch_init(D, seg, 0, q.vec_kind, q.seed, nullptr, part, st));
     KPM_HIP(launch_reduce(D, part, norms, nullptr, st));
@@ -1651,6 +1657,13 @@ int run_vjp(const kpm_problem* p, int n, const kpm_params& q, const double* h_ab
       const int rb = between();
       if (rb != KPM_OK) return rb;
     }
+  }
+  }
+  if (!(phases & kVjpReverse)) {
+    int h_flag = 0;
+    KPM_HIP(hipMemcpyAsync(&h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    KPM_HIP(hipStreamSynchronize(st));
+    return h_flag ? KPM_EDEVICE : KPM_OK;
   }
   // Each checkpoint m holds v_{mC} in slot (mC)&1 = 0 (C is even) and v_{mC+1} in slot 1.
   DoublingVjpArgs dv{};
@@ -2258,6 +2271,60 @@ int chebyshev_moments_vjp(const kpm_problem* p, int32_t n, const kpm_params* q,
   KPM_HIP(hipMemcpyAsync(h_ab.data(), d_ab, h_ab.size() * 8, hipMemcpyDeviceToHost, st));
   KPM_HIP(hipStreamSynchronize(st));
   return run_vjp(p, n, *q, h_ab.data(), d_dmu, ckpt_every, d_dJ, work, st);
+}
+
+size_t chebyshev_moments_ckpt_workspace_size(const kpm_problem* p, int32_t n, const kpm_params* q,
+                                             int32_t ckpt_every) {
+  if (check_problems(p, n) != KPM_OK || !q || check_params(*q) != KPM_OK || ckpt_every < 2) return 0;
+  const size_t m = moments_workspace(p, n, *q);
+  const size_t v = vjp_workspace(p, n, *q, ckpt_every);
+  return (m && v) ? std::max(m, v) : 0;
+}
+
+int chebyshev_moments_ckpt(const kpm_problem* p, int32_t n, const kpm_params* q, int32_t ckpt_every,
+                           double* d_mu, double* d_ab, void* d_work, size_t work_bytes, void* stream) {
+  int r = check_problems(p, n);
+  if (r != KPM_OK) return r;
+  if (!q || check_params(*q) != KPM_OK || !d_mu || !d_ab || !d_work || ckpt_every < 2) return KPM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StreamSync guard{st};
+  const size_t need = chebyshev_moments_ckpt_workspace_size(p, n, q, ckpt_every);
+  if (need == 0) return KPM_EINVAL;
+  if (work_bytes < need) return KPM_EWORKSPACE;
+  unsigned char* work = static_cast<unsigned char*>(d_work);
+  Planned P0;
+  r = make_plan(p, n, shape_of(*q), nullptr, nullptr, P0);
+  if (r != KPM_OK) return r;
+  const MomLayout L0 = moments_layout(P0, n_steps(q->M), 0);
+  std::vector<double> a, b;
+  r = resolve_scale(p, n, *q, work + L0.lz, st, a, b);
+  if (r != KPM_OK) return r;
+  std::vector<double> h_ab(2 * n);
+  for (int i = 0; i < n; ++i) {
+    h_ab[2 * i] = a[i];
+    h_ab[2 * i + 1] = b[i];
+  }
+  KPM_HIP(hipMemcpyAsync(d_ab, h_ab.data(), h_ab.size() * 8, hipMemcpyHostToDevice, st));
+  return run_vjp(p, n, *q, h_ab.data(), nullptr, ckpt_every, nullptr, work, st, d_mu, {}, kVjpForward);
+}
+
+int chebyshev_moments_vjp_resume(const kpm_problem* p, int32_t n, const kpm_params* q,
+                                 const double* d_ab, const double* d_dmu, int32_t ckpt_every,
+                                 double* d_dJ, void* d_work, size_t work_bytes, void* stream) {
+  int r = check_problems(p, n);
+  if (r != KPM_OK) return r;
+  if (!q || check_params(*q) != KPM_OK || !d_ab || !d_dmu || !d_dJ || !d_work || ckpt_every < 2)
+    return KPM_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StreamSync guard{st};
+  const size_t need = chebyshev_moments_ckpt_workspace_size(p, n, q, ckpt_every);
+  if (need == 0) return KPM_EINVAL;
+  if (work_bytes < need) return KPM_EWORKSPACE;
+  std::vector<double> h_ab(2 * n);
+  KPM_HIP(hipMemcpyAsync(h_ab.data(), d_ab, h_ab.size() * 8, hipMemcpyDeviceToHost, st));
+  KPM_HIP(hipStreamSynchronize(st));
+  return run_vjp(p, n, *q, h_ab.data(), d_dmu, ckpt_every, d_dJ, static_cast<unsigned char*>(d_work), st,
+                 nullptr, {}, kVjpReverse);
 }
 
 int kpm_thermo_grad(const kpm_problem* p, int32_t n, const kpm_params* q, int32_t kernel,

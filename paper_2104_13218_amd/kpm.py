@@ -86,6 +86,12 @@ _SIGS = {
                                                         c_int32]),
     "chebyshev_moments_vjp": (c_int32, [POINTER(Problem), c_int32, POINTER(Params), c_void_p, c_void_p,
                                         c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "chebyshev_moments_ckpt_workspace_size": (c_size_t, [POINTER(Problem), c_int32, POINTER(Params),
+                                                         c_int32]),
+    "chebyshev_moments_ckpt": (c_int32, [POINTER(Problem), c_int32, POINTER(Params), c_int32, c_void_p,
+                                         c_void_p, c_void_p, c_size_t, c_void_p]),
+    "chebyshev_moments_vjp_resume": (c_int32, [POINTER(Problem), c_int32, POINTER(Params), c_void_p,
+                                               c_void_p, c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
     "kpm_thermo_grad": (c_int32, [POINTER(Problem), c_int32, POINTER(Params), c_int32, c_int32,
                                   c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_size_t, c_void_p]),
@@ -384,6 +390,37 @@ def moments_vjp(sectors, M, R, ab, dmu, vec_kind="rademacher", precision="fp64",
     return dJ[:nb]
 
 
+def moments_ckpt(sectors, M, R=1, vec_kind="rademacher", precision="fp64", eps=0.025, seed=0,
+                 col_block=0, ckpt_every=64, bounds=None, problems=None, stream=None):
+    """Moments mu [n, M] and (a, b) [n, 2] as chebyshev_moments, with the
+    recursion's checkpoints kept in the returned workspace for moments_vjp_resume."""
+    ps = problems or ProblemSet(sectors, bounds)
+    q = make_params(M, R, vec_kind, precision, eps, seed, col_block)
+    lib = load()
+    nbytes = lib.chebyshev_moments_ckpt_workspace_size(ps.arr, len(ps), ctypes.byref(q), ckpt_every)
+    if nbytes == 0:
+        raise KPMError(KPM_EINVAL, "chebyshev_moments_ckpt_workspace_size")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    mu = torch.empty((len(ps), M), dtype=torch.float64, device="cuda")
+    ab = torch.empty((len(ps), 2), dtype=torch.float64, device="cuda")
+    _check(lib.chebyshev_moments_ckpt(ps.arr, len(ps), ctypes.byref(q), ckpt_every, _ptr(mu), _ptr(ab),
+                                      _ptr(ws), nbytes, _stream(stream)), "chebyshev_moments_ckpt")
+    return mu, ab, ws
+
+
+def moments_vjp_resume(ps, M, R, ab, dmu, ws, vec_kind="rademacher", precision="fp64", eps=0.025, seed=0,
+                       col_block=0, ckpt_every=64, stream=None):
+    """dL/dJ from the checkpoints moments_ckpt left in ws (same arguments)."""
+    q = make_params(M, R, vec_kind, precision, eps, seed, col_block)
+    nb = sum(s.cluster.n_bonds for s in ps.sectors)
+    dJ = torch.empty(max(nb, 1), dtype=torch.float64, device="cuda")
+    dmu = dmu.to(device="cuda", dtype=torch.float64).contiguous()
+    _check(load().chebyshev_moments_vjp_resume(ps.arr, len(ps), ctypes.byref(q), _ptr(ab.contiguous()),
+                                               _ptr(dmu), ckpt_every, _ptr(dJ), _ptr(ws), ws.numel(),
+                                               _stream(stream)), "chebyshev_moments_vjp_resume")
+    return dJ[:nb]
+
+
 def thermo_grad(sectors, M, R, T, wC, wchi, vec_kind="rademacher", precision="fp64", eps=0.025, seed=0,
                 col_block=0, kernel="none", n_nodes=0, ckpt_every=64, bounds=None, problems=None,
                 stream=None):
@@ -407,7 +444,9 @@ class KPMMoments(torch.autograd.Function):
     """mu, ab = KPMMoments.apply(J, cluster, n_ups, M, R, vec_kind, precision, eps, seed, col_block,
     bounds, ckpt_every): Chebyshev moments of the sectors n_ups of one cluster whose
     couplings are J (float64 tensor [n_bonds]); backward gives dL/dJ through the
-    recursion adjoint with the rescaling held at the forward's values."""
+    recursion adjoint with the rescaling held at the forward's values.  The
+    forward keeps the recursion's checkpoints (one workspace held until
+    backward), so the backward runs only the reverse sweep."""
 
     @staticmethod
     def forward(ctx, J, cluster, n_ups, M, R, vec_kind="rademacher", precision="fp64", eps=0.025, seed=0,
@@ -416,8 +455,8 @@ class KPMMoments(torch.autograd.Function):
         cl = cluster.with_J(J.detach().to("cpu", torch.float64).numpy())
         secs = [W.Sector(cl, k, 0) for k in n_ups]
         ps = ProblemSet(secs, bounds)
-        mu, ab = chebyshev_moments(None, M, R, vec_kind, precision, eps, seed, col_block, problems=ps)
-        ctx.ps, ctx.ab = ps, ab
+        mu, ab, ws = moments_ckpt(None, M, R, vec_kind, precision, eps, seed, col_block, ckpt_every, problems=ps)
+        ctx.ps, ctx.ab, ctx.ws = ps, ab, ws
         ctx.args = (M, R, vec_kind, precision, eps, seed, col_block, ckpt_every)
         ctx.n_bonds, ctx.J_device = cl.n_bonds, J.device
         ctx.mark_non_differentiable(ab)
@@ -426,8 +465,9 @@ class KPMMoments(torch.autograd.Function):
     @staticmethod
     def backward(ctx, dmu, dab):
         M, R, vec_kind, precision, eps, seed, col_block, ckpt_every = ctx.args
-        dJ = moments_vjp(None, M, R, ctx.ab, dmu, vec_kind, precision, eps, seed, col_block, ckpt_every,
-                         problems=ctx.ps)
+        dJ = moments_vjp_resume(ctx.ps, M, R, ctx.ab, dmu, ctx.ws, vec_kind, precision, eps, seed, col_block,
+                                ckpt_every)
+        ctx.ws = None
         dJ = dJ.view(len(ctx.ps), ctx.n_bonds).sum(0).to(ctx.J_device)
         return (dJ,) + (None,) * 11
 

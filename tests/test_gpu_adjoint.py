@@ -44,6 +44,27 @@ def test_moments_vjp_matches_oracle(kpm, kind, R, precision, col_block, ckpt):
         assert np.abs(dJ[p] - want).max() <= tol * np.abs(want).max(), p
 
 
+@pytest.mark.parametrize("kind,R,precision,ckpt", [
+    ("rademacher", 3, "fp64", 4), ("gaussian", 5, "fp64", 64), ("complex_gaussian", 4, "fp32", 8)])
+def test_checkpointed_forward_and_resumed_reverse(kpm, kind, R, precision, ckpt):
+    """moments_ckpt gives chebyshev_moments' moments and (a, b); the reverse
+    sweep resumed from its checkpoints gives moments_vjp's dL/dJ."""
+    secs = W.sectors(W.j1j2_chain(12, 1.0, 0.5))[:3]
+    bl = _bounds(secs)
+    M = 60
+    mu0, ab0 = kpm.chebyshev_moments(secs, M, R, kind, precision, 0.025, 5, bounds=bl)
+    ps = kpm.ProblemSet(secs, bl)
+    mu, ab, ws = kpm.moments_ckpt(None, M, R, kind, precision, 0.025, 5, 0, ckpt, problems=ps)
+    assert torch.equal(ab, ab0)
+    m0 = mu0.cpu().numpy()
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    assert np.abs(mu.cpu().numpy() - m0).max() <= tol * np.abs(m0[:, 0]).max()
+    lam = torch.tensor(np.random.default_rng(2).normal(size=(len(secs), M)), device="cuda")
+    want = kpm.moments_vjp(secs, M, R, ab, lam, kind, precision, 0.025, 5, 0, ckpt_every=ckpt).cpu().numpy()
+    got = kpm.moments_vjp_resume(ps, M, R, ab, lam, ws, kind, precision, 0.025, 5, 0, ckpt).cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
 def test_checkpoint_interval_does_not_change_result(kpm):
     secs = W.sectors(W.ring(12))[:2]
     bl = _bounds(secs)
