@@ -327,6 +327,13 @@ int kpm_thermo_grad(const kpm_problem* p, int32_t n, const kpm_params* q, int32_
                     const double* d_wchi, int32_t ckpt_every, double* d_L, double* d_dJ,
                     double* d_ab, void* d_work, size_t work_bytes, void* stream);
 
+/* Debug export (host only): the site relabelling a block plan with L low
+ * bits would use for spin-1/2 problem *p.  h_perm (host int32 [n_sites])
+ * gets the new label of every site (the identity when the first L sites
+ * already cut the fewest bonds found).  Returns 1 if relabelled, 0 if not,
+ * KPM_EINVAL for invalid arguments (spin s > 1/2, L outside 1..16). */
+int kpm_site_relabel(const kpm_problem* p, int32_t L, int32_t* h_perm);
+
 /* Launch statistics of the last chebyshev_moments call on this thread.
  * Host only (reads what the call recorded). */
 typedef struct {

@@ -1979,6 +1979,14 @@ const char* kpm_strerror(int code) {
   }
 }
 
+int kpm_site_relabel(const kpm_problem* p, int32_t L, int32_t* h_perm) {
+  if (!p || !h_perm || check_problem(*p) != KPM_OK || two_s_of(*p) > 1 || L < 1 || L > 16) return KPM_EINVAL;
+  std::vector<uint8_t> perm;
+  const bool moved = choose_relabel(*p, std::min<int>(L, p->n_sites), perm);
+  for (int i = 0; i < p->n_sites; ++i) h_perm[i] = moved ? perm[i] : i;
+  return moved ? 1 : 0;
+}
+
 uint64_t kpm_sector_dim(int32_t n_sites, int32_t n_up) {
   if (n_sites < 0 || n_sites > 64) return 0;
   return binom64(n_sites, n_up);

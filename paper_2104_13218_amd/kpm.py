@@ -96,6 +96,7 @@ _SIGS = {
                                   c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_size_t, c_void_p]),
     "kpm_last_run_stats": (c_int32, [POINTER(RunStats)]),
+    "kpm_site_relabel": (c_int32, [POINTER(Problem), c_int32, POINTER(c_int32)]),
     "kpm_autotune_reset": (c_int32, []),
 }
 

@@ -133,3 +133,41 @@ def test_empty_and_spin_arguments_on_host(kpmlib):
     assert lib.chebyshev_moments_workspace_size(big.arr, 1, ctypes.byref(q)) == 0
     low = kpmlib.ProblemSet([W.SpinSector(W.ring(4), 5, 9)])            # S^z = 9 - 10 < 0
     assert lib.chebyshev_moments_workspace_size(low.arr, 1, ctypes.byref(q)) == 0
+
+
+def _cut(cluster, labels, L):
+    low = np.asarray(labels)[np.asarray(cluster.bond_i)] < L
+    return int(np.sum(low != (np.asarray(labels)[np.asarray(cluster.bond_j)] < L)))
+
+
+@pytest.mark.parametrize("n,seed,L", [(13, 21, 9), (18, 23, 9), (24, 5, 9), (16, 2, 6), (30, 0, 9)])
+def test_site_relabel_cuts_fewer_bonds(kpmlib, n, seed, L):
+    """The relabelling of the block kernels (host logic): a permutation of the
+    sites whose first L labels cut strictly fewer bonds than the identity's,
+    and within 2 of the minimum over all L-sets (brute force, small n)."""
+    import itertools
+    import workloads as W
+    cl = W.random_regular_cluster(n, 3 if n != 30 else 4, seed)
+    ps = kpmlib.ProblemSet([W.Sector(cl, (n + 1) // 2, 0)])
+    perm = (ctypes.c_int32 * n)()
+    rc = kpmlib.load().kpm_site_relabel(ps.arr, L, perm)
+    assert rc in (0, 1), rc
+    perm = np.array(perm[:])
+    assert sorted(perm) == list(range(n))
+    ident = _cut(cl, np.arange(n), L)
+    if rc == 1:
+        assert _cut(cl, perm, L) < ident
+    else:
+        assert rc == 0 and np.array_equal(perm, np.arange(n))
+    if n <= 18:
+        best = min(_cut(cl, [0 if i in S else L for i in range(n)], L)
+                   for S in map(set, itertools.combinations(range(n), L)))
+        assert _cut(cl, perm, L) <= best + 2
+
+
+def test_site_relabel_keeps_the_ring(kpmlib):
+    import workloads as W
+    ps = kpmlib.ProblemSet([W.Sector(W.ring(24), 12, 0)])
+    perm = (ctypes.c_int32 * 24)()
+    assert kpmlib.load().kpm_site_relabel(ps.arr, 9, perm) == 0
+    assert list(perm) == list(range(24))
