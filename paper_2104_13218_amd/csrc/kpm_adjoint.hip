@@ -73,7 +73,7 @@ hipError_t launch_doubling_vjp(const DoublingVjpArgs& a, hipStream_t st) {
 // sub_rows states and the workgroup sub_rows * Q threads.
 template <typename T, int LD>
 __global__ __launch_bounds__(kThreads) void adjoint_kernel(const AdjArgs a) {
-  constexpr int CPT = LD < 4 ? LD : 4;
+  constexpr int CPT = LD < kAdjCpt ? LD : kAdjCpt;
   constexpr int Q = LD / CPT;
   extern __shared__ __align__(16) unsigned char smem[];
   const int nthr = blockDim.x;

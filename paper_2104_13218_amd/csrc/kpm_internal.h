@@ -356,8 +356,9 @@ struct DoublingVjpArgs {
 };
 
 // Threads per basis state in adjoint_kernel for a block of ld columns (each
-// takes min(ld, 4) of them).
-__host__ __device__ inline int adjoint_lanes(int ld) { return ld / (ld < 4 ? ld : 4); }
+// takes min(ld, kAdjCpt) of them).
+constexpr int kAdjCpt = 4;
+__host__ __device__ inline int adjoint_lanes(int ld) { return ld / (ld < kAdjCpt ? ld : kAdjCpt); }
 
 struct AdjArgs {
   const ProbDev* probs;
