@@ -1852,7 +1852,7 @@ int thermo_forward(const double* d_mu, const double* d_ab, const kpm_problem* p,
 // ---------------------------------------------- finite-temperature Lanczos
 
 struct FtlmLayout {
-  size_t plan, vec, part, dots, b2, norm, err, states, ritz, escr, weight, len, total;
+  size_t plan, vec, part, dots, b2, norm, ww, fixed, err, states, ritz, escr, weight, len, total;
 };
 
 // Every real column runs its own Lanczos recursion; columns are batched in
@@ -1886,6 +1886,8 @@ FtlmLayout ftlm_layout(const Planned& P, int steps) {
   L.dots = put((size_t)steps * TC * 8);
   L.b2 = put((size_t)steps * TC * 8);
   L.norm = put(TC * 8);
+  L.ww = put(TC * 8);
+  L.fixed = put(TC * 8);
   L.err = put(256);
   L.states = put((size_t)P.plan.n_states * 4);
   L.ritz = put(TC * steps * 8);
@@ -2457,23 +2459,21 @@ int kpm_ftlm(const kpm_problem* p, int32_t n, const kpm_params* q, const double*
   KPM_HIP(launch_reduce(D, part, norm, nullptr, st));
   KPM_HIP(launch_init(D, vec, 2, q->vec_kind, q->seed, norm, part, st));
   // Lanczos (per column): slot x holds q_j, slot y holds beta_j q_{j-1} (0 at
-  // j = 0).  One recursion step gives w_j = 2 H' q_j - y = H q_j - beta_j q_{j-1}
-  // and alpha_j = <w_j, q_j>; then w_j -= alpha_j q_j with |w_j|^2 = beta_{j+1}^2;
-  // the turn leaves q_{j+1} in slot y and beta_{j+1} q_j in slot x, whose roles
-  // then swap.
+  // j = 0).  One recursion step gives w_j = 2 H' q_j - y = H q_j - beta_j q_{j-1},
+  // alpha_j = <w_j, q_j> and <w_j, w_j>; then w_j -= alpha_j q_j with
+  // beta_{j+1}^2 = |w_j|^2, q_{j+1} = w_j / beta_{j+1} in slot y and
+  // beta_{j+1} q_j in slot x (one sweep where <w,w> - alpha^2 is well
+  // conditioned, else an exact second pass), and the slots' roles swap.
+  // <w, w> and the exact |w - alpha q|^2 of the columns finished slowly
+  double* ww = reinterpret_cast<double*>(work + L.ww);
+  double* fixed = reinterpret_cast<double*>(work + L.fixed);
   int px = 0;
   for (int j = 0; j < steps; ++j) {
     KPM_HIP(launch_step(D, vec, part, nullptr, 0, nullptr, nullptr, nullptr, 0, px, 0, st));
-    KPM_HIP(launch_reduce(D, part, nullptr, dots + (size_t)j * TC, st));
-    LzArgs a2{};
-    a2.w = vec; a2.w_hi = 1 - px;
-    a2.q = vec; a2.q_hi = px;
-    a2.coef = dots + (size_t)j * TC;
-    a2.dotvec = nullptr;
-    a2.part_out = part;
-    KPM_HIP(launch_lz_axpy(D, a2, st));
-    KPM_HIP(launch_reduce(D, part, b2 + (size_t)j * TC, nullptr, st));
-    KPM_HIP(launch_lz_turn(D, vec, 1 - px, b2 + (size_t)j * TC, st));
+    KPM_HIP(launch_reduce(D, part, ww, dots + (size_t)j * TC, st));
+    KPM_HIP(launch_lz_fused(D, vec, 1 - px, dots + (size_t)j * TC, ww, part, st));
+    KPM_HIP(launch_reduce(D, part, fixed, nullptr, st));
+    KPM_HIP(launch_lz_fix(D, vec, 1 - px, dots + (size_t)j * TC, ww, fixed, b2 + (size_t)j * TC, st));
     px = 1 - px;
   }
   // thermodynamic metadata (sector weights, S^z, clusters)

@@ -38,26 +38,35 @@ __device__ __forceinline__ double ftlm_wmin(double v, double* sh) {
 
 }  // namespace
 
-// One thread per Lanczos column: the tridiagonal is cut at the first
-// negligible off-diagonal (beta < 1e-12) or at the sector dimension, then
-// Ritz values and weights (squared first components times the column's
-// weight in the estimator: dim/R, or its share of |r|^2 for the two real
-// columns of a complex vector, or 1 for the complete basis).
-__global__ __launch_bounds__(kThreads) void ftlm_ritz_kernel(const FtlmArgs a) {
-  const int c = blockIdx.x * kThreads + threadIdx.x;
-  if (c >= a.total_cols) return;
+// One Lanczos column per workgroup, worked by its first lane: the
+// tridiagonal is cut at the first negligible off-diagonal (beta < 1e-12) or
+// at the sector dimension, then Ritz values and weights (squared first
+// components times the column's weight in the estimator: dim/R, or its share
+// of |r|^2 for the two real columns of a complex vector, or 1 for the
+// complete basis).  The QL sweeps are a serial chain of dependent loads and
+// stores, so d, e and z live in LDS when 3 S doubles fit (kRitzLds), else in
+// the global result arrays.
+constexpr int kRitzLds = 64 * 1024;
+
+__global__ __launch_bounds__(64) void ftlm_ritz_kernel(const FtlmArgs a) {
+  extern __shared__ double ritz_sh[];
+  const int c = blockIdx.x;
+  if (c >= a.total_cols || threadIdx.x != 0) return;
   const UnitDev U = a.units[a.job_unit[2 * c]];
   const ProbDev P = a.probs[U.prob];
   const int S = a.steps;
-  double* d = a.ritz + (int64_t)c * S;
-  double* e = a.escr + (int64_t)c * S;
-  double* z = a.weight + (int64_t)c * S;
+  double* dg = a.ritz + (int64_t)c * S;
+  double* zg = a.weight + (int64_t)c * S;
   const int lc = c - U.col_off;          // column inside the block; padding past ncols
   if (lc >= U.ncols) {
-    for (int j = 0; j < S; ++j) d[j] = z[j] = 0.0;
+    for (int j = 0; j < S; ++j) dg[j] = zg[j] = 0.0;
     a.len[c] = 0;
     return;
   }
+  const bool in_lds = (size_t)3 * S * sizeof(double) <= (size_t)kRitzLds;
+  double* d = in_lds ? ritz_sh : dg;
+  double* e = in_lds ? ritz_sh + S : a.escr + (int64_t)c * S;
+  double* z = in_lds ? ritz_sh + 2 * S : zg;
   const int L = (int)min((int64_t)S, P.dim);
   int n = 0;
   for (int j = 0; j < L; ++j) {
@@ -76,17 +85,21 @@ __global__ __launch_bounds__(kThreads) void ftlm_ritz_kernel(const FtlmArgs a) {
   } else {
     cw = (double)P.dim / a.R;
   }
-  for (int j = 0; j < n; ++j) z[j] = z[j] * z[j] * cw;
+  for (int j = 0; j < n; ++j) {
+    dg[j] = d[j];
+    zg[j] = z[j] * z[j] * cw;
+  }
   for (int j = n; j < S; ++j) {
-    d[j] = 0.0;
-    z[j] = 0.0;
+    dg[j] = 0.0;
+    zg[j] = 0.0;
   }
   a.len[c] = n;
 }
 
 hipError_t launch_ftlm_ritz(const FtlmArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(ftlm_ritz_kernel, dim3((a.total_cols + kThreads - 1) / kThreads), dim3(kThreads),
-                     0, st, a);
+  const size_t want = (size_t)3 * a.steps * sizeof(double);
+  const size_t lds = want <= (size_t)kRitzLds ? want : 0;
+  hipLaunchKernelGGL(ftlm_ritz_kernel, dim3(a.total_cols), dim3(64), lds, st, a);
   return hipGetLastError();
 }
 

@@ -440,8 +440,13 @@ size_t tab_lds_bytes(const DevicePlan& p);
 size_t tab_meta_bytes(const DevicePlan& p);
 hipError_t launch_matrix(const MatrixArgs& a, size_t lds, int grid, hipStream_t st);
 hipError_t launch_lz_axpy(const DevicePlan& p, const LzArgs& args, hipStream_t st);
-// FTLM: y <- y / beta, x <- beta x per column (slot y_hi holds y, the other x).
-hipError_t launch_lz_turn(const DevicePlan& p, double* vec, int y_hi, const double* beta2, hipStream_t st);
+// FTLM: fused w -= alpha q_j and turn for well-conditioned columns (ww = <w, w>),
+// then the exact finish of the others (fixed = their |w - alpha q_j|^2) and
+// beta_{j+1}^2 of every column.
+hipError_t launch_lz_fused(const DevicePlan& p, double* vec, int y_hi, const double* alpha, const double* ww,
+                           double* part_out, hipStream_t st);
+hipError_t launch_lz_fix(const DevicePlan& p, double* vec, int y_hi, const double* alpha, const double* ww,
+                         const double* fixed, double* beta2, hipStream_t st);
 hipError_t launch_lz_next(const DevicePlan& p, double* qprev, double* q, const double* w,
                           const double* beta2, hipStream_t st);
 hipError_t launch_kernel_coef(int M, int kernel, double* g, hipStream_t st);

@@ -2312,12 +2312,24 @@ __global__ __launch_bounds__(kThreads) void lz_next_kernel(const LzArgs a, doubl
   }
 }
 
-// After w_j = H q_j - beta_j q_{j-1} and w_j -= alpha_j q_j: per column with
-// beta_{j+1}^2 = |w_j|^2 > 1e-24, y <- w_j / beta_{j+1} (= q_{j+1}) and
-// x <- beta_{j+1} q_j (the term the next step subtracts); a column whose Krylov
-// space is exhausted keeps q_j (y <- x) and drops the term (x <- 0).  The
-// caller then swaps the two slots' roles.
-__global__ __launch_bounds__(kThreads) void lz_turn_kernel(const LzArgs a, const double* beta2) {
+// FTLM, one sweep per step where it is safe: with alpha = <w, q_j> and
+// <w, w> from the recursion step, beta^2 = <w, w> - alpha^2 loses at most
+// eps <w, w> / beta^2 to cancellation; for a column with beta^2 > kLzFast
+// <w, w> the sweep writes y <- (w - alpha q_j) / beta and x <- beta q_j at
+// once.  Other columns get y <- w - alpha q_j and their exact |y|^2 partials,
+// and lz_fix_kernel finishes them.  The cut keeps the
+// normalisation error of q_{j+1} near 1e-15: a looser one (1e-3) leaves
+// errors near 1e-13 that surface as a residual above the 1e-12 exhaustion
+// cut of an invariant Krylov space (the one-magnon sector of a 10-site ring).
+constexpr double kLzFast = 0.1;
+
+__device__ __forceinline__ bool lz_fast(double ww, double al) {
+  const double b2 = ww - al * al;
+  return b2 > kLzFast * ww && b2 > 1e-24;
+}
+
+__global__ __launch_bounds__(kThreads) void lz_fused_kernel(const LzArgs a, const double* ww) {
+  __shared__ double red[kThreads];
   const int tile = xcd_tile(blockIdx.x, a.grid_tiles);
   if (tile >= a.n_tiles) return;
   const UnitDev U = a.units[a.tile_unit[tile]];
@@ -2325,11 +2337,69 @@ __global__ __launch_bounds__(kThreads) void lz_turn_kernel(const LzArgs a, const
   const int64_t row1 = row0 + a.tile_nrows[tile];
   const int ld = U.ld;
   const int nrg = kThreads / ld;
-  const int c = threadIdx.x % ld, rg = threadIdx.x / ld;
-  if (rg >= nrg) return;
+  const int tid = threadIdx.x;
+  const int c = tid % ld, rg = tid / ld;
   double* y = lz_sel(a.w, a.w_hi, U, a.slot_stride);
   double* x = lz_sel(const_cast<double*>(a.q), a.q_hi, U, a.slot_stride);
-  const double b2 = beta2[U.col_off + c];
+  double acc = 0.0;
+  if (rg < nrg) {
+    const double al = a.coef[U.col_off + c], w2 = ww[U.col_off + c];
+    if (lz_fast(w2, al)) {
+      const double b = sqrt(w2 - al * al), inv = 1.0 / b;
+      for (int64_t r = row0 + rg; r < row1; r += nrg) {
+        const int64_t i = r * ld + c;
+        const double xv = x[i];
+        y[i] = (y[i] - al * xv) * inv;
+        x[i] = b * xv;
+      }
+    } else {
+      for (int64_t r = row0 + rg; r < row1; r += nrg) {
+        const int64_t i = r * ld + c;
+        const double wv = y[i] - al * x[i];
+        y[i] = wv;
+        acc = fma(wv, wv, acc);
+      }
+    }
+  }
+  red[tid] = rg < nrg ? acc : 0.0;
+  int p2 = 1;
+  while (p2 < nrg) p2 <<= 1;
+  for (int s = p2 >> 1; s > 0; s >>= 1) {
+    __syncthreads();
+    if (rg < s && rg + s < nrg) red[tid] += red[tid + s * ld];
+  }
+  __syncthreads();
+  if (tid < ld) {
+    const int tl = tile - U.tile0;
+    a.part_out[U.part_off + (int64_t)tid * U.ntiles + tl] = red[tid];
+    a.part_out[U.part_off + (int64_t)(ld + tid) * U.ntiles + tl] = 0.0;
+  }
+}
+
+// Records beta_{j+1}^2 of every column (first tile of each block) and
+// finishes the columns lz_fused_kernel left, whose exact |w - alpha q_j|^2
+// fixed[] holds: with beta^2 > 1e-24, y <- y / beta (= q_{j+1}) and
+// x <- beta q_j (the term the next step subtracts); a column whose Krylov
+// space is exhausted keeps q_j (y <- x) and drops the term (x <- 0).  The
+// caller then swaps the two slots' roles.
+__global__ __launch_bounds__(kThreads) void lz_fix_kernel(const LzArgs a, const double* ww,
+                                                          const double* fixed, double* beta2) {
+  const int tile = xcd_tile(blockIdx.x, a.grid_tiles);
+  if (tile >= a.n_tiles) return;
+  const UnitDev U = a.units[a.tile_unit[tile]];
+  const int ld = U.ld;
+  const int nrg = kThreads / ld;
+  const int c = threadIdx.x % ld, rg = threadIdx.x / ld;
+  if (rg >= nrg) return;
+  const double al = a.coef[U.col_off + c], w2 = ww[U.col_off + c];
+  const bool fast = lz_fast(w2, al);
+  const double b2 = fast ? w2 - al * al : fixed[U.col_off + c];
+  if (tile == U.tile0 && rg == 0) beta2[U.col_off + c] = b2;
+  if (fast) return;
+  double* y = lz_sel(a.w, a.w_hi, U, a.slot_stride);
+  double* x = lz_sel(const_cast<double*>(a.q), a.q_hi, U, a.slot_stride);
+  const int64_t row0 = a.tile_row0[tile];
+  const int64_t row1 = row0 + a.tile_nrows[tile];
   const bool live = b2 > 1e-24;
   const double b = live ? sqrt(b2) : 0.0;
   const double inv = live ? 1.0 / b : 0.0;
@@ -2341,7 +2411,8 @@ __global__ __launch_bounds__(kThreads) void lz_turn_kernel(const LzArgs a, const
   }
 }
 
-hipError_t launch_lz_turn(const DevicePlan& p, double* vec, int y_hi, const double* beta2, hipStream_t st) {
+hipError_t launch_lz_fused(const DevicePlan& p, double* vec, int y_hi, const double* alpha, const double* ww,
+                           double* part_out, hipStream_t st) {
   LzArgs a{};
   a.probs = p.probs;
   a.units = p.units;
@@ -2355,7 +2426,29 @@ hipError_t launch_lz_turn(const DevicePlan& p, double* vec, int y_hi, const doub
   a.w_hi = y_hi;
   a.q = vec;
   a.q_hi = 1 - y_hi;
-  hipLaunchKernelGGL(lz_turn_kernel, dim3(p.grid_tiles), dim3(kThreads), 0, st, a, beta2);
+  a.coef = alpha;
+  a.part_out = part_out;
+  hipLaunchKernelGGL(lz_fused_kernel, dim3(p.grid_tiles), dim3(kThreads), 0, st, a, ww);
+  return hipGetLastError();
+}
+
+hipError_t launch_lz_fix(const DevicePlan& p, double* vec, int y_hi, const double* alpha, const double* ww,
+                         const double* fixed, double* beta2, hipStream_t st) {
+  LzArgs a{};
+  a.probs = p.probs;
+  a.units = p.units;
+  a.tile_unit = p.tile_unit;
+  a.n_tiles = p.n_tiles;
+  a.grid_tiles = p.grid_tiles;
+  a.tile_row0 = p.tile_row0;
+  a.tile_nrows = p.tile_nrows;
+  a.slot_stride = p.slot_stride;
+  a.w = vec;
+  a.w_hi = y_hi;
+  a.q = vec;
+  a.q_hi = 1 - y_hi;
+  a.coef = alpha;
+  hipLaunchKernelGGL(lz_fix_kernel, dim3(p.grid_tiles), dim3(kThreads), 0, st, a, ww, fixed, beta2);
   return hipGetLastError();
 }
 
