@@ -329,8 +329,11 @@ int kpm_thermo_grad(const kpm_problem* p, int32_t n, const kpm_params* q, int32_
 
 /* Debug export (host only): the site relabelling a block plan with L low
  * bits would use for spin-1/2 problem *p.  h_perm (host int32 [n_sites])
- * gets the new label of every site (the identity when the first L sites
- * already cut the fewest bonds found).  Returns 1 if relabelled, 0 if not,
+ * gets the new label of every site: labels 0..L-1 go to a set of L sites
+ * that cuts few bonds (the first L sites unless a set with a strictly
+ * smaller cut is found), the higher labels to the other sites in an order
+ * where few bonds touch the highest labels (the slowest-varying bits of the
+ * state words).  Returns 1 if relabelled, 0 if the identity is kept,
  * KPM_EINVAL for invalid arguments (spin s > 1/2, L outside 1..16). */
 int kpm_site_relabel(const kpm_problem* p, int32_t L, int32_t* h_perm);
 

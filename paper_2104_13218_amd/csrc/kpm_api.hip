@@ -280,10 +280,21 @@ int pick_col_block(const kpm_problem* p, int n, const RunShape& s) {
 // gathered row by row through the rank tables; bonds inside S stay in the
 // block, bonds outside it move whole blocks).  Local search (best single swap
 // between S and its complement until none lowers the cut) from the first L
-// sites of a breadth-first walk from every site; the identity is kept unless
-// a set with a strictly smaller cut is found.  perm[i] is the new label of
-// site i: S in ascending order gets 0..L-1, the other sites follow in
-// breadth-first order from S (sites bonded to S get the lowest high bits).
+// sites of a breadth-first walk from every site; the first L sites are kept
+// unless a set with a strictly smaller cut is found.  S in ascending order
+// gets labels 0..L-1.
+//
+// The high sites are then ordered for locality: states are ranked in
+// ascending order of their words, so the highest labels vary slowest and a
+// bond touching one of the top t sites moves a state far in rank (out of the
+// range a cache holds at once).  The cost of an order is the number of bonds
+// touching the top t sites, summed over t; the breadth-first order from S
+// (sites bonded to S get the lowest high bits; the given order when S is the
+// first L sites) is replaced by a greedy one that fills the top labels
+// downwards, each time with the site having the most bonds into the sites
+// already placed (ties: fewest bonds elsewhere, then lowest index), started
+// from every high site, when that lowers the cost strictly.  perm[i] is the
+// new label of site i; returns false when it is the identity.
 bool choose_relabel(const kpm_problem& p, int L, std::vector<uint8_t>& perm) {
   const int N = p.n_sites;
   if (L <= 0 || L >= N || env_int("KPM_RELABEL", 1) == 0) return false;
@@ -347,26 +358,79 @@ bool choose_relabel(const kpm_problem& p, int L, std::vector<uint8_t>& perm) {
       best = in;
     }
   }
-  if (best_cut >= cut0) return false;
-  perm.assign(32, 0);
+  const bool moved = best_cut < cut0;
+  std::vector<int> lab(N, -1);
   int next = 0;
-  std::vector<char> placed(N, 0);
-  std::vector<int> queue;
   for (int v = 0; v < N; ++v)
-    if (best[v]) {
-      perm[v] = (uint8_t)next++;
-      placed[v] = 1;
-      queue.push_back(v);
+    if (best[v]) lab[v] = next++;
+  // high order A: breadth-first from S, or the given order when S is kept
+  std::vector<int> high_a;
+  if (moved) {
+    std::vector<char> placed(best.begin(), best.end());
+    std::vector<int> queue;
+    for (int v = 0; v < N; ++v)
+      if (best[v]) queue.push_back(v);
+    for (size_t h = 0; h < queue.size(); ++h)
+      for (int u : adj[queue[h]])
+        if (!placed[u]) {
+          placed[u] = 1;
+          high_a.push_back(u);
+          queue.push_back(u);
+        }
+    for (int v = 0; v < N; ++v)
+      if (!placed[v]) high_a.push_back(v);
+  } else {
+    for (int v = 0; v < N; ++v)
+      if (!best[v]) high_a.push_back(v);
+  }
+  // cost of a high order (lowest label first): bonds touching the top t sites, summed over t
+  const int H = N - L;
+  auto order_cost = [&](const std::vector<int>& high) {
+    std::vector<int> rank(N, -1);   // position from the top: 0 = highest label
+    for (int i = 0; i < H; ++i) rank[high[i]] = H - 1 - i;
+    long c = 0;
+    for (int k = 0; k < p.n_bonds; ++k) {
+      int top = H;   // the bond touches the top t sites for every t > min rank
+      if (rank[p.bond_i[k]] >= 0) top = std::min(top, rank[p.bond_i[k]]);
+      if (rank[p.bond_j[k]] >= 0) top = std::min(top, rank[p.bond_j[k]]);
+      if (top < H) c += H - 1 - top;   // t = top + 1 .. H - 1
     }
-  for (size_t h = 0; h < queue.size(); ++h)
-    for (int u : adj[queue[h]])
-      if (!placed[u]) {
-        placed[u] = 1;
-        perm[u] = (uint8_t)next++;
-        queue.push_back(u);
+    return c;
+  };
+  std::vector<int> high = high_a;
+  long best_cost = order_cost(high_a);
+  for (int start : high_a) {
+    std::vector<int> top{start};   // highest label first
+    std::vector<char> placed(N, 0);
+    placed[start] = 1;
+    while ((int)top.size() < H) {
+      int pick = -1, pin = -1, pout = 0;
+      for (int v : high_a) {
+        if (placed[v]) continue;
+        int in_top = 0, out = 0;
+        for (int u : adj[v]) (placed[u] ? in_top : out) += 1;
+        if (in_top > pin || (in_top == pin && (out < pout || (out == pout && v < pick)))) {
+          pick = v;
+          pin = in_top;
+          pout = out;
+        }
       }
-  for (int v = 0; v < N; ++v)
-    if (!placed[v]) perm[v] = (uint8_t)next++;
+      placed[pick] = 1;
+      top.push_back(pick);
+    }
+    std::vector<int> cand(top.rbegin(), top.rend());
+    const long c = order_cost(cand);
+    if (c < best_cost) {
+      best_cost = c;
+      high = cand;
+    }
+  }
+  for (int v : high) lab[v] = next++;
+  bool ident = true;
+  for (int v = 0; v < N; ++v) ident = ident && lab[v] == v;
+  if (ident) return false;
+  perm.assign(32, 0);
+  for (int v = 0; v < N; ++v) perm[v] = (uint8_t)lab[v];
   return true;
 }
 

@@ -135,6 +135,15 @@ def test_empty_and_spin_arguments_on_host(kpmlib):
     assert lib.chebyshev_moments_workspace_size(low.arr, 1, ctypes.byref(q)) == 0
 
 
+def _top_cost(cluster, labels, L):
+    """Bonds touching the top t labels, summed over t = 1 .. n - L - 1."""
+    n = cluster.n_sites
+    lab = np.asarray(labels)
+    bi, bj = lab[np.asarray(cluster.bond_i)], lab[np.asarray(cluster.bond_j)]
+    hi = np.maximum(bi, bj)
+    return int(sum(np.sum(hi >= n - t) for t in range(1, n - L)))
+
+
 def _cut(cluster, labels, L):
     low = np.asarray(labels)[np.asarray(cluster.bond_i)] < L
     return int(np.sum(low != (np.asarray(labels)[np.asarray(cluster.bond_j)] < L)))
@@ -143,8 +152,10 @@ def _cut(cluster, labels, L):
 @pytest.mark.parametrize("n,seed,L", [(13, 21, 9), (18, 23, 9), (24, 5, 9), (16, 2, 6), (30, 0, 9)])
 def test_site_relabel_cuts_fewer_bonds(kpmlib, n, seed, L):
     """The relabelling of the block kernels (host logic): a permutation of the
-    sites whose first L labels cut strictly fewer bonds than the identity's,
-    and within 2 of the minimum over all L-sets (brute force, small n)."""
+    sites whose first L labels cut no more bonds than the identity's, within 2
+    of the minimum over all L-sets (brute force, small n), and whose high
+    labels are ordered so that no more bonds touch the top t labels, summed
+    over t, than in the identity's order."""
     import itertools
     import workloads as W
     cl = W.random_regular_cluster(n, 3 if n != 30 else 4, seed)
@@ -155,10 +166,9 @@ def test_site_relabel_cuts_fewer_bonds(kpmlib, n, seed, L):
     perm = np.array(perm[:])
     assert sorted(perm) == list(range(n))
     ident = _cut(cl, np.arange(n), L)
-    if rc == 1:
-        assert _cut(cl, perm, L) < ident
-    else:
-        assert rc == 0 and np.array_equal(perm, np.arange(n))
+    assert _cut(cl, perm, L) <= ident
+    assert (rc == 1) == (not np.array_equal(perm, np.arange(n)))
+    assert _top_cost(cl, perm, L) <= _top_cost(cl, np.arange(n), L) or _cut(cl, perm, L) < ident
     if n <= 18:
         best = min(_cut(cl, [0 if i in S else L for i in range(n)], L)
                    for S in map(set, itertools.combinations(range(n), L)))
@@ -171,3 +181,55 @@ def test_site_relabel_keeps_the_ring(kpmlib):
     perm = (ctypes.c_int32 * 24)()
     assert kpmlib.load().kpm_site_relabel(ps.arr, 9, perm) == 0
     assert list(perm) == list(range(24))
+
+
+def test_site_relabel_scrambled_ring(kpmlib):
+    """A 24-site ring under a random labelling: the relabelling finds a set of
+    9 sites cutting the minimum of 2 bonds (an arc) and orders the other 15 so
+    that the top t labels touch t + 1 bonds (the minimum for t sites of a
+    ring: an arc), i.e. a summed cost of 2 + 3 + ... + 15 = 119."""
+    import workloads as W
+    rng = np.random.default_rng(11)
+    pi = rng.permutation(24)
+    i = np.arange(24)
+    cl = W.Cluster(24, pi[i], pi[(i + 1) % 24], np.ones(24), name="ring24_scrambled")
+    ps = kpmlib.ProblemSet([W.Sector(cl, 12, 0)])
+    perm = (ctypes.c_int32 * 24)()
+    assert kpmlib.load().kpm_site_relabel(ps.arr, 9, perm) == 1
+    perm = np.array(perm[:])
+    assert sorted(perm) == list(range(24))
+    assert _cut(cl, perm, 9) == 2
+    assert _top_cost(cl, perm, 9) == 119 == _top_cost(W.ring(24), np.arange(24), 9)
+
+
+def test_site_relabel_orders_high_sites_for_locality(kpmlib):
+    """The 30-site random 4-regular cluster: the high labels are ordered so
+    that fewer bonds touch the top labels than in breadth-first order from
+    the low set (the order used before the locality pass; recomputed here)."""
+    import workloads as W
+    cl = W.random_regular_cluster(30, 4, 0)
+    ps = kpmlib.ProblemSet([W.Sector(cl, 15, 0)])
+    perm = (ctypes.c_int32 * 30)()
+    assert kpmlib.load().kpm_site_relabel(ps.arr, 9, perm) == 1
+    perm = np.array(perm[:])
+    low = [v for v in range(30) if perm[v] < 9]
+    adj = [[] for _ in range(30)]
+    for a, b in zip(cl.bond_i, cl.bond_j):
+        adj[a].append(b)
+        adj[b].append(a)
+    bfs, seen = [], set(low)
+    queue = list(low)
+    for v in queue:
+        for u in sorted(adj[v]):
+            if u not in seen:
+                seen.add(u)
+                bfs.append(u)
+                queue.append(u)
+    bfs += [v for v in range(30) if v not in seen]
+    ref = np.empty(30, dtype=np.int64)
+    for k, v in enumerate(sorted(low)):
+        ref[v] = k
+    for k, v in enumerate(bfs):
+        ref[v] = 9 + k
+    assert _cut(cl, perm, 9) == _cut(cl, ref, 9)
+    assert _top_cost(cl, perm, 9) < _top_cost(cl, ref, 9)
