@@ -212,6 +212,7 @@ def main():
                      "avg_launch_us": avg_launch_s * 1e6,
                      "traffic": traffic,
                      "measured_GBs": None if traffic is None else traffic / avg_launch_s / 1e9,
+                     "measured_frac": None if traffic is None else traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS,
                      "copy_GBs": copy_gbs},
     }
 
