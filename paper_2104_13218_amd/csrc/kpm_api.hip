@@ -665,9 +665,8 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
       D.lds_hh = hh;
       D.lds_mx = mx;
       D.lds_ll = ll;
-      // the block-table kernel packs (row, low-low bond) into 16 bits and pads
-      // each row's list to a multiple of 4 (at most 252 entries: 8-bit counts)
-      if ((tab ? tab_lds_bytes(D) : block_lds_bytes(D)) <= cap && (!tab || ll <= 252))
+      // the block-table kernel packs (row, low-low bond) into 16 bits
+      if ((tab ? tab_lds_bytes(D) : block_lds_bytes(D)) <= cap && (!tab || ll <= 255))
         D.block = tab ? 2 : 1;
     }
   }

@@ -1331,14 +1331,9 @@ static hipError_t launch_block(const DevicePlan& p, const StepArgs& a, hipStream
 // runs diagonal, low-low, high-high, mixed (each in bond order).
 
 struct TabLds {
-  size_t mask, off, zz, lrank, lunr, koff, bstart, bh, boff, bcnt, bhs, bhc, bms, llc, rblk, rl, ri,
+  size_t mask, off, zz, lrank, lunr, koff, bstart, bh, boff, bcnt, bhs, bhq, bms, rblk, rl, ri,
       rdiag, rlln, rll, xs, total;
 };
-
-// Slots per block in the high-high tables (a multiple of every gather batch)
-// and per row in the low-low lists (a multiple of their batch of 4).
-__host__ __device__ inline int tab_hh_stride(int lds_hh) { return (lds_hh + 7) & ~7; }
-__host__ __device__ inline int tab_ll_stride(int lds_ll) { return (lds_ll + 3) & ~3; }
 
 // xs_bytes: the sub-tile's rows of v_n in LDS (0 = read through L1).
 __host__ __device__ inline TabLds tab_lds_layout(int lds_bonds, int lds_lr, int blk_max,
@@ -1361,18 +1356,17 @@ __host__ __device__ inline TabLds tab_lds_layout(int lds_bonds, int lds_lr, int 
   L.bh = put(size_t(blk_max) * 4);
   L.boff = put(size_t(blk_max) * 4);
   L.bcnt = put(size_t(blk_max) * 4);
-  // per block and acting high-high bond: target element offset and
-  // coefficient, padded to a multiple of 8 slots (own block, coefficient 0)
-  L.bhs = put(size_t(blk_max) * tab_hh_stride(lds_hh) * 4);
-  L.bhc = put(size_t(blk_max) * tab_hh_stride(lds_hh) * 8);
+  // + 8 entries: a batch of gathers may read up to GB - 1 entries past a
+  // block's list (those lanes are masked)
+  L.bhs = put((size_t(blk_max) * lds_hh + 8) * 4);
+  L.bhq = put((size_t(blk_max) * lds_hh + 8) * 2);
   L.bms = put(size_t(blk_max) * lds_mx * 4);
-  L.llc = put(size_t(lds_ll + 1) * 8);
   L.rblk = put(size_t(rows));
   L.rl = put(size_t(rows) * 2);
   L.ri = put(size_t(rows) * 2);
   L.rdiag = put(size_t(rows) * 8);
   L.rlln = put(size_t(rows));
-  L.rll = put(size_t(rows) * tab_ll_stride(lds_ll) * 2);
+  L.rll = put((size_t(rows) * lds_ll + 4) * 2);
   L.xs = put(xs_bytes);
   const size_t red = size_t(2 * cpl) * kThreads * 8;   // final reduction overlays all of it
   L.total = o > red ? o : red;
@@ -1484,28 +1478,6 @@ hipError_t build_tab_meta(const DevicePlan& p, hipStream_t st) {
   return hipGetLastError();
 }
 
-// One batch of NB high-high neighbour rows of a (row, chunk) item: the
-// block's table holds each target's element offset (target block start
-// times the row length) and coefficient; the item adds its own index in the
-// block and column chunk (ie).  Padded slots point at the item's own block
-// with coefficient 0, so every lane issues its loads without branching.
-template <typename T, int CPL, int NB>
-__device__ __forceinline__ void tab_hh_batch(const T* X, const uint32_t* hs, const double* hc, int k0,
-                                             uint32_t ie, double* acc) {
-  VecT<T, CPL> nv[NB];
-  double cf[NB];
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    cf[j] = hc[k0 + j];
-    nv[j] = vload<T, CPL>(X + (hs[k0 + j] + ie));
-  }
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-#pragma unroll
-    for (int i = 0; i < CPL; ++i) acc[i] = fma(cf[j], (double)nv[j].v[i], acc[i]);
-  }
-}
-
 // One batch of NB mixed bonds (one low and one high site) of a (row, chunk)
 // item: the bond acts when the two sites differ; the neighbour row is the
 // target block's first rank plus the colex rank of the flipped low word.
@@ -1583,9 +1555,8 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
   int32_t* s_boff = reinterpret_cast<int32_t*>(smem + Lo.boff);
   int32_t* s_bcnt = reinterpret_cast<int32_t*>(smem + Lo.bcnt);
   uint32_t* s_bhs = reinterpret_cast<uint32_t*>(smem + Lo.bhs);
-  double* s_bhc = reinterpret_cast<double*>(smem + Lo.bhc);
+  uint16_t* s_bhq = reinterpret_cast<uint16_t*>(smem + Lo.bhq);
   uint32_t* s_bms = reinterpret_cast<uint32_t*>(smem + Lo.bms);
-  double* s_llc = reinterpret_cast<double*>(smem + Lo.llc);
   uint8_t* s_rblk = reinterpret_cast<uint8_t*>(smem + Lo.rblk);
   uint16_t* s_rl = reinterpret_cast<uint16_t*>(smem + Lo.rl);
   uint16_t* s_ri = reinterpret_cast<uint16_t*>(smem + Lo.ri);
@@ -1607,9 +1578,6 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
     s_lunr[l] = a.lunr[l];
   }
   for (int k = tid; k < kKoffLen; k += kThreads) s_koff[k] = a.koff[k];
-  // low-low coefficients by bond, and a zero at index lds_ll for padded slots
-  for (int q = tid; q <= a.lds_ll; q += kThreads)
-    s_llc[q] = q < nll ? a.boff[P.bond_off + a.bperm[P.bond_off + q]] : 0.0;
 
   const int ld = U.ld;
   T* base = reinterpret_cast<T*>(a.vec) + U.vec_off;
@@ -1638,19 +1606,11 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
       s_boff[t] = (int)((int64_t)st - row0);
       s_bcnt[t] = (int)min(a.meta_hcnt[g0 + t], (uint32_t)nhh);
     }
-    const int hst = tab_hh_stride(a.lds_hh);
-    for (int t = tid; t < nblk * hst; t += kThreads) {
-      const int kb = t / hst, j = t - kb * hst;
-      const int cnt = (int)min(a.meta_hcnt[g0 + kb], (uint32_t)nhh);
-      uint32_t st = a.blk_start[g0 + kb];
-      double cf = 0.0;
-      if (j < cnt) {
-        const int64_t src = (int64_t)(g0 + kb) * a.meta_hh + j;
-        st = a.meta_hstart[src];
-        cf = a.boff[P.bond_off + a.bperm[P.bond_off + nll + a.meta_hq[src]]];
-      }
-      s_bhs[kb * hst + j] = st * (uint32_t)ld;
-      s_bhc[kb * hst + j] = cf;
+    for (int t = tid; t < nblk * nhh; t += kThreads) {
+      const int kb = t / nhh, j = t - kb * nhh;
+      const int64_t src = (int64_t)(g0 + kb) * a.meta_hh + j;
+      s_bhs[kb * a.lds_hh + j] = a.meta_hstart[src];
+      s_bhq[kb * a.lds_hh + j] = a.meta_hq[src];
     }
     for (int t = tid; t < nblk * nmx; t += kThreads) {
       const int kb = t / nmx, j = t - kb * nmx;
@@ -1686,9 +1646,7 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
         d += (v == 0u || v == m) ? s_zz[q] : -s_zz[q];
       }
       // acting low-low bonds: the neighbour is row boff + lrank(l ^ m) of this
-      // sub-tile; (row, bond) packed in 16 bits, padded to a multiple of 4
-      // with (own row, zero coefficient)
-      const int lst = tab_ll_stride(a.lds_ll);
+      // sub-tile; (row, bond) packed in 16 bits
       int nl = 0;
       for (int q = 0; q < nll; ++q) {
         const uint32_t m = s_mask[q];
@@ -1699,10 +1657,9 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
           if (a.err) atomicOr(a.err, 4);
           continue;
         }
-        s_rll[tid * lst + nl] = (uint16_t)(jr | (q << 8));
+        s_rll[tid * a.lds_ll + nl] = (uint16_t)(jr | (q << 8));
         ++nl;
       }
-      while (nl & 3) s_rll[tid * lst + nl++] = (uint16_t)(tid | (a.lds_ll << 8));
       s_rlln[tid] = (uint8_t)nl;
       s_rblk[tid] = (uint8_t)kb;
       s_rl[tid] = (uint16_t)l;
@@ -1712,12 +1669,13 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
     __syncthreads();
 
     // Phase C: (row, column chunk) items.  Diagonal, low-low (own sub-tile),
-    // high-high and mixed rows, GB loads in flight per batch; the own row is
-    // read again only at the end, so that few registers stay live across the
-    // gathers.  Element offsets inside the block's slot fit
-    // 32 bits (the planner guarantees dim * ld < 2^32); a slot past a row's
-    // count reads the row itself with a zero coefficient, so every lane of a
-    // batch issues its loads without branching.
+    // high-high and mixed rows, GB loads in flight per batch (mixed ones 2 at
+    // a time when the problem has at most 2); the own row is read again only
+    // at the end, so that few registers stay live across the gathers.
+    // Element offsets inside the block's slot fit 32 bits (the planner
+    // guarantees dim * ld < 2^32); a slot past a row's count reads the row
+    // itself with a zero coefficient, so every lane of a batch issues its
+    // loads without branching.
     if (rg < nrg) {
       const uint32_t ldu = (uint32_t)ld, cc = (uint32_t)(c * CPL);
       for (int r = rg; r < nrows; r += nrg) {
@@ -1737,19 +1695,20 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
           for (int i = 0; i < CPL; ++i) acc[i] = dg * (double)xv.v[i];
         }
         {
-          // acting low-low neighbours, four at a time (lists padded to 4)
+          // acting low-low neighbours, four at a time
           const int nl = s_rlln[r];
-          const uint16_t* ll = s_rll + r * tab_ll_stride(a.lds_ll);
+          const uint16_t* ll = s_rll + r * a.lds_ll;
           for (int k0 = 0; k0 < nl; k0 += 4) {
             VecT<T, CPL> nv[4];
             double cl[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
+              const bool on = k0 + u < nl;
               const uint32_t e = ll[k0 + u];
-              cl[u] = s_llc[e >> 8];
-              // row < 256 and row length <= 64: the 24-bit product is exact
-              const uint32_t jr = e & 0xFFu;
-              nv[u] = XL ? vload<T, CPL>(xs + (__umul24(jr, ldu) + cc))
+              cl[u] = s_off[on ? (e >> 8) : 0u];
+              cl[u] = on ? cl[u] : 0.0;
+              const uint32_t jr = on ? (e & 0xFFu) : (uint32_t)r;
+              nv[u] = XL ? vload<T, CPL>(xs + jr * ldu + cc)
                          : vload<T, CPL>(X + (((uint32_t)row0 + jr) * ldu + cc));
             }
 #pragma unroll
@@ -1762,12 +1721,29 @@ __global__ __launch_bounds__(kThreads) void tab_kernel(const StepArgs a) {
         const int kb = s_rblk[r];
         const uint32_t ib = s_ri[r];
         const int nh = s_bcnt[kb];
-        const int hst = tab_hh_stride(a.lds_hh);
-        const uint32_t* hs = s_bhs + kb * hst;
-        const double* hc = s_bhc + kb * hst;
-        const uint32_t ie = ib * ldu + cc;
+        const uint32_t* hs = s_bhs + kb * a.lds_hh;
+        const uint16_t* hq = s_bhq + kb * a.lds_hh;
         // high-high rows: target block start + index in block
-        for (int k0 = 0; k0 < nh; k0 += GB) tab_hh_batch<T, CPL, GB>(X, hs, hc, k0, ie, acc);
+        for (int k0 = 0; k0 < nh; k0 += GB) {
+          VecT<T, CPL> nv[GB];
+          double cf[GB];
+#pragma unroll
+          for (int j = 0; j < GB; ++j) {
+            const int k = k0 + j;
+            const bool on = k < nh;
+            const uint32_t hsv = hs[k];
+            const uint32_t hqv = hq[k];
+            const uint32_t row = on ? hsv + ib : rho;
+            cf[j] = s_off[nll + (on ? hqv : 0u)];
+            cf[j] = on ? cf[j] : 0.0;
+            nv[j] = vload<T, CPL>(X + (row * ldu + cc));
+          }
+#pragma unroll
+          for (int j = 0; j < GB; ++j) {
+#pragma unroll
+            for (int i = 0; i < CPL; ++i) acc[i] = fma(cf[j], (double)nv[j].v[i], acc[i]);
+          }
+        }
         if (nmx > 0) {
           const uint32_t l = s_rl[r];
           const uint32_t h = s_bh[kb];

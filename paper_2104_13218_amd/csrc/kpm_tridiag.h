@@ -23,10 +23,14 @@ __host__ __device__ inline bool tridiag_ql_first_row(double* d, double* e, doubl
     int iter = 0;
     int m;
     do {
-      // smallest m >= l whose off-diagonal is negligible next to its diagonal pair
+      // smallest m >= l whose off-diagonal is negligible next to its diagonal
+      // pair (d[m + 1] carried to the next test in a register)
+      double dm = d[l];
       for (m = l; m < n - 1; ++m) {
-        const double dd = fabs(d[m]) + fabs(d[m + 1]);
+        const double dm1 = d[m + 1];
+        const double dd = fabs(dm) + fabs(dm1);
         if (fabs(e[m]) + dd == dd) break;
+        dm = dm1;
       }
       if (m != l) {
         if (++iter > 60) return false;
@@ -34,31 +38,41 @@ __host__ __device__ inline bool tridiag_ql_first_row(double* d, double* e, doubl
         double r = hypot(g, 1.0);
         g = d[m] - d[l] + e[l] / (g + copysign(r, g));
         double s = 1.0, c = 1.0, p = 0.0;
-        int i;
+        // the sweep from i = m - 1 down to l: z[i + 1] and d[i + 1] of each
+        // rotation are the values the previous one left, carried in registers
+        // (zc, dn) so that the serial chain does not pass through memory
+        double zc = z[m], dn = d[m];
         bool deflated = false;
-        for (i = m - 1; i >= l; --i) {
-          double f = s * e[i];
-          const double b = c * e[i];
-          r = hypot(f, g);
+        for (int i = m - 1; i >= l; --i) {
+          const double ei = e[i], di = d[i], zi = z[i];
+          double f = s * ei;
+          const double b = c * ei;
+          // f and g are of the order of the spectral width (Lanczos
+          // coefficients), far from float64 overflow and underflow: the plain
+          // norm and one reciprocal replace hypot and two divisions
+          r = sqrt(fma(f, f, g * g));
           e[i + 1] = r;
           if (r == 0.0) {
-            d[i + 1] -= p;
+            d[i + 1] = dn - p;
+            z[i + 1] = zc;
             e[m] = 0.0;
             deflated = true;
             break;
           }
-          s = f / r;
-          c = g / r;
-          g = d[i + 1] - p;
-          r = (d[i] - g) * s + 2.0 * c * b;
+          const double inv = 1.0 / r;
+          s = f * inv;
+          c = g * inv;
+          g = dn - p;
+          r = (di - g) * s + 2.0 * c * b;
           p = s * r;
           d[i + 1] = g + p;
           g = c * r - b;
-          f = z[i + 1];
-          z[i + 1] = s * z[i] + c * f;
-          z[i] = c * z[i] - s * f;
+          z[i + 1] = s * zi + c * zc;
+          zc = c * zi - s * zc;
+          dn = di;
         }
         if (deflated) continue;
+        z[l] = zc;
         d[l] -= p;
         e[l] = g;
         e[m] = 0.0;
