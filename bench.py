@@ -315,14 +315,19 @@ def other_workload(args, kpm, W, np, torch, dev):
         dt, _ = _timed(args, torch, lambda: kpm.sector_eigenvalues(ps, 1024))
         # Householder tridiagonalisation: 2 n^2 (A v) + 4 n^2 (rank-2 update) per column
         flops = float(sum(2.0 * s.dim ** 3 for s in small))
-        ach = flops / dt / 1e12
+        # ... at about half a flop per byte it is bound by memory: each step reads
+        # and writes the n x n trailing block once (16 n^2 bytes), n = D-1 .. 2
+        nbytes = float(sum(16.0 * ((s.dim - 1) * s.dim * (2 * s.dim - 1) // 6 - 1)
+                           for s in small if s.dim > 2))
+        ach = nbytes / dt / 1e9
         cfg = {"sectors": len(small), "max_dim": int(max(s.dim for s in small)),
                "states": int(sum(s.dim for s in small)), "storage": "f64", "device": dev}
-        # the whole call (build, ~3 launches per Householder step, bisection) against its flops
-        roof = {"bound": "alu", "kernel": "ed_* (one kpm_sector_eigenvalues call)", "achieved": ach,
-                "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS,
-                "algorithmic_flops_per_launch": flops, "traffic": None}
+        # the whole call (build, ~3 launches per Householder step, bisection) against its bytes
+        roof = {"bound": "hbm", "kernel": "ed_* (one kpm_sector_eigenvalues call)", "achieved": ach,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "algorithmic_bytes_per_launch": nbytes, "traffic": None,
+                "flops": {"algorithmic_flops_per_launch": flops, "achieved_TFLOPs": flops / dt / 1e12,
+                          "frac_of_fp64_vector_peak": flops / dt / 1e12 / FP64_VECTOR_PEAK_TFLOPS}}
         return _line(args, name, len(small) / dt, "sectors/s", dt, cfg, roof)
     if name == "j1j2_grad":
         wl = W.j1j2_grad_workload()
