@@ -1228,23 +1228,6 @@ std::vector<Tune> tune_candidates(const kpm_problem* p, int n, const kpm_params&
   return c;
 }
 
-size_t moments_workspace(const kpm_problem* p, int n, const kpm_params& q) {
-  std::vector<kpm_problem> need;
-  for (int i = 0; i < n; ++i)
-    if (std::isnan(p[i].e_lo) || std::isnan(p[i].e_hi)) need.push_back(p[i]);
-  const size_t lz = need.empty() ? 0 : lanczos_bytes(need.data(), (int)need.size(), lanczos_steps_of(q));
-  Planned P;
-  if (make_plan(p, n, shape_of(q), nullptr, nullptr, P) != KPM_OK) return 0;
-  size_t total = moments_layout(P, n_steps(q.M), lz).total;
-  if (q.autotune)
-    for (const Tune& t : tune_candidates(p, n, q)) {
-      Planned Pc;
-      if (make_plan(p, n, shape_of(q, &t), nullptr, nullptr, Pc) == KPM_OK)
-        total = std::max(total, moments_layout(Pc, n_steps(q.M), lz).total);
-    }
-  return total;
-}
-
 // Seconds per step of one candidate: plan, Rademacher start, two warm-up and
 // six timed steps (values are irrelevant to the timing).
 double time_candidate(const kpm_problem* p, int n, const kpm_params& q, const Tune& t,
@@ -1327,6 +1310,37 @@ int get_tune(const kpm_problem* p, int n, const kpm_params& q, const double* a, 
   out = pick;
   return KPM_OK;
 }
+
+size_t moments_workspace(const kpm_problem* p, int n, const kpm_params& q) {
+  std::vector<kpm_problem> need;
+  for (int i = 0; i < n; ++i)
+    if (std::isnan(p[i].e_lo) || std::isnan(p[i].e_hi)) need.push_back(p[i]);
+  const size_t lz = need.empty() ? 0 : lanczos_bytes(need.data(), (int)need.size(), lanczos_steps_of(q));
+  Planned P;
+  if (make_plan(p, n, shape_of(q), nullptr, nullptr, P) != KPM_OK) return 0;
+  size_t total = moments_layout(P, n_steps(q.M), lz).total;
+  if (q.autotune) {
+    // Before the first trial runs the workspace must hold every candidate's
+    // plan; once a shape is cached for these problems only its plan is run
+    // (planning all ~30 candidates took over a second per call on the 64
+    // random clusters).
+    std::vector<Tune> cands;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      auto it = g_tune_cache.find(tune_key(dev, p, n, q));
+      if (it != g_tune_cache.end()) cands.push_back(it->second);
+    }
+    if (cands.empty()) cands = tune_candidates(p, n, q);
+    for (const Tune& t : cands) {
+      Planned Pc;
+      if (make_plan(p, n, shape_of(q, &t), nullptr, nullptr, Pc) == KPM_OK)
+        total = std::max(total, moments_layout(Pc, n_steps(q.M), lz).total);
+    }
+  }
+  return total;
+}
+
 
 int graph_segment() {
   int S = env_int("KPM_GRAPH_SEGMENT", 64);
