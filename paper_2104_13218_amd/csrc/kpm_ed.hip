@@ -197,13 +197,25 @@ __global__ __launch_bounds__(kThreads) void ed_hh_update_kernel(const EigArgs a,
 // Number of eigenvalues below x of the symmetric tridiagonal matrix (d, e):
 // the negative pivots of the LDL^T factorisation of T - x (Sturm sequence),
 // a pivot of magnitude below pivmin taken as -pivmin.
+// 1/q from the hardware estimate and two Newton steps, r <- r (2 - q r)
+// (each squares the relative error; |q| >= pivmin keeps q normal): the
+// quotient below then differs from a correctly rounded division by a few ulps,
+// which moves no pivot's sign except at the rounding level that bounds the
+// bisection anyway, at a fraction of the divide sequence's latency on this
+// serial chain.
+__device__ __forceinline__ double sturm_recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return fma(r, fma(-q, r, 1.0), r);
+}
+
 __device__ __forceinline__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
   int cnt = 0;
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   cnt += q < 0.0;
   for (int i = 1; i < n; ++i) {
-    q = (d[i] - x) - e2[i - 1] / q;
+    q = (d[i] - x) - e2[i - 1] * sturm_recip(q);
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
   }
