@@ -74,6 +74,8 @@ def _parse():
     ap.add_argument("--workload", default="ring24_sz0",
                     choices=["ring24_sz0", "batched_rr3", "j1j2_grad", "rr4_30", "ftlm_ring24", "fe10",
                              "ed_batched"])
+    ap.add_argument("--accuracy-curve", default=None, metavar="PATH",
+                    help="also write the per-T float32-vs-float64 error curves of C and chi (JSON)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (reference for HBM byte counters)")
     return ap.parse_args()
@@ -399,6 +401,7 @@ def extras(args, kpm, W, np, torch, sec, ps, T, M, value, ws):
     mu32, ab32 = kpm.chebyshev_moments(allsec, M, 10, "complex_gaussian", "fp32", 0.025, 0, col_block=20)
     Th = T.cpu().numpy()
     acc = {"moments_max_abs_err_over_mu0": float((mu32 - mu64).abs().max(dim=1).values.div(mu64[:, 0]).max())}
+    curves = {"T": Th.tolist()}
     for kern in ("jackson", "none"):
         t64 = kpm.thermo(mu64, ab64, allsec, T, kern)
         t32 = kpm.thermo(mu32, ab32, allsec, T, kern)
@@ -411,6 +414,8 @@ def extras(args, kpm, W, np, torch, sec, ps, T, M, value, ws):
             a = t64[qn].cpu().numpy()[0]
             b = t32[qn].cpu().numpy()[0]
             err = np.abs(a - b) / np.abs(a[band]).max()
+            curves[f"{kern}_{qn}_err_over_peak"] = err.tolist()
+            curves[f"{kern}_{qn}_fp64"] = a.tolist()
             rec[f"{qn}_max_err_T>=T_phys"] = float(err[band].max())
             ok = np.nonzero(err <= 1e-6)[0]
             lowest = None
@@ -425,6 +430,11 @@ def extras(args, kpm, W, np, torch, sec, ps, T, M, value, ws):
             rec[f"{qn}_max_rel_err_T>=T_phys"] = float(np.nanmax(np.abs(a - b) / np.abs(a)))
         acc[kern] = rec
     out["accuracy_fp32_vs_fp64_all_sectors"] = acc
+    if args.accuracy_curve:
+        with open(args.accuracy_curve, "w") as f:
+            json.dump({"workload": "ring N=24, all S^z >= 0 sectors, 10 complex Gaussian vectors, M=%d" % M,
+                       **curves, **{k: v for k, v in acc.items() if k != "moments_max_abs_err_over_mu0"},
+                       "moments_max_abs_err_over_mu0": acc["moments_max_abs_err_over_mu0"]}, f)
 
     return out
 
