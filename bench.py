@@ -431,6 +431,16 @@ def extras(args, kpm, W, np, torch, sec, ps, T, M, value, ws):
         acc[kern] = rec
     out["accuracy_fp32_vs_fp64_all_sectors"] = acc
     if args.accuracy_curve:
+        # conditioning of C(T) in the moments, from the thermodynamics VJP at
+        # one temperature at a time: kappa(T) = sum_{p,n} |dC/dmu_pn| mu_p0 / |C|
+        one, zero = np.ones((1, 1)), np.zeros((1, 1))
+        for kern in ("jackson", "none"):
+            C64 = kpm.thermo(mu64, ab64, allsec, T, kern)["C"].cpu().numpy()[0]
+            kap = []
+            for i in range(Th.size):
+                lam = kpm.thermo_vjp(mu64, ab64, allsec, Th[i:i + 1], one, zero, kern)
+                kap.append(float((lam.abs() * mu64[:, :1]).sum()) / abs(float(C64[i])))
+            curves[f"{kern}_C_condition"] = kap
         with open(args.accuracy_curve, "w") as f:
             json.dump({"workload": "ring N=24, all S^z >= 0 sectors, 10 complex Gaussian vectors, M=%d" % M,
                        **curves, **{k: v for k, v in acc.items() if k != "moments_max_abs_err_over_mu0"},
