@@ -134,8 +134,8 @@ def main():
     args = _parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the work would shard over independent sectors and column blocks; see the design notes).",
+        print("bench.py runs on one GPU only: there is no multi-GPU path "
+              "(the work would shard over independent sectors and column blocks).",
               file=sys.stderr)
         sys.exit(2)
 

@@ -10,9 +10,8 @@ only common module is `workloads`, which describes problems (bond lists,
 sectors, temperature grids) and does none of the method's arithmetic.
 
 Every function cites the passage of the paper it follows (section / equation).
-Points where the paper is silent or ambiguous are resolved by the readings
-listed in the repository's design notes; the ones used here are restated in
-the docstrings.
+Points where the paper is silent or ambiguous are resolved by explicit
+readings, each restated in the docstring of the function that uses it.
 
 Modules
   basis        S^z-sector enumeration, combinatorial-number-system rank
