@@ -317,6 +317,20 @@ int chebyshev_moments_vjp_resume(const kpm_problem* p, int32_t n, const kpm_para
                                  const double* d_ab, const double* d_dmu, int32_t ckpt_every,
                                  double* d_dJ, void* d_work, size_t work_bytes, void* stream);
 
+/* Derivatives with respect to each cluster's couplings: the sectors of one
+ * cluster (problems sharing its id) share its bond list, and Z is the sum over
+ * sectors (Sec. II, below Eq. (9)), so dL/dJ_b of the cluster is the sum of
+ * the per-sector derivatives.  d_dJ: device double, problem after problem in
+ * bond order, as written by chebyshev_moments_vjp, chebyshev_moments_vjp_resume
+ * or kpm_thermo_grad; d_dJ_cluster: device double, cluster after cluster (ids
+ * ascending, 1 + largest id of them), each cluster's bonds in bond order (an
+ * id with no problem contributes nothing).  Sums are formed in problem order
+ * on `stream`, complete at return.  Errors: KPM_EINVAL (problems of one
+ * cluster with different bond counts, invalid problems or NULL pointers),
+ * KPM_ENOMEM, KPM_EDEVICE. */
+int kpm_cluster_bond_grad(const kpm_problem* p, int32_t n, const double* d_dJ, double* d_dJ_cluster,
+                          void* stream);
+
 /* Loss and gradient in one call: moments, thermodynamics, their derivative
  * and the recursion adjoint, with the recursion run forward once (its
  * checkpointed pass gives the moments).  d_T [n_T], d_wC, d_wchi
@@ -355,7 +369,8 @@ typedef struct {
   int32_t rows_per_tile;   /* basis states per workgroup tile (block kernels: mean) */
   int32_t graph_segment;   /* steps per captured graph (0 = direct launches) */
   int32_t kernel;          /* step kernel used: 0 column-chunk, 1 row, 2 block,
-                              3 block-table, 4 spin-s */
+                              3 block-table, 4 spin-s, 5 slice (block-table
+                              tiles, each wave on rows of one block) */
   double recursion_ms;     /* hipEvent time on the call's stream from the first
                               to the last recursion-step launch, inclusive */
   int32_t relabelled;      /* problems whose sites the block kernels relabel (fewer

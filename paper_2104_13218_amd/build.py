@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libkpm.so")
-SOURCES = ["kpm_kernels.hip", "kpm_thermo.hip", "kpm_adjoint.hip", "kpm_ftlm.hip", "kpm_ed.hip",
+SOURCES = ["kpm_kernels.hip", "kpm_slice.hip", "kpm_thermo.hip", "kpm_adjoint.hip", "kpm_ftlm.hip", "kpm_ed.hip",
            "kpm_api.hip"]
 ARCH = os.environ.get("KPM_OFFLOAD_ARCH", "gfx950")
 

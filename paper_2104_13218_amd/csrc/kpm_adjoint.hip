@@ -294,6 +294,30 @@ hipError_t launch_bond_reduce(const BondReduceArgs& a, int total_bonds, hipStrea
   return hipGetLastError();
 }
 
+// Per-cluster sums of per-problem bond derivatives: workgroup row c = cluster,
+// one thread per bond; problems added in their order.  info: per problem
+// (cluster, offset of its bonds in dJ); cinfo: per cluster (output offset,
+// bond count).
+__global__ __launch_bounds__(kThreads) void cluster_grad_kernel(const int32_t* info, int n,
+                                                               const int32_t* cinfo, const double* dJ,
+                                                               double* out) {
+  const int c = blockIdx.y;
+  const int b = blockIdx.x * kThreads + threadIdx.x;
+  if (b >= cinfo[2 * c + 1]) return;
+  double s = 0.0;
+  for (int q = 0; q < n; ++q)
+    if (info[2 * q] == c) s += dJ[info[2 * q + 1] + b];
+  out[cinfo[2 * c] + b] = s;
+}
+
+hipError_t launch_cluster_grad(const int32_t* info, int n, const int32_t* cinfo, int n_clusters,
+                               int max_bonds, const double* dJ, double* out, hipStream_t st) {
+  if (n_clusters <= 0 || max_bonds <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cluster_grad_kernel, dim3((max_bonds + kThreads - 1) / kThreads, n_clusters),
+                     dim3(kThreads), 0, st, info, n, cinfo, dJ, out);
+  return hipGetLastError();
+}
+
 // L = sum_{c,T} wC C + wchi chi (one workgroup, fixed-order tree).
 __global__ __launch_bounds__(kThreads) void loss_kernel(const double* C, const double* chi,
                                                         const double* wC, const double* wchi,

@@ -204,12 +204,13 @@ size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 // Launch shape chosen by the autotuner (0 / -1 = the planner's heuristic);
 // KPM_* environment variables, when set, override both.
 struct Tune {
-  int kernel = -1;        // -1 heuristic, 0 column-chunk, 1 row, 2 block, 3 block-table
+  int kernel = -1;        // -1 heuristic, 0 column-chunk, 1 row, 2 block, 3 block-table, 5 slice
   int col_block = 0;      // real columns per block
   int block_L = 0;        // low bits of a block (block kernel)
   int spt = 0;            // sub-tiles per workgroup (block kernel) / tiles' sub-tiles
   int gather_batch = 0;   // neighbour rows in flight per lane
   int lds_x = -1;         // block-table kernel: 1 rows of v_n staged in LDS, 0 not, -1 heuristic
+  int rows = 0;           // slice kernel: rows per sub-tile (0 = heuristic)
 };
 
 struct RunShape {
@@ -247,12 +248,15 @@ struct Planned {
   std::vector<uint32_t> blk_h, blk_start;
   std::vector<int32_t> sub_blk0, sub_nblk, koff;
   std::vector<uint16_t> lunr;
+  std::vector<uint32_t> cmask;        // bonds in class order (slice kernel)
+  std::vector<double> coff, czz;
   DevicePlan plan;
   double bytes_per_step = 0;     // algorithmic (3 * storage * dim * real columns)
   double state_cols = 0;         // sum of dim * real columns
   // byte offsets of the packed plan arrays
   size_t o_probs, o_units, o_tile, o_job, o_pu0, o_tab, o_mask, o_off, o_zz, o_binom, o_trow0,
-      o_tnrows, o_bperm, o_tsub0, o_subn, o_lrank, o_bh, o_bst, o_sb0, o_snb, o_lunr, o_koff, bytes;
+      o_tnrows, o_bperm, o_tsub0, o_subn, o_lrank, o_bh, o_bst, o_sb0, o_snb, o_lunr, o_koff, o_cmask,
+      o_coff, o_czz, bytes;
 };
 
 int env_int(const char* name, int dflt) {
@@ -492,8 +496,14 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
     adj_ld = 1;
     while (adj_ld < rb) adj_ld <<= 1;
   }
+  // slice kernel (KPM_BLOCK=3 or tuned): rows of one or two 16-byte chunks, so
+  // blocks of at most 8 float32 / 4 float64 columns, every unit padded to the
+  // same width
+  const bool slice_req =
+      !s.adjoint && env_int("KPM_BLOCK", s.tune.kernel == 5 ? 3 : -1) == 3;
+  if (slice_req) rb = std::min(rb, fp32 ? 8 : 4);
   int cpl = 1;
-  if (fp32) cpl = rb >= 4 ? 4 : (rb >= 2 ? 2 : 1);
+  if (fp32) cpl = rb >= (slice_req ? 3 : 4) ? 4 : (rb >= 2 ? 2 : 1);
   else cpl = rb >= 2 ? 2 : 1;
   if (const int f = env_int("KPM_CPL", 0)) cpl = f;
   if (adj_ld) cpl = std::min(cpl, adj_ld);
@@ -607,23 +617,33 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   // Default: the block-table kernel for blocks too wide for the row kernel
   // (the measured case where it is the fastest kernel); KPM_BLOCK=0/1/2 and
   // the autotuner override.
-  const int block_env = env_int("KPM_BLOCK", kern < 0 ? -1 : (kern == 2 ? 1 : (kern == 3 ? 2 : 0)));
+  const int block_env = env_int("KPM_BLOCK", kern < 0 ? -1
+                                                 : (kern == 2 ? 1 : (kern == 3 ? 2 : (kern == 5 ? 3 : 0))));
   const bool block_default = rb > 8;
   // the block-table kernel addresses a block's slot with 32-bit element offsets
   int64_t max_elems = 0;
   for (int i = 0; i < n; ++i)
     max_elems = std::max<int64_t>(max_elems, (int64_t)prob_dim(p[i]) *
                                                  ((rb + cpl - 1) / cpl * cpl));
-  const bool tab = (block_env == 2 || (block_env < 0 && block_default)) && max_elems < (int64_t(1) << 32);
+  // the slice kernel uses the block-table kernel's tiles and tables (64-bit offsets)
+  const bool slice = block_env == 3;
+  const bool tab =
+      slice || ((block_env == 2 || (block_env < 0 && block_default)) && max_elems < (int64_t(1) << 32));
   if (!spin && !s.adjoint && s.allow_row && (block_env == 1 || tab || (block_env < 0 && block_default))) {
     D.ld_max = adj_ld ? adj_ld : (rb + cpl - 1) / cpl * cpl;
-    D.blk_max = std::max(1, std::min(255, env_int("KPM_BLOCK_MAX", 16)));
+    // slice kernel: one lane per block of a sub-tile in its table pass (<= 64)
+    D.blk_max = slice ? std::max(1, std::min(64, env_int("KPM_BLOCK_MAX", 64)))
+                      : std::max(1, std::min(255, env_int("KPM_BLOCK_MAX", 16)));
     const size_t cap = (size_t)env_int("KPM_BLOCK_LDS", 64 * 1024);
     // rows of v_n staged in LDS: measured faster for float32 storage only
-    D.tab_xl = tab ? env_int("KPM_TAB_XL", s.tune.lds_x >= 0 ? s.tune.lds_x : fp32) != 0 : 0;
-    for (int rows = std::min(kThreads, std::max(32, env_int("KPM_BLOCK_ROWS", kThreads)));
-         rows >= 32 && !D.block; rows >>= 1) {
+    D.tab_xl = tab && !slice ? env_int("KPM_TAB_XL", s.tune.lds_x >= 0 ? s.tune.lds_x : fp32) != 0 : 0;
+    // slice kernel: sub-tiles of up to 1024 rows whose LDS copy of v_n stays
+    // near 16 KB (the per-sub-tile barrier is paid once per sub-tile)
+    const int rows0 = std::min(kThreads, std::max(32, env_int("KPM_BLOCK_ROWS", kThreads)));
+    for (int rows = rows0; rows >= 32 && !D.block; rows >>= 1) {
       int Lm = std::max(1, std::min(env_int("KPM_BLOCK_L", s.tune.block_L > 0 ? s.tune.block_L : 9), 16));
+      // slice kernel: blocks of at most 254 members (u8 LDS row numbers)
+      if (slice) Lm = std::min(Lm, 10);
       while (Lm > 1 && binom64(Lm, Lm / 2) > (uint64_t)rows) --Lm;
       int lr = 1, hh = 1, mx = 1, ll = 1;
       for (int i = 0; i < n; ++i) {
@@ -666,8 +686,32 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
       D.lds_mx = mx;
       D.lds_ll = ll;
       // the block-table kernel packs (row, low-low bond) into 16 bits
-      if ((tab ? tab_lds_bytes(D) : block_lds_bytes(D)) <= cap && (!tab || ll <= 255))
+      if (slice) {
+        // word rows must hold each problem's mixed and low-low bonds, and a
+        // slot must fit 32-bit buffer offsets
+        int wb = 32, brows = 1;
+        bool ok = (int64_t)max_elems * elt < (int64_t(1) << 32);
+        // every unit is padded to the same width, 1 or 2 chunks of cpl columns
+        const int nchu = D.ld_max / cpl;
+        ok = ok && !adj_ld && (nchu == 1 || (nchu == 2 && cpl == (fp32 ? 4 : 2)));
+        for (int i = 0; i < n && ok; ++i) {
+          const int w = slice_word_bytes(P.probs[i].n_mx, P.probs[i].n_ll);
+          ok = w > 0;
+          wb = std::max(wb, w);
+          brows = std::max(brows, (int)binom64(P.probs[i].blk_L, P.probs[i].blk_L / 2));
+        }
+        D.slice_wb = wb;
+        D.slice_words = lr;
+        D.blk_lds_rows = brows;
+        if (ok && brows <= 254 && slice_lds_bytes(D) <= cap) {
+          D.block = 3;
+        } else {
+          D.slice_wb = D.slice_words = D.blk_lds_rows = 0;
+          break;
+        }
+      } else if ((tab ? tab_lds_bytes(D) : block_lds_bytes(D)) <= cap && (!tab || ll <= 255)) {
         D.block = tab ? 2 : 1;
+      }
     }
   }
   int bspt = 1;
@@ -687,6 +731,12 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   if (const int f = env_int("KPM_GATHER_BATCH", 0)) D.gather_batch = f;
   if (D.gather_batch != 2 && D.gather_batch != 4 && D.gather_batch != 8) D.gather_batch = 4;
   if (!row_ld && D.gather_batch < 4) D.gather_batch = 4;
+  // slice kernel: high-high rows in flight per lane per batch (4 or 8; default 8)
+  if (D.block == 3) {
+    D.gather_batch = s.tune.gather_batch > 0 ? s.tune.gather_batch : 8;
+    if (const int f = env_int("KPM_GATHER_BATCH", 0)) D.gather_batch = f;
+    if (D.gather_batch != 4) D.gather_batch = 8;
+  }
   if (D.block) {
     D.row_ld = row_ld = 0;
     size_t max_sub = 1;
@@ -737,6 +787,8 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
     const double per_sub = 3.0 * D.blk_rows * D.ld_max * elt;
     int spt = (int)std::ceil(8.0 * fixed / per_sub);
     spt = (int)std::max<size_t>(1, std::min<size_t>((size_t)spt, std::max<size_t>(1, max_sub / 2048)));
+    // slice kernel: about 1000 rows per one-wave workgroup (no per-tile LDS fill)
+    if (D.block == 3) spt = 4;
     if (s.tune.spt > 0) spt = s.tune.spt;
     if (const int f = env_int("KPM_SUB_PER_TILE", 0)) spt = f;
     bspt = std::max(1, std::min(spt, 64));
@@ -769,6 +821,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
       u.prob = i;
       u.ncols = (int32_t)std::min<int64_t>(rb, nc - c0);
       u.ld = adj_ld ? adj_ld : (row_ld ? row_ld : (u.ncols + cpl - 1) / cpl * cpl);
+      if (D.block == 3) u.ld = D.ld_max;   // the slice kernel's width is a template constant
       u.col0 = (int32_t)c0;
       u.vec_off = vec_elems;
       vec_elems += (int64_t)align_up((size_t)(dim * u.ld), 64);
@@ -813,10 +866,16 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   P.prob_unit0.push_back((int32_t)P.units.size());
   // the row and block kernels also stream the 4-byte state word of every row;
   // the block-table kernel reads its per-block tables instead
+  // the per-block table layout depends on the problem count (word tables)
+  D.n_probs = n;
   if (D.block >= 2) {
     for (const auto& u : P.units) {
       const ProbDev& d = P.probs[u.prob];
       P.bytes_per_step += (double)d.n_blk * (12.0 + 6.0 * d.n_hh + 4.0 * d.n_mx);
+      // slice kernel: per block the coefficients and the diagonal part, per
+      // unit the word table
+      if (D.block == 3)
+        P.bytes_per_step += (double)d.n_blk * (8.0 + 8.0 * d.n_hh) + (double)(1u << d.blk_L) * D.slice_wb;
     }
     D.n_states = (int64_t)((tab_meta_bytes(D) + 3) / 4);
   } else if (D.row_ld || D.block) {
@@ -827,6 +886,21 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
       const ProbDev& d = P.probs[u.prob];
       P.bytes_per_step += (8.0 + 8.0 * d.n_bonds) * (double)d.dim;
     }
+  }
+  // bonds in class order (the slice kernel reads them with scalar loads)
+  for (int i = 0; i < n; ++i)
+    for (int q = 0; q < p[i].n_bonds; ++q) {
+      const int b = P.probs[i].bond_off + P.bperm[P.probs[i].bond_off + q];
+      P.cmask.push_back(P.bmask[b]);
+      P.coff.push_back(P.boff[b]);
+      P.czz.push_back(P.bzz[b]);
+    }
+  // zeros past the last bond: the slice kernel reads a few entries past a
+  // problem's class ranges and uses them with zero weight
+  for (int t = 0; t < 16; ++t) {
+    P.cmask.push_back(0);
+    P.coff.push_back(0);
+    P.czz.push_back(0);
   }
   P.tile_sub0.push_back((int32_t)P.sub_nrows.size());
   if (P.sub_nrows.empty()) P.sub_nrows.push_back(0);
@@ -869,6 +943,9 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   P.o_snb = put(P.sub_nblk.size() * 4);
   P.o_lunr = put(P.lunr.size() * 2);
   P.o_koff = put(P.koff.size() * 4);
+  P.o_cmask = put(P.cmask.size() * 4);
+  P.o_coff = put(P.coff.size() * 8);
+  P.o_czz = put(P.czz.size() * 8);
   P.bytes = o;
   return KPM_OK;
 }
@@ -902,6 +979,9 @@ int upload_plan(Planned& P, unsigned char* dst, std::vector<unsigned char>& stag
   cp(P.o_snb, P.sub_nblk.data(), P.sub_nblk.size() * 4);
   cp(P.o_lunr, P.lunr.data(), P.lunr.size() * 2);
   cp(P.o_koff, P.koff.data(), P.koff.size() * 4);
+  cp(P.o_cmask, P.cmask.data(), P.cmask.size() * 4);
+  cp(P.o_coff, P.coff.data(), P.coff.size() * 8);
+  cp(P.o_czz, P.czz.data(), P.czz.size() * 8);
   KPM_HIP(hipMemcpyAsync(dst, staging.data(), P.bytes, hipMemcpyHostToDevice, st));
   DevicePlan& D = P.plan;
   D.probs = reinterpret_cast<ProbDev*>(dst + P.o_probs);
@@ -926,6 +1006,9 @@ int upload_plan(Planned& P, unsigned char* dst, std::vector<unsigned char>& stag
   D.sub_nblk = reinterpret_cast<int32_t*>(dst + P.o_snb);
   D.lunr = reinterpret_cast<uint16_t*>(dst + P.o_lunr);
   D.koff = reinterpret_cast<int32_t*>(dst + P.o_koff);
+  D.cmask = reinterpret_cast<uint32_t*>(dst + P.o_cmask);
+  D.coff = reinterpret_cast<double*>(dst + P.o_coff);
+  D.czz = reinterpret_cast<double*>(dst + P.o_czz);
   return KPM_OK;
 }
 
@@ -1224,6 +1307,18 @@ std::vector<Tune> tune_candidates(const kpm_problem* p, int n, const kpm_params&
         b.lds_x = xl;
         c.push_back(b);
       }
+    // slice kernel (blocks of at most two 16-byte chunks per row): 10 low
+    // bits, 1-3 sub-tiles per workgroup, 4 or 8 high-high rows in flight
+    if (w <= (fp32 ? 8 : 4))
+      for (int spt : {1, 2, 3})
+        for (int gh : {4, 8}) {
+          Tune b = t;
+          b.kernel = 5;
+          b.block_L = 10;
+          b.spt = spt;
+          b.gather_batch = gh;
+          c.push_back(b);
+        }
   }
   return c;
 }
@@ -1270,9 +1365,16 @@ std::string tune_key(int dev, const kpm_problem* p, int n, const kpm_params& q) 
   std::string k = std::to_string(dev) + "|" + std::to_string(q.precision) + "," +
                   std::to_string(q.vec_kind) + "," + std::to_string(q.R) + "," +
                   std::to_string(q.col_block) + "|";
-  for (int i = 0; i < n; ++i)
-    k += std::to_string(p[i].n_sites) + "." + std::to_string(p[i].n_up) + "." +
-         std::to_string(p[i].n_bonds) + ";";
+  for (int i = 0; i < n; ++i) {
+    // the bond graph and the site spin fix the launch shape (couplings do not)
+    uint64_t hsh = 1469598103934665603ull;   // FNV-1a over the bond list
+    for (int b = 0; b < p[i].n_bonds; ++b) {
+      const uint32_t e = (uint32_t)p[i].bond_i[b] | ((uint32_t)p[i].bond_j[b] << 16);
+      for (int t = 0; t < 4; ++t) hsh = (hsh ^ ((e >> (8 * t)) & 0xFFu)) * 1099511628211ull;
+    }
+    k += std::to_string(p[i].n_sites) + "." + std::to_string(p[i].n_up) + "." + std::to_string(p[i].n_bonds) +
+         "." + std::to_string(two_s_of(p[i])) + "." + std::to_string(hsh) + ";";
+  }
   return k;
 }
 
@@ -1449,7 +1551,7 @@ int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
     for (int32_t r : P.tile_nrows) rows += r;
     g_stats.rows_per_tile = (int32_t)std::lround(rows / (double)P.tile_nrows.size());
   }
-  g_stats.kernel = D.spin ? 4 : (D.block == 2 ? 3 : (D.block ? 2 : (D.row_ld ? 1 : 0)));
+  g_stats.kernel = D.spin ? 4 : (D.block == 3 ? 5 : (D.block == 2 ? 3 : (D.block ? 2 : (D.row_ld ? 1 : 0))));
   g_stats.graph_segment = used_segment;
   g_stats.relabelled = 0;
   for (const auto& d : P.probs) g_stats.relabelled += d.relabel;
@@ -2413,6 +2515,46 @@ int chebyshev_moments_vjp_resume(const kpm_problem* p, int32_t n, const kpm_para
   KPM_HIP(hipStreamSynchronize(st));
   return run_vjp(p, n, *q, h_ab.data(), d_dmu, ckpt_every, d_dJ, static_cast<unsigned char*>(d_work), st,
                  nullptr, {}, kVjpReverse);
+}
+
+int kpm_cluster_bond_grad(const kpm_problem* p, int32_t n, const double* d_dJ, double* d_dJ_cluster,
+                          void* stream) {
+  if (!p || n <= 0 || !d_dJ || !d_dJ_cluster) return KPM_EINVAL;
+  if (const int e = check_problems(p, n)) return e;
+  int nc = 0, max_b = 0;
+  for (int i = 0; i < n; ++i) nc = std::max(nc, p[i].cluster + 1);
+  std::vector<int32_t> info(2 * (size_t)n), cinfo(2 * (size_t)nc, 0), nb(nc, -1);
+  int32_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    const int c = p[i].cluster;
+    if (nb[c] >= 0 && nb[c] != p[i].n_bonds) return KPM_EINVAL;   // one bond list per cluster
+    nb[c] = p[i].n_bonds;
+    info[2 * i] = c;
+    info[2 * i + 1] = off;
+    off += p[i].n_bonds;
+  }
+  int32_t out = 0;
+  for (int c = 0; c < nc; ++c) {
+    cinfo[2 * c] = out;
+    cinfo[2 * c + 1] = std::max(nb[c], 0);
+    out += cinfo[2 * c + 1];
+    max_b = std::max(max_b, cinfo[2 * c + 1]);
+  }
+  if (max_b == 0) return KPM_OK;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  StreamSync sync{st};
+  int32_t* d_tab = nullptr;
+  const size_t bytes = (info.size() + cinfo.size()) * sizeof(int32_t);
+  if (hipMalloc(&d_tab, bytes) != hipSuccess) return KPM_ENOMEM;
+  int rc = KPM_OK;
+  if (hipMemcpyAsync(d_tab, info.data(), info.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(d_tab + info.size(), cinfo.data(), cinfo.size() * 4, hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      launch_cluster_grad(d_tab, n, d_tab + info.size(), nc, max_b, d_dJ, d_dJ_cluster, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    rc = KPM_EDEVICE;
+  (void)hipFree(d_tab);
+  return rc;
 }
 
 int kpm_thermo_grad(const kpm_problem* p, int32_t n, const kpm_params* q, int32_t kernel,

@@ -14,6 +14,7 @@ constexpr int kMaxBonds = 512;    // bonds per problem
 constexpr int kMaxLd = 64;        // real columns per recursion block (padded)
 constexpr int kBinomN = 33;       // binomial table C(n, j), n, j < 33
 constexpr int kKoffLen = 34;      // popcount-class offsets of the low-word table (0..32, end)
+constexpr uint32_t kNoRun = 0xFFFFFFFFu;   // per-block table entry: no target block
 
 // One (cluster, S^z sector) problem as the kernels see it.
 struct ProbDev {
@@ -119,6 +120,16 @@ struct StepArgs {
   const uint32_t* meta_mstart; // [n_blk][meta_mx] per mixed bond: target block's first rank
   int32_t meta_hh, meta_mx;    // row lengths of the per-block tables (>= 1)
   int32_t lds_ll;              // low-low bond capacity per row (block-table kernel)
+  // slice kernel
+  const uint32_t* cmask;       // per bond in class order (bond_off + q): mask
+  const double* coff;          // ... J_b / (2a)
+  const double* czz;           // ... J_b / (4a)
+  const double* meta_hcoef;    // [n_blk][meta_hh] J_b/(2a) of each acting high-high bond
+  const double* meta_dhh;      // [n_blk] -b/a + high-high part of the diagonal
+  const uint8_t* wtab;         // [n_probs][slice_words][slice_wb] word tables
+  int32_t slice_wb;            // bytes per word-table row (32 or 64)
+  int32_t slice_words;         // rows per problem (1 << largest blk_L)
+  int32_t blk_lds_rows;        // largest block (members), LDS rows of the slice kernel
 };
 
 // Device-side plan of one run (pointers into the workspace) + launch shape.
@@ -157,6 +168,8 @@ struct DevicePlan {
   int32_t gather_batch = 4;    // neighbour rows in flight per lane (2, 4 or 8)
   int32_t block = 0;           // 1: block kernel (tiles of whole low-bit blocks),
                                // 2: block-table kernel (same tiles, per-block tables),
+                               // 3: slice kernel (block-table tiles and tables, each
+                               //    wave on rows of one block at a time),
   int32_t n_blk = 0;           // block-table kernel: blocks of all problems
   int32_t meta_hh = 1, meta_mx = 1;   // per-block table widths (StepArgs)
   int32_t tab_xl = 0;          // block-table kernel: sub-tile rows of v_n staged in LDS
@@ -166,6 +179,12 @@ struct DevicePlan {
                                // [lds_nb][dim] u32 neighbour ranks (slot 2b + w: bond b,
                                // w = 0 S^+_i S^-_j, w = 1 S^-_i S^+_j; written when acting)
   int32_t lds_ll = 1;          // block-table kernel: low-low bond capacity per row (<= 255)
+  uint32_t* cmask = nullptr;   // bonds of every problem in class order (slice kernel)
+  double* coff = nullptr;
+  double* czz = nullptr;
+  int32_t slice_wb = 0;        // slice kernel: word-table row bytes (0 = no slice plan)
+  int32_t slice_words = 0;     // slice kernel: word-table rows per problem
+  int32_t blk_lds_rows = 0;    // slice kernel: members of the largest block
   int32_t blk_max = 16, blk_rows = kThreads, lds_lr = 1, lds_hh = 1, lds_mx = 1, ld_max = 1;
   int64_t n_states = 0;        // entries of the state table
   int64_t part_len = 0;        // doubles per partial buffer
@@ -400,6 +419,8 @@ size_t adjoint_lds_bytes(const DevicePlan& p);
 hipError_t launch_doubling_vjp(const DoublingVjpArgs& a, hipStream_t st);
 hipError_t launch_adjoint(const DevicePlan& p, AdjArgs a, int ld, hipStream_t st);
 hipError_t launch_bond_reduce(const BondReduceArgs& a, int total_bonds, hipStream_t st);
+hipError_t launch_cluster_grad(const int32_t* info, int n, const int32_t* cinfo, int n_clusters,
+                               int max_bonds, const double* dJ, double* out, hipStream_t st);
 hipError_t launch_loss(const double* C, const double* chi, const double* wC, const double* wchi,
                        int n, double* L, hipStream_t st);
 
@@ -435,6 +456,10 @@ size_t row_lds_bytes(const DevicePlan& p);
 size_t block_lds_bytes(const DevicePlan& p);
 size_t spin_lds_bytes(const DevicePlan& p);
 size_t tab_lds_bytes(const DevicePlan& p);
+size_t slice_lds_bytes(const DevicePlan& p);
+int slice_word_bytes(int n_mx, int n_ll);   // 32, 64, or 0 when a word row cannot hold the bonds
+hipError_t build_slice_words(const DevicePlan& p, uint8_t* wtab, hipStream_t st);
+hipError_t launch_slice(const DevicePlan& p, const StepArgs& a, hipStream_t st);
 // Bytes of the per-block tables of the block-table kernel (kept in the state
 // table region; built by fill_states).
 size_t tab_meta_bytes(const DevicePlan& p);

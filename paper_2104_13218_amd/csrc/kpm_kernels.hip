@@ -22,103 +22,9 @@
 
 #include "kpm_device.h"
 #include "kpm_internal.h"
+#include "kpm_vec.h"
 
 namespace kpm {
-
-// ------------------------------------------------------------------ helpers
-
-template <typename T, int N>
-struct alignas(sizeof(T) * N >= 16 ? 16 : sizeof(T) * N) VecT {
-  T v[N];
-};
-
-template <typename T, int N>
-__device__ __forceinline__ VecT<T, N> vload(const T* p) {
-  return *reinterpret_cast<const VecT<T, N>*>(p);
-}
-template <typename T, int N>
-__device__ __forceinline__ void vstore(T* p, const VecT<T, N>& x) {
-  *reinterpret_cast<VecT<T, N>*>(p) = x;
-}
-
-// Non-temporal (streaming) 16-byte accesses for data touched once per step:
-// v_{n-1} is read once and v_{n+1} written once, so they should not displace
-// the gathered rows of v_n from the caches.
-template <typename T, int N>
-struct NtVec;
-template <> struct NtVec<float, 4> { typedef float type __attribute__((ext_vector_type(4))); };
-template <> struct NtVec<float, 2> { typedef float type __attribute__((ext_vector_type(2))); };
-template <> struct NtVec<float, 1> { typedef float type; };
-template <> struct NtVec<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
-template <> struct NtVec<double, 1> { typedef double type; };
-
-template <typename T, int N>
-__device__ __forceinline__ VecT<T, N> vload_nt(const T* p) {
-  VecT<T, N> r;
-  if constexpr (N == 4 && sizeof(T) == 8) {
-    typedef typename NtVec<double, 2>::type V;
-    const V a = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
-    const V b = __builtin_nontemporal_load(reinterpret_cast<const V*>(p) + 1);
-    r.v[0] = a[0]; r.v[1] = a[1]; r.v[2] = b[0]; r.v[3] = b[1];
-  } else if constexpr (N == 1) {
-    r.v[0] = __builtin_nontemporal_load(p);
-  } else {
-    typedef typename NtVec<T, N>::type V;
-    const V a = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
-#pragma unroll
-    for (int i = 0; i < N; ++i) r.v[i] = a[i];
-  }
-  return r;
-}
-
-template <typename T, int N>
-__device__ __forceinline__ void vstore_nt(T* p, const VecT<T, N>& x) {
-  if constexpr (N == 4 && sizeof(T) == 8) {
-    typedef typename NtVec<double, 2>::type V;
-    V a, b;
-    a[0] = x.v[0]; a[1] = x.v[1]; b[0] = x.v[2]; b[1] = x.v[3];
-    __builtin_nontemporal_store(a, reinterpret_cast<V*>(p));
-    __builtin_nontemporal_store(b, reinterpret_cast<V*>(p) + 1);
-  } else if constexpr (N == 1) {
-    __builtin_nontemporal_store(x.v[0], p);
-  } else {
-    typedef typename NtVec<T, N>::type V;
-    V a;
-#pragma unroll
-    for (int i = 0; i < N; ++i) a[i] = x.v[i];
-    __builtin_nontemporal_store(a, reinterpret_cast<V*>(p));
-  }
-}
-
-constexpr int kGatherBatch = 4;   // neighbour loads in flight per lane
-
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous range of tiles so neighbour rows with small rank offsets are
-// found in that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int b, int grid_tiles) {
-  const int per = grid_tiles >> 3;
-  return (b & 7) * per + (b >> 3);
-}
-
-// Deterministic workgroup sum (valid in thread 0). sh: >= 4 doubles of LDS.
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[w] = v;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0) r = ((sh[0] + sh[1]) + sh[2]) + sh[3];
-  return r;
-}
-
-// Sum of n partials in a fixed order (strided per thread, then tree).
-__device__ __forceinline__ double sum_partials(const double* p, int n, double* sh) {
-  double acc = 0.0;
-  for (int t = threadIdx.x; t < n; t += kThreads) acc += p[t];
-  return block_sum(acc, sh);
-}
 
 // LDS carve-up shared by the step kernel and the matrix export.
 struct StepSmem {
@@ -962,7 +868,6 @@ size_t block_lds_bytes(const DevicePlan& p) {
       .total;
 }
 
-constexpr uint32_t kNoRun = 0xFFFFFFFFu;
 
 // One workgroup walks the sub-tiles [tile_sub0[t], tile_sub0[t + 1]) of its
 // tile; each sub-tile is a run of whole blocks of at most blk_rows states.
@@ -1381,10 +1286,12 @@ size_t tab_lds_bytes(const DevicePlan& p) {
 }
 
 struct TabMeta {
-  size_t hcnt, hstart, mstart, hq, total;
+  size_t hcnt, hstart, mstart, hq, hcoef, dhh, wtab, total;
 };
 
-__host__ __device__ inline TabMeta tab_meta_layout(int64_t n_blk, int hh, int mx) {
+// wtab_bytes > 0 (slice kernel): also per-block coefficients and diagonal
+// parts, and the word tables.
+__host__ __device__ inline TabMeta tab_meta_layout(int64_t n_blk, int hh, int mx, size_t wtab_bytes) {
   TabMeta m{};
   size_t o = 0;
   auto put = [&](size_t b) {
@@ -1392,15 +1299,29 @@ __host__ __device__ inline TabMeta tab_meta_layout(int64_t n_blk, int hh, int mx
     o = (o + b + 255) & ~size_t(255);
     return r;
   };
+  // + 16 entries: the slice kernel reads whole batches past a block's count
   m.hcnt = put(size_t(n_blk) * 4);
-  m.hstart = put(size_t(n_blk) * hh * 4);
-  m.mstart = put(size_t(n_blk) * mx * 4);
+  m.hstart = put((size_t(n_blk) * hh + 16) * 4);
+  m.mstart = put((size_t(n_blk) * mx + 16) * 4);
   m.hq = put(size_t(n_blk) * hh * 2);
+  if (wtab_bytes) {
+    m.hcoef = put((size_t(n_blk) * hh + 16) * 8);
+    m.dhh = put(size_t(n_blk) * 8);
+    m.wtab = put(wtab_bytes);
+  }
   m.total = o;
   return m;
 }
 
-size_t tab_meta_bytes(const DevicePlan& p) { return tab_meta_layout(p.n_blk, p.meta_hh, p.meta_mx).total; }
+static size_t slice_wtab_bytes(const DevicePlan& p) {
+  return p.slice_wb ? size_t(p.n_probs) * p.slice_words * p.slice_wb : 0;
+}
+
+static TabMeta plan_meta(const DevicePlan& p) {
+  return tab_meta_layout(p.n_blk, p.meta_hh, p.meta_mx, slice_wtab_bytes(p));
+}
+
+size_t tab_meta_bytes(const DevicePlan& p) { return plan_meta(p).total; }
 
 // Rank of the first state of block hp with k low bits set: the k lowest bits
 // contribute C(j - 1, j) = 0, so only the high bits count.
@@ -1423,7 +1344,9 @@ __global__ __launch_bounds__(kThreads) void tab_meta_kernel(const ProbDev* probs
                                                             const uint32_t* blk_h, int meta_hh,
                                                             int meta_mx, uint32_t* hcnt,
                                                             uint32_t* hstart, uint32_t* mstart,
-                                                            uint16_t* hq, int* err) {
+                                                            uint16_t* hq, const double* boff,
+                                                            const double* bzz, double* hcoef,
+                                                            double* dhh, int* err) {
   __shared__ uint32_t sb[kBinomN * kBinomN];
   for (int i = threadIdx.x; i < kBinomN * kBinomN; i += kThreads) sb[i] = binom[i];
   __syncthreads();
@@ -1447,9 +1370,20 @@ __global__ __launch_bounds__(kThreads) void tab_meta_kernel(const ProbDev* probs
       }
       hstart[g * meta_hh + n] = st;
       hq[g * meta_hh + n] = (uint16_t)q;
+      if (hcoef) hcoef[g * meta_hh + n] = boff[P.bond_off + bperm[q_hh + q]];
       ++n;
     }
     hcnt[g] = (uint32_t)n;
+    if (dhh) {
+      // the diagonal's high-high part: sum_b (+-) J_b/(4a) over bonds between high sites
+      double d = P.shift;
+      for (int q = 0; q < P.n_hh; ++q) {
+        const int b = P.bond_off + bperm[q_hh + q];
+        const uint32_t mh = bmask[b] >> L, x = h & mh;
+        d += (x == 0u || x == mh) ? bzz[b] : -bzz[b];
+      }
+      dhh[g] = d;
+    }
     for (int q = 0; q < P.n_mx; ++q) {
       const uint32_t mh = bmask[P.bond_off + bperm[q_mx + q]] >> L;   // one high bit
       const int kk = (h & mh) ? k + 1 : k - 1;
@@ -1467,15 +1401,22 @@ __global__ __launch_bounds__(kThreads) void tab_meta_kernel(const ProbDev* probs
 }
 
 hipError_t build_tab_meta(const DevicePlan& p, hipStream_t st) {
-  const TabMeta m = tab_meta_layout(p.n_blk, p.meta_hh, p.meta_mx);
+  const TabMeta m = plan_meta(p);
+  // the tables live in the plan's state-table region of the workspace
+  if (m.total > (size_t)p.n_states * 4) return hipErrorInvalidValue;
   unsigned char* base = reinterpret_cast<unsigned char*>(p.states);
+  const bool slice = p.slice_wb > 0;
   hipLaunchKernelGGL(tab_meta_kernel, dim3(256, p.n_probs), dim3(kThreads), 0, st, p.probs,
                      p.bmask, p.bperm, p.binom, p.blk_h, p.meta_hh, p.meta_mx,
                      reinterpret_cast<uint32_t*>(base + m.hcnt),
                      reinterpret_cast<uint32_t*>(base + m.hstart),
                      reinterpret_cast<uint32_t*>(base + m.mstart),
-                     reinterpret_cast<uint16_t*>(base + m.hq), p.err);
-  return hipGetLastError();
+                     reinterpret_cast<uint16_t*>(base + m.hq), p.boff, p.bzz,
+                     slice ? reinterpret_cast<double*>(base + m.hcoef) : nullptr,
+                     slice ? reinterpret_cast<double*>(base + m.dhh) : nullptr, p.err);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && slice) e = build_slice_words(p, reinterpret_cast<uint8_t*>(base + m.wtab), st);
+  return e;
 }
 
 // One batch of NB mixed bonds (one low and one high site) of a (row, chunk)
@@ -1895,7 +1836,7 @@ static StepArgs make_step_args(const DevicePlan& p) {
   a.sub_nrows = p.sub_nrows;
   a.lrank = p.lrank;
   if (p.block >= 2) {
-    const TabMeta m = tab_meta_layout(p.n_blk, p.meta_hh, p.meta_mx);
+    const TabMeta m = plan_meta(p);
     const unsigned char* mb = reinterpret_cast<const unsigned char*>(p.states);
     a.blk_h = p.blk_h;
     a.blk_start = p.blk_start;
@@ -1910,6 +1851,17 @@ static StepArgs make_step_args(const DevicePlan& p) {
     a.meta_hh = p.meta_hh;
     a.meta_mx = p.meta_mx;
     a.lds_ll = p.lds_ll;
+    if (p.slice_wb) {
+      a.cmask = p.cmask;
+      a.coff = p.coff;
+      a.czz = p.czz;
+      a.meta_hcoef = reinterpret_cast<const double*>(mb + m.hcoef);
+      a.meta_dhh = reinterpret_cast<const double*>(mb + m.dhh);
+      a.wtab = reinterpret_cast<const uint8_t*>(mb + m.wtab);
+      a.slice_wb = p.slice_wb;
+      a.slice_words = p.slice_words;
+      a.blk_lds_rows = p.blk_lds_rows;
+    }
   }
   return a;
 }
@@ -1957,6 +1909,7 @@ hipError_t launch_step_slots(const DevicePlan& p, void* vec, double* part_out, i
 
 hipError_t launch_step_args(const DevicePlan& p, const StepArgs& a, hipStream_t st) {
   if (p.spin) return launch_spin(p, a, st);
+  if (p.block == 3) return launch_slice(p, a, st);
   if (p.block == 2) return launch_tab(p, a, st);
   if (p.block) return launch_block(p, a, st);
   if (p.row_ld > 0) return launch_row(p, a, st);

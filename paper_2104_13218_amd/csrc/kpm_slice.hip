@@ -1,0 +1,531 @@
+// Slice step kernel: the recursion step v_{n+1} = 2 H' v_n - v_{n-1} (v_1 =
+// H' v_0) with the fused dots (paper, Eqs. (4)-(7); the S^z-sector bit basis of
+// Sec. II), for narrow column blocks (16-byte chunks, at most a few per row).
+//
+// Basis blocks are those of the block-table kernel: the states sharing their
+// high word h = s >> L, member i of block h holding the i-th L-bit low word of
+// its popcount class in colex order.  A bond between two high sites acts on
+// every member of a block or on none and maps member i of block h to member i
+// of block h ^ m; a bond between two low sites stays inside the block; a mixed
+// bond (one low, one high site) moves a member to the block h ^ m_high, at the
+// colex rank of the flipped low word.
+//
+// One wave per workgroup, no workgroup barriers.  A workgroup walks the blocks
+// of its tile; per block it
+//   1. copies the block's rows of v_n into LDS (row 0 of its LDS area stays
+//      zero);
+//   2. runs "slices" of 64 / nch members (nch = 16-byte chunks per row), one
+//      member and chunk per lane.  Everything a block shares is scalar:
+//      its high word, the acting high-high bonds (their target blocks' first
+//      ranks and coefficients J_b/(2a) from per-block tables), and the
+//      high-high part of the diagonal.  High-high rows are buffer loads whose
+//      per-lane offset (member i, chunk c) is the same for every target block
+//      and whose scalar offset is the target block's start.
+// Per lane, one row of a per-call word table (indexed by the low word's
+// position in its class) gives the low-low part of the diagonal, the low
+// word l, the colex rank of l ^ m_low for each mixed bond, and per low-low
+// bond the LDS row of the neighbour (0, the zero row, when the bond does not
+// act).  Sum order per element: diagonal, low-low, high-high, mixed, each in
+// bond order.
+#include <hip/hip_runtime.h>
+
+#include "kpm_device.h"
+#include "kpm_internal.h"
+#include "kpm_vec.h"
+
+namespace kpm {
+
+// Constant-address-space views: loads at wave-uniform indices become scalar
+// loads (the tables are not written during a step).
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ cptr<T> cview(const T* p) {
+  return (cptr<T>)(const void*)p;
+}
+
+// A plan struct at a wave-uniform address, word by word through scalar loads.
+template <typename S>
+__device__ __forceinline__ S sload(const S* p) {
+  static_assert(sizeof(S) % 4 == 0, "word-sized struct");
+  S out;
+  const cptr<uint32_t> q = cview(reinterpret_cast<const uint32_t*>(p));
+  uint32_t w[sizeof(S) / 4];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(S) / 4); ++i) w[i] = q[i];
+  __builtin_memcpy(&out, w, sizeof(S));
+  return out;
+}
+
+// LDS ordering inside one wave (the block's rows are written by some lanes
+// and read by others).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, int CPL>
+__device__ __forceinline__ VecT<T, CPL> bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  VecT<T, CPL> v;
+  constexpr int bytes = (int)sizeof(T) * CPL;
+  if constexpr (bytes == 16) {
+    const auto x = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    __builtin_memcpy(&v, &x, 16);
+  } else if constexpr (bytes == 8) {
+    const auto x = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    __builtin_memcpy(&v, &x, 8);
+  } else {
+    const auto x = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    __builtin_memcpy(&v, &x, 4);
+  }
+  return v;
+}
+
+// v_{n-1} is read once and v_{n+1} written once per step: streaming (glc slc)
+template <typename T, int CPL>
+__device__ __forceinline__ VecT<T, CPL> bload_nt(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  VecT<T, CPL> v;
+  constexpr int bytes = (int)sizeof(T) * CPL;
+  if constexpr (bytes == 16) {
+    const auto x = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 3);
+    __builtin_memcpy(&v, &x, 16);
+  } else if constexpr (bytes == 8) {
+    const auto x = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 3);
+    __builtin_memcpy(&v, &x, 8);
+  } else {
+    const auto x = __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 3);
+    __builtin_memcpy(&v, &x, 4);
+  }
+  return v;
+}
+
+template <typename T, int CPL>
+__device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, uint32_t voff, const VecT<T, CPL>& v) {
+  constexpr int bytes = (int)sizeof(T) * CPL;
+  if constexpr (bytes == 16) {
+    __attribute__((ext_vector_type(4))) uint32_t x;
+    __builtin_memcpy(&x, &v, 16);
+    __builtin_amdgcn_raw_buffer_store_b128(x, r, voff, 0, 3);
+  } else if constexpr (bytes == 8) {
+    __attribute__((ext_vector_type(2))) uint32_t x;
+    __builtin_memcpy(&x, &v, 8);
+    __builtin_amdgcn_raw_buffer_store_b64(x, r, voff, 0, 3);
+  } else {
+    uint32_t x;
+    __builtin_memcpy(&x, &v, 4);
+    __builtin_amdgcn_raw_buffer_store_b32(x, r, voff, 0, 3);
+  }
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+// Word-table layout (one row of WB bytes per low word, indexed by the word's
+// position koff[k] + i in the class-ordered list):
+//   bytes 0..7       low-low part of the diagonal, sum_b (+-) J_b/(4a), float64
+//   bytes 8..9       the low word l
+//   bytes 12..       per mixed bond: colex rank of l ^ m_low (u16)
+//   bytes kLlOff..   per low-low bond: LDS row of the neighbour (1 + its member
+//                    index) when the bond acts on l, else 0 (u8)
+template <int WB>
+struct WordRow {
+  static constexpr int kMx = WB == 32 ? 2 : 10;      // mixed bonds held
+  static constexpr int kLlOff = WB == 32 ? 16 : 32;  // first low-low byte
+  static constexpr int kLl = WB - kLlOff;            // low-low bonds held
+};
+
+int slice_word_bytes(int n_mx, int n_ll) {
+  if (n_mx <= WordRow<32>::kMx && n_ll <= WordRow<32>::kLl) return 32;
+  if (n_mx <= WordRow<64>::kMx && n_ll <= WordRow<64>::kLl) return 64;
+  return 0;
+}
+
+__global__ __launch_bounds__(kThreads) void slice_words_kernel(const ProbDev* probs, const uint32_t* cmask,
+                                                              const double* czz, const uint16_t* lunr,
+                                                              const uint16_t* lrank, int words, int wb,
+                                                              uint8_t* wtab) {
+  const int w = blockIdx.x * kThreads + threadIdx.x;
+  if (w >= words) return;
+  const ProbDev P = probs[blockIdx.y];
+  uint32_t* row = reinterpret_cast<uint32_t*>(wtab + ((size_t)blockIdx.y * words + w) * wb);
+  uint32_t dw[16];
+  for (int t = 0; t < 16; ++t) dw[t] = 0u;
+  const uint32_t l = lunr[w];
+  const int Lb = P.blk_L;
+  if (Lb < 32 && (l >> Lb) == 0u) {
+    const uint32_t* cm = cmask + P.bond_off;
+    const double* cz = czz + P.bond_off;
+    double d = 0.0;
+    for (int q = 0; q < P.n_ll; ++q) {
+      const uint32_t v = l & cm[q];
+      d += (v == 0u || v == cm[q]) ? cz[q] : -cz[q];
+    }
+    uint64_t db;
+    __builtin_memcpy(&db, &d, 8);
+    dw[0] = (uint32_t)db;
+    dw[1] = (uint32_t)(db >> 32);
+    dw[2] = l;
+    const uint32_t lmask = (1u << Lb) - 1u;
+    const int mx0 = P.n_ll + P.n_hh;
+    for (int q = 0; q < P.n_mx; ++q) {
+      const uint32_t r = lrank[l ^ (cm[mx0 + q] & lmask)];
+      const int byte = 12 + 2 * q;
+      dw[byte >> 2] |= r << ((byte & 3) * 8);
+    }
+    const int llo = wb == 32 ? WordRow<32>::kLlOff : WordRow<64>::kLlOff;
+    for (int q = 0; q < P.n_ll; ++q) {
+      const uint32_t m = cm[q], v = l & m;
+      const uint32_t r = (v == 0u || v == m) ? 0u : 1u + lrank[l ^ m];
+      const int byte = llo + q;
+      dw[byte >> 2] |= r << ((byte & 3) * 8);
+    }
+  }
+  for (int t = 0; t < wb / 4; ++t) row[t] = dw[t];
+}
+
+hipError_t build_slice_words(const DevicePlan& p, uint8_t* wtab, hipStream_t st) {
+  const int grid = (p.slice_words + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(slice_words_kernel, dim3(grid, p.n_probs), dim3(kThreads), 0, st, p.probs, p.cmask,
+                     p.czz, p.lunr, p.lrank, p.slice_words, p.slice_wb, wtab);
+  return hipGetLastError();
+}
+
+// LDS of the slice kernel: the low-low coefficients of the tile's problem
+// (kLlMax doubles, zero past its count), then the rows of the largest block
+// (at most 254 members, storage precision) after the zero row.
+constexpr int kLlMax = 32;
+
+size_t slice_lds_bytes(const DevicePlan& p) {
+  return (size_t)kLlMax * 8 + (size_t)(p.blk_lds_rows + 1) * p.ld_max * (p.fp32 ? 4 : 8);
+}
+
+template <int WB>
+__device__ __forceinline__ uint32_t row_byte(const uint32_t (&w)[WB / 4], int byte) {
+  return (w[byte >> 2] >> ((byte & 3) * 8)) & 0xFFu;
+}
+template <int WB>
+__device__ __forceinline__ uint32_t row_u16(const uint32_t (&w)[WB / 4], int byte) {
+  return (w[byte >> 2] >> ((byte & 3) * 8)) & 0xFFFFu;
+}
+
+template <typename T, int CPL, int NCH, int GH, int WB>
+__global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x;
+  using RowT = WordRow<WB>;
+  constexpr int LD = NCH * CPL;          // columns per row (every unit of the plan)
+  constexpr int RPS = 64 / NCH;          // members per slice
+  constexpr uint32_t ROWB = LD * sizeof(T);
+
+  if (a.n_jobs > 0) {
+    // the previous step's partial dots: one column sum per job, fixed order
+    const int64_t s = (a.step_base ? *a.step_base : 0) + a.step_add;
+    for (int job = blockIdx.x; job < a.n_jobs; job += gridDim.x) {
+      const UnitDev U = sload(a.units + cview(a.job_unit)[job]);
+      const int v = job - 2 * U.col_off;
+      const double* p = a.part_in + U.part_off + (int64_t)v * U.ntiles;
+      double acc = 0.0;
+      for (int t = lane; t < U.ntiles; t += 64) acc += p[t];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+      if (lane == 0) {
+        if (v < U.ld) a.alpha[s * a.total_cols + U.col_off + v] = acc;
+        else a.beta[(s - 1) * a.total_cols + U.col_off + (v - U.ld)] = acc;
+      }
+    }
+  }
+
+  const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.grid_tiles) : (int)blockIdx.x;
+  if (tile >= a.n_tiles) return;
+  const UnitDev U = sload(a.units + cview(a.tile_unit)[tile]);
+  const ProbDev P = sload(a.probs + U.prob);
+  const int rl = lane / NCH;
+  const int c = lane - rl * NCH;
+  const uint32_t cc = (uint32_t)(c * CPL);
+  const int Lb = P.blk_L, nll = P.n_ll, nhh = P.n_hh, nmx = P.n_mx;
+  const uint32_t lmask = (1u << Lb) - 1u;
+
+  T* base = reinterpret_cast<T*>(a.vec) + U.vec_off;
+  const T* X = base + a.x_slot * a.slot_stride;
+  const T* Yin = base + a.yin_slot * a.slot_stride;
+  T* Y = base + a.yout_slot * a.slot_stride;
+  const uint32_t slot_bytes = (uint32_t)((uint64_t)P.dim * ROWB);
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc(X, slot_bytes);
+  // the first step reads v_n in place of v_{n-1} and ignores it
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc(a.first ? X : Yin, slot_bytes);
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(Y, slot_bytes);
+  const __amdgpu_buffer_rsrc_t rw =
+      make_rsrc(a.wtab + (size_t)U.prob * a.slice_words * WB, (uint32_t)a.slice_words * WB);
+
+  // bonds in class order (padded with zeros past the last problem)
+  const cptr<uint32_t> cm = cview(a.cmask) + P.bond_off;
+  const cptr<double> co = cview(a.coff) + P.bond_off;
+  const cptr<double> cz = cview(a.czz) + P.bond_off;
+
+  double* lco = reinterpret_cast<double*>(smem);             // low-low coefficients
+  T* xs = reinterpret_cast<T*>(lco + kLlMax);                // [1 + members][LD], row 0 = 0
+  for (int e = lane; e < LD; e += 64) xs[e] = T(0);
+  for (int q = lane; q < kLlMax; q += 64) lco[q] = q < nll ? a.coff[P.bond_off + q] : 0.0;
+
+  double acc_a[CPL], acc_b[CPL];
+#pragma unroll
+  for (int e = 0; e < CPL; ++e) acc_a[e] = acc_b[e] = 0.0;
+
+  const int sub1 = cview(a.tile_sub0)[tile + 1];
+  for (int sub = cview(a.tile_sub0)[tile]; sub < sub1; ++sub) {
+    const int g0 = cview(a.sub_blk0)[sub];
+    const int nblk = cview(a.sub_nblk)[sub];
+    for (int g = g0; g < g0 + nblk; ++g) {
+      const uint32_t h = cview(a.blk_h)[g];
+      const uint32_t st = cview(a.blk_start)[g];
+      const int k = P.n_up - __popc(h);
+      const int bsz = (k >= 0 && k <= Lb) ? (int)cview(a.binom)[Lb * kBinomN + k] : 0;
+      if (bsz == 0 || bsz > a.blk_lds_rows) {
+        if (lane == 0 && a.err) atomicOr(a.err, 4);
+        continue;
+      }
+      const int nh = min((int)cview(a.meta_hcnt)[g], nhh);
+      const double dhh = cview(a.meta_dhh)[g];
+      const uint32_t kofs = (uint32_t)cview(a.koff)[k];
+      const cptr<uint32_t> hs = cview(a.meta_hstart) + (int64_t)g * a.meta_hh;
+      const cptr<double> hc = cview(a.meta_hcoef) + (int64_t)g * a.meta_hh;
+      const cptr<uint32_t> ms = cview(a.meta_mstart) + (int64_t)g * a.meta_mx;
+
+      // 1. the block's rows of v_n into LDS rows 1..bsz
+      {
+        const int ne = bsz * NCH;
+        for (int e0 = 0; e0 < ne; e0 += 4 * 64) {
+          VecT<T, CPL> v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const uint32_t e = (uint32_t)min(e0 + u * 64 + lane, ne - 1);
+            v[u] = bload<T, CPL>(rx, (st * LD + e * CPL) * (uint32_t)sizeof(T), 0);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * 64 + lane;
+            if (e < ne) *reinterpret_cast<VecT<T, CPL>*>(xs + LD + e * CPL) = v[u];
+          }
+        }
+      }
+      wave_sync();
+
+      // 2. slices of the block.  A slice's v_{n+1} is stored after the next
+      // slice's loads are issued (its data registers are then not the next
+      // loads' targets, so those loads need not wait for the store).
+      const int nsl = (bsz + RPS - 1) / RPS;
+      VecT<T, CPL> pend;
+      uint32_t pend_off = 0u;
+      bool pend_on = false;
+      for (int s = 0; s < nsl; ++s) {
+        const int i = s * RPS + rl;
+        const bool on = i < bsz;
+        const uint32_t ii = on ? (uint32_t)i : 0u;
+        // word-table row first: the loads after it may still be in flight
+        // when it is consumed
+        uint32_t w[WB / 4];
+#pragma unroll
+        for (int t = 0; t < WB / 16; ++t) {
+          const auto q = __builtin_amdgcn_raw_buffer_load_b128(rw, (kofs + ii) * WB + 16 * t, 0, 0);
+          w[4 * t] = q[0];
+          w[4 * t + 1] = q[1];
+          w[4 * t + 2] = q[2];
+          w[4 * t + 3] = q[3];
+        }
+        const uint32_t own = st + ii;
+        const uint32_t voff_own = own * ROWB + cc * (uint32_t)sizeof(T);
+        const uint32_t voff_m = ii * ROWB + cc * (uint32_t)sizeof(T);
+        const VecT<T, CPL> yv = bload_nt<T, CPL>(ry, voff_own);
+        // first batch of high-high rows: starts and coefficients by scalar
+        // loads (entries past the block's count are read, not used)
+        VecT<T, CPL> hv[GH];
+        double hcf[GH];
+#pragma unroll
+        for (int j = 0; j < GH; ++j) {
+          const uint32_t tj = hs[j];
+          const double cj = hc[j];
+          const uint32_t t = j < nh ? tj : st;    // past the count: own member, coefficient 0
+          hcf[j] = j < nh ? cj : 0.0;
+          hv[j] = bload<T, CPL>(rx, voff_m, t * ROWB);
+        }
+        if (pend_on) bstore_nt<T, CPL>(ro, pend_off, pend);
+
+        const uint32_t l = w[2] & 0xFFFFu;
+        double dll;
+        {
+          const uint64_t db = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+          __builtin_memcpy(&dll, &db, 8);
+        }
+        // mixed bonds act where their low and high sites differ
+        bool mact[RowT::kMx];
+        double d = dhh + dll;
+#pragma unroll
+        for (int q = 0; q < RowT::kMx; ++q) {
+          mact[q] = false;
+          if (q < nmx) {
+            const uint32_t m = cm[nll + nhh + q];
+            mact[q] = ((l & m & lmask) != 0u) != ((h & (m >> Lb)) != 0u);
+            d = fma(mact[q] ? -1.0 : 1.0, cz[nll + nhh + q], d);
+          }
+        }
+        double acc[CPL];
+        {
+          const VecT<T, CPL> xv = *reinterpret_cast<const VecT<T, CPL>*>(xs + (1 + ii) * LD + cc);
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) acc[e] = d * (double)xv.v[e];
+        }
+        // low-low neighbours in batches of four: the word table names the LDS
+        // row (0 = the zero row for a bond that does not act, and for the
+        // slots past the problem's count)
+#pragma unroll
+        for (int q0 = 0; q0 < RowT::kLl; q0 += 4) {
+          if (q0 < nll) {
+            VecT<T, CPL> xv[4];
+            double cf[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const uint32_t r = row_byte<WB>(w, RowT::kLlOff + q0 + u);
+              cf[u] = lco[q0 + u];
+              xv[u] = *reinterpret_cast<const VecT<T, CPL>*>(xs + r * LD + cc);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+#pragma unroll
+              for (int e = 0; e < CPL; ++e) acc[e] = fma(cf[u], (double)xv[u].v[e], acc[e]);
+            }
+          }
+        }
+        // mixed rows (requested now; their latency overlaps the high-high sums)
+        VecT<T, CPL> mv[2];
+        auto mx_issue = [&](int q0) {
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int q = q0 + u;
+            uint32_t row = own;
+            if (q < nmx && q < RowT::kMx) {
+              const uint32_t stq = ms[q];
+              if (mact[q] && stq == kNoRun) {
+                if (a.err) atomicOr(a.err, 2);
+                mact[q] = false;
+              }
+              if (mact[q]) row = stq + row_u16<WB>(w, 12 + 2 * q);
+            }
+            mv[u] = bload<T, CPL>(rx, row * ROWB + cc * (uint32_t)sizeof(T), 0);
+          }
+        };
+        mx_issue(0);
+        // high-high rows
+#pragma unroll
+        for (int j = 0; j < GH; ++j) {
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) acc[e] = fma(hcf[j], (double)hv[j].v[e], acc[e]);
+        }
+        for (int k0 = GH; k0 < nh; k0 += GH) {
+#pragma unroll
+          for (int j = 0; j < GH; ++j) {
+            const uint32_t tj = hs[k0 + j];
+            const double cj = hc[k0 + j];
+            const uint32_t t = k0 + j < nh ? tj : st;
+            hcf[j] = k0 + j < nh ? cj : 0.0;
+            hv[j] = bload<T, CPL>(rx, voff_m, t * ROWB);
+          }
+#pragma unroll
+          for (int j = 0; j < GH; ++j) {
+#pragma unroll
+            for (int e = 0; e < CPL; ++e) acc[e] = fma(hcf[j], (double)hv[j].v[e], acc[e]);
+          }
+        }
+#pragma unroll
+        for (int q0 = 0; q0 < RowT::kMx; q0 += 2) {
+          if (q0 < nmx) {
+            if (q0 > 0) mx_issue(q0);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              const int q = q0 + u;
+              const double cq = co[nll + nhh + q];
+              const double cf = (q < nmx && mact[q]) ? cq : 0.0;
+#pragma unroll
+              for (int e = 0; e < CPL; ++e) acc[e] = fma(cf, (double)mv[u].v[e], acc[e]);
+            }
+          }
+        }
+        pend_on = on;
+        pend_off = voff_own;
+        if (on) {
+          VecT<T, CPL> ov;
+          if (a.first) {
+#pragma unroll
+            for (int e = 0; e < CPL; ++e) ov.v[e] = (T)acc[e];
+          } else {
+#pragma unroll
+            for (int e = 0; e < CPL; ++e) ov.v[e] = (T)(2.0 * acc[e] - (double)yv.v[e]);
+          }
+          pend = ov;
+          const VecT<T, CPL> xv = *reinterpret_cast<const VecT<T, CPL>*>(xs + (1 + ii) * LD + cc);
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) {
+            const double o = (double)ov.v[e];
+            acc_a[e] = fma(o, o, acc_a[e]);
+            acc_b[e] = fma(o, (double)xv.v[e], acc_b[e]);
+          }
+        }
+      }
+      if (pend_on) bstore_nt<T, CPL>(ro, pend_off, pend);
+      wave_sync();
+    }
+  }
+
+  // dots: a fixed tree over the members of each column chunk
+#pragma unroll
+  for (int v = 0; v < 2 * CPL; ++v) {
+    double val = v < CPL ? acc_a[v] : acc_b[v - CPL];
+#pragma unroll
+    for (int s = 1; s < RPS; s <<= 1) {
+      const double o = __shfl_down(val, s * NCH, 64);
+      if ((rl & (2 * s - 1)) == 0) val += o;
+    }
+    if (rl == 0) {
+      const int dot = v < CPL ? 0 : 1;
+      const int col = (int)cc + (v - dot * CPL);
+      a.part_out[U.part_off + (int64_t)(dot * LD + col) * U.ntiles + (tile - U.tile0)] = val;
+    }
+  }
+}
+
+template <typename T, int CPL, int NCH, int WB>
+static hipError_t launch_slice_w(const StepArgs& a, size_t lds, int grid, int gh, hipStream_t st) {
+  if (gh == 4) hipLaunchKernelGGL((slice_kernel<T, CPL, NCH, 4, WB>), dim3(grid), dim3(64), lds, st, a);
+  else hipLaunchKernelGGL((slice_kernel<T, CPL, NCH, 8, WB>), dim3(grid), dim3(64), lds, st, a);
+  return hipGetLastError();
+}
+
+template <typename T, int CPL, int NCH>
+static hipError_t launch_slice_t(const StepArgs& a, size_t lds, int grid, int gh, int wb, hipStream_t st) {
+  if (wb == 32) return launch_slice_w<T, CPL, NCH, 32>(a, lds, grid, gh, st);
+  return launch_slice_w<T, CPL, NCH, 64>(a, lds, grid, gh, st);
+}
+
+// Every unit of a slice plan has ld = cpl * nch with nch 1 or 2.
+hipError_t launch_slice(const DevicePlan& p, const StepArgs& a, hipStream_t st) {
+  const size_t lds = slice_lds_bytes(p);
+  const int grid = p.grid_tiles;
+  const int gh = p.gather_batch;
+  const int wb = p.slice_wb;
+  const int nch = p.ld_max / p.cpl;
+  if (p.ld_max != nch * p.cpl || (nch != 1 && nch != 2)) return hipErrorInvalidValue;
+  if (p.fp32) {
+    if (p.cpl == 4) return nch == 1 ? launch_slice_t<float, 4, 1>(a, lds, grid, gh, wb, st)
+                                    : launch_slice_t<float, 4, 2>(a, lds, grid, gh, wb, st);
+    if (p.cpl == 2 && nch == 1) return launch_slice_t<float, 2, 1>(a, lds, grid, gh, wb, st);
+    if (p.cpl == 1 && nch == 1) return launch_slice_t<float, 1, 1>(a, lds, grid, gh, wb, st);
+    return hipErrorInvalidValue;
+  }
+  if (p.cpl == 2) return nch == 1 ? launch_slice_t<double, 2, 1>(a, lds, grid, gh, wb, st)
+                                  : launch_slice_t<double, 2, 2>(a, lds, grid, gh, wb, st);
+  if (p.cpl == 1 && nch == 1) return launch_slice_t<double, 1, 1>(a, lds, grid, gh, wb, st);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace kpm

@@ -1,4 +1,4 @@
-"""Every step kernel (column-chunk, row, block, block-table) against the oracle on the same
+"""Every step kernel (column-chunk, row, block, block-table, slice) against the oracle on the same
 seeds and bounds, including block geometries that force many small tiles,
 several blocks per tile and clusters smaller than the block width.
 
@@ -29,6 +29,13 @@ KERNELS = {
     "tab_small": ({"KPM_BLOCK": "2", "KPM_BLOCK_ROWS": "64", "KPM_BLOCK_MAX": "2",
                    "KPM_SUB_PER_TILE": "3", "KPM_GATHER_BATCH": "8"}, 3),
     "tab_l4": ({"KPM_BLOCK": "2", "KPM_BLOCK_L": "4", "KPM_SUB_PER_TILE": "1"}, 3),
+    # slice kernel (each wave on rows of one block): default geometry, small
+    # sub-tiles with 4 high-high rows per batch, 4 low bits, 10 low bits
+    "slice": ({"KPM_BLOCK": "3"}, 5),
+    "slice_small": ({"KPM_BLOCK": "3", "KPM_BLOCK_ROWS": "64", "KPM_BLOCK_MAX": "2",
+                     "KPM_SUB_PER_TILE": "3", "KPM_GATHER_BATCH": "4"}, 5),
+    "slice_l4": ({"KPM_BLOCK": "3", "KPM_BLOCK_L": "4", "KPM_SUB_PER_TILE": "1"}, 5),
+    "slice_l10": ({"KPM_BLOCK": "3", "KPM_BLOCK_L": "10", "KPM_SUB_PER_TILE": "2"}, 5),
 }
 
 
@@ -96,7 +103,8 @@ def test_j1j2_n18_sz0_wide_block(kpm, monkeypatch, kernel):
     _check(kpm, monkeypatch, kernel, secs, 40, 10, "complex_gaussian", "fp32", 20, seed=2)
 
 
-@pytest.mark.parametrize("kernel", ["block", "block_small", "block_l4", "tab", "tab_small", "tab_l4"])
+@pytest.mark.parametrize("kernel", ["block", "block_small", "block_l4", "tab", "tab_small", "tab_l4", "slice",
+                                    "slice_small", "slice_l4", "slice_l10"])
 def test_block_extreme_sectors(kpm, monkeypatch, kernel):
     """Sectors whose blocks are tiny (n_up near N) or single (N below the
     block width), dimension-1 sectors and the dimer."""
@@ -130,7 +138,7 @@ def _rr(n, seed):
     return W.random_regular_cluster(n, 3, seed, J_range=(0.5, 1.5))
 
 
-@pytest.mark.parametrize("kernel", ["block", "tab", "tab_small"])
+@pytest.mark.parametrize("kernel", ["block", "tab", "tab_small", "slice", "slice_small"])
 @pytest.mark.parametrize("kind,R", [("rademacher", 4), ("gaussian", 3), ("complex_gaussian", 2), ("basis", 1)])
 def test_relabelled_random_graphs(kpm, monkeypatch, kernel, kind, R):
     """Random 3-regular clusters (N = 13, 15) whose labels cut many bonds at
