@@ -95,6 +95,7 @@ _SIGS = {
     "kpm_thermo_grad": (c_int32, [POINTER(Problem), c_int32, POINTER(Params), c_int32, c_int32,
                                   c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_size_t, c_void_p]),
+    "kpm_cluster_bond_grad": (c_int32, [POINTER(Problem), c_int32, c_void_p, c_void_p, c_void_p]),
     "kpm_last_run_stats": (c_int32, [POINTER(RunStats)]),
     "kpm_site_relabel": (c_int32, [POINTER(Problem), c_int32, POINTER(c_int32)]),
     "kpm_autotune_reset": (c_int32, []),
@@ -118,6 +119,11 @@ def load():
 
 def strerror(code: int) -> str:
     return load().kpm_strerror(code).decode()
+
+
+def _f64(x):
+    """x as a contiguous float64 CUDA tensor (the ABI's double arrays)."""
+    return torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
 
 
 def _check(code: int, what: str):
@@ -249,8 +255,8 @@ def chebyshev_vectors(sector, n_vec, R=1, vec_kind="rademacher", precision="fp64
 def thermo(mu, ab, sectors, T, kernel="jackson", n_nodes=0, stream=None):
     """ln Z, E, C, chi [n_clusters, n_T] and the Z <= 0 flags."""
     ps = sectors if isinstance(sectors, ProblemSet) else ProblemSet(sectors)
-    mu = mu.contiguous()
-    ab = ab.contiguous()
+    mu = _f64(mu)
+    ab = _f64(ab)
     T = torch.as_tensor(T, dtype=torch.float64, device="cuda").contiguous()
     nc, nT = ps.n_clusters, T.numel()
     out = {k: torch.empty((nc, nT), dtype=torch.float64, device="cuda") for k in ("lnZ", "E", "C", "chi")}
@@ -265,8 +271,8 @@ def thermo_field(mu, ab, sectors, T, h, kernel="jackson", n_nodes=0, stream=None
     """ln Z, E, C, chi, M = <S^z> [n_clusters, n_pts] at the points (T, h) with
     the Zeeman term h S^z (h = g mu_B B), and the Z <= 0 flags."""
     ps = sectors if isinstance(sectors, ProblemSet) else ProblemSet(sectors)
-    mu = mu.contiguous()
-    ab = ab.contiguous()
+    mu = _f64(mu)
+    ab = _f64(ab)
     T = torch.as_tensor(T, dtype=torch.float64, device="cuda").contiguous()
     h = torch.as_tensor(h, dtype=torch.float64, device="cuda").expand_as(T).contiguous()
     nc, nT = ps.n_clusters, T.numel()
@@ -335,11 +341,12 @@ def thermo_hybrid(mu, ab, sectors, evals, exact, T, h=None, kernel="jackson", n_
     ex = np.ascontiguousarray(np.asarray(exact, dtype=np.uint8))
     if ex.size != len(ps):
         raise KPMError(KPM_EINVAL, "thermo_hybrid: one exact flag per problem")
-    evals = evals.contiguous()
+    evals = _f64(evals)
+    mu, ab = _f64(mu), _f64(ab)
     nc, nT = ps.n_clusters, T.numel()
     out = {k: torch.empty((nc, nT), dtype=torch.float64, device="cuda") for k in ("lnZ", "E", "C", "chi", "M")}
     out["z_nonpos"] = torch.empty((nc, nT), dtype=torch.uint8, device="cuda")
-    _check(load().kpm_thermo_hybrid(_ptr(mu.contiguous()), _ptr(ab.contiguous()), ps.arr, len(ps), mu.shape[1],
+    _check(load().kpm_thermo_hybrid(_ptr(mu), _ptr(ab), ps.arr, len(ps), mu.shape[1],
                                     KERNELS[kernel], n_nodes, _ptr(evals), evals.shape[1],
                                     ex.ctypes.data_as(c_void_p), _ptr(T), _ptr(hh), nT, _ptr(out["lnZ"]),
                                     _ptr(out["E"]), _ptr(out["C"]), _ptr(out["chi"]), _ptr(out["M"]),
@@ -350,12 +357,12 @@ def thermo_hybrid(mu, ab, sectors, evals, exact, T, h=None, kernel="jackson", n_
 def thermo_vjp(mu, ab, sectors, T, wC, wchi, kernel="jackson", n_nodes=0, stream=None):
     """dL/dmu [n, M] for L = sum wC C + wchi chi."""
     ps = sectors if isinstance(sectors, ProblemSet) else ProblemSet(sectors)
-    mu = mu.contiguous()
+    mu, ab = _f64(mu), _f64(ab)
     T = torch.as_tensor(T, dtype=torch.float64, device="cuda").contiguous()
     wC = torch.as_tensor(wC, dtype=torch.float64, device="cuda").contiguous()
     wchi = torch.as_tensor(wchi, dtype=torch.float64, device="cuda").contiguous()
     lam = torch.empty_like(mu)
-    _check(load().kpm_thermo_vjp(_ptr(mu), _ptr(ab.contiguous()), ps.arr, len(ps), mu.shape[1], KERNELS[kernel],
+    _check(load().kpm_thermo_vjp(_ptr(mu), _ptr(ab), ps.arr, len(ps), mu.shape[1], KERNELS[kernel],
                                  n_nodes, _ptr(T), T.numel(), _ptr(wC), _ptr(wchi), _ptr(lam), _stream(stream)),
            "kpm_thermo_vjp")
     return lam
@@ -384,7 +391,7 @@ def moments_vjp(sectors, M, R, ab, dmu, vec_kind="rademacher", precision="fp64",
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     nb = sum(s.cluster.n_bonds for s in ps.sectors)
     dJ = torch.empty(max(nb, 1), dtype=torch.float64, device="cuda")
-    ab = ab.contiguous()
+    ab = _f64(ab)
     dmu = dmu.to(device="cuda", dtype=torch.float64).contiguous()
     _check(lib.chebyshev_moments_vjp(ps.arr, len(ps), ctypes.byref(q), _ptr(ab), _ptr(dmu), ckpt_every,
                                      _ptr(dJ), _ptr(ws), nbytes, _stream(stream)), "chebyshev_moments_vjp")
@@ -416,10 +423,25 @@ def moments_vjp_resume(ps, M, R, ab, dmu, ws, vec_kind="rademacher", precision="
     nb = sum(s.cluster.n_bonds for s in ps.sectors)
     dJ = torch.empty(max(nb, 1), dtype=torch.float64, device="cuda")
     dmu = dmu.to(device="cuda", dtype=torch.float64).contiguous()
-    _check(load().chebyshev_moments_vjp_resume(ps.arr, len(ps), ctypes.byref(q), _ptr(ab.contiguous()),
+    _check(load().chebyshev_moments_vjp_resume(ps.arr, len(ps), ctypes.byref(q), _ptr(_f64(ab)),
                                                _ptr(dmu), ckpt_every, _ptr(dJ), _ptr(ws), ws.numel(),
                                                _stream(stream)), "chebyshev_moments_vjp_resume")
     return dJ[:nb]
+
+
+def cluster_bond_grad(problems, dJ, stream=None):
+    """Per-cluster dL/dJ (clusters by id, bonds in order) from the per-problem
+    derivatives dJ (problem after problem), summed by the library."""
+    ps = problems if isinstance(problems, ProblemSet) else ProblemSet(problems)
+    ncl = max(s.cluster_id for s in ps.sectors) + 1
+    nb = [0] * ncl
+    for s in ps.sectors:
+        nb[s.cluster_id] = s.cluster.n_bonds
+    out = torch.empty(max(sum(nb), 1), dtype=torch.float64, device="cuda")
+    dJ = dJ.to(device="cuda", dtype=torch.float64).contiguous()
+    _check(load().kpm_cluster_bond_grad(ps.arr, len(ps), _ptr(dJ), _ptr(out), _stream(stream)),
+           "kpm_cluster_bond_grad")
+    return out[:sum(nb)]
 
 
 def thermo_grad(sectors, M, R, T, wC, wchi, vec_kind="rademacher", precision="fp64", eps=0.025, seed=0,
@@ -469,7 +491,7 @@ class KPMMoments(torch.autograd.Function):
         dJ = moments_vjp_resume(ctx.ps, M, R, ctx.ab, dmu, ctx.ws, vec_kind, precision, eps, seed, col_block,
                                 ckpt_every)
         ctx.ws = None
-        dJ = dJ.view(len(ctx.ps), ctx.n_bonds).sum(0).to(ctx.J_device)
+        dJ = cluster_bond_grad(ctx.ps, dJ).to(ctx.J_device)
         return (dJ,) + (None,) * 11
 
 

@@ -233,3 +233,19 @@ def test_site_relabel_orders_high_sites_for_locality(kpmlib):
         ref[v] = 9 + k
     assert _cut(cl, perm, 9) == _cut(cl, ref, 9)
     assert _top_cost(cl, perm, 9) < _top_cost(cl, ref, 9)
+
+
+def test_cluster_bond_grad_rejects_mixed_bond_lists(kpmlib):
+    """kpm_cluster_bond_grad sums per-sector derivatives of one bond list per
+    cluster: two problems of one cluster with different bond counts, or NULL
+    arrays, are refused before any device work."""
+    import workloads as W
+    bi, bj = np.array([0, 1]), np.array([1, 2])
+    c2 = W.Cluster(6, bi, bj, np.array([1.0, 1.0]))
+    c1 = W.Cluster(6, bi[:1], bj[:1], np.array([1.0]))
+    mixed = kpmlib.ProblemSet([W.Sector(c2, 3, 0), W.Sector(c1, 4, 0)])
+    lib = kpmlib.load()
+    dummy = ctypes.c_void_p(16)        # never dereferenced: the call fails on the host
+    assert lib.kpm_cluster_bond_grad(mixed.arr, len(mixed), dummy, dummy, None) == kpmlib.KPM_EINVAL
+    ok = kpmlib.ProblemSet([W.Sector(c2, 3, 0), W.Sector(c2, 4, 0)])
+    assert lib.kpm_cluster_bond_grad(ok.arr, len(ok), None, dummy, None) == kpmlib.KPM_EINVAL

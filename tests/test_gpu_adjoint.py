@@ -188,3 +188,91 @@ def test_j1j2_n20_full_size_vs_finite_differences(kpm, t_lo, h, points):
         # relative to the gradient's scale: bonds whose derivative is ~500x
         # smaller than the rest carry the same absolute quotient noise
         assert abs(g[b] - fd) <= 1e-5 * np.abs(g).max(), (b, g[b], fd)
+
+
+def test_j1j2_n20_all_40_bonds_central_differences(kpm):
+    """J1-J2 chain N=20 (40 couplings), S^z = 0, M = 1000, R = 16, loss
+    sum_T C(T) over 64 log-spaced T in [0.1, 5], bounds fixed: the adjoint
+    gradient against central differences on every bond (the forward of each
+    difference is one chebyshev_moments call and kpm_thermo).
+    * h = 1e-5 (two-point): ||g - fd||_2 / ||g||_2 <= 1e-5.  Per bond this
+      quotient carries the loss's rounding divided by h, ~1e-5 max|g| here
+      (reported, bounded at 2e-5 max|g|).
+    * four-point stencil at h = 2e-4 (truncation O(h^4), rounding 20x
+      smaller): every bond within 2e-6 max|g|, which places the h = 1e-5
+      spread on the quotient, not on the adjoint."""
+    wl = W.j1j2_grad_workload()
+    secs = wl.problems
+    cl, n_up = secs[0].cluster, secs[0].n_up
+    bl = [tuple(x) for x in kpm.spectral_bounds(secs)]
+    T = W.log_temperatures(64, 0.1, 5.0)
+    wC, wX = np.ones((1, T.size)), np.zeros((1, T.size))
+    L, dJ, _ = kpm.thermo_grad(secs, wl.M, wl.R, T, wC, wX, wl.vec_kind, "fp64", wl.eps, wl.seed,
+                               kernel="none", ckpt_every=64, bounds=bl)
+    g = dJ.cpu().numpy()
+    Tt = torch.tensor(T, device="cuda")
+
+    def loss(J):
+        s = [W.Sector(cl.with_J(J), n_up, 0)]
+        mu, ab = kpm.chebyshev_moments(s, wl.M, wl.R, wl.vec_kind, "fp64", wl.eps, wl.seed, bounds=bl)
+        return float(kpm.thermo(mu, ab, s, Tt, "none")["C"].sum())
+
+    assert abs(loss(cl.J.copy()) - L.item()) <= 1e-10 * abs(L.item())
+    def shifted(b, dh):
+        J = cl.J.copy()
+        J[b] += dh
+        return loss(J)
+
+    h = 1e-5
+    fd = np.array([(shifted(b, h) - shifted(b, -h)) / (2 * h) for b in range(cl.n_bonds)])
+    rel = np.linalg.norm(g - fd) / np.linalg.norm(g)
+    mx = np.abs(g - fd).max() / np.abs(g).max()
+    h4 = 2e-4
+    fd4 = np.array([(8 * (shifted(b, h4) - shifted(b, -h4)) - (shifted(b, 2 * h4) - shifted(b, -2 * h4)))
+                    / (12 * h4) for b in range(cl.n_bonds)])
+    rel4 = np.linalg.norm(g - fd4) / np.linalg.norm(g)
+    mx4 = np.abs(g - fd4).max() / np.abs(g).max()
+    print(f"N=20 J1-J2, 40 bonds, T in [0.1, 5]: h = 1e-5 central: ||g - fd|| / ||g|| = {rel:.2e}, "
+          f"max |g_b - fd_b| / max |g| = {mx:.2e}; h = 2e-4 four-point: {rel4:.2e}, {mx4:.2e}")
+    assert rel <= 1e-5, rel
+    assert mx <= 2e-5, mx
+    assert mx4 <= 2e-6, mx4
+
+
+def test_exact_trace_gradient_vs_ed_hellmann_feynman_n12(kpm):
+    """J1-J2 chain N = 12 (24 couplings), S^z = 0 (dim 924), exact traces
+    (complete basis), M = 1000, loss sum_T C(T) over 64 log-spaced T in
+    [0.05, 5]: the GPU adjoint against the Hellmann-Feynman derivative of the
+    exactly diagonalised thermodynamics (dE_i/dJ_b = <i|h_b|i>).  Their
+    difference is the Chebyshev truncation error of the method at this M,
+    reported, and bounded by 1e-6 of the gradient's norm."""
+    from oracle import ed
+    cl = W.j1j2_chain(12, 1.0, 0.5)
+    s = W.Sector(cl, 6, 0)
+    bl = _bounds([s], pad=0.05)
+    T = W.log_temperatures(64, 0.05, 5.0)
+    wC, wX = np.ones((1, T.size)), np.zeros((1, T.size))
+    L, dJ, _ = kpm.thermo_grad([s], 1000, 1, T, wC, wX, "basis", "fp64", 0.025, 0, kernel="none",
+                               ckpt_every=64, bounds=bl)
+    g = dJ.cpu().numpy()
+    want = ed.hellmann_feynman_C([s], T).sum(axis=1)
+    C_ed = ed.thermo_from_spectra(ed.sector_spectra([s]), T)["C"].sum()
+    rel = np.linalg.norm(g - want) / np.linalg.norm(want)
+    mx = np.abs(g - want).max() / np.abs(want).max()
+    print(f"N=12 exact traces, M=1000: ||g - g_HF|| / ||g_HF|| = {rel:.2e}, max = {mx:.2e}; "
+          f"|L - L_ED| / L_ED = {abs(L.item() - C_ed) / C_ed:.2e}")
+    assert abs(L.item() - C_ed) <= 1e-6 * C_ed
+    assert rel <= 1e-6, rel
+
+
+def test_cluster_bond_grad_sums_sectors(kpm):
+    """kpm_cluster_bond_grad: per-cluster sums of per-sector dL/dJ, two
+    clusters with different bond lists, in problem order."""
+    c0, c1 = W.j1j2_chain(8, 1.0, 0.5), W.ring(7)
+    secs = W.sectors(c0, cluster_id=0) + W.sectors(c1, cluster_id=1)
+    rng = np.random.default_rng(3)
+    per = [rng.normal(size=s.cluster.n_bonds) for s in secs]
+    got = kpm.cluster_bond_grad(secs, torch.tensor(np.concatenate(per), device="cuda")).cpu().numpy()
+    n0 = len(W.sectors(c0))
+    want = np.concatenate([np.sum(per[:n0], axis=0), np.sum(per[n0:], axis=0)])
+    np.testing.assert_allclose(got, want, rtol=1e-14, atol=1e-14)
