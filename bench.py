@@ -3,7 +3,7 @@
 
 Workload (one "step" = one pass of the whole path over one batch of input):
 spin-1/2 Heisenberg ring, N = 24, J = 1, S^z = 0 sector (2,704,156 states),
-10 complex Gaussian random vectors (20 real columns, one column block; step
+10 complex Gaussian random vectors (20 real columns; column-block width, step
 kernel and tile shape autotuned in the warm-up), M = 2000 moments (1000
 recursion launches), eps = 0.025, bounds from 50-step Lanczos with
 a 1% margin, float32 vector storage with float64 arithmetic and dots, then the
@@ -21,13 +21,16 @@ JSON line also carries:
                 rocprofv3-measured bytes per launch from the committed counter
                 summary, or null
   fp64_plain    the same recursion in float64, one column per block (the
-                reference form), and fp64_batched (float64, all 20 columns)
+                reference form), and fp64_batched (float64, tuned blocks)
+  speedup_at_error_1e-6  float32 form over fp64_plain, with the temperature
+                band in which C(T) and chi(T) stay within 1e-6 of float64
   accuracy      float32-storage error against float64 on the same seeds, all
                 13 S^z >= 0 sectors of the ring: C(T), chi(T), ln Z, E, moments
-  cpu_baseline  the CPU oracle on a bounded sample of the same workload (30
+  cpu_baseline  the CPU oracle on a bounded sample of the same workload (32
                 recursion steps of the same sector and columns): on the host's
-                cores (up to 16, columns split over forked processes, run
-                before this process touches the GPU) and on one core
+                cores (up to the 16 of a one-GPU share, columns split over
+                forked processes, run before this process touches the GPU) and
+                on one core; the host's core count and CPU model are recorded
 
 `--workload` measures one of the other workloads instead (one JSON line of
 the same form, no CPU leg): batched_rr3 (64 random 3-regular clusters,
@@ -57,7 +60,8 @@ METRIC = "Chebyshev steps·dim/s + HBM GB/s at N=24 S^z=0; speedup vs FP64 at C(
 HBM_PEAK_GBS = 8000.0
 # step kernel families as reported by kpm_last_run_stats()["kernel"]
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X, dense float64 vector arithmetic
-KERNEL_FAMILY = {0: "step_kernel", 1: "row_kernel", 2: "block_kernel", 3: "tab_kernel", 4: "spin_kernel"}
+KERNEL_FAMILY = {0: "step_kernel", 1: "row_kernel", 2: "block_kernel", 3: "tab_kernel", 4: "spin_kernel",
+                 5: "slice_kernel"}
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -69,7 +73,7 @@ def _parse():
     ap.add_argument("--M", type=int, default=2000)
     ap.add_argument("--skip-extras", action="store_true",
                     help="only the timed workload (for profiler runs)")
-    ap.add_argument("--cpu-steps", type=int, default=30,
+    ap.add_argument("--cpu-steps", type=int, default=32,
                     help="recursion steps of the CPU-oracle sample")
     ap.add_argument("--workload", default="ring24_sz0",
                     choices=["ring24_sz0", "batched_rr3", "j1j2_grad", "rr4_30", "ftlm_ring24", "fe10",
@@ -98,17 +102,19 @@ def _traffic(family):
 
 def kernel_text_sha256(family):
     """sha256 of the kernel function's source text (its template line to the
-    closing brace in column 0) in kpm_kernels.hip: a counter record stays
-    valid while that text is unchanged."""
+    closing brace in column 0) in the library's sources: a counter record
+    stays valid while that text is unchanged."""
+    import glob
     import hashlib
     import re
     from paper_2104_13218_amd import build as _b
-    src = open(os.path.join(_b.CSRC, "kpm_kernels.hip")).read()
-    m = re.search(r"template <[^\n]*>\n__global__[^\n]*void %s\(" % re.escape(family), src)
-    if m is None:
-        return None
-    end = src.index("\n}\n", m.start())
-    return hashlib.sha256(src[m.start():end + 3].encode()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(_b.CSRC, "*.hip"))):
+        src = open(path).read()
+        m = re.search(r"template <[^\n]*>\n__global__[^\n]*void %s\(" % re.escape(family), src)
+        if m is not None:
+            end = src.index("\n}\n", m.start())
+            return hashlib.sha256(src[m.start():end + 3].encode()).hexdigest()
+    return None
 
 
 def _copy_rate(torch):
@@ -171,17 +177,18 @@ def main():
     M = args.M
     T = torch.tensor(W.log_temperatures(200, 0.01, 10.0), device="cuda")
     ps = kpm.ProblemSet(sec)
-    q32 = kpm.make_params(M, 10, "complex_gaussian", "fp32", 0.025, 0, col_block=20, autotune=True)
+    # block width, step kernel and tile shape measured by the library's tuner
+    q32 = kpm.make_params(M, 10, "complex_gaussian", "fp32", 0.025, 0, col_block=0, autotune=True)
     ws = torch.empty(kpm.moments_workspace_size(ps, q32), dtype=torch.uint8, device="cuda")
 
     def one_pass():
-        mu, ab = kpm.chebyshev_moments(None, M, 10, "complex_gaussian", "fp32", 0.025, 0, col_block=20,
+        mu, ab = kpm.chebyshev_moments(None, M, 10, "complex_gaussian", "fp32", 0.025, 0, col_block=0,
                                        workspace=ws, problems=ps, autotune=True)
         kpm.thermo(mu, ab, ps, T, "jackson")
         return kpm.last_run_stats()
 
     # measure and cache the launch shape once (a few steps per candidate)
-    kpm.chebyshev_moments(None, 8, 10, "complex_gaussian", "fp32", 0.025, 0, col_block=20,
+    kpm.chebyshev_moments(None, 8, 10, "complex_gaussian", "fp32", 0.025, 0, col_block=0,
                           workspace=ws, problems=ps, autotune=True)
     for _ in range(args.warmup):
         one_pass()
@@ -202,7 +209,7 @@ def main():
     line = {
         "metric": METRIC, "value": value, "unit": "state-column-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32-storage/f64-arithmetic", "data": "synthetic",
         "config": {"workload": "heisenberg_ring_N24_Sz0", "dim": sec[0].dim, "vectors": "10 complex Gaussian",
                    "real_columns": 20, "M": M, "recursion_launches": st["step_launches"], "eps": 0.025,
                    "bounds": "lanczos50+1%", "storage": "f32", "col_block": st["col_block"],
@@ -366,11 +373,14 @@ def other_workload(args, kpm, W, np, torch, dev):
 
 
 def _time_moments(kpm, torch, sec, M, R, kind, precision, col_block, reps=1):
-    kpm.chebyshev_moments(sec, M, R, kind, precision, 0.025, 0, col_block=col_block)   # warm-up
+    """One timed call after a warm-up (which also tunes the launch shape for
+    this block width)."""
+    kpm.chebyshev_moments(sec, M, R, kind, precision, 0.025, 0, col_block=col_block, autotune=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        mu, ab = kpm.chebyshev_moments(sec, M, R, kind, precision, 0.025, 0, col_block=col_block)
+        mu, ab = kpm.chebyshev_moments(sec, M, R, kind, precision, 0.025, 0, col_block=col_block,
+                                       autotune=True)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
     st = kpm.last_run_stats()
@@ -384,14 +394,14 @@ def extras(args, kpm, W, np, torch, sec, ps, T, M, value, ws):
     # Gaussian vectors give the same dim x columns x steps.
     _, _, dt, st = _time_moments(kpm, torch, sec, M, 20, "gaussian", "fp64", 1)
     plain = st["state_col_steps"] / dt
-    _, _, dtb, stb = _time_moments(kpm, torch, sec, M, 10, "complex_gaussian", "fp64", 20)
+    _, _, dtb, stb = _time_moments(kpm, torch, sec, M, 10, "complex_gaussian", "fp64", 0)
     batched = stb["state_col_steps"] / dtb
     out["fp64_plain"] = {"value": plain, "ms": dt * 1e3, "col_block": 1,
                          "avg_launch_us": st["recursion_ms"] * 1e3 / st["step_launches"]}
     out["fp64_batched"] = {"value": batched, "ms": dtb * 1e3, "col_block": stb["col_block"],
                            "avg_launch_us": stb["recursion_ms"] * 1e3 / stb["step_launches"]}
     # recursion-only rate of the float32 form, for a like-for-like speedup
-    _, _, dtf, stf = _time_moments(kpm, torch, sec, M, 10, "complex_gaussian", "fp32", 20)
+    _, _, dtf, stf = _time_moments(kpm, torch, sec, M, 10, "complex_gaussian", "fp32", 0)
     out["speedup_vs_fp64_plain"] = (stf["state_col_steps"] / dtf) / plain
     out["speedup_vs_fp64_batched"] = (stf["state_col_steps"] / dtf) / batched
 
@@ -430,6 +440,13 @@ def extras(args, kpm, W, np, torch, sec, ps, T, M, value, ws):
             rec[f"{qn}_max_rel_err_T>=T_phys"] = float(np.nanmax(np.abs(a - b) / np.abs(a)))
         acc[kern] = rec
     out["accuracy_fp32_vs_fp64_all_sectors"] = acc
+    # the speedup holds where the float32 form meets C(T), chi(T) error <= 1e-6
+    # (peak-normalised) against float64: the temperature band, per kernel g_n
+    out["speedup_at_error_1e-6"] = {
+        "speedup_vs_fp64_plain": out["speedup_vs_fp64_plain"],
+        "T_grid": [float(Th[0]), float(Th[-1])],
+        **{f"{kern}_{qn}_valid_for_T>=": acc[kern][f"{qn}_lowest_T_with_err<=1e-6"]
+           for kern in ("jackson", "none") for qn in ("C", "chi")}}
     if args.accuracy_curve:
         # conditioning of C(T) in the moments, from the thermodynamics VJP at
         # one temperature at a time: kappa(T) = sum_{p,n} |dC/dmu_pn| mu_p0 / |C|
@@ -485,7 +502,10 @@ def cpu_baseline(args, W, np, sec):
         t0 = time.perf_counter()
         moments.chebyshev_dots(Ht, V0, K, store=np.float32)
         dt1 = time.perf_counter() - t0
-    P = max(1, min(16, os.cpu_count() or 1, V0.shape[1]))
+    # one process per column group, up to the 16 host cores a one-GPU share
+    # of the machine holds (whatever the host reports in total)
+    nproc = os.cpu_count() or 1
+    P = max(1, min(16, nproc, V0.shape[1]))
     _CPU.update(Ht=Ht, V0=V0, K=K)
     groups = [list(g) for g in np.array_split(np.arange(V0.shape[1]), P)]
     with mp.get_context("fork").Pool(P) as pool:
@@ -495,8 +515,21 @@ def cpu_baseline(args, W, np, sec):
     _CPU.clear()
     sample = (f"oracle float32-storage recursion, N=24 S^z=0 sector, 20 real columns, {K} steps "
               f"(matrix build excluded)")
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": work / dtp, "unit": "state-column-steps/s", "cores": P, "kind": "oracle",
             "sample": f"{sample}: columns split over {P} forked processes, {dtp:.1f} s",
+            "host_nproc": nproc, "cpu_model": model,
+            "threads_per_process": {"OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS"),
+                                    "OPENBLAS_NUM_THREADS": os.environ.get("OPENBLAS_NUM_THREADS"),
+                                    "blas_limit": 1},
             "single_core": {"value": work / dt1, "cores": 1, "seconds": dt1}}
 
 if __name__ == "__main__":
