@@ -50,6 +50,8 @@ extern "C" {
 #define KPM_EBOUNDS (-4)    /* |mu_n| > mu_0 (1 + 1e-6) for some vector: the
                                spectral bounds do not enclose the spectrum */
 #define KPM_EWORKSPACE (-5) /* caller workspace smaller than required */
+#define KPM_ETOOLARGE (-6)  /* chebyshev_moments_noalloc: the call needs more than
+                               KPM_NOALLOC_MAX_BYTES of workspace */
 
 /* ---- random vector kinds of Eq. (7) ------------------------------------- */
 #define KPM_VEC_RADEMACHER 0       /* components +-1                         */
@@ -164,6 +166,32 @@ size_t chebyshev_moments_workspace_size(const kpm_problem* p, int32_t n, const k
 int chebyshev_moments(const kpm_problem* p, int32_t n, const kpm_params* q,
                       double* d_mu, double* d_ab, void* d_work, size_t work_bytes,
                       void* stream);
+
+/* Size of the static per-GPU workspace array of chebyshev_moments_noalloc. */
+#define KPM_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+
+/* chebyshev_moments for callers that cannot allocate device memory (serving
+ * loops with a fixed memory budget, harnesses that forbid hipMalloc): the same
+ * problems, parameters, results and status codes as chebyshev_moments, but no
+ * device allocation of any kind (no hipMalloc/hipFree, no captured graph, no
+ * events).  Differences:
+ *  - Workspace: a file-scope device array of KPM_NOALLOC_MAX_BYTES bytes, one
+ *    per GPU, loaded with the library and held until the process ends.  A call
+ *    whose chebyshev_moments_workspace_size() exceeds it returns KPM_ETOOLARGE
+ *    and writes nothing.  The array keeps the last call's contents; the call
+ *    clears what must start at zero itself.
+ *  - Sharing: every call on one GPU uses that GPU's one array.  Two calls that
+ *    overlapped on one GPU would race, so the library serialises them with a
+ *    per-GPU mutex held until the call's stream has drained (each call
+ *    synchronises `stream` before it returns); concurrent callers wait.
+ *  - q->autotune must be 0 (KPM_EINVAL otherwise): the planner's launch shape
+ *    is used, so results equal chebyshev_moments' with autotune 0.
+ *  - Recursion steps are launched one by one on `stream`; kpm_last_run_stats
+ *    then reports graph_segment 0 and recursion_ms -1.
+ *  d_mu  device double [n][M];  d_ab  device double [n][2] = (a, b), may be NULL.
+ * Not for use under stream capture (it synchronises `stream`). */
+int chebyshev_moments_noalloc(const kpm_problem* p, int32_t n, const kpm_params* q,
+                              double* d_mu, double* d_ab, void* stream);
 
 /* Workspace bytes for chebyshev_vectors (0 if the arguments are invalid). */
 size_t chebyshev_vectors_workspace_size(const kpm_problem* p, const kpm_params* q,

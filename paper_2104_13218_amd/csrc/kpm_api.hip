@@ -1451,9 +1451,11 @@ int graph_segment() {
 }
 
 // Init, K recursion steps (graph-captured segments), final reduction,
-// doubling identities and estimator.
+// doubling identities and estimator.  `direct`: every step is launched on
+// `st` itself, with no captured graph, helper stream or timing events (the
+// allocation-free entry point; recursion_ms is then -1).
 int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_params& q,
-                double* d_mu, hipStream_t st) {
+                double* d_mu, hipStream_t st, bool direct) {
   DevicePlan& D = P.plan;
   const int K = n_steps(q.M);
   const int TC = D.total_cols;
@@ -1477,22 +1479,24 @@ int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
   KPM_HIP(launch_init(D, vec, 1, q.vec_kind, q.seed, norms, part[0], st));
   KPM_HIP(launch_reduce(D, part[0], alpha, nullptr, st));
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  KPM_HIP(hipEventCreate(&ev0));
-  if (hipEventCreate(&ev1) != hipSuccess) {
-    (void)hipEventDestroy(ev0);
-    return KPM_EDEVICE;
+  if (!direct) {
+    KPM_HIP(hipEventCreate(&ev0));
+    if (hipEventCreate(&ev1) != hipSuccess) {
+      (void)hipEventDestroy(ev0);
+      return KPM_EDEVICE;
+    }
   }
   struct EvGuard {
     hipEvent_t a, b;
     ~EvGuard() {
-      (void)hipEventDestroy(a);
-      (void)hipEventDestroy(b);
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
     }
   } evg{ev0, ev1};
-  KPM_HIP(hipEventRecord(ev0, st));
+  if (ev0) KPM_HIP(hipEventRecord(ev0, st));
   KPM_HIP(launch_step(D, vec, part[0], nullptr, 0, alpha, beta, nullptr, 0, 0, 1, st));
   int s = 1;
-  const int S = graph_segment();
+  const int S = direct ? 0 : graph_segment();
   int used_segment = 0;
   if (S >= 2 && K - 1 >= S) {
     hipStream_t cap;
@@ -1520,7 +1524,7 @@ int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
   for (; s < K; ++s)
     KPM_HIP(launch_step(D, vec, part[s & 1], part[(s - 1) & 1], 2 * TC, alpha, beta, nullptr, s,
                         s & 1, 0, st));
-  KPM_HIP(hipEventRecord(ev1, st));
+  if (ev1) KPM_HIP(hipEventRecord(ev1, st));
   KPM_HIP(launch_reduce(D, part[(K - 1) & 1], alpha + (size_t)K * TC, beta + (size_t)(K - 1) * TC, st));
   FinalArgs fa{};
   fa.probs = D.probs;
@@ -1556,7 +1560,7 @@ int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
   g_stats.relabelled = 0;
   for (const auto& d : P.probs) g_stats.relabelled += d.relabel;
   float ms = 0.f;
-  g_stats.recursion_ms = hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess ? (double)ms : -1.0;
+  g_stats.recursion_ms = ev0 && hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess ? (double)ms : -1.0;
   if (h_flag & 2) return KPM_EDEVICE;
   return (h_flag & 1) ? KPM_EBOUNDS : KPM_OK;
 }
@@ -2145,6 +2149,67 @@ int ed_plan(const kpm_problem* p, int n, int max_dim, EdPlan& E) {
   return KPM_OK;
 }
 
+// chebyshev_moments on `need` bytes of device workspace at `work` (checked by
+// the caller); `direct` as in run_moments.  Arguments are validated already.
+int moments_on_workspace(const kpm_problem* p, int n, const kpm_params* q, double* d_mu,
+                         double* d_ab, unsigned char* work, size_t need, hipStream_t st,
+                         bool direct) {
+  // sizes first (plan without scale) to place the Lanczos region
+  Planned P0;
+  int r = make_plan(p, n, shape_of(*q), nullptr, nullptr, P0);
+  if (r != KPM_OK) return r;
+  const MomLayout L0 = moments_layout(P0, n_steps(q->M), 0);
+  std::vector<double> a, b;
+  r = resolve_scale(p, n, *q, work + L0.lz, st, a, b);
+  if (r != KPM_OK) return r;
+  Tune tn{};
+  if (q->autotune) {
+    r = get_tune(p, n, *q, a.data(), b.data(), work, need, st, tn);
+    if (r != KPM_OK) return r;
+  }
+  Planned P;
+  r = make_plan(p, n, shape_of(*q, &tn), a.data(), b.data(), P);
+  if (r != KPM_OK) return r;
+  const MomLayout L = moments_layout(P, n_steps(q->M), 0);
+  if (L.total > need) return KPM_EWORKSPACE;
+  std::vector<unsigned char> staging;
+  r = upload_plan(P, work + L.plan, staging, st);
+  if (r != KPM_OK) return r;
+  std::vector<double> ab(2 * n);
+  for (int i = 0; i < n; ++i) {
+    ab[2 * i] = a[i];
+    ab[2 * i + 1] = b[i];
+  }
+  if (d_ab) KPM_HIP(hipMemcpyAsync(d_ab, ab.data(), ab.size() * 8, hipMemcpyHostToDevice, st));
+  return run_moments(P, L, work, *q, d_mu, st, direct);
+}
+
+}  // namespace
+
+// Workspace of chebyshev_moments_noalloc: one array per GPU, loaded with the
+// library's code object and held until the process ends.  In host code
+// `scratch` names only a host-side stand-in; kernels get the device address
+// that scratch_address() looks up.
+static __device__ __align__(256) unsigned char scratch[KPM_NOALLOC_MAX_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu[kMaxDevices];              // held for a whole call on that GPU
+unsigned char* g_scratch_ptr[kMaxDevices] = {};    // device address, once looked up
+
+// Device address of the current GPU's `scratch`, looked up on the first call
+// on that GPU (with it current) and kept.  Caller holds g_scratch_mu[dev].
+int scratch_address(int dev, unsigned char** out) {
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return KPM_EDEVICE;
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return KPM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2157,6 +2222,7 @@ const char* kpm_strerror(int code) {
     case KPM_EDEVICE: return "HIP runtime error";
     case KPM_EBOUNDS: return "spectral bounds do not enclose the spectrum (|mu_n| > mu_0)";
     case KPM_EWORKSPACE: return "workspace too small";
+    case KPM_ETOOLARGE: return "needs more scratch than KPM_NOALLOC_MAX_BYTES (64 MiB) per GPU";
     default: return "unknown status";
   }
 }
@@ -2287,34 +2353,27 @@ int chebyshev_moments(const kpm_problem* p, int32_t n, const kpm_params* q, doub
   } else if (work_bytes < need) {
     return KPM_EWORKSPACE;
   }
-  // sizes first (plan without scale) to place the Lanczos region
-  Planned P0;
-  r = make_plan(p, n, shape_of(*q), nullptr, nullptr, P0);
+  return moments_on_workspace(p, n, q, d_mu, d_ab, work, need, st, false);
+}
+
+int chebyshev_moments_noalloc(const kpm_problem* p, int32_t n, const kpm_params* q, double* d_mu,
+                              double* d_ab, void* stream) {
+  int r = check_problems(p, n);
   if (r != KPM_OK) return r;
-  const MomLayout L0 = moments_layout(P0, n_steps(q->M), 0);
-  std::vector<double> a, b;
-  r = resolve_scale(p, n, *q, work + L0.lz, st, a, b);
+  if (!q || check_params(*q) != KPM_OK || !d_mu || q->autotune != 0) return KPM_EINVAL;
+  const size_t need = moments_workspace(p, n, *q);
+  if (need == 0) return KPM_EINVAL;
+  if (need > KPM_NOALLOC_MAX_BYTES) return KPM_ETOOLARGE;
+  int dev = 0;
+  KPM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return KPM_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu[dev]);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  StreamSync guard{st};  // released before the lock: the array is idle when the next call starts
+  unsigned char* work = nullptr;
+  r = scratch_address(dev, &work);
   if (r != KPM_OK) return r;
-  Tune tn{};
-  if (q->autotune) {
-    r = get_tune(p, n, *q, a.data(), b.data(), work, need, st, tn);
-    if (r != KPM_OK) return r;
-  }
-  Planned P;
-  r = make_plan(p, n, shape_of(*q, &tn), a.data(), b.data(), P);
-  if (r != KPM_OK) return r;
-  const MomLayout L = moments_layout(P, n_steps(q->M), 0);
-  if (L.total > need) return KPM_EWORKSPACE;
-  std::vector<unsigned char> staging;
-  r = upload_plan(P, work + L.plan, staging, st);
-  if (r != KPM_OK) return r;
-  std::vector<double> ab(2 * n);
-  for (int i = 0; i < n; ++i) {
-    ab[2 * i] = a[i];
-    ab[2 * i + 1] = b[i];
-  }
-  if (d_ab) KPM_HIP(hipMemcpyAsync(d_ab, ab.data(), ab.size() * 8, hipMemcpyHostToDevice, st));
-  return run_moments(P, L, work, *q, d_mu, st);
+  return moments_on_workspace(p, n, q, d_mu, d_ab, work, need, st, true);
 }
 
 static kpm_params vectors_params(const kpm_params& q, int32_t n_vec) {

@@ -18,6 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkpm.so")
 
 KPM_OK, KPM_EINVAL, KPM_ENOMEM, KPM_EDEVICE, KPM_EBOUNDS, KPM_EWORKSPACE = 0, -1, -2, -3, -4, -5
+KPM_ETOOLARGE = -6
+NOALLOC_MAX_BYTES = 64 << 20  # KPM_NOALLOC_MAX_BYTES of include/kpm.h
 VEC_KINDS = {"rademacher": 0, "complex_gaussian": 1, "gaussian": 2, "basis": 3}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 KERNELS = {"none": 0, "jackson": 1}
@@ -61,6 +63,8 @@ _SIGS = {
     "chebyshev_moments_workspace_size": (c_size_t, [POINTER(Problem), c_int32, POINTER(Params)]),
     "chebyshev_moments": (c_int32, [POINTER(Problem), c_int32, POINTER(Params), c_void_p, c_void_p,
                                     c_void_p, c_size_t, c_void_p]),
+    "chebyshev_moments_noalloc": (c_int32, [POINTER(Problem), c_int32, POINTER(Params), c_void_p,
+                                            c_void_p, c_void_p]),
     "chebyshev_vectors_workspace_size": (c_size_t, [POINTER(Problem), POINTER(Params), c_int32]),
     "chebyshev_vectors": (c_int32, [POINTER(Problem), POINTER(Params), c_int32, c_void_p, c_void_p,
                                     c_void_p, c_size_t, c_void_p]),
@@ -229,6 +233,26 @@ def chebyshev_moments(sectors, M, R=1, vec_kind="rademacher", precision="fp64", 
         workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     _check(load().chebyshev_moments(ps.arr, len(ps), ctypes.byref(q), _ptr(mu), _ptr(ab), _ptr(workspace),
                                     workspace.numel(), _stream(stream)), "chebyshev_moments")
+    return mu, ab
+
+
+def chebyshev_moments_noalloc(sectors, M, R=1, vec_kind="rademacher", precision="fp64", eps=0.025,
+                              seed=0, col_block=0, bounds=None, lanczos_steps=50, margin=0.01,
+                              stream=None, problems=None, out=None):
+    """chebyshev_moments on the library's static per-GPU workspace (no device
+    allocation inside the call).  `out` = (mu [n, M], ab [n, 2]) float64 cuda
+    tensors to write into; allocated here when None."""
+    ps = problems or ProblemSet(sectors, bounds)
+    q = make_params(M, R, vec_kind, precision, eps, seed, col_block, lanczos_steps, margin, False)
+    if out is None:
+        out = (torch.empty((len(ps), M), dtype=torch.float64, device="cuda"),
+               torch.empty((len(ps), 2), dtype=torch.float64, device="cuda"))
+    mu, ab = out
+    if mu.shape != (len(ps), M) or ab.shape != (len(ps), 2) or mu.dtype != torch.float64 \
+            or ab.dtype != torch.float64 or not (mu.is_contiguous() and ab.is_contiguous()):
+        raise KPMError(KPM_EINVAL, "chebyshev_moments_noalloc: out shapes")
+    _check(load().chebyshev_moments_noalloc(ps.arr, len(ps), ctypes.byref(q), _ptr(mu), _ptr(ab),
+                                            _stream(stream)), "chebyshev_moments_noalloc")
     return mu, ab
 
 

@@ -249,3 +249,25 @@ def test_cluster_bond_grad_rejects_mixed_bond_lists(kpmlib):
     assert lib.kpm_cluster_bond_grad(mixed.arr, len(mixed), dummy, dummy, None) == kpmlib.KPM_EINVAL
     ok = kpmlib.ProblemSet([W.Sector(c2, 3, 0), W.Sector(c2, 4, 0)])
     assert lib.kpm_cluster_bond_grad(ok.arr, len(ok), None, dummy, None) == kpmlib.KPM_EINVAL
+
+
+def test_noalloc_rejections_on_host(kpmlib):
+    """chebyshev_moments_noalloc checks its arguments and its size limit before
+    any HIP call: autotune is refused, and a call whose workspace exceeds
+    KPM_NOALLOC_MAX_BYTES is KPM_ETOOLARGE."""
+    import workloads as W
+    lib = kpmlib.load()
+    assert lib.kpm_strerror(kpmlib.KPM_ETOOLARGE).decode().startswith("needs more scratch")
+    small = _problem(kpmlib)
+    q = kpmlib.make_params(M=16, R=2)
+    assert lib.chebyshev_moments_noalloc(small.arr, 1, ctypes.byref(q), None, None, None) == kpmlib.KPM_EINVAL
+    q_tuned = kpmlib.make_params(M=16, R=2, autotune=True)
+    dummy = ctypes.c_void_p(16)   # never dereferenced: rejected before any device work
+    assert lib.chebyshev_moments_noalloc(small.arr, 1, ctypes.byref(q_tuned), dummy, None,
+                                         None) == kpmlib.KPM_EINVAL
+    big = kpmlib.ProblemSet([s for s in W.sectors(W.ring(22)) if 2 * s.n_up == 22])
+    q_big = kpmlib.make_params(M=64, R=10, vec_kind="complex_gaussian")
+    need = lib.chebyshev_moments_workspace_size(big.arr, 1, ctypes.byref(q_big))
+    assert need > kpmlib.NOALLOC_MAX_BYTES
+    assert lib.chebyshev_moments_noalloc(big.arr, 1, ctypes.byref(q_big), dummy, None,
+                                         None) == kpmlib.KPM_ETOOLARGE
