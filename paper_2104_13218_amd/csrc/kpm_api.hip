@@ -250,13 +250,14 @@ struct Planned {
   std::vector<uint16_t> lunr;
   std::vector<uint32_t> cmask;        // bonds in class order (slice kernel)
   std::vector<double> coff, czz;
+  std::vector<int32_t> wg_tile;       // slice kernel: workgroup -> tile (-1 none)
   DevicePlan plan;
   double bytes_per_step = 0;     // algorithmic (3 * storage * dim * real columns)
   double state_cols = 0;         // sum of dim * real columns
   // byte offsets of the packed plan arrays
   size_t o_probs, o_units, o_tile, o_job, o_pu0, o_tab, o_mask, o_off, o_zz, o_binom, o_trow0,
       o_tnrows, o_bperm, o_tsub0, o_subn, o_lrank, o_bh, o_bst, o_sb0, o_snb, o_lunr, o_koff, o_cmask,
-      o_coff, o_czz, bytes;
+      o_coff, o_czz, o_wgt, bytes;
 };
 
 int env_int(const char* name, int dflt) {
@@ -806,7 +807,9 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   if (s.tune.spt > 0) spt = s.tune.spt;
   if (const int f = env_int("KPM_SUB_PER_TILE", 0)) spt = f;
   D.sub_per_tile = spt;
-  D.xcd_remap = env_int("KPM_XCD_REMAP", 1);
+  // slice kernel: every XCD on the same column block at a time (measured 4 %
+  // faster on the 24-site ring than contiguous tile ranges per XCD)
+  D.xcd_remap = env_int("KPM_XCD_REMAP", D.block == 3 ? 2 : 1);
   D.dense = env_int("KPM_DENSE_LISTS", 0);
   const int64_t tile_rows = (int64_t)D.sub_rows * spt;
 
@@ -909,6 +912,23 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   D.n_units = (int32_t)P.units.size();
   D.n_tiles = tiles;
   D.grid_tiles = (tiles + 7) / 8 * 8;
+  // Slice kernel, KPM_XCD_REMAP=2: each unit's tiles in 8 contiguous chunks,
+  // chunk x to XCD x (workgroup b runs on XCD b mod 8), units one after the
+  // other, so that all XCDs sweep the same column block at the same time.
+  P.wg_tile.clear();
+  D.slice_grid = 0;
+  if (D.block == 3 && D.xcd_remap == 2) {
+    for (const UnitDev& u : P.units) {
+      const int c = (u.ntiles + 7) / 8;
+      for (int j = 0; j < c; ++j)
+        for (int x = 0; x < 8; ++x) {
+          const int t = x * c + j;
+          P.wg_tile.push_back(t < u.ntiles ? u.tile0 + t : -1);
+        }
+    }
+    if (P.wg_tile.empty() || P.wg_tile.size() > (size_t)INT32_MAX) return KPM_EINVAL;
+    D.slice_grid = (int32_t)P.wg_tile.size();
+  }
   D.total_cols = col_off;
   D.part_len = std::max<int64_t>(part_len, 1);
   D.slot_stride = vec_elems;
@@ -946,6 +966,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   P.o_cmask = put(P.cmask.size() * 4);
   P.o_coff = put(P.coff.size() * 8);
   P.o_czz = put(P.czz.size() * 8);
+  P.o_wgt = put(P.wg_tile.size() * 4);
   P.bytes = o;
   return KPM_OK;
 }
@@ -982,6 +1003,7 @@ int upload_plan(Planned& P, unsigned char* dst, std::vector<unsigned char>& stag
   cp(P.o_cmask, P.cmask.data(), P.cmask.size() * 4);
   cp(P.o_coff, P.coff.data(), P.coff.size() * 8);
   cp(P.o_czz, P.czz.data(), P.czz.size() * 8);
+  cp(P.o_wgt, P.wg_tile.data(), P.wg_tile.size() * 4);
   KPM_HIP(hipMemcpyAsync(dst, staging.data(), P.bytes, hipMemcpyHostToDevice, st));
   DevicePlan& D = P.plan;
   D.probs = reinterpret_cast<ProbDev*>(dst + P.o_probs);
@@ -1009,6 +1031,7 @@ int upload_plan(Planned& P, unsigned char* dst, std::vector<unsigned char>& stag
   D.cmask = reinterpret_cast<uint32_t*>(dst + P.o_cmask);
   D.coff = reinterpret_cast<double*>(dst + P.o_coff);
   D.czz = reinterpret_cast<double*>(dst + P.o_czz);
+  D.wg_tile = P.wg_tile.empty() ? nullptr : reinterpret_cast<int32_t*>(dst + P.o_wgt);
   return KPM_OK;
 }
 

@@ -130,6 +130,8 @@ struct StepArgs {
   int32_t slice_wb;            // bytes per word-table row (32 or 64)
   int32_t slice_words;         // rows per problem (1 << largest blk_L)
   int32_t blk_lds_rows;        // largest block (members), LDS rows of the slice kernel
+  const int32_t* wg_tile;      // slice kernel: tile of each workgroup (-1: none); NULL =
+                               // the xcd_remap mapping over grid_tiles workgroups
 };
 
 // Device-side plan of one run (pointers into the workspace) + launch shape.
@@ -185,6 +187,8 @@ struct DevicePlan {
   int32_t slice_wb = 0;        // slice kernel: word-table row bytes (0 = no slice plan)
   int32_t slice_words = 0;     // slice kernel: word-table rows per problem
   int32_t blk_lds_rows = 0;    // slice kernel: members of the largest block
+  int32_t* wg_tile = nullptr;  // slice kernel: tile of each of slice_grid workgroups
+  int32_t slice_grid = 0;      // slice kernel: workgroups launched (0 = grid_tiles)
   int32_t blk_max = 16, blk_rows = kThreads, lds_lr = 1, lds_hh = 1, lds_mx = 1, ld_max = 1;
   int64_t n_states = 0;        // entries of the state table
   int64_t part_len = 0;        // doubles per partial buffer

@@ -1861,6 +1861,7 @@ static StepArgs make_step_args(const DevicePlan& p) {
       a.slice_wb = p.slice_wb;
       a.slice_words = p.slice_words;
       a.blk_lds_rows = p.blk_lds_rows;
+      a.wg_tile = p.wg_tile;
     }
   }
   return a;

@@ -226,8 +226,7 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
       const UnitDev U = sload(a.units + cview(a.job_unit)[job]);
       const int v = job - 2 * U.col_off;
       const double* p = a.part_in + U.part_off + (int64_t)v * U.ntiles;
-      double acc = 0.0;
-      for (int t = lane; t < U.ntiles; t += 64) acc += p[t];
+      double acc = strided_sum(p, U.ntiles, lane, 64);
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
       if (lane == 0) {
@@ -237,8 +236,9 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
     }
   }
 
-  const int tile = a.xcd_remap ? xcd_tile(blockIdx.x, a.grid_tiles) : (int)blockIdx.x;
-  if (tile >= a.n_tiles) return;
+  const int tile = a.wg_tile ? cview(a.wg_tile)[blockIdx.x]
+                             : (a.xcd_remap ? xcd_tile(blockIdx.x, a.grid_tiles) : (int)blockIdx.x);
+  if (tile < 0 || tile >= a.n_tiles) return;
   const UnitDev U = sload(a.units + cview(a.tile_unit)[tile]);
   const ProbDev P = sload(a.probs + U.prob);
   const int rl = lane / NCH;
@@ -510,7 +510,7 @@ static hipError_t launch_slice_t(const StepArgs& a, size_t lds, int grid, int gh
 // Every unit of a slice plan has ld = cpl * nch with nch 1 or 2.
 hipError_t launch_slice(const DevicePlan& p, const StepArgs& a, hipStream_t st) {
   const size_t lds = slice_lds_bytes(p);
-  const int grid = p.grid_tiles;
+  const int grid = p.slice_grid > 0 ? p.slice_grid : p.grid_tiles;
   const int gh = p.gather_batch;
   const int wb = p.slice_wb;
   const int nch = p.ld_max / p.cpl;

@@ -95,11 +95,27 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
+// p[first] + p[first + stride] + ... (indices < n) in a fixed association:
+// eight running sums, so that eight loads are in flight per lane, added in
+// index order at the end.
+__device__ __forceinline__ double strided_sum(const double* p, int n, int first, int stride) {
+  double s[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s[j] = 0.0;
+  int t = first;
+  for (; t + 7 * stride < n; t += 8 * stride) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j] += p[t + j * stride];
+  }
+#pragma unroll
+  for (int j = 0; j < 7; ++j)
+    if (t + j * stride < n) s[j] += p[t + j * stride];
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
 // Sum of n partials in a fixed order (strided per thread, then tree).
 __device__ __forceinline__ double sum_partials(const double* p, int n, double* sh) {
-  double acc = 0.0;
-  for (int t = threadIdx.x; t < n; t += kThreads) acc += p[t];
-  return block_sum(acc, sh);
+  return block_sum(strided_sum(p, n, threadIdx.x, kThreads), sh);
 }
 
 }  // namespace kpm

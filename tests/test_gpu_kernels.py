@@ -36,6 +36,8 @@ KERNELS = {
                      "KPM_SUB_PER_TILE": "3", "KPM_GATHER_BATCH": "4"}, 5),
     "slice_l4": ({"KPM_BLOCK": "3", "KPM_BLOCK_L": "4", "KPM_SUB_PER_TILE": "1"}, 5),
     "slice_l10": ({"KPM_BLOCK": "3", "KPM_BLOCK_L": "10", "KPM_SUB_PER_TILE": "2"}, 5),
+    # contiguous tile ranges per XCD in place of the default per-column-block chunks
+    "slice_contig": ({"KPM_BLOCK": "3", "KPM_XCD_REMAP": "1"}, 5),
 }
 
 
@@ -130,6 +132,23 @@ def test_kernels_agree_ring20(kpm, monkeypatch):
     ref = out["chunk"]
     for name, mu in out.items():
         assert np.abs(mu - ref).max() <= 1e-11 * ref[0], name
+
+
+def test_slice_workgroup_mappings_identical(kpm, monkeypatch):
+    """The slice kernel's workgroup-to-tile maps (per-column-block chunks per
+    XCD, with idle workgroups where a block's tile count is not a multiple of
+    8, and contiguous ranges) run the same tiles: bit-identical moments on a
+    batch of many problems and column blocks."""
+    secs = list(_batched()) + W.sectors(W.ring(18), only_sz0=True)
+    bl = [_bounds(s)[0] for s in secs]
+    monkeypatch.setenv("KPM_BLOCK", "3")
+    out = {}
+    for remap in ("1", "2"):
+        monkeypatch.setenv("KPM_XCD_REMAP", remap)
+        mu, _ = kpm.chebyshev_moments(secs, 64, 10, "complex_gaussian", "fp32", 0.025, 6, 4, bounds=bl)
+        assert kpm.last_run_stats()["kernel"] == 5
+        out[remap] = mu.cpu().numpy()
+    assert np.array_equal(out["1"], out["2"])
 
 
 # ------------------------------------------------- relabelled sites (block kernels)
