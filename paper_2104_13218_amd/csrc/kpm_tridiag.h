@@ -4,6 +4,14 @@
 // of every normalised eigenvector, by the implicit QL method with the shift
 // from the trailing 2x2 block.  Only row 0 of the accumulated plane rotations
 // is kept (it starts as the unit vector e_0), so the cost is O(n^2).
+//
+// Source of the method: the implicit QL algorithm of A. Bowdler, R. S. Martin,
+// C. Reinsch and J. H. Wilkinson, "The QR and QL algorithms for symmetric
+// matrices", Numer. Math. 11, 293-306 (1968), as distributed in EISPACK (tql1,
+// tql2) and restated in Numerical Recipes (tqli).  The sweep, the Wilkinson-
+// type shift, the deflation test |e_m| + (|d_m| + |d_m+1|) == |d_m| + |d_m+1|
+// and the single-letter variable names follow that published form; the change
+// here is that the eigenvector update is restricted to row 0.
 #pragma once
 
 #include <hip/hip_runtime.h>

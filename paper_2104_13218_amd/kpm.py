@@ -15,7 +15,8 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libkpm.so")
+# KPM_LIBRARY names another build of the same library (the sanitized one)
+LIB_PATH = os.environ.get("KPM_LIBRARY") or os.path.join(_HERE, "libkpm.so")
 
 KPM_OK, KPM_EINVAL, KPM_ENOMEM, KPM_EDEVICE, KPM_EBOUNDS, KPM_EWORKSPACE = 0, -1, -2, -3, -4, -5
 KPM_ETOOLARGE = -6
