@@ -85,11 +85,11 @@ def _parse():
     return ap.parse_args()
 
 
-def _traffic(family):
-    """Measured HBM bytes per step launch from the committed rocprofv3 counter
-    summary of this kernel on this workload, when it was taken on the current
-    kernel source."""
-    path = os.path.join(PROFILES, f"{family}_ring24_sz0_fp32_traffic.json")
+def _traffic(family, tag="ring24_sz0_fp32"):
+    """Measured HBM-side bytes per step launch from the committed rocprofv3
+    counter summary of this kernel on this workload (`tag`), when it was taken
+    on the current kernel source."""
+    path = os.path.join(PROFILES, f"{family}_{tag}_traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
@@ -243,13 +243,17 @@ def _line(args, workload, value, unit, dt, config, roofline=None, extra=None):
     return line
 
 
-def _roofline(st):
+def _roofline(st, tag=None):
     t = st["recursion_ms"] / 1e3 / st["step_launches"]
     ach = st["bytes_per_launch"] / t / 1e9
-    return {"bound": "hbm", "kernel": KERNEL_FAMILY.get(st["kernel"], "step_kernel"), "achieved": ach,
+    family = KERNEL_FAMILY.get(st["kernel"], "step_kernel")
+    traffic = _traffic(family, tag) if tag else None
+    return {"bound": "hbm", "kernel": family, "achieved": ach,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "algorithmic_bytes_per_launch": st["bytes_per_launch"], "avg_launch_us": t * 1e6,
-            "traffic": None}
+            "traffic": traffic,
+            "measured_GBs": None if traffic is None else traffic / t / 1e9,
+            "measured_frac": None if traffic is None else traffic / t / 1e9 / HBM_PEAK_GBS}
 
 
 def _timed(args, torch, fn):
@@ -288,10 +292,11 @@ def other_workload(args, kpm, W, np, torch, dev):
         if name == "rr4_30":
             dt64, st64 = _timed(args, torch, lambda: run("fp64"))
             extra = {"fp64": {"value": st64["state_col_steps"] / dt64, "ms": dt64 * 1e3,
-                              "roofline": _roofline(st64)},
+                              "roofline": _roofline(st64, "rr4_30_sz0_fp64")},
                      "speedup_vs_fp64": (st["state_col_steps"] / dt) / (st64["state_col_steps"] / dt64)}
+        tag = "rr4_30_sz0_fp32" if name == "rr4_30" else "batched_rr3_fp32"
         return _line(args, name, st["state_col_steps"] / dt, "state-column-steps/s", dt, cfg,
-                     _roofline(st), extra)
+                     _roofline(st, tag), extra)
     if name == "fe10":
         wl = W.fe10_workload("fp32")
         ab = kpm.spectral_bounds(wl.problems)              # fixed bounds: Lanczos outside the timing
