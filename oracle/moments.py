@@ -20,6 +20,35 @@ import scipy.linalg as sla
 from . import basis, hamiltonian, rng
 
 
+F32R = "f32r"   # storage name of the float32 + 16-bit residual form
+
+
+def f32_residual16(x) -> np.ndarray:
+    """The stored values of the float32 + 16-bit residual storage form.
+
+    Not in the paper (it fixes no storage format): a reduced-storage form of
+    this implementation, defined here as its reference.  Each element x is kept
+    as hi = float32(x) (round to nearest even) and the integer
+    q = rint((x - hi) * 2**(165 - e)) (half to even), where e is the biased
+    exponent of hi, at least 1; the stored value is hi + q * 2**(e - 165).
+    |x - hi| <= 2**(e - 151), so |q| <= 2**14 and the stored value is x to
+    within 2**(e - 166) (relative 2**-39 for normal hi).  Returns float64."""
+    x = np.asarray(x, dtype=np.float64)
+    hi = x.astype(np.float32)
+    e = np.maximum((hi.view(np.uint32) >> 23) & 0xFF, 1).astype(np.int64)
+    unit = np.ldexp(np.ones_like(x), (e - 165).astype(np.int32))
+    q = np.rint((x - hi.astype(np.float64)) / unit)
+    return hi.astype(np.float64) + q * unit
+
+
+def stored(x, store) -> np.ndarray:
+    """x rounded as the storage form `store` keeps it: a numpy float type
+    (float64, float32) or F32R."""
+    if isinstance(store, str) and store == F32R:
+        return f32_residual16(x)
+    return np.asarray(x).astype(store)
+
+
 def n_steps(M: int) -> int:
     """Matrix-vector products needed for mu_0..mu_{M-1} by doubling."""
     return max(1, M // 2)
@@ -27,20 +56,21 @@ def n_steps(M: int) -> int:
 
 def chebyshev_dots(Ht, V0: np.ndarray, K: int, store=np.float64, keep=False):
     """Run the recursion for K products.  Vectors are stored in `store`
-    precision (float64, or float32 for the reduced-storage form); products and
-    sums are float64.  Returns alpha[n] = <v_n, v_n> (n = 0..K) and
-    beta[n] = <v_{n+1}, v_n> (n = 0..K-1), per column, from the stored values."""
+    precision (float64, float32 or F32R for the reduced-storage forms);
+    products and sums are float64.  Returns alpha[n] = <v_n, v_n> (n = 0..K)
+    and beta[n] = <v_{n+1}, v_n> (n = 0..K-1), per column, from the stored
+    values."""
     f64 = np.float64
-    prev = np.asarray(V0, dtype=f64).astype(store)
+    prev = stored(np.asarray(V0, dtype=f64), store)
     alpha = np.zeros((K + 1, V0.shape[1]))
     beta = np.zeros((K, V0.shape[1]))
     alpha[0] = np.einsum("ij,ij->j", prev.astype(f64), prev.astype(f64))
-    cur = (Ht @ prev.astype(f64)).astype(store)
+    cur = stored(Ht @ prev.astype(f64), store)
     saved = [prev, cur] if keep else None
     alpha[1] = np.einsum("ij,ij->j", cur.astype(f64), cur.astype(f64))
     beta[0] = np.einsum("ij,ij->j", cur.astype(f64), prev.astype(f64))
     for n in range(1, K):
-        nxt = (2.0 * (Ht @ cur.astype(f64)) - prev.astype(f64)).astype(store)
+        nxt = stored(2.0 * (Ht @ cur.astype(f64)) - prev.astype(f64), store)
         alpha[n + 1] = np.einsum("ij,ij->j", nxt.astype(f64), nxt.astype(f64))
         beta[n] = np.einsum("ij,ij->j", nxt.astype(f64), cur.astype(f64))
         prev, cur = cur, nxt
@@ -148,7 +178,7 @@ def sector_moments(sector, a: float, b: float, M: int, R: int, kind: str, seed: 
     dim = H.shape[0]
     V0, vec_of_col, R_eff = rng.random_columns(kind, seed, sector.cluster_id, sector.n_up, R, dim)
     if direct:
-        mu_cols = moments_direct(Ht, V0.astype(store).astype(np.float64), M)
+        mu_cols = moments_direct(Ht, stored(V0, store).astype(np.float64), M)
         norms = mu_cols[0]
     else:
         alpha, beta = chebyshev_dots(Ht, V0, n_steps(M), store=store)
