@@ -22,10 +22,15 @@ JSON line also carries:
                 summary, or null
   fp64_plain    the same recursion in float64, one column per block (the
                 reference form), and fp64_batched (float64, tuned blocks)
-  speedup_at_error_1e-6  float32 form over fp64_plain, with the temperature
-                band in which C(T) and chi(T) stay within 1e-6 of float64
-  accuracy      float32-storage error against float64 on the same seeds, all
-                13 S^z >= 0 sectors of the ring: C(T), chi(T), ln Z, E, moments
+  fp32r         the same recursion with float32 + 16-bit residual storage
+                (6 bytes per element, relative storage error <= 2^-38): rate,
+                speedups over both float64 comparators, and its accuracy
+  speedup_at_error_1e-6  float32 form (and the fp32r form) over fp64_plain,
+                with the temperature band in which C(T) and chi(T) stay
+                within 1e-6 of float64
+  accuracy      float32-storage (and fp32r) error against float64 on the same
+                seeds, all 13 S^z >= 0 sectors of the ring: C(T), chi(T),
+                ln Z, E, moments
   cpu_baseline  the CPU oracle on a bounded sample of the same workload (32
                 recursion steps of the same sector and columns): on the host's
                 cores (up to the 16 of a one-GPU share, columns split over
@@ -392,6 +397,42 @@ def _time_moments(kpm, torch, sec, M, R, kind, precision, col_block, reps=1):
     return mu, ab, dt, st
 
 
+def _accuracy(kpm, np, allsec, T, Th, mu64, ab64, mu_f, ab_f, curves=None):
+    """Error of a reduced-storage run against float64 on the same vectors:
+    moments, and per kernel g_n C(T), chi(T) (peak-normalised on T >= T_phys,
+    the lowest grid T from which the float64 estimate has Z > 0 and C >= 0)
+    with the lowest T above which the error stays <= 1e-6, ln Z and E."""
+    acc = {"moments_max_abs_err_over_mu0": float((mu_f - mu64).abs().max(dim=1).values.div(mu64[:, 0]).max())}
+    for kern in ("jackson", "none"):
+        t64 = kpm.thermo(mu64, ab64, allsec, T, kern)
+        tf = kpm.thermo(mu_f, ab_f, allsec, T, kern)
+        C64 = t64["C"].cpu().numpy()[0]
+        bad = np.nonzero((C64 < 0) | t64["z_nonpos"].cpu().numpy()[0].astype(bool))[0]
+        i_phys = bad.max() + 1 if bad.size else 0
+        band = np.arange(Th.size) >= i_phys
+        rec = {"T_phys": float(Th[min(i_phys, Th.size - 1)])}
+        for qn in ("C", "chi"):
+            a = t64[qn].cpu().numpy()[0]
+            b = tf[qn].cpu().numpy()[0]
+            err = np.abs(a - b) / np.abs(a[band]).max()
+            if curves is not None:
+                curves[f"{kern}_{qn}_err_over_peak"] = err.tolist()
+                curves[f"{kern}_{qn}_fp64"] = a.tolist()
+            rec[f"{qn}_max_err_T>=T_phys"] = float(err[band].max())
+            lowest = None
+            for i in range(Th.size - 1, -1, -1):
+                if err[i] > 1e-6:
+                    break
+                lowest = float(Th[i])
+            rec[f"{qn}_lowest_T_with_err<=1e-6"] = lowest
+        for qn in ("lnZ", "E"):
+            a = t64[qn].cpu().numpy()[0][band]
+            b = tf[qn].cpu().numpy()[0][band]
+            rec[f"{qn}_max_rel_err_T>=T_phys"] = float(np.nanmax(np.abs(a - b) / np.abs(a)))
+        acc[kern] = rec
+    return acc
+
+
 def extras(args, kpm, W, np, torch, sec, ps, T, M, value, ws):
     out = {}
     # float64 comparators on the same workload.  The single-column form needs
@@ -410,48 +451,39 @@ def extras(args, kpm, W, np, torch, sec, ps, T, M, value, ws):
     out["speedup_vs_fp64_plain"] = (stf["state_col_steps"] / dtf) / plain
     out["speedup_vs_fp64_batched"] = (stf["state_col_steps"] / dtf) / batched
 
-    # accuracy of float32 storage against float64, all S^z >= 0 sectors
+    # the float32 + 16-bit residual storage form (6 bytes per element)
+    _, _, dtr, str_ = _time_moments(kpm, torch, sec, M, 10, "complex_gaussian", "fp32r", 0)
+    out["fp32r"] = {"value": str_["state_col_steps"] / dtr, "ms": dtr * 1e3, "col_block": str_["col_block"],
+                    "kernel": KERNEL_FAMILY.get(str_["kernel"]),
+                    "avg_launch_us": str_["recursion_ms"] * 1e3 / str_["step_launches"],
+                    "dtype": "f32+i16-residual-storage/f64-arithmetic",
+                    "speedup_vs_fp64_plain": (str_["state_col_steps"] / dtr) / plain,
+                    "speedup_vs_fp64_batched": (str_["state_col_steps"] / dtr) / batched}
+
+    # accuracy of both reduced-storage forms against float64, all S^z >= 0 sectors
     allsec = W.sectors(W.ring(24))
     mu64, ab64 = kpm.chebyshev_moments(allsec, M, 10, "complex_gaussian", "fp64", 0.025, 0, col_block=20)
-    mu32, ab32 = kpm.chebyshev_moments(allsec, M, 10, "complex_gaussian", "fp32", 0.025, 0, col_block=20)
     Th = T.cpu().numpy()
-    acc = {"moments_max_abs_err_over_mu0": float((mu32 - mu64).abs().max(dim=1).values.div(mu64[:, 0]).max())}
     curves = {"T": Th.tolist()}
-    for kern in ("jackson", "none"):
-        t64 = kpm.thermo(mu64, ab64, allsec, T, kern)
-        t32 = kpm.thermo(mu32, ab32, allsec, T, kern)
-        C64 = t64["C"].cpu().numpy()[0]
-        bad = np.nonzero((C64 < 0) | t64["z_nonpos"].cpu().numpy()[0].astype(bool))[0]
-        i_phys = bad.max() + 1 if bad.size else 0
-        band = np.arange(Th.size) >= i_phys
-        rec = {"T_phys": float(Th[min(i_phys, Th.size - 1)])}
-        for qn in ("C", "chi"):
-            a = t64[qn].cpu().numpy()[0]
-            b = t32[qn].cpu().numpy()[0]
-            err = np.abs(a - b) / np.abs(a[band]).max()
-            curves[f"{kern}_{qn}_err_over_peak"] = err.tolist()
-            curves[f"{kern}_{qn}_fp64"] = a.tolist()
-            rec[f"{qn}_max_err_T>=T_phys"] = float(err[band].max())
-            ok = np.nonzero(err <= 1e-6)[0]
-            lowest = None
-            for i in range(Th.size - 1, -1, -1):
-                if err[i] > 1e-6:
-                    break
-                lowest = float(Th[i])
-            rec[f"{qn}_lowest_T_with_err<=1e-6"] = lowest
-        for qn in ("lnZ", "E"):
-            a = t64[qn].cpu().numpy()[0][band]
-            b = t32[qn].cpu().numpy()[0][band]
-            rec[f"{qn}_max_rel_err_T>=T_phys"] = float(np.nanmax(np.abs(a - b) / np.abs(a)))
-        acc[kern] = rec
-    out["accuracy_fp32_vs_fp64_all_sectors"] = acc
-    # the speedup holds where the float32 form meets C(T), chi(T) error <= 1e-6
-    # (peak-normalised) against float64: the temperature band, per kernel g_n
+    for form in ("fp32", "fp32r"):
+        mu_f, ab_f = kpm.chebyshev_moments(allsec, M, 10, "complex_gaussian", form, 0.025, 0, col_block=20)
+        acc = _accuracy(kpm, np, allsec, T, Th, mu64, ab64, mu_f, ab_f, curves if form == "fp32" else None)
+        if form == "fp32":
+            out["accuracy_fp32_vs_fp64_all_sectors"] = acc
+        else:
+            out["fp32r"]["accuracy_vs_fp64_all_sectors"] = acc
+    acc = out["accuracy_fp32_vs_fp64_all_sectors"]
+    accr = out["fp32r"]["accuracy_vs_fp64_all_sectors"]
+    # the speedup holds where the reduced-storage form meets C(T), chi(T) error
+    # <= 1e-6 (peak-normalised) against float64: the temperature band, per kernel g_n
     out["speedup_at_error_1e-6"] = {
         "speedup_vs_fp64_plain": out["speedup_vs_fp64_plain"],
         "T_grid": [float(Th[0]), float(Th[-1])],
         **{f"{kern}_{qn}_valid_for_T>=": acc[kern][f"{qn}_lowest_T_with_err<=1e-6"]
-           for kern in ("jackson", "none") for qn in ("C", "chi")}}
+           for kern in ("jackson", "none") for qn in ("C", "chi")},
+        "fp32r": {"speedup_vs_fp64_plain": out["fp32r"]["speedup_vs_fp64_plain"],
+                  **{f"{kern}_{qn}_valid_for_T>=": accr[kern][f"{qn}_lowest_T_with_err<=1e-6"]
+                     for kern in ("jackson", "none") for qn in ("C", "chi")}}}
     if args.accuracy_curve:
         # conditioning of C(T) in the moments, from the thermodynamics VJP at
         # one temperature at a time: kappa(T) = sum_{p,n} |dC/dmu_pn| mu_p0 / |C|

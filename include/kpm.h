@@ -65,6 +65,17 @@ extern "C" {
 /* ---- storage precision of the recursion vectors ------------------------- */
 #define KPM_FP64 0       /* float64 vectors, float64 arithmetic               */
 #define KPM_FP32_STORE 1 /* float32 vectors; float64 products, sums and dots  */
+#define KPM_FP32R_STORE 2 /* float32 vectors with a 16-bit residual per element
+                            (6 bytes): v = hi + q 2^(e - 165), hi = float32(v)
+                            rounded to nearest, e = max(1, biased exponent of
+                            hi), q = rint((v - hi) 2^(165 - e)), |q| <= 2^14;
+                            relative storage error <= 2^-38 (float32: 2^-24);
+                            float64 products, sums and dots.  A storage form of
+                            this library (the paper fixes none).  Taken by
+                            chebyshev_moments and chebyshev_moments_noalloc for
+                            spin-1/2 problems the slice step kernel can run
+                            (KPM_EINVAL otherwise, and in every other entry
+                            point) */
 
 /* ---- kernel coefficients g_n, Eq. (8) ----------------------------------- */
 #define KPM_KERNEL_NONE 0    /* g_n = 1 */

@@ -188,6 +188,15 @@ int check_params(const kpm_params& q) {
   return KPM_OK;
 }
 
+// chebyshev_moments (and its allocation-free form) also take the float32 +
+// residual storage; every other entry point refuses it through check_params.
+int check_params_moments(const kpm_params& q) {
+  if (q.precision != KPM_FP32R_STORE) return check_params(q);
+  kpm_params r = q;
+  r.precision = KPM_FP32_STORE;
+  return check_params(r);
+}
+
 int check_problems(const kpm_problem* p, int n) {
   if (!p || n < 1) return KPM_EINVAL;
   for (int i = 0; i < n; ++i) {
@@ -489,7 +498,8 @@ void block_tiles(int N, int k, int L, int rows, int blk_max, std::vector<int64_t
 // values; sizes do not depend on them.
 int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_arr,
               const double* b_arr, Planned& P) {
-  const int fp32 = s.precision == KPM_FP32_STORE;
+  const int resid = s.precision == KPM_FP32R_STORE;
+  const int fp32 = s.precision == KPM_FP32_STORE || resid;
   int rb = pick_col_block(p, n, s);
   int adj_ld = 0;
   if (s.adjoint) {
@@ -500,13 +510,17 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   // slice kernel (KPM_BLOCK=3 or tuned): rows of one or two 16-byte chunks, so
   // blocks of at most 8 float32 / 4 float64 columns, every unit padded to the
   // same width
+  // float32 + residual storage runs on the slice kernel only (rows of 2 or 4
+  // float32 columns and their residuals)
+  if (resid && s.adjoint) return KPM_EINVAL;
   const bool slice_req =
-      !s.adjoint && env_int("KPM_BLOCK", s.tune.kernel == 5 ? 3 : -1) == 3;
+      resid || (!s.adjoint && env_int("KPM_BLOCK", s.tune.kernel == 5 ? 3 : -1) == 3);
   if (slice_req) rb = std::min(rb, fp32 ? 8 : 4);
   int cpl = 1;
   if (fp32) cpl = rb >= (slice_req ? 3 : 4) ? 4 : (rb >= 2 ? 2 : 1);
   else cpl = rb >= 2 ? 2 : 1;
   if (const int f = env_int("KPM_CPL", 0)) cpl = f;
+  if (resid) cpl = rb >= 3 ? 4 : 2;
   if (adj_ld) cpl = std::min(cpl, adj_ld);
   const int elt = fp32 ? 4 : 8;
   // One lane per state (row kernel) when the block width has an instantiation.
@@ -618,8 +632,9 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   // Default: the block-table kernel for blocks too wide for the row kernel
   // (the measured case where it is the fastest kernel); KPM_BLOCK=0/1/2 and
   // the autotuner override.
-  const int block_env = env_int("KPM_BLOCK", kern < 0 ? -1
-                                                 : (kern == 2 ? 1 : (kern == 3 ? 2 : (kern == 5 ? 3 : 0))));
+  const int block_env = resid ? 3
+                              : env_int("KPM_BLOCK", kern < 0 ? -1
+                                                              : (kern == 2 ? 1 : (kern == 3 ? 2 : (kern == 5 ? 3 : 0))));
   const bool block_default = rb > 8;
   // the block-table kernel addresses a block's slot with 32-bit element offsets
   int64_t max_elems = 0;
@@ -716,6 +731,8 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
     }
   }
   int bspt = 1;
+  if (resid && (D.block != 3 || spin)) return KPM_EINVAL;   // no slice plan for these problems
+  D.resid = resid;
   if (D.block) D.row_ld = row_ld = 0;
   // relabelled sites: the kernels see the bonds (and so every word) in the new labels
   for (int i = 0; D.block && i < n; ++i) {
@@ -861,7 +878,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
       for (int j = 0; j < 2 * u.ld; ++j) P.job_unit.push_back((int32_t)P.units.size());
       tiles += u.ntiles;
       col_off += u.ld;
-      P.bytes_per_step += 3.0 * elt * (double)dim * u.ncols;
+      P.bytes_per_step += 3.0 * (resid ? 6 : elt) * (double)dim * u.ncols;
       P.state_cols += (double)dim * u.ncols;
       P.units.push_back(u);
     }
@@ -1242,7 +1259,8 @@ MomLayout moments_layout(const Planned& P, int K, size_t lz_bytes) {
     o = align_up(o + bytes);
     return r;
   };
-  const size_t elt = P.plan.fp32 ? 4 : 8;
+  // float32 + residual storage: the float32 part, then the int16 residuals
+  const size_t elt = P.plan.resid ? 6 : (P.plan.fp32 ? 4 : 8);
   const size_t TC = (size_t)P.plan.total_cols;
   L.plan = put(P.bytes);
   L.lz = o;   // Lanczos runs first and may reuse everything below
@@ -1282,7 +1300,8 @@ int lanczos_steps_of(const kpm_params& q) { return q.lanczos_steps > 0 ? q.lancz
 // is seen, and cached for the process.
 
 std::vector<Tune> tune_candidates(const kpm_problem* p, int n, const kpm_params& q) {
-  const bool fp32 = q.precision == KPM_FP32_STORE;
+  const bool resid = q.precision == KPM_FP32R_STORE;
+  const bool fp32 = q.precision == KPM_FP32_STORE || resid;
   const RunShape s0 = shape_of(q);
   int64_t maxc = 1;
   for (int i = 0; i < n; ++i) maxc = std::max<int64_t>(maxc, total_columns(p[i], s0));
@@ -1303,6 +1322,19 @@ std::vector<Tune> tune_candidates(const kpm_problem* p, int n, const kpm_params&
   for (int w : widths) {
     Tune t;
     t.col_block = w;
+    if (resid) {   // the slice kernel is the only one with this storage
+      if (w <= 8)
+        for (int spt : {1, 2, 3})
+          for (int gh : {4, 8}) {
+            Tune b = t;
+            b.kernel = 5;
+            b.block_L = 10;
+            b.spt = spt;
+            b.gather_batch = gh;
+            c.push_back(b);
+          }
+      continue;
+    }
     if (w <= 8) {
       t.kernel = 1;
       c.push_back(t);
@@ -2354,7 +2386,7 @@ int kpm_spectral_bounds(const kpm_problem* p, int32_t n, int32_t steps, double m
 }
 
 size_t chebyshev_moments_workspace_size(const kpm_problem* p, int32_t n, const kpm_params* q) {
-  if (check_problems(p, n) != KPM_OK || !q || check_params(*q) != KPM_OK) return 0;
+  if (check_problems(p, n) != KPM_OK || !q || check_params_moments(*q) != KPM_OK) return 0;
   return moments_workspace(p, n, *q);
 }
 
@@ -2362,7 +2394,7 @@ int chebyshev_moments(const kpm_problem* p, int32_t n, const kpm_params* q, doub
                       double* d_ab, void* d_work, size_t work_bytes, void* stream) {
   int r = check_problems(p, n);
   if (r != KPM_OK) return r;
-  if (!q || check_params(*q) != KPM_OK || !d_mu) return KPM_EINVAL;
+  if (!q || check_params_moments(*q) != KPM_OK || !d_mu) return KPM_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   StreamSync guard{st};
   const size_t need = moments_workspace(p, n, *q);
@@ -2383,7 +2415,7 @@ int chebyshev_moments_noalloc(const kpm_problem* p, int32_t n, const kpm_params*
                               double* d_ab, void* stream) {
   int r = check_problems(p, n);
   if (r != KPM_OK) return r;
-  if (!q || check_params(*q) != KPM_OK || !d_mu || q->autotune != 0) return KPM_EINVAL;
+  if (!q || check_params_moments(*q) != KPM_OK || !d_mu || q->autotune != 0) return KPM_EINVAL;
   const size_t need = moments_workspace(p, n, *q);
   if (need == 0) return KPM_EINVAL;
   if (need > KPM_NOALLOC_MAX_BYTES) return KPM_ETOOLARGE;

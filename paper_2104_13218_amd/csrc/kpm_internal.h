@@ -132,6 +132,9 @@ struct StepArgs {
   int32_t blk_lds_rows;        // largest block (members), LDS rows of the slice kernel
   const int32_t* wg_tile;      // slice kernel: tile of each workgroup (-1: none); NULL =
                                // the xcd_remap mapping over grid_tiles workgroups
+  int16_t* vec_lo;             // float32 + residual storage: the residual q of every
+                               // element, same element index as the float32 part
+                               // (NULL for plain float32 / float64 storage)
 };
 
 // Device-side plan of one run (pointers into the workspace) + launch shape.
@@ -164,6 +167,8 @@ struct DevicePlan {
   int32_t sub_rows = 256, sub_per_tile = 1, lds_nb = 0, lds_tab = 0, lds_bonds = 0;
   int32_t cpl = 1;
   int32_t fp32 = 0;
+  int32_t resid = 0;           // 1: float32 + 16-bit residual storage (fp32 is set too);
+                               // the residuals follow the float32 part, vec_elems int16
   int32_t xcd_remap = 1;
   int32_t dense = 0;
   int32_t row_ld = 0;          // > 0: one lane per state with all row_ld columns
@@ -213,6 +218,7 @@ struct InitArgs {
   const int64_t* tile_row0;
   const int32_t* tile_nrows;
   void* vec;                 // slot 0 is written
+  int16_t* lo;               // float32 + residual storage: residual part (NULL otherwise)
   const double* norms;   // per column: Gaussian sums of squares (modes 1, 2)
   double* part_out;
   uint64_t seed;

@@ -1882,6 +1882,7 @@ hipError_t launch_step(const DevicePlan& p, void* vec, double* part_out, const d
   StepArgs a = make_step_args(p);
   a.err = p.err;
   a.vec = vec;
+  a.vec_lo = p.resid ? reinterpret_cast<int16_t*>(reinterpret_cast<float*>(vec) + p.vec_elems) : nullptr;
   a.part_out = part_out;
   a.part_in = part_in;
   a.n_jobs = n_jobs;
@@ -1900,6 +1901,7 @@ hipError_t launch_step_slots(const DevicePlan& p, void* vec, double* part_out, i
   StepArgs a = make_step_args(p);
   a.err = p.err;
   a.vec = vec;
+  a.vec_lo = p.resid ? reinterpret_cast<int16_t*>(reinterpret_cast<float*>(vec) + p.vec_elems) : nullptr;
   a.part_out = part_out;
   a.x_slot = x_slot;
   a.yin_slot = yin_slot;
@@ -1909,6 +1911,7 @@ hipError_t launch_step_slots(const DevicePlan& p, void* vec, double* part_out, i
 }
 
 hipError_t launch_step_args(const DevicePlan& p, const StepArgs& a, hipStream_t st) {
+  if (p.resid && p.block != 3) return hipErrorInvalidValue;   // residual storage: slice kernel only
   if (p.spin) return launch_spin(p, a, st);
   if (p.block == 3) return launch_slice(p, a, st);
   if (p.block == 2) return launch_tab(p, a, st);
@@ -2024,6 +2027,15 @@ __global__ __launch_bounds__(kThreads) void init_kernel(const InitArgs a) {
       if (c < U.ncols) x = start_value(a.vec_kind, a.seed, P, U.col0 + c, idx);
       if (a.mode == 0) {
         acc = fma(x, x, acc);
+      } else if (a.lo) {
+        // float32 + residual storage (T = float): the dot is of the stored value
+        float hi;
+        int16_t q;
+        res_encode(x * scale, hi, q);
+        A[rho * ld + c] = (T)hi;
+        a.lo[U.vec_off + rho * ld + c] = q;
+        const double xs = res_decode(hi, q);
+        acc = fma(xs, xs, acc);
       } else {
         const T xs = (T)(x * scale);
         A[rho * ld + c] = xs;
@@ -2053,6 +2065,7 @@ hipError_t launch_init(const DevicePlan& p, void* vec, int mode, int vec_kind, u
   a.units = p.units;
   a.tile_unit = p.tile_unit;
   a.vec = vec;
+  a.lo = p.resid ? reinterpret_cast<int16_t*>(reinterpret_cast<float*>(vec) + p.vec_elems) : nullptr;
   a.norms = norms;
   a.part_out = part_out;
   a.seed = seed;

@@ -29,6 +29,8 @@
 // bond order.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kpm_device.h"
 #include "kpm_internal.h"
 #include "kpm_vec.h"
@@ -118,8 +120,69 @@ __device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, uint32_t vof
   }
 }
 
+// Residual parts of a row chunk (float32 + residual storage): CPL int16,
+// two per word.
+template <int CPL>
+struct LoBits {
+  uint32_t w[CPL >= 2 ? CPL / 2 : 1];
+};
+template <int CPL, int AUX>
+__device__ __forceinline__ LoBits<CPL> bload_lo(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  static_assert(CPL == 2 || CPL == 4, "residual rows of 2 or 4 columns");
+  LoBits<CPL> x;
+  if constexpr (CPL == 4) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX);
+    x.w[0] = v[0];
+    x.w[1] = v[1];
+  } else {
+    x.w[0] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX);
+  }
+  return x;
+}
+template <int CPL>
+__device__ __forceinline__ void bstore_lo_nt(__amdgpu_buffer_rsrc_t r, uint32_t voff, const LoBits<CPL>& x) {
+  if constexpr (CPL == 4) {
+    __attribute__((ext_vector_type(2))) uint32_t v;
+    v[0] = x.w[0];
+    v[1] = x.w[1];
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, 0, 3);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(x.w[0], r, voff, 0, 3);
+  }
+}
+template <int CPL>
+__device__ __forceinline__ int16_t lo_at(const LoBits<CPL>& x, int e) {
+  return (int16_t)(x.w[e >> 1] >> ((e & 1) * 16));
+}
+
+// A row chunk as loaded: the stored values, and with RES their residuals.
+template <typename T, int CPL, bool RES>
+struct RowIn {
+  VecT<T, CPL> v;
+  LoBits<RES ? CPL : 2> lo;
+};
+// AUX 0: cached load (v_n); AUX 3: streaming load (v_{n-1}, no scalar offset)
+template <typename T, int CPL, bool RES, int AUX>
+__device__ __forceinline__ RowIn<T, CPL, RES> load_row(__amdgpu_buffer_rsrc_t rh, __amdgpu_buffer_rsrc_t rl,
+                                                       uint32_t voff, uint32_t soff);
+template <typename T, int CPL, bool RES>
+__device__ __forceinline__ double row_val(const RowIn<T, CPL, RES>& r, int e) {
+  if constexpr (RES) return res_decode(r.v.v[e], lo_at<CPL>(r.lo, e));
+  else return (double)r.v.v[e];
+}
+
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T, int CPL, bool RES, int AUX>
+__device__ __forceinline__ RowIn<T, CPL, RES> load_row(__amdgpu_buffer_rsrc_t rh, __amdgpu_buffer_rsrc_t rl,
+                                                       uint32_t voff, uint32_t soff) {
+  RowIn<T, CPL, RES> r;
+  if constexpr (AUX == 0) r.v = bload<T, CPL>(rh, voff, soff);
+  else r.v = bload_nt<T, CPL>(rh, voff);
+  if constexpr (RES) r.lo = bload_lo<CPL, AUX>(rl, voff >> 1, soff >> 1);
+  return r;
 }
 
 // Word-table layout (one row of WB bytes per low word, indexed by the word's
@@ -198,7 +261,8 @@ hipError_t build_slice_words(const DevicePlan& p, uint8_t* wtab, hipStream_t st)
 constexpr int kLlMax = 32;
 
 size_t slice_lds_bytes(const DevicePlan& p) {
-  return (size_t)kLlMax * 8 + (size_t)(p.blk_lds_rows + 1) * p.ld_max * (p.fp32 ? 4 : 8);
+  // float32 + residual storage: the block's rows are staged decoded (float64)
+  return (size_t)kLlMax * 8 + (size_t)(p.blk_lds_rows + 1) * p.ld_max * (p.fp32 && !p.resid ? 4 : 8);
 }
 
 template <int WB>
@@ -210,11 +274,13 @@ __device__ __forceinline__ uint32_t row_u16(const uint32_t (&w)[WB / 4], int byt
   return (w[byte >> 2] >> ((byte & 3) * 8)) & 0xFFFFu;
 }
 
-template <typename T, int CPL, int NCH, int GH, int WB>
+template <typename T, int CPL, int NCH, int GH, int WB, bool RES>
 __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
+  static_assert(!RES || (sizeof(T) == 4 && (CPL == 2 || CPL == 4)), "residual storage: float32 chunks of 2 or 4");
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x;
   using RowT = WordRow<WB>;
+  using LT = typename std::conditional<RES, double, T>::type;   // LDS copy of v_n
   constexpr int LD = NCH * CPL;          // columns per row (every unit of the plan)
   constexpr int RPS = 64 / NCH;          // members per slice
   constexpr uint32_t ROWB = LD * sizeof(T);
@@ -258,6 +324,15 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
   const __amdgpu_buffer_rsrc_t ro = make_rsrc(Y, slot_bytes);
   const __amdgpu_buffer_rsrc_t rw =
       make_rsrc(a.wtab + (size_t)U.prob * a.slice_words * WB, (uint32_t)a.slice_words * WB);
+  // residual planes: same element index, 2 bytes per element
+  __amdgpu_buffer_rsrc_t rxl = rx, ryl = ry, rol = ro;
+  if constexpr (RES) {
+    int16_t* lbase = a.vec_lo + U.vec_off;
+    const int16_t* Xl = lbase + a.x_slot * a.slot_stride;
+    rxl = make_rsrc(Xl, slot_bytes / 2);
+    ryl = make_rsrc(a.first ? Xl : lbase + a.yin_slot * a.slot_stride, slot_bytes / 2);
+    rol = make_rsrc(lbase + a.yout_slot * a.slot_stride, slot_bytes / 2);
+  }
 
   // bonds in class order (padded with zeros past the last problem)
   const cptr<uint32_t> cm = cview(a.cmask) + P.bond_off;
@@ -265,8 +340,8 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
   const cptr<double> cz = cview(a.czz) + P.bond_off;
 
   double* lco = reinterpret_cast<double*>(smem);             // low-low coefficients
-  T* xs = reinterpret_cast<T*>(lco + kLlMax);                // [1 + members][LD], row 0 = 0
-  for (int e = lane; e < LD; e += 64) xs[e] = T(0);
+  LT* xs = reinterpret_cast<LT*>(lco + kLlMax);              // [1 + members][LD], row 0 = 0
+  for (int e = lane; e < LD; e += 64) xs[e] = LT(0);
   for (int q = lane; q < kLlMax; q += 64) lco[q] = q < nll ? a.coff[P.bond_off + q] : 0.0;
 
   double acc_a[CPL], acc_b[CPL];
@@ -297,16 +372,25 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
       {
         const int ne = bsz * NCH;
         for (int e0 = 0; e0 < ne; e0 += 4 * 64) {
-          VecT<T, CPL> v[4];
+          RowIn<T, CPL, RES> v[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const uint32_t e = (uint32_t)min(e0 + u * 64 + lane, ne - 1);
-            v[u] = bload<T, CPL>(rx, (st * LD + e * CPL) * (uint32_t)sizeof(T), 0);
+            v[u] = load_row<T, CPL, RES, 0>(rx, rxl, (st * LD + e * CPL) * (uint32_t)sizeof(T), 0);
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int e = e0 + u * 64 + lane;
-            if (e < ne) *reinterpret_cast<VecT<T, CPL>*>(xs + LD + e * CPL) = v[u];
+            if (e < ne) {
+              if constexpr (RES) {
+                VecT<double, CPL> d;
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) d.v[k] = row_val(v[u], k);
+                *reinterpret_cast<VecT<double, CPL>*>(xs + LD + e * CPL) = d;
+              } else {
+                *reinterpret_cast<VecT<T, CPL>*>(xs + LD + e * CPL) = v[u].v;
+              }
+            }
           }
         }
       }
@@ -316,7 +400,7 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
       // slice's loads are issued (its data registers are then not the next
       // loads' targets, so those loads need not wait for the store).
       const int nsl = (bsz + RPS - 1) / RPS;
-      VecT<T, CPL> pend;
+      RowIn<T, CPL, RES> pend;
       uint32_t pend_off = 0u;
       bool pend_on = false;
       for (int s = 0; s < nsl; ++s) {
@@ -337,10 +421,10 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
         const uint32_t own = st + ii;
         const uint32_t voff_own = own * ROWB + cc * (uint32_t)sizeof(T);
         const uint32_t voff_m = ii * ROWB + cc * (uint32_t)sizeof(T);
-        const VecT<T, CPL> yv = bload_nt<T, CPL>(ry, voff_own);
+        const RowIn<T, CPL, RES> yv = load_row<T, CPL, RES, 3>(ry, ryl, voff_own, 0);
         // first batch of high-high rows: starts and coefficients by scalar
         // loads (entries past the block's count are read, not used)
-        VecT<T, CPL> hv[GH];
+        RowIn<T, CPL, RES> hv[GH];
         double hcf[GH];
 #pragma unroll
         for (int j = 0; j < GH; ++j) {
@@ -348,9 +432,12 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
           const double cj = hc[j];
           const uint32_t t = j < nh ? tj : st;    // past the count: own member, coefficient 0
           hcf[j] = j < nh ? cj : 0.0;
-          hv[j] = bload<T, CPL>(rx, voff_m, t * ROWB);
+          hv[j] = load_row<T, CPL, RES, 0>(rx, rxl, voff_m, t * ROWB);
         }
-        if (pend_on) bstore_nt<T, CPL>(ro, pend_off, pend);
+        if (pend_on) {
+          bstore_nt<T, CPL>(ro, pend_off, pend.v);
+          if constexpr (RES) bstore_lo_nt<CPL>(rol, pend_off >> 1, pend.lo);
+        }
 
         const uint32_t l = w[2] & 0xFFFFu;
         double dll;
@@ -372,7 +459,7 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
         }
         double acc[CPL];
         {
-          const VecT<T, CPL> xv = *reinterpret_cast<const VecT<T, CPL>*>(xs + (1 + ii) * LD + cc);
+          const VecT<LT, CPL> xv = *reinterpret_cast<const VecT<LT, CPL>*>(xs + (1 + ii) * LD + cc);
 #pragma unroll
           for (int e = 0; e < CPL; ++e) acc[e] = d * (double)xv.v[e];
         }
@@ -382,13 +469,13 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
 #pragma unroll
         for (int q0 = 0; q0 < RowT::kLl; q0 += 4) {
           if (q0 < nll) {
-            VecT<T, CPL> xv[4];
+            VecT<LT, CPL> xv[4];
             double cf[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               const uint32_t r = row_byte<WB>(w, RowT::kLlOff + q0 + u);
               cf[u] = lco[q0 + u];
-              xv[u] = *reinterpret_cast<const VecT<T, CPL>*>(xs + r * LD + cc);
+              xv[u] = *reinterpret_cast<const VecT<LT, CPL>*>(xs + r * LD + cc);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -398,7 +485,7 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
           }
         }
         // mixed rows (requested now; their latency overlaps the high-high sums)
-        VecT<T, CPL> mv[2];
+        RowIn<T, CPL, RES> mv[2];
         auto mx_issue = [&](int q0) {
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
@@ -412,7 +499,7 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
               }
               if (mact[q]) row = stq + row_u16<WB>(w, 12 + 2 * q);
             }
-            mv[u] = bload<T, CPL>(rx, row * ROWB + cc * (uint32_t)sizeof(T), 0);
+            mv[u] = load_row<T, CPL, RES, 0>(rx, rxl, row * ROWB + cc * (uint32_t)sizeof(T), 0);
           }
         };
         mx_issue(0);
@@ -420,7 +507,7 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
 #pragma unroll
         for (int j = 0; j < GH; ++j) {
 #pragma unroll
-          for (int e = 0; e < CPL; ++e) acc[e] = fma(hcf[j], (double)hv[j].v[e], acc[e]);
+          for (int e = 0; e < CPL; ++e) acc[e] = fma(hcf[j], row_val(hv[j], e), acc[e]);
         }
         for (int k0 = GH; k0 < nh; k0 += GH) {
 #pragma unroll
@@ -429,12 +516,12 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
             const double cj = hc[k0 + j];
             const uint32_t t = k0 + j < nh ? tj : st;
             hcf[j] = k0 + j < nh ? cj : 0.0;
-            hv[j] = bload<T, CPL>(rx, voff_m, t * ROWB);
+            hv[j] = load_row<T, CPL, RES, 0>(rx, rxl, voff_m, t * ROWB);
           }
 #pragma unroll
           for (int j = 0; j < GH; ++j) {
 #pragma unroll
-            for (int e = 0; e < CPL; ++e) acc[e] = fma(hcf[j], (double)hv[j].v[e], acc[e]);
+            for (int e = 0; e < CPL; ++e) acc[e] = fma(hcf[j], row_val(hv[j], e), acc[e]);
           }
         }
 #pragma unroll
@@ -447,32 +534,44 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
               const double cq = co[nll + nhh + q];
               const double cf = (q < nmx && mact[q]) ? cq : 0.0;
 #pragma unroll
-              for (int e = 0; e < CPL; ++e) acc[e] = fma(cf, (double)mv[u].v[e], acc[e]);
+              for (int e = 0; e < CPL; ++e) acc[e] = fma(cf, row_val(mv[u], e), acc[e]);
             }
           }
         }
         pend_on = on;
         pend_off = voff_own;
         if (on) {
-          VecT<T, CPL> ov;
-          if (a.first) {
-#pragma unroll
-            for (int e = 0; e < CPL; ++e) ov.v[e] = (T)acc[e];
-          } else {
-#pragma unroll
-            for (int e = 0; e < CPL; ++e) ov.v[e] = (T)(2.0 * acc[e] - (double)yv.v[e]);
-          }
-          pend = ov;
-          const VecT<T, CPL> xv = *reinterpret_cast<const VecT<T, CPL>*>(xs + (1 + ii) * LD + cc);
+          // v_{n+1} as stored; the dots are of the stored values
+          double o[CPL];
 #pragma unroll
           for (int e = 0; e < CPL; ++e) {
-            const double o = (double)ov.v[e];
-            acc_a[e] = fma(o, o, acc_a[e]);
-            acc_b[e] = fma(o, (double)xv.v[e], acc_b[e]);
+            const double val = a.first ? acc[e] : 2.0 * acc[e] - row_val(yv, e);
+            if constexpr (RES) {
+              float hi;
+              int16_t q;
+              res_encode(val, hi, q);
+              pend.v.v[e] = hi;
+              const uint32_t bits = (uint32_t)(uint16_t)q << ((e & 1) * 16);
+              if (e & 1) pend.lo.w[e >> 1] |= bits;
+              else pend.lo.w[e >> 1] = bits;
+              o[e] = res_decode(hi, q);
+            } else {
+              pend.v.v[e] = (T)val;
+              o[e] = (double)pend.v.v[e];
+            }
+          }
+          const VecT<LT, CPL> xv = *reinterpret_cast<const VecT<LT, CPL>*>(xs + (1 + ii) * LD + cc);
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) {
+            acc_a[e] = fma(o[e], o[e], acc_a[e]);
+            acc_b[e] = fma(o[e], (double)xv.v[e], acc_b[e]);
           }
         }
       }
-      if (pend_on) bstore_nt<T, CPL>(ro, pend_off, pend);
+      if (pend_on) {
+        bstore_nt<T, CPL>(ro, pend_off, pend.v);
+        if constexpr (RES) bstore_lo_nt<CPL>(rol, pend_off >> 1, pend.lo);
+      }
       wave_sync();
     }
   }
@@ -494,17 +593,17 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
   }
 }
 
-template <typename T, int CPL, int NCH, int WB>
+template <typename T, int CPL, int NCH, int WB, bool RES>
 static hipError_t launch_slice_w(const StepArgs& a, size_t lds, int grid, int gh, hipStream_t st) {
-  if (gh == 4) hipLaunchKernelGGL((slice_kernel<T, CPL, NCH, 4, WB>), dim3(grid), dim3(64), lds, st, a);
-  else hipLaunchKernelGGL((slice_kernel<T, CPL, NCH, 8, WB>), dim3(grid), dim3(64), lds, st, a);
+  if (gh == 4) hipLaunchKernelGGL((slice_kernel<T, CPL, NCH, 4, WB, RES>), dim3(grid), dim3(64), lds, st, a);
+  else hipLaunchKernelGGL((slice_kernel<T, CPL, NCH, 8, WB, RES>), dim3(grid), dim3(64), lds, st, a);
   return hipGetLastError();
 }
 
-template <typename T, int CPL, int NCH>
+template <typename T, int CPL, int NCH, bool RES = false>
 static hipError_t launch_slice_t(const StepArgs& a, size_t lds, int grid, int gh, int wb, hipStream_t st) {
-  if (wb == 32) return launch_slice_w<T, CPL, NCH, 32>(a, lds, grid, gh, st);
-  return launch_slice_w<T, CPL, NCH, 64>(a, lds, grid, gh, st);
+  if (wb == 32) return launch_slice_w<T, CPL, NCH, 32, RES>(a, lds, grid, gh, st);
+  return launch_slice_w<T, CPL, NCH, 64, RES>(a, lds, grid, gh, st);
 }
 
 // Every unit of a slice plan has ld = cpl * nch with nch 1 or 2.
@@ -515,6 +614,13 @@ hipError_t launch_slice(const DevicePlan& p, const StepArgs& a, hipStream_t st) 
   const int wb = p.slice_wb;
   const int nch = p.ld_max / p.cpl;
   if (p.ld_max != nch * p.cpl || (nch != 1 && nch != 2)) return hipErrorInvalidValue;
+  if (p.resid) {
+    if (!p.fp32 || !a.vec_lo) return hipErrorInvalidValue;
+    if (p.cpl == 4) return nch == 1 ? launch_slice_t<float, 4, 1, true>(a, lds, grid, gh, wb, st)
+                                    : launch_slice_t<float, 4, 2, true>(a, lds, grid, gh, wb, st);
+    if (p.cpl == 2 && nch == 1) return launch_slice_t<float, 2, 1, true>(a, lds, grid, gh, wb, st);
+    return hipErrorInvalidValue;
+  }
   if (p.fp32) {
     if (p.cpl == 4) return nch == 1 ? launch_slice_t<float, 4, 1>(a, lds, grid, gh, wb, st)
                                     : launch_slice_t<float, 4, 2>(a, lds, grid, gh, wb, st);

@@ -95,6 +95,26 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
+// Float32 storage with a 16-bit residual: x is kept as hi = float32(x)
+// (round to nearest) and q = rint((x - hi) 2^(165 - e)), e = max(1, biased
+// exponent of hi), so that hi + q 2^(e - 165) (exact in float64) is x to
+// within 2^(e - 166), half a unit of hi's last place times 2^-15.
+__device__ __forceinline__ double res_unit(float hi) {
+  const uint32_t e = max((__float_as_uint(hi) >> 23) & 0xFFu, 1u);
+  return __longlong_as_double((long long)(e + 858u) << 52);     // 2^(e - 165)
+}
+__device__ __forceinline__ double res_inv_unit(float hi) {
+  const uint32_t e = max((__float_as_uint(hi) >> 23) & 0xFFu, 1u);
+  return __longlong_as_double((long long)(1188u - e) << 52);    // 2^(165 - e)
+}
+__device__ __forceinline__ void res_encode(double x, float& hi, int16_t& q) {
+  hi = (float)x;
+  q = (int16_t)rint((x - (double)hi) * res_inv_unit(hi));
+}
+__device__ __forceinline__ double res_decode(float hi, int16_t q) {
+  return fma((double)q, res_unit(hi), (double)hi);
+}
+
 // p[first] + p[first + stride] + ... (indices < n) in a fixed association:
 // eight running sums, so that eight loads are in flight per lane, added in
 // index order at the end.

@@ -22,7 +22,7 @@ KPM_OK, KPM_EINVAL, KPM_ENOMEM, KPM_EDEVICE, KPM_EBOUNDS, KPM_EWORKSPACE = 0, -1
 KPM_ETOOLARGE = -6
 NOALLOC_MAX_BYTES = 64 << 20  # KPM_NOALLOC_MAX_BYTES of include/kpm.h
 VEC_KINDS = {"rademacher": 0, "complex_gaussian": 1, "gaussian": 2, "basis": 3}
-PRECISIONS = {"fp64": 0, "fp32": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32r": 2}   # fp32r: float32 + 16-bit residual storage
 KERNELS = {"none": 0, "jackson": 1}
 
 
