@@ -259,7 +259,7 @@ struct Planned {
   std::vector<uint16_t> lunr;
   std::vector<uint32_t> cmask;        // bonds in class order (slice kernel)
   std::vector<double> coff, czz;
-  std::vector<int32_t> wg_tile;       // slice kernel: workgroup -> tile (-1 none)
+  std::vector<SliceWg> wg_rec;        // slice kernel: workgroup records
   DevicePlan plan;
   double bytes_per_step = 0;     // algorithmic (3 * storage * dim * real columns)
   double state_cols = 0;         // sum of dim * real columns
@@ -891,11 +891,11 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   if (D.block >= 2) {
     for (const auto& u : P.units) {
       const ProbDev& d = P.probs[u.prob];
-      P.bytes_per_step += (double)d.n_blk * (12.0 + 6.0 * d.n_hh + 4.0 * d.n_mx);
-      // slice kernel: per block the coefficients and the diagonal part, per
-      // unit the word table
-      if (D.block == 3)
-        P.bytes_per_step += (double)d.n_blk * (8.0 + 8.0 * d.n_hh) + (double)(1u << d.blk_L) * D.slice_wb;
+      if (D.block == 3)   // slice kernel: per block its record, targets, coefficients; per unit the word table
+        P.bytes_per_step += (double)d.n_blk * (sizeof(SliceBlk) + 12.0 * d.n_hh + 4.0 * d.n_mx) +
+                            (double)(1u << d.blk_L) * D.slice_wb;
+      else
+        P.bytes_per_step += (double)d.n_blk * (12.0 + 6.0 * d.n_hh + 4.0 * d.n_mx);
     }
     D.n_states = (int64_t)((tab_meta_bytes(D) + 3) / 4);
   } else if (D.row_ld || D.block) {
@@ -929,22 +929,41 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   D.n_units = (int32_t)P.units.size();
   D.n_tiles = tiles;
   D.grid_tiles = (tiles + 7) / 8 * 8;
-  // Slice kernel, KPM_XCD_REMAP=2: each unit's tiles in 8 contiguous chunks,
-  // chunk x to XCD x (workgroup b runs on XCD b mod 8), units one after the
-  // other, so that all XCDs sweep the same column block at the same time.
-  P.wg_tile.clear();
+  // Slice kernel: one record per workgroup (its tile, column block, problem
+  // and block range).  KPM_XCD_REMAP=2 (default): each column block's tiles
+  // in 8 contiguous chunks, chunk x to XCD x (workgroup b runs on XCD b mod
+  // 8), column blocks one after the other, so that all XCDs sweep the same
+  // column block at a time; 1: contiguous tile ranges per XCD; 0: in order.
+  P.wg_rec.clear();
   D.slice_grid = 0;
-  if (D.block == 3 && D.xcd_remap == 2) {
-    for (const UnitDev& u : P.units) {
-      const int c = (u.ntiles + 7) / 8;
-      for (int j = 0; j < c; ++j)
-        for (int x = 0; x < 8; ++x) {
-          const int t = x * c + j;
-          P.wg_tile.push_back(t < u.ntiles ? u.tile0 + t : -1);
-        }
+  if (D.block == 3) {
+    auto rec = [&](int t) {
+      SliceWg w{};
+      w.tile = -1;
+      if (t >= 0 && t < tiles) {
+        const UnitDev& u = P.units[P.tile_unit[t]];
+        const int s0 = P.tile_sub0[t], s1 = P.tile_sub0[t + 1];
+        w.tile = t;
+        w.unit = P.tile_unit[t];
+        w.prob = u.prob;
+        w.g0 = P.sub_blk0[s0];
+        w.ng = P.sub_blk0[s1 - 1] + P.sub_nblk[s1 - 1] - w.g0;
+      }
+      return w;
+    };
+    if (D.xcd_remap == 2) {
+      for (const UnitDev& u : P.units) {
+        const int c = (u.ntiles + 7) / 8;
+        for (int j = 0; j < c; ++j)
+          for (int x = 0; x < 8; ++x) P.wg_rec.push_back(rec(x * c + j < u.ntiles ? u.tile0 + x * c + j : -1));
+      }
+    } else {
+      const int per = D.grid_tiles / 8;
+      for (int b = 0; b < D.grid_tiles; ++b)
+        P.wg_rec.push_back(rec(D.xcd_remap ? (b & 7) * per + (b >> 3) : b));
     }
-    if (P.wg_tile.empty() || P.wg_tile.size() > (size_t)INT32_MAX) return KPM_EINVAL;
-    D.slice_grid = (int32_t)P.wg_tile.size();
+    if (P.wg_rec.empty() || P.wg_rec.size() > (size_t)INT32_MAX) return KPM_EINVAL;
+    D.slice_grid = (int32_t)P.wg_rec.size();
   }
   D.total_cols = col_off;
   D.part_len = std::max<int64_t>(part_len, 1);
@@ -983,7 +1002,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   P.o_cmask = put(P.cmask.size() * 4);
   P.o_coff = put(P.coff.size() * 8);
   P.o_czz = put(P.czz.size() * 8);
-  P.o_wgt = put(P.wg_tile.size() * 4);
+  P.o_wgt = put(P.wg_rec.size() * sizeof(SliceWg));
   P.bytes = o;
   return KPM_OK;
 }
@@ -1020,7 +1039,7 @@ int upload_plan(Planned& P, unsigned char* dst, std::vector<unsigned char>& stag
   cp(P.o_cmask, P.cmask.data(), P.cmask.size() * 4);
   cp(P.o_coff, P.coff.data(), P.coff.size() * 8);
   cp(P.o_czz, P.czz.data(), P.czz.size() * 8);
-  cp(P.o_wgt, P.wg_tile.data(), P.wg_tile.size() * 4);
+  cp(P.o_wgt, P.wg_rec.data(), P.wg_rec.size() * sizeof(SliceWg));
   KPM_HIP(hipMemcpyAsync(dst, staging.data(), P.bytes, hipMemcpyHostToDevice, st));
   DevicePlan& D = P.plan;
   D.probs = reinterpret_cast<ProbDev*>(dst + P.o_probs);
@@ -1048,7 +1067,7 @@ int upload_plan(Planned& P, unsigned char* dst, std::vector<unsigned char>& stag
   D.cmask = reinterpret_cast<uint32_t*>(dst + P.o_cmask);
   D.coff = reinterpret_cast<double*>(dst + P.o_coff);
   D.czz = reinterpret_cast<double*>(dst + P.o_czz);
-  D.wg_tile = P.wg_tile.empty() ? nullptr : reinterpret_cast<int32_t*>(dst + P.o_wgt);
+  D.wg_rec = P.wg_rec.empty() ? nullptr : reinterpret_cast<SliceWg*>(dst + P.o_wgt);
   return KPM_OK;
 }
 

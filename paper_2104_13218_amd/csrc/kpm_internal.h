@@ -57,6 +57,24 @@ struct UnitDev {
 };
 
 // Arguments of the fused recursion step (one launch per step).
+// Slice kernel: what a workgroup needs first, one scalar load each.
+struct SliceWg {
+  int32_t tile;      // plan tile (< 0: the workgroup has no tile)
+  int32_t unit;      // its column block
+  int32_t prob;      // the block's problem
+  int32_t g0, ng;    // its low-bit blocks [g0, g0 + ng) (global block index)
+  int32_t pad[3];
+};
+struct SliceBlk {    // written once per call with the per-block tables
+  uint32_t h;        // high word
+  uint32_t start;    // rank of the first member
+  uint32_t size;     // members C(L, k), k = n_up - popcount(h) (0 if k is out of range)
+  uint32_t kofs;     // position of popcount class k in the low-word tables
+  uint32_t nh;       // acting high-high bonds
+  uint32_t pad;
+  double dhh;        // -b/a + high-high part of the diagonal
+};
+
 struct StepArgs {
   const ProbDev* probs;
   const UnitDev* units;
@@ -130,8 +148,8 @@ struct StepArgs {
   int32_t slice_wb;            // bytes per word-table row (32 or 64)
   int32_t slice_words;         // rows per problem (1 << largest blk_L)
   int32_t blk_lds_rows;        // largest block (members), LDS rows of the slice kernel
-  const int32_t* wg_tile;      // slice kernel: tile of each workgroup (-1: none); NULL =
-                               // the xcd_remap mapping over grid_tiles workgroups
+  const SliceWg* wg_rec;       // slice kernel: per workgroup, its tile (tile < 0: idle)
+  const SliceBlk* blk_rec;     // slice kernel: per block (global index), its record
   int16_t* vec_lo;             // float32 + residual storage: the residual q of every
                                // element, same element index as the float32 part
                                // (NULL for plain float32 / float64 storage)
@@ -192,7 +210,7 @@ struct DevicePlan {
   int32_t slice_wb = 0;        // slice kernel: word-table row bytes (0 = no slice plan)
   int32_t slice_words = 0;     // slice kernel: word-table rows per problem
   int32_t blk_lds_rows = 0;    // slice kernel: members of the largest block
-  int32_t* wg_tile = nullptr;  // slice kernel: tile of each of slice_grid workgroups
+  SliceWg* wg_rec = nullptr;   // slice kernel: record of each of slice_grid workgroups
   int32_t slice_grid = 0;      // slice kernel: workgroups launched (0 = grid_tiles)
   int32_t blk_max = 16, blk_rows = kThreads, lds_lr = 1, lds_hh = 1, lds_mx = 1, ld_max = 1;
   int64_t n_states = 0;        // entries of the state table

@@ -1286,7 +1286,7 @@ size_t tab_lds_bytes(const DevicePlan& p) {
 }
 
 struct TabMeta {
-  size_t hcnt, hstart, mstart, hq, hcoef, dhh, wtab, total;
+  size_t hcnt, hstart, mstart, hq, hcoef, dhh, wtab, brec, total;
 };
 
 // wtab_bytes > 0 (slice kernel): also per-block coefficients and diagonal
@@ -1308,6 +1308,7 @@ __host__ __device__ inline TabMeta tab_meta_layout(int64_t n_blk, int hh, int mx
     m.hcoef = put((size_t(n_blk) * hh + 16) * 8);
     m.dhh = put(size_t(n_blk) * 8);
     m.wtab = put(wtab_bytes);
+    m.brec = put(size_t(n_blk) * sizeof(SliceBlk));
   }
   m.total = o;
   return m;
@@ -1346,7 +1347,9 @@ __global__ __launch_bounds__(kThreads) void tab_meta_kernel(const ProbDev* probs
                                                             uint32_t* hstart, uint32_t* mstart,
                                                             uint16_t* hq, const double* boff,
                                                             const double* bzz, double* hcoef,
-                                                            double* dhh, int* err) {
+                                                            double* dhh, const uint32_t* blk_start,
+                                                            const int32_t* koff, SliceBlk* brec,
+                                                            int* err) {
   __shared__ uint32_t sb[kBinomN * kBinomN];
   for (int i = threadIdx.x; i < kBinomN * kBinomN; i += kThreads) sb[i] = binom[i];
   __syncthreads();
@@ -1383,6 +1386,16 @@ __global__ __launch_bounds__(kThreads) void tab_meta_kernel(const ProbDev* probs
         d += (x == 0u || x == mh) ? bzz[b] : -bzz[b];
       }
       dhh[g] = d;
+      if (brec) {
+        SliceBlk r{};
+        r.h = h;
+        r.start = blk_start[g];
+        r.size = (k >= 0 && k <= L) ? sb[L * kBinomN + k] : 0u;
+        r.kofs = (k >= 0 && k <= L) ? (uint32_t)koff[k] : 0u;
+        r.nh = (uint32_t)n;
+        r.dhh = d;
+        brec[g] = r;
+      }
     }
     for (int q = 0; q < P.n_mx; ++q) {
       const uint32_t mh = bmask[P.bond_off + bperm[q_mx + q]] >> L;   // one high bit
@@ -1413,7 +1426,8 @@ hipError_t build_tab_meta(const DevicePlan& p, hipStream_t st) {
                      reinterpret_cast<uint32_t*>(base + m.mstart),
                      reinterpret_cast<uint16_t*>(base + m.hq), p.boff, p.bzz,
                      slice ? reinterpret_cast<double*>(base + m.hcoef) : nullptr,
-                     slice ? reinterpret_cast<double*>(base + m.dhh) : nullptr, p.err);
+                     slice ? reinterpret_cast<double*>(base + m.dhh) : nullptr, p.blk_start, p.koff,
+                     slice ? reinterpret_cast<SliceBlk*>(base + m.brec) : nullptr, p.err);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && slice) e = build_slice_words(p, reinterpret_cast<uint8_t*>(base + m.wtab), st);
   return e;
@@ -1861,7 +1875,8 @@ static StepArgs make_step_args(const DevicePlan& p) {
       a.slice_wb = p.slice_wb;
       a.slice_words = p.slice_words;
       a.blk_lds_rows = p.blk_lds_rows;
-      a.wg_tile = p.wg_tile;
+      a.wg_rec = p.wg_rec;
+      a.blk_rec = reinterpret_cast<const SliceBlk*>(mb + m.brec);
     }
   }
   return a;

@@ -302,11 +302,14 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
     }
   }
 
-  const int tile = a.wg_tile ? cview(a.wg_tile)[blockIdx.x]
-                             : (a.xcd_remap ? xcd_tile(blockIdx.x, a.grid_tiles) : (int)blockIdx.x);
+  // the workgroup's record names its tile, column block, problem and blocks,
+  // so that the unit, problem and first block record load side by side
+  const SliceWg R = sload(a.wg_rec + blockIdx.x);
+  const int tile = R.tile;
   if (tile < 0 || tile >= a.n_tiles) return;
-  const UnitDev U = sload(a.units + cview(a.tile_unit)[tile]);
-  const ProbDev P = sload(a.probs + U.prob);
+  const UnitDev U = sload(a.units + R.unit);
+  const ProbDev P = sload(a.probs + R.prob);
+  SliceBlk Bn = sload(a.blk_rec + R.g0);
   const int rl = lane / NCH;
   const int c = lane - rl * NCH;
   const uint32_t cc = (uint32_t)(c * CPL);
@@ -348,22 +351,22 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
 #pragma unroll
   for (int e = 0; e < CPL; ++e) acc_a[e] = acc_b[e] = 0.0;
 
-  const int sub1 = cview(a.tile_sub0)[tile + 1];
-  for (int sub = cview(a.tile_sub0)[tile]; sub < sub1; ++sub) {
-    const int g0 = cview(a.sub_blk0)[sub];
-    const int nblk = cview(a.sub_nblk)[sub];
-    for (int g = g0; g < g0 + nblk; ++g) {
-      const uint32_t h = cview(a.blk_h)[g];
-      const uint32_t st = cview(a.blk_start)[g];
-      const int k = P.n_up - __popc(h);
-      const int bsz = (k >= 0 && k <= Lb) ? (int)cview(a.binom)[Lb * kBinomN + k] : 0;
+  {
+    const int gend = R.g0 + R.ng;
+    for (int g = R.g0; g < gend; ++g) {
+      // this block's record; the next one is requested now and used next
+      const SliceBlk B = Bn;
+      if (g + 1 < gend) Bn = sload(a.blk_rec + g + 1);
+      const uint32_t h = B.h;
+      const uint32_t st = B.start;
+      const int bsz = (int)B.size;
       if (bsz == 0 || bsz > a.blk_lds_rows) {
         if (lane == 0 && a.err) atomicOr(a.err, 4);
         continue;
       }
-      const int nh = min((int)cview(a.meta_hcnt)[g], nhh);
-      const double dhh = cview(a.meta_dhh)[g];
-      const uint32_t kofs = (uint32_t)cview(a.koff)[k];
+      const int nh = min((int)B.nh, nhh);
+      const double dhh = B.dhh;
+      const uint32_t kofs = B.kofs;
       const cptr<uint32_t> hs = cview(a.meta_hstart) + (int64_t)g * a.meta_hh;
       const cptr<double> hc = cview(a.meta_hcoef) + (int64_t)g * a.meta_hh;
       const cptr<uint32_t> ms = cview(a.meta_mstart) + (int64_t)g * a.meta_mx;
