@@ -406,21 +406,30 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
       RowIn<T, CPL, RES> pend;
       uint32_t pend_off = 0u;
       bool pend_on = false;
+      // word-table rows one slice ahead: slice s's row was requested during
+      // slice s - 1, so its mixed-bond targets are known when s starts
+      auto wload = [&](int sl, uint32_t (&wr)[WB / 4]) {
+        const int i = sl * RPS + rl;
+        const uint32_t ii = i < bsz ? (uint32_t)i : 0u;
+#pragma unroll
+        for (int t = 0; t < WB / 16; ++t) {
+          const auto q = __builtin_amdgcn_raw_buffer_load_b128(rw, (kofs + ii) * WB + 16 * t, 0, 0);
+          wr[4 * t] = q[0];
+          wr[4 * t + 1] = q[1];
+          wr[4 * t + 2] = q[2];
+          wr[4 * t + 3] = q[3];
+        }
+      };
+      uint32_t wn[WB / 4];
+      wload(0, wn);
       for (int s = 0; s < nsl; ++s) {
         const int i = s * RPS + rl;
         const bool on = i < bsz;
         const uint32_t ii = on ? (uint32_t)i : 0u;
-        // word-table row first: the loads after it may still be in flight
-        // when it is consumed
         uint32_t w[WB / 4];
 #pragma unroll
-        for (int t = 0; t < WB / 16; ++t) {
-          const auto q = __builtin_amdgcn_raw_buffer_load_b128(rw, (kofs + ii) * WB + 16 * t, 0, 0);
-          w[4 * t] = q[0];
-          w[4 * t + 1] = q[1];
-          w[4 * t + 2] = q[2];
-          w[4 * t + 3] = q[3];
-        }
+        for (int t = 0; t < WB / 4; ++t) w[t] = wn[t];
+        if (s + 1 < nsl) wload(s + 1, wn);
         const uint32_t own = st + ii;
         const uint32_t voff_own = own * ROWB + cc * (uint32_t)sizeof(T);
         const uint32_t voff_m = ii * ROWB + cc * (uint32_t)sizeof(T);
