@@ -261,6 +261,11 @@ hipError_t build_slice_words(const DevicePlan& p, uint8_t* wtab, hipStream_t st)
 constexpr int kLlMax = 32;
 
 size_t slice_lds_bytes(const DevicePlan& p) {
+  const size_t rowb = (size_t)p.ld_max * (p.fp32 ? 4 : 8);
+  // rows of a multiple of 16 bytes: two buffers for direct staging, each the
+  // zero row plus the largest block rounded up to whole 1 KB loads
+  if (!p.resid && rowb % 16 == 0)
+    return (size_t)kLlMax * 8 + 2 * (rowb + ((size_t)p.blk_lds_rows * rowb + 1023) / 1024 * 1024);
   // float32 + residual storage: the block's rows are staged decoded (float64)
   return (size_t)kLlMax * 8 + (size_t)(p.blk_lds_rows + 1) * p.ld_max * (p.fp32 && !p.resid ? 4 : 8);
 }
@@ -342,10 +347,33 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
   const cptr<double> co = cview(a.coff) + P.bond_off;
   const cptr<double> cz = cview(a.czz) + P.bond_off;
 
-  double* lco = reinterpret_cast<double*>(smem);             // low-low coefficients
-  LT* xs = reinterpret_cast<LT*>(lco + kLlMax);              // [1 + members][LD], row 0 = 0
-  for (int e = lane; e < LD; e += 64) xs[e] = LT(0);
+  // LDS: low-low coefficients, then the staged rows of v_n ([1 + members][LD],
+  // row 0 = 0).  Rows of a multiple of 16 bytes are staged by direct
+  // buffer-to-LDS loads into two buffers, the next block's while the current
+  // one is computed; other rows go through registers into one buffer.
+  constexpr bool DIRECT = !RES && (ROWB % 16u == 0u);
+  double* lco = reinterpret_cast<double*>(smem);
+  LT* xs0 = reinterpret_cast<LT*>(lco + kLlMax);
+  const int buf_elems = DIRECT ? (int)(LD + (((uint32_t)a.blk_lds_rows * ROWB + 1023u) / 1024u) * 1024u / sizeof(T))
+                               : 0;
+  LT* xs1 = xs0 + buf_elems;
+  for (int e = lane; e < LD; e += 64) {
+    xs0[e] = LT(0);
+    if constexpr (DIRECT) xs1[e] = LT(0);
+  }
   for (int q = lane; q < kLlMax; q += 64) lco[q] = q < nll ? a.coff[P.bond_off + q] : 0.0;
+  auto valid = [&](const SliceBlk& b) { return b.size != 0u && (int)b.size <= a.blk_lds_rows; };
+  // a block's rows, contiguous in v_n, to LDS rows 1.. of buf: 1 KB per
+  // instruction (lane i writes bytes 16i..16i+15 of the instruction's 1 KB);
+  // lanes past the block's end re-read its last 16 bytes into the buffer's
+  // rounded-up capacity, so every read stays inside the block
+  auto stage_direct = [&](const SliceBlk& b, LT* buf) {
+    const uint32_t bytes = b.size * ROWB, soff = b.start * ROWB;
+    for (uint32_t o = 0; o < bytes; o += 1024u)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          rx, (__attribute__((address_space(3))) void*)(reinterpret_cast<unsigned char*>(buf + LD) + o), 16,
+          min(o + (uint32_t)lane * 16u, bytes - 16u), soff, 0, 0);
+  };
 
   double acc_a[CPL], acc_b[CPL];
 #pragma unroll
@@ -353,15 +381,31 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
 
   {
     const int gend = R.g0 + R.ng;
+    // records: the current block's and the next one's are at hand, the one
+    // after is requested while the current block runs
+    SliceBlk Bx = R.ng > 1 ? sload(a.blk_rec + R.g0 + 1) : Bn;
+    if constexpr (DIRECT)
+      if (valid(Bn)) stage_direct(Bn, xs0);
+    uint32_t wn[WB / 4];
+    bool wpre = false;   // wn holds slice 0's word row of the current block
     for (int g = R.g0; g < gend; ++g) {
-      // this block's record; the next one is requested now and used next
       const SliceBlk B = Bn;
-      if (g + 1 < gend) Bn = sload(a.blk_rec + g + 1);
+      Bn = Bx;
+      if (g + 2 < gend) Bx = sload(a.blk_rec + g + 2);
+      LT* xs = DIRECT && ((g - R.g0) & 1) ? xs1 : xs0;
+      if constexpr (DIRECT) {
+        // this block's rows (and every earlier memory operation) complete,
+        // the other buffer's last readers done: stage the next block there
+        __builtin_amdgcn_s_waitcnt(0);
+        wave_sync();
+        if (g + 1 < gend && valid(Bn)) stage_direct(Bn, ((g + 1 - R.g0) & 1) ? xs1 : xs0);
+      }
       const uint32_t h = B.h;
       const uint32_t st = B.start;
       const int bsz = (int)B.size;
-      if (bsz == 0 || bsz > a.blk_lds_rows) {
+      if (!valid(B)) {
         if (lane == 0 && a.err) atomicOr(a.err, 4);
+        wpre = false;
         continue;
       }
       const int nh = min((int)B.nh, nhh);
@@ -371,8 +415,8 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
       const cptr<double> hc = cview(a.meta_hcoef) + (int64_t)g * a.meta_hh;
       const cptr<uint32_t> ms = cview(a.meta_mstart) + (int64_t)g * a.meta_mx;
 
-      // 1. the block's rows of v_n into LDS rows 1..bsz
-      {
+      // 1. the block's rows of v_n into LDS rows 1..bsz (direct staging: done)
+      if constexpr (!DIRECT) {
         const int ne = bsz * NCH;
         for (int e0 = 0; e0 < ne; e0 += 4 * 64) {
           RowIn<T, CPL, RES> v[4];
@@ -396,8 +440,8 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
             }
           }
         }
+        wave_sync();
       }
-      wave_sync();
 
       // 2. slices of the block.  A slice's v_{n+1} is stored after the next
       // slice's loads are issued (its data registers are then not the next
@@ -408,20 +452,20 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
       bool pend_on = false;
       // word-table rows one slice ahead: slice s's row was requested during
       // slice s - 1, so its mixed-bond targets are known when s starts
-      auto wload = [&](int sl, uint32_t (&wr)[WB / 4]) {
+      // (and the next block's first one during this block's last slice)
+      auto wload = [&](uint32_t kof, int nmem, int sl, uint32_t (&wr)[WB / 4]) {
         const int i = sl * RPS + rl;
-        const uint32_t ii = i < bsz ? (uint32_t)i : 0u;
+        const uint32_t ii = i < nmem ? (uint32_t)i : 0u;
 #pragma unroll
         for (int t = 0; t < WB / 16; ++t) {
-          const auto q = __builtin_amdgcn_raw_buffer_load_b128(rw, (kofs + ii) * WB + 16 * t, 0, 0);
+          const auto q = __builtin_amdgcn_raw_buffer_load_b128(rw, (kof + ii) * WB + 16 * t, 0, 0);
           wr[4 * t] = q[0];
           wr[4 * t + 1] = q[1];
           wr[4 * t + 2] = q[2];
           wr[4 * t + 3] = q[3];
         }
       };
-      uint32_t wn[WB / 4];
-      wload(0, wn);
+      if (!wpre) wload(kofs, bsz, 0, wn);
       for (int s = 0; s < nsl; ++s) {
         const int i = s * RPS + rl;
         const bool on = i < bsz;
@@ -429,7 +473,12 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
         uint32_t w[WB / 4];
 #pragma unroll
         for (int t = 0; t < WB / 4; ++t) w[t] = wn[t];
-        if (s + 1 < nsl) wload(s + 1, wn);
+        if (s + 1 < nsl) {
+          wload(kofs, bsz, s + 1, wn);
+        } else {
+          wpre = g + 1 < gend && valid(Bn);
+          if (wpre) wload(Bn.kofs, (int)Bn.size, 0, wn);
+        }
         const uint32_t own = st + ii;
         const uint32_t voff_own = own * ROWB + cc * (uint32_t)sizeof(T);
         const uint32_t voff_m = ii * ROWB + cc * (uint32_t)sizeof(T);
