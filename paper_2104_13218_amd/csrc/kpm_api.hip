@@ -2116,10 +2116,22 @@ struct FtlmLayout {
 // Every real column runs its own Lanczos recursion; columns are batched in
 // blocks like the Chebyshev recursion (q->col_block, 0 = the planner's width;
 // width 1 splits a complex vector's Re and Im into separate blocks).
-RunShape ftlm_shape(const kpm_params& q) {
+// FTLM runs float64 vectors.  Without a requested block width, spin-1/2
+// problems take the slice kernel on blocks of 2 columns, 2 sub-tiles per
+// workgroup, 4 high-high rows in flight (ring N=24, 20 columns, 200 steps:
+// 208 ms per call against 301 ms with the planner's block-table default);
+// the planner falls back where no slice plan exists.
+RunShape ftlm_shape(const kpm_params& q, const kpm_problem* p, int n) {
   RunShape s = shape_of(q);
   s.precision = KPM_FP64;
   s.split_vectors = q.col_block == 1;
+  if (q.col_block == 0 && !any_spin(p, n)) {
+    s.col_block = 2;
+    s.tune.kernel = 5;
+    s.tune.block_L = 10;
+    s.tune.spt = 2;
+    s.tune.gather_batch = 4;
+  }
   return s;
 }
 
@@ -2762,7 +2774,7 @@ size_t kpm_ftlm_workspace_size(const kpm_problem* p, int32_t n, const kpm_params
   if (q->precision != KPM_FP64) return 0;
   Planned P;
   const std::vector<double> two(n, 2.0), zero(n, 0.0);
-  if (make_plan(p, n, ftlm_shape(*q), two.data(), zero.data(), P) != KPM_OK) return 0;
+  if (make_plan(p, n, ftlm_shape(*q, p, n), two.data(), zero.data(), P) != KPM_OK) return 0;
   return ftlm_layout(P, ftlm_steps(P, q->M)).total;
 }
 
@@ -2779,7 +2791,7 @@ int kpm_ftlm(const kpm_problem* p, int32_t n, const kpm_params* q, const double*
   Planned P;
   // H' = H / 2 (a = 2, b = 0), so that the recursion step's 2 H' x - y is H q_j - beta_j q_{j-1}
   const std::vector<double> two(n, 2.0), zero_b(n, 0.0);
-  r = make_plan(p, n, ftlm_shape(*q), two.data(), zero_b.data(), P);
+  r = make_plan(p, n, ftlm_shape(*q, p, n), two.data(), zero_b.data(), P);
   if (r != KPM_OK) return r;
   const int steps = ftlm_steps(P, q->M);
   const FtlmLayout L = ftlm_layout(P, steps);
