@@ -361,15 +361,26 @@ def other_workload(args, kpm, W, np, torch, dev):
                                    kernel=wl.kernel, ckpt_every=64, bounds=bl)
 
         dt, _ = _timed(args, torch, run)
-        dtf, _ = _timed(args, torch, lambda: kpm.chebyshev_moments(wl.problems, wl.M, wl.R, wl.vec_kind, "fp64",
-                                                                    wl.eps, wl.seed, bounds=bl))
+
+        def forward():
+            kpm.chebyshev_moments(wl.problems, wl.M, wl.R, wl.vec_kind, "fp64", wl.eps, wl.seed, bounds=bl)
+            return kpm.last_run_stats()
+
+        dtf, stf = _timed(args, torch, forward)
         dim = wl.problems[0].dim
         work = dim * wl.R * (wl.M // 2)
         cfg = {"dim": dim, "bonds": wl.problems[0].cluster.n_bonds, "M": wl.M, "vectors": f"{wl.R} rademacher",
                "storage": "f64", "checkpoint_every": 64, "loss": "sum_T C(T), 64 T in [0.05, 5]",
                "device": dev}
-        return _line(args, name, work / dt, "forward-equivalent state-column-steps/s", dt, cfg, None,
-                     {"forward_ms": dtf * 1e3, "gradient_over_forward_time": dt / dtf})
+        # the reverse step reads w_{n+1} (gathers), w_{n+2}, v_{n-1}, v_n, v_{n+1}
+        # and writes w_n: 6 x 8 bytes per state and column; its launch time is
+        # in the committed kernel trace (profiles/j1j2_grad_kernels.md)
+        adj = {"kernel": "adjoint_kernel", "launches_per_gradient": wl.M // 2,
+               "algorithmic_bytes_per_launch": 6.0 * 8 * wl.R * dim,
+               "traffic": _traffic("adjoint_kernel", "j1j2_n20_sz0_fp64")}
+        return _line(args, name, work / dt, "forward-equivalent state-column-steps/s", dt, cfg,
+                     _roofline(stf, "j1j2_n20_sz0_fp64"),
+                     {"forward_ms": dtf * 1e3, "gradient_over_forward_time": dt / dtf, "adjoint": adj})
     if name == "ftlm_ring24":
         sec = W.sectors(W.ring(24), only_sz0=True)
         T = W.log_temperatures(200, 0.01, 10.0)
