@@ -320,9 +320,10 @@ def other_workload(args, kpm, W, np, torch, dev):
         cfg = {"sites": 10, "spin": "5/2", "problems": len(dims), "states": int(sum(dims)),
                "max_dim": int(max(dims)), "M": wl.M, "vectors": f"{wl.R} {wl.vec_kind}", "storage": "f32",
                "col_block": st["col_block"], "bounds": "lanczos50+1% (outside the timing)", "device": dev}
-        extra = {"fp64": {"value": st64["state_col_steps"] / dt64, "ms": dt64 * 1e3, "roofline": _roofline(st64)}}
+        extra = {"fp64": {"value": st64["state_col_steps"] / dt64, "ms": dt64 * 1e3,
+                          "roofline": _roofline(st64, "fe10_fp64")}}
         return _line(args, name, st["state_col_steps"] / dt, "state-column-steps/s", dt, cfg,
-                     _roofline(st), extra)
+                     _roofline(st, "fe10_fp32"), extra)
     if name == "ed_batched":
         # exact spectra of the small sectors of the 64 random clusters (the
         # hybrid form: sectors of dimension <= 1024 diagonalised completely)
