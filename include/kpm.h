@@ -416,7 +416,8 @@ typedef struct {
                               bonds between the low and the high bits; results are
                               unchanged: start vectors and exported rows keep the
                               original basis order) */
-  int32_t reserved;
+  int32_t waves;           /* waves per workgroup of the step kernel (slice
+                              kernel: 1, or 2 / 4 sharing one tile; others 1) */
 } kpm_run_stats;
 int kpm_last_run_stats(kpm_run_stats* out);
 

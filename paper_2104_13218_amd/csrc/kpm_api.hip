@@ -220,6 +220,7 @@ struct Tune {
   int gather_batch = 0;   // neighbour rows in flight per lane
   int lds_x = -1;         // block-table kernel: 1 rows of v_n staged in LDS, 0 not, -1 heuristic
   int rows = 0;           // slice kernel: rows per sub-tile (0 = heuristic)
+  int waves = 0;          // slice kernel: waves per workgroup (0 = heuristic)
 };
 
 struct RunShape {
@@ -964,6 +965,19 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
     }
     if (P.wg_rec.empty() || P.wg_rec.size() > (size_t)INT32_MAX) return KPM_EINVAL;
     D.slice_grid = (int32_t)P.wg_rec.size();
+    // waves per workgroup: 2 (default) or 4 share a tile (rows of 16 or 32
+    // bytes staged by direct loads, the tile's rows within the LDS limit),
+    // else 1.  On the 24-site ring (20 float32 columns in blocks of 4) two
+    // waves per tile took 290-297 us per step against 307-311 us for one.
+    D.slice_tile_rows = 0;
+    for (int32_t r : P.tile_nrows) D.slice_tile_rows = std::max(D.slice_tile_rows, r);
+    int nw = s.tune.waves > 0 ? s.tune.waves : 2;
+    if (const int f = env_int("KPM_SLICE_WAVES", 0)) nw = f;
+    if (nw != 2 && nw != 4) nw = 1;
+    const size_t rowb = (size_t)D.ld_max * (fp32 ? 4 : 8);
+    D.slice_nw = nw;
+    if (nw > 1 && (resid || rowb % 16 != 0 || slice_lds_bytes(D) > (size_t)env_int("KPM_BLOCK_LDS", 64 * 1024)))
+      D.slice_nw = 1;
   }
   D.total_cols = col_off;
   D.part_len = std::max<int64_t>(part_len, 1);
@@ -1382,17 +1396,21 @@ std::vector<Tune> tune_candidates(const kpm_problem* p, int n, const kpm_params&
         c.push_back(b);
       }
     // slice kernel (blocks of at most two 16-byte chunks per row): 10 low
-    // bits, 1-3 sub-tiles per workgroup, 4 or 8 high-high rows in flight
+    // bits, 1-3 sub-tiles per workgroup, 4 or 8 high-high rows in flight,
+    // 1, 2 or 4 waves per tile (the planner falls back to 1 where rows are
+    // not 16-byte multiples)
     if (w <= (fp32 ? 8 : 4))
       for (int spt : {1, 2, 3})
-        for (int gh : {4, 8}) {
-          Tune b = t;
-          b.kernel = 5;
-          b.block_L = 10;
-          b.spt = spt;
-          b.gather_batch = gh;
-          c.push_back(b);
-        }
+        for (int gh : {4, 8})
+          for (int nw : {1, 2, 4}) {
+            Tune b = t;
+            b.kernel = 5;
+            b.block_L = 10;
+            b.spt = spt;
+            b.gather_batch = gh;
+            b.waves = nw;
+            c.push_back(b);
+          }
   }
   return c;
 }
@@ -1631,6 +1649,7 @@ int run_moments(Planned& P, const MomLayout& L, unsigned char* work, const kpm_p
   }
   g_stats.kernel = D.spin ? 4 : (D.block == 3 ? 5 : (D.block == 2 ? 3 : (D.block ? 2 : (D.row_ld ? 1 : 0))));
   g_stats.graph_segment = used_segment;
+  g_stats.waves = D.block == 3 ? D.slice_nw : 1;
   g_stats.relabelled = 0;
   for (const auto& d : P.probs) g_stats.relabelled += d.relabel;
   float ms = 0.f;

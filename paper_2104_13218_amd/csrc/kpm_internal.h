@@ -147,7 +147,7 @@ struct StepArgs {
   const uint8_t* wtab;         // [n_probs][slice_words][slice_wb] word tables
   int32_t slice_wb;            // bytes per word-table row (32 or 64)
   int32_t slice_words;         // rows per problem (1 << largest blk_L)
-  int32_t blk_lds_rows;        // largest block (members), LDS rows of the slice kernel
+  int32_t blk_lds_rows;        // slice kernel: LDS rows per buffer (largest block, or tile when shared)
   const SliceWg* wg_rec;       // slice kernel: per workgroup, its tile (tile < 0: idle)
   const SliceBlk* blk_rec;     // slice kernel: per block (global index), its record
   int16_t* vec_lo;             // float32 + residual storage: the residual q of every
@@ -212,6 +212,8 @@ struct DevicePlan {
   int32_t blk_lds_rows = 0;    // slice kernel: members of the largest block
   SliceWg* wg_rec = nullptr;   // slice kernel: record of each of slice_grid workgroups
   int32_t slice_grid = 0;      // slice kernel: workgroups launched (0 = grid_tiles)
+  int32_t slice_nw = 1;        // slice kernel: waves per workgroup (1; 2 or 4 share a tile)
+  int32_t slice_tile_rows = 0; // slice kernel: rows of the largest tile
   int32_t blk_max = 16, blk_rows = kThreads, lds_lr = 1, lds_hh = 1, lds_mx = 1, ld_max = 1;
   int64_t n_states = 0;        // entries of the state table
   int64_t part_len = 0;        // doubles per partial buffer

@@ -1874,7 +1874,7 @@ static StepArgs make_step_args(const DevicePlan& p) {
       a.wtab = reinterpret_cast<const uint8_t*>(mb + m.wtab);
       a.slice_wb = p.slice_wb;
       a.slice_words = p.slice_words;
-      a.blk_lds_rows = p.blk_lds_rows;
+      a.blk_lds_rows = p.slice_nw > 1 ? p.slice_tile_rows : p.blk_lds_rows;
       a.wg_rec = p.wg_rec;
       a.blk_rec = reinterpret_cast<const SliceBlk*>(mb + m.brec);
     }

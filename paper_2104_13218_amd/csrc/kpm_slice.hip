@@ -10,12 +10,15 @@
 // bond (one low, one high site) moves a member to the block h ^ m_high, at the
 // colex rank of the flipped low word.
 //
-// One wave per workgroup, no workgroup barriers.  A workgroup walks the blocks
-// of its tile; per block it
+// One wave per workgroup (nw = 1, no workgroup barriers) or nw waves sharing a
+// tile.  A workgroup walks the blocks of its tile; per block it
 //   1. copies the block's rows of v_n into LDS (row 0 of its LDS area stays
-//      zero);
+//      zero); with nw > 1 the whole tile's rows (consecutive ranks) are
+//      copied once, before one barrier;
 //   2. runs "slices" of 64 / nch members (nch = 16-byte chunks per row), one
-//      member and chunk per lane.  Everything a block shares is scalar:
+//      member and chunk per lane; with nw > 1 the tile's slices, numbered
+//      across its blocks, go round robin to the waves (slice k to wave
+//      k mod nw).  Everything a block shares is scalar:
 //      its high word, the acting high-high bonds (their target blocks' first
 //      ranks and coefficients J_b/(2a) from per-block tables), and the
 //      high-high part of the diagonal.  High-high rows are buffer loads whose
@@ -27,6 +30,12 @@
 // bond the LDS row of the neighbour (0, the zero row, when the bond does not
 // act).  Sum order per element: diagonal, low-low, high-high, mixed, each in
 // bond order.
+//
+// Why nw > 1: the far high-high partners of a row are re-read from the L2
+// only while their rows are still there.  The rows in use at any time span
+// every tile open on an XCD; with one wave per tile that is every resident
+// wave's tile, with nw waves per tile nw times fewer tiles, each finished nw
+// times sooner, so more partner reads find their rows in the L2.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -262,6 +271,11 @@ constexpr int kLlMax = 32;
 
 size_t slice_lds_bytes(const DevicePlan& p) {
   const size_t rowb = (size_t)p.ld_max * (p.fp32 ? 4 : 8);
+  // nw > 1: one buffer of the largest tile's rows after the zero row, then
+  // each wave's partial dots (2 ld doubles per wave)
+  if (p.slice_nw > 1)
+    return (size_t)kLlMax * 8 + rowb + ((size_t)p.slice_tile_rows * rowb + 1023) / 1024 * 1024 +
+           (size_t)p.slice_nw * 2 * p.ld_max * 8;
   // rows of a multiple of 16 bytes: two buffers for direct staging, each the
   // zero row plus the largest block rounded up to whole 1 KB loads
   if (!p.resid && rowb % 16 == 0)
@@ -279,21 +293,66 @@ __device__ __forceinline__ uint32_t row_u16(const uint32_t (&w)[WB / 4], int byt
   return (w[byte >> 2] >> ((byte & 3) * 8)) & 0xFFFFu;
 }
 
-template <typename T, int CPL, int NCH, int GH, int WB, bool RES>
-__global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
+// The double held by lane (lane ^ M) of the wave, M a power of two below 64:
+// quad permutes for 1 and 2, a rotation by 8 inside rows of 16 lanes for 8,
+// swizzles inside halves of 32 lanes for 4 and 16, a lane permute for 32.
+template <int M>
+__device__ __forceinline__ double lane_xor(double x) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  if constexpr (M == 1 || M == 2 || M == 8) {
+    constexpr int ctrl = M == 1 ? 0xB1 : (M == 2 ? 0x4E : 0x128);
+    lo = __builtin_amdgcn_mov_dpp(lo, ctrl, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_mov_dpp(hi, ctrl, 0xF, 0xF, false);
+  } else if constexpr (M == 4 || M == 16) {
+    constexpr int pat = 0x1F | (M << 10);
+    lo = __builtin_amdgcn_ds_swizzle(lo, pat);
+    hi = __builtin_amdgcn_ds_swizzle(hi, pat);
+  } else {
+    return __shfl_xor(x, M, 64);
+  }
+  return __hiloint2double(hi, lo);
+}
+
+// V values per lane folded to one: at step t the lanes that differ in bit
+// M << t swap halves of what they hold and add, so each lane ends with one
+// value, of index sum_t b_t * V / 2^(t+1) (b_t = its bit M << t), summed
+// over the V lanes that differ from it only in those bits.
+template <int M, int V>
+__device__ __forceinline__ double fold_lanes(const double (&v)[V], int lane) {
+  if constexpr (V == 1) {
+    return v[0];
+  } else {
+    constexpr int H = V / 2;
+    const bool up = (lane & M) != 0;
+    double nv[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const double keep = up ? v[j + H] : v[j];
+      const double send = up ? v[j] : v[j + H];
+      nv[j] = keep + lane_xor<M>(send);
+    }
+    return fold_lanes<2 * M, H>(nv, lane);
+  }
+}
+
+template <typename T, int CPL, int NCH, int GH, int WB, bool RES, int NW>
+__global__ __launch_bounds__(64 * NW) void slice_kernel(const StepArgs a) {
   static_assert(!RES || (sizeof(T) == 4 && (CPL == 2 || CPL == 4)), "residual storage: float32 chunks of 2 or 4");
   extern __shared__ __align__(16) unsigned char smem[];
-  const int lane = threadIdx.x;
   using RowT = WordRow<WB>;
   using LT = typename std::conditional<RES, double, T>::type;   // LDS copy of v_n
   constexpr int LD = NCH * CPL;          // columns per row (every unit of the plan)
   constexpr int RPS = 64 / NCH;          // members per slice
   constexpr uint32_t ROWB = LD * sizeof(T);
+  static_assert(NW == 1 || NW == 2 || NW == 4, "waves per workgroup: 1, 2 or 4");
+  static_assert(NW == 1 || (!RES && ROWB % 16u == 0u), "shared tiles: rows staged by direct loads");
+  const int lane = (int)threadIdx.x & 63;
+  const int wid = NW > 1 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) : 0;
 
   if (a.n_jobs > 0) {
     // the previous step's partial dots: one column sum per job, fixed order
     const int64_t s = (a.step_base ? *a.step_base : 0) + a.step_add;
-    for (int job = blockIdx.x; job < a.n_jobs; job += gridDim.x) {
+    for (int job = (int)blockIdx.x * NW + wid; job < a.n_jobs; job += (int)gridDim.x * NW) {
       const UnitDev U = sload(a.units + cview(a.job_unit)[job]);
       const int v = job - 2 * U.col_off;
       const double* p = a.part_in + U.part_off + (int64_t)v * U.ntiles;
@@ -357,43 +416,66 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
   const int buf_elems = DIRECT ? (int)(LD + (((uint32_t)a.blk_lds_rows * ROWB + 1023u) / 1024u) * 1024u / sizeof(T))
                                : 0;
   LT* xs1 = xs0 + buf_elems;
-  for (int e = lane; e < LD; e += 64) {
-    xs0[e] = LT(0);
-    if constexpr (DIRECT) xs1[e] = LT(0);
+  // nw > 1: each wave's partial dots after the one buffer
+  double* red = reinterpret_cast<double*>(xs1);
+  if (wid == 0) {
+    for (int e = lane; e < LD; e += 64) {
+      xs0[e] = LT(0);
+      if constexpr (DIRECT && NW == 1) xs1[e] = LT(0);
+    }
+    for (int q = lane; q < kLlMax; q += 64) lco[q] = q < nll ? a.coff[P.bond_off + q] : 0.0;
   }
-  for (int q = lane; q < kLlMax; q += 64) lco[q] = q < nll ? a.coff[P.bond_off + q] : 0.0;
-  auto valid = [&](const SliceBlk& b) { return b.size != 0u && (int)b.size <= a.blk_lds_rows; };
-  // a block's rows, contiguous in v_n, to LDS rows 1.. of buf: 1 KB per
+  // a run of rows, contiguous in v_n, to LDS rows 1.. of buf: 1 KB per
   // instruction (lane i writes bytes 16i..16i+15 of the instruction's 1 KB);
-  // lanes past the block's end re-read its last 16 bytes into the buffer's
-  // rounded-up capacity, so every read stays inside the block
-  auto stage_direct = [&](const SliceBlk& b, LT* buf) {
-    const uint32_t bytes = b.size * ROWB, soff = b.start * ROWB;
-    for (uint32_t o = 0; o < bytes; o += 1024u)
+  // lanes past the run's end re-read its last 16 bytes into the buffer's
+  // rounded-up capacity, so every read stays inside the run.  The wave issues
+  // the instructions o0, o0 + ostep, ... (bytes).
+  auto stage_rows = [&](uint32_t start, uint32_t rows, LT* buf, uint32_t o0, uint32_t ostep) {
+    const uint32_t bytes = rows * ROWB, soff = start * ROWB;
+    for (uint32_t o = o0; o < bytes; o += ostep)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(
           rx, (__attribute__((address_space(3))) void*)(reinterpret_cast<unsigned char*>(buf + LD) + o), 16,
           min(o + (uint32_t)lane * 16u, bytes - 16u), soff, 0, 0);
   };
+  auto stage_direct = [&](const SliceBlk& b, LT* buf) { stage_rows(b.start, b.size, buf, 0u, 1024u); };
+  // nw > 1: the tile's rows [tstart, tstart + trows) staged once, by all waves
+  uint32_t tstart = 0u;
+  bool tile_ok = true;
+  if constexpr (NW > 1) {
+    const SliceBlk Bl = sload(a.blk_rec + R.g0 + R.ng - 1);
+    tstart = Bn.start;
+    const uint32_t trows = Bl.start + Bl.size - Bn.start;
+    tile_ok = R.ng > 0 && Bl.start >= Bn.start && trows <= (uint32_t)a.blk_lds_rows;
+    if (tile_ok) stage_rows(tstart, trows, xs0, (uint32_t)wid * 1024u, (uint32_t)NW * 1024u);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  auto valid = [&](const SliceBlk& b) {
+    if constexpr (NW > 1) return tile_ok && b.size != 0u;
+    return b.size != 0u && (int)b.size <= a.blk_lds_rows;
+  };
 
-  double acc_a[CPL], acc_b[CPL];
-#pragma unroll
-  for (int e = 0; e < CPL; ++e) acc_a[e] = acc_b[e] = 0.0;
+  // the dots <v_{n+1}, v_{n+1}> and <v_{n+1}, v_n> of the wave's rows: per
+  // slice the 2 CPL products of each lane are folded over 2 CPL lanes
+  // (fold_lanes), so one sum per lane carries them from slice to slice
+  double dacc = 0.0;
 
   {
     const int gend = R.g0 + R.ng;
     // records: the current block's and the next one's are at hand, the one
     // after is requested while the current block runs
     SliceBlk Bx = R.ng > 1 ? sload(a.blk_rec + R.g0 + 1) : Bn;
-    if constexpr (DIRECT)
+    if constexpr (DIRECT && NW == 1)
       if (valid(Bn)) stage_direct(Bn, xs0);
     uint32_t wn[WB / 4];
-    bool wpre = false;   // wn holds slice 0's word row of the current block
+    bool wpre = false;   // wn holds the word row of this wave's first slice of the current block
+    int soff = 0;        // nw > 1: the tile's slices before the current block
     for (int g = R.g0; g < gend; ++g) {
       const SliceBlk B = Bn;
       Bn = Bx;
       if (g + 2 < gend) Bx = sload(a.blk_rec + g + 2);
-      LT* xs = DIRECT && ((g - R.g0) & 1) ? xs1 : xs0;
-      if constexpr (DIRECT) {
+      LT* xs = DIRECT && NW == 1 && ((g - R.g0) & 1) ? xs1 : xs0;
+      if constexpr (DIRECT && NW == 1) {
         // this block's rows (and every earlier memory operation) complete,
         // the other buffer's last readers done: stage the next block there
         __builtin_amdgcn_s_waitcnt(0);
@@ -403,11 +485,17 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
       const uint32_t h = B.h;
       const uint32_t st = B.start;
       const int bsz = (int)B.size;
+      const int nsl = (bsz + RPS - 1) / RPS;
+      // this wave's first slice of the block (slice soff + s of the tile)
+      const int s_first = NW > 1 ? ((wid - soff) & (NW - 1)) : 0;
+      soff += nsl;
       if (!valid(B)) {
-        if (lane == 0 && a.err) atomicOr(a.err, 4);
+        if (lane == 0 && wid == 0 && a.err) atomicOr(a.err, 4);
         wpre = false;
         continue;
       }
+      // LDS row of member 0 is 1 + xbase (nw > 1: the block's place in the tile)
+      const uint32_t xbase = NW > 1 ? st - tstart : 0u;
       const int nh = min((int)B.nh, nhh);
       const double dhh = B.dhh;
       const uint32_t kofs = B.kofs;
@@ -446,13 +534,13 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
       // 2. slices of the block.  A slice's v_{n+1} is stored after the next
       // slice's loads are issued (its data registers are then not the next
       // loads' targets, so those loads need not wait for the store).
-      const int nsl = (bsz + RPS - 1) / RPS;
       RowIn<T, CPL, RES> pend;
       uint32_t pend_off = 0u;
       bool pend_on = false;
-      // word-table rows one slice ahead: slice s's row was requested during
-      // slice s - 1, so its mixed-bond targets are known when s starts
-      // (and the next block's first one during this block's last slice)
+      // word-table rows one slice ahead: the row of the wave's slice s was
+      // requested during its previous slice, so its mixed-bond targets are
+      // known when s starts (and the wave's first one of the next block
+      // during its last one of this block)
       auto wload = [&](uint32_t kof, int nmem, int sl, uint32_t (&wr)[WB / 4]) {
         const int i = sl * RPS + rl;
         const uint32_t ii = i < nmem ? (uint32_t)i : 0u;
@@ -465,19 +553,21 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
           wr[4 * t + 3] = q[3];
         }
       };
-      if (!wpre) wload(kofs, bsz, 0, wn);
-      for (int s = 0; s < nsl; ++s) {
+      if (!wpre && s_first < nsl) wload(kofs, bsz, s_first, wn);
+      for (int s = s_first; s < nsl; s += NW) {
         const int i = s * RPS + rl;
         const bool on = i < bsz;
         const uint32_t ii = on ? (uint32_t)i : 0u;
         uint32_t w[WB / 4];
 #pragma unroll
         for (int t = 0; t < WB / 4; ++t) w[t] = wn[t];
-        if (s + 1 < nsl) {
-          wload(kofs, bsz, s + 1, wn);
+        if (s + NW < nsl) {
+          wload(kofs, bsz, s + NW, wn);
         } else {
-          wpre = g + 1 < gend && valid(Bn);
-          if (wpre) wload(Bn.kofs, (int)Bn.size, 0, wn);
+          // the wave's next slice is slice sn of the next block, if it has one
+          const int sn = s + NW - nsl;
+          wpre = g + 1 < gend && valid(Bn) && sn * RPS < (int)Bn.size;
+          if (wpre) wload(Bn.kofs, (int)Bn.size, sn, wn);
         }
         const uint32_t own = st + ii;
         const uint32_t voff_own = own * ROWB + cc * (uint32_t)sizeof(T);
@@ -520,7 +610,7 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
         }
         double acc[CPL];
         {
-          const VecT<LT, CPL> xv = *reinterpret_cast<const VecT<LT, CPL>*>(xs + (1 + ii) * LD + cc);
+          const VecT<LT, CPL> xv = *reinterpret_cast<const VecT<LT, CPL>*>(xs + (1 + xbase + ii) * LD + cc);
 #pragma unroll
           for (int e = 0; e < CPL; ++e) acc[e] = d * (double)xv.v[e];
         }
@@ -534,7 +624,8 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
             double cf[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-              const uint32_t r = row_byte<WB>(w, RowT::kLlOff + q0 + u);
+              const uint32_t r0 = row_byte<WB>(w, RowT::kLlOff + q0 + u);
+              const uint32_t r = NW > 1 && r0 != 0u ? r0 + xbase : r0;
               cf[u] = lco[q0 + u];
               xv[u] = *reinterpret_cast<const VecT<LT, CPL>*>(xs + r * LD + cc);
             }
@@ -601,12 +692,15 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
         }
         pend_on = on;
         pend_off = voff_own;
-        if (on) {
-          // v_{n+1} as stored; the dots are of the stored values
-          double o[CPL];
+        {
+          // v_{n+1} as stored (lanes past the block: member 0's rows, not
+          // stored); the dots are of the stored values
+          const VecT<LT, CPL> xv = *reinterpret_cast<const VecT<LT, CPL>*>(xs + (1 + xbase + ii) * LD + cc);
+          double fv[2 * CPL];
 #pragma unroll
           for (int e = 0; e < CPL; ++e) {
             const double val = a.first ? acc[e] : 2.0 * acc[e] - row_val(yv, e);
+            double o;
             if constexpr (RES) {
               float hi;
               int16_t q;
@@ -615,18 +709,15 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
               const uint32_t bits = (uint32_t)(uint16_t)q << ((e & 1) * 16);
               if (e & 1) pend.lo.w[e >> 1] |= bits;
               else pend.lo.w[e >> 1] = bits;
-              o[e] = res_decode(hi, q);
+              o = res_decode(hi, q);
             } else {
               pend.v.v[e] = (T)val;
-              o[e] = (double)pend.v.v[e];
+              o = (double)pend.v.v[e];
             }
+            fv[e] = on ? o * o : 0.0;
+            fv[CPL + e] = on ? o * (double)xv.v[e] : 0.0;
           }
-          const VecT<LT, CPL> xv = *reinterpret_cast<const VecT<LT, CPL>*>(xs + (1 + ii) * LD + cc);
-#pragma unroll
-          for (int e = 0; e < CPL; ++e) {
-            acc_a[e] = fma(o[e], o[e], acc_a[e]);
-            acc_b[e] = fma(o[e], (double)xv.v[e], acc_b[e]);
-          }
+          dacc += fold_lanes<NCH, 2 * CPL>(fv, lane);
         }
       }
       if (pend_on) {
@@ -637,34 +728,60 @@ __global__ __launch_bounds__(64) void slice_kernel(const StepArgs a) {
     }
   }
 
-  // dots: a fixed tree over the members of each column chunk
+  // dots: the lanes' sums over the member bits not folded per slice (fixed
+  // order); lane l < 2 CPL * NCH then holds chunk l % NCH's value of index
+  // bit-reversed(l / NCH)
+  {
+    constexpr int V = 2 * CPL;
+    double dv = dacc;
 #pragma unroll
-  for (int v = 0; v < 2 * CPL; ++v) {
-    double val = v < CPL ? acc_a[v] : acc_b[v - CPL];
+    for (int m = NCH * V; m < 64; m <<= 1) dv += __shfl_xor(dv, m, 64);
+    if (lane < NCH * V) {
+      const int r = lane / NCH;
+      int idx = 0;
 #pragma unroll
-    for (int s = 1; s < RPS; s <<= 1) {
-      const double o = __shfl_down(val, s * NCH, 64);
-      if ((rl & (2 * s - 1)) == 0) val += o;
+      for (int t = 0; (1 << t) < V; ++t) idx += ((r >> t) & 1) * (V >> (t + 1));
+      const int dot = idx < CPL ? 0 : 1;
+      const int col = (lane % NCH) * CPL + idx - dot * CPL;
+      if constexpr (NW == 1) a.part_out[U.part_off + (int64_t)(dot * LD + col) * U.ntiles + (tile - U.tile0)] = dv;
+      else red[wid * 2 * LD + dot * LD + col] = dv;
     }
-    if (rl == 0) {
-      const int dot = v < CPL ? 0 : 1;
-      const int col = (int)cc + (v - dot * CPL);
-      a.part_out[U.part_off + (int64_t)(dot * LD + col) * U.ntiles + (tile - U.tile0)] = val;
+  }
+  if constexpr (NW > 1) {
+    // then over the waves, in wave order
+    __syncthreads();
+    if (wid == 0 && lane < 2 * LD) {
+      double sum = red[lane];
+      for (int w = 1; w < NW; ++w) sum += red[w * 2 * LD + lane];
+      a.part_out[U.part_off + (int64_t)lane * U.ntiles + (tile - U.tile0)] = sum;
     }
   }
 }
 
-template <typename T, int CPL, int NCH, int WB, bool RES>
+template <typename T, int CPL, int NCH, int WB, bool RES, int NW>
 static hipError_t launch_slice_w(const StepArgs& a, size_t lds, int grid, int gh, hipStream_t st) {
-  if (gh == 4) hipLaunchKernelGGL((slice_kernel<T, CPL, NCH, 4, WB, RES>), dim3(grid), dim3(64), lds, st, a);
-  else hipLaunchKernelGGL((slice_kernel<T, CPL, NCH, 8, WB, RES>), dim3(grid), dim3(64), lds, st, a);
+  if (gh == 4)
+    hipLaunchKernelGGL((slice_kernel<T, CPL, NCH, 4, WB, RES, NW>), dim3(grid), dim3(64 * NW), lds, st, a);
+  else
+    hipLaunchKernelGGL((slice_kernel<T, CPL, NCH, 8, WB, RES, NW>), dim3(grid), dim3(64 * NW), lds, st, a);
   return hipGetLastError();
 }
 
+template <typename T, int CPL, int NCH, bool RES, int NW>
+static hipError_t launch_slice_n(const StepArgs& a, size_t lds, int grid, int gh, int wb, hipStream_t st) {
+  if (wb == 32) return launch_slice_w<T, CPL, NCH, 32, RES, NW>(a, lds, grid, gh, st);
+  return launch_slice_w<T, CPL, NCH, 64, RES, NW>(a, lds, grid, gh, st);
+}
+
+// waves per workgroup: 1, or 2 / 4 for rows of 16 or 32 bytes (direct staging)
 template <typename T, int CPL, int NCH, bool RES = false>
-static hipError_t launch_slice_t(const StepArgs& a, size_t lds, int grid, int gh, int wb, hipStream_t st) {
-  if (wb == 32) return launch_slice_w<T, CPL, NCH, 32, RES>(a, lds, grid, gh, st);
-  return launch_slice_w<T, CPL, NCH, 64, RES>(a, lds, grid, gh, st);
+static hipError_t launch_slice_t(const StepArgs& a, size_t lds, int grid, int gh, int wb, int nw, hipStream_t st) {
+  if constexpr (!RES && (NCH * CPL * sizeof(T)) % 16 == 0) {
+    if (nw == 4) return launch_slice_n<T, CPL, NCH, RES, 4>(a, lds, grid, gh, wb, st);
+    if (nw == 2) return launch_slice_n<T, CPL, NCH, RES, 2>(a, lds, grid, gh, wb, st);
+  }
+  if (nw != 1) return hipErrorInvalidValue;
+  return launch_slice_n<T, CPL, NCH, RES, 1>(a, lds, grid, gh, wb, st);
 }
 
 // Every unit of a slice plan has ld = cpl * nch with nch 1 or 2.
@@ -673,25 +790,26 @@ hipError_t launch_slice(const DevicePlan& p, const StepArgs& a, hipStream_t st) 
   const int grid = p.slice_grid > 0 ? p.slice_grid : p.grid_tiles;
   const int gh = p.gather_batch;
   const int wb = p.slice_wb;
+  const int nw = p.slice_nw;
   const int nch = p.ld_max / p.cpl;
   if (p.ld_max != nch * p.cpl || (nch != 1 && nch != 2)) return hipErrorInvalidValue;
   if (p.resid) {
     if (!p.fp32 || !a.vec_lo) return hipErrorInvalidValue;
-    if (p.cpl == 4) return nch == 1 ? launch_slice_t<float, 4, 1, true>(a, lds, grid, gh, wb, st)
-                                    : launch_slice_t<float, 4, 2, true>(a, lds, grid, gh, wb, st);
-    if (p.cpl == 2 && nch == 1) return launch_slice_t<float, 2, 1, true>(a, lds, grid, gh, wb, st);
+    if (p.cpl == 4) return nch == 1 ? launch_slice_t<float, 4, 1, true>(a, lds, grid, gh, wb, nw, st)
+                                    : launch_slice_t<float, 4, 2, true>(a, lds, grid, gh, wb, nw, st);
+    if (p.cpl == 2 && nch == 1) return launch_slice_t<float, 2, 1, true>(a, lds, grid, gh, wb, nw, st);
     return hipErrorInvalidValue;
   }
   if (p.fp32) {
-    if (p.cpl == 4) return nch == 1 ? launch_slice_t<float, 4, 1>(a, lds, grid, gh, wb, st)
-                                    : launch_slice_t<float, 4, 2>(a, lds, grid, gh, wb, st);
-    if (p.cpl == 2 && nch == 1) return launch_slice_t<float, 2, 1>(a, lds, grid, gh, wb, st);
-    if (p.cpl == 1 && nch == 1) return launch_slice_t<float, 1, 1>(a, lds, grid, gh, wb, st);
+    if (p.cpl == 4) return nch == 1 ? launch_slice_t<float, 4, 1>(a, lds, grid, gh, wb, nw, st)
+                                    : launch_slice_t<float, 4, 2>(a, lds, grid, gh, wb, nw, st);
+    if (p.cpl == 2 && nch == 1) return launch_slice_t<float, 2, 1>(a, lds, grid, gh, wb, nw, st);
+    if (p.cpl == 1 && nch == 1) return launch_slice_t<float, 1, 1>(a, lds, grid, gh, wb, nw, st);
     return hipErrorInvalidValue;
   }
-  if (p.cpl == 2) return nch == 1 ? launch_slice_t<double, 2, 1>(a, lds, grid, gh, wb, st)
-                                  : launch_slice_t<double, 2, 2>(a, lds, grid, gh, wb, st);
-  if (p.cpl == 1 && nch == 1) return launch_slice_t<double, 1, 1>(a, lds, grid, gh, wb, st);
+  if (p.cpl == 2) return nch == 1 ? launch_slice_t<double, 2, 1>(a, lds, grid, gh, wb, nw, st)
+                                  : launch_slice_t<double, 2, 2>(a, lds, grid, gh, wb, nw, st);
+  if (p.cpl == 1 && nch == 1) return launch_slice_t<double, 1, 1>(a, lds, grid, gh, wb, nw, st);
   return hipErrorInvalidValue;
 }
 

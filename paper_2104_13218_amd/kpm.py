@@ -48,7 +48,7 @@ class RunStats(ctypes.Structure):
     _fields_ = [("step_launches", c_int64), ("bytes_per_launch", c_double),
                 ("state_col_steps", c_double), ("col_block", c_int32), ("rows_per_tile", c_int32),
                 ("graph_segment", c_int32), ("kernel", c_int32), ("recursion_ms", c_double),
-                ("relabelled", c_int32), ("reserved", c_int32)]
+                ("relabelled", c_int32), ("waves", c_int32)]
 
 
 _lib = None

@@ -38,6 +38,15 @@ KERNELS = {
     "slice_l10": ({"KPM_BLOCK": "3", "KPM_BLOCK_L": "10", "KPM_SUB_PER_TILE": "2"}, 5),
     # contiguous tile ranges per XCD in place of the default per-column-block chunks
     "slice_contig": ({"KPM_BLOCK": "3", "KPM_XCD_REMAP": "1"}, 5),
+    # waves per tile (default 2 where rows are 16-byte multiples): one wave,
+    # four waves, four waves on tiles of many small blocks (slices numbered
+    # across blocks), two waves on 4-bit blocks (one slice per block, so a
+    # wave skips every other block)
+    "slice_w1": ({"KPM_BLOCK": "3", "KPM_SLICE_WAVES": "1"}, 5),
+    "slice_w4": ({"KPM_BLOCK": "3", "KPM_SLICE_WAVES": "4"}, 5),
+    "slice_w4_small": ({"KPM_BLOCK": "3", "KPM_SLICE_WAVES": "4", "KPM_BLOCK_ROWS": "64", "KPM_BLOCK_MAX": "2",
+                        "KPM_SUB_PER_TILE": "3"}, 5),
+    "slice_w2_l4": ({"KPM_BLOCK": "3", "KPM_SLICE_WAVES": "2", "KPM_BLOCK_L": "4", "KPM_SUB_PER_TILE": "2"}, 5),
 }
 
 
@@ -106,7 +115,7 @@ def test_j1j2_n18_sz0_wide_block(kpm, monkeypatch, kernel):
 
 
 @pytest.mark.parametrize("kernel", ["block", "block_small", "block_l4", "tab", "tab_small", "tab_l4", "slice",
-                                    "slice_small", "slice_l4", "slice_l10"])
+                                    "slice_small", "slice_l4", "slice_l10", "slice_w1", "slice_w4", "slice_w2_l4"])
 def test_block_extreme_sectors(kpm, monkeypatch, kernel):
     """Sectors whose blocks are tiny (n_up near N) or single (N below the
     block width), dimension-1 sectors and the dimer."""
@@ -149,6 +158,29 @@ def test_slice_workgroup_mappings_identical(kpm, monkeypatch):
         assert kpm.last_run_stats()["kernel"] == 5
         out[remap] = mu.cpu().numpy()
     assert np.array_equal(out["1"], out["2"])
+
+
+@pytest.mark.parametrize("precision,col_block,env_waves,want", [
+    ("fp32", 4, None, 2), ("fp32", 8, "4", 4), ("fp32", 4, "1", 1), ("fp64", 2, None, 2),
+    ("fp32", 2, None, 1), ("fp64", 1, "4", 1), ("fp32r", 4, "2", 1)])
+def test_slice_waves_per_tile(kpm, monkeypatch, precision, col_block, env_waves, want):
+    """Waves per workgroup as planned: 2 by default, as asked where rows are
+    16 or 32 bytes (float32 blocks of 4 or 8 columns, float64 blocks of 2),
+    1 for narrower rows and for float32 + residual storage; the moments match
+    the oracle either way."""
+    monkeypatch.setenv("KPM_BLOCK", "3")
+    if env_waves:
+        monkeypatch.setenv("KPM_SLICE_WAVES", env_waves)
+    secs = W.sectors(W.ring(16), only_sz0=True)
+    (lo, hi), H = _bounds(secs[0])
+    mu, _ = kpm.chebyshev_moments(secs, 40, 8, "rademacher", precision, 0.025, 5, col_block, bounds=[(lo, hi)])
+    st = kpm.last_run_stats()
+    assert st["kernel"] == 5 and st["waves"] == want, st
+    a, b = hamiltonian.scale_from_bounds(lo, hi, 0.025)
+    ref = moments.sector_moments(secs[0], a, b, 40, 8, "rademacher", 5, H=H,
+                                 store=moments.F32R if precision == "fp32r" else np.float64)
+    tol = {"fp64": 1e-10, "fp32": 1e-5, "fp32r": 1e-10}[precision]
+    assert np.abs(mu.cpu().numpy()[0] - ref).max() <= tol * abs(ref[0])
 
 
 # ------------------------------------------------- relabelled sites (block kernels)
