@@ -90,10 +90,12 @@ def _parse():
     return ap.parse_args()
 
 
-def _traffic(family, tag="ring24_sz0_fp32"):
+def _traffic(family, tag="ring24_sz0_fp32", st=None):
     """Measured HBM-side bytes per step launch from the committed rocprofv3
     counter summary of this kernel on this workload (`tag`), when it was taken
-    on the current kernel source."""
+    on the current kernel source and, where the record names the launch shape
+    (column block, mean rows per tile, waves per tile), on the shape of the
+    run `st`."""
     path = os.path.join(PROFILES, f"{family}_{tag}_traffic.json")
     try:
         with open(path) as f:
@@ -102,7 +104,16 @@ def _traffic(family, tag="ring24_sz0_fp32"):
         return None
     if d.get("kernel_text_sha256") != kernel_text_sha256(family):
         return None
+    shape = d.get("shape")
+    if shape and st is not None:
+        if any(st.get(k) != v for k, v in shape.items()):
+            return None
     return d.get("hbm_bytes_per_launch")
+
+
+def _shape(st):
+    """The launch shape a counter record must share with a run."""
+    return {k: st[k] for k in ("col_block", "rows_per_tile", "waves")}
 
 
 def kernel_text_sha256(family):
@@ -209,7 +220,7 @@ def main():
     avg_launch_s = sum(s["recursion_ms"] for s in stats) / len(stats) / 1e3 / st["step_launches"]
     achieved = st["bytes_per_launch"] / avg_launch_s / 1e9
     family = KERNEL_FAMILY.get(st["kernel"], "step_kernel")
-    traffic = _traffic(family)
+    traffic = _traffic(family, st=st)
     copy_gbs = _copy_rate(torch)
     line = {
         "metric": METRIC, "value": value, "unit": "state-column-steps/s", "n_gpus": 1,
@@ -218,13 +229,13 @@ def main():
         "config": {"workload": "heisenberg_ring_N24_Sz0", "dim": sec[0].dim, "vectors": "10 complex Gaussian",
                    "real_columns": 20, "M": M, "recursion_launches": st["step_launches"], "eps": 0.025,
                    "bounds": "lanczos50+1%", "storage": "f32", "col_block": st["col_block"],
-                   "rows_per_tile": st["rows_per_tile"], "graph_segment": st["graph_segment"],
+                   "rows_per_tile": st["rows_per_tile"], "waves_per_tile": st["waves"], "graph_segment": st["graph_segment"],
                    "device": dev},
         "roofline": {"bound": "hbm", "kernel": family, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "algorithmic_bytes_per_launch": st["bytes_per_launch"],
                      "avg_launch_us": avg_launch_s * 1e6,
-                     "traffic": traffic,
+                     "shape": _shape(st), "traffic": traffic,
                      "measured_GBs": None if traffic is None else traffic / avg_launch_s / 1e9,
                      "measured_frac": None if traffic is None else traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS,
                      "copy_GBs": copy_gbs},
@@ -252,11 +263,11 @@ def _roofline(st, tag=None):
     t = st["recursion_ms"] / 1e3 / st["step_launches"]
     ach = st["bytes_per_launch"] / t / 1e9
     family = KERNEL_FAMILY.get(st["kernel"], "step_kernel")
-    traffic = _traffic(family, tag) if tag else None
+    traffic = _traffic(family, tag, st) if tag else None
     return {"bound": "hbm", "kernel": family, "achieved": ach,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "algorithmic_bytes_per_launch": st["bytes_per_launch"], "avg_launch_us": t * 1e6,
-            "traffic": traffic,
+            "shape": _shape(st), "traffic": traffic,
             "measured_GBs": None if traffic is None else traffic / t / 1e9,
             "measured_frac": None if traffic is None else traffic / t / 1e9 / HBM_PEAK_GBS}
 

@@ -1397,12 +1397,13 @@ std::vector<Tune> tune_candidates(const kpm_problem* p, int n, const kpm_params&
       }
     // slice kernel (blocks of at most two 16-byte chunks per row): 10 low
     // bits, 1-3 sub-tiles per workgroup, 4 or 8 high-high rows in flight,
-    // 1, 2 or 4 waves per tile (the planner falls back to 1 where rows are
-    // not 16-byte multiples)
+    // 2, 4 or 1 waves per tile (the planner falls back to 1 where rows are
+    // not 16-byte multiples); the shape measured best on the 24-site ring
+    // first
     if (w <= (fp32 ? 8 : 4))
-      for (int spt : {1, 2, 3})
+      for (int spt : {2, 1, 3})
         for (int gh : {4, 8})
-          for (int nw : {1, 2, 4}) {
+          for (int nw : {2, 4, 1}) {
             Tune b = t;
             b.kernel = 5;
             b.block_L = 10;
@@ -1415,11 +1416,12 @@ std::vector<Tune> tune_candidates(const kpm_problem* p, int n, const kpm_params&
   return c;
 }
 
-// Seconds per step of one candidate: plan, Rademacher start, two warm-up and
-// six timed steps (values are irrelevant to the timing).
+// Seconds per step of one candidate: plan, Rademacher start, three warm-up
+// and `meas` timed steps (values are irrelevant to the timing; the steps
+// reduce no dots).
 double time_candidate(const kpm_problem* p, int n, const kpm_params& q, const Tune& t,
                       const double* a, const double* b, unsigned char* work, size_t bytes,
-                      hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+                      hipStream_t st, hipEvent_t e0, hipEvent_t e1, int meas = 6) {
   Planned P;
   if (make_plan(p, n, shape_of(q, &t), a, b, P) != KPM_OK) return INFINITY;
   const MomLayout L = moments_layout(P, 8, 0);
@@ -1435,7 +1437,7 @@ double time_candidate(const kpm_problem* p, int n, const kpm_params& q, const Tu
   bool ok = hipMemsetAsync(D.err, 0, sizeof(int), st) == hipSuccess;
   if (ok && (D.row_ld || D.block || D.spin)) ok = fill_states(D, st) == hipSuccess;
   if (ok) ok = launch_init(D, vec, 1, KPM_VEC_RADEMACHER, q.seed, nullptr, part[0], st) == hipSuccess;
-  const int warm = 3, meas = 6;
+  const int warm = 3;
   for (int k = 0; ok && k < warm + meas; ++k) {
     if (k == warm) ok = hipEventRecord(e0, st) == hipSuccess;
     if (ok)
@@ -1489,13 +1491,25 @@ int get_tune(const kpm_problem* p, int n, const kpm_params& q, const double* a, 
     (void)hipEventDestroy(e0);
     return KPM_EDEVICE;
   }
+  // Every candidate over 6 steps, then those within 5 % of the fastest again
+  // over 30 steps, in list order: a later one replaces the pick only when
+  // more than 1 % faster, so shapes within the timing noise of each other
+  // resolve to the earlier one, the same in every process.
+  const std::vector<Tune> cands = tune_candidates(p, n, q);
+  std::vector<double> sec(cands.size());
+  double first = INFINITY;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    sec[i] = time_candidate(p, n, q, cands[i], a, b, work, bytes, st, e0, e1);
+    first = std::min(first, sec[i]);
+  }
   double best = INFINITY;
   Tune pick{};
-  for (const Tune& t : tune_candidates(p, n, q)) {
-    const double sec = time_candidate(p, n, q, t, a, b, work, bytes, st, e0, e1);
-    if (sec < best) {
-      best = sec;
-      pick = t;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    if (!(sec[i] <= first * 1.05)) continue;
+    const double s30 = time_candidate(p, n, q, cands[i], a, b, work, bytes, st, e0, e1, 30);
+    if (s30 < best * (1.0 - 0.01)) {
+      best = s30;
+      pick = cands[i];
     }
   }
   (void)hipEventDestroy(e0);

@@ -467,8 +467,6 @@ __global__ __launch_bounds__(64 * NW) void slice_kernel(const StepArgs a) {
     SliceBlk Bx = R.ng > 1 ? sload(a.blk_rec + R.g0 + 1) : Bn;
     if constexpr (DIRECT && NW == 1)
       if (valid(Bn)) stage_direct(Bn, xs0);
-    uint32_t wn[WB / 4];
-    bool wpre = false;   // wn holds the word row of this wave's first slice of the current block
     int soff = 0;        // nw > 1: the tile's slices before the current block
     for (int g = R.g0; g < gend; ++g) {
       const SliceBlk B = Bn;
@@ -491,7 +489,6 @@ __global__ __launch_bounds__(64 * NW) void slice_kernel(const StepArgs a) {
       soff += nsl;
       if (!valid(B)) {
         if (lane == 0 && wid == 0 && a.err) atomicOr(a.err, 4);
-        wpre = false;
         continue;
       }
       // LDS row of member 0 is 1 + xbase (nw > 1: the block's place in the tile)
@@ -537,10 +534,9 @@ __global__ __launch_bounds__(64 * NW) void slice_kernel(const StepArgs a) {
       RowIn<T, CPL, RES> pend;
       uint32_t pend_off = 0u;
       bool pend_on = false;
-      // word-table rows one slice ahead: the row of the wave's slice s was
-      // requested during its previous slice, so its mixed-bond targets are
-      // known when s starts (and the wave's first one of the next block
-      // during its last one of this block)
+      // the word-table row of a member (requested at its slice's start: a row
+      // requested a slice ahead held 4-5 more VGPRs, one wave per SIMD fewer,
+      // and was 1 % slower)
       auto wload = [&](uint32_t kof, int nmem, int sl, uint32_t (&wr)[WB / 4]) {
         const int i = sl * RPS + rl;
         const uint32_t ii = i < nmem ? (uint32_t)i : 0u;
@@ -553,22 +549,12 @@ __global__ __launch_bounds__(64 * NW) void slice_kernel(const StepArgs a) {
           wr[4 * t + 3] = q[3];
         }
       };
-      if (!wpre && s_first < nsl) wload(kofs, bsz, s_first, wn);
       for (int s = s_first; s < nsl; s += NW) {
         const int i = s * RPS + rl;
         const bool on = i < bsz;
         const uint32_t ii = on ? (uint32_t)i : 0u;
         uint32_t w[WB / 4];
-#pragma unroll
-        for (int t = 0; t < WB / 4; ++t) w[t] = wn[t];
-        if (s + NW < nsl) {
-          wload(kofs, bsz, s + NW, wn);
-        } else {
-          // the wave's next slice is slice sn of the next block, if it has one
-          const int sn = s + NW - nsl;
-          wpre = g + 1 < gend && valid(Bn) && sn * RPS < (int)Bn.size;
-          if (wpre) wload(Bn.kofs, (int)Bn.size, sn, wn);
-        }
+        wload(kofs, bsz, s, w);
         const uint32_t own = st + ii;
         const uint32_t voff_own = own * ROWB + cc * (uint32_t)sizeof(T);
         const uint32_t voff_m = ii * ROWB + cc * (uint32_t)sizeof(T);
