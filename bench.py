@@ -104,11 +104,13 @@ def _traffic(family, tag="ring24_sz0_fp32", st=None):
         return None
     if d.get("kernel_text_sha256") != kernel_text_sha256(family):
         return None
-    shape = d.get("shape")
-    if shape and st is not None:
-        if any(st.get(k) != v for k, v in shape.items()):
-            return None
-    return d.get("hbm_bytes_per_launch")
+    # one record, or one per launch shape the tuner may pick
+    for rec in d.get("records", [d]):
+        shape = rec.get("shape")
+        if shape and st is not None and any(st.get(k) != v for k, v in shape.items()):
+            continue
+        return rec.get("hbm_bytes_per_launch")
+    return None
 
 
 def _shape(st):
