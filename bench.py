@@ -370,9 +370,13 @@ def other_workload(args, kpm, W, np, torch, dev):
         wC = np.ones((1, T.size))
         wX = np.zeros((1, T.size))
 
+        # every v_n of the forward pass kept (M/2 + 2 vectors of dim x R float64,
+        # 12 GB here): the reverse sweep recomputes nothing
+        ckpt = wl.M // 2
+
         def run():
             return kpm.thermo_grad(wl.problems, wl.M, wl.R, T, wC, wX, wl.vec_kind, "fp64", wl.eps, wl.seed,
-                                   kernel=wl.kernel, ckpt_every=64, bounds=bl)
+                                   kernel=wl.kernel, ckpt_every=ckpt, bounds=bl)
 
         dt, _ = _timed(args, torch, run)
 
@@ -384,7 +388,8 @@ def other_workload(args, kpm, W, np, torch, dev):
         dim = wl.problems[0].dim
         work = dim * wl.R * (wl.M // 2)
         cfg = {"dim": dim, "bonds": wl.problems[0].cluster.n_bonds, "M": wl.M, "vectors": f"{wl.R} rademacher",
-               "storage": "f64", "checkpoint_every": 64, "loss": "sum_T C(T), 64 T in [0.05, 5]",
+               "storage": "f64", "checkpoint_every": ckpt,
+               "trajectory_bytes": (wl.M // 2 + 2) * dim * wl.R * 8, "loss": "sum_T C(T), 64 T in [0.05, 5]",
                "device": dev}
         # the reverse step reads w_{n+1} (gathers), w_{n+2}, v_{n-1}, v_n, v_{n+1}
         # and writes w_n: 6 x 8 bytes per state and column; its launch time is

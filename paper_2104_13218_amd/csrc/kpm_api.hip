@@ -1885,6 +1885,10 @@ int run_vjp(const kpm_problem* p, int n, const kpm_params& q, const double* h_ab
     part_fw = reinterpret_cast<double*>(work + L.partf);
   }
   const int K = L.K, C = L.C;
+  // C >= K: the segment buffer holds the whole trajectory v_0 .. v_K (slot j
+  // holds v_j), written by the forward pass, so the reverse sweep recomputes
+  // nothing (memory K + 2 vectors instead of 2 K / C + C + 2)
+  const bool full = C >= K;
   const size_t elt = D.fp32 ? 4 : 8;
   const size_t slot_bytes = (size_t)D.slot_stride * elt;
   unsigned char* seg = work + L.seg;
@@ -1911,8 +1915,11 @@ int run_vjp(const kpm_problem* p, int n, const kpm_params& q, const double* h_ab
   if (!d_mu) {
     KPM_HIP(launch_step_slots(*Dfw, seg, part_fw, 0, 1, 1, 1, st));
     for (int j = 0; j < K; ++j) {
-      if (j > 0) KPM_HIP(launch_step_slots(*Dfw, seg, part_fw, j & 1, (j + 1) & 1, (j + 1) & 1, 0, st));
-      if (j % C == 0)
+      if (j > 0) {
+        if (full) KPM_HIP(launch_step_slots(*Dfw, seg, part_fw, j, j - 1, j + 1, 0, st));
+        else KPM_HIP(launch_step_slots(*Dfw, seg, part_fw, j & 1, (j + 1) & 1, (j + 1) & 1, 0, st));
+      }
+      if (!full && j % C == 0)
         KPM_HIP(hipMemcpyAsync(ckpt + (size_t)(j / C) * 2 * slot_bytes, seg, 2 * slot_bytes,
                                hipMemcpyDeviceToDevice, st));
     }
@@ -1926,9 +1933,16 @@ int run_vjp(const kpm_problem* p, int n, const kpm_params& q, const double* h_ab
     KPM_HIP(hipMemcpyAsync(fal, alpha0, (size_t)TF * 8, hipMemcpyDeviceToDevice, st));   // <v_0, v_0>
     KPM_HIP(launch_step(*Dfw, seg, pf[0], nullptr, 0, fal, fbe, nullptr, 0, 0, 1, st));
     for (int j = 0; j < K; ++j) {
-      if (j > 0)
-        KPM_HIP(launch_step(*Dfw, seg, pf[j & 1], pf[(j - 1) & 1], 2 * TF, fal, fbe, nullptr, j, j & 1, 0, st));
-      if (j % C == 0)
+      if (j > 0) {
+        if (full) {
+          // v_{j+1} into slot j + 1, the dots as in the two-slot ring
+          KPM_HIP(launch_step_slots_dots(*Dfw, seg, pf[j & 1], pf[(j - 1) & 1], 2 * TF, fal, fbe, j, j, j - 1,
+                                         j + 1, st));
+        } else {
+          KPM_HIP(launch_step(*Dfw, seg, pf[j & 1], pf[(j - 1) & 1], 2 * TF, fal, fbe, nullptr, j, j & 1, 0, st));
+        }
+      }
+      if (!full && j % C == 0)
         KPM_HIP(hipMemcpyAsync(ckpt + (size_t)(j / C) * 2 * slot_bytes, seg, 2 * slot_bytes,
                                hipMemcpyDeviceToDevice, st));
     }
@@ -1986,11 +2000,13 @@ int run_vjp(const kpm_problem* p, int n, const kpm_params& q, const double* h_ab
   for (int m = L.nck - 1; m >= 0; --m) {
     const int j0 = m * C;
     const int j1 = std::min(j0 + C, K);
-    KPM_HIP(hipMemcpyAsync(seg, ckpt + (size_t)m * 2 * slot_bytes, 2 * slot_bytes,
-                           hipMemcpyDeviceToDevice, st));
-    const int top = std::min(j1 + 1, K);   // highest v index needed
-    for (int t = 1; j0 + t + 1 <= top; ++t)
-      KPM_HIP(launch_step_slots(*Dfw, seg, part_fw, t, t - 1, t + 1, 0, st));
+    if (!full) {
+      KPM_HIP(hipMemcpyAsync(seg, ckpt + (size_t)m * 2 * slot_bytes, 2 * slot_bytes,
+                             hipMemcpyDeviceToDevice, st));
+      const int top = std::min(j1 + 1, K);   // highest v index needed
+      for (int t = 1; j0 + t + 1 <= top; ++t)
+        KPM_HIP(launch_step_slots(*Dfw, seg, part_fw, t, t - 1, t + 1, 0, st));
+    }
     for (int nn = j1; nn >= j0 + 1; --nn) {
       AdjArgs aa{};
       aa.vseg = seg;

@@ -460,6 +460,11 @@ hipError_t launch_step(const DevicePlan& p, void* vec, double* part_out, const d
 // Same step with explicit buffer slots (x, v_{n-1} in, v_{n+1} out).
 hipError_t launch_step_slots(const DevicePlan& p, void* vec, double* part_out, int x_slot,
                              int yin_slot, int yout_slot, int first, hipStream_t st);
+// A step with explicit slots that also reduces the previous step's dots
+// (as launch_step does in the two-slot ring).
+hipError_t launch_step_slots_dots(const DevicePlan& p, void* vec, double* part_out, const double* part_in,
+                                  int n_jobs, double* alpha, double* beta, int step_add, int x_slot,
+                                  int yin_slot, int yout_slot, hipStream_t st);
 hipError_t launch_reduce(const DevicePlan& p, const double* part, double* dst_a, double* dst_b,
                          hipStream_t st);
 hipError_t launch_init(const DevicePlan& p, void* vec, int mode, int vec_kind, uint64_t seed,

@@ -1925,6 +1925,26 @@ hipError_t launch_step_slots(const DevicePlan& p, void* vec, double* part_out, i
   return launch_step_args(p, a, st);
 }
 
+hipError_t launch_step_slots_dots(const DevicePlan& p, void* vec, double* part_out, const double* part_in,
+                                  int n_jobs, double* alpha, double* beta, int step_add, int x_slot,
+                                  int yin_slot, int yout_slot, hipStream_t st) {
+  StepArgs a = make_step_args(p);
+  a.err = p.err;
+  a.vec = vec;
+  a.vec_lo = p.resid ? reinterpret_cast<int16_t*>(reinterpret_cast<float*>(vec) + p.vec_elems) : nullptr;
+  a.part_out = part_out;
+  a.part_in = part_in;
+  a.n_jobs = n_jobs;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.step_add = step_add;
+  a.x_slot = x_slot;
+  a.yin_slot = yin_slot;
+  a.yout_slot = yout_slot;
+  a.first = 0;
+  return launch_step_args(p, a, st);
+}
+
 hipError_t launch_step_args(const DevicePlan& p, const StepArgs& a, hipStream_t st) {
   if (p.resid && p.block != 3) return hipErrorInvalidValue;   // residual storage: slice kernel only
   if (p.spin) return launch_spin(p, a, st);

@@ -77,6 +77,25 @@ def test_checkpoint_interval_does_not_change_result(kpm):
         assert np.array_equal(got, ref), c
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_thermo_grad_whole_trajectory_equals_checkpointed(kpm, precision):
+    """ckpt_every >= M/2 keeps every v_n of the forward pass (which also
+    gives the moments) resident and recomputes nothing; L and dL/dJ are
+    bit-identical to the checkpointed run's."""
+    secs = W.sectors(W.j1j2_chain(12, 1.0, 0.5))[:3]
+    bl = _bounds(secs)
+    T = np.linspace(0.2, 3.0, 12)
+    wC = np.full(len(T), 0.5)
+    wX = np.full(len(T), 0.25)
+    out = {}
+    for c in (6, 200):
+        L, dJ, _ = kpm.thermo_grad(secs, 120, 3, T, wC, wX, "rademacher", precision, kernel="jackson",
+                                   ckpt_every=c, bounds=bl)
+        out[c] = (L.cpu().numpy(), dJ.cpu().numpy())
+    assert np.array_equal(out[6][0], out[200][0])
+    assert np.array_equal(out[6][1], out[200][1])
+
+
 def test_thermo_grad_matches_oracle_and_finite_differences(kpm):
     cl = W.j1j2_chain(8, 1.0, 0.5)
     secs = W.sectors(cl, only_sz0=True) + [W.Sector(cl, 5, 0)]
