@@ -331,7 +331,10 @@ size_t chebyshev_moments_vjp_workspace_size(const kpm_problem* p, int32_t n,
  * forward (device [n][2]), writes d_dJ (device double, sum_p n_bonds(p)
  * entries, problem after problem in bond order) = dL/dJ_b.  The forward
  * recursion is recomputed from checkpoints taken every ckpt_every steps
- * (even, >= 2). Same seeds and vectors as chebyshev_moments. */
+ * (even, >= 2); with ckpt_every >= M/2 every vector of the forward pass is
+ * kept (M/2 + 2 vectors in d_work) and nothing is recomputed.  The result
+ * does not depend on ckpt_every.  Same seeds and vectors as
+ * chebyshev_moments. */
 int chebyshev_moments_vjp(const kpm_problem* p, int32_t n, const kpm_params* q,
                           const double* d_ab, const double* d_dmu, int32_t ckpt_every,
                           double* d_dJ, void* d_work, size_t work_bytes, void* stream);
