@@ -2174,16 +2174,16 @@ struct FtlmLayout {
 // blocks like the Chebyshev recursion (q->col_block, 0 = the planner's width;
 // width 1 splits a complex vector's Re and Im into separate blocks).
 // FTLM runs float64 vectors.  Without a requested block width, spin-1/2
-// problems take the slice kernel on blocks of 2 columns, 2 sub-tiles per
-// workgroup, 4 high-high rows in flight (ring N=24, 20 columns, 200 steps:
-// 208 ms per call against 301 ms with the planner's block-table default);
-// the planner falls back where no slice plan exists.
+// problems take the slice kernel on blocks of 4 columns, 2 sub-tiles per
+// tile, 4 high-high rows in flight (ring N=24, 20 columns, 200 steps: 195 ms
+// per call, 201 ms on blocks of 2, 301 ms with the planner's block-table
+// default); the planner falls back where no slice plan exists.
 RunShape ftlm_shape(const kpm_params& q, const kpm_problem* p, int n) {
   RunShape s = shape_of(q);
   s.precision = KPM_FP64;
   s.split_vectors = q.col_block == 1;
   if (q.col_block == 0 && !any_spin(p, n)) {
-    s.col_block = 2;
+    s.col_block = 4;
     s.tune.kernel = 5;
     s.tune.block_L = 10;
     s.tune.spt = 2;
