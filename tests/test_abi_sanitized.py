@@ -3,7 +3,8 @@
 planner and launch layer), in a child process with the sanitizer runtime
 preloaded.  Any invalid host memory access or undefined behaviour in the
 argument checks, workspace queries, planner or relabelling search aborts the
-child.  The sanitized library is built here when missing (about 20 s)."""
+child.  The sanitized library is built here when missing or older than any
+of the library's sources (about 40 s)."""
 import os
 import subprocess
 import sys
@@ -15,7 +16,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_abi_suite_under_address_and_ub_sanitizers():
     from paper_2104_13218_amd import build
-    if not os.path.exists(build.LIB_ASAN):
+    srcs = [os.path.join(build.CSRC, f) for f in os.listdir(build.CSRC)]
+    srcs.append(os.path.join(ROOT, "include", "kpm.h"))
+    stale = not os.path.exists(build.LIB_ASAN) or max(os.path.getmtime(f) for f in srcs) > os.path.getmtime(
+        build.LIB_ASAN)
+    if stale:
         try:
             build.build(sanitize=True)
         except RuntimeError as e:
