@@ -966,8 +966,8 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
     if (P.wg_rec.empty() || P.wg_rec.size() > (size_t)INT32_MAX) return KPM_EINVAL;
     D.slice_grid = (int32_t)P.wg_rec.size();
     // waves per workgroup: 2 (default) or 4 share a tile (rows of 16 or 32
-    // bytes staged by direct loads, the tile's rows within the LDS limit),
-    // else 1.  On the 24-site ring (20 float32 columns in blocks of 4) two
+    // bytes staged by direct loads, or float32 + residual rows decoded
+    // through registers; the tile's rows within the LDS limit), else 1.  On the 24-site ring (20 float32 columns in blocks of 4) two
     // waves per tile took 290-297 us per step against 307-311 us for one.
     D.slice_tile_rows = 0;
     for (int32_t r : P.tile_nrows) D.slice_tile_rows = std::max(D.slice_tile_rows, r);
@@ -976,7 +976,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
     if (nw != 2 && nw != 4) nw = 1;
     const size_t rowb = (size_t)D.ld_max * (fp32 ? 4 : 8);
     D.slice_nw = nw;
-    if (nw > 1 && (resid || rowb % 16 != 0 || slice_lds_bytes(D) > (size_t)env_int("KPM_BLOCK_LDS", 64 * 1024)))
+    if (nw > 1 && ((!resid && rowb % 16 != 0) || slice_lds_bytes(D) > (size_t)env_int("KPM_BLOCK_LDS", 64 * 1024)))
       D.slice_nw = 1;
   }
   D.total_cols = col_off;
@@ -1365,15 +1365,17 @@ std::vector<Tune> tune_candidates(const kpm_problem* p, int n, const kpm_params&
     t.col_block = w;
     if (resid) {   // the slice kernel is the only one with this storage
       if (w <= 8)
-        for (int spt : {1, 2, 3})
-          for (int gh : {4, 8}) {
-            Tune b = t;
-            b.kernel = 5;
-            b.block_L = 10;
-            b.spt = spt;
-            b.gather_batch = gh;
-            c.push_back(b);
-          }
+        for (int spt : {2, 1, 3})
+          for (int gh : {4, 8})
+            for (int nw : {2, 1}) {
+              Tune b = t;
+              b.kernel = 5;
+              b.block_L = 10;
+              b.spt = spt;
+              b.gather_batch = gh;
+              b.waves = nw;
+              c.push_back(b);
+            }
       continue;
     }
     if (w <= 8) {

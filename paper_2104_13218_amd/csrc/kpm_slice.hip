@@ -273,6 +273,8 @@ size_t slice_lds_bytes(const DevicePlan& p) {
   const size_t rowb = (size_t)p.ld_max * (p.fp32 ? 4 : 8);
   // nw > 1: one buffer of the largest tile's rows after the zero row, then
   // each wave's partial dots (2 ld doubles per wave)
+  if (p.slice_nw > 1 && p.resid)   // decoded float64 rows, staged through registers
+    return (size_t)kLlMax * 8 + (size_t)(p.slice_tile_rows + 1) * p.ld_max * 8 + (size_t)p.slice_nw * 2 * p.ld_max * 8;
   if (p.slice_nw > 1)
     return (size_t)kLlMax * 8 + rowb + ((size_t)p.slice_tile_rows * rowb + 1023) / 1024 * 1024 +
            (size_t)p.slice_nw * 2 * p.ld_max * 8;
@@ -345,7 +347,7 @@ __global__ __launch_bounds__(64 * NW) void slice_kernel(const StepArgs a) {
   constexpr int RPS = 64 / NCH;          // members per slice
   constexpr uint32_t ROWB = LD * sizeof(T);
   static_assert(NW == 1 || NW == 2 || NW == 4, "waves per workgroup: 1, 2 or 4");
-  static_assert(NW == 1 || (!RES && ROWB % 16u == 0u), "shared tiles: rows staged by direct loads");
+  static_assert(NW == 1 || RES || ROWB % 16u == 0u, "shared tiles: direct loads, or decoded residual rows");
   const int lane = (int)threadIdx.x & 63;
   const int wid = NW > 1 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) : 0;
 
@@ -413,8 +415,9 @@ __global__ __launch_bounds__(64 * NW) void slice_kernel(const StepArgs a) {
   constexpr bool DIRECT = !RES && (ROWB % 16u == 0u);
   double* lco = reinterpret_cast<double*>(smem);
   LT* xs0 = reinterpret_cast<LT*>(lco + kLlMax);
+  // (nw > 1 with rows staged through registers: the zero row and the tile's rows)
   const int buf_elems = DIRECT ? (int)(LD + (((uint32_t)a.blk_lds_rows * ROWB + 1023u) / 1024u) * 1024u / sizeof(T))
-                               : 0;
+                               : (NW > 1 ? LD + a.blk_lds_rows * LD : 0);
   LT* xs1 = xs0 + buf_elems;
   // nw > 1: each wave's partial dots after the one buffer
   double* red = reinterpret_cast<double*>(xs1);
@@ -446,7 +449,31 @@ __global__ __launch_bounds__(64 * NW) void slice_kernel(const StepArgs a) {
     tstart = Bn.start;
     const uint32_t trows = Bl.start + Bl.size - Bn.start;
     tile_ok = R.ng > 0 && Bl.start >= Bn.start && trows <= (uint32_t)a.blk_lds_rows;
-    if (tile_ok) stage_rows(tstart, trows, xs0, (uint32_t)wid * 1024u, (uint32_t)NW * 1024u);
+    if constexpr (DIRECT) {
+      if (tile_ok) stage_rows(tstart, trows, xs0, (uint32_t)wid * 1024u, (uint32_t)NW * 1024u);
+    } else if (tile_ok) {
+      // residual rows, decoded to float64 through registers by all waves
+      const int ne = (int)trows * NCH;
+      const int tid = wid * 64 + lane;
+      for (int e0 = 0; e0 < ne; e0 += 4 * NW * 64) {
+        RowIn<T, CPL, RES> v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t e = (uint32_t)min(e0 + u * NW * 64 + tid, ne - 1);
+          v[u] = load_row<T, CPL, RES, 0>(rx, rxl, (tstart * LD + e * CPL) * (uint32_t)sizeof(T), 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = e0 + u * NW * 64 + tid;
+          if (e < ne) {
+            VecT<LT, CPL> d;
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) d.v[k] = (LT)row_val(v[u], k);
+            *reinterpret_cast<VecT<LT, CPL>*>(xs0 + LD + e * CPL) = d;
+          }
+        }
+      }
+    }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
@@ -501,7 +528,7 @@ __global__ __launch_bounds__(64 * NW) void slice_kernel(const StepArgs a) {
       const cptr<uint32_t> ms = cview(a.meta_mstart) + (int64_t)g * a.meta_mx;
 
       // 1. the block's rows of v_n into LDS rows 1..bsz (direct staging: done)
-      if constexpr (!DIRECT) {
+      if constexpr (!DIRECT && NW == 1) {
         const int ne = bsz * NCH;
         for (int e0 = 0; e0 < ne; e0 += 4 * 64) {
           RowIn<T, CPL, RES> v[4];
@@ -762,7 +789,7 @@ static hipError_t launch_slice_n(const StepArgs& a, size_t lds, int grid, int gh
 // waves per workgroup: 1, or 2 / 4 for rows of 16 or 32 bytes (direct staging)
 template <typename T, int CPL, int NCH, bool RES = false>
 static hipError_t launch_slice_t(const StepArgs& a, size_t lds, int grid, int gh, int wb, int nw, hipStream_t st) {
-  if constexpr (!RES && (NCH * CPL * sizeof(T)) % 16 == 0) {
+  if constexpr (RES || (NCH * CPL * sizeof(T)) % 16 == 0) {
     if (nw == 4) return launch_slice_n<T, CPL, NCH, RES, 4>(a, lds, grid, gh, wb, st);
     if (nw == 2) return launch_slice_n<T, CPL, NCH, RES, 2>(a, lds, grid, gh, wb, st);
   }

@@ -162,12 +162,13 @@ def test_slice_workgroup_mappings_identical(kpm, monkeypatch):
 
 @pytest.mark.parametrize("precision,col_block,env_waves,want", [
     ("fp32", 4, None, 2), ("fp32", 8, "4", 4), ("fp32", 4, "1", 1), ("fp64", 2, None, 2),
-    ("fp32", 2, None, 1), ("fp64", 1, "4", 1), ("fp32r", 4, "2", 1)])
+    ("fp32", 2, None, 1), ("fp64", 1, "4", 1), ("fp32r", 4, None, 2), ("fp32r", 4, "4", 4),
+    ("fp32r", 2, "1", 1)])
 def test_slice_waves_per_tile(kpm, monkeypatch, precision, col_block, env_waves, want):
     """Waves per workgroup as planned: 2 by default, as asked where rows are
-    16 or 32 bytes (float32 blocks of 4 or 8 columns, float64 blocks of 2),
-    1 for narrower rows and for float32 + residual storage; the moments match
-    the oracle either way."""
+    16 or 32 bytes (float32 blocks of 4 or 8 columns, float64 blocks of 2)
+    and for float32 + residual storage (rows decoded through registers), 1
+    for narrower plain rows; the moments match the oracle either way."""
     monkeypatch.setenv("KPM_BLOCK", "3")
     if env_waves:
         monkeypatch.setenv("KPM_SLICE_WAVES", env_waves)
