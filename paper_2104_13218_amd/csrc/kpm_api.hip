@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <future>
 #include <map>
 #include <mutex>
 #include <string>
@@ -497,6 +498,30 @@ void block_tiles(int N, int k, int L, int rows, int blk_max, std::vector<int64_t
 
 // a, b per problem must already be known (scale != nullptr) for the bond
 // values; sizes do not depend on them.
+// The spectral map H' = (H - b)/a (Sec. II) enters a plan only through each
+// problem's diagonal shift -b/a and 1/a and the bond coefficients J/(2a),
+// J/(4a), in input order and in class order.  A plan made at a = 1, b = 0
+// takes its map here; make_plan applies the map the same way.
+void apply_scale(const kpm_problem* p, int n, const double* a_arr, const double* b_arr, Planned& P) {
+  for (int i = 0; i < n; ++i) {
+    const double a = a_arr[i], b = b_arr[i];
+    ProbDev& d = P.probs[i];
+    d.shift = -b / a;
+    d.inv_a = 1.0 / a;
+    for (int k = 0; k < p[i].n_bonds; ++k) {
+      P.boff[d.bond_off + k] = p[i].J[k] / (2.0 * a);
+      P.bzz[d.bond_off + k] = p[i].J[k] / (4.0 * a);
+    }
+  }
+  size_t c = 0;
+  for (int i = 0; i < n; ++i)
+    for (int q = 0; q < p[i].n_bonds; ++q, ++c) {
+      const int b = P.probs[i].bond_off + P.bperm[P.probs[i].bond_off + q];
+      P.coff[c] = P.boff[b];
+      P.czz[c] = P.bzz[b];
+    }
+}
+
 int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_arr,
               const double* b_arr, Planned& P) {
   const int resid = s.precision == KPM_FP32R_STORE;
@@ -561,16 +586,16 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
       build_tables(p[i].n_sites, p[i].n_up, sp, P.tables);
     }
     d.cluster = p[i].cluster;
-    const double a = a_arr ? a_arr[i] : 1.0, b = b_arr ? b_arr[i] : 0.0;
-    d.shift = -b / a;
-    d.inv_a = 1.0 / a;
+    // unit map (a = 1, b = 0) here; apply_scale below sets the given one
+    d.shift = 0.0;
+    d.inv_a = 1.0;
     d.state_off = n_states;
     n_states += d.dim;
     for (int k = 0; k < p[i].n_bonds; ++k) {
       if (spin) P.bmask.push_back((uint32_t)p[i].bond_i[k] | ((uint32_t)p[i].bond_j[k] << 8));
       else P.bmask.push_back((1u << p[i].bond_i[k]) | (1u << p[i].bond_j[k]));
-      P.boff.push_back(p[i].J[k] / (2.0 * a));
-      P.bzz.push_back(p[i].J[k] / (4.0 * a));
+      P.boff.push_back(p[i].J[k] / 2.0);
+      P.bzz.push_back(p[i].J[k] / 4.0);
     }
     bond_total += p[i].n_bonds;
     max_bonds = std::max(max_bonds, p[i].n_bonds);
@@ -1018,6 +1043,7 @@ int make_plan(const kpm_problem* p, int n, const RunShape& s, const double* a_ar
   P.o_czz = put(P.czz.size() * 8);
   P.o_wgt = put(P.wg_rec.size() * sizeof(SliceWg));
   P.bytes = o;
+  if (a_arr && b_arr) apply_scale(p, n, a_arr, b_arr, P);
   return KPM_OK;
 }
 
@@ -1484,6 +1510,18 @@ std::string tune_key(int dev, const kpm_problem* p, int n, const kpm_params& q) 
 
 // The cached or freshly measured launch shape for these problems.  `work`
 // (bytes) is scratch for the trial runs.
+// The launch shape measured earlier for these problems and parameters, if any.
+bool cached_tune(const kpm_problem* p, int n, const kpm_params& q, Tune& out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  const std::string key = tune_key(dev, p, n, q);
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune_cache.find(key);
+  if (it == g_tune_cache.end()) return false;
+  out = it->second;
+  return true;
+}
+
 int get_tune(const kpm_problem* p, int n, const kpm_params& q, const double* a, const double* b,
              unsigned char* work, size_t bytes, hipStream_t st, Tune& out) {
   int dev = 0;
@@ -2299,22 +2337,30 @@ int ed_plan(const kpm_problem* p, int n, int max_dim, EdPlan& E) {
 int moments_on_workspace(const kpm_problem* p, int n, const kpm_params* q, double* d_mu,
                          double* d_ab, unsigned char* work, size_t need, hipStream_t st,
                          bool direct) {
-  // sizes first (plan without scale) to place the Lanczos region
-  Planned P0;
-  int r = make_plan(p, n, shape_of(*q), nullptr, nullptr, P0);
-  if (r != KPM_OK) return r;
-  const MomLayout L0 = moments_layout(P0, n_steps(q->M), 0);
-  std::vector<double> a, b;
-  r = resolve_scale(p, n, *q, work + L0.lz, st, a, b);
-  if (r != KPM_OK) return r;
+  // When the launch shape is known already (no tuning, or measured before),
+  // the host builds the plan at the unit map while the GPU runs the Lanczos
+  // bounds, then applies the map.  The Lanczos region starts the workspace:
+  // every layout of these problems holds at least its bytes, and it is done
+  // (its tridiagonal read back) before anything else is uploaded.
   Tune tn{};
-  if (q->autotune) {
+  const bool known = !q->autotune || cached_tune(p, n, *q, tn);
+  Planned P;
+  std::future<int> planned;
+  if (known)
+    planned = std::async(std::launch::async, [&]() { return make_plan(p, n, shape_of(*q, &tn), nullptr, nullptr, P); });
+  std::vector<double> a, b;
+  int r = resolve_scale(p, n, *q, work, st, a, b);
+  const int rp = known ? planned.get() : KPM_OK;
+  if (r != KPM_OK) return r;
+  if (known) {
+    if (rp != KPM_OK) return rp;
+    apply_scale(p, n, a.data(), b.data(), P);
+  } else {
     r = get_tune(p, n, *q, a.data(), b.data(), work, need, st, tn);
     if (r != KPM_OK) return r;
+    r = make_plan(p, n, shape_of(*q, &tn), a.data(), b.data(), P);
+    if (r != KPM_OK) return r;
   }
-  Planned P;
-  r = make_plan(p, n, shape_of(*q, &tn), a.data(), b.data(), P);
-  if (r != KPM_OK) return r;
   const MomLayout L = moments_layout(P, n_steps(q->M), 0);
   if (L.total > need) return KPM_EWORKSPACE;
   std::vector<unsigned char> staging;
