@@ -50,10 +50,13 @@ __device__ __forceinline__ double wmin(double v, double* sh) {
   return r;
 }
 
+// cos(m pi / (2 Nt)) for the reduced argument m = n (2k - 1) mod 4 Nt.
+__device__ __forceinline__ double reduced_cos(int64_t m, int64_t Nt) {
+  return cos(M_PI * (double)m / (double)(2 * Nt));
+}
 // cos(n pi (k - 1/2) / Nt) for 1-based k, argument reduced exactly.
 __device__ __forceinline__ double node_cos(int64_t n, int64_t k, int64_t Nt) {
-  const int64_t m = (n * (2 * k - 1)) % (4 * Nt);
-  return cos(M_PI * (double)m / (double)(2 * Nt));
+  return reduced_cos((n * (2 * k - 1)) % (4 * Nt), Nt);
 }
 
 __device__ __forceinline__ double node_x(int64_t k, int64_t Nt) {
@@ -79,29 +82,60 @@ hipError_t launch_kernel_coef(int M, int kernel, double* g, hipStream_t st) {
   return hipGetLastError();
 }
 
-// gamma[p][k-1], one thread per node, coefficients staged through LDS.
+// gamma[p][k-1], one wave per node.  Without damping the weights of the
+// lowest nodes are small differences of large terms, so the sum is compensated
+// (the Dot2 scheme of Ogita, Rump and Oishi, "Accurate sum and dot product",
+// SIAM J. Sci. Comput. 26 (2005)): each product's rounding error from an fma,
+// each addition's from TwoSum, carried in a second sum; lane l takes the terms
+// n = l, l + 64, ... in order, then the lanes' (sum, error) pairs combine in a
+// fixed butterfly (lane 0's order).  The reduced cosine argument
+// m = n (2k - 1) mod 4 Nt advances by the reduced stride each term, exactly as
+// the direct reduction gives it.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
 __global__ __launch_bounds__(kThreads) void gamma_kernel(int M, int Nt, const double* g,
                                                          const double* mu, double* gamma) {
-  __shared__ double cs[kThreads];
+#pragma clang fp contract(off)
   const int p = blockIdx.y;
-  const int k = blockIdx.x * kThreads + threadIdx.x + 1;
-  double acc = 0.0;
-  for (int n0 = 0; n0 < M; n0 += kThreads) {
-    const int n = n0 + threadIdx.x;
-    __syncthreads();
-    cs[threadIdx.x] = n < M ? g[n] * mu[(int64_t)p * M + n] * (n == 0 ? 1.0 : 2.0) : 0.0;
-    __syncthreads();
-    if (k <= Nt) {
-      const int lim = min(kThreads, M - n0);
-      for (int j = 0; j < lim; ++j) acc = fma(cs[j], node_cos(n0 + j, k, Nt), acc);
-    }
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6) + 1;
+  if (k > Nt) return;   // k is the same across the wave
+  const double* mp = mu + (int64_t)p * M;
+  const int64_t period = 4 * (int64_t)Nt;
+  const int64_t stride = (64 * (2 * (int64_t)k - 1)) % period;
+  int64_t m = ((int64_t)lane * (2 * (int64_t)k - 1)) % period;
+  double sum = 0.0, err = 0.0;
+  for (int n = lane; n < M; n += 64) {
+    const double cn = g[n] * mp[n] * (n == 0 ? 1.0 : 2.0);
+    const double cv = reduced_cos(m, Nt);
+    const double x = cn * cv;
+    const double ex = fma(cn, cv, -x);
+    double e;
+    two_sum(sum, x, sum, e);
+    err += e + ex;
+    m += stride;
+    if (m >= period) m -= period;
   }
-  if (k <= Nt) gamma[(int64_t)p * Nt + (k - 1)] = acc;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double s2 = __shfl_xor(sum, off, 64);
+    const double e2 = __shfl_xor(err, off, 64);
+    double e;
+    two_sum(sum, s2, sum, e);
+    err += e2 + e;
+  }
+  if (lane == 0) gamma[(int64_t)p * Nt + (k - 1)] = sum + err;
 }
 
 hipError_t launch_gamma(int n_probs, int M, int n_nodes, const double* g, const double* mu,
                         double* gamma, hipStream_t st) {
-  dim3 grid((n_nodes + kThreads - 1) / kThreads, n_probs);
+  constexpr int kNodesPerGroup = kThreads / 64;
+  dim3 grid((n_nodes + kNodesPerGroup - 1) / kNodesPerGroup, n_probs);
   hipLaunchKernelGGL(gamma_kernel, grid, dim3(kThreads), 0, st, M, n_nodes, g, mu, gamma);
   return hipGetLastError();
 }

@@ -130,10 +130,12 @@ def test_ring24_thermo_on_identical_moments(kpm, kernel):
     thermodynamics on the 200-point grid in [0.01, 10]: <= 5e-12 (relative for
     ln Z and E, peak-normalised for C and chi) on T >= 0.25, <= 1e-6 on
     T >= T_phys.  The oracle sums the 2000-term DOS weights and the Boltzmann
-    sums exactly rounded, the library in a fixed float64 order with its own
-    node cosines; at low T the thermodynamics amplify those last-bit
-    differences of the weights of the lowest nodes (measured: ~1e-12 from
-    T ~ 0.1-0.4, up to 3e-7 near T_phys)."""
+    sums exactly rounded, the library the weights by a compensated sum (near
+    exact rounding) and the Boltzmann sums in a fixed float64 order, with its
+    own node cosines; at low T the thermodynamics amplify the remaining
+    last-bit differences of the weights of the lowest nodes (measured:
+    <= 2.3e-12 on T >= 0.25; near T_phys up to 5e-8 with the Jackson kernel,
+    4.6e-7 without)."""
     secs = W.sectors(W.ring(24))
     mu = torch.tensor(_golden("ring24_all_fp64_M2000.txt").T.copy(), device="cuda")
     gb = _golden_bounds()
