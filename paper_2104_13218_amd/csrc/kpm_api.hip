@@ -12,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <system_error>
 #include <vector>
 
 #include "kpm.h"
@@ -2343,11 +2344,17 @@ int moments_on_workspace(const kpm_problem* p, int n, const kpm_params* q, doubl
   // every layout of these problems holds at least its bytes, and it is done
   // (its tridiagonal read back) before anything else is uploaded.
   Tune tn{};
-  const bool known = !q->autotune || cached_tune(p, n, *q, tn);
+  bool known = !q->autotune || cached_tune(p, n, *q, tn);
   Planned P;
   std::future<int> planned;
-  if (known)
-    planned = std::async(std::launch::async, [&]() { return make_plan(p, n, shape_of(*q, &tn), nullptr, nullptr, P); });
+  if (known) {
+    try {
+      planned = std::async(std::launch::async,
+                           [&]() { return make_plan(p, n, shape_of(*q, &tn), nullptr, nullptr, P); });
+    } catch (const std::system_error&) {
+      known = false;   // no thread to be had: plan after the bounds
+    }
+  }
   std::vector<double> a, b;
   int r = resolve_scale(p, n, *q, work, st, a, b);
   const int rp = known ? planned.get() : KPM_OK;
@@ -2356,8 +2363,10 @@ int moments_on_workspace(const kpm_problem* p, int n, const kpm_params* q, doubl
     if (rp != KPM_OK) return rp;
     apply_scale(p, n, a.data(), b.data(), P);
   } else {
-    r = get_tune(p, n, *q, a.data(), b.data(), work, need, st, tn);
-    if (r != KPM_OK) return r;
+    if (q->autotune) {
+      r = get_tune(p, n, *q, a.data(), b.data(), work, need, st, tn);
+      if (r != KPM_OK) return r;
+    }
     r = make_plan(p, n, shape_of(*q, &tn), a.data(), b.data(), P);
     if (r != KPM_OK) return r;
   }
