@@ -15,7 +15,9 @@
  * Conventions
  *  - Every function returns an int status: KPM_OK (0) or a negative KPM_E*
  *    code; kpm_strerror() names it.  On error the outputs are unspecified,
- *    nothing is leaked and the library stays usable.
+ *    nothing is leaked and the library stays usable.  No C++ exception leaves
+ *    the library: a failed host allocation is KPM_ENOMEM, any other internal
+ *    failure KPM_EDEVICE, and a *_workspace_size() query that fails returns 0.
  *  - Problem descriptions (kpm_problem, kpm_params, bond arrays, and host
  *    arrays marked "host") are read during the call only.
  *  - Arrays marked "device" are device pointers in the current HIP device's
@@ -45,7 +47,7 @@ extern "C" {
 /* ---- status codes ------------------------------------------------------- */
 #define KPM_OK 0
 #define KPM_EINVAL (-1)     /* invalid argument (bad bond, n_up, M, ...) */
-#define KPM_ENOMEM (-2)     /* device allocation failed */
+#define KPM_ENOMEM (-2)     /* device (or host) allocation failed */
 #define KPM_EDEVICE (-3)    /* HIP runtime error */
 #define KPM_EBOUNDS (-4)    /* |mu_n| > mu_0 (1 + 1e-6) for some vector: the
                                spectral bounds do not enclose the spectrum */

@@ -11,6 +11,7 @@
 #include <future>
 #include <map>
 #include <mutex>
+#include <new>
 #include <string>
 #include <system_error>
 #include <vector>
@@ -2410,6 +2411,28 @@ int scratch_address(int dev, unsigned char** out) {
   return KPM_OK;
 }
 
+// No C++ exception leaves the library (the C ABI has no way to carry one): a
+// failed host allocation, here or in the planning thread, reports KPM_ENOMEM,
+// any other exception KPM_EDEVICE; a size query reports 0.
+template <typename F>
+int guarded(F&& f) noexcept {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return KPM_ENOMEM;
+  } catch (...) {
+    return KPM_EDEVICE;
+  }
+}
+template <typename F>
+size_t guarded_size(F&& f) noexcept {
+  try {
+    return f();
+  } catch (...) {
+    return 0;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -2418,7 +2441,7 @@ const char* kpm_strerror(int code) {
   switch (code) {
     case KPM_OK: return "ok";
     case KPM_EINVAL: return "invalid argument";
-    case KPM_ENOMEM: return "device allocation failed";
+    case KPM_ENOMEM: return "allocation failed";
     case KPM_EDEVICE: return "HIP runtime error";
     case KPM_EBOUNDS: return "spectral bounds do not enclose the spectrum (|mu_n| > mu_0)";
     case KPM_EWORKSPACE: return "workspace too small";
@@ -2428,11 +2451,13 @@ const char* kpm_strerror(int code) {
 }
 
 int kpm_site_relabel(const kpm_problem* p, int32_t L, int32_t* h_perm) {
-  if (!p || !h_perm || check_problem(*p) != KPM_OK || two_s_of(*p) > 1 || L < 1 || L > 16) return KPM_EINVAL;
-  std::vector<uint8_t> perm;
-  const bool moved = choose_relabel(*p, std::min<int>(L, p->n_sites), perm);
-  for (int i = 0; i < p->n_sites; ++i) h_perm[i] = moved ? perm[i] : i;
-  return moved ? 1 : 0;
+  return guarded([&]() -> int {
+    if (!p || !h_perm || check_problem(*p) != KPM_OK || two_s_of(*p) > 1 || L < 1 || L > 16) return KPM_EINVAL;
+    std::vector<uint8_t> perm;
+    const bool moved = choose_relabel(*p, std::min<int>(L, p->n_sites), perm);
+    for (int i = 0; i < p->n_sites; ++i) h_perm[i] = moved ? perm[i] : i;
+    return moved ? 1 : 0;
+  });
 }
 
 uint64_t kpm_sector_dim(int32_t n_sites, int32_t n_up) {
@@ -2441,139 +2466,155 @@ uint64_t kpm_sector_dim(int32_t n_sites, int32_t n_up) {
 }
 
 int kpm_autotune_reset(void) {
-  std::lock_guard<std::mutex> lock(g_tune_mu);
-  g_tune_cache.clear();
-  return KPM_OK;
+  return guarded([&]() -> int {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache.clear();
+    return KPM_OK;
+  });
 }
 
 int kpm_last_run_stats(kpm_run_stats* out) {
-  if (!out) return KPM_EINVAL;
-  *out = g_stats;
-  return KPM_OK;
+  return guarded([&]() -> int {
+    if (!out) return KPM_EINVAL;
+    *out = g_stats;
+    return KPM_OK;
+  });
 }
 
 int kpm_sector_states(int32_t n_sites, int32_t n_up, uint32_t* d_states, void* stream) {
-  if (n_sites < 1 || n_sites > 32 || n_up < 0 || n_up > n_sites || !d_states) return KPM_EINVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  StreamSync guard{st};
-  const int64_t dim = (int64_t)binom64(n_sites, n_up);
-  const std::vector<uint32_t> bt = binom_table();
-  DevBuf buf;
-  int r = buf.alloc(bt.size() * 4);
-  if (r != KPM_OK) return r;
-  KPM_HIP(hipMemcpyAsync(buf.p, bt.data(), bt.size() * 4, hipMemcpyHostToDevice, st));
-  KPM_HIP(launch_states(n_sites, n_up, static_cast<uint32_t*>(buf.p), d_states, dim, st));
-  KPM_HIP(hipStreamSynchronize(st));
-  return KPM_OK;
+  return guarded([&]() -> int {
+    if (n_sites < 1 || n_sites > 32 || n_up < 0 || n_up > n_sites || !d_states) return KPM_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamSync guard{st};
+    const int64_t dim = (int64_t)binom64(n_sites, n_up);
+    const std::vector<uint32_t> bt = binom_table();
+    DevBuf buf;
+    int r = buf.alloc(bt.size() * 4);
+    if (r != KPM_OK) return r;
+    KPM_HIP(hipMemcpyAsync(buf.p, bt.data(), bt.size() * 4, hipMemcpyHostToDevice, st));
+    KPM_HIP(launch_states(n_sites, n_up, static_cast<uint32_t*>(buf.p), d_states, dim, st));
+    KPM_HIP(hipStreamSynchronize(st));
+    return KPM_OK;
+  });
 }
 
 int kpm_sector_matrix(const kpm_problem* p, int64_t row0, int64_t nrows, int32_t max_nb,
                       uint32_t* d_cols, int32_t* d_bond, int32_t* d_cnt, double* d_diag,
                       void* stream) {
-  if (!p || check_problem(*p) != KPM_OK || two_s_of(*p) > 1) return KPM_EINVAL;
-  const int64_t dim = (int64_t)binom64(p->n_sites, p->n_up);
-  if (row0 < 0 || nrows < 0 || row0 + nrows > dim || max_nb < p->n_bonds || max_nb < 1)
-    return KPM_EINVAL;
-  if (nrows == 0) return KPM_OK;
-  if (!d_cols || !d_bond || !d_cnt || !d_diag) return KPM_EINVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  StreamSync guard{st};
-  RunShape s;
-  s.precision = KPM_FP64;
-  s.col_block = 1;
-  s.allow_row = false;
-  Planned P;
-  const double one = 1.0, zero = 0.0;
-  int r = make_plan(p, 1, s, &one, &zero, P);
-  if (r != KPM_OK) return r;
-  DevBuf buf;
-  r = buf.alloc(P.bytes);
-  if (r != KPM_OK) return r;
-  std::vector<unsigned char> staging;
-  r = upload_plan(P, static_cast<unsigned char*>(buf.p), staging, st);
-  if (r != KPM_OK) return r;
-  const DevicePlan& D = P.plan;
-  MatrixArgs a{};
-  a.probs = D.probs;
-  a.tables = D.tables;
-  a.bmask = D.bmask;
-  a.boff = D.boff;
-  a.bzz = D.bzz;
-  a.binom = D.binom;
-  a.row0 = row0;
-  a.nrows = nrows;
-  a.max_nb = max_nb;
-  a.lds_tab = D.lds_tab;
-  a.lds_bonds = D.lds_bonds;
-  a.sub_rows = D.sub_rows;
-  a.lds_nb = D.lds_nb;
-  a.cols = d_cols;
-  a.bond = d_bond;
-  a.cnt = d_cnt;
-  a.diag = d_diag;
-  const int64_t grid = (nrows + D.sub_rows - 1) / D.sub_rows;
-  if (grid > (1LL << 30)) return KPM_EINVAL;
-  KPM_HIP(launch_matrix(a, step_lds_bytes(D), (int)grid, st));
-  KPM_HIP(hipStreamSynchronize(st));
-  return KPM_OK;
+  return guarded([&]() -> int {
+    if (!p || check_problem(*p) != KPM_OK || two_s_of(*p) > 1) return KPM_EINVAL;
+    const int64_t dim = (int64_t)binom64(p->n_sites, p->n_up);
+    if (row0 < 0 || nrows < 0 || row0 + nrows > dim || max_nb < p->n_bonds || max_nb < 1)
+      return KPM_EINVAL;
+    if (nrows == 0) return KPM_OK;
+    if (!d_cols || !d_bond || !d_cnt || !d_diag) return KPM_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamSync guard{st};
+    RunShape s;
+    s.precision = KPM_FP64;
+    s.col_block = 1;
+    s.allow_row = false;
+    Planned P;
+    const double one = 1.0, zero = 0.0;
+    int r = make_plan(p, 1, s, &one, &zero, P);
+    if (r != KPM_OK) return r;
+    DevBuf buf;
+    r = buf.alloc(P.bytes);
+    if (r != KPM_OK) return r;
+    std::vector<unsigned char> staging;
+    r = upload_plan(P, static_cast<unsigned char*>(buf.p), staging, st);
+    if (r != KPM_OK) return r;
+    const DevicePlan& D = P.plan;
+    MatrixArgs a{};
+    a.probs = D.probs;
+    a.tables = D.tables;
+    a.bmask = D.bmask;
+    a.boff = D.boff;
+    a.bzz = D.bzz;
+    a.binom = D.binom;
+    a.row0 = row0;
+    a.nrows = nrows;
+    a.max_nb = max_nb;
+    a.lds_tab = D.lds_tab;
+    a.lds_bonds = D.lds_bonds;
+    a.sub_rows = D.sub_rows;
+    a.lds_nb = D.lds_nb;
+    a.cols = d_cols;
+    a.bond = d_bond;
+    a.cnt = d_cnt;
+    a.diag = d_diag;
+    const int64_t grid = (nrows + D.sub_rows - 1) / D.sub_rows;
+    if (grid > (1LL << 30)) return KPM_EINVAL;
+    KPM_HIP(launch_matrix(a, step_lds_bytes(D), (int)grid, st));
+    KPM_HIP(hipStreamSynchronize(st));
+    return KPM_OK;
+  });
 }
 
 int kpm_spectral_bounds(const kpm_problem* p, int32_t n, int32_t steps, double margin,
                         uint64_t seed, double* e_lo_hi, void* stream) {
-  if (check_problems(p, n) != KPM_OK || steps < 1 || !(margin >= 0.0) || !e_lo_hi)
-    return KPM_EINVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  StreamSync guard{st};
-  DevBuf buf;
-  int r = buf.alloc(lanczos_bytes(p, n, steps));
-  if (r != KPM_OK) return r;
-  return run_lanczos(p, n, steps, margin, seed, e_lo_hi, static_cast<unsigned char*>(buf.p), st);
+  return guarded([&]() -> int {
+    if (check_problems(p, n) != KPM_OK || steps < 1 || !(margin >= 0.0) || !e_lo_hi)
+      return KPM_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamSync guard{st};
+    DevBuf buf;
+    int r = buf.alloc(lanczos_bytes(p, n, steps));
+    if (r != KPM_OK) return r;
+    return run_lanczos(p, n, steps, margin, seed, e_lo_hi, static_cast<unsigned char*>(buf.p), st);
+  });
 }
 
 size_t chebyshev_moments_workspace_size(const kpm_problem* p, int32_t n, const kpm_params* q) {
-  if (check_problems(p, n) != KPM_OK || !q || check_params_moments(*q) != KPM_OK) return 0;
-  return moments_workspace(p, n, *q);
+  return guarded_size([&]() -> size_t {
+    if (check_problems(p, n) != KPM_OK || !q || check_params_moments(*q) != KPM_OK) return 0;
+    return moments_workspace(p, n, *q);
+  });
 }
 
 int chebyshev_moments(const kpm_problem* p, int32_t n, const kpm_params* q, double* d_mu,
                       double* d_ab, void* d_work, size_t work_bytes, void* stream) {
-  int r = check_problems(p, n);
-  if (r != KPM_OK) return r;
-  if (!q || check_params_moments(*q) != KPM_OK || !d_mu) return KPM_EINVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  StreamSync guard{st};
-  const size_t need = moments_workspace(p, n, *q);
-  if (need == 0) return KPM_EINVAL;
-  DevBuf own;
-  unsigned char* work = static_cast<unsigned char*>(d_work);
-  if (!work) {
-    r = own.alloc(need);
+  return guarded([&]() -> int {
+    int r = check_problems(p, n);
     if (r != KPM_OK) return r;
-    work = static_cast<unsigned char*>(own.p);
-  } else if (work_bytes < need) {
-    return KPM_EWORKSPACE;
-  }
-  return moments_on_workspace(p, n, q, d_mu, d_ab, work, need, st, false);
+    if (!q || check_params_moments(*q) != KPM_OK || !d_mu) return KPM_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamSync guard{st};
+    const size_t need = moments_workspace(p, n, *q);
+    if (need == 0) return KPM_EINVAL;
+    DevBuf own;
+    unsigned char* work = static_cast<unsigned char*>(d_work);
+    if (!work) {
+      r = own.alloc(need);
+      if (r != KPM_OK) return r;
+      work = static_cast<unsigned char*>(own.p);
+    } else if (work_bytes < need) {
+      return KPM_EWORKSPACE;
+    }
+    return moments_on_workspace(p, n, q, d_mu, d_ab, work, need, st, false);
+  });
 }
 
 int chebyshev_moments_noalloc(const kpm_problem* p, int32_t n, const kpm_params* q, double* d_mu,
                               double* d_ab, void* stream) {
-  int r = check_problems(p, n);
-  if (r != KPM_OK) return r;
-  if (!q || check_params_moments(*q) != KPM_OK || !d_mu || q->autotune != 0) return KPM_EINVAL;
-  const size_t need = moments_workspace(p, n, *q);
-  if (need == 0) return KPM_EINVAL;
-  if (need > KPM_NOALLOC_MAX_BYTES) return KPM_ETOOLARGE;
-  int dev = 0;
-  KPM_HIP(hipGetDevice(&dev));
-  if (dev < 0 || dev >= kMaxDevices) return KPM_EDEVICE;
-  std::lock_guard<std::mutex> lock(g_scratch_mu[dev]);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  StreamSync guard{st};  // released before the lock: the array is idle when the next call starts
-  unsigned char* work = nullptr;
-  r = scratch_address(dev, &work);
-  if (r != KPM_OK) return r;
-  return moments_on_workspace(p, n, q, d_mu, d_ab, work, need, st, true);
+  return guarded([&]() -> int {
+    int r = check_problems(p, n);
+    if (r != KPM_OK) return r;
+    if (!q || check_params_moments(*q) != KPM_OK || !d_mu || q->autotune != 0) return KPM_EINVAL;
+    const size_t need = moments_workspace(p, n, *q);
+    if (need == 0) return KPM_EINVAL;
+    if (need > KPM_NOALLOC_MAX_BYTES) return KPM_ETOOLARGE;
+    int dev = 0;
+    KPM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return KPM_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu[dev]);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamSync guard{st};  // released before the lock: the array is idle when the next call starts
+    unsigned char* work = nullptr;
+    r = scratch_address(dev, &work);
+    if (r != KPM_OK) return r;
+    return moments_on_workspace(p, n, q, d_mu, d_ab, work, need, st, true);
+  });
 }
 
 static kpm_params vectors_params(const kpm_params& q, int32_t n_vec) {
@@ -2583,507 +2624,539 @@ static kpm_params vectors_params(const kpm_params& q, int32_t n_vec) {
 }
 
 size_t chebyshev_vectors_workspace_size(const kpm_problem* p, const kpm_params* q, int32_t n_vec) {
-  if (check_problems(p, 1) != KPM_OK || !q || n_vec < 0) return 0;
-  const kpm_params q2 = vectors_params(*q, n_vec);
-  if (check_params(q2) != KPM_OK) return 0;
-  return moments_workspace(p, 1, q2);
+  return guarded_size([&]() -> size_t {
+    if (check_problems(p, 1) != KPM_OK || !q || n_vec < 0) return 0;
+    const kpm_params q2 = vectors_params(*q, n_vec);
+    if (check_params(q2) != KPM_OK) return 0;
+    return moments_workspace(p, 1, q2);
+  });
 }
 
 int chebyshev_vectors(const kpm_problem* p, const kpm_params* q, int32_t n_vec, void* d_out,
                       double* d_ab, void* d_work, size_t work_bytes, void* stream) {
-  int r = check_problems(p, 1);
-  if (r != KPM_OK) return r;
-  if (!q || n_vec < 0 || !d_out) return KPM_EINVAL;
-  const kpm_params q2 = vectors_params(*q, n_vec);
-  if (check_params(q2) != KPM_OK) return KPM_EINVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  StreamSync guard{st};
-  const size_t need = moments_workspace(p, 1, q2);
-  if (need == 0) return KPM_EINVAL;
-  DevBuf own;
-  unsigned char* work = static_cast<unsigned char*>(d_work);
-  if (!work) {
-    r = own.alloc(need);
+  return guarded([&]() -> int {
+    int r = check_problems(p, 1);
     if (r != KPM_OK) return r;
-    work = static_cast<unsigned char*>(own.p);
-  } else if (work_bytes < need) {
-    return KPM_EWORKSPACE;
-  }
-  Planned P0;
-  r = make_plan(p, 1, shape_of(q2), nullptr, nullptr, P0);
-  if (r != KPM_OK) return r;
-  const MomLayout L0 = moments_layout(P0, n_steps(q2.M), 0);
-  std::vector<double> a, b;
-  r = resolve_scale(p, 1, q2, work + L0.lz, st, a, b);
-  if (r != KPM_OK) return r;
-  Planned P;
-  r = make_plan(p, 1, shape_of(q2), a.data(), b.data(), P);
-  if (r != KPM_OK) return r;
-  const MomLayout L = moments_layout(P, n_steps(q2.M), 0);
-  std::vector<unsigned char> staging;
-  r = upload_plan(P, work + L.plan, staging, st);
-  if (r != KPM_OK) return r;
-  const double ab[2] = {a[0], b[0]};
-  if (d_ab) KPM_HIP(hipMemcpyAsync(d_ab, ab, sizeof(ab), hipMemcpyHostToDevice, st));
-  return run_vectors(P, L, work, q2, n_vec, d_out, st);
+    if (!q || n_vec < 0 || !d_out) return KPM_EINVAL;
+    const kpm_params q2 = vectors_params(*q, n_vec);
+    if (check_params(q2) != KPM_OK) return KPM_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamSync guard{st};
+    const size_t need = moments_workspace(p, 1, q2);
+    if (need == 0) return KPM_EINVAL;
+    DevBuf own;
+    unsigned char* work = static_cast<unsigned char*>(d_work);
+    if (!work) {
+      r = own.alloc(need);
+      if (r != KPM_OK) return r;
+      work = static_cast<unsigned char*>(own.p);
+    } else if (work_bytes < need) {
+      return KPM_EWORKSPACE;
+    }
+    Planned P0;
+    r = make_plan(p, 1, shape_of(q2), nullptr, nullptr, P0);
+    if (r != KPM_OK) return r;
+    const MomLayout L0 = moments_layout(P0, n_steps(q2.M), 0);
+    std::vector<double> a, b;
+    r = resolve_scale(p, 1, q2, work + L0.lz, st, a, b);
+    if (r != KPM_OK) return r;
+    Planned P;
+    r = make_plan(p, 1, shape_of(q2), a.data(), b.data(), P);
+    if (r != KPM_OK) return r;
+    const MomLayout L = moments_layout(P, n_steps(q2.M), 0);
+    std::vector<unsigned char> staging;
+    r = upload_plan(P, work + L.plan, staging, st);
+    if (r != KPM_OK) return r;
+    const double ab[2] = {a[0], b[0]};
+    if (d_ab) KPM_HIP(hipMemcpyAsync(d_ab, ab, sizeof(ab), hipMemcpyHostToDevice, st));
+    return run_vectors(P, L, work, q2, n_vec, d_out, st);
+  });
 }
 
 int kpm_thermo(const double* d_mu, const double* d_ab, const kpm_problem* p, int32_t n,
                int32_t M, int32_t kernel, int32_t n_nodes, const double* d_T, int32_t n_T,
                double* d_lnZ, double* d_E, double* d_C, double* d_chi, uint8_t* d_znonpos,
                void* stream) {
-  if (!d_lnZ || !d_E || !d_C || !d_chi) return KPM_EINVAL;
-  ThermoDev TD;
-  std::vector<ThermoProb> tp;
-  int nc = 0;
-  return thermo_forward(d_mu, d_ab, p, n, M, kernel, n_nodes, d_T, n_T, d_lnZ, d_E, d_C, d_chi,
-                        d_znonpos, static_cast<hipStream_t>(stream), TD, tp, nc, false);
+  return guarded([&]() -> int {
+    if (!d_lnZ || !d_E || !d_C || !d_chi) return KPM_EINVAL;
+    ThermoDev TD;
+    std::vector<ThermoProb> tp;
+    int nc = 0;
+    return thermo_forward(d_mu, d_ab, p, n, M, kernel, n_nodes, d_T, n_T, d_lnZ, d_E, d_C, d_chi,
+                          d_znonpos, static_cast<hipStream_t>(stream), TD, tp, nc, false);
+  });
 }
 
 int kpm_thermo_field(const double* d_mu, const double* d_ab, const kpm_problem* p, int32_t n,
                      int32_t M, int32_t kernel, int32_t n_nodes, const double* d_T,
                      const double* d_h, int32_t n_pts, double* d_lnZ, double* d_E, double* d_C,
                      double* d_chi, double* d_mag, uint8_t* d_znonpos, void* stream) {
-  if (!d_h || !d_lnZ || !d_E || !d_C || !d_chi) return KPM_EINVAL;
-  ThermoDev TD;
-  std::vector<ThermoProb> tp;
-  int nc = 0;
-  return thermo_forward(d_mu, d_ab, p, n, M, kernel, n_nodes, d_T, n_pts, d_lnZ, d_E, d_C, d_chi,
-                        d_znonpos, static_cast<hipStream_t>(stream), TD, tp, nc, false, d_h, d_mag);
+  return guarded([&]() -> int {
+    if (!d_h || !d_lnZ || !d_E || !d_C || !d_chi) return KPM_EINVAL;
+    ThermoDev TD;
+    std::vector<ThermoProb> tp;
+    int nc = 0;
+    return thermo_forward(d_mu, d_ab, p, n, M, kernel, n_nodes, d_T, n_pts, d_lnZ, d_E, d_C, d_chi,
+                          d_znonpos, static_cast<hipStream_t>(stream), TD, tp, nc, false, d_h, d_mag);
+  });
 }
 
 int kpm_thermo_vjp(const double* d_mu, const double* d_ab, const kpm_problem* p, int32_t n,
                    int32_t M, int32_t kernel, int32_t n_nodes, const double* d_T, int32_t n_T,
                    const double* d_wC, const double* d_wchi, double* d_lambda, void* stream) {
-  if (!d_wC || !d_wchi || !d_lambda) return KPM_EINVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  std::vector<ThermoProb> tp;
-  std::vector<int32_t> start, list;
-  int nc = 0;
-  if (thermo_meta(p, n, tp, start, list, nc) != KPM_OK) return KPM_EINVAL;
-  StreamSync guard{st};
-  DevBuf outs;
-  int r = outs.alloc((size_t)4 * nc * n_T * 8);
-  if (r != KPM_OK) return r;
-  double* o = static_cast<double*>(outs.p);
-  const size_t m = (size_t)nc * n_T;
-  ThermoDev TD;
-  r = thermo_forward(d_mu, d_ab, p, n, M, kernel, n_nodes, d_T, n_T, o, o + m, o + 2 * m, o + 3 * m,
-                     nullptr, st, TD, tp, nc, true);
-  if (r != KPM_OK) return r;
-  ThermoVjpArgs va{};
-  va.tp = TD.tp;
-  va.ab = d_ab;
-  va.stats = TD.stats;
-  va.wC = d_wC;
-  va.wchi = d_wchi;
-  va.g = TD.g;
-  va.node_adj = TD.adj;
-  va.lambda = d_lambda;
-  va.n_probs = n;
-  va.M = M;
-  va.n_nodes = n_nodes ? n_nodes : M;
-  va.n_T = n_T;
-  KPM_HIP(launch_thermo_vjp(va, st));
-  KPM_HIP(hipStreamSynchronize(st));
-  return KPM_OK;
+  return guarded([&]() -> int {
+    if (!d_wC || !d_wchi || !d_lambda) return KPM_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<ThermoProb> tp;
+    std::vector<int32_t> start, list;
+    int nc = 0;
+    if (thermo_meta(p, n, tp, start, list, nc) != KPM_OK) return KPM_EINVAL;
+    StreamSync guard{st};
+    DevBuf outs;
+    int r = outs.alloc((size_t)4 * nc * n_T * 8);
+    if (r != KPM_OK) return r;
+    double* o = static_cast<double*>(outs.p);
+    const size_t m = (size_t)nc * n_T;
+    ThermoDev TD;
+    r = thermo_forward(d_mu, d_ab, p, n, M, kernel, n_nodes, d_T, n_T, o, o + m, o + 2 * m, o + 3 * m,
+                       nullptr, st, TD, tp, nc, true);
+    if (r != KPM_OK) return r;
+    ThermoVjpArgs va{};
+    va.tp = TD.tp;
+    va.ab = d_ab;
+    va.stats = TD.stats;
+    va.wC = d_wC;
+    va.wchi = d_wchi;
+    va.g = TD.g;
+    va.node_adj = TD.adj;
+    va.lambda = d_lambda;
+    va.n_probs = n;
+    va.M = M;
+    va.n_nodes = n_nodes ? n_nodes : M;
+    va.n_T = n_T;
+    KPM_HIP(launch_thermo_vjp(va, st));
+    KPM_HIP(hipStreamSynchronize(st));
+    return KPM_OK;
+  });
 }
 
 size_t chebyshev_moments_vjp_workspace_size(const kpm_problem* p, int32_t n, const kpm_params* q,
                                             int32_t ckpt_every) {
-  if (check_problems(p, n) != KPM_OK || !q || check_params(*q) != KPM_OK || ckpt_every < 2)
-    return 0;
-  return vjp_workspace(p, n, *q, ckpt_every);
+  return guarded_size([&]() -> size_t {
+    if (check_problems(p, n) != KPM_OK || !q || check_params(*q) != KPM_OK || ckpt_every < 2)
+      return 0;
+    return vjp_workspace(p, n, *q, ckpt_every);
+  });
 }
 
 int chebyshev_moments_vjp(const kpm_problem* p, int32_t n, const kpm_params* q,
                           const double* d_ab, const double* d_dmu, int32_t ckpt_every,
                           double* d_dJ, void* d_work, size_t work_bytes, void* stream) {
-  int r = check_problems(p, n);
-  if (r != KPM_OK) return r;
-  if (!q || check_params(*q) != KPM_OK || !d_ab || !d_dmu || !d_dJ || ckpt_every < 2)
-    return KPM_EINVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  StreamSync guard{st};
-  const size_t need = vjp_workspace(p, n, *q, ckpt_every);
-  if (need == 0) return KPM_EINVAL;
-  DevBuf own;
-  unsigned char* work = static_cast<unsigned char*>(d_work);
-  if (!work) {
-    r = own.alloc(need);
+  return guarded([&]() -> int {
+    int r = check_problems(p, n);
     if (r != KPM_OK) return r;
-    work = static_cast<unsigned char*>(own.p);
-  } else if (work_bytes < need) {
-    return KPM_EWORKSPACE;
-  }
-  std::vector<double> h_ab(2 * n);
-  KPM_HIP(hipMemcpyAsync(h_ab.data(), d_ab, h_ab.size() * 8, hipMemcpyDeviceToHost, st));
-  KPM_HIP(hipStreamSynchronize(st));
-  return run_vjp(p, n, *q, h_ab.data(), d_dmu, ckpt_every, d_dJ, work, st);
+    if (!q || check_params(*q) != KPM_OK || !d_ab || !d_dmu || !d_dJ || ckpt_every < 2)
+      return KPM_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamSync guard{st};
+    const size_t need = vjp_workspace(p, n, *q, ckpt_every);
+    if (need == 0) return KPM_EINVAL;
+    DevBuf own;
+    unsigned char* work = static_cast<unsigned char*>(d_work);
+    if (!work) {
+      r = own.alloc(need);
+      if (r != KPM_OK) return r;
+      work = static_cast<unsigned char*>(own.p);
+    } else if (work_bytes < need) {
+      return KPM_EWORKSPACE;
+    }
+    std::vector<double> h_ab(2 * n);
+    KPM_HIP(hipMemcpyAsync(h_ab.data(), d_ab, h_ab.size() * 8, hipMemcpyDeviceToHost, st));
+    KPM_HIP(hipStreamSynchronize(st));
+    return run_vjp(p, n, *q, h_ab.data(), d_dmu, ckpt_every, d_dJ, work, st);
+  });
 }
 
 size_t chebyshev_moments_ckpt_workspace_size(const kpm_problem* p, int32_t n, const kpm_params* q,
                                              int32_t ckpt_every) {
-  if (check_problems(p, n) != KPM_OK || !q || check_params(*q) != KPM_OK || ckpt_every < 2) return 0;
-  const size_t m = moments_workspace(p, n, *q);
-  const size_t v = vjp_workspace(p, n, *q, ckpt_every);
-  return (m && v) ? std::max(m, v) : 0;
+  return guarded_size([&]() -> size_t {
+    if (check_problems(p, n) != KPM_OK || !q || check_params(*q) != KPM_OK || ckpt_every < 2) return 0;
+    const size_t m = moments_workspace(p, n, *q);
+    const size_t v = vjp_workspace(p, n, *q, ckpt_every);
+    return (m && v) ? std::max(m, v) : 0;
+  });
 }
 
 int chebyshev_moments_ckpt(const kpm_problem* p, int32_t n, const kpm_params* q, int32_t ckpt_every,
                            double* d_mu, double* d_ab, void* d_work, size_t work_bytes, void* stream) {
-  int r = check_problems(p, n);
-  if (r != KPM_OK) return r;
-  if (!q || check_params(*q) != KPM_OK || !d_mu || !d_ab || !d_work || ckpt_every < 2) return KPM_EINVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  StreamSync guard{st};
-  const size_t need = chebyshev_moments_ckpt_workspace_size(p, n, q, ckpt_every);
-  if (need == 0) return KPM_EINVAL;
-  if (work_bytes < need) return KPM_EWORKSPACE;
-  unsigned char* work = static_cast<unsigned char*>(d_work);
-  Planned P0;
-  r = make_plan(p, n, shape_of(*q), nullptr, nullptr, P0);
-  if (r != KPM_OK) return r;
-  const MomLayout L0 = moments_layout(P0, n_steps(q->M), 0);
-  std::vector<double> a, b;
-  r = resolve_scale(p, n, *q, work + L0.lz, st, a, b);
-  if (r != KPM_OK) return r;
-  std::vector<double> h_ab(2 * n);
-  for (int i = 0; i < n; ++i) {
-    h_ab[2 * i] = a[i];
-    h_ab[2 * i + 1] = b[i];
-  }
-  KPM_HIP(hipMemcpyAsync(d_ab, h_ab.data(), h_ab.size() * 8, hipMemcpyHostToDevice, st));
-  return run_vjp(p, n, *q, h_ab.data(), nullptr, ckpt_every, nullptr, work, st, d_mu, {}, kVjpForward);
+  return guarded([&]() -> int {
+    int r = check_problems(p, n);
+    if (r != KPM_OK) return r;
+    if (!q || check_params(*q) != KPM_OK || !d_mu || !d_ab || !d_work || ckpt_every < 2) return KPM_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamSync guard{st};
+    const size_t need = chebyshev_moments_ckpt_workspace_size(p, n, q, ckpt_every);
+    if (need == 0) return KPM_EINVAL;
+    if (work_bytes < need) return KPM_EWORKSPACE;
+    unsigned char* work = static_cast<unsigned char*>(d_work);
+    Planned P0;
+    r = make_plan(p, n, shape_of(*q), nullptr, nullptr, P0);
+    if (r != KPM_OK) return r;
+    const MomLayout L0 = moments_layout(P0, n_steps(q->M), 0);
+    std::vector<double> a, b;
+    r = resolve_scale(p, n, *q, work + L0.lz, st, a, b);
+    if (r != KPM_OK) return r;
+    std::vector<double> h_ab(2 * n);
+    for (int i = 0; i < n; ++i) {
+      h_ab[2 * i] = a[i];
+      h_ab[2 * i + 1] = b[i];
+    }
+    KPM_HIP(hipMemcpyAsync(d_ab, h_ab.data(), h_ab.size() * 8, hipMemcpyHostToDevice, st));
+    return run_vjp(p, n, *q, h_ab.data(), nullptr, ckpt_every, nullptr, work, st, d_mu, {}, kVjpForward);
+  });
 }
 
 int chebyshev_moments_vjp_resume(const kpm_problem* p, int32_t n, const kpm_params* q,
                                  const double* d_ab, const double* d_dmu, int32_t ckpt_every,
                                  double* d_dJ, void* d_work, size_t work_bytes, void* stream) {
-  int r = check_problems(p, n);
-  if (r != KPM_OK) return r;
-  if (!q || check_params(*q) != KPM_OK || !d_ab || !d_dmu || !d_dJ || !d_work || ckpt_every < 2)
-    return KPM_EINVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  StreamSync guard{st};
-  const size_t need = chebyshev_moments_ckpt_workspace_size(p, n, q, ckpt_every);
-  if (need == 0) return KPM_EINVAL;
-  if (work_bytes < need) return KPM_EWORKSPACE;
-  std::vector<double> h_ab(2 * n);
-  KPM_HIP(hipMemcpyAsync(h_ab.data(), d_ab, h_ab.size() * 8, hipMemcpyDeviceToHost, st));
-  KPM_HIP(hipStreamSynchronize(st));
-  return run_vjp(p, n, *q, h_ab.data(), d_dmu, ckpt_every, d_dJ, static_cast<unsigned char*>(d_work), st,
-                 nullptr, {}, kVjpReverse);
+  return guarded([&]() -> int {
+    int r = check_problems(p, n);
+    if (r != KPM_OK) return r;
+    if (!q || check_params(*q) != KPM_OK || !d_ab || !d_dmu || !d_dJ || !d_work || ckpt_every < 2)
+      return KPM_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamSync guard{st};
+    const size_t need = chebyshev_moments_ckpt_workspace_size(p, n, q, ckpt_every);
+    if (need == 0) return KPM_EINVAL;
+    if (work_bytes < need) return KPM_EWORKSPACE;
+    std::vector<double> h_ab(2 * n);
+    KPM_HIP(hipMemcpyAsync(h_ab.data(), d_ab, h_ab.size() * 8, hipMemcpyDeviceToHost, st));
+    KPM_HIP(hipStreamSynchronize(st));
+    return run_vjp(p, n, *q, h_ab.data(), d_dmu, ckpt_every, d_dJ, static_cast<unsigned char*>(d_work), st,
+                   nullptr, {}, kVjpReverse);
+  });
 }
 
 int kpm_cluster_bond_grad(const kpm_problem* p, int32_t n, const double* d_dJ, double* d_dJ_cluster,
                           void* stream) {
-  if (!p || n <= 0 || !d_dJ || !d_dJ_cluster) return KPM_EINVAL;
-  if (const int e = check_problems(p, n)) return e;
-  int nc = 0, max_b = 0;
-  for (int i = 0; i < n; ++i) nc = std::max(nc, p[i].cluster + 1);
-  std::vector<int32_t> info(2 * (size_t)n), cinfo(2 * (size_t)nc, 0), nb(nc, -1);
-  int32_t off = 0;
-  for (int i = 0; i < n; ++i) {
-    const int c = p[i].cluster;
-    if (nb[c] >= 0 && nb[c] != p[i].n_bonds) return KPM_EINVAL;   // one bond list per cluster
-    nb[c] = p[i].n_bonds;
-    info[2 * i] = c;
-    info[2 * i + 1] = off;
-    off += p[i].n_bonds;
-  }
-  int32_t out = 0;
-  for (int c = 0; c < nc; ++c) {
-    cinfo[2 * c] = out;
-    cinfo[2 * c + 1] = std::max(nb[c], 0);
-    out += cinfo[2 * c + 1];
-    max_b = std::max(max_b, cinfo[2 * c + 1]);
-  }
-  if (max_b == 0) return KPM_OK;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  StreamSync sync{st};
-  int32_t* d_tab = nullptr;
-  const size_t bytes = (info.size() + cinfo.size()) * sizeof(int32_t);
-  if (hipMalloc(&d_tab, bytes) != hipSuccess) return KPM_ENOMEM;
-  int rc = KPM_OK;
-  if (hipMemcpyAsync(d_tab, info.data(), info.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(d_tab + info.size(), cinfo.data(), cinfo.size() * 4, hipMemcpyHostToDevice, st) !=
-          hipSuccess ||
-      launch_cluster_grad(d_tab, n, d_tab + info.size(), nc, max_b, d_dJ, d_dJ_cluster, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    rc = KPM_EDEVICE;
-  (void)hipFree(d_tab);
-  return rc;
+  return guarded([&]() -> int {
+    if (!p || n <= 0 || !d_dJ || !d_dJ_cluster) return KPM_EINVAL;
+    if (const int e = check_problems(p, n)) return e;
+    int nc = 0, max_b = 0;
+    for (int i = 0; i < n; ++i) nc = std::max(nc, p[i].cluster + 1);
+    std::vector<int32_t> info(2 * (size_t)n), cinfo(2 * (size_t)nc, 0), nb(nc, -1);
+    int32_t off = 0;
+    for (int i = 0; i < n; ++i) {
+      const int c = p[i].cluster;
+      if (nb[c] >= 0 && nb[c] != p[i].n_bonds) return KPM_EINVAL;   // one bond list per cluster
+      nb[c] = p[i].n_bonds;
+      info[2 * i] = c;
+      info[2 * i + 1] = off;
+      off += p[i].n_bonds;
+    }
+    int32_t out = 0;
+    for (int c = 0; c < nc; ++c) {
+      cinfo[2 * c] = out;
+      cinfo[2 * c + 1] = std::max(nb[c], 0);
+      out += cinfo[2 * c + 1];
+      max_b = std::max(max_b, cinfo[2 * c + 1]);
+    }
+    if (max_b == 0) return KPM_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    StreamSync sync{st};
+    int32_t* d_tab = nullptr;
+    const size_t bytes = (info.size() + cinfo.size()) * sizeof(int32_t);
+    if (hipMalloc(&d_tab, bytes) != hipSuccess) return KPM_ENOMEM;
+    int rc = KPM_OK;
+    if (hipMemcpyAsync(d_tab, info.data(), info.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(d_tab + info.size(), cinfo.data(), cinfo.size() * 4, hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        launch_cluster_grad(d_tab, n, d_tab + info.size(), nc, max_b, d_dJ, d_dJ_cluster, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      rc = KPM_EDEVICE;
+    (void)hipFree(d_tab);
+    return rc;
+  });
 }
 
 int kpm_thermo_grad(const kpm_problem* p, int32_t n, const kpm_params* q, int32_t kernel,
                     int32_t n_nodes, const double* d_T, int32_t n_T, const double* d_wC,
                     const double* d_wchi, int32_t ckpt_every, double* d_L, double* d_dJ,
                     double* d_ab, void* d_work, size_t work_bytes, void* stream) {
-  int r = check_problems(p, n);
-  if (r != KPM_OK) return r;
-  if (!q || check_params(*q) != KPM_OK || !d_T || n_T < 1 || !d_wC || !d_wchi || !d_L || !d_dJ ||
-      ckpt_every < 2 || (kernel != 0 && kernel != 1) || n_nodes < 0)
-    return KPM_EINVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  StreamSync guard{st};
-  std::vector<ThermoProb> tp;
-  std::vector<int32_t> start, list;
-  int nc = 0;
-  if (thermo_meta(p, n, tp, start, list, nc) != KPM_OK) return KPM_EINVAL;
-  const size_t need_m = moments_workspace(p, n, *q);
-  const size_t need_v = vjp_workspace(p, n, *q, ckpt_every);
-  if (!need_m || !need_v) return KPM_EINVAL;
-  const size_t need = std::max(need_m, need_v);
-  DevBuf own;
-  unsigned char* work = static_cast<unsigned char*>(d_work);
-  if (!work) {
-    r = own.alloc(need);
+  return guarded([&]() -> int {
+    int r = check_problems(p, n);
     if (r != KPM_OK) return r;
-    work = static_cast<unsigned char*>(own.p);
-  } else if (work_bytes < need) {
-    return KPM_EWORKSPACE;
-  }
-  const size_t m = (size_t)nc * n_T;
-  DevBuf tmp;
-  r = tmp.alloc(align_up((size_t)n * q->M * 8) * 2 + align_up((size_t)n * 16) + 4 * align_up(m * 8));
-  if (r != KPM_OK) return r;
-  unsigned char* t8 = static_cast<unsigned char*>(tmp.p);
-  double* mu = reinterpret_cast<double*>(t8);
-  double* lam = reinterpret_cast<double*>(t8 + align_up((size_t)n * q->M * 8));
-  double* ab = reinterpret_cast<double*>(t8 + 2 * align_up((size_t)n * q->M * 8));
-  double* outs = reinterpret_cast<double*>(t8 + 2 * align_up((size_t)n * q->M * 8) + align_up((size_t)n * 16));
-  const size_t ms = align_up(m * 8) / 8;
-  // bounds and (a, b) as chebyshev_moments resolves them
-  Planned P0;
-  r = make_plan(p, n, shape_of(*q), nullptr, nullptr, P0);
-  if (r != KPM_OK) return r;
-  const MomLayout L0 = moments_layout(P0, n_steps(q->M), 0);
-  std::vector<double> a, b;
-  r = resolve_scale(p, n, *q, work + L0.lz, st, a, b);
-  if (r != KPM_OK) return r;
-  std::vector<double> h_ab(2 * n);
-  for (int i = 0; i < n; ++i) {
-    h_ab[2 * i] = a[i];
-    h_ab[2 * i + 1] = b[i];
-  }
-  KPM_HIP(hipMemcpyAsync(ab, h_ab.data(), h_ab.size() * 8, hipMemcpyHostToDevice, st));
-  if (d_ab) KPM_HIP(hipMemcpyAsync(d_ab, ab, (size_t)n * 16, hipMemcpyDeviceToDevice, st));
-  // the adjoint's checkpointed forward pass gives the moments; between it and
-  // the reverse sweep: dL/dmu, and L from the thermodynamics
-  auto between = [&]() -> int {
-    int rr = kpm_thermo_vjp(mu, ab, p, n, q->M, kernel, n_nodes, d_T, n_T, d_wC, d_wchi, lam, stream);
-    if (rr != KPM_OK) return rr;
-    rr = kpm_thermo(mu, ab, p, n, q->M, kernel, n_nodes, d_T, n_T, outs, outs + ms, outs + 2 * ms,
-                    outs + 3 * ms, nullptr, stream);
-    if (rr != KPM_OK) return rr;
-    KPM_HIP(launch_loss(outs + 2 * ms, outs + 3 * ms, d_wC, d_wchi, (int)m, d_L, st));
-    return KPM_OK;
-  };
-  return run_vjp(p, n, *q, h_ab.data(), lam, ckpt_every, d_dJ, work, st, mu, between);
+    if (!q || check_params(*q) != KPM_OK || !d_T || n_T < 1 || !d_wC || !d_wchi || !d_L || !d_dJ ||
+        ckpt_every < 2 || (kernel != 0 && kernel != 1) || n_nodes < 0)
+      return KPM_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamSync guard{st};
+    std::vector<ThermoProb> tp;
+    std::vector<int32_t> start, list;
+    int nc = 0;
+    if (thermo_meta(p, n, tp, start, list, nc) != KPM_OK) return KPM_EINVAL;
+    const size_t need_m = moments_workspace(p, n, *q);
+    const size_t need_v = vjp_workspace(p, n, *q, ckpt_every);
+    if (!need_m || !need_v) return KPM_EINVAL;
+    const size_t need = std::max(need_m, need_v);
+    DevBuf own;
+    unsigned char* work = static_cast<unsigned char*>(d_work);
+    if (!work) {
+      r = own.alloc(need);
+      if (r != KPM_OK) return r;
+      work = static_cast<unsigned char*>(own.p);
+    } else if (work_bytes < need) {
+      return KPM_EWORKSPACE;
+    }
+    const size_t m = (size_t)nc * n_T;
+    DevBuf tmp;
+    r = tmp.alloc(align_up((size_t)n * q->M * 8) * 2 + align_up((size_t)n * 16) + 4 * align_up(m * 8));
+    if (r != KPM_OK) return r;
+    unsigned char* t8 = static_cast<unsigned char*>(tmp.p);
+    double* mu = reinterpret_cast<double*>(t8);
+    double* lam = reinterpret_cast<double*>(t8 + align_up((size_t)n * q->M * 8));
+    double* ab = reinterpret_cast<double*>(t8 + 2 * align_up((size_t)n * q->M * 8));
+    double* outs = reinterpret_cast<double*>(t8 + 2 * align_up((size_t)n * q->M * 8) + align_up((size_t)n * 16));
+    const size_t ms = align_up(m * 8) / 8;
+    // bounds and (a, b) as chebyshev_moments resolves them
+    Planned P0;
+    r = make_plan(p, n, shape_of(*q), nullptr, nullptr, P0);
+    if (r != KPM_OK) return r;
+    const MomLayout L0 = moments_layout(P0, n_steps(q->M), 0);
+    std::vector<double> a, b;
+    r = resolve_scale(p, n, *q, work + L0.lz, st, a, b);
+    if (r != KPM_OK) return r;
+    std::vector<double> h_ab(2 * n);
+    for (int i = 0; i < n; ++i) {
+      h_ab[2 * i] = a[i];
+      h_ab[2 * i + 1] = b[i];
+    }
+    KPM_HIP(hipMemcpyAsync(ab, h_ab.data(), h_ab.size() * 8, hipMemcpyHostToDevice, st));
+    if (d_ab) KPM_HIP(hipMemcpyAsync(d_ab, ab, (size_t)n * 16, hipMemcpyDeviceToDevice, st));
+    // the adjoint's checkpointed forward pass gives the moments; between it and
+    // the reverse sweep: dL/dmu, and L from the thermodynamics
+    auto between = [&]() -> int {
+      int rr = kpm_thermo_vjp(mu, ab, p, n, q->M, kernel, n_nodes, d_T, n_T, d_wC, d_wchi, lam, stream);
+      if (rr != KPM_OK) return rr;
+      rr = kpm_thermo(mu, ab, p, n, q->M, kernel, n_nodes, d_T, n_T, outs, outs + ms, outs + 2 * ms,
+                      outs + 3 * ms, nullptr, stream);
+      if (rr != KPM_OK) return rr;
+      KPM_HIP(launch_loss(outs + 2 * ms, outs + 3 * ms, d_wC, d_wchi, (int)m, d_L, st));
+      return KPM_OK;
+    };
+    return run_vjp(p, n, *q, h_ab.data(), lam, ckpt_every, d_dJ, work, st, mu, between);
+  });
 }
 
 size_t kpm_ftlm_workspace_size(const kpm_problem* p, int32_t n, const kpm_params* q) {
-  if (check_problems(p, n) != KPM_OK || !q || check_params(*q) != KPM_OK) return 0;
-  if (q->precision != KPM_FP64) return 0;
-  Planned P;
-  const std::vector<double> two(n, 2.0), zero(n, 0.0);
-  if (make_plan(p, n, ftlm_shape(*q, p, n), two.data(), zero.data(), P) != KPM_OK) return 0;
-  return ftlm_layout(P, ftlm_steps(P, q->M)).total;
+  return guarded_size([&]() -> size_t {
+    if (check_problems(p, n) != KPM_OK || !q || check_params(*q) != KPM_OK) return 0;
+    if (q->precision != KPM_FP64) return 0;
+    Planned P;
+    const std::vector<double> two(n, 2.0), zero(n, 0.0);
+    if (make_plan(p, n, ftlm_shape(*q, p, n), two.data(), zero.data(), P) != KPM_OK) return 0;
+    return ftlm_layout(P, ftlm_steps(P, q->M)).total;
+  });
 }
 
 int kpm_ftlm(const kpm_problem* p, int32_t n, const kpm_params* q, const double* d_T,
              const double* d_h, int32_t n_pts, double* d_lnZ, double* d_E, double* d_C,
              double* d_chi, double* d_mag, double* d_ritz, double* d_weight, void* d_work,
              size_t work_bytes, void* stream) {
-  int r = check_problems(p, n);
-  if (r != KPM_OK) return r;
-  if (!q || check_params(*q) != KPM_OK || q->precision != KPM_FP64) return KPM_EINVAL;
-  if (!d_T || n_pts < 1 || !d_lnZ || !d_E || !d_C || !d_chi) return KPM_EINVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  StreamSync guard{st};
-  Planned P;
-  // H' = H / 2 (a = 2, b = 0), so that the recursion step's 2 H' x - y is H q_j - beta_j q_{j-1}
-  const std::vector<double> two(n, 2.0), zero_b(n, 0.0);
-  r = make_plan(p, n, ftlm_shape(*q, p, n), two.data(), zero_b.data(), P);
-  if (r != KPM_OK) return r;
-  const int steps = ftlm_steps(P, q->M);
-  const FtlmLayout L = ftlm_layout(P, steps);
-  DevBuf own;
-  unsigned char* work = static_cast<unsigned char*>(d_work);
-  if (!work) {
-    r = own.alloc(L.total);
+  return guarded([&]() -> int {
+    int r = check_problems(p, n);
     if (r != KPM_OK) return r;
-    work = static_cast<unsigned char*>(own.p);
-  } else if (work_bytes < L.total) {
-    return KPM_EWORKSPACE;
-  }
-  std::vector<unsigned char> staging;
-  r = upload_plan(P, work + L.plan, staging, st);
-  if (r != KPM_OK) return r;
-  DevicePlan& D = P.plan;
-  D.err = reinterpret_cast<int*>(work + L.err);
-  D.states = reinterpret_cast<uint32_t*>(work + L.states);
-  KPM_HIP(hipMemsetAsync(D.err, 0, sizeof(int), st));
-  if (D.row_ld || D.block || D.spin) KPM_HIP(fill_states(D, st));
-  double* vec = reinterpret_cast<double*>(work + L.vec);
-  double* part = reinterpret_cast<double*>(work + L.part);
-  double* dots = reinterpret_cast<double*>(work + L.dots);
-  double* b2 = reinterpret_cast<double*>(work + L.b2);
-  double* norm = reinterpret_cast<double*>(work + L.norm);
-  const int TC = D.total_cols;
-  KPM_HIP(hipMemsetAsync(vec, 0, (size_t)D.vec_elems * 8, st));
-  // unit-norm start columns (the random vectors of Eq. (7)), |column|^2 kept
-  KPM_HIP(launch_init(D, vec, 0, q->vec_kind, q->seed, nullptr, part, st));
-  KPM_HIP(launch_reduce(D, part, norm, nullptr, st));
-  KPM_HIP(launch_init(D, vec, 2, q->vec_kind, q->seed, norm, part, st));
-  // Lanczos (per column): slot x holds q_j, slot y holds beta_j q_{j-1} (0 at
-  // j = 0).  One recursion step gives w_j = 2 H' q_j - y = H q_j - beta_j q_{j-1},
-  // alpha_j = <w_j, q_j> and <w_j, w_j>; then w_j -= alpha_j q_j with
-  // beta_{j+1}^2 = |w_j|^2, q_{j+1} = w_j / beta_{j+1} in slot y and
-  // beta_{j+1} q_j in slot x (one sweep where <w,w> - alpha^2 is well
-  // conditioned, else an exact second pass), and the slots' roles swap.
-  // <w, w> and the exact |w - alpha q|^2 of the columns finished slowly
-  double* ww = reinterpret_cast<double*>(work + L.ww);
-  double* fixed = reinterpret_cast<double*>(work + L.fixed);
-  int px = 0;
-  for (int j = 0; j < steps; ++j) {
-    KPM_HIP(launch_step(D, vec, part, nullptr, 0, nullptr, nullptr, nullptr, 0, px, 0, st));
-    KPM_HIP(launch_reduce(D, part, ww, dots + (size_t)j * TC, st));
-    KPM_HIP(launch_lz_fused(D, vec, 1 - px, dots + (size_t)j * TC, ww, part, st));
-    KPM_HIP(launch_reduce(D, part, fixed, nullptr, st));
-    KPM_HIP(launch_lz_fix(D, vec, 1 - px, dots + (size_t)j * TC, ww, fixed, b2 + (size_t)j * TC, st));
-    px = 1 - px;
-  }
-  // thermodynamic metadata (sector weights, S^z, clusters)
-  std::vector<ThermoProb> tp;
-  std::vector<int32_t> start, list;
-  int nc = 0;
-  r = thermo_meta(p, n, tp, start, list, nc);
-  if (r != KPM_OK) return r;
-  DevBuf meta;
-  const size_t otp = 0, ost = align_up(tp.size() * sizeof(ThermoProb)),
-               oli = ost + align_up(start.size() * 4);
-  r = meta.alloc(oli + list.size() * 4);
-  if (r != KPM_OK) return r;
-  unsigned char* mb = static_cast<unsigned char*>(meta.p);
-  KPM_HIP(hipMemcpyAsync(mb + otp, tp.data(), tp.size() * sizeof(ThermoProb), hipMemcpyHostToDevice, st));
-  KPM_HIP(hipMemcpyAsync(mb + ost, start.data(), start.size() * 4, hipMemcpyHostToDevice, st));
-  KPM_HIP(hipMemcpyAsync(mb + oli, list.data(), list.size() * 4, hipMemcpyHostToDevice, st));
-  FtlmArgs fa{};
-  fa.probs = D.probs;
-  fa.units = D.units;
-  fa.job_unit = D.job_unit;
-  fa.prob_unit0 = D.prob_unit0;
-  fa.dots = dots;
-  fa.b2 = b2;
-  fa.norms = norm;
-  fa.ritz = reinterpret_cast<double*>(work + L.ritz);
-  fa.escr = reinterpret_cast<double*>(work + L.escr);
-  fa.weight = reinterpret_cast<double*>(work + L.weight);
-  fa.len = reinterpret_cast<int32_t*>(work + L.len);
-  fa.err = D.err;
-  fa.total_cols = TC;
-  fa.steps = steps;
-  fa.vec_kind = q->vec_kind;
-  fa.R = q->vec_kind == KPM_VEC_BASIS ? 0 : q->R;
-  fa.tp = reinterpret_cast<ThermoProb*>(mb + otp);
-  fa.cl_start = reinterpret_cast<int32_t*>(mb + ost);
-  fa.cl_list = reinterpret_cast<int32_t*>(mb + oli);
-  fa.T = d_T;
-  fa.h = d_h;
-  fa.lnZ = d_lnZ;
-  fa.E = d_E;
-  fa.C = d_C;
-  fa.chi = d_chi;
-  fa.mag = d_mag;
-  fa.n_pts = n_pts;
-  fa.n_clusters = nc;
-  KPM_HIP(launch_ftlm_ritz(fa, st));
-  KPM_HIP(launch_ftlm_thermo(fa, st));
-  // real columns only (blocks may be padded), problem after problem
-  if (d_ritz || d_weight) {
-    size_t row = 0;
-    for (const auto& u : P.units) {
-      const size_t bytes = (size_t)u.ncols * steps * 8, src = (size_t)u.col_off * steps;
-      if (d_ritz)
-        KPM_HIP(hipMemcpyAsync(d_ritz + row * steps, fa.ritz + src, bytes, hipMemcpyDeviceToDevice, st));
-      if (d_weight)
-        KPM_HIP(hipMemcpyAsync(d_weight + row * steps, fa.weight + src, bytes, hipMemcpyDeviceToDevice, st));
-      row += (size_t)u.ncols;
+    if (!q || check_params(*q) != KPM_OK || q->precision != KPM_FP64) return KPM_EINVAL;
+    if (!d_T || n_pts < 1 || !d_lnZ || !d_E || !d_C || !d_chi) return KPM_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamSync guard{st};
+    Planned P;
+    // H' = H / 2 (a = 2, b = 0), so that the recursion step's 2 H' x - y is H q_j - beta_j q_{j-1}
+    const std::vector<double> two(n, 2.0), zero_b(n, 0.0);
+    r = make_plan(p, n, ftlm_shape(*q, p, n), two.data(), zero_b.data(), P);
+    if (r != KPM_OK) return r;
+    const int steps = ftlm_steps(P, q->M);
+    const FtlmLayout L = ftlm_layout(P, steps);
+    DevBuf own;
+    unsigned char* work = static_cast<unsigned char*>(d_work);
+    if (!work) {
+      r = own.alloc(L.total);
+      if (r != KPM_OK) return r;
+      work = static_cast<unsigned char*>(own.p);
+    } else if (work_bytes < L.total) {
+      return KPM_EWORKSPACE;
     }
-  }
-  int h_err = 0;
-  KPM_HIP(hipMemcpyAsync(&h_err, D.err, sizeof(int), hipMemcpyDeviceToHost, st));
-  KPM_HIP(hipStreamSynchronize(st));
-  return h_err ? KPM_EDEVICE : KPM_OK;
+    std::vector<unsigned char> staging;
+    r = upload_plan(P, work + L.plan, staging, st);
+    if (r != KPM_OK) return r;
+    DevicePlan& D = P.plan;
+    D.err = reinterpret_cast<int*>(work + L.err);
+    D.states = reinterpret_cast<uint32_t*>(work + L.states);
+    KPM_HIP(hipMemsetAsync(D.err, 0, sizeof(int), st));
+    if (D.row_ld || D.block || D.spin) KPM_HIP(fill_states(D, st));
+    double* vec = reinterpret_cast<double*>(work + L.vec);
+    double* part = reinterpret_cast<double*>(work + L.part);
+    double* dots = reinterpret_cast<double*>(work + L.dots);
+    double* b2 = reinterpret_cast<double*>(work + L.b2);
+    double* norm = reinterpret_cast<double*>(work + L.norm);
+    const int TC = D.total_cols;
+    KPM_HIP(hipMemsetAsync(vec, 0, (size_t)D.vec_elems * 8, st));
+    // unit-norm start columns (the random vectors of Eq. (7)), |column|^2 kept
+    KPM_HIP(launch_init(D, vec, 0, q->vec_kind, q->seed, nullptr, part, st));
+    KPM_HIP(launch_reduce(D, part, norm, nullptr, st));
+    KPM_HIP(launch_init(D, vec, 2, q->vec_kind, q->seed, norm, part, st));
+    // Lanczos (per column): slot x holds q_j, slot y holds beta_j q_{j-1} (0 at
+    // j = 0).  One recursion step gives w_j = 2 H' q_j - y = H q_j - beta_j q_{j-1},
+    // alpha_j = <w_j, q_j> and <w_j, w_j>; then w_j -= alpha_j q_j with
+    // beta_{j+1}^2 = |w_j|^2, q_{j+1} = w_j / beta_{j+1} in slot y and
+    // beta_{j+1} q_j in slot x (one sweep where <w,w> - alpha^2 is well
+    // conditioned, else an exact second pass), and the slots' roles swap.
+    // <w, w> and the exact |w - alpha q|^2 of the columns finished slowly
+    double* ww = reinterpret_cast<double*>(work + L.ww);
+    double* fixed = reinterpret_cast<double*>(work + L.fixed);
+    int px = 0;
+    for (int j = 0; j < steps; ++j) {
+      KPM_HIP(launch_step(D, vec, part, nullptr, 0, nullptr, nullptr, nullptr, 0, px, 0, st));
+      KPM_HIP(launch_reduce(D, part, ww, dots + (size_t)j * TC, st));
+      KPM_HIP(launch_lz_fused(D, vec, 1 - px, dots + (size_t)j * TC, ww, part, st));
+      KPM_HIP(launch_reduce(D, part, fixed, nullptr, st));
+      KPM_HIP(launch_lz_fix(D, vec, 1 - px, dots + (size_t)j * TC, ww, fixed, b2 + (size_t)j * TC, st));
+      px = 1 - px;
+    }
+    // thermodynamic metadata (sector weights, S^z, clusters)
+    std::vector<ThermoProb> tp;
+    std::vector<int32_t> start, list;
+    int nc = 0;
+    r = thermo_meta(p, n, tp, start, list, nc);
+    if (r != KPM_OK) return r;
+    DevBuf meta;
+    const size_t otp = 0, ost = align_up(tp.size() * sizeof(ThermoProb)),
+                 oli = ost + align_up(start.size() * 4);
+    r = meta.alloc(oli + list.size() * 4);
+    if (r != KPM_OK) return r;
+    unsigned char* mb = static_cast<unsigned char*>(meta.p);
+    KPM_HIP(hipMemcpyAsync(mb + otp, tp.data(), tp.size() * sizeof(ThermoProb), hipMemcpyHostToDevice, st));
+    KPM_HIP(hipMemcpyAsync(mb + ost, start.data(), start.size() * 4, hipMemcpyHostToDevice, st));
+    KPM_HIP(hipMemcpyAsync(mb + oli, list.data(), list.size() * 4, hipMemcpyHostToDevice, st));
+    FtlmArgs fa{};
+    fa.probs = D.probs;
+    fa.units = D.units;
+    fa.job_unit = D.job_unit;
+    fa.prob_unit0 = D.prob_unit0;
+    fa.dots = dots;
+    fa.b2 = b2;
+    fa.norms = norm;
+    fa.ritz = reinterpret_cast<double*>(work + L.ritz);
+    fa.escr = reinterpret_cast<double*>(work + L.escr);
+    fa.weight = reinterpret_cast<double*>(work + L.weight);
+    fa.len = reinterpret_cast<int32_t*>(work + L.len);
+    fa.err = D.err;
+    fa.total_cols = TC;
+    fa.steps = steps;
+    fa.vec_kind = q->vec_kind;
+    fa.R = q->vec_kind == KPM_VEC_BASIS ? 0 : q->R;
+    fa.tp = reinterpret_cast<ThermoProb*>(mb + otp);
+    fa.cl_start = reinterpret_cast<int32_t*>(mb + ost);
+    fa.cl_list = reinterpret_cast<int32_t*>(mb + oli);
+    fa.T = d_T;
+    fa.h = d_h;
+    fa.lnZ = d_lnZ;
+    fa.E = d_E;
+    fa.C = d_C;
+    fa.chi = d_chi;
+    fa.mag = d_mag;
+    fa.n_pts = n_pts;
+    fa.n_clusters = nc;
+    KPM_HIP(launch_ftlm_ritz(fa, st));
+    KPM_HIP(launch_ftlm_thermo(fa, st));
+    // real columns only (blocks may be padded), problem after problem
+    if (d_ritz || d_weight) {
+      size_t row = 0;
+      for (const auto& u : P.units) {
+        const size_t bytes = (size_t)u.ncols * steps * 8, src = (size_t)u.col_off * steps;
+        if (d_ritz)
+          KPM_HIP(hipMemcpyAsync(d_ritz + row * steps, fa.ritz + src, bytes, hipMemcpyDeviceToDevice, st));
+        if (d_weight)
+          KPM_HIP(hipMemcpyAsync(d_weight + row * steps, fa.weight + src, bytes, hipMemcpyDeviceToDevice, st));
+        row += (size_t)u.ncols;
+      }
+    }
+    int h_err = 0;
+    KPM_HIP(hipMemcpyAsync(&h_err, D.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    KPM_HIP(hipStreamSynchronize(st));
+    return h_err ? KPM_EDEVICE : KPM_OK;
+  });
 }
 
 size_t kpm_sector_eigenvalues_workspace_size(const kpm_problem* p, int32_t n, int32_t max_dim) {
-  EdPlan E;
-  if (ed_plan(p, n, max_dim, E) != KPM_OK) return 0;
-  return E.total;
+  return guarded_size([&]() -> size_t {
+    EdPlan E;
+    if (ed_plan(p, n, max_dim, E) != KPM_OK) return 0;
+    return E.total;
+  });
 }
 
 int kpm_sector_eigenvalues(const kpm_problem* p, int32_t n, int32_t max_dim, double* d_evals,
                            void* d_work, size_t work_bytes, void* stream) {
-  EdPlan E;
-  int r = ed_plan(p, n, max_dim, E);
-  if (r != KPM_OK) return r;
-  if (!d_evals) return KPM_EINVAL;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  StreamSync guard{st};
-  DevBuf own;
-  unsigned char* work = static_cast<unsigned char*>(d_work);
-  if (!work) {
-    r = own.alloc(E.total);
+  return guarded([&]() -> int {
+    EdPlan E;
+    int r = ed_plan(p, n, max_dim, E);
     if (r != KPM_OK) return r;
-    work = static_cast<unsigned char*>(own.p);
-  } else if (work_bytes < E.total) {
-    return KPM_EWORKSPACE;
-  }
-  // NaN (all bits set) past each spectrum and in the rows of larger sectors
-  KPM_HIP(hipMemsetAsync(d_evals, 0xFF, (size_t)n * max_dim * 8, st));
-  const std::vector<uint32_t> bt = binom_table();
-  std::vector<unsigned char> staging(E.o_mat, 0);
-  std::memcpy(staging.data() + E.o_probs, E.probs.data(), E.probs.size() * sizeof(EigProb));
-  std::memcpy(staging.data() + E.o_mask, E.bmask.data(), E.bmask.size() * 4);
-  std::memcpy(staging.data() + E.o_J, E.J.data(), E.J.size() * 8);
-  std::memcpy(staging.data() + E.o_binom, bt.data(), bt.size() * 4);
-  if (!E.tables.empty()) std::memcpy(staging.data() + E.o_tab, E.tables.data(), E.tables.size() * 4);
-  KPM_HIP(hipMemcpyAsync(work, staging.data(), E.o_mat, hipMemcpyHostToDevice, st));
-  EigArgs a{};
-  a.probs = reinterpret_cast<const EigProb*>(work + E.o_probs);
-  a.bmask = reinterpret_cast<const uint32_t*>(work + E.o_mask);
-  a.J = reinterpret_cast<const double*>(work + E.o_J);
-  a.binom = reinterpret_cast<const uint32_t*>(work + E.o_binom);
-  a.tables = reinterpret_cast<const uint32_t*>(work + E.o_tab);
-  a.err = reinterpret_cast<int*>(work + E.o_err);
-  a.mat = reinterpret_cast<double*>(work + E.o_mat);
-  double* vecs = reinterpret_cast<double*>(work + E.o_vecs);
-  a.hv = vecs;
-  a.hp = vecs + E.vec_len;
-  a.hd = vecs + 2 * E.vec_len;
-  a.he = vecs + 3 * E.vec_len;
-  a.evals = d_evals;
-  a.ld = max_dim;
-  a.max_dim = 1;
-  std::vector<int> dims;
-  for (const auto& e : E.probs) {
-    a.max_dim = std::max(a.max_dim, e.dim);
-    dims.push_back(e.dim);
-  }
-  // LDS: binomial table, bond masks and J values (build); the tridiagonal matrix (finish)
-  a.o_bonds = (int32_t)align_up((size_t)(kBinomN * kBinomN + E.max_bonds) * 4, 16);
-  const size_t lds_build = (size_t)a.o_bonds + (size_t)E.max_bonds * 8;
-  const size_t lds_finish = (size_t)2 * a.max_dim * 8;   // d, e^2 (bisection)
-  if (lds_build > 64 * 1024 || lds_finish > 64 * 1024) return KPM_EINVAL;
-  KPM_HIP(hipMemsetAsync(a.err, 0, sizeof(int), st));
-  KPM_HIP(launch_sector_eig(a, dims.data(), (int)E.probs.size(), lds_build, lds_finish, st));
-  int h_err = 0;
-  KPM_HIP(hipMemcpyAsync(&h_err, a.err, sizeof(int), hipMemcpyDeviceToHost, st));
-  KPM_HIP(hipStreamSynchronize(st));
-  return h_err ? KPM_EDEVICE : KPM_OK;
+    if (!d_evals) return KPM_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamSync guard{st};
+    DevBuf own;
+    unsigned char* work = static_cast<unsigned char*>(d_work);
+    if (!work) {
+      r = own.alloc(E.total);
+      if (r != KPM_OK) return r;
+      work = static_cast<unsigned char*>(own.p);
+    } else if (work_bytes < E.total) {
+      return KPM_EWORKSPACE;
+    }
+    // NaN (all bits set) past each spectrum and in the rows of larger sectors
+    KPM_HIP(hipMemsetAsync(d_evals, 0xFF, (size_t)n * max_dim * 8, st));
+    const std::vector<uint32_t> bt = binom_table();
+    std::vector<unsigned char> staging(E.o_mat, 0);
+    std::memcpy(staging.data() + E.o_probs, E.probs.data(), E.probs.size() * sizeof(EigProb));
+    std::memcpy(staging.data() + E.o_mask, E.bmask.data(), E.bmask.size() * 4);
+    std::memcpy(staging.data() + E.o_J, E.J.data(), E.J.size() * 8);
+    std::memcpy(staging.data() + E.o_binom, bt.data(), bt.size() * 4);
+    if (!E.tables.empty()) std::memcpy(staging.data() + E.o_tab, E.tables.data(), E.tables.size() * 4);
+    KPM_HIP(hipMemcpyAsync(work, staging.data(), E.o_mat, hipMemcpyHostToDevice, st));
+    EigArgs a{};
+    a.probs = reinterpret_cast<const EigProb*>(work + E.o_probs);
+    a.bmask = reinterpret_cast<const uint32_t*>(work + E.o_mask);
+    a.J = reinterpret_cast<const double*>(work + E.o_J);
+    a.binom = reinterpret_cast<const uint32_t*>(work + E.o_binom);
+    a.tables = reinterpret_cast<const uint32_t*>(work + E.o_tab);
+    a.err = reinterpret_cast<int*>(work + E.o_err);
+    a.mat = reinterpret_cast<double*>(work + E.o_mat);
+    double* vecs = reinterpret_cast<double*>(work + E.o_vecs);
+    a.hv = vecs;
+    a.hp = vecs + E.vec_len;
+    a.hd = vecs + 2 * E.vec_len;
+    a.he = vecs + 3 * E.vec_len;
+    a.evals = d_evals;
+    a.ld = max_dim;
+    a.max_dim = 1;
+    std::vector<int> dims;
+    for (const auto& e : E.probs) {
+      a.max_dim = std::max(a.max_dim, e.dim);
+      dims.push_back(e.dim);
+    }
+    // LDS: binomial table, bond masks and J values (build); the tridiagonal matrix (finish)
+    a.o_bonds = (int32_t)align_up((size_t)(kBinomN * kBinomN + E.max_bonds) * 4, 16);
+    const size_t lds_build = (size_t)a.o_bonds + (size_t)E.max_bonds * 8;
+    const size_t lds_finish = (size_t)2 * a.max_dim * 8;   // d, e^2 (bisection)
+    if (lds_build > 64 * 1024 || lds_finish > 64 * 1024) return KPM_EINVAL;
+    KPM_HIP(hipMemsetAsync(a.err, 0, sizeof(int), st));
+    KPM_HIP(launch_sector_eig(a, dims.data(), (int)E.probs.size(), lds_build, lds_finish, st));
+    int h_err = 0;
+    KPM_HIP(hipMemcpyAsync(&h_err, a.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    KPM_HIP(hipStreamSynchronize(st));
+    return h_err ? KPM_EDEVICE : KPM_OK;
+  });
 }
 
 int kpm_thermo_hybrid(const double* d_mu, const double* d_ab, const kpm_problem* p, int32_t n,
@@ -3091,68 +3164,70 @@ int kpm_thermo_hybrid(const double* d_mu, const double* d_ab, const kpm_problem*
                       int32_t evals_ld, const uint8_t* h_exact, const double* d_T, const double* d_h,
                       int32_t n_pts, double* d_lnZ, double* d_E, double* d_C, double* d_chi,
                       double* d_mag, uint8_t* d_znonpos, void* stream) {
-  if (!d_mu || !d_ab || !d_T || !h_exact || !d_lnZ || !d_E || !d_C || !d_chi || M < 1 ||
-      n_pts < 1 || n_nodes < 0 || (kernel != 0 && kernel != 1))
-    return KPM_EINVAL;
-  std::vector<ThermoProb> tp;
-  std::vector<int32_t> start, list;
-  int nc = 0;
-  int r = thermo_meta(p, n, tp, start, list, nc);
-  if (r != KPM_OK) return r;
-  std::vector<int32_t> cnt(n, 0);
-  for (int i = 0; i < n; ++i) {
-    if (!h_exact[i]) continue;
-    const uint64_t dim = prob_dim(p[i]);
-    if (!d_evals || dim > (uint64_t)std::max(evals_ld, 0)) return KPM_EINVAL;
-    cnt[i] = (int32_t)dim;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  StreamSync guard{st};
-  const int Nt = n_nodes ? n_nodes : M;
-  size_t o = 0;
-  auto put = [&](size_t bytes) {
-    const size_t rr = o;
-    o = align_up(o + bytes);
-    return rr;
-  };
-  const size_t og = put((size_t)M * 8), ogam = put((size_t)n * Nt * 8),
-               otp = put(tp.size() * sizeof(ThermoProb)), ostart = put(start.size() * 4),
-               olist = put(list.size() * 4), ocnt = put(cnt.size() * 4);
-  DevBuf buf;
-  r = buf.alloc(o);
-  if (r != KPM_OK) return r;
-  unsigned char* w = static_cast<unsigned char*>(buf.p);
-  KPM_HIP(hipMemcpyAsync(w + otp, tp.data(), tp.size() * sizeof(ThermoProb), hipMemcpyHostToDevice, st));
-  KPM_HIP(hipMemcpyAsync(w + ostart, start.data(), start.size() * 4, hipMemcpyHostToDevice, st));
-  KPM_HIP(hipMemcpyAsync(w + olist, list.data(), list.size() * 4, hipMemcpyHostToDevice, st));
-  KPM_HIP(hipMemcpyAsync(w + ocnt, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice, st));
-  double* g = reinterpret_cast<double*>(w + og);
-  double* gamma = reinterpret_cast<double*>(w + ogam);
-  KPM_HIP(launch_kernel_coef(M, kernel, g, st));
-  KPM_HIP(launch_gamma(n, M, Nt, g, d_mu, gamma, st));
-  ThermoArgs ta{};
-  ta.tp = reinterpret_cast<const ThermoProb*>(w + otp);
-  ta.cl_start = reinterpret_cast<const int32_t*>(w + ostart);
-  ta.cl_list = reinterpret_cast<const int32_t*>(w + olist);
-  ta.gamma = gamma;
-  ta.ab = d_ab;
-  ta.T = d_T;
-  ta.lnZ = d_lnZ;
-  ta.E = d_E;
-  ta.C = d_C;
-  ta.chi = d_chi;
-  ta.znonpos = d_znonpos;
-  ta.n_nodes = Nt;
-  ta.n_T = n_pts;
-  ta.n_clusters = nc;
-  ta.h = d_h;
-  ta.mag = d_mag;
-  ta.ed_count = reinterpret_cast<const int32_t*>(w + ocnt);
-  ta.evals = d_evals;
-  ta.evals_ld = evals_ld;
-  KPM_HIP(launch_thermo_hybrid(ta, st));
-  KPM_HIP(hipStreamSynchronize(st));
-  return KPM_OK;
+  return guarded([&]() -> int {
+    if (!d_mu || !d_ab || !d_T || !h_exact || !d_lnZ || !d_E || !d_C || !d_chi || M < 1 ||
+        n_pts < 1 || n_nodes < 0 || (kernel != 0 && kernel != 1))
+      return KPM_EINVAL;
+    std::vector<ThermoProb> tp;
+    std::vector<int32_t> start, list;
+    int nc = 0;
+    int r = thermo_meta(p, n, tp, start, list, nc);
+    if (r != KPM_OK) return r;
+    std::vector<int32_t> cnt(n, 0);
+    for (int i = 0; i < n; ++i) {
+      if (!h_exact[i]) continue;
+      const uint64_t dim = prob_dim(p[i]);
+      if (!d_evals || dim > (uint64_t)std::max(evals_ld, 0)) return KPM_EINVAL;
+      cnt[i] = (int32_t)dim;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamSync guard{st};
+    const int Nt = n_nodes ? n_nodes : M;
+    size_t o = 0;
+    auto put = [&](size_t bytes) {
+      const size_t rr = o;
+      o = align_up(o + bytes);
+      return rr;
+    };
+    const size_t og = put((size_t)M * 8), ogam = put((size_t)n * Nt * 8),
+                 otp = put(tp.size() * sizeof(ThermoProb)), ostart = put(start.size() * 4),
+                 olist = put(list.size() * 4), ocnt = put(cnt.size() * 4);
+    DevBuf buf;
+    r = buf.alloc(o);
+    if (r != KPM_OK) return r;
+    unsigned char* w = static_cast<unsigned char*>(buf.p);
+    KPM_HIP(hipMemcpyAsync(w + otp, tp.data(), tp.size() * sizeof(ThermoProb), hipMemcpyHostToDevice, st));
+    KPM_HIP(hipMemcpyAsync(w + ostart, start.data(), start.size() * 4, hipMemcpyHostToDevice, st));
+    KPM_HIP(hipMemcpyAsync(w + olist, list.data(), list.size() * 4, hipMemcpyHostToDevice, st));
+    KPM_HIP(hipMemcpyAsync(w + ocnt, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice, st));
+    double* g = reinterpret_cast<double*>(w + og);
+    double* gamma = reinterpret_cast<double*>(w + ogam);
+    KPM_HIP(launch_kernel_coef(M, kernel, g, st));
+    KPM_HIP(launch_gamma(n, M, Nt, g, d_mu, gamma, st));
+    ThermoArgs ta{};
+    ta.tp = reinterpret_cast<const ThermoProb*>(w + otp);
+    ta.cl_start = reinterpret_cast<const int32_t*>(w + ostart);
+    ta.cl_list = reinterpret_cast<const int32_t*>(w + olist);
+    ta.gamma = gamma;
+    ta.ab = d_ab;
+    ta.T = d_T;
+    ta.lnZ = d_lnZ;
+    ta.E = d_E;
+    ta.C = d_C;
+    ta.chi = d_chi;
+    ta.znonpos = d_znonpos;
+    ta.n_nodes = Nt;
+    ta.n_T = n_pts;
+    ta.n_clusters = nc;
+    ta.h = d_h;
+    ta.mag = d_mag;
+    ta.ed_count = reinterpret_cast<const int32_t*>(w + ocnt);
+    ta.evals = d_evals;
+    ta.evals_ld = evals_ld;
+    KPM_HIP(launch_thermo_hybrid(ta, st));
+    KPM_HIP(hipStreamSynchronize(st));
+    return KPM_OK;
+  });
 }
 
 }  // extern "C"
