@@ -31,8 +31,11 @@
  *  - Layout conventions: a problem's basis is the ascending-integer order of
  *    N-bit words with n_up set bits (bit p set <=> site p is up); index = rank
  *    in the combinatorial number system.
- *  - Thread safety: calls on different streams may run concurrently; the only
- *    global state is a per-device cache of tuned launch shapes (mutex-guarded).
+ *  - Thread safety: calls on different streams may run concurrently.  Global
+ *    state: a per-device cache of tuned launch shapes (mutex-guarded), the
+ *    per-device scratch array of chebyshev_moments_noalloc (its calls on one
+ *    device are serialised by a mutex), and the statistics of each host
+ *    thread's last run (kpm_last_run_stats, thread-local).
  */
 #ifndef KPM_H
 #define KPM_H
