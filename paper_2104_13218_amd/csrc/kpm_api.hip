@@ -2209,7 +2209,7 @@ int thermo_forward(const double* d_mu, const double* d_ab, const kpm_problem* p,
 // ---------------------------------------------- finite-temperature Lanczos
 
 struct FtlmLayout {
-  size_t plan, vec, part, dots, b2, norm, ww, fixed, err, states, ritz, escr, weight, len, total;
+  size_t plan, vec, part, dots, b2, norm, ww, fixed, ybeta, err, states, ritz, escr, weight, len, total;
 };
 
 // Every real column runs its own Lanczos recursion; columns are batched in
@@ -2257,6 +2257,7 @@ FtlmLayout ftlm_layout(const Planned& P, int steps) {
   L.norm = put(TC * 8);
   L.ww = put(TC * 8);
   L.fixed = put(TC * 8);
+  L.ybeta = put(TC * 8);
   L.err = put(256);
   L.states = put((size_t)P.plan.n_states * 4);
   L.ritz = put(TC * steps * 8);
@@ -3011,16 +3012,22 @@ int kpm_ftlm(const kpm_problem* p, int32_t n, const kpm_params* q, const double*
     // beta_{j+1}^2 = |w_j|^2, q_{j+1} = w_j / beta_{j+1} in slot y and
     // beta_{j+1} q_j in slot x (one sweep where <w,w> - alpha^2 is well
     // conditioned, else an exact second pass), and the slots' roles swap.
+    // On a float64 slice plan slot x keeps q_j instead and the next step
+    // scales it by beta_{j+1} (ybeta), the same product rounded the same way,
+    // so that the turn writes one vector instead of two.
     // <w, w> and the exact |w - alpha q|^2 of the columns finished slowly
     double* ww = reinterpret_cast<double*>(work + L.ww);
     double* fixed = reinterpret_cast<double*>(work + L.fixed);
+    double* ybeta = D.block == 3 && !D.fp32 ? reinterpret_cast<double*>(work + L.ybeta) : nullptr;
+    if (ybeta) KPM_HIP(hipMemsetAsync(ybeta, 0, (size_t)TC * 8, st));
     int px = 0;
     for (int j = 0; j < steps; ++j) {
-      KPM_HIP(launch_step(D, vec, part, nullptr, 0, nullptr, nullptr, nullptr, 0, px, 0, st));
+      if (ybeta) KPM_HIP(launch_step_scaled(D, vec, part, px, ybeta, st));
+      else KPM_HIP(launch_step(D, vec, part, nullptr, 0, nullptr, nullptr, nullptr, 0, px, 0, st));
       KPM_HIP(launch_reduce(D, part, ww, dots + (size_t)j * TC, st));
-      KPM_HIP(launch_lz_fused(D, vec, 1 - px, dots + (size_t)j * TC, ww, part, st));
+      KPM_HIP(launch_lz_fused(D, vec, 1 - px, dots + (size_t)j * TC, ww, part, ybeta, st));
       KPM_HIP(launch_reduce(D, part, fixed, nullptr, st));
-      KPM_HIP(launch_lz_fix(D, vec, 1 - px, dots + (size_t)j * TC, ww, fixed, b2 + (size_t)j * TC, st));
+      KPM_HIP(launch_lz_fix(D, vec, 1 - px, dots + (size_t)j * TC, ww, fixed, b2 + (size_t)j * TC, ybeta, st));
       px = 1 - px;
     }
     // thermodynamic metadata (sector weights, S^z, clusters)

@@ -153,6 +153,8 @@ struct StepArgs {
   int16_t* vec_lo;             // float32 + residual storage: the residual q of every
                                // element, same element index as the float32 part
                                // (NULL for plain float32 / float64 storage)
+  const double* yscale;        // slice kernel, float64 storage: per column (col_off + c) the
+                               // factor of v_{n-1} in 2 H' v_n - y (NULL: 1; the FTLM's beta_j)
 };
 
 // Device-side plan of one run (pointers into the workspace) + launch shape.
@@ -286,6 +288,8 @@ struct LzArgs {
   int64_t slot_stride;
   int32_t n_tiles, grid_tiles, coef_sqrt;
   int32_t w_hi, q_hi, d_hi;  // select slot 1 instead of slot 0
+  double* ybeta;           // FTLM: non-NULL => q_j stays in its slot and ybeta[col] gets the
+                           // beta_{j+1} by which the next step scales it (0: term dropped)
 };
 
 // Per-problem metadata of the thermodynamic sums.
@@ -465,6 +469,10 @@ hipError_t launch_step_slots(const DevicePlan& p, void* vec, double* part_out, i
 hipError_t launch_step_slots_dots(const DevicePlan& p, void* vec, double* part_out, const double* part_in,
                                   int n_jobs, double* alpha, double* beta, int step_add, int x_slot,
                                   int yin_slot, int yout_slot, hipStream_t st);
+// The two-slot step 2 H' x - s y with v_{n-1} scaled per column by yscale
+// (slice plans in float64 storage only; the FTLM's beta_j q_{j-1}).
+hipError_t launch_step_scaled(const DevicePlan& p, void* vec, double* part_out, int x_parity,
+                              const double* yscale, hipStream_t st);
 hipError_t launch_reduce(const DevicePlan& p, const double* part, double* dst_a, double* dst_b,
                          hipStream_t st);
 hipError_t launch_init(const DevicePlan& p, void* vec, int mode, int vec_kind, uint64_t seed,
@@ -502,11 +510,12 @@ hipError_t launch_matrix(const MatrixArgs& a, size_t lds, int grid, hipStream_t 
 hipError_t launch_lz_axpy(const DevicePlan& p, const LzArgs& args, hipStream_t st);
 // FTLM: fused w -= alpha q_j and turn for well-conditioned columns (ww = <w, w>),
 // then the exact finish of the others (fixed = their |w - alpha q_j|^2) and
-// beta_{j+1}^2 of every column.
+// beta_{j+1}^2 of every column.  ybeta NULL: slot x receives beta_{j+1} q_j;
+// else q_j stays and ybeta[col] receives beta_{j+1} for launch_step_scaled.
 hipError_t launch_lz_fused(const DevicePlan& p, double* vec, int y_hi, const double* alpha, const double* ww,
-                           double* part_out, hipStream_t st);
+                           double* part_out, double* ybeta, hipStream_t st);
 hipError_t launch_lz_fix(const DevicePlan& p, double* vec, int y_hi, const double* alpha, const double* ww,
-                         const double* fixed, double* beta2, hipStream_t st);
+                         const double* fixed, double* beta2, double* ybeta, hipStream_t st);
 hipError_t launch_lz_next(const DevicePlan& p, double* qprev, double* q, const double* w,
                           const double* beta2, hipStream_t st);
 hipError_t launch_kernel_coef(int M, int kernel, double* g, hipStream_t st);

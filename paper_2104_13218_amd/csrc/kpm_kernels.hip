@@ -1911,6 +1911,19 @@ hipError_t launch_step(const DevicePlan& p, void* vec, double* part_out, const d
   return launch_step_args(p, a, st);
 }
 
+hipError_t launch_step_scaled(const DevicePlan& p, void* vec, double* part_out, int x_parity,
+                              const double* yscale, hipStream_t st) {
+  if (p.block != 3 || p.fp32 || !yscale) return hipErrorInvalidValue;
+  StepArgs a = make_step_args(p);
+  a.err = p.err;
+  a.vec = vec;
+  a.part_out = part_out;
+  a.x_slot = x_parity;
+  a.yin_slot = a.yout_slot = 1 - x_parity;
+  a.yscale = yscale;
+  return launch_step_args(p, a, st);
+}
+
 hipError_t launch_step_slots(const DevicePlan& p, void* vec, double* part_out, int x_slot,
                              int yin_slot, int yout_slot, int first, hipStream_t st) {
   StepArgs a = make_step_args(p);
@@ -2373,11 +2386,20 @@ __global__ __launch_bounds__(kThreads) void lz_fused_kernel(const LzArgs a, cons
     const double al = a.coef[U.col_off + c], w2 = ww[U.col_off + c];
     if (lz_fast(w2, al)) {
       const double b = sqrt(w2 - al * al), inv = 1.0 / b;
-      for (int64_t r = row0 + rg; r < row1; r += nrg) {
-        const int64_t i = r * ld + c;
-        const double xv = x[i];
-        y[i] = (y[i] - al * xv) * inv;
-        x[i] = b * xv;
+      if (a.ybeta) {
+        // q_j stays; the next step scales it by b
+        if (tile == U.tile0 && rg == 0) a.ybeta[U.col_off + c] = b;
+        for (int64_t r = row0 + rg; r < row1; r += nrg) {
+          const int64_t i = r * ld + c;
+          y[i] = (y[i] - al * x[i]) * inv;
+        }
+      } else {
+        for (int64_t r = row0 + rg; r < row1; r += nrg) {
+          const int64_t i = r * ld + c;
+          const double xv = x[i];
+          y[i] = (y[i] - al * xv) * inv;
+          x[i] = b * xv;
+        }
       }
     } else {
       for (int64_t r = row0 + rg; r < row1; r += nrg) {
@@ -2430,6 +2452,15 @@ __global__ __launch_bounds__(kThreads) void lz_fix_kernel(const LzArgs a, const 
   const bool live = b2 > 1e-24;
   const double b = live ? sqrt(b2) : 0.0;
   const double inv = live ? 1.0 / b : 0.0;
+  if (a.ybeta) {
+    // q_j stays; the next step scales it by b (0: the term is dropped)
+    if (tile == U.tile0 && rg == 0) a.ybeta[U.col_off + c] = b;
+    for (int64_t r = row0 + rg; r < row1; r += nrg) {
+      const int64_t i = r * ld + c;
+      y[i] = live ? y[i] * inv : x[i];
+    }
+    return;
+  }
   for (int64_t r = row0 + rg; r < row1; r += nrg) {
     const int64_t i = r * ld + c;
     const double xv = x[i];
@@ -2439,7 +2470,7 @@ __global__ __launch_bounds__(kThreads) void lz_fix_kernel(const LzArgs a, const 
 }
 
 hipError_t launch_lz_fused(const DevicePlan& p, double* vec, int y_hi, const double* alpha, const double* ww,
-                           double* part_out, hipStream_t st) {
+                           double* part_out, double* ybeta, hipStream_t st) {
   LzArgs a{};
   a.probs = p.probs;
   a.units = p.units;
@@ -2455,12 +2486,13 @@ hipError_t launch_lz_fused(const DevicePlan& p, double* vec, int y_hi, const dou
   a.q_hi = 1 - y_hi;
   a.coef = alpha;
   a.part_out = part_out;
+  a.ybeta = ybeta;
   hipLaunchKernelGGL(lz_fused_kernel, dim3(p.grid_tiles), dim3(kThreads), 0, st, a, ww);
   return hipGetLastError();
 }
 
 hipError_t launch_lz_fix(const DevicePlan& p, double* vec, int y_hi, const double* alpha, const double* ww,
-                         const double* fixed, double* beta2, hipStream_t st) {
+                         const double* fixed, double* beta2, double* ybeta, hipStream_t st) {
   LzArgs a{};
   a.probs = p.probs;
   a.units = p.units;
@@ -2475,6 +2507,7 @@ hipError_t launch_lz_fix(const DevicePlan& p, double* vec, int y_hi, const doubl
   a.q = vec;
   a.q_hi = 1 - y_hi;
   a.coef = alpha;
+  a.ybeta = ybeta;
   hipLaunchKernelGGL(lz_fix_kernel, dim3(p.grid_tiles), dim3(kThreads), 0, st, a, ww, fixed, beta2);
   return hipGetLastError();
 }

@@ -337,9 +337,17 @@ __device__ __forceinline__ double fold_lanes(const double (&v)[V], int lane) {
   }
 }
 
-template <typename T, int CPL, int NCH, int GH, int WB, bool RES, int NW>
+// s * y rounded on its own (the product a caller would have stored as the
+// scaled v_{n-1}), not fused into the subtraction that follows.
+__device__ __forceinline__ double scaled_term(double s, double y) {
+#pragma clang fp contract(off)
+  return s * y;
+}
+
+template <typename T, int CPL, int NCH, int GH, int WB, bool RES, int NW, bool YS = false>
 __global__ __launch_bounds__(64 * NW) void slice_kernel(const StepArgs a) {
   static_assert(!RES || (sizeof(T) == 4 && (CPL == 2 || CPL == 4)), "residual storage: float32 chunks of 2 or 4");
+  static_assert(!YS || (sizeof(T) == 8 && !RES), "scaled v_{n-1}: float64 storage");
   extern __shared__ __align__(16) unsigned char smem[];
   using RowT = WordRow<WB>;
   using LT = typename std::conditional<RES, double, T>::type;   // LDS copy of v_n
@@ -379,6 +387,12 @@ __global__ __launch_bounds__(64 * NW) void slice_kernel(const StepArgs a) {
   const int rl = lane / NCH;
   const int c = lane - rl * NCH;
   const uint32_t cc = (uint32_t)(c * CPL);
+  // YS: v_{n-1} enters scaled per column (the FTLM's beta_j q_{j-1})
+  double ysc[YS ? CPL : 1];
+  if constexpr (YS) {
+#pragma unroll
+    for (int e = 0; e < CPL; ++e) ysc[e] = a.yscale[U.col_off + cc + e];
+  }
   const int Lb = P.blk_L, nll = P.n_ll, nhh = P.n_hh, nmx = P.n_mx;
   const uint32_t lmask = (1u << Lb) - 1u;
 
@@ -712,7 +726,9 @@ __global__ __launch_bounds__(64 * NW) void slice_kernel(const StepArgs a) {
           double fv[2 * CPL];
 #pragma unroll
           for (int e = 0; e < CPL; ++e) {
-            const double val = a.first ? acc[e] : 2.0 * acc[e] - row_val(yv, e);
+            double yt = row_val(yv, e);
+            if constexpr (YS) yt = scaled_term(ysc[e], yt);
+            const double val = a.first ? acc[e] : 2.0 * acc[e] - yt;
             double o;
             if constexpr (RES) {
               float hi;
@@ -771,30 +787,30 @@ __global__ __launch_bounds__(64 * NW) void slice_kernel(const StepArgs a) {
   }
 }
 
-template <typename T, int CPL, int NCH, int WB, bool RES, int NW>
+template <typename T, int CPL, int NCH, int WB, bool RES, int NW, bool YS>
 static hipError_t launch_slice_w(const StepArgs& a, size_t lds, int grid, int gh, hipStream_t st) {
   if (gh == 4)
-    hipLaunchKernelGGL((slice_kernel<T, CPL, NCH, 4, WB, RES, NW>), dim3(grid), dim3(64 * NW), lds, st, a);
+    hipLaunchKernelGGL((slice_kernel<T, CPL, NCH, 4, WB, RES, NW, YS>), dim3(grid), dim3(64 * NW), lds, st, a);
   else
-    hipLaunchKernelGGL((slice_kernel<T, CPL, NCH, 8, WB, RES, NW>), dim3(grid), dim3(64 * NW), lds, st, a);
+    hipLaunchKernelGGL((slice_kernel<T, CPL, NCH, 8, WB, RES, NW, YS>), dim3(grid), dim3(64 * NW), lds, st, a);
   return hipGetLastError();
 }
 
-template <typename T, int CPL, int NCH, bool RES, int NW>
+template <typename T, int CPL, int NCH, bool RES, int NW, bool YS>
 static hipError_t launch_slice_n(const StepArgs& a, size_t lds, int grid, int gh, int wb, hipStream_t st) {
-  if (wb == 32) return launch_slice_w<T, CPL, NCH, 32, RES, NW>(a, lds, grid, gh, st);
-  return launch_slice_w<T, CPL, NCH, 64, RES, NW>(a, lds, grid, gh, st);
+  if (wb == 32) return launch_slice_w<T, CPL, NCH, 32, RES, NW, YS>(a, lds, grid, gh, st);
+  return launch_slice_w<T, CPL, NCH, 64, RES, NW, YS>(a, lds, grid, gh, st);
 }
 
 // waves per workgroup: 1, or 2 / 4 for rows of 16 or 32 bytes (direct staging)
-template <typename T, int CPL, int NCH, bool RES = false>
+template <typename T, int CPL, int NCH, bool RES = false, bool YS = false>
 static hipError_t launch_slice_t(const StepArgs& a, size_t lds, int grid, int gh, int wb, int nw, hipStream_t st) {
   if constexpr (RES || (NCH * CPL * sizeof(T)) % 16 == 0) {
-    if (nw == 4) return launch_slice_n<T, CPL, NCH, RES, 4>(a, lds, grid, gh, wb, st);
-    if (nw == 2) return launch_slice_n<T, CPL, NCH, RES, 2>(a, lds, grid, gh, wb, st);
+    if (nw == 4) return launch_slice_n<T, CPL, NCH, RES, 4, YS>(a, lds, grid, gh, wb, st);
+    if (nw == 2) return launch_slice_n<T, CPL, NCH, RES, 2, YS>(a, lds, grid, gh, wb, st);
   }
   if (nw != 1) return hipErrorInvalidValue;
-  return launch_slice_n<T, CPL, NCH, RES, 1>(a, lds, grid, gh, wb, st);
+  return launch_slice_n<T, CPL, NCH, RES, 1, YS>(a, lds, grid, gh, wb, st);
 }
 
 // Every unit of a slice plan has ld = cpl * nch with nch 1 or 2.
@@ -806,6 +822,7 @@ hipError_t launch_slice(const DevicePlan& p, const StepArgs& a, hipStream_t st) 
   const int nw = p.slice_nw;
   const int nch = p.ld_max / p.cpl;
   if (p.ld_max != nch * p.cpl || (nch != 1 && nch != 2)) return hipErrorInvalidValue;
+  if (a.yscale && p.fp32) return hipErrorInvalidValue;   // scaled v_{n-1}: float64 storage only
   if (p.resid) {
     if (!p.fp32 || !a.vec_lo) return hipErrorInvalidValue;
     if (p.cpl == 4) return nch == 1 ? launch_slice_t<float, 4, 1, true>(a, lds, grid, gh, wb, nw, st)
@@ -818,6 +835,12 @@ hipError_t launch_slice(const DevicePlan& p, const StepArgs& a, hipStream_t st) 
                                     : launch_slice_t<float, 4, 2>(a, lds, grid, gh, wb, nw, st);
     if (p.cpl == 2 && nch == 1) return launch_slice_t<float, 2, 1>(a, lds, grid, gh, wb, nw, st);
     if (p.cpl == 1 && nch == 1) return launch_slice_t<float, 1, 1>(a, lds, grid, gh, wb, nw, st);
+    return hipErrorInvalidValue;
+  }
+  if (a.yscale) {   // float64 with v_{n-1} scaled per column
+    if (p.cpl == 2) return nch == 1 ? launch_slice_t<double, 2, 1, false, true>(a, lds, grid, gh, wb, nw, st)
+                                    : launch_slice_t<double, 2, 2, false, true>(a, lds, grid, gh, wb, nw, st);
+    if (p.cpl == 1 && nch == 1) return launch_slice_t<double, 1, 1, false, true>(a, lds, grid, gh, wb, nw, st);
     return hipErrorInvalidValue;
   }
   if (p.cpl == 2) return nch == 1 ? launch_slice_t<double, 2, 1>(a, lds, grid, gh, wb, nw, st)
