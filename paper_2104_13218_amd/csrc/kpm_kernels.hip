@@ -2361,11 +2361,19 @@ __global__ __launch_bounds__(kThreads) void lz_next_kernel(const LzArgs a, doubl
 // normalisation error of q_{j+1} near 1e-15: a looser one (1e-3) leaves
 // errors near 1e-13 that surface as a residual above the 1e-12 exhaustion
 // cut of an invariant Krylov space (the one-magnon sector of a 10-site ring).
+// The shortcut also takes <q_j, q_j> as 1: where it is 1 + d the true
+// |w - alpha q_j|^2 exceeds <w, w> - alpha^2 by alpha^2 d, so q_{j+1} carries
+// the error (alpha^2 / beta^2) d on.  The sweep is therefore taken only where
+// alpha^2 < beta^2 / 2, which damps the error; with the first cut alone a
+// spectrum far from 0 (the three-magnon sector of the 24-site ring, energies
+// in [0.077, 6], alpha^2 / beta^2 near 4) grew it geometrically and the Ritz
+// values left the spectrum.
 constexpr double kLzFast = 0.1;
+constexpr double kLzDamp = 0.5;
 
 __device__ __forceinline__ bool lz_fast(double ww, double al) {
   const double b2 = ww - al * al;
-  return b2 > kLzFast * ww && b2 > 1e-24;
+  return b2 > kLzFast * ww && b2 > 1e-24 && al * al < kLzDamp * b2;
 }
 
 __global__ __launch_bounds__(kThreads) void lz_fused_kernel(const LzArgs a, const double* ww) {
