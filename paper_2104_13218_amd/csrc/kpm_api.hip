@@ -1138,7 +1138,7 @@ struct DevBuf {
 // ------------------------------------------------------------- Lanczos bounds
 
 struct LzLayout {
-  size_t plan, vec, vecC, part, dots, b2, zero, norm, err, states, total;
+  size_t plan, vec, part, dots, b2, norm, ww, fixed, ybeta, err, states, total;
 };
 
 LzLayout lanczos_layout(const Planned& P, int steps) {
@@ -1151,12 +1151,13 @@ LzLayout lanczos_layout(const Planned& P, int steps) {
   };
   L.plan = put(P.bytes);
   L.vec = put((size_t)P.plan.vec_elems * 8);
-  L.vecC = put((size_t)P.plan.vec_elems * 8);
   L.part = put((size_t)P.plan.part_len * 8);
   L.dots = put((size_t)steps * P.plan.total_cols * 8);
   L.b2 = put((size_t)steps * P.plan.total_cols * 8);
-  L.zero = put((size_t)P.plan.total_cols * 8);
   L.norm = put((size_t)P.plan.total_cols * 8);
+  L.ww = put((size_t)P.plan.total_cols * 8);
+  L.fixed = put((size_t)P.plan.total_cols * 8);
+  L.ybeta = put((size_t)P.plan.total_cols * 8);
   L.err = put(256);
   L.states = put((size_t)P.plan.n_states * 4);
   L.total = o;
@@ -1224,12 +1225,44 @@ void tri_extremes(const std::vector<double>& a, const std::vector<double>& b, do
   hi = kth(n - 1);
 }
 
-// Batched Lanczos over every problem (one float64 column each): the A/B
-// buffers of a block hold q_j and w, a third buffer holds q_{j-1}.
+// Lanczos recursion, every column its own (the bounds below and the FTLM), on
+// a plan of H' = H/2 whose two slots hold the unit start columns (slot 0) and
+// zeros (slot 1).  Slot x holds q_j, slot y beta_j q_{j-1} (0 at j = 0).  One
+// recursion step gives w_j = 2 H' q_j - y = H q_j - beta_j q_{j-1},
+// alpha_j = <w_j, q_j> and <w_j, w_j>; then w_j -= alpha_j q_j with
+// beta_{j+1}^2 = |w_j|^2, q_{j+1} = w_j / beta_{j+1} in slot y and
+// beta_{j+1} q_j in slot x (one sweep where <w,w> - alpha^2 is safe, else an
+// exact second pass), and the slots' roles swap.  On a float64 slice plan
+// slot x keeps q_j instead and the next step scales it by beta_{j+1} (ybeta),
+// the same product rounded the same way, so that the turn writes one vector
+// instead of two.  alpha_j goes to dots[j], beta_{j+1}^2 to b2[j] (rows of
+// total_cols); ww and fixed hold <w, w> and the exact |w - alpha q|^2 of the
+// columns finished slowly; ybeta is total_cols doubles.
+int lanczos_turns(const DevicePlan& D, double* vec, double* part, double* dots, double* b2, double* ww,
+                  double* fixed, double* ybeta_buf, int steps, hipStream_t st) {
+  const int TC = D.total_cols;
+  double* ybeta = D.block == 3 && !D.fp32 ? ybeta_buf : nullptr;
+  if (ybeta) KPM_HIP(hipMemsetAsync(ybeta, 0, (size_t)TC * 8, st));
+  int px = 0;
+  for (int j = 0; j < steps; ++j) {
+    if (ybeta) KPM_HIP(launch_step_scaled(D, vec, part, px, ybeta, st));
+    else KPM_HIP(launch_step(D, vec, part, nullptr, 0, nullptr, nullptr, nullptr, 0, px, 0, st));
+    KPM_HIP(launch_reduce(D, part, ww, dots + (size_t)j * TC, st));
+    KPM_HIP(launch_lz_fused(D, vec, 1 - px, dots + (size_t)j * TC, ww, part, ybeta, st));
+    KPM_HIP(launch_reduce(D, part, fixed, nullptr, st));
+    KPM_HIP(launch_lz_fix(D, vec, 1 - px, dots + (size_t)j * TC, ww, fixed, b2 + (size_t)j * TC, ybeta, st));
+    px = 1 - px;
+  }
+  return KPM_OK;
+}
+
+// Batched Lanczos over every problem (one float64 column each), the recursion
+// of lanczos_turns on H' = H/2.
 int run_lanczos(const kpm_problem* p, int n, int steps, double margin, uint64_t seed,
                 double* e_lo_hi, unsigned char* work, hipStream_t st) {
   Planned P;
-  int r = make_plan(p, n, lanczos_shape(p, n), nullptr, nullptr, P);
+  const std::vector<double> two(n, 2.0), zero_b(n, 0.0);
+  int r = make_plan(p, n, lanczos_shape(p, n), two.data(), zero_b.data(), P);
   if (r != KPM_OK) return r;
   for (auto& u : P.units) u.col0 = 1023;   // RNG stream r = 1023 for the start vector
   int64_t max_dim = 1;
@@ -1245,44 +1278,19 @@ int run_lanczos(const kpm_problem* p, int n, int steps, double margin, uint64_t 
   KPM_HIP(hipMemsetAsync(D.err, 0, sizeof(int), st));
   if (D.row_ld || D.block || D.spin) KPM_HIP(fill_states(D, st));
   double* vec = reinterpret_cast<double*>(work + L.vec);
-  double* vecC = reinterpret_cast<double*>(work + L.vecC);
   double* part = reinterpret_cast<double*>(work + L.part);
   double* dots = reinterpret_cast<double*>(work + L.dots);
   double* b2 = reinterpret_cast<double*>(work + L.b2);
-  double* zero = reinterpret_cast<double*>(work + L.zero);
   const int TC = D.total_cols;
   KPM_HIP(hipMemsetAsync(vec, 0, (size_t)D.vec_elems * 8, st));
-  KPM_HIP(hipMemsetAsync(vecC, 0, (size_t)D.vec_elems * 8, st));
-  KPM_HIP(hipMemsetAsync(zero, 0, (size_t)TC * 8, st));
   // unit-norm real Gaussian start vector (RNG stream r = 1023)
   double* norm = reinterpret_cast<double*>(work + L.norm);
   KPM_HIP(launch_init(D, vec, 0, KPM_VEC_GAUSSIAN, seed, nullptr, part, st));
   KPM_HIP(launch_reduce(D, part, norm, nullptr, st));
   KPM_HIP(launch_init(D, vec, 2, KPM_VEC_GAUSSIAN, seed, norm, part, st));
-  for (int j = 0; j < nsteps; ++j) {
-    // w = H q_j  (A -> B; a = 1, b = 0 so H' = H)
-    KPM_HIP(launch_step(D, vec, part, nullptr, 0, nullptr, nullptr, nullptr, 0, 0, 1, st));
-    // w -= beta_{j-1} q_{j-1};  alpha_j = <w, q_j>
-    LzArgs a1{};
-    a1.w = vec; a1.w_hi = 1;
-    a1.q = vecC; a1.q_hi = 0;
-    a1.coef = j ? b2 + (size_t)(j - 1) * TC : zero;
-    a1.coef_sqrt = 1;
-    a1.dotvec = vec; a1.d_hi = 0;
-    a1.part_out = part;
-    KPM_HIP(launch_lz_axpy(D, a1, st));
-    KPM_HIP(launch_reduce(D, part, dots + (size_t)j * TC, nullptr, st));
-    // w -= alpha_j q_j;  beta_j^2 = <w, w>
-    LzArgs a2{};
-    a2.w = vec; a2.w_hi = 1;
-    a2.q = vec; a2.q_hi = 0;
-    a2.coef = dots + (size_t)j * TC;
-    a2.dotvec = nullptr;
-    a2.part_out = part;
-    KPM_HIP(launch_lz_axpy(D, a2, st));
-    KPM_HIP(launch_reduce(D, part, b2 + (size_t)j * TC, nullptr, st));
-    KPM_HIP(launch_lz_next(D, vecC, vec, vec, b2 + (size_t)j * TC, st));
-  }
+  r = lanczos_turns(D, vec, part, dots, b2, reinterpret_cast<double*>(work + L.ww),
+                    reinterpret_cast<double*>(work + L.fixed), reinterpret_cast<double*>(work + L.ybeta), nsteps, st);
+  if (r != KPM_OK) return r;
   std::vector<double> h_dots((size_t)nsteps * TC), h_b2((size_t)nsteps * TC);
   int h_err = 0;
   KPM_HIP(hipMemcpyAsync(h_dots.data(), dots, h_dots.size() * 8, hipMemcpyDeviceToHost, st));
@@ -3006,30 +3014,10 @@ int kpm_ftlm(const kpm_problem* p, int32_t n, const kpm_params* q, const double*
     KPM_HIP(launch_init(D, vec, 0, q->vec_kind, q->seed, nullptr, part, st));
     KPM_HIP(launch_reduce(D, part, norm, nullptr, st));
     KPM_HIP(launch_init(D, vec, 2, q->vec_kind, q->seed, norm, part, st));
-    // Lanczos (per column): slot x holds q_j, slot y holds beta_j q_{j-1} (0 at
-    // j = 0).  One recursion step gives w_j = 2 H' q_j - y = H q_j - beta_j q_{j-1},
-    // alpha_j = <w_j, q_j> and <w_j, w_j>; then w_j -= alpha_j q_j with
-    // beta_{j+1}^2 = |w_j|^2, q_{j+1} = w_j / beta_{j+1} in slot y and
-    // beta_{j+1} q_j in slot x (one sweep where <w,w> - alpha^2 is well
-    // conditioned, else an exact second pass), and the slots' roles swap.
-    // On a float64 slice plan slot x keeps q_j instead and the next step
-    // scales it by beta_{j+1} (ybeta), the same product rounded the same way,
-    // so that the turn writes one vector instead of two.
-    // <w, w> and the exact |w - alpha q|^2 of the columns finished slowly
-    double* ww = reinterpret_cast<double*>(work + L.ww);
-    double* fixed = reinterpret_cast<double*>(work + L.fixed);
-    double* ybeta = D.block == 3 && !D.fp32 ? reinterpret_cast<double*>(work + L.ybeta) : nullptr;
-    if (ybeta) KPM_HIP(hipMemsetAsync(ybeta, 0, (size_t)TC * 8, st));
-    int px = 0;
-    for (int j = 0; j < steps; ++j) {
-      if (ybeta) KPM_HIP(launch_step_scaled(D, vec, part, px, ybeta, st));
-      else KPM_HIP(launch_step(D, vec, part, nullptr, 0, nullptr, nullptr, nullptr, 0, px, 0, st));
-      KPM_HIP(launch_reduce(D, part, ww, dots + (size_t)j * TC, st));
-      KPM_HIP(launch_lz_fused(D, vec, 1 - px, dots + (size_t)j * TC, ww, part, ybeta, st));
-      KPM_HIP(launch_reduce(D, part, fixed, nullptr, st));
-      KPM_HIP(launch_lz_fix(D, vec, 1 - px, dots + (size_t)j * TC, ww, fixed, b2 + (size_t)j * TC, ybeta, st));
-      px = 1 - px;
-    }
+    // Lanczos per column (lanczos_turns)
+    r = lanczos_turns(D, vec, part, dots, b2, reinterpret_cast<double*>(work + L.ww),
+                      reinterpret_cast<double*>(work + L.fixed), reinterpret_cast<double*>(work + L.ybeta), steps, st);
+    if (r != KPM_OK) return r;
     // thermodynamic metadata (sector weights, S^z, clusters)
     std::vector<ThermoProb> tp;
     std::vector<int32_t> start, list;

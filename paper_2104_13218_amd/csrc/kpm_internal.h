@@ -282,13 +282,12 @@ struct LzArgs {
   const int32_t* tile_nrows;
   double* w;
   const double* q;
-  const double* coef;      // per column (col_off + c); squared if coef_sqrt
-  const double* dotvec;    // NULL => dot with the updated w itself
+  const double* coef;      // per column (col_off + c): alpha_j
   double* part_out;
   int64_t slot_stride;
-  int32_t n_tiles, grid_tiles, coef_sqrt;
-  int32_t w_hi, q_hi, d_hi;  // select slot 1 instead of slot 0
-  double* ybeta;           // FTLM: non-NULL => q_j stays in its slot and ybeta[col] gets the
+  int32_t n_tiles, grid_tiles;
+  int32_t w_hi, q_hi;      // select slot 1 instead of slot 0
+  double* ybeta;           // non-NULL => q_j stays in its slot and ybeta[col] gets the
                            // beta_{j+1} by which the next step scales it (0: term dropped)
 };
 
@@ -507,8 +506,7 @@ hipError_t launch_slice(const DevicePlan& p, const StepArgs& a, hipStream_t st);
 // table region; built by fill_states).
 size_t tab_meta_bytes(const DevicePlan& p);
 hipError_t launch_matrix(const MatrixArgs& a, size_t lds, int grid, hipStream_t st);
-hipError_t launch_lz_axpy(const DevicePlan& p, const LzArgs& args, hipStream_t st);
-// FTLM: fused w -= alpha q_j and turn for well-conditioned columns (ww = <w, w>),
+// Lanczos turn (bounds and FTLM): fused w -= alpha q_j and turn for well-conditioned columns (ww = <w, w>),
 // then the exact finish of the others (fixed = their |w - alpha q_j|^2) and
 // beta_{j+1}^2 of every column.  ybeta NULL: slot x receives beta_{j+1} q_j;
 // else q_j stays and ybeta[col] receives beta_{j+1} for launch_step_scaled.
@@ -516,8 +514,6 @@ hipError_t launch_lz_fused(const DevicePlan& p, double* vec, int y_hi, const dou
                            double* part_out, double* ybeta, hipStream_t st);
 hipError_t launch_lz_fix(const DevicePlan& p, double* vec, int y_hi, const double* alpha, const double* ww,
                          const double* fixed, double* beta2, double* ybeta, hipStream_t st);
-hipError_t launch_lz_next(const DevicePlan& p, double* qprev, double* q, const double* w,
-                          const double* beta2, hipStream_t st);
 hipError_t launch_kernel_coef(int M, int kernel, double* g, hipStream_t st);
 hipError_t launch_gamma(int n_probs, int M, int n_nodes, const double* g, const double* mu,
                         double* gamma, hipStream_t st);

@@ -2268,90 +2268,6 @@ __device__ __forceinline__ double* lz_sel(double* base, int hi, const UnitDev& U
   return base + U.vec_off + (hi ? stride : 0);
 }
 
-// w -= coef * q per column (coef[col_off + c], or its square root), with
-// per-column partials of <w, d> (d = w itself when d is NULL).  Thread
-// (row group, column) as in init_kernel; the partials of a tile are summed
-// over row groups in a fixed tree.
-__global__ __launch_bounds__(kThreads) void lz_axpy_kernel(const LzArgs a) {
-  __shared__ double red[kThreads];
-  const int tile = xcd_tile(blockIdx.x, a.grid_tiles);
-  if (tile >= a.n_tiles) return;
-  const UnitDev U = a.units[a.tile_unit[tile]];
-  const int64_t row0 = a.tile_row0[tile];
-  const int64_t row1 = row0 + a.tile_nrows[tile];
-  const int ld = U.ld;
-  const int nrg = kThreads / ld;
-  const int tid = threadIdx.x;
-  const int c = tid % ld, rg = tid / ld;
-  double* w = lz_sel(a.w, a.w_hi, U, a.slot_stride);
-  const double* q = lz_sel(const_cast<double*>(a.q), a.q_hi, U, a.slot_stride);
-  const double* d = a.dotvec ? lz_sel(const_cast<double*>(a.dotvec), a.d_hi, U, a.slot_stride) : nullptr;
-  double acc = 0.0;
-  if (rg < nrg) {
-    const double cf = a.coef_sqrt ? sqrt(a.coef[U.col_off + c]) : a.coef[U.col_off + c];
-    for (int64_t r = row0 + rg; r < row1; r += nrg) {
-      const int64_t i = r * ld + c;
-      const double wv = w[i] - cf * q[i];
-      w[i] = wv;
-      acc = fma(wv, d ? d[i] : wv, acc);
-    }
-  }
-  red[tid] = rg < nrg ? acc : 0.0;
-  int p2 = 1;
-  while (p2 < nrg) p2 <<= 1;
-  for (int s = p2 >> 1; s > 0; s >>= 1) {
-    __syncthreads();
-    if (rg < s && rg + s < nrg) red[tid] += red[tid + s * ld];
-  }
-  __syncthreads();
-  if (tid < ld) {
-    const int tl = tile - U.tile0;
-    a.part_out[U.part_off + (int64_t)tid * U.ntiles + tl] = red[tid];
-    a.part_out[U.part_off + (int64_t)(ld + tid) * U.ntiles + tl] = 0.0;
-  }
-}
-
-hipError_t launch_lz_axpy(const DevicePlan& p, const LzArgs& args, hipStream_t st) {
-  LzArgs a = args;
-  a.probs = p.probs;
-  a.units = p.units;
-  a.tile_unit = p.tile_unit;
-  a.n_tiles = p.n_tiles;
-  a.grid_tiles = p.grid_tiles;
-  a.tile_row0 = p.tile_row0;
-  a.tile_nrows = p.tile_nrows;
-  a.slot_stride = p.slot_stride;
-  hipLaunchKernelGGL(lz_axpy_kernel, dim3(p.grid_tiles), dim3(kThreads), 0, st, a);
-  return hipGetLastError();
-}
-
-// Per column: qprev <- q; q <- w / sqrt(beta2)   (skipped once beta2 < 1e-24:
-// that column's Krylov space is exhausted).
-__global__ __launch_bounds__(kThreads) void lz_next_kernel(const LzArgs a, double* qprev,
-                                                           double* q, const double* w,
-                                                           const double* beta2) {
-  const int tile = xcd_tile(blockIdx.x, a.grid_tiles);
-  if (tile >= a.n_tiles) return;
-  const UnitDev U = a.units[a.tile_unit[tile]];
-  const int64_t row0 = a.tile_row0[tile];
-  const int64_t row1 = row0 + a.tile_nrows[tile];
-  const int ld = U.ld;
-  const int nrg = kThreads / ld;
-  const int c = threadIdx.x % ld, rg = threadIdx.x / ld;
-  if (rg >= nrg) return;
-  const double b2 = beta2[U.col_off + c];
-  if (!(b2 > 1e-24)) return;
-  const double inv = 1.0 / sqrt(b2);
-  double* qp = qprev + U.vec_off;
-  double* qq = q + U.vec_off;
-  const double* ww = w + U.vec_off + a.slot_stride;
-  for (int64_t r = row0 + rg; r < row1; r += nrg) {
-    const int64_t i = r * ld + c;
-    qp[i] = qq[i];
-    qq[i] = ww[i] * inv;
-  }
-}
-
 // FTLM, one sweep per step where it is safe: with alpha = <w, q_j> and
 // <w, w> from the recursion step, beta^2 = <w, w> - alpha^2 loses at most
 // eps <w, w> / beta^2 to cancellation; for a column with beta^2 > kLzFast
@@ -2517,22 +2433,6 @@ hipError_t launch_lz_fix(const DevicePlan& p, double* vec, int y_hi, const doubl
   a.coef = alpha;
   a.ybeta = ybeta;
   hipLaunchKernelGGL(lz_fix_kernel, dim3(p.grid_tiles), dim3(kThreads), 0, st, a, ww, fixed, beta2);
-  return hipGetLastError();
-}
-
-hipError_t launch_lz_next(const DevicePlan& p, double* qprev, double* q, const double* w,
-                          const double* beta2, hipStream_t st) {
-  LzArgs a{};
-  a.probs = p.probs;
-  a.units = p.units;
-  a.tile_unit = p.tile_unit;
-  a.n_tiles = p.n_tiles;
-  a.grid_tiles = p.grid_tiles;
-  a.tile_row0 = p.tile_row0;
-  a.tile_nrows = p.tile_nrows;
-  a.slot_stride = p.slot_stride;
-  hipLaunchKernelGGL(lz_next_kernel, dim3(p.grid_tiles), dim3(kThreads), 0, st, a, qprev, q, w,
-                     beta2);
   return hipGetLastError();
 }
 
