@@ -1225,7 +1225,8 @@ void tri_extremes(const std::vector<double>& a, const std::vector<double>& b, do
   hi = kth(n - 1);
 }
 
-// Lanczos recursion, every column its own (the bounds below and the FTLM), on
+// Lanczos recursion, every column its own (the spectral bounds of Eqs. (4)-(5)
+// below and the FTLM that Sec. III.C compares against), on
 // a plan of H' = H/2 whose two slots hold the unit start columns (slot 0) and
 // zeros (slot 1).  Slot x holds q_j, slot y beta_j q_{j-1} (0 at j = 0).  One
 // recursion step gives w_j = 2 H' q_j - y = H q_j - beta_j q_{j-1},
